@@ -1,0 +1,170 @@
+/*
+ * svlcov.h -- C ABI of an MI355X (gfx950) engine that keeps a rank-k truncated
+ * SVD  A ~= U diag(sigma) V^T  of a sparse, evolving matrix up to date under
+ * the three update forms of arXiv 2401.09703 (Section 2):
+ *
+ *     add rows        [A ; E_r]            E_r  s x n
+ *     add columns     [A , E_c]            E_c  m x s   (passed as E_c^T, s x m)
+ *     update weights  A + D E_m^T          D    m x s   (passed as D^T,  s x m)
+ *                                          E_m  n x s   (passed as E_m^T, s x n)
+ *
+ * Each update maintains an approximate rank-k truncated SVD in the sense of
+ * Definition 2: the new factors are SVD_k of the update applied to
+ * U diag(sigma) V^T (Theorem 1).  The factors are held in the extended
+ * decomposition of Section 3.2, U = U_base W_U and V = V_base W_V with W_U,
+ * W_V k x k, so that an update touches only the rows of the tall factors that
+ * the update's sparsity reaches plus the appended rows.
+ *
+ * Every update runs on the GPU: the projection of the update onto the tall
+ * factor (Lemma 1), the Gram of the augmented matrix without forming it
+ * (Lemma 2, Lemma 3), its FP64 Cholesky factor (the R of Algorithm 2), the
+ * (k+s) Rayleigh-Ritz SVD (Section 2.1, step 2), the k x k factor updates and
+ * the sparse row updates of the tall factors (Equation (1); Algorithms 3, 4
+ * and 11).
+ *
+ * Conventions
+ *   - Matrices are row-major unless stated.  Sparse inputs are canonical CSR:
+ *     0-based, int64 row_ptr[rows+1] with row_ptr[0] = 0 and row_ptr[rows] =
+ *     nnz, int32 column ids strictly increasing within each row, finite
+ *     values (explicit zeros allowed, empty rows allowed).
+ *   - Ownership: the caller owns every input pointer.  Host inputs are read
+ *     before the call returns.  Device inputs must stay valid until the next
+ *     svlcov_sync() on the same state.  The state owns all device memory it
+ *     allocates (factors and workspaces).
+ *   - Streams: all device work of a state is ordered on the stream given in
+ *     svlcov_options (NULL = a stream the library creates).  Update calls are
+ *     asynchronous; svlcov_sync() waits and reports deferred errors.
+ *   - Errors: return codes only, nothing is thrown or printed across the ABI.
+ *     A call that fails validation on the host leaves the state unchanged.  A
+ *     failure found on the device (malformed device-resident CSR, non-finite
+ *     intermediate) makes every remaining kernel of that update and of later
+ *     updates a no-op, so the factors stay as they were before the failing
+ *     update; the error is returned by the next svlcov_sync(), which also
+ *     restores the row/column counts to their values before that update.
+ *   - Threads: one state must not be used from two threads at once
+ *     (SVLCOV_E_BUSY is returned to the second caller).
+ */
+#ifndef SVLCOV_H
+#define SVLCOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct svlcov_state svlcov_state;
+
+typedef enum {
+  SVLCOV_OK = 0,
+  SVLCOV_E_INVALID = 1,     /* malformed argument or CSR                      */
+  SVLCOV_E_SHAPE = 2,       /* dimensions do not match the state              */
+  SVLCOV_E_NOMEM = 3,       /* device allocation failed                       */
+  SVLCOV_E_NUMERIC = 4,     /* non-finite input or intermediate               */
+  SVLCOV_E_DEVICE = 5,      /* HIP runtime error                              */
+  SVLCOV_E_BUSY = 6,        /* state in use by another thread                 */
+  SVLCOV_E_UNSUPPORTED = 7  /* size or option outside what is built           */
+} svlcov_status;
+
+typedef enum {
+  SVLCOV_FP64 = 0,    /* all storage and arithmetic FP64                       */
+  SVLCOV_FP32 = 1,    /* FP32 tall factors, FP32 SpMM/GEMM; FP64 small dense    */
+  SVLCOV_BF16X3 = 2   /* as FP32, but the residual Gram and the realisation    */
+                      /* GEMMs run as three BF16 MFMA products (hi*hi + hi*lo  */
+                      /* + lo*hi) with FP32 accumulation                       */
+} svlcov_precision;
+
+typedef enum { SVLCOV_F32 = 0, SVLCOV_F64 = 1 } svlcov_dtype;
+
+typedef struct {
+  int64_t rows, cols, nnz;
+  const int64_t *row_ptr;   /* rows + 1 */
+  const int32_t *col_idx;   /* nnz      */
+  const void *val;          /* nnz, float or double per val_dtype */
+  int32_t val_dtype;        /* svlcov_dtype */
+  int32_t on_device;        /* 0: host memory, 1: device memory of the state */
+} svlcov_csr;
+
+typedef struct {
+  int32_t precision;          /* svlcov_precision                              */
+  int32_t device;             /* HIP device ordinal                            */
+  void *stream;               /* hipStream_t, NULL = library-created stream    */
+  int64_t row_capacity;       /* initial row capacity of U_base (>= m), 0=auto */
+  int64_t col_capacity;       /* initial row capacity of V_base (>= n), 0=auto */
+  double rank_tol;            /* relative pivot floor of the residual Gram     */
+                              /* Cholesky (drop when d_j <= rank_tol * max_i   */
+                              /* ||e_i||^2); <= 0 selects the mode's default   */
+  double cond_reset;          /* fold W into the tall factor when its 1-norm   */
+                              /* condition number exceeds this; <= 0 default   */
+  int32_t validate_device_inputs; /* 1: check device CSR on the device         */
+} svlcov_options;
+
+typedef struct {
+  int64_t updates;            /* completed update calls                        */
+  int64_t resets_U, resets_V; /* times W_U / W_V was folded into the base      */
+  int32_t last_rank;          /* kept pivots of the last orthogonalisation     */
+  int32_t last_rank2;         /* second side of a weight update (else -1)      */
+  double last_kappa_U;        /* 1-norm condition estimate of W_U after last   */
+  double last_kappa_V;        /*   update (before any reset)                   */
+  double last_min_kept_pivot; /* smallest kept / largest dropped pivot ratio   */
+  double last_max_dropped_pivot; /* relative to max ||e_i||^2 (-1 if none)     */
+} svlcov_stats;
+
+/* Fill *opt with defaults: FP64, device 0, library stream, automatic
+ * capacities, default tolerances, device-input validation on. */
+void svlcov_default_options(svlcov_options *opt);
+
+/* Create a state holding m x k U, k sigma, n x k V (FP64, row-major, host
+ * memory if factors_on_device == 0, else device memory).  U and V must have
+ * orthonormal columns and sigma must be non-increasing and >= 0: these are
+ * the starting factors U', V' of the extended decomposition with U'' = V'' =
+ * I (Section 3.2).  k must be one of 16, 32, 64, 128. */
+svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k,
+                          const double *U, const double *sigma, const double *V,
+                          int32_t factors_on_device, const svlcov_options *opt);
+
+/* Add rows: E_r is s x n (Algorithm 11; Theorem 1, add rows).  m grows by s. */
+svlcov_status svlcov_add_rows(svlcov_state *h, const svlcov_csr *E_r);
+
+/* Add columns: E_c_T is s x m, the transpose of the new columns (Algorithm 3;
+ * Theorem 1, add columns).  n grows by s. */
+svlcov_status svlcov_add_cols(svlcov_state *h, const svlcov_csr *E_c_T);
+
+/* Update weights: A + D E_m^T with D_T s x m and E_m_T s x n (Algorithm 4;
+ * Theorem 1, update weights).  Both must have the same number of rows s. */
+svlcov_status svlcov_update_weights(svlcov_state *h, const svlcov_csr *D_T,
+                                    const svlcov_csr *E_m_T);
+
+/* Realise and return the factors U = U_base W_U (m x k), sigma (k) and
+ * V = V_base W_V (n x k).  Any output pointer may be NULL; m, n, k receive the
+ * current shape when non-NULL.  out_dtype selects float or double outputs,
+ * out_on_device selects device or host output buffers.  Waits for the state's
+ * stream. */
+svlcov_status svlcov_get_factors(svlcov_state *h, int64_t *m, int64_t *n,
+                                 int32_t *k, int32_t out_dtype,
+                                 int32_t out_on_device, void *U, double *sigma,
+                                 void *V);
+
+/* Query(i) of Theorem 1: row i of U (side 0) or of V (side 1) as
+ * U_base[i] W_U in O(k^2); writes k doubles to host memory. */
+svlcov_status svlcov_query_row(svlcov_state *h, int32_t side, int64_t i,
+                               double *out_k);
+
+/* Wait for all work queued on the state and report a deferred error. */
+svlcov_status svlcov_sync(svlcov_state *h);
+
+/* Counters and the numerical diagnostics of the last update (waits). */
+svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out);
+
+/* The hipStream_t the state enqueues on. */
+void *svlcov_stream(svlcov_state *h);
+
+void svlcov_destroy(svlcov_state *h);
+
+const char *svlcov_status_str(svlcov_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVLCOV_H */

@@ -1,0 +1,251 @@
+"""Python binding of libsvlcov.so (ctypes; argument marshalling only).
+
+Every step of an update runs in the library's HIP kernels; this module only
+turns NumPy arrays or torch tensors into the C structs and pointers the C ABI
+takes, and raises on non-OK status codes.  It never falls back to another
+implementation: if the shared library is missing or fails to load, importing
+the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+try:
+    # torch and this library must share one HIP runtime: both link
+    # libamdhip64.so.7, and the first copy loaded into the process is the one
+    # every later user binds to.  Loading torch first keeps its device memory
+    # and streams valid for the library.
+    import torch  # noqa: F401
+except ImportError:  # CPU-only environments without torch
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsvlcov.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+_STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "out of device memory",
+           4: "non-finite value", 5: "HIP runtime error", 6: "state busy",
+           7: "unsupported size or option"}
+
+
+class SvlcovError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {_STATUS.get(code, code)} (status {code})")
+        self.code = code
+
+
+class _Csr(C.Structure):
+    _fields_ = [("rows", C.c_int64), ("cols", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("val_dtype", C.c_int32), ("on_device", C.c_int32)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
+                ("row_capacity", C.c_int64), ("col_capacity", C.c_int64),
+                ("rank_tol", C.c_double), ("cond_reset", C.c_double),
+                ("validate_device_inputs", C.c_int32)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("updates", C.c_int64), ("resets_U", C.c_int64), ("resets_V", C.c_int64),
+                ("last_rank", C.c_int32), ("last_rank2", C.c_int32),
+                ("last_kappa_U", C.c_double), ("last_kappa_V", C.c_double),
+                ("last_min_kept_pivot", C.c_double), ("last_max_dropped_pivot", C.c_double)]
+
+
+EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_add_cols",
+           "svlcov_update_weights", "svlcov_get_factors", "svlcov_query_row", "svlcov_sync",
+           "svlcov_get_stats", "svlcov_stream", "svlcov_destroy", "svlcov_status_str"]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libsvlcov.so not built at {path}; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.svlcov_default_options.argtypes = [C.POINTER(_Options)]
+    lib.svlcov_default_options.restype = None
+    lib.svlcov_init.argtypes = [C.POINTER(P), I64, I64, I32, P, P, P, I32, C.POINTER(_Options)]
+    lib.svlcov_add_rows.argtypes = [P, C.POINTER(_Csr)]
+    lib.svlcov_add_cols.argtypes = [P, C.POINTER(_Csr)]
+    lib.svlcov_update_weights.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Csr)]
+    lib.svlcov_get_factors.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), I32,
+                                       I32, P, P, P]
+    lib.svlcov_query_row.argtypes = [P, I32, I64, P]
+    lib.svlcov_sync.argtypes = [P]
+    lib.svlcov_get_stats.argtypes = [P, C.POINTER(_Stats)]
+    lib.svlcov_stream.argtypes = [P]
+    lib.svlcov_stream.restype = P
+    lib.svlcov_destroy.argtypes = [P]
+    lib.svlcov_destroy.restype = None
+    lib.svlcov_status_str.argtypes = [I32]
+    lib.svlcov_status_str.restype = C.c_char_p
+    for name in ("svlcov_init", "svlcov_add_rows", "svlcov_add_cols", "svlcov_update_weights",
+                 "svlcov_get_factors", "svlcov_query_row", "svlcov_sync", "svlcov_get_stats"):
+        getattr(lib, name).restype = I32
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise SvlcovError(code, where)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class DeviceCSR:
+    """CSR whose arrays are torch tensors on the GPU (int64 row_ptr, int32
+    col_idx, float64/float32 val).  Keeps the tensors alive."""
+
+    def __init__(self, rows, cols, row_ptr, col_idx, val):
+        self.rows, self.cols = int(rows), int(cols)
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+
+    @staticmethod
+    def from_host(m, device="cuda"):
+        import torch
+        return DeviceCSR(m.rows, m.cols,
+                         torch.as_tensor(np.ascontiguousarray(m.row_ptr, dtype=np.int64), device=device),
+                         torch.as_tensor(np.ascontiguousarray(m.col_idx, dtype=np.int32), device=device),
+                         torch.as_tensor(np.ascontiguousarray(m.val, dtype=np.float64), device=device))
+
+
+def _csr_struct(m, keep: list) -> _Csr:
+    """Marshal a CSR given with .rows .cols .row_ptr .col_idx .val (NumPy
+    arrays = host, CUDA torch tensors = device)."""
+    rp, ci, v = m.row_ptr, m.col_idx, m.val
+    if _is_torch(rp):
+        import torch
+        assert rp.dtype == torch.int64 and ci.dtype == torch.int32
+        assert v.dtype in (torch.float64, torch.float32)
+        for t in (rp, ci, v):
+            assert t.is_cuda and t.is_contiguous()
+        keep.extend([rp, ci, v])
+        return _Csr(m.rows, m.cols, int(ci.numel()),
+                    rp.data_ptr(), ci.data_ptr(), v.data_ptr(),
+                    1 if v.dtype == torch.float64 else 0, 1)
+    rp = np.ascontiguousarray(rp, dtype=np.int64)
+    ci = np.ascontiguousarray(ci, dtype=np.int32)
+    v = np.ascontiguousarray(v)
+    if v.dtype not in (np.float64, np.float32):
+        v = v.astype(np.float64)
+    keep.extend([rp, ci, v])
+    return _Csr(int(m.rows), int(m.cols), int(ci.size), rp.ctypes.data, ci.ctypes.data,
+                v.ctypes.data, 1 if v.dtype == np.float64 else 0, 0)
+
+
+class TruncatedSVD:
+    """A rank-k truncated SVD kept on the GPU in the extended form
+    U = U_base W_U, V = V_base W_V (Section 3.2), updated by the library."""
+
+    def __init__(self, U, s, V, precision: str = "fp64", device: int = 0, stream=None,
+                 row_capacity: int = 0, col_capacity: int = 0, rank_tol: float = 0.0,
+                 cond_reset: float = 0.0, validate_device_inputs: bool = True):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        opt = _Options()
+        _lib.svlcov_default_options(C.byref(opt))
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opt.device = device
+        opt.stream = stream
+        opt.row_capacity = row_capacity
+        opt.col_capacity = col_capacity
+        opt.rank_tol = rank_tol
+        opt.cond_reset = cond_reset
+        opt.validate_device_inputs = 1 if validate_device_inputs else 0
+        h = C.c_void_p()
+        _check(_lib.svlcov_init(C.byref(h), U.shape[0], V.shape[0], s.size, U.ctypes.data,
+                                s.ctypes.data, V.ctypes.data, 0, C.byref(opt)), "svlcov_init")
+        self._h = h
+        self.k = int(s.size)
+        self.precision = precision
+        self._keep = []
+
+    # -- updates (asynchronous; inputs must stay alive until sync)
+    def add_rows(self, E):
+        st = _csr_struct(E, self._keep)
+        _check(_lib.svlcov_add_rows(self._h, C.byref(st)), "svlcov_add_rows")
+
+    def add_cols(self, Ec_T):
+        st = _csr_struct(Ec_T, self._keep)
+        _check(_lib.svlcov_add_cols(self._h, C.byref(st)), "svlcov_add_cols")
+
+    def update_weights(self, D_T, Em_T):
+        a = _csr_struct(D_T, self._keep)
+        b = _csr_struct(Em_T, self._keep)
+        _check(_lib.svlcov_update_weights(self._h, C.byref(a), C.byref(b)),
+               "svlcov_update_weights")
+
+    def apply(self, update):
+        kind = update[0]
+        if kind == "rows":
+            self.add_rows(update[1])
+        elif kind == "cols":
+            self.add_cols(update[1])
+        elif kind == "weights":
+            self.update_weights(update[1], update[2])
+        else:
+            raise ValueError(kind)
+
+    def sync(self):
+        code = _lib.svlcov_sync(self._h)
+        self._keep = []
+        _check(code, "svlcov_sync")
+
+    @property
+    def stream(self) -> int:
+        return int(_lib.svlcov_stream(self._h) or 0)
+
+    def shape(self):
+        m, n, k = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_lib.svlcov_get_factors(self._h, C.byref(m), C.byref(n), C.byref(k), 1, 0,
+                                       None, None, None), "svlcov_get_factors")
+        return m.value, n.value
+
+    def factors(self, dtype=np.float64):
+        """Realised (U, s, V) as host NumPy arrays."""
+        m, n = self.shape()
+        U = np.empty((m, self.k), dtype=dtype)
+        V = np.empty((n, self.k), dtype=dtype)
+        s = np.empty(self.k, dtype=np.float64)
+        _check(_lib.svlcov_get_factors(self._h, None, None, None,
+                                       1 if dtype == np.float64 else 0, 0, U.ctypes.data,
+                                       s.ctypes.data, V.ctypes.data), "svlcov_get_factors")
+        self._keep = []
+        return U, s, V
+
+    def query(self, side: int, i: int):
+        out = np.empty(self.k, dtype=np.float64)
+        _check(_lib.svlcov_query_row(self._h, side, i, out.ctypes.data), "svlcov_query_row")
+        return out
+
+    def stats(self) -> dict:
+        st = _Stats()
+        _check(_lib.svlcov_get_stats(self._h, C.byref(st)), "svlcov_get_stats")
+        return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.svlcov_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "load_library", "LIB_PATH", "EXPORTS",
+           "FP64", "FP32", "BF16X3"]

@@ -1,0 +1,93 @@
+// Shared device helpers for the gfx950 kernels (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SV_WAVE 64
+
+namespace svk {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide sum; every thread returns the same value (fixed summation order,
+// so identical inputs give bitwise identical results in every block).
+// red must hold blockDim.x / 64 doubles.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += red[i];
+  return t;
+}
+
+__device__ __forceinline__ double block_max(double v, double *red) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int i = 1; i < nw; ++i) t = fmax(t, red[i]);
+  return t;
+}
+
+template <typename T>
+__device__ __forceinline__ double load_val(const void *p, int64_t i);
+template <>
+__device__ __forceinline__ double load_val<float>(const void *p, int64_t i) {
+  return (double)((const float *)p)[i];
+}
+template <>
+__device__ __forceinline__ double load_val<double>(const void *p, int64_t i) {
+  return ((const double *)p)[i];
+}
+
+// Deterministic pseudo-random double in [-1, 1) from a 64-bit key
+// (SplitMix64 finaliser).
+__device__ __forceinline__ double hash_unit(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+}  // namespace svk
+
+// Device status word layout (one per state).
+struct SvDevInfo {
+  int32_t status;       // 0 ok; else the svlcov_status of the first failure
+  int32_t failed_seq;   // sequence number of the update that failed
+  int32_t rank;         // kept pivots, first orthogonalisation of last update
+  int32_t rank2;        // second orthogonalisation (weights) or -1
+  int32_t reset_U;      // set by the condition check of the last update
+  int32_t reset_V;
+  int32_t pad0, pad1;
+  double kappa_U, kappa_V;
+  double min_kept, max_dropped;   // relative pivots of the last Cholesky
+  double scale;                   // max_i ||e_i||^2 of the last Gram
+  double scale2;
+  int64_t resets_U, resets_V;
+  int64_t updates;
+};

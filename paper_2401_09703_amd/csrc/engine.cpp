@@ -1,0 +1,774 @@
+// Update engine and C ABI: the factor state of one matrix in the extended
+// decomposition (Section 3.2), host-side validation, workspace management and
+// the step sequence of each update (Algorithms 3, 4 and 11), every step of
+// which is a kernel on the state's stream.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/svlcov.h"
+#include "kernels.hpp"
+
+namespace {
+
+constexpr double DEF_TOL[3] = {1e-13, 1e-6, 1e-5};   // FP64, FP32, BF16X3
+constexpr double DEF_COND[3] = {1e8, 1e2, 1e2};
+
+struct Snapshot {
+  int seq;
+  int64_t m, n;
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct svlcov_state {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int prec = SVLCOV_FP64;
+  int k = 0;
+  int64_t m = 0, n = 0;
+  int64_t capU = 0, capV = 0;
+  void *Ubase = nullptr, *Vbase = nullptr;  // double (FP64) or float
+  double *WU = nullptr, *WV = nullptr, *sigma = nullptr;
+  SvDevInfo *info = nullptr;
+  DevBuf ws;        // update workspace
+  DevBuf stage;     // device copies of host CSR inputs
+  DevBuf outbuf;    // get_factors staging
+  double rank_tol = 0, cond_reset = 0;
+  int validate = 1;
+  int seq = 0;
+  std::vector<Snapshot> history;
+  std::atomic<bool> busy{false};
+  size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
+};
+
+namespace {
+
+struct BusyGuard {
+  svlcov_state *h;
+  bool ok;
+  explicit BusyGuard(svlcov_state *hh) : h(hh) {
+    bool expected = false;
+    ok = h->busy.compare_exchange_strong(expected, true);
+  }
+  ~BusyGuard() {
+    if (ok) h->busy.store(false);
+  }
+};
+
+svlcov_status dev_err(hipError_t e) {
+  if (e == hipSuccess) return SVLCOV_OK;
+  if (e == hipErrorOutOfMemory) return SVLCOV_E_NOMEM;
+  return SVLCOV_E_DEVICE;
+}
+
+#define SV_TRY(expr)                                   \
+  do {                                                 \
+    svlcov_status _s = dev_err(expr);                  \
+    if (_s != SVLCOV_OK) return _s;                    \
+  } while (0)
+
+svlcov_status ensure(svlcov_state *h, DevBuf &b, size_t bytes) {
+  if (b.bytes >= bytes) return SVLCOV_OK;
+  size_t want = bytes + bytes / 4 + 4096;
+  if (b.p) SV_TRY(hipFreeAsync(b.p, h->stream));
+  b.p = nullptr;
+  b.bytes = 0;
+  SV_TRY(hipMallocAsync(&b.p, want, h->stream));
+  b.bytes = want;
+  return SVLCOV_OK;
+}
+
+// Grow the row capacity of a tall factor (rows x k), keeping its contents.
+svlcov_status grow_base(svlcov_state *h, void **base, int64_t *cap, int64_t rows_used,
+                        int64_t need) {
+  if (need <= *cap) return SVLCOV_OK;
+  int64_t ncap = *cap + *cap / 2;
+  if (ncap < need) ncap = need;
+  void *nb = nullptr;
+  SV_TRY(hipMallocAsync(&nb, (size_t)ncap * h->k * h->elem(), h->stream));
+  if (rows_used > 0)
+    SV_TRY(hipMemcpyAsync(nb, *base, (size_t)rows_used * h->k * h->elem(),
+                          hipMemcpyDeviceToDevice, h->stream));
+  if (*base) SV_TRY(hipFreeAsync(*base, h->stream));
+  *base = nb;
+  *cap = ncap;
+  return SVLCOV_OK;
+}
+
+bool finite_vals(const void *v, int dt, int64_t n) {
+  if (dt == SVLCOV_F64) {
+    const double *x = (const double *)v;
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(x[i])) return false;
+  } else {
+    const float *x = (const float *)v;
+    for (int64_t i = 0; i < n; ++i)
+      if (!std::isfinite(x[i])) return false;
+  }
+  return true;
+}
+
+// Host check of a canonical CSR (only for host-resident inputs).
+svlcov_status check_host_csr(const svlcov_csr *E) {
+  if (!E->row_ptr || (E->nnz > 0 && (!E->col_idx || !E->val))) return SVLCOV_E_INVALID;
+  if (E->row_ptr[0] != 0 || E->row_ptr[E->rows] != E->nnz) return SVLCOV_E_INVALID;
+  for (int64_t i = 0; i < E->rows; ++i) {
+    const int64_t p0 = E->row_ptr[i], p1 = E->row_ptr[i + 1];
+    if (p0 < 0 || p1 < p0 || p1 > E->nnz) return SVLCOV_E_INVALID;
+    int32_t prev = -1;
+    for (int64_t p = p0; p < p1; ++p) {
+      const int32_t c = E->col_idx[p];
+      if (c <= prev || c >= E->cols) return SVLCOV_E_INVALID;
+      prev = c;
+    }
+  }
+  if (!finite_vals(E->val, E->val_dtype, E->nnz)) return SVLCOV_E_NUMERIC;
+  return SVLCOV_OK;
+}
+
+svlcov_status check_csr_header(const svlcov_csr *E) {
+  if (!E) return SVLCOV_E_INVALID;
+  if (E->rows < 0 || E->cols < 0 || E->nnz < 0) return SVLCOV_E_INVALID;
+  if (E->val_dtype != SVLCOV_F32 && E->val_dtype != SVLCOV_F64) return SVLCOV_E_INVALID;
+  if (E->nnz > INT32_MAX || E->cols > INT32_MAX) return SVLCOV_E_UNSUPPORTED;
+  return SVLCOV_OK;
+}
+
+// Device view of a CSR input (host inputs are copied into `stage` at `off`).
+struct DevCsr {
+  int64_t rows, cols, nnz;
+  const int64_t *rp;
+  const int32_t *ci;
+  const void *v;
+  int vdt;
+};
+
+size_t csr_stage_bytes(const svlcov_csr *E) {
+  if (E->on_device) return 0;
+  const size_t vb = E->val_dtype == SVLCOV_F64 ? 8 : 4;
+  return ((size_t)(E->rows + 1) * 8 + 255) / 256 * 256 + ((size_t)E->nnz * 4 + 255) / 256 * 256 +
+         ((size_t)E->nnz * vb + 255) / 256 * 256;
+}
+
+svlcov_status to_device(svlcov_state *h, const svlcov_csr *E, char *&cursor, DevCsr *out) {
+  out->rows = E->rows;
+  out->cols = E->cols;
+  out->nnz = E->nnz;
+  out->vdt = E->val_dtype == SVLCOV_F64 ? 1 : 0;
+  if (E->on_device) {
+    out->rp = E->row_ptr;
+    out->ci = E->col_idx;
+    out->v = E->val;
+    return SVLCOV_OK;
+  }
+  const size_t vb = E->val_dtype == SVLCOV_F64 ? 8 : 4;
+  const size_t b_rp = (size_t)(E->rows + 1) * 8, b_ci = (size_t)E->nnz * 4,
+               b_v = (size_t)E->nnz * vb;
+  char *prp = cursor;
+  cursor += (b_rp + 255) / 256 * 256;
+  char *pci = cursor;
+  cursor += (b_ci + 255) / 256 * 256;
+  char *pv = cursor;
+  cursor += (b_v + 255) / 256 * 256;
+  SV_TRY(hipMemcpyAsync(prp, E->row_ptr, b_rp, hipMemcpyHostToDevice, h->stream));
+  if (b_ci) SV_TRY(hipMemcpyAsync(pci, E->col_idx, b_ci, hipMemcpyHostToDevice, h->stream));
+  if (b_v) SV_TRY(hipMemcpyAsync(pv, E->val, b_v, hipMemcpyHostToDevice, h->stream));
+  out->rp = (const int64_t *)prp;
+  out->ci = (const int32_t *)pci;
+  out->v = pv;
+  return SVLCOV_OK;
+}
+
+// Workspace carving (all regions 256-byte aligned).
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <typename T>
+  T *take(size_t count) {
+    T *p = (T *)(base ? base + off : nullptr);
+    off += (count * sizeof(T) + 255) / 256 * 256;
+    return p;
+  }
+};
+
+int mode_of(int prec) { return prec == SVLCOV_FP64 ? 0 : (prec == SVLCOV_FP32 ? 1 : 2); }
+
+// One side's orthogonalisation: projection, sparse Gram, residual Gram and its
+// Cholesky (Algorithm 2 realised as R^T R = E E^T - (E V)(E V)^T, Lemma 3).
+template <typename T>
+void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
+                   float *Cp32, double *rown, double *Gm, double *Linv, int which) {
+  const int K = h->k;
+  const int64_t s = E.rows;
+  hipStream_t st = h->stream;
+  svl::spmm_w<T>(st, K, s, E.rp, E.ci, E.v, E.vdt, base, W, Cp64,
+                 h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info);
+  svl::sparse_gram(st, s, E.rp, E.ci, E.v, E.vdt, Gm, s, h->info);
+  if (h->prec == SVLCOV_FP64)
+    svl::gemm_f64(st, false, true, s, s, K, -1.0, Cp64, K, Cp64, K, 1.0, Gm, s, h->info);
+  else
+    svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
+  svl::max_into(st, s, rown, h->info, which);
+  svl::cholesky_drop(st, s, Gm, s, Linv, h->rank_tol, h->info, which);
+}
+
+// The (k+s) Rayleigh-Ritz SVD of K (N x N) through the eigenpairs of K K^T:
+// F (rows of Fv) are the left singular vectors, theta the singular values,
+// G = K^T F diag(theta)^{-1} the right ones (rows of Gv); both sets are
+// re-orthonormalised, with an orthonormal completion where theta vanishes.
+svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mmat, double *lam,
+                            double *theta, int32_t *complete, double *Fv, double *Gv,
+                            double *eigw) {
+  const int K = h->k;
+  hipStream_t st = h->stream;
+  svl::gemm_f64(st, false, true, N, N, N, 1.0, Kmat, N, Kmat, N, 0.0, Mmat, N, h->info);
+  if (svl::eig_topk(st, N, Mmat, K, lam, Fv, eigw, h->info) != 0) return SVLCOV_E_DEVICE;
+  svl::gemm_f64(st, false, false, K, N, N, 1.0, Fv, N, Kmat, N, 0.0, Gv, N, h->info);
+  svl::theta_scale(st, K, lam, theta, Gv, N, complete, h->info);
+  svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, h->info);
+  svl::orthonormalize_rows(st, K, N, Gv, complete, (uint64_t)h->seq * 2 + 2, h->info);
+  svl::check_finite(st, K, theta, h->info, h->seq);
+  return SVLCOV_OK;
+}
+
+// The sparse-side factor update (Equation (1)): Y = T X[k:] with T = L^{-T}
+// (the normalisation of Algorithm 2), Wnew = W (X[:k] - C_n X[k:]) with
+// C_n X[k:] = Cp^T Y.  X is given by rows (Xv, K x N).
+void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, const double *Cp64,
+                      const double *L, const double *Linv, const double *W, double *Y,
+                      double *T1, double *Wnew, double *Winv, int32_t *flag, int side) {
+  const int K = h->k;
+  hipStream_t st = h->stream;
+  svl::copy_strided(st, s, K, Xv + K, 1, N, Y, K, h->info);
+  svl::trsm_lt(st, s, K, L, s, Linv, Y, h->info);
+  svl::copy_strided(st, K, K, Xv, 1, N, T1, K, h->info);
+  svl::gemm_f64(st, true, false, K, K, s, -1.0, Cp64, K, Y, K, 1.0, T1, K, h->info);
+  svl::gemm_f64(st, false, false, K, K, K, 1.0, W, K, T1, K, 0.0, Wnew, K, h->info);
+  svl::inverse_cond(st, K, Wnew, Winv, flag, h->cond_reset, h->info, side);
+}
+
+template <typename T>
+void sparse_side_commit(svlcov_state *h, const DevCsr &E, int64_t rows_used, T *base,
+                        const double *Y, double *Mupd, const double *Wnew, const double *Winv,
+                        const int32_t *flag, double *W, const double *theta, double *sig,
+                        int side) {
+  const int K = h->k;
+  hipStream_t st = h->stream;
+  const int mode = mode_of(h->prec);
+  svl::realise<T, T>(st, mode, K, rows_used, base, Wnew, base, flag, h->info);
+  svl::append_rows<double>(st, K, E.rows, Y, K, 1, Winv, flag, Mupd, h->info);
+  svl::scatter<T>(st, K, E.rows, E.rp, E.ci, E.v, E.vdt, Mupd, base, h->info);
+  svl::commit_small(st, K, Wnew, flag, W, theta, sig, h->info, side);
+}
+
+// Row-append form shared by add_rows (append side U, sparse side V) and
+// add_cols (append side V, sparse side U, the transpose of the same problem).
+template <typename T>
+svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
+  svlcov_status r = check_csr_header(E);
+  if (r != SVLCOV_OK) return r;
+  const int K = h->k;
+  const int64_t s = E->rows;
+  const int64_t nB = rows_form ? h->n : h->m;   // width of E
+  const int64_t nA = rows_form ? h->m : h->n;   // rows of the append side
+  if (E->cols != nB) return SVLCOV_E_SHAPE;
+  if (s == 0) return SVLCOV_OK;
+  if (K + s > svl::eig_max_n()) return SVLCOV_E_UNSUPPORTED;
+  if (!E->on_device) {
+    r = check_host_csr(E);
+    if (r != SVLCOV_OK) return r;
+  }
+  void **Abase = rows_form ? &h->Ubase : &h->Vbase;
+  int64_t *Acap = rows_form ? &h->capU : &h->capV;
+  r = grow_base(h, Abase, Acap, nA, nA + s);
+  if (r != SVLCOV_OK) return r;
+  T *A_base = (T *)*Abase;
+  T *B_base = (T *)(rows_form ? h->Vbase : h->Ubase);
+  double *W_A = rows_form ? h->WU : h->WV;
+  double *W_B = rows_form ? h->WV : h->WU;
+  const int sideA = rows_form ? 0 : 1, sideB = 1 - sideA;
+  const int64_t N = K + s;
+  // workspace
+  Carver c{nullptr};
+  auto layout = [&](Carver &cv, double **Cp64, float **Cp32, double **rown, double **Gm,
+                    double **Linv, double **Kmat, double **Mmat, double **lam, double **theta,
+                    int32_t **complete, double **Fv, double **Gv, double **eigw, double **Y,
+                    double **T1, double **WnA, double **WiA, double **WnB, double **WiB,
+                    double **Mupd, int32_t **flags) {
+    *Cp64 = cv.take<double>(s * K);
+    *Cp32 = cv.take<float>(s * K);
+    *rown = cv.take<double>(s);
+    *Gm = cv.take<double>(s * s);
+    *Linv = cv.take<double>(((s + svl::CHOL_NB - 1) / svl::CHOL_NB) * svl::CHOL_NB * svl::CHOL_NB);
+    *Kmat = cv.take<double>(N * N);
+    *Mmat = cv.take<double>(N * N);
+    *lam = cv.take<double>(K);
+    *theta = cv.take<double>(K);
+    *complete = cv.take<int32_t>(K);
+    *Fv = cv.take<double>(K * N);
+    *Gv = cv.take<double>(K * N);
+    *eigw = cv.take<double>(svl::eig_work_doubles(N, K));
+    *Y = cv.take<double>(s * K);
+    *T1 = cv.take<double>(K * K);
+    *WnA = cv.take<double>(K * K);
+    *WiA = cv.take<double>(K * K);
+    *WnB = cv.take<double>(K * K);
+    *WiB = cv.take<double>(K * K);
+    *Mupd = cv.take<double>(s * K);
+    *flags = cv.take<int32_t>(2);
+  };
+  double *Cp64, *rown, *Gm, *Linv, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA,
+      *WiA, *WnB, *WiB, *Mupd;
+  float *Cp32;
+  int32_t *complete, *flags;
+  layout(c, &Cp64, &Cp32, &rown, &Gm, &Linv, &Kmat, &Mmat, &lam, &theta, &complete, &Fv, &Gv,
+         &eigw, &Y, &T1, &WnA, &WiA, &WnB, &WiB, &Mupd, &flags);
+  r = ensure(h, h->ws, c.off);
+  if (r != SVLCOV_OK) return r;
+  r = ensure(h, h->stage, csr_stage_bytes(E) + 256);
+  if (r != SVLCOV_OK) return r;
+  Carver c2{(char *)h->ws.p};
+  layout(c2, &Cp64, &Cp32, &rown, &Gm, &Linv, &Kmat, &Mmat, &lam, &theta, &complete, &Fv, &Gv,
+         &eigw, &Y, &T1, &WnA, &WiA, &WnB, &WiB, &Mupd, &flags);
+  char *cursor = (char *)h->stage.p;
+  DevCsr dE;
+  r = to_device(h, E, cursor, &dE);
+  if (r != SVLCOV_OK) return r;
+
+  h->seq += 1;
+  h->history.push_back({h->seq, h->m, h->n});
+  hipStream_t st = h->stream;
+  if (E->on_device && h->validate)
+    svl::validate_csr(st, dE.rows, dE.cols, dE.nnz, dE.rp, dE.ci, dE.v, dE.vdt, h->info, h->seq);
+  svl::op_begin(st, h->info, 0);
+  // orthogonalise the augmented matrix of the sparse side
+  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, 0);
+  // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
+  svl::build_K_rows(st, K, s, h->sigma, Cp64, Gm, s, Kmat, h->info);
+  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw);
+  if (r != SVLCOV_OK) return r;
+  // append side: W_A F[:k]; its inverse and condition
+  svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
+  svl::inverse_cond(st, K, WnA, WiA, flags, h->cond_reset, h->info, sideA);
+  // sparse side: W_B (G[:k] - C_n G[k:])
+  sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB);
+  svl::check_finite(st, K * K, WnB, h->info, h->seq);
+  svl::check_finite(st, K * K, WnA, h->info, h->seq);
+  // commit: append side (realise on reset, appended rows F[k:] W^{-1})
+  const int mode = mode_of(h->prec);
+  svl::realise<T, T>(st, mode, K, nA, A_base, WnA, A_base, flags, h->info);
+  svl::append_rows<T>(st, K, s, Fv + K, 1, N, WiA, flags, A_base + nA * K, h->info);
+  svl::commit_small(st, K, WnA, flags, W_A, theta, h->sigma, h->info, sideA);
+  // commit: sparse side
+  sparse_side_commit<T>(h, dE, nB, B_base, Y, Mupd, WnB, WiB, flags + 1, W_B, nullptr, nullptr,
+                        sideB);
+  svl::op_end(st, h->info);
+  if (rows_form) h->m += s; else h->n += s;
+  return SVLCOV_OK;
+}
+
+template <typename T>
+svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr *Em) {
+  svlcov_status r = check_csr_header(D);
+  if (r != SVLCOV_OK) return r;
+  r = check_csr_header(Em);
+  if (r != SVLCOV_OK) return r;
+  const int K = h->k;
+  if (D->rows != Em->rows) return SVLCOV_E_SHAPE;
+  if (D->cols != h->m || Em->cols != h->n) return SVLCOV_E_SHAPE;
+  const int64_t s = D->rows;
+  if (s == 0) return SVLCOV_OK;
+  if (K + s > svl::eig_max_n()) return SVLCOV_E_UNSUPPORTED;
+  if (!D->on_device) { r = check_host_csr(D); if (r != SVLCOV_OK) return r; }
+  if (!Em->on_device) { r = check_host_csr(Em); if (r != SVLCOV_OK) return r; }
+  const int64_t N = K + s;
+  T *Ub = (T *)h->Ubase, *Vb = (T *)h->Vbase;
+  auto layout = [&](Carver &cv, double **CpD, double **CpE, float **C32D, float **C32E,
+                    double **rnD, double **rnE, double **GD, double **GE, double **LiD,
+                    double **LiE, double **X, double **Yx, double **Kmat, double **Mmat,
+                    double **lam, double **theta, int32_t **complete, double **Fv, double **Gv,
+                    double **eigw, double **YD, double **YE, double **T1, double **WnU,
+                    double **WiU, double **WnV, double **WiV, double **MD, double **ME,
+                    int32_t **flags) {
+    const size_t nbl = ((s + svl::CHOL_NB - 1) / svl::CHOL_NB) * svl::CHOL_NB * svl::CHOL_NB;
+    *CpD = cv.take<double>(s * K); *CpE = cv.take<double>(s * K);
+    *C32D = cv.take<float>(s * K); *C32E = cv.take<float>(s * K);
+    *rnD = cv.take<double>(s); *rnE = cv.take<double>(s);
+    *GD = cv.take<double>(s * s); *GE = cv.take<double>(s * s);
+    *LiD = cv.take<double>(nbl); *LiE = cv.take<double>(nbl);
+    *X = cv.take<double>(N * s); *Yx = cv.take<double>(N * s);
+    *Kmat = cv.take<double>(N * N); *Mmat = cv.take<double>(N * N);
+    *lam = cv.take<double>(K); *theta = cv.take<double>(K);
+    *complete = cv.take<int32_t>(K);
+    *Fv = cv.take<double>(K * N); *Gv = cv.take<double>(K * N);
+    *eigw = cv.take<double>(svl::eig_work_doubles(N, K));
+    *YD = cv.take<double>(s * K); *YE = cv.take<double>(s * K);
+    *T1 = cv.take<double>(K * K);
+    *WnU = cv.take<double>(K * K); *WiU = cv.take<double>(K * K);
+    *WnV = cv.take<double>(K * K); *WiV = cv.take<double>(K * K);
+    *MD = cv.take<double>(s * K); *ME = cv.take<double>(s * K);
+    *flags = cv.take<int32_t>(2);
+  };
+  double *CpD, *CpE, *rnD, *rnE, *GD, *GE, *LiD, *LiE, *X, *Yx, *Kmat, *Mmat, *lam, *theta, *Fv,
+      *Gv, *eigw, *YD, *YE, *T1, *WnU, *WiU, *WnV, *WiV, *MD, *ME;
+  float *C32D, *C32E;
+  int32_t *complete, *flags;
+  Carver c{nullptr};
+  layout(c, &CpD, &CpE, &C32D, &C32E, &rnD, &rnE, &GD, &GE, &LiD, &LiE, &X, &Yx, &Kmat, &Mmat,
+         &lam, &theta, &complete, &Fv, &Gv, &eigw, &YD, &YE, &T1, &WnU, &WiU, &WnV, &WiV, &MD,
+         &ME, &flags);
+  r = ensure(h, h->ws, c.off);
+  if (r != SVLCOV_OK) return r;
+  r = ensure(h, h->stage, csr_stage_bytes(D) + csr_stage_bytes(Em) + 512);
+  if (r != SVLCOV_OK) return r;
+  Carver c2{(char *)h->ws.p};
+  layout(c2, &CpD, &CpE, &C32D, &C32E, &rnD, &rnE, &GD, &GE, &LiD, &LiE, &X, &Yx, &Kmat, &Mmat,
+         &lam, &theta, &complete, &Fv, &Gv, &eigw, &YD, &YE, &T1, &WnU, &WiU, &WnV, &WiV, &MD,
+         &ME, &flags);
+  char *cursor = (char *)h->stage.p;
+  DevCsr dD, dEm;
+  r = to_device(h, D, cursor, &dD);
+  if (r != SVLCOV_OK) return r;
+  r = to_device(h, Em, cursor, &dEm);
+  if (r != SVLCOV_OK) return r;
+
+  h->seq += 1;
+  h->history.push_back({h->seq, h->m, h->n});
+  hipStream_t st = h->stream;
+  if (h->validate) {
+    if (D->on_device)
+      svl::validate_csr(st, dD.rows, dD.cols, dD.nnz, dD.rp, dD.ci, dD.v, dD.vdt, h->info, h->seq);
+    if (Em->on_device)
+      svl::validate_csr(st, dEm.rows, dEm.cols, dEm.nnz, dEm.rp, dEm.ci, dEm.v, dEm.vdt, h->info,
+                        h->seq);
+  }
+  svl::op_begin(st, h->info, 1);
+  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, 0);
+  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, 1);
+  // K = [[Sigma, 0], [0, 0]] + [U^T D ; R_D] [V^T E_m ; R_E]^T
+  svl::build_X(st, K, s, CpD, GD, s, X, h->info);
+  svl::build_X(st, K, s, CpE, GE, s, Yx, h->info);
+  svl::gemm_f64(st, false, true, N, N, s, 1.0, X, s, Yx, s, 0.0, Kmat, N, h->info);
+  svl::add_sigma_diag(st, K, h->sigma, Kmat, N, h->info);
+  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw);
+  if (r != SVLCOV_OK) return r;
+  sparse_side_math(h, s, N, Fv, CpD, GD, LiD, h->WU, YD, T1, WnU, WiU, flags, 0);
+  sparse_side_math(h, s, N, Gv, CpE, GE, LiE, h->WV, YE, T1, WnV, WiV, flags + 1, 1);
+  svl::check_finite(st, K * K, WnU, h->info, h->seq);
+  svl::check_finite(st, K * K, WnV, h->info, h->seq);
+  sparse_side_commit<T>(h, dD, h->m, Ub, YD, MD, WnU, WiU, flags, h->WU, theta, h->sigma, 0);
+  sparse_side_commit<T>(h, dEm, h->n, Vb, YE, ME, WnV, WiV, flags + 1, h->WV, nullptr, nullptr, 1);
+  svl::op_end(st, h->info);
+  return SVLCOV_OK;
+}
+
+svlcov_status read_info(svlcov_state *h, SvDevInfo *out) {
+  SV_TRY(hipMemcpyAsync(out, h->info, sizeof(SvDevInfo), hipMemcpyDeviceToHost, h->stream));
+  SV_TRY(hipStreamSynchronize(h->stream));
+  return SVLCOV_OK;
+}
+
+// Wait, then turn a device-side failure into a return code and roll the host
+// shape back to what it was before the failing update.
+svlcov_status settle(svlcov_state *h) {
+  SvDevInfo inf;
+  svlcov_status r = read_info(h, &inf);
+  if (r != SVLCOV_OK) return r;
+  if (inf.status == 0) {
+    h->history.clear();
+    return SVLCOV_OK;
+  }
+  const svlcov_status code = (svlcov_status)inf.status;
+  for (const Snapshot &sn : h->history) {
+    if (sn.seq == inf.failed_seq || inf.failed_seq < 0) {
+      h->m = sn.m;
+      h->n = sn.n;
+      break;
+    }
+  }
+  h->history.clear();
+  int32_t zero[2] = {0, 0};
+  SV_TRY(hipMemcpyAsync(h->info, zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+  SV_TRY(hipStreamSynchronize(h->stream));
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+void svlcov_default_options(svlcov_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = SVLCOV_FP64;
+  o->device = 0;
+  o->stream = nullptr;
+  o->rank_tol = 0.0;
+  o->cond_reset = 0.0;
+  o->validate_device_inputs = 1;
+}
+
+svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k, const double *U,
+                          const double *sigma, const double *V, int32_t factors_on_device,
+                          const svlcov_options *opt) {
+  if (!out) return SVLCOV_E_INVALID;
+  *out = nullptr;
+  if (m < 0 || n < 0 || !sigma) return SVLCOV_E_INVALID;
+  if (k != 16 && k != 32 && k != 64 && k != 128) return SVLCOV_E_UNSUPPORTED;
+  if ((m > 0 && !U) || (n > 0 && !V)) return SVLCOV_E_INVALID;
+  svlcov_options o;
+  if (opt) o = *opt; else svlcov_default_options(&o);
+  if (o.precision < 0 || o.precision > 2) return SVLCOV_E_INVALID;
+  if (!factors_on_device) {
+    for (int i = 0; i < k; ++i)
+      if (!std::isfinite(sigma[i]) || sigma[i] < 0 || (i > 0 && sigma[i] > sigma[i - 1]))
+        return SVLCOV_E_INVALID;
+    if (!finite_vals(U, SVLCOV_F64, m * k) || !finite_vals(V, SVLCOV_F64, n * k))
+      return SVLCOV_E_NUMERIC;
+  }
+  svlcov_state *h = new (std::nothrow) svlcov_state();
+  if (!h) return SVLCOV_E_NOMEM;
+  h->device = o.device;
+  h->prec = o.precision;
+  h->k = k;
+  h->m = m;
+  h->n = n;
+  h->rank_tol = o.rank_tol > 0 ? o.rank_tol : DEF_TOL[h->prec];
+  h->cond_reset = o.cond_reset > 0 ? o.cond_reset : DEF_COND[h->prec];
+  h->validate = o.validate_device_inputs ? 1 : 0;
+  auto fail = [&](svlcov_status s) {
+    svlcov_destroy(h);
+    return s;
+  };
+  if (hipSetDevice(h->device) != hipSuccess) return fail(SVLCOV_E_DEVICE);
+  if (o.stream) {
+    h->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(SVLCOV_E_DEVICE);
+    h->own_stream = true;
+  }
+  h->capU = o.row_capacity > m ? o.row_capacity : m + m / 4 + 1024;
+  h->capV = o.col_capacity > n ? o.col_capacity : n + n / 4 + 1024;
+  const size_t es = h->elem();
+  if (hipMalloc(&h->Ubase, (size_t)h->capU * k * es) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  if (hipMalloc(&h->Vbase, (size_t)h->capV * k * es) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  if (hipMalloc(&h->WU, (size_t)k * k * 8) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  if (hipMalloc(&h->WV, (size_t)k * k * 8) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  if (hipMalloc(&h->sigma, (size_t)k * 8) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  if (hipMalloc(&h->info, sizeof(SvDevInfo)) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  SvDevInfo zi;
+  std::memset(&zi, 0, sizeof(zi));
+  zi.rank2 = -1;
+  zi.max_dropped = -1.0;
+  hipMemcpyKind kind = factors_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (hipMemcpyAsync(h->info, &zi, sizeof(zi), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return fail(SVLCOV_E_DEVICE);
+  if (hipMemcpyAsync(h->sigma, sigma, (size_t)k * 8, kind, h->stream) != hipSuccess)
+    return fail(SVLCOV_E_DEVICE);
+  svl::fill_identity(h->stream, k, h->WU);
+  svl::fill_identity(h->stream, k, h->WV);
+  // U', V' start as the given singular vectors (converted to the storage type)
+  for (int side = 0; side < 2; ++side) {
+    const int64_t rows = side == 0 ? m : n;
+    const double *src = side == 0 ? U : V;
+    void *dst = side == 0 ? h->Ubase : h->Vbase;
+    if (rows == 0) continue;
+    if (h->prec == SVLCOV_FP64) {
+      if (hipMemcpyAsync(dst, src, (size_t)rows * k * 8, kind, h->stream) != hipSuccess)
+        return fail(SVLCOV_E_DEVICE);
+    } else {
+      const double *dsrc = src;
+      double *tmp = nullptr;
+      if (!factors_on_device) {
+        if (hipMallocAsync((void **)&tmp, (size_t)rows * k * 8, h->stream) != hipSuccess)
+          return fail(SVLCOV_E_NOMEM);
+        if (hipMemcpyAsync(tmp, src, (size_t)rows * k * 8, hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess)
+          return fail(SVLCOV_E_DEVICE);
+        dsrc = tmp;
+      }
+      // identity W: the realisation kernel doubles as a converting copy
+      svl::realise<double, float>(h->stream, 0, k, rows, dsrc, h->WU, (float *)dst, nullptr,
+                                  nullptr);
+      if (tmp) (void)hipFreeAsync(tmp, h->stream);
+    }
+  }
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return fail(SVLCOV_E_DEVICE);
+  *out = h;
+  return SVLCOV_OK;
+}
+
+svlcov_status svlcov_add_rows(svlcov_state *h, const svlcov_csr *E) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  return h->prec == SVLCOV_FP64 ? op_append<double>(h, E, true) : op_append<float>(h, E, true);
+}
+
+svlcov_status svlcov_add_cols(svlcov_state *h, const svlcov_csr *E) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  return h->prec == SVLCOV_FP64 ? op_append<double>(h, E, false) : op_append<float>(h, E, false);
+}
+
+svlcov_status svlcov_update_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr *Em) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  return h->prec == SVLCOV_FP64 ? op_weights<double>(h, D, Em) : op_weights<float>(h, D, Em);
+}
+
+svlcov_status svlcov_sync(svlcov_state *h) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  return settle(h);
+}
+
+svlcov_status svlcov_get_factors(svlcov_state *h, int64_t *m, int64_t *n, int32_t *k,
+                                 int32_t out_dtype, int32_t out_on_device, void *U, double *sigma,
+                                 void *V) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  svlcov_status r = settle(h);
+  if (r != SVLCOV_OK) return r;
+  if (m) *m = h->m;
+  if (n) *n = h->n;
+  if (k) *k = h->k;
+  const int K = h->k;
+  const size_t osz = out_dtype == SVLCOV_F64 ? 8 : 4;
+  hipStream_t st = h->stream;
+  for (int side = 0; side < 2; ++side) {
+    void *dst = side == 0 ? U : V;
+    if (!dst) continue;
+    const int64_t rows = side == 0 ? h->m : h->n;
+    if (rows == 0) continue;
+    const double *W = side == 0 ? h->WU : h->WV;
+    const void *base = side == 0 ? h->Ubase : h->Vbase;
+    void *target = dst;
+    if (!out_on_device) {
+      r = ensure(h, h->outbuf, (size_t)rows * K * osz);
+      if (r != SVLCOV_OK) return r;
+      target = h->outbuf.p;
+    }
+    if (h->prec == SVLCOV_FP64) {
+      if (out_dtype == SVLCOV_F64)
+        svl::realise<double, double>(st, 0, K, rows, (const double *)base, W, (double *)target,
+                                     nullptr, nullptr);
+      else
+        svl::realise<double, float>(st, 0, K, rows, (const double *)base, W, (float *)target,
+                                    nullptr, nullptr);
+    } else {
+      if (out_dtype == SVLCOV_F64)
+        svl::realise<float, double>(st, 0, K, rows, (const float *)base, W, (double *)target,
+                                    nullptr, nullptr);
+      else
+        svl::realise<float, float>(st, 0, K, rows, (const float *)base, W, (float *)target,
+                                   nullptr, nullptr);
+    }
+    if (!out_on_device)
+      SV_TRY(hipMemcpyAsync(dst, target, (size_t)rows * K * osz, hipMemcpyDeviceToHost, st));
+  }
+  if (sigma) SV_TRY(hipMemcpyAsync(sigma, h->sigma, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+  SV_TRY(hipStreamSynchronize(st));
+  return SVLCOV_OK;
+}
+
+svlcov_status svlcov_query_row(svlcov_state *h, int32_t side, int64_t i, double *out_k) {
+  if (!h || !out_k || (side != 0 && side != 1)) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  svlcov_status r = settle(h);
+  if (r != SVLCOV_OK) return r;
+  const int64_t rows = side == 0 ? h->m : h->n;
+  if (i < 0 || i >= rows) return SVLCOV_E_SHAPE;
+  const int K = h->k;
+  r = ensure(h, h->outbuf, (size_t)K * 8);
+  if (r != SVLCOV_OK) return r;
+  const double *W = side == 0 ? h->WU : h->WV;
+  const void *base = side == 0 ? h->Ubase : h->Vbase;
+  if (h->prec == SVLCOV_FP64)
+    svl::realise<double, double>(h->stream, 0, K, 1, (const double *)base + i * K, W,
+                                 (double *)h->outbuf.p, nullptr, nullptr);
+  else
+    svl::realise<float, double>(h->stream, 0, K, 1, (const float *)base + i * K, W,
+                                (double *)h->outbuf.p, nullptr, nullptr);
+  SV_TRY(hipMemcpyAsync(out_k, h->outbuf.p, (size_t)K * 8, hipMemcpyDeviceToHost, h->stream));
+  SV_TRY(hipStreamSynchronize(h->stream));
+  return SVLCOV_OK;
+}
+
+svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out) {
+  if (!h || !out) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  SvDevInfo inf;
+  svlcov_status r = read_info(h, &inf);
+  if (r != SVLCOV_OK) return r;
+  out->updates = inf.updates;
+  out->resets_U = inf.resets_U;
+  out->resets_V = inf.resets_V;
+  out->last_rank = inf.rank;
+  out->last_rank2 = inf.rank2;
+  out->last_kappa_U = inf.kappa_U;
+  out->last_kappa_V = inf.kappa_V;
+  out->last_min_kept_pivot = inf.min_kept;
+  out->last_max_dropped_pivot = inf.max_dropped;
+  return SVLCOV_OK;
+}
+
+void *svlcov_stream(svlcov_state *h) { return h ? (void *)h->stream : nullptr; }
+
+void svlcov_destroy(svlcov_state *h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->ws.p) (void)hipFree(h->ws.p);
+  if (h->stage.p) (void)hipFree(h->stage.p);
+  if (h->outbuf.p) (void)hipFree(h->outbuf.p);
+  if (h->Ubase) (void)hipFree(h->Ubase);
+  if (h->Vbase) (void)hipFree(h->Vbase);
+  if (h->WU) (void)hipFree(h->WU);
+  if (h->WV) (void)hipFree(h->WV);
+  if (h->sigma) (void)hipFree(h->sigma);
+  if (h->info) (void)hipFree(h->info);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+const char *svlcov_status_str(svlcov_status s) {
+  switch (s) {
+    case SVLCOV_OK: return "ok";
+    case SVLCOV_E_INVALID: return "invalid argument";
+    case SVLCOV_E_SHAPE: return "shape mismatch";
+    case SVLCOV_E_NOMEM: return "out of device memory";
+    case SVLCOV_E_NUMERIC: return "non-finite value";
+    case SVLCOV_E_DEVICE: return "HIP runtime error";
+    case SVLCOV_E_BUSY: return "state busy";
+    case SVLCOV_E_UNSUPPORTED: return "unsupported size or option";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,852 @@
+// Dense kernels of one update: FP64 GEMM, the residual Gram on MFMA (FP32 and
+// BF16x3), the FP64 Cholesky with pivot dropping and its triangular solve,
+// assembly of K, the k x k inverse with a condition estimate, row
+// orthonormalisation and the tall-skinny realisation GEMM.
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <type_traits>
+
+using namespace svk;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// ------------------------------------------------------------------ FP64 GEMM
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256)
+k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *__restrict__ A,
+           int64_t lda, const double *__restrict__ B, int64_t ldb, double beta,
+           double *__restrict__ C, int64_t ldc, const SvDevInfo *__restrict__ info) {
+  if (info && info->status) return;
+  __shared__ double As[GB_K][GB_M + 1];
+  __shared__ double Bs[GB_K][GB_N + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t m0 = (int64_t)blockIdx.y * GB_M, n0 = (int64_t)blockIdx.x * GB_N;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  for (int64_t k0 = 0; k0 < K; k0 += GB_K) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + t * 256;  // 0..1023
+      int i, p;
+      if (!TA) { p = e & 15; i = e >> 4; } else { i = e & 63; p = e >> 6; }
+      const int64_t gi = m0 + i, gp = k0 + p;
+      double v = 0.0;
+      if (gi < M && gp < K) v = TA ? A[gp * lda + gi] : A[gi * lda + gp];
+      As[p][i] = v;
+      int j, q;
+      if (TB) { q = e & 15; j = e >> 4; } else { j = e & 63; q = e >> 6; }
+      const int64_t gj = n0 + j, gq = k0 + q;
+      double u = 0.0;
+      if (gj < N && gq < K) u = TB ? B[gj * ldb + gq] : B[gq * ldb + gj];
+      Bs[q][j] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < GB_K; ++p) {
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[p][ty + 16 * r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[p][tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t gi = m0 + ty + 16 * r;
+    if (gi >= M) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t gj = n0 + tx + 16 * c;
+      if (gj >= N) continue;
+      double v = alpha * acc[r][c];
+      if (beta != 0.0) v += beta * C[gi * ldc + gj];
+      C[gi * ldc + gj] = v;
+    }
+  }
+}
+
+// ------------------------------------------------- residual Gram on MFMA
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned)h) << 16);
+}
+
+// Tile 64 x 64 of the lower triangle; 4 waves, each a 32 x 32 quadrant made
+// of 2 x 2 MFMA 16 x 16 blocks.  LDS holds the two 64-row panels of C.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_gram_lowp(int64_t s, int K, const float *__restrict__ C, double *__restrict__ G,
+            int64_t ldg, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int KP = 128 + 8;  // padded row length (elements)
+  extern __shared__ unsigned char smem[];
+  // decode lower-triangular tile pair (ti >= tj)
+  const int64_t t = blockIdx.x;
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int64_t tj = t - ti * (ti + 1) / 2;
+  const int64_t r0 = ti * 64, c0 = tj * 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (MODE == 1) {
+    float *As = (float *)smem;
+    float *Bs = As + 64 * KP;
+    for (int e = tid; e < 64 * K; e += 256) {
+      const int rr = e / K, cc = e % K;
+      As[rr * KP + cc] = (r0 + rr < s) ? C[(r0 + rr) * K + cc] : 0.f;
+      Bs[rr * KP + cc] = (c0 + rr < s) ? C[(c0 + rr) * K + cc] : 0.f;
+    }
+    __syncthreads();
+    const int li = lane & 15, lk = lane >> 4;
+    for (int kk = 0; kk < K; kk += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        a[x] = As[(wr * 32 + x * 16 + li) * KP + kk + lk];
+        b[x] = Bs[(wc * 32 + x * 16 + li) * KP + kk + lk];
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+  } else {
+    unsigned short *Ah = (unsigned short *)smem;
+    unsigned short *Al = Ah + 64 * KP;
+    unsigned short *Bh = Al + 64 * KP;
+    unsigned short *Bl = Bh + 64 * KP;
+    for (int e = tid; e < 64 * K; e += 256) {
+      const int rr = e / K, cc = e % K;
+      const float xa = (r0 + rr < s) ? C[(r0 + rr) * K + cc] : 0.f;
+      const float xb = (c0 + rr < s) ? C[(c0 + rr) * K + cc] : 0.f;
+      const unsigned short ha = f32_to_bf16_rne(xa), hb = f32_to_bf16_rne(xb);
+      Ah[rr * KP + cc] = ha;
+      Al[rr * KP + cc] = f32_to_bf16_rne(xa - bf16_to_f32(ha));
+      Bh[rr * KP + cc] = hb;
+      Bl[rr * KP + cc] = f32_to_bf16_rne(xb - bf16_to_f32(hb));
+    }
+    __syncthreads();
+    const int li = lane & 15, lk = (lane >> 4) * 4;
+    for (int kk = 0; kk < K; kk += 16) {
+      s16x4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int ra = (wr * 32 + x * 16 + li) * KP + kk + lk;
+        const int rb = (wc * 32 + x * 16 + li) * KP + kk + lk;
+        ah[x] = *(const s16x4 *)(Ah + ra);
+        al[x] = *(const s16x4 *)(Al + ra);
+        bh[x] = *(const s16x4 *)(Bh + rb);
+        bl[x] = *(const s16x4 *)(Bl + rb);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          f32x4 c = acc[x][y];
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[x], bh[y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[x], bl[y], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[x], bh[y], c, 0, 0, 0);
+          acc[x][y] = c;
+        }
+    }
+  }
+  // D[i][j] for lane: i = 4*(lane/16) + q, j = lane % 16 within each 16 x 16 block
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = r0 + wr * 32 + x * 16 + 4 * (lane >> 4) + q;
+        const int64_t gj = c0 + wc * 32 + y * 16 + (lane & 15);
+        if (gi < s && gj < s) G[gi * ldg + gj] -= (double)acc[x][y][q];
+      }
+}
+
+// ------------------------------------------------------------- small helpers
+__global__ void k_copy_strided(int64_t R, int64_t Cn, const double *__restrict__ src,
+                               int64_t rs, int64_t cs, double *__restrict__ dst, int64_t ldd,
+                               const SvDevInfo *__restrict__ info) {
+  if (info && info->status) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * Cn) return;
+  const int64_t i = e / Cn, j = e % Cn;
+  dst[i * ldd + j] = src[i * rs + j * cs];
+}
+
+__global__ void k_max_into(int64_t n, const double *__restrict__ v, SvDevInfo *info,
+                           int which) {
+  __shared__ double red[16];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, v[i]);
+  m = block_max(m, red);
+  if (threadIdx.x == 0) {
+    if (which == 0) info->scale = m; else info->scale2 = m;
+  }
+}
+
+// Factor the nb x nb diagonal block at (b0, b0) of the (already updated)
+// lower triangle.  A pivot d_j <= tol * scale is dropped: column j of L is set
+// to zero.  Writes L into G, zeroes the block's strict upper part, and writes
+// Linv = inverse of L with 1 in place of each dropped pivot, then with row
+// and column j of every dropped pivot zeroed.
+__global__ void __launch_bounds__(256)
+k_chol_diag(int64_t s, double *__restrict__ G, int64_t ld, int64_t b0,
+            double *__restrict__ Linv, double tol, SvDevInfo *__restrict__ info, int which) {
+  if (info->status) return;
+  constexpr int NB = svl::CHOL_NB;
+  __shared__ double L[NB][NB + 1];
+  __shared__ double Li[NB][NB + 1];
+  __shared__ int dropped[NB];
+  const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
+  const int tid = threadIdx.x;
+  const double scale = which == 0 ? info->scale : info->scale2;
+  const double thr = tol * scale;
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    L[i][j] = (i < nb && j <= i) ? G[(b0 + i) * ld + b0 + j] : 0.0;
+    Li[i][j] = 0.0;
+  }
+  __syncthreads();
+  // left-looking column Cholesky inside the block
+  __shared__ double rd_sh;
+  __shared__ int drop_sh;
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      double d = L[j][j];
+      for (int p = 0; p < j; ++p) d -= L[j][p] * L[j][p];
+      const bool drop = !(d > thr) || !(scale > 0.0);
+      const double rd = drop ? 0.0 : sqrt(d);
+      dropped[j] = drop ? 1 : 0;
+      drop_sh = drop ? 1 : 0;
+      rd_sh = rd;
+      L[j][j] = rd;
+      const double rel = scale > 0.0 ? d / scale : 0.0;
+      if (drop) {
+        if (rel > info->max_dropped) info->max_dropped = rel;
+      } else {
+        if (rel < info->min_kept) info->min_kept = rel;
+        if (which == 0) info->rank += 1; else info->rank2 += 1;
+      }
+    }
+    __syncthreads();
+    const int i = j + 1 + tid;
+    if (i < nb) {
+      double v = L[i][j];
+      for (int p = 0; p < j; ++p) v -= L[i][p] * L[j][p];
+      L[i][j] = drop_sh ? 0.0 : v / rd_sh;
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular block with unit placeholders: one thread
+  // per column, forward substitution.
+  if (tid < nb) {
+    const int c = tid;
+    for (int i = 0; i < nb; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int p = c; p < i; ++p) v -= L[i][p] * Li[p][c];
+      const double dii = dropped[i] ? 1.0 : L[i][i];
+      Li[i][c] = (i < c) ? 0.0 : v / dii;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    double v = Li[i][j];
+    if (i >= nb || j >= nb || dropped[i] || dropped[j]) v = 0.0;
+    Linv[e] = v;
+    if (i < nb && j < nb) G[(b0 + i) * ld + b0 + j] = (j <= i) ? L[i][j] : 0.0;
+  }
+}
+
+// Y_b = Linv_b^T Y_b for one nb-row block of Y (K columns), in place.
+__global__ void k_trsm_diag(int64_t s, int K, int64_t b0, const double *__restrict__ Linv,
+                            double *__restrict__ Y, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int NB = svl::CHOL_NB;
+  __shared__ double Yb[NB][129];
+  __shared__ double Li[NB][NB + 1];
+  const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Li[e / NB][e % NB] = Linv[e];
+  for (int e = threadIdx.x; e < nb * K; e += blockDim.x)
+    Yb[e / K][e % K] = Y[(b0 + e / K) * K + e % K];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nb * K; e += blockDim.x) {
+    const int i = e / K, c = e % K;
+    double v = 0.0;
+    for (int p = 0; p < nb; ++p) v += Li[p][i] * Yb[p][c];
+    Y[(b0 + i) * K + c] = v;
+  }
+}
+
+__global__ void k_build_K_rows(int K, int64_t s, const double *__restrict__ sig,
+                               const double *__restrict__ Cp, const double *__restrict__ L,
+                               int64_t ldl, double *__restrict__ Ko,
+                               const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int64_t N = K + s;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  const int64_t r = e / N, c = e % N;
+  double v = 0.0;
+  if (r < K) {
+    v = (c == r) ? sig[r] : 0.0;
+  } else if (c < K) {
+    v = Cp[(r - K) * K + c];
+  } else if (c - K <= r - K) {
+    v = L[(r - K) * ldl + (c - K)];
+  }
+  Ko[e] = v;
+}
+
+__global__ void k_build_X(int K, int64_t s, const double *__restrict__ Cp,
+                          const double *__restrict__ L, int64_t ldl, double *__restrict__ X,
+                          const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int64_t N = K + s;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * s) return;
+  const int64_t r = e / s, c = e % s;
+  double v;
+  if (r < K) v = Cp[c * K + r];
+  else v = (c >= r - K) ? L[c * ldl + (r - K)] : 0.0;   // (L^T)[r-K][c] = L[c][r-K]
+  X[e] = v;
+}
+
+__global__ void k_add_sigma_diag(int K, const double *__restrict__ sig, double *__restrict__ Ko,
+                                 int64_t ld, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int i = threadIdx.x;
+  if (i < K) Ko[(int64_t)i * ld + i] += sig[i];
+}
+
+__global__ void k_theta_scale(int K, const double *__restrict__ lam, double *__restrict__ theta,
+                              double *__restrict__ Gv, int64_t N, int32_t *__restrict__ complete,
+                              const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int j = blockIdx.x;
+  const double t0 = sqrt(fmax(lam[0], 0.0));
+  const double tj = sqrt(fmax(lam[j], 0.0));
+  const bool tiny = !(tj > 1e-12 * t0) || t0 <= 0.0;
+  if (threadIdx.x == 0) {
+    theta[j] = tj;
+    complete[j] = tiny ? 1 : 0;
+  }
+  const double inv = tiny ? 0.0 : 1.0 / tj;
+  for (int64_t c = threadIdx.x; c < N; c += blockDim.x) Gv[(int64_t)j * N + c] *= inv;
+}
+
+// Classical Gram-Schmidt, twice, over the K rows of X (K x N), one block.
+__global__ void __launch_bounds__(1024)
+k_orth_rows(int K, int64_t N, double *__restrict__ X, const int32_t *__restrict__ complete,
+            uint64_t seed, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ double dots[128];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j < K; ++j) {
+    double *xj = X + (int64_t)j * N;
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      const bool refill = (attempt > 0) || (complete && complete[j]);
+      if (refill) {
+        for (int64_t c = tid; c < N; c += blockDim.x)
+          xj[c] = hash_unit(seed * 1000003ull + (uint64_t)j * 7919ull +
+                            (uint64_t)attempt * 104729ull + (uint64_t)c * 2654435761ull);
+        __syncthreads();
+      }
+      double nrm0 = 0.0;
+      for (int64_t c = tid; c < N; c += blockDim.x) nrm0 += xj[c] * xj[c];
+      nrm0 = sqrt(block_sum(nrm0, red));
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i = w; i < j; i += nw) {
+          const double *xi = X + (int64_t)i * N;
+          double d = 0.0;
+          for (int64_t c = lane; c < N; c += 64) d += xi[c] * xj[c];
+          d = wave_sum(d);
+          if (lane == 0) dots[i] = d;
+        }
+        __syncthreads();
+        for (int64_t c = tid; c < N; c += blockDim.x) {
+          double v = xj[c];
+          for (int i = 0; i < j; ++i) v -= dots[i] * X[(int64_t)i * N + c];
+          xj[c] = v;
+        }
+        __syncthreads();
+      }
+      double nrm = 0.0;
+      for (int64_t c = tid; c < N; c += blockDim.x) nrm += xj[c] * xj[c];
+      nrm = sqrt(block_sum(nrm, red));
+      if (nrm > 1e-3 * nrm0 && nrm > 0.0) {
+        const double inv = 1.0 / nrm;
+        for (int64_t c = tid; c < N; c += blockDim.x) xj[c] *= inv;
+        __syncthreads();
+        break;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting (k <= 128, in LDS).
+__global__ void __launch_bounds__(1024)
+k_inverse_cond(int K, const double *__restrict__ W, double *__restrict__ Winv,
+               int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
+               int side) {
+  if (info->status) return;
+  extern __shared__ double sm[];
+  double *A = sm;                 // K x (K+1)
+  int *piv = (int *)(A + K * (K + 1));
+  __shared__ double red[16];
+  __shared__ int sing;
+  const int tid = threadIdx.x, ld = K + 1;
+  for (int e = tid; e < K * K; e += blockDim.x) A[(e / K) * ld + e % K] = W[e];
+  if (tid == 0) sing = 0;
+  __syncthreads();
+  // ||W||_1: max column sum
+  double cs = 0.0;
+  if (tid < K) for (int r = 0; r < K; ++r) cs += fabs(A[r * ld + tid]);
+  const double n1 = block_max(tid < K ? cs : 0.0, red);
+  bool finite_in = isfinite(n1);
+  for (int c = 0; c < K && finite_in; ++c) {
+    // pivot search in column c (one wave)
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = c;
+      for (int r = c + tid; r < K; r += 64) {
+        const double a = fabs(A[r * ld + c]);
+        if (a > best) { best = a; bi = r; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        piv[c] = bi;
+        if (!(best > 1e-300) || !(best > 1e-15 * n1)) sing = 1;
+      }
+    }
+    __syncthreads();
+    if (sing) break;
+    const int p = piv[c];
+    if (p != c)
+      for (int j = tid; j < K; j += blockDim.x) {
+        const double t = A[c * ld + j];
+        A[c * ld + j] = A[p * ld + j];
+        A[p * ld + j] = t;
+      }
+    __syncthreads();
+    const double pv = A[c * ld + c];
+    __syncthreads();
+    if (tid == 0) A[c * ld + c] = 1.0;
+    __syncthreads();
+    for (int j = tid; j < K; j += blockDim.x) A[c * ld + j] /= pv;
+    __syncthreads();
+    // eliminate rows r != c; A[r][c] (the multiplier) is read before the
+    // column itself is overwritten in the next phase
+    for (int e = tid; e < K * K; e += blockDim.x) {
+      const int r = e / K, j = e % K;
+      if (r == c || j == c) continue;
+      A[r * ld + j] -= A[r * ld + c] * A[c * ld + j];
+    }
+    __syncthreads();
+    for (int r = tid; r < K; r += blockDim.x)
+      if (r != c) A[r * ld + c] = -A[r * ld + c] * A[c * ld + c];
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, in reverse order
+  if (!sing && finite_in) {
+    for (int c = K - 1; c >= 0; --c) {
+      const int p = piv[c];
+      if (p != c)
+        for (int r = tid; r < K; r += blockDim.x) {
+          const double t = A[r * ld + c];
+          A[r * ld + c] = A[r * ld + p];
+          A[r * ld + p] = t;
+        }
+      __syncthreads();
+    }
+  }
+  double cs2 = 0.0;
+  if (tid < K) for (int r = 0; r < K; ++r) cs2 += fabs(A[r * ld + tid]);
+  const double ninv = block_max(tid < K ? cs2 : 0.0, red);
+  const double kappa = (sing || !finite_in) ? INFINITY : n1 * ninv;
+  for (int e = tid; e < K * K; e += blockDim.x) Winv[e] = A[(e / K) * ld + e % K];
+  if (tid == 0) {
+    const bool reset = !(kappa <= cond_reset);
+    *flag = reset ? 1 : 0;
+    if (side == 0) info->kappa_U = kappa; else info->kappa_V = kappa;
+    if (!finite_in) {
+      if (atomicCAS(&info->status, 0, 4) == 0) info->failed_seq = -1;
+    }
+  }
+}
+
+__global__ void k_commit_small(int K, const double *__restrict__ Wnew,
+                               const int32_t *__restrict__ flag, double *__restrict__ W,
+                               const double *__restrict__ theta, double *__restrict__ sig,
+                               SvDevInfo *__restrict__ info, int side) {
+  if (info->status) return;
+  const bool reset = *flag != 0;
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x)
+    W[e] = reset ? ((e / K == e % K) ? 1.0 : 0.0) : Wnew[e];
+  if (sig && threadIdx.x < K) sig[threadIdx.x] = theta[threadIdx.x];
+  if (threadIdx.x == 0 && reset) {
+    if (side == 0) info->resets_U += 1; else info->resets_V += 1;
+  }
+}
+
+__global__ void k_check_finite(int64_t n, const double *__restrict__ x, SvDevInfo *info, int seq) {
+  if (info->status) return;
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) bad |= !isfinite(x[i]);
+  if (__syncthreads_or(bad) && threadIdx.x == 0) {
+    if (atomicCAS(&info->status, 0, 4) == 0) info->failed_seq = seq;
+  }
+}
+
+__global__ void k_op_begin(SvDevInfo *info, int two_sided) {
+  if (info->status) return;
+  info->rank = 0;
+  info->rank2 = two_sided ? 0 : -1;
+  info->min_kept = INFINITY;
+  info->max_dropped = -1.0;
+  info->reset_U = 0;
+  info->reset_V = 0;
+}
+
+__global__ void k_op_end(SvDevInfo *info) {
+  if (info->status) return;
+  info->updates += 1;
+}
+
+__global__ void k_fill_identity(int K, double *W) {
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) W[e] = (e / K == e % K) ? 1.0 : 0.0;
+}
+
+// --------------------------------------------------------- realisation GEMM
+// FP64 FMA variant: one block = 64 rows; the row tile is staged in LDS.
+template <typename Tin, typename Tout, int K>
+__global__ void __launch_bounds__(256)
+k_realise_f64(int64_t rows, const Tin *__restrict__ in, const double *__restrict__ W,
+              Tout *__restrict__ out, const int32_t *__restrict__ flag,
+              const SvDevInfo *__restrict__ info) {
+  if (info && info->status) return;
+  if (flag && *flag == 0) return;
+  constexpr int RB = K >= 128 ? 32 : 64;
+  __shared__ double tile[RB][K + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
+  const int nr = (int)((rows - r0) < RB ? (rows - r0) : RB);
+  for (int e = threadIdx.x; e < nr * K; e += blockDim.x)
+    tile[e / K][e % K] = (double)in[(r0 + e / K) * K + e % K];
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * K; e += blockDim.x) {
+    const int r = e / K, c = e % K;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < K; ++l) acc += tile[r][l] * W[l * K + c];
+    out[(r0 + r) * K + c] = (Tout)acc;
+  }
+}
+
+// FP32 (MODE 1) and BF16x3 (MODE 2) MFMA variants, float in / float out.
+// One block = 64 rows (4 waves x 16 rows), all K output columns per wave.
+template <int MODE, int K>
+__global__ void __launch_bounds__(256)
+k_realise_lowp(int64_t rows, const float *__restrict__ in, const double *__restrict__ W,
+               float *__restrict__ out, const int32_t *__restrict__ flag,
+               const SvDevInfo *__restrict__ info) {
+  if (info && info->status) return;
+  if (flag && *flag == 0) return;
+  constexpr int KP = K + 8;
+  extern __shared__ unsigned char smem[];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int nr = (int)((rows - r0) < 64 ? (rows - r0) : 64);
+  const int li = lane & 15;
+  if constexpr (MODE == 1) {
+    float *At = (float *)smem;            // 64 x KP
+    float *Wt = At + 64 * KP;             // K x KP, W^T (row j = column j of W)
+    for (int e = tid; e < 64 * K; e += 256) {
+      const int r = e / K, c = e % K;
+      At[r * KP + c] = r < nr ? in[(r0 + r) * K + c] : 0.f;
+    }
+    for (int e = tid; e < K * K; e += 256) Wt[(e % K) * KP + e / K] = (float)W[e];
+    __syncthreads();
+    const int lk = lane >> 4;
+    for (int cb = 0; cb < K / 16; ++cb) {
+      f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int kk = 0; kk < K; kk += 4) {
+        const float a = At[(w * 16 + li) * KP + kk + lk];
+        const float b = Wt[(cb * 16 + li) * KP + kk + lk];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = w * 16 + 4 * (lane >> 4) + q;
+        if (r < nr) out[(r0 + r) * K + cb * 16 + li] = acc[q];
+      }
+    }
+  } else {
+    unsigned short *Ah = (unsigned short *)smem;   // 64 x KP
+    unsigned short *Al = Ah + 64 * KP;
+    unsigned short *Wh = Al + 64 * KP;             // K x KP (W^T)
+    unsigned short *Wl = Wh + K * KP;
+    for (int e = tid; e < 64 * K; e += 256) {
+      const int r = e / K, c = e % K;
+      const float x = r < nr ? in[(r0 + r) * K + c] : 0.f;
+      const unsigned short h = f32_to_bf16_rne(x);
+      Ah[r * KP + c] = h;
+      Al[r * KP + c] = f32_to_bf16_rne(x - bf16_to_f32(h));
+    }
+    for (int e = tid; e < K * K; e += 256) {
+      const float x = (float)W[e];
+      const unsigned short h = f32_to_bf16_rne(x);
+      Wh[(e % K) * KP + e / K] = h;
+      Wl[(e % K) * KP + e / K] = f32_to_bf16_rne(x - bf16_to_f32(h));
+    }
+    __syncthreads();
+    const int lk = (lane >> 4) * 4;
+    f32x4 accs[K / 16];
+#pragma unroll
+    for (int cb = 0; cb < K / 16; ++cb) accs[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < K; kk += 16) {
+      const int ra = (w * 16 + li) * KP + kk + lk;
+      const s16x4 ah = *(const s16x4 *)(Ah + ra);
+      const s16x4 al = *(const s16x4 *)(Al + ra);
+#pragma unroll
+      for (int cb = 0; cb < K / 16; ++cb) {
+        const int rb = (cb * 16 + li) * KP + kk + lk;
+        const s16x4 bh = *(const s16x4 *)(Wh + rb);
+        const s16x4 bl = *(const s16x4 *)(Wl + rb);
+        f32x4 c = accs[cb];
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+        accs[cb] = c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cb = 0; cb < K / 16; ++cb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = w * 16 + 4 * (lane >> 4) + q;
+        if (r < nr) out[(r0 + r) * K + cb * 16 + li] = accs[cb][q];
+      }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+namespace svl {
+
+// Kernels whose dynamic LDS may exceed 64 KiB must opt in once per process.
+template <typename F>
+static void allow_big_lds(F *f) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(f),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+
+void gemm_f64(hipStream_t st, bool tA, bool tB, int64_t M, int64_t N, int64_t K, double alpha,
+              const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+              double *C, int64_t ldc, const SvDevInfo *info) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid((unsigned)((N + GB_N - 1) / GB_N), (unsigned)((M + GB_M - 1) / GB_M));
+  if (!tA && !tB) hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
+  else if (!tA && tB) hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
+  else if (tA && !tB) hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
+  else hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
+}
+
+void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, double *G,
+               int64_t ldg, const SvDevInfo *info) {
+  if (s <= 0) return;
+  const int64_t nt = (s + 63) / 64;
+  const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
+  constexpr int KP = 128 + 8;
+  static bool once = false;
+  if (!once) { allow_big_lds(k_gram_lowp<1>); allow_big_lds(k_gram_lowp<2>); once = true; }
+  if (mode == 1) {
+    const size_t sh = 2 * 64 * KP * sizeof(float);
+    hipLaunchKernelGGL((k_gram_lowp<1>), dim3(tiles), dim3(256), sh, st, s, K, C, G, ldg, info);
+  } else {
+    const size_t sh = 4 * 64 * KP * sizeof(unsigned short);
+    hipLaunchKernelGGL((k_gram_lowp<2>), dim3(tiles), dim3(256), sh, st, s, K, C, G, ldg, info);
+  }
+}
+
+void copy_strided(hipStream_t st, int64_t R, int64_t C, const double *src, int64_t rs,
+                  int64_t cs, double *dst, int64_t ldd, const SvDevInfo *info) {
+  const int64_t n = R * C;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy_strided, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R, C,
+                     src, rs, cs, dst, ldd, info);
+}
+
+void max_into(hipStream_t st, int64_t n, const double *v, SvDevInfo *info, int which) {
+  hipLaunchKernelGGL(k_max_into, dim3(1), dim3(1024), 0, st, n, v, info, which);
+}
+
+void cholesky_drop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
+                   double tol, SvDevInfo *info, int which) {
+  const int NB = CHOL_NB;
+  for (int64_t b0 = 0; b0 < s; b0 += NB) {
+    const int64_t bi = b0 / NB;
+    double *Lb = Linv + bi * NB * NB;
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, s, G, ld, b0, Lb, tol, info,
+                       which);
+    const int64_t rest = s - b0 - NB;
+    if (rest > 0) {
+      // panel: L21 = A21 * Linv^T  (in place through a GEMM into the panel)
+      // the panel is read and written by the same GEMM tile only when the
+      // tile covers all NB columns, which holds (GB_N >= NB).
+      gemm_f64(st, false, true, rest, NB, NB, 1.0, G + (b0 + NB) * ld + b0, ld, Lb, NB, 0.0,
+               G + (b0 + NB) * ld + b0, ld, info);
+      // trailing update A22 -= L21 L21^T
+      gemm_f64(st, false, true, rest, rest, NB, -1.0, G + (b0 + NB) * ld + b0, ld,
+               G + (b0 + NB) * ld + b0, ld, 1.0, G + (b0 + NB) * ld + b0 + NB, ld, info);
+    }
+  }
+}
+
+void trsm_lt(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,
+             double *Y, const SvDevInfo *info) {
+  const int NB = CHOL_NB;
+  const int64_t nblk = (s + NB - 1) / NB;
+  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
+    const int64_t b0 = bi * NB;
+    hipLaunchKernelGGL(k_trsm_diag, dim3(1), dim3(256), 0, st, s, K, b0, Linv + bi * NB * NB, Y,
+                       info);
+    if (b0 > 0) {
+      const int64_t nb = (s - b0) < NB ? (s - b0) : NB;
+      // Y[0:b0] -= L[b0:b0+nb, 0:b0]^T * Y[b0:b0+nb]
+      gemm_f64(st, true, false, b0, K, nb, -1.0, L + b0 * ld, ld, Y + b0 * K, K, 1.0, Y, K,
+               info);
+    }
+  }
+}
+
+void build_K_rows(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
+                  const double *L, int64_t ldl, double *Ko, const SvDevInfo *info) {
+  const int64_t N = K + s, n = N * N;
+  hipLaunchKernelGGL(k_build_K_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, s,
+                     sig, Cp, L, ldl, Ko, info);
+}
+
+void build_X(hipStream_t st, int K, int64_t s, const double *Cp, const double *L, int64_t ldl,
+             double *X, const SvDevInfo *info) {
+  const int64_t n = (K + s) * s;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_build_X, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, s, Cp,
+                     L, ldl, X, info);
+}
+
+void add_sigma_diag(hipStream_t st, int K, const double *sig, double *Ko, int64_t ld,
+                    const SvDevInfo *info) {
+  hipLaunchKernelGGL(k_add_sigma_diag, dim3(1), dim3(128), 0, st, K, sig, Ko, ld, info);
+}
+
+void theta_scale(hipStream_t st, int K, const double *lam, double *theta, double *Gv, int64_t N,
+                 int32_t *complete, const SvDevInfo *info) {
+  hipLaunchKernelGGL(k_theta_scale, dim3(K), dim3(256), 0, st, K, lam, theta, Gv, N, complete,
+                     info);
+}
+
+void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int32_t *complete,
+                         uint64_t seed, const SvDevInfo *info) {
+  hipLaunchKernelGGL(k_orth_rows, dim3(1), dim3(1024), 0, st, K, N, X, complete, seed, info);
+}
+
+void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
+                  double cond_reset, SvDevInfo *info, int side) {
+  const size_t sh = (size_t)K * (K + 1) * sizeof(double) + (size_t)K * sizeof(int) + 16;
+  static bool once = false;
+  if (!once) { allow_big_lds(k_inverse_cond); once = true; }
+  hipLaunchKernelGGL(k_inverse_cond, dim3(1), dim3(1024), sh, st, K, W, Winv, flag, cond_reset,
+                     info, side);
+}
+
+void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,
+                  const double *theta, double *sig, SvDevInfo *info, int side) {
+  hipLaunchKernelGGL(k_commit_small, dim3(1), dim3(256), 0, st, K, Wnew, flag, W, theta, sig,
+                     info, side);
+}
+
+void check_finite(hipStream_t st, int64_t n, const double *x, SvDevInfo *info, int seq) {
+  hipLaunchKernelGGL(k_check_finite, dim3(1), dim3(256), 0, st, n, x, info, seq);
+}
+
+void op_begin(hipStream_t st, SvDevInfo *info, int two_sided) {
+  hipLaunchKernelGGL(k_op_begin, dim3(1), dim3(1), 0, st, info, two_sided);
+}
+
+void op_end(hipStream_t st, SvDevInfo *info) {
+  hipLaunchKernelGGL(k_op_end, dim3(1), dim3(1), 0, st, info);
+}
+
+void fill_identity(hipStream_t st, int K, double *W) {
+  hipLaunchKernelGGL(k_fill_identity, dim3(1), dim3(256), 0, st, K, W);
+}
+
+template <typename Tin, typename Tout>
+void realise(hipStream_t st, int mode, int K, int64_t rows, const Tin *in, const double *W,
+             Tout *out, const int32_t *flag, const SvDevInfo *info) {
+  if (rows <= 0) return;
+  const unsigned blocks = (unsigned)((rows + 63) / 64);
+  if constexpr (std::is_same<Tin, float>::value && std::is_same<Tout, float>::value) {
+    if (mode == 1 || mode == 2) {
+      const int KP = K + 8;
+      const size_t sh1 = (size_t)(64 + K) * KP * sizeof(float);
+      const size_t sh2 = (size_t)2 * (64 + K) * KP * sizeof(unsigned short);
+#define SV_RL(MM, KK, SH) do { allow_big_lds(k_realise_lowp<MM, KK>); hipLaunchKernelGGL((k_realise_lowp<MM, KK>), dim3(blocks), dim3(256), SH, st, rows, in, W, out, flag, info); } while (0)
+      if (mode == 1) {
+        switch (K) { case 16: SV_RL(1, 16, sh1); break; case 32: SV_RL(1, 32, sh1); break;
+                     case 64: SV_RL(1, 64, sh1); break; case 128: SV_RL(1, 128, sh1); break; }
+      } else {
+        switch (K) { case 16: SV_RL(2, 16, sh2); break; case 32: SV_RL(2, 32, sh2); break;
+                     case 64: SV_RL(2, 64, sh2); break; case 128: SV_RL(2, 128, sh2); break; }
+      }
+#undef SV_RL
+      return;
+    }
+  }
+#define SV_RF(KK) hipLaunchKernelGGL((k_realise_f64<Tin, Tout, KK>), dim3((unsigned)((rows + (KK >= 128 ? 31 : 63)) / (KK >= 128 ? 32 : 64))), dim3(256), 0, st, rows, in, W, out, flag, info)
+  switch (K) { case 16: SV_RF(16); break; case 32: SV_RF(32); break;
+               case 64: SV_RF(64); break; case 128: SV_RF(128); break; }
+#undef SV_RF
+}
+template void realise<float, float>(hipStream_t, int, int, int64_t, const float *, const double *, float *, const int32_t *, const SvDevInfo *);
+template void realise<double, double>(hipStream_t, int, int, int64_t, const double *, const double *, double *, const int32_t *, const SvDevInfo *);
+template void realise<float, double>(hipStream_t, int, int, int64_t, const float *, const double *, double *, const int32_t *, const SvDevInfo *);
+template void realise<double, float>(hipStream_t, int, int, int64_t, const double *, const double *, float *, const int32_t *, const SvDevInfo *);
+
+}  // namespace svl

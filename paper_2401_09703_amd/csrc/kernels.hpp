@@ -1,0 +1,97 @@
+// Host-side launchers of the gfx950 kernels (all enqueue on the given stream).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace svl {
+
+// ---- sparse (k_sparse.hip)
+void validate_csr(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz,
+                  const int64_t *rp, const int32_t *ci, const void *v, int vdt,
+                  SvDevInfo *info, int seq);
+template <typename T>
+void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
+            const void *v, int vdt, const T *base, const double *W, double *Cp64,
+            float *Cp32, double *rownorm2, const SvDevInfo *info);
+void sparse_gram(hipStream_t st, int64_t s, const int64_t *rp, const int32_t *ci,
+                 const void *v, int vdt, double *S, int64_t lds, const SvDevInfo *info);
+template <typename T>
+void scatter(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
+             const void *v, int vdt, const double *M, T *base, const SvDevInfo *info);
+// out[i] = X[i,:] Winv (or X[i,:] when *reset_flag), X[i][l] = src[i*rs + l*cs].
+template <typename T>
+void append_rows(hipStream_t st, int K, int64_t s, const double *src, int64_t rs, int64_t cs,
+                 const double *Winv, const int32_t *reset_flag, T *out,
+                 const SvDevInfo *info);
+
+// ---- dense (k_dense.hip)
+// C = alpha op(A) op(B) + beta C, FP64, row-major; op(X) = X^T when trans.
+void gemm_f64(hipStream_t st, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
+              double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+              double beta, double *C, int64_t ldc, const SvDevInfo *info);
+// G[i][j] -= sum_l C[i][l] C[j][l] on the lower-triangular tiles, with C
+// (s x K, float) multiplied on MFMA: mode 1 FP32, mode 2 BF16x3.
+void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, double *G,
+               int64_t ldg, const SvDevInfo *info);
+// dst[i][j] = src[i*rs + j*cs], i < R, j < C (FP64).
+void copy_strided(hipStream_t st, int64_t R, int64_t C, const double *src, int64_t rs,
+                  int64_t cs, double *dst, int64_t ldd, const SvDevInfo *info);
+// max_i v[i] into info->scale (which = 0) or info->scale2 (which = 1).
+void max_into(hipStream_t st, int64_t n, const double *v, SvDevInfo *info, int which);
+// Blocked right-looking Cholesky of the lower triangle of G (s x s, ld) with
+// pivot dropping; L overwrites the lower triangle, the upper triangle is
+// zeroed.  Linv receives the inverses of the nb x nb diagonal blocks.
+void cholesky_drop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
+                   double rank_tol, SvDevInfo *info, int which);
+// Y = L^{-T} Y in place (Y s x K, row-major), using the diagonal-block inverses.
+void trsm_lt(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
+             const double *Linv, double *Y, const SvDevInfo *info);
+constexpr int CHOL_NB = 32;
+// K = [[diag(sig), 0], [Cp, L]]  (N = K+s square, the add-rows form).
+void build_K_rows(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
+                  const double *L, int64_t ldl, double *Kout, const SvDevInfo *info);
+// X = [Cp^T ; L^T]  ((K+s) x s) for the weight form.
+void build_X(hipStream_t st, int K, int64_t s, const double *Cp, const double *L,
+             int64_t ldl, double *X, const SvDevInfo *info);
+// Kout[i][i] += sig[i] for i < K.
+void add_sigma_diag(hipStream_t st, int K, const double *sig, double *Kout, int64_t ld,
+                    const SvDevInfo *info);
+// theta = sqrt(max(lambda, 0)); scale rows of Gv by 1/theta; mark rows whose
+// theta is below tol * theta_0 for completion.
+void theta_scale(hipStream_t st, int K, const double *lam, double *theta, double *Gv,
+                 int64_t N, int32_t *complete, const SvDevInfo *info);
+// Orthonormalise the K rows of X (K x N) by classical Gram-Schmidt twice,
+// replacing rows flagged in complete (may be NULL) by pseudo-random rows first.
+void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X,
+                         const int32_t *complete, uint64_t seed, const SvDevInfo *info);
+// Winv = W^{-1} (k x k) by Gauss-Jordan with partial pivoting; kappa_1 into
+// info; *flag = 1 when kappa > cond_reset or W is singular.
+void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
+                  double cond_reset, SvDevInfo *info, int side);
+// W = (reset ? I : Wnew); sig = theta (when sig_out != NULL); count resets.
+void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,
+                  const double *theta, double *sig_out, SvDevInfo *info, int side);
+// out[r] = in[r] * W for r < rows (tall-skinny).  When flag != NULL the kernel
+// does nothing unless *flag.  mode 0: FP64 FMA, 1: FP32 MFMA, 2: BF16x3 MFMA.
+template <typename Tin, typename Tout>
+void realise(hipStream_t st, int mode, int K, int64_t rows, const Tin *in, const double *W,
+             Tout *out, const int32_t *flag, const SvDevInfo *info);
+// status = E_NUMERIC if any of x[0..n) is not finite.
+void check_finite(hipStream_t st, int64_t n, const double *x, SvDevInfo *info, int seq);
+void fill_identity(hipStream_t st, int K, double *W);
+// Per-update bookkeeping in the device status block.
+void op_begin(hipStream_t st, SvDevInfo *info, int two_sided);
+void op_end(hipStream_t st, SvDevInfo *info);
+
+// ---- eigen (k_eig.hip)
+// Top-k eigenpairs of a symmetric N x N FP64 matrix (A is destroyed):
+// lam[0..k) descending, Fv (k x N) row j = eigenvector of lam[j].
+// work must hold eig_work_doubles(N, k) doubles.
+size_t eig_work_doubles(int64_t N, int k);
+int eig_topk(hipStream_t st, int64_t N, double *A, int k, double *lam, double *Fv,
+             double *work, const SvDevInfo *info);
+int eig_max_n();
+
+}  // namespace svl

@@ -1,0 +1,65 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point declared in include/svlcov.h, and rejects bad arguments before touching
+the device (CPU only; no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "svlcov.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    decl = r"^\s*(?:svlcov_status|void\s*\*|void|const\s+char\s*\*)\s*(svlcov_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(decl, txt, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("svlcov_init", "svlcov_add_rows", "svlcov_add_cols", "svlcov_update_weights",
+              "svlcov_get_factors", "svlcov_sync", "svlcov_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2401_09703_amd as L
+    lib = C.CDLL(L.LIB_PATH)
+    for n in _declared():
+        assert hasattr(lib, n), n
+    assert set(L.EXPORTS) <= set(_declared())
+
+
+def test_status_strings_and_defaults():
+    import paper_2401_09703_amd as L
+    lib = L._lib
+    assert lib.svlcov_status_str(0) == b"ok"
+    assert lib.svlcov_status_str(2) == b"shape mismatch"
+    opt = L._Options()
+    lib.svlcov_default_options(C.byref(opt))
+    assert opt.precision == 0 and opt.validate_device_inputs == 1 and opt.stream is None
+
+
+def test_init_rejects_bad_arguments_before_device_use():
+    import paper_2401_09703_amd as L
+    lib = L._lib
+    h = C.c_void_p()
+    U = np.zeros((4, 16)); V = np.zeros((3, 16)); s = np.ones(16)
+    # unsupported k
+    assert lib.svlcov_init(C.byref(h), 4, 3, 7, U.ctypes.data, s[:7].ctypes.data,
+                           V.ctypes.data, 0, None) == 7
+    # increasing sigma
+    bad = np.arange(16, dtype=np.float64)
+    assert lib.svlcov_init(C.byref(h), 4, 3, 16, U.ctypes.data, bad.ctypes.data,
+                           V.ctypes.data, 0, None) == 1
+    # non-finite factor
+    U2 = U.copy(); U2[0, 0] = np.nan
+    assert lib.svlcov_init(C.byref(h), 4, 3, 16, U2.ctypes.data, s.ctypes.data,
+                           V.ctypes.data, 0, None) == 4
+    assert not h.value
+    # NULL state handles
+    assert lib.svlcov_sync(None) == 1
+    assert lib.svlcov_add_rows(None, None) == 1

@@ -1,0 +1,164 @@
+"""GPU parity: the HIP update path against the FP64 oracle (Zha-Simon, O1).
+
+Every comparison is lock-step (the oracle starts from the factors the GPU
+holds before the update, realised in FP64), so a difference measures the
+update alone.  Singular values are compared elementwise; singular vectors
+through principal angles of the leading subspace up to the last spectral gap
+(vectors are only defined up to sign and rotation inside repeated values).
+
+Tolerances: FP64 mode sigma_rel <= 1e-10, sin(angle) <= 1e-8 (gap 1e-6);
+FP32 and BF16x3 modes sigma_rel <= 1e-5, sin(angle) <= 1e-4 (gap 1e-3);
+orthonormality ||X^T X - I|| <= 1e-12 (FP64) / 1e-5 (FP32, BF16x3).
+"""
+import numpy as np
+import pytest
+
+from oracle import metrics, zha_simon
+from synth import CSR, small_case, synthetic_factors
+from synth.sparse import bernoulli_uniform
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": dict(sig=1e-10, ang=1e-8, delta=1e-6, orth=1e-12),
+       "fp32": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=1e-5),
+       "bf16x3": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=1e-5)}
+
+
+def _L():
+    import paper_2401_09703_amd as L
+    return L
+
+
+def _upd(c):
+    return ("weights", c["D_T"], c["Em_T"]) if c["kind"] == "weights" else (c["kind"], c["E"])
+
+
+def _lockstep(svd, update, prec, label):
+    U0, s0, V0 = svd.factors()
+    svd.apply(update)
+    svd.sync()
+    U1, s1, V1 = svd.factors()
+    Ur, sr, Vr, info = zha_simon.apply(U0, s0, V0, update)
+    t = TOL[prec]
+    r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], t["delta"])
+    print(label, prec, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in r.items()},
+          flush=True)
+    assert r["sigma_rel"] <= t["sig"], (label, r)
+    assert r["angle_U"] <= t["ang"] and r["angle_V"] <= t["ang"], (label, r)
+    assert r["orth_U"] <= t["orth"] and r["orth_V"] <= t["orth"], (label, r)
+    return r
+
+
+CASES = [
+    # m, n, k, s, kind, density, dup, empty, inspan
+    (300, 200, 16, 70, "rows", 0.05, 0, 0, 0),
+    (260, 330, 32, 100, "cols", 0.04, 0, 0, 0),
+    (250, 200, 64, 45, "weights", 0.05, 0, 0, 0),
+    (400, 300, 16, 90, "rows", 0.03, 3, 2, 0),
+    (300, 250, 32, 40, "cols", 0.05, 2, 1, 0),
+    (200, 150, 16, 20, "rows", 0.1, 0, 0, 3),
+    (600, 500, 128, 50, "rows", 0.04, 0, 0, 0),
+    (300, 280, 64, 33, "weights", 0.05, 2, 1, 0),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[4]}-m{c[0]}n{c[1]}k{c[2]}s{c[3]}")
+def test_single_update_parity(case, prec):
+    m, n, k, s, kind, dens, dup, empty, inspan = case
+    rng = np.random.default_rng(hash((m, n, k, s, kind)) % 2**32)
+    c = small_case(rng, m, n, k, s, kind=kind, density=dens, dup_rows=dup, empty_rows=empty,
+                   in_span_rows=inspan)
+    svd = _L().TruncatedSVD(c["U"], c["s"], c["V"], precision=prec)
+    try:
+        _lockstep(svd, _upd(c), prec, f"{kind} m{m} n{n} k{k} s{s}")
+    finally:
+        svd.close()
+
+
+def test_bernoulli_sequence_fp64():
+    """The small FP64 workload shape: Bernoulli 2000 x 1000 (density 0.5%),
+    k = 16, ten appends of 100 rows; lock-step after each, and the free-running
+    result at the end against the oracle run on its own from the same start."""
+    from synth import config1_rows
+    cfg = config1_rows()
+    svd = _L().TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision="fp64")
+    Uf, sf, Vf = cfg["U"], cfg["s"], cfg["V"]
+    try:
+        for t, up in enumerate(cfg["updates"]):
+            _lockstep(svd, up, "fp64", f"step{t}")
+            Uf, sf, Vf, info = zha_simon.apply(Uf, sf, Vf, up)
+        U, s, V = svd.factors()
+        r = metrics.compare((U, s, V), (Uf, sf, Vf), info["theta_hat"], 1e-6)
+        assert r["sigma_rel"] < 1e-10 and r["angle_U"] < 1e-7 and r["angle_V"] < 1e-7, r
+        assert U.shape == (3000, 16) and V.shape == (1000, 16)
+    finally:
+        svd.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_device_inputs_and_query(prec):
+    import torch
+    L = _L()
+    rng = np.random.default_rng(5)
+    c = small_case(rng, 200, 150, 32, 40, kind="rows", density=0.06)
+    svd = L.TruncatedSVD(c["U"], c["s"], c["V"], precision=prec)
+    try:
+        U0, s0, V0 = svd.factors()
+        E = L.DeviceCSR.from_host(c["E"])
+        svd.add_rows(E)
+        svd.sync()
+        U1, s1, V1 = svd.factors()
+        Ur, sr, Vr, info = zha_simon.add_rows(U0, s0, V0, c["E"])
+        r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], TOL[prec]["delta"])
+        assert r["sigma_rel"] <= TOL[prec]["sig"], r
+        # Query(i): one row of U and of V in O(k^2)
+        np.testing.assert_allclose(svd.query(0, 210), U1[210], atol=1e-12)
+        np.testing.assert_allclose(svd.query(1, 7), V1[7], atol=1e-12)
+    finally:
+        svd.close()
+
+
+def test_invalid_inputs_leave_state_unchanged():
+    L = _L()
+    rng = np.random.default_rng(9)
+    U, s, V = synthetic_factors(100, 80, 16, rng)
+    svd = L.TruncatedSVD(U, s, V, precision="fp64")
+    try:
+        before = svd.factors()
+        good = bernoulli_uniform(5, 80, 0.1, rng)
+        # wrong width
+        bad_shape = bernoulli_uniform(5, 81, 0.1, rng)
+        with pytest.raises(L.SvlcovError) as e:
+            svd.add_rows(bad_shape)
+        assert e.value.code == 2
+        # unsorted column ids in a host CSR
+        bad = CSR(good.rows, good.cols, good.row_ptr.copy(), good.col_idx.copy(), good.val.copy())
+        r0, r1 = bad.row_ptr[0], bad.row_ptr[1]
+        if r1 - r0 >= 2:
+            bad.col_idx[r0], bad.col_idx[r0 + 1] = bad.col_idx[r0 + 1], bad.col_idx[r0]
+        else:
+            bad.col_idx[0] = 80
+        with pytest.raises(L.SvlcovError) as e:
+            svd.add_rows(bad)
+        assert e.value.code == 1
+        # NaN value
+        nanv = CSR(good.rows, good.cols, good.row_ptr, good.col_idx, good.val.copy())
+        nanv.val[0] = np.nan
+        with pytest.raises(L.SvlcovError) as e:
+            svd.add_rows(nanv)
+        assert e.value.code == 4
+        # malformed device-resident CSR: detected on the device, reported at
+        # sync, and the factors and shape are unchanged
+        import torch
+        dev = L.DeviceCSR.from_host(good)
+        dev.col_idx[0] = 1000
+        svd.add_rows(dev)
+        with pytest.raises(L.SvlcovError) as e:
+            svd.sync()
+        assert e.value.code == 1
+        after = svd.factors()
+        for a, b in zip(before, after):
+            assert a.shape == b.shape and np.array_equal(a, b)
+    finally:
+        svd.close()
