@@ -157,6 +157,28 @@ svlcov_status svlcov_sync(svlcov_state *h);
 /* Counters and the numerical diagnostics of the last update (waits). */
 svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out);
 
+/* Diagnostics.  With profiling enabled, every phase of an update is bracketed
+ * by HIP events on the state's stream; svlcov_phase_times() waits, then adds
+ * the elapsed milliseconds and the number of occurrences of each phase since
+ * the previous call into ms[0..n) and count[0..n) (either may be NULL).  The
+ * phases are, in order: validate, spmm_w, sparse_gram, resid_gram, cholesky,
+ * build_K, kkt_gemm, tridiag, bisect, stein, backtransform, recover_G,
+ * orthonormalize, small_factor, trsm, commit. */
+#define SVLCOV_NUM_PHASES 16
+svlcov_status svlcov_profile(svlcov_state *h, int32_t enable);
+svlcov_status svlcov_phase_times(svlcov_state *h, double *ms, int64_t *count, int32_t n);
+const char *svlcov_phase_name(int32_t i);
+
+/* Building block of the (k+s) Rayleigh-Ritz SVD (Section 2.1, step 2): the k
+ * largest eigenpairs of the symmetric N x N FP64 matrix M (row-major, device
+ * memory, not modified).  lam (device, k doubles) receives the eigenvalues in
+ * non-increasing order, vecs (device, k x N row-major) the eigenvectors, one
+ * per row, sign fixed so that the entry of largest magnitude is positive.
+ * Workspace is allocated and freed on `stream` (hipStream_t, NULL = default
+ * stream).  N <= 6144 and k <= 128. */
+svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,
+                                  double *vecs, void *stream);
+
 /* The hipStream_t the state enqueues on. */
 void *svlcov_stream(svlcov_state *h);
 

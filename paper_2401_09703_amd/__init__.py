@@ -60,7 +60,10 @@ class _Stats(C.Structure):
 
 EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_add_cols",
            "svlcov_update_weights", "svlcov_get_factors", "svlcov_query_row", "svlcov_sync",
-           "svlcov_get_stats", "svlcov_stream", "svlcov_destroy", "svlcov_status_str"]
+           "svlcov_get_stats", "svlcov_stream", "svlcov_destroy", "svlcov_status_str",
+           "svlcov_profile", "svlcov_phase_times", "svlcov_phase_name",
+           "svlcov_sym_eig_topk"]
+NUM_PHASES = 16
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -83,6 +86,14 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_stream.restype = P
     lib.svlcov_destroy.argtypes = [P]
     lib.svlcov_destroy.restype = None
+    lib.svlcov_profile.argtypes = [P, I32]
+    lib.svlcov_profile.restype = I32
+    lib.svlcov_phase_times.argtypes = [P, P, P, I32]
+    lib.svlcov_phase_times.restype = I32
+    lib.svlcov_phase_name.argtypes = [I32]
+    lib.svlcov_phase_name.restype = C.c_char_p
+    lib.svlcov_sym_eig_topk.argtypes = [I64, P, I32, P, P, P]
+    lib.svlcov_sym_eig_topk.restype = I32
     lib.svlcov_status_str.argtypes = [I32]
     lib.svlcov_status_str.restype = C.c_char_p
     for name in ("svlcov_init", "svlcov_add_rows", "svlcov_add_cols", "svlcov_update_weights",
@@ -142,6 +153,20 @@ def _csr_struct(m, keep: list) -> _Csr:
     keep.extend([rp, ci, v])
     return _Csr(int(m.rows), int(m.cols), int(ci.size), rp.ctypes.data, ci.ctypes.data,
                 v.ctypes.data, 1 if v.dtype == np.float64 else 0, 0)
+
+
+def sym_eig_topk(M, k: int, stream=None):
+    """Top-k eigenpairs of a symmetric FP64 CUDA tensor M (N x N) on the GPU:
+    returns (lam, vecs) as CUDA tensors, lam descending, vecs k x N."""
+    import torch as _t
+    assert M.is_cuda and M.dtype == _t.float64 and M.is_contiguous()
+    N = M.shape[0]
+    lam = _t.empty(k, dtype=_t.float64, device=M.device)
+    vecs = _t.empty((k, N), dtype=_t.float64, device=M.device)
+    st = stream if stream is not None else _t.cuda.current_stream().cuda_stream
+    _check(_lib.svlcov_sym_eig_topk(N, M.data_ptr(), k, lam.data_ptr(), vecs.data_ptr(), st),
+           "svlcov_sym_eig_topk")
+    return lam, vecs
 
 
 class TruncatedSVD:
@@ -234,6 +259,18 @@ class TruncatedSVD:
         st = _Stats()
         _check(_lib.svlcov_get_stats(self._h, C.byref(st)), "svlcov_get_stats")
         return {f: getattr(st, f) for f, _ in _Stats._fields_}
+
+    def profile(self, enable: bool = True):
+        _check(_lib.svlcov_profile(self._h, 1 if enable else 0), "svlcov_profile")
+
+    def phase_times(self) -> dict:
+        """{phase name: (total ms, occurrences)} since the previous call."""
+        ms = np.zeros(NUM_PHASES)
+        cnt = np.zeros(NUM_PHASES, dtype=np.int64)
+        _check(_lib.svlcov_phase_times(self._h, ms.ctypes.data, cnt.ctypes.data, NUM_PHASES),
+               "svlcov_phase_times")
+        return {_lib.svlcov_phase_name(i).decode(): (float(ms[i]), int(cnt[i]))
+                for i in range(NUM_PHASES)}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -73,6 +73,54 @@ __device__ __forceinline__ double hash_unit(uint64_t x) {
   return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// Coherent (L2-bypassing) accesses for data that blocks of one cooperative
+// launch exchange: agent-scope relaxed atomics are served at the device
+// coherence point, so neither side needs an L2-wide writeback or invalidate.
+__device__ __forceinline__ void st_coh(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_coh(const double *p) {
+  return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr int FLAG_STRIDE = 16;   // one flag per 64-byte line
+
+// All-to-all arrival barrier of a cooperative launch: every block publishes
+// the epoch once its coherent stores have completed, then waits until every
+// block has published it.  Flags grow monotonically across launches (epochs
+// are never reused), so no reset is needed between barriers.
+__device__ __forceinline__ void flag_barrier(unsigned *flags, unsigned epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&flags[blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  for (unsigned t = threadIdx.x; t < gridDim.x; t += blockDim.x)
+    while (__hip_atomic_load(&flags[t * FLAG_STRIDE], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT) < epoch)
+      __builtin_amdgcn_s_sleep(1);
+  __syncthreads();
+}
+
+// In-place inverse of the n x n lower-triangular matrix in LDS (row stride
+// ld), column by column from the last one: column j of the inverse is
+// -inv(L_jj) * inv(L22) * L[j+1:, j] with the trailing block already
+// inverted.  tmp holds n doubles.  All threads of the block take part.
+__device__ inline void tri_lower_inv_inplace(double *L, int ld, int n, double *tmp) {
+  for (int j = n - 1; j >= 0; --j) {
+    const double ljj = 1.0 / L[j * ld + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      double y = 0.0;
+      for (int p = j + 1; p <= i; ++p) y += L[i * ld + p] * L[p * ld + j];
+      tmp[i] = -ljj * y;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) L[i * ld + j] = tmp[i];
+    if (threadIdx.x == 0) L[j * ld + j] = ljj;
+    __syncthreads();
+  }
+}
+
 }  // namespace svk
 
 // Device status word layout (one per state).

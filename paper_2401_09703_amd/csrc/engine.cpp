@@ -28,6 +28,22 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Phases of one update, timed with HIP events on the state's stream when
+// profiling is enabled (names in svlcov_phase_name).
+enum Phase {
+  PH_VALIDATE, PH_SPMM, PH_SGRAM, PH_RGRAM, PH_CHOL, PH_BUILDK, PH_KKT, PH_TRIDIAG, PH_BISECT,
+  PH_STEIN, PH_BACK, PH_RECOVER, PH_ORTH, PH_SMALL, PH_TRSM, PH_COMMIT, PH_COUNT
+};
+const char *PHASE_NAMES[PH_COUNT] = {
+    "validate", "spmm_w", "sparse_gram", "resid_gram", "cholesky", "build_K", "kkt_gemm",
+    "tridiag", "bisect", "stein", "backtransform", "recover_G", "orthonormalize",
+    "small_factor", "trsm", "commit"};
+
+struct EvRec {
+  int ph;
+  hipEvent_t a, b;
+};
+
 }  // namespace
 
 struct svlcov_state {
@@ -41,6 +57,9 @@ struct svlcov_state {
   void *Ubase = nullptr, *Vbase = nullptr;  // double (FP64) or float
   double *WU = nullptr, *WV = nullptr, *sigma = nullptr;
   SvDevInfo *info = nullptr;
+  unsigned *flags = nullptr;   // tridiagonalisation barrier flags
+  unsigned epoch = 0;
+  bool launch_failed = false;   // a cooperative launch was refused
   DevBuf ws;        // update workspace
   DevBuf stage;     // device copies of host CSR inputs
   DevBuf outbuf;    // get_factors staging
@@ -49,6 +68,9 @@ struct svlcov_state {
   int seq = 0;
   std::vector<Snapshot> history;
   std::atomic<bool> busy{false};
+  bool prof = false;
+  std::vector<EvRec> recs;
+  std::vector<hipEvent_t> evpool;
   size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
 };
 
@@ -71,6 +93,36 @@ svlcov_status dev_err(hipError_t e) {
   if (e == hipErrorOutOfMemory) return SVLCOV_E_NOMEM;
   return SVLCOV_E_DEVICE;
 }
+
+hipEvent_t get_event(svlcov_state *h) {
+  if (!h->evpool.empty()) {
+    hipEvent_t e = h->evpool.back();
+    h->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseScope {
+  svlcov_state *h;
+  int ph;
+  hipEvent_t a = nullptr;
+  PhaseScope(svlcov_state *hh, int p) : h(hh), ph(p) {
+    if (h->prof) {
+      a = get_event(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = get_event(h);
+    if (!b) return;
+    (void)hipEventRecord(b, h->stream);
+    h->recs.push_back({ph, a, b});
+  }
+};
 
 #define SV_TRY(expr)                                   \
   do {                                                 \
@@ -212,15 +264,28 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
-  svl::spmm_w<T>(st, K, s, E.rp, E.ci, E.v, E.vdt, base, W, Cp64,
-                 h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info);
-  svl::sparse_gram(st, s, E.rp, E.ci, E.v, E.vdt, Gm, s, h->info);
-  if (h->prec == SVLCOV_FP64)
-    svl::gemm_f64(st, false, true, s, s, K, -1.0, Cp64, K, Cp64, K, 1.0, Gm, s, h->info);
-  else
-    svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
+  {
+    PhaseScope ps(h, PH_SPMM);
+    svl::spmm_w<T>(st, K, s, E.rp, E.ci, E.v, E.vdt, base, W, Cp64,
+                   h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_SGRAM);
+    svl::sparse_gram(st, s, E.rp, E.ci, E.v, E.vdt, Gm, s, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_RGRAM);
+    if (h->prec == SVLCOV_FP64)
+      svl::gemm_f64(st, false, true, s, s, K, -1.0, Cp64, K, Cp64, K, 1.0, Gm, s, h->info);
+    else
+      svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
+  }
+  PhaseScope ps(h, PH_CHOL);
   svl::max_into(st, s, rown, h->info, which);
-  svl::cholesky_drop(st, s, Gm, s, Linv, h->rank_tol, h->info, which);
+  if (svl::cholesky_coop(st, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags, &h->epoch)) {
+    h->launch_failed = true;
+    svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+  }
 }
 
 // The (k+s) Rayleigh-Ritz SVD of K (N x N) through the eigenpairs of K K^T:
@@ -229,16 +294,51 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
 // re-orthonormalised, with an orthonormal completion where theta vanishes.
 svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mmat, double *lam,
                             double *theta, int32_t *complete, double *Fv, double *Gv,
-                            double *eigw) {
+                            double *eigw, double *gram_kk) {
   const int K = h->k;
   hipStream_t st = h->stream;
-  svl::gemm_f64(st, false, true, N, N, N, 1.0, Kmat, N, Kmat, N, 0.0, Mmat, N, h->info);
-  if (svl::eig_topk(st, N, Mmat, K, lam, Fv, eigw, h->info) != 0) return SVLCOV_E_DEVICE;
-  svl::gemm_f64(st, false, false, K, N, N, 1.0, Fv, N, Kmat, N, 0.0, Gv, N, h->info);
-  svl::theta_scale(st, K, lam, theta, Gv, N, complete, h->info);
-  svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, h->info);
-  svl::orthonormalize_rows(st, K, N, Gv, complete, (uint64_t)h->seq * 2 + 2, h->info);
+  {
+    PhaseScope ps(h, PH_KKT);
+    svl::gemm_f64(st, false, true, N, N, N, 1.0, Kmat, N, Kmat, N, 0.0, Mmat, N, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_TRIDIAG);
+    if (svl::eig_tridiag(st, N, Mmat, eigw, h->flags, &h->epoch, h->info) != 0) {
+      h->launch_failed = true;
+      svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+    }
+  }
+  {
+    PhaseScope ps(h, PH_BISECT);
+    svl::eig_bisect(st, N, K, lam, eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_STEIN);
+    svl::eig_stein(st, N, K, lam, Fv, eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_BACK);
+    svl::eig_back(st, N, K, Mmat, Fv, eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_RECOVER);
+    svl::gemm_f64_sk(st, false, false, K, N, N, 1.0, Fv, N, Kmat, N, 0.0, Gv, N,
+                     gram_kk + 2 * K * K + K * N, (size_t)8 * K * N, h->info);
+    svl::theta_scale(st, K, lam, theta, Gv, N, complete, h->info);
+  }
+  PhaseScope ps(h, PH_ORTH);
+  double *linv_kk = gram_kk + K * K, *xtmp = gram_kk + 2 * K * K;
+  double *gws = xtmp + K * N;
+  const size_t gws_len = (size_t)8 * K * N;
+  svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, gram_kk, linv_kk,
+                           xtmp, gws, gws_len, h->info);
+  svl::orthonormalize_rows(st, K, N, Gv, complete, (uint64_t)h->seq * 2 + 2, gram_kk, linv_kk,
+                           xtmp, gws, gws_len, h->info);
   svl::check_finite(st, K, theta, h->info, h->seq);
+  if (hipGetLastError() != hipSuccess) {   // a launch was refused: stop here
+    h->launch_failed = true;
+    svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+  }
   return SVLCOV_OK;
 }
 
@@ -247,13 +347,22 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
 // C_n X[k:] = Cp^T Y.  X is given by rows (Xv, K x N).
 void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, const double *Cp64,
                       const double *L, const double *Linv, const double *W, double *Y,
-                      double *T1, double *Wnew, double *Winv, int32_t *flag, int side) {
+                      double *T1, double *Wnew, double *Winv, int32_t *flag, int side,
+                      double *gws, size_t gws_len) {
   const int K = h->k;
   hipStream_t st = h->stream;
-  svl::copy_strided(st, s, K, Xv + K, 1, N, Y, K, h->info);
-  svl::trsm_lt(st, s, K, L, s, Linv, Y, h->info);
+  {
+    PhaseScope ps(h, PH_TRSM);
+    svl::copy_strided(st, s, K, Xv + K, 1, N, Y, K, h->info);
+    if (svl::trsm_coop(st, s, K, L, s, Linv, Y, h->info, h->flags, &h->epoch)) {
+      h->launch_failed = true;
+      svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+    }
+  }
+  PhaseScope ps(h, PH_SMALL);
   svl::copy_strided(st, K, K, Xv, 1, N, T1, K, h->info);
-  svl::gemm_f64(st, true, false, K, K, s, -1.0, Cp64, K, Y, K, 1.0, T1, K, h->info);
+  svl::gemm_f64_sk(st, true, false, K, K, s, -1.0, Cp64, K, Y, K, 1.0, T1, K, gws, gws_len,
+                   h->info);
   svl::gemm_f64(st, false, false, K, K, K, 1.0, W, K, T1, K, 0.0, Wnew, K, h->info);
   svl::inverse_cond(st, K, Wnew, Winv, flag, h->cond_reset, h->info, side);
 }
@@ -266,6 +375,7 @@ void sparse_side_commit(svlcov_state *h, const DevCsr &E, int64_t rows_used, T *
   const int K = h->k;
   hipStream_t st = h->stream;
   const int mode = mode_of(h->prec);
+  PhaseScope ps(h, PH_COMMIT);
   svl::realise<T, T>(st, mode, K, rows_used, base, Wnew, base, flag, h->info);
   svl::append_rows<double>(st, K, E.rows, Y, K, 1, Winv, flag, Mupd, h->info);
   svl::scatter<T>(st, K, E.rows, E.rp, E.ci, E.v, E.vdt, Mupd, base, h->info);
@@ -301,6 +411,8 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   const int64_t N = K + s;
   // workspace
   Carver c{nullptr};
+  double *orthw_p = nullptr;
+  double **orthw = &orthw_p;
   auto layout = [&](Carver &cv, double **Cp64, float **Cp32, double **rown, double **Gm,
                     double **Linv, double **Kmat, double **Mmat, double **lam, double **theta,
                     int32_t **complete, double **Fv, double **Gv, double **eigw, double **Y,
@@ -327,6 +439,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
     *WiB = cv.take<double>(K * K);
     *Mupd = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
+    *orthw = cv.take<double>(2 * K * K + 9 * K * N);
   };
   double *Cp64, *rown, *Gm, *Linv, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA,
       *WiA, *WnB, *WiB, *Mupd;
@@ -349,32 +462,48 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   h->seq += 1;
   h->history.push_back({h->seq, h->m, h->n});
   hipStream_t st = h->stream;
-  if (E->on_device && h->validate)
+  if (E->on_device && h->validate) {
+    PhaseScope ps(h, PH_VALIDATE);
     svl::validate_csr(st, dE.rows, dE.cols, dE.nnz, dE.rp, dE.ci, dE.v, dE.vdt, h->info, h->seq);
+  }
   svl::op_begin(st, h->info, 0);
   // orthogonalise the augmented matrix of the sparse side
   orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, 0);
   // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
-  svl::build_K_rows(st, K, s, h->sigma, Cp64, Gm, s, Kmat, h->info);
-  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw);
+  {
+    PhaseScope ps(h, PH_BUILDK);
+    svl::build_K_rows(st, K, s, h->sigma, Cp64, Gm, s, Kmat, h->info);
+  }
+  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p);
   if (r != SVLCOV_OK) return r;
   // append side: W_A F[:k]; its inverse and condition
-  svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
-  svl::inverse_cond(st, K, WnA, WiA, flags, h->cond_reset, h->info, sideA);
+  {
+    PhaseScope ps(h, PH_SMALL);
+    svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
+    svl::inverse_cond(st, K, WnA, WiA, flags, h->cond_reset, h->info, sideA);
+  }
   // sparse side: W_B (G[:k] - C_n G[k:])
-  sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB);
+  sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
+                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N);
   svl::check_finite(st, K * K, WnB, h->info, h->seq);
   svl::check_finite(st, K * K, WnA, h->info, h->seq);
   // commit: append side (realise on reset, appended rows F[k:] W^{-1})
   const int mode = mode_of(h->prec);
-  svl::realise<T, T>(st, mode, K, nA, A_base, WnA, A_base, flags, h->info);
-  svl::append_rows<T>(st, K, s, Fv + K, 1, N, WiA, flags, A_base + nA * K, h->info);
-  svl::commit_small(st, K, WnA, flags, W_A, theta, h->sigma, h->info, sideA);
+  {
+    PhaseScope ps(h, PH_COMMIT);
+    svl::realise<T, T>(st, mode, K, nA, A_base, WnA, A_base, flags, h->info);
+    svl::append_rows<T>(st, K, s, Fv + K, 1, N, WiA, flags, A_base + nA * K, h->info);
+    svl::commit_small(st, K, WnA, flags, W_A, theta, h->sigma, h->info, sideA);
+  }
   // commit: sparse side
   sparse_side_commit<T>(h, dE, nB, B_base, Y, Mupd, WnB, WiB, flags + 1, W_B, nullptr, nullptr,
                         sideB);
   svl::op_end(st, h->info);
   if (rows_form) h->m += s; else h->n += s;
+  if (h->launch_failed) {
+    h->launch_failed = false;
+    return SVLCOV_E_DEVICE;
+  }
   return SVLCOV_OK;
 }
 
@@ -394,6 +523,8 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
   if (!Em->on_device) { r = check_host_csr(Em); if (r != SVLCOV_OK) return r; }
   const int64_t N = K + s;
   T *Ub = (T *)h->Ubase, *Vb = (T *)h->Vbase;
+  double *orthw_p = nullptr;
+  double **orthw = &orthw_p;
   auto layout = [&](Carver &cv, double **CpD, double **CpE, float **C32D, float **C32E,
                     double **rnD, double **rnE, double **GD, double **GE, double **LiD,
                     double **LiE, double **X, double **Yx, double **Kmat, double **Mmat,
@@ -419,6 +550,7 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
     *WnV = cv.take<double>(K * K); *WiV = cv.take<double>(K * K);
     *MD = cv.take<double>(s * K); *ME = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
+    *orthw = cv.take<double>(2 * K * K + 9 * K * N);
   };
   double *CpD, *CpE, *rnD, *rnE, *GD, *GE, *LiD, *LiE, *X, *Yx, *Kmat, *Mmat, *lam, *theta, *Fv,
       *Gv, *eigw, *YD, *YE, *T1, *WnU, *WiU, *WnV, *WiV, *MD, *ME;
@@ -447,6 +579,7 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
   h->history.push_back({h->seq, h->m, h->n});
   hipStream_t st = h->stream;
   if (h->validate) {
+    PhaseScope ps(h, PH_VALIDATE);
     if (D->on_device)
       svl::validate_csr(st, dD.rows, dD.cols, dD.nnz, dD.rp, dD.ci, dD.v, dD.vdt, h->info, h->seq);
     if (Em->on_device)
@@ -457,19 +590,28 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
   orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, 0);
   orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, 1);
   // K = [[Sigma, 0], [0, 0]] + [U^T D ; R_D] [V^T E_m ; R_E]^T
-  svl::build_X(st, K, s, CpD, GD, s, X, h->info);
-  svl::build_X(st, K, s, CpE, GE, s, Yx, h->info);
-  svl::gemm_f64(st, false, true, N, N, s, 1.0, X, s, Yx, s, 0.0, Kmat, N, h->info);
-  svl::add_sigma_diag(st, K, h->sigma, Kmat, N, h->info);
-  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw);
+  {
+    PhaseScope ps(h, PH_BUILDK);
+    svl::build_X(st, K, s, CpD, GD, s, X, h->info);
+    svl::build_X(st, K, s, CpE, GE, s, Yx, h->info);
+    svl::gemm_f64(st, false, true, N, N, s, 1.0, X, s, Yx, s, 0.0, Kmat, N, h->info);
+    svl::add_sigma_diag(st, K, h->sigma, Kmat, N, h->info);
+  }
+  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p);
   if (r != SVLCOV_OK) return r;
-  sparse_side_math(h, s, N, Fv, CpD, GD, LiD, h->WU, YD, T1, WnU, WiU, flags, 0);
-  sparse_side_math(h, s, N, Gv, CpE, GE, LiE, h->WV, YE, T1, WnV, WiV, flags + 1, 1);
+  sparse_side_math(h, s, N, Fv, CpD, GD, LiD, h->WU, YD, T1, WnU, WiU, flags, 0,
+                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N);
+  sparse_side_math(h, s, N, Gv, CpE, GE, LiE, h->WV, YE, T1, WnV, WiV, flags + 1, 1,
+                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N);
   svl::check_finite(st, K * K, WnU, h->info, h->seq);
   svl::check_finite(st, K * K, WnV, h->info, h->seq);
   sparse_side_commit<T>(h, dD, h->m, Ub, YD, MD, WnU, WiU, flags, h->WU, theta, h->sigma, 0);
   sparse_side_commit<T>(h, dEm, h->n, Vb, YE, ME, WnV, WiV, flags + 1, h->WV, nullptr, nullptr, 1);
   svl::op_end(st, h->info);
+  if (h->launch_failed) {
+    h->launch_failed = false;
+    return SVLCOV_E_DEVICE;
+  }
   return SVLCOV_OK;
 }
 
@@ -568,6 +710,11 @@ svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k, c
   if (hipMalloc(&h->WV, (size_t)k * k * 8) != hipSuccess) return fail(SVLCOV_E_NOMEM);
   if (hipMalloc(&h->sigma, (size_t)k * 8) != hipSuccess) return fail(SVLCOV_E_NOMEM);
   if (hipMalloc(&h->info, sizeof(SvDevInfo)) != hipSuccess) return fail(SVLCOV_E_NOMEM);
+  if (hipMalloc(&h->flags, svl::TRI_FLAG_WORDS * sizeof(unsigned)) != hipSuccess)
+    return fail(SVLCOV_E_NOMEM);
+  if (hipMemsetAsync(h->flags, 0, svl::TRI_FLAG_WORDS * sizeof(unsigned), h->stream) !=
+      hipSuccess)
+    return fail(SVLCOV_E_DEVICE);
   SvDevInfo zi;
   std::memset(&zi, 0, sizeof(zi));
   zi.rank2 = -1;
@@ -740,6 +887,38 @@ svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out) {
 
 void *svlcov_stream(svlcov_state *h) { return h ? (void *)h->stream : nullptr; }
 
+svlcov_status svlcov_profile(svlcov_state *h, int32_t enable) {
+  if (!h) return SVLCOV_E_INVALID;
+  h->prof = enable != 0;
+  return SVLCOV_OK;
+}
+
+svlcov_status svlcov_phase_times(svlcov_state *h, double *ms, int64_t *count, int32_t n) {
+  if (!h || n < 0) return SVLCOV_E_INVALID;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  SV_TRY(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < n; ++i) {
+    if (ms) ms[i] = 0.0;
+    if (count) count[i] = 0;
+  }
+  for (const EvRec &r : h->recs) {
+    float t = 0.f;
+    SV_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    if (r.ph < n) {
+      if (ms) ms[r.ph] += t;
+      if (count) count[r.ph] += 1;
+    }
+    h->evpool.push_back(r.a);
+    h->evpool.push_back(r.b);
+  }
+  h->recs.clear();
+  return SVLCOV_OK;
+}
+
+const char *svlcov_phase_name(int32_t i) {
+  return (i >= 0 && i < PH_COUNT) ? PHASE_NAMES[i] : "";
+}
+
 void svlcov_destroy(svlcov_state *h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
@@ -753,8 +932,36 @@ void svlcov_destroy(svlcov_state *h) {
   if (h->WV) (void)hipFree(h->WV);
   if (h->sigma) (void)hipFree(h->sigma);
   if (h->info) (void)hipFree(h->info);
+  if (h->flags) (void)hipFree(h->flags);
+  for (const EvRec &r : h->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
+}
+
+svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,
+                                  double *vecs, void *stream) {
+  if (N < 1 || k < 1 || k > N || !M || !lam || !vecs) return SVLCOV_E_INVALID;
+  if (N > svl::eig_max_n() || k > 128) return SVLCOV_E_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t wd = svl::eig_work_doubles(N, k);
+  char *mem = nullptr;
+  const size_t bytes = ((size_t)N * N + wd) * sizeof(double) + sizeof(SvDevInfo) +
+                       svl::TRI_FLAG_WORDS * sizeof(unsigned) + 1024;
+  SV_TRY(hipMallocAsync((void **)&mem, bytes, st));
+  double *A = (double *)mem;
+  double *work = A + (size_t)N * N;
+  SvDevInfo *info = (SvDevInfo *)(work + wd);
+  unsigned *flags = (unsigned *)(info + 1);
+  SV_TRY(hipMemsetAsync(info, 0, sizeof(SvDevInfo) + svl::TRI_FLAG_WORDS * sizeof(unsigned), st));
+  SV_TRY(hipMemcpyAsync(A, M, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  unsigned epoch = 0;
+  const int r = svl::eig_topk(st, N, A, k, lam, vecs, work, flags, &epoch, info);
+  SV_TRY(hipFreeAsync(mem, st));
+  return r == 0 ? SVLCOV_OK : SVLCOV_E_DEVICE;
 }
 
 const char *svlcov_status_str(svlcov_status s) {

@@ -1,0 +1,277 @@
+// The FP64 Cholesky of the residual Gram (the R of Algorithm 2, through
+// Lemma 3's identity R^T R = E E^T - (E V)(E V)^T) and the triangular solve
+// with its transpose (the normalisation T = R^{-1} applied to the Ritz block,
+// Equation (1)), each as one cooperative launch.  Blocks exchange data through
+// coherent (L2-bypassing) loads and stores and meet at flag barriers, so a
+// factorisation of s = 1000 costs two launches instead of ~150.
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace svk;
+
+namespace {
+
+constexpr int NB = svl::CHOL_NB;   // 32
+constexpr int CT = 64;   // one wave per block: block barriers are nearly free
+
+// Blocked right-looking Cholesky of the lower triangle of A (s x s, row
+// stride ld), pivot dropping as in the single-block diagonal factor: a pivot
+// d_j <= tol * scale sets column j of L to zero.  Per block column: every
+// block factors the diagonal block redundantly; the panel rows and the lower
+// trailing tiles are spread over the blocks; two barriers.  Linv receives the
+// inverse of each diagonal block (unit placeholders on dropped pivots, whose
+// rows and columns are then zeroed).
+__global__ void __launch_bounds__(CT)
+k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double *__restrict__ Linv, double tol,
+            SvDevInfo *__restrict__ info, int which, unsigned *__restrict__ flags,
+            unsigned epoch0) {
+  if (info->status) return;
+  __shared__ double Ld[NB][NB + 1];
+  __shared__ double Li[NB][NB + 1];
+  __shared__ double pan[CT / NB][NB + 1];
+  __shared__ double ta[NB][NB + 1];
+  __shared__ double tb[NB][NB + 1];
+  __shared__ double tmp[NB];
+  __shared__ int dropped[NB];
+  __shared__ double rd_sh;
+  __shared__ int drop_sh;
+  const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const double scale = which == 0 ? info->scale : info->scale2;
+  const double thr = tol * scale;
+  const int64_t nblk = (s + NB - 1) / NB;
+  unsigned ep = epoch0;
+  double st_maxdrop = -1.0, st_minkept = INFINITY;
+  int st_kept = 0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int64_t b0 = b * NB;
+    const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
+    const int64_t r0 = b0 + nb;
+    // (1) diagonal block, factored by every block
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int i = e / NB, j = e % NB;
+      Ld[i][j] = (i < nb && j <= i) ? ld_coh(&A[(b0 + i) * ld + b0 + j]) : 0.0;
+    }
+    if (tid < NB) dropped[tid] = 0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+      if (tid == 0) {
+        const double d = Ld[j][j];
+        const bool drop = !(d > thr) || !(scale > 0.0);
+        const double rd = drop ? 0.0 : sqrt(d);
+        dropped[j] = drop ? 1 : 0;
+        drop_sh = drop ? 1 : 0;
+        rd_sh = rd;
+        Ld[j][j] = rd;
+        const double rel = scale > 0.0 ? d / scale : 0.0;
+        if (drop) st_maxdrop = fmax(st_maxdrop, rel);
+        else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
+      }
+      __syncthreads();
+      const int m = nb - j - 1;
+      if (tid < m) Ld[j + 1 + tid][j] = drop_sh ? 0.0 : Ld[j + 1 + tid][j] / rd_sh;
+      __syncthreads();
+      for (int e = tid; e < m * m; e += CT) {
+        const int i = j + 1 + e / m, c = j + 1 + e % m;
+        if (c <= i) Ld[i][c] -= Ld[i][j] * Ld[c][j];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int i = e / NB, j = e % NB;
+      double v = (i < nb && j <= i) ? Ld[i][j] : 0.0;
+      if (i == j && (i >= nb || dropped[i])) v = 1.0;
+      Li[i][j] = v;
+    }
+    __syncthreads();
+    tri_lower_inv_inplace(&Li[0][0], NB + 1, NB, tmp);
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int i = e / NB, j = e % NB;
+      if (j > i || i >= nb || j >= nb || dropped[i] || dropped[j]) Li[i][j] = 0.0;
+    }
+    __syncthreads();
+    // (2) panel: L[r][b0:b0+nb] = A[r][b0:b0+nb] Linv^T for r >= r0; 8 rows
+    // per pass, 32 threads per row
+    const int grp = tid / NB, c = tid % NB;
+    for (int64_t base = (int64_t)g * (CT / NB); base < s - r0; base += (int64_t)P * (CT / NB)) {
+      const int64_t r = r0 + base + grp;
+      pan[grp][c] = (r < s && c < nb) ? ld_coh(&A[r * ld + b0 + c]) : 0.0;
+      __syncthreads();
+      if (r < s && c < nb) {
+        double v = 0.0;
+        for (int p = 0; p < nb; ++p) v += pan[grp][p] * Li[c][p];
+        st_coh(&A[r * ld + b0 + c], v);
+      }
+      __syncthreads();
+    }
+    flag_barrier(flags, ++ep);
+    // every block has read the diagonal block: block 0 may now overwrite it
+    // with its factor (nothing reads it again in this launch)
+    if (g == 0) {
+      for (int e = tid; e < nb * nb; e += CT) {
+        const int i = e / nb, j = e % nb;
+        st_coh(&A[(b0 + i) * ld + b0 + j], j <= i ? Ld[i][j] : 0.0);
+      }
+      for (int e = tid; e < NB * NB; e += CT) Linv[b * NB * NB + e] = Li[e / NB][e % NB];
+    }
+    // (3) trailing update of the lower tiles of rows/columns >= r0
+    const int64_t T = (s - r0 + NB - 1) / NB;
+    const int64_t ntiles = T * (T + 1) / 2;
+    for (int64_t t = g; t < ntiles; t += P) {
+      int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      while (ti * (ti + 1) / 2 > t) --ti;
+      const int64_t tj = t - ti * (ti + 1) / 2;
+      const int64_t ra = r0 + ti * NB, rb = r0 + tj * NB;
+      for (int e = tid; e < NB * NB; e += CT) {
+        const int i = e / NB, p = e % NB;
+        ta[i][p] = (ra + i < s && p < nb) ? ld_coh(&A[(ra + i) * ld + b0 + p]) : 0.0;
+        tb[i][p] = (rb + i < s && p < nb) ? ld_coh(&A[(rb + i) * ld + b0 + p]) : 0.0;
+      }
+      __syncthreads();
+      for (int e = tid; e < NB * NB; e += CT) {
+        const int i = e / NB, j = e % NB;
+        if (ra + i < s && rb + j < s && (ti != tj || j <= i)) {
+          double acc = 0.0;
+          for (int p = 0; p < nb; ++p) acc += ta[i][p] * tb[j][p];
+          double *dst = &A[(ra + i) * ld + rb + j];
+          st_coh(dst, ld_coh(dst) - acc);
+        }
+      }
+      __syncthreads();
+    }
+    flag_barrier(flags, ++ep);
+  }
+  if (g == 0 && tid == 0) {
+    if (st_maxdrop > info->max_dropped) info->max_dropped = st_maxdrop;
+    if (st_minkept < info->min_kept) info->min_kept = st_minkept;
+    if (which == 0) info->rank += st_kept; else info->rank2 += st_kept;
+  }
+}
+
+// Y <- L^{-T} Y (Y is s x K row-major, K <= 128) with the factor and the
+// diagonal-block inverses of k_chol_coop, by block rows from the bottom.
+// Per block row b every block forms Y_b = Linv_b^T Z_b redundantly; block 0
+// stores it; the rows above are updated, Z_r -= L[b rows, r]^T Y_b, spread
+// over the blocks; one barrier.
+__global__ void __launch_bounds__(CT)
+k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
+            const double *__restrict__ Linv, double *__restrict__ Y,
+            const SvDevInfo *__restrict__ info, unsigned *__restrict__ flags, unsigned epoch0) {
+  if (info->status) return;
+  __shared__ double Zb[NB][129];
+  __shared__ double Yb[NB][129];
+  __shared__ double Li[NB][NB + 1];
+  __shared__ double lc[1][NB];
+  const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int64_t nblk = (s + NB - 1) / NB;
+  unsigned ep = epoch0;
+  for (int64_t b = nblk - 1; b >= 0; --b) {
+    const int64_t b0 = b * NB;
+    const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
+    for (int e = tid; e < NB * NB; e += CT) Li[e / NB][e % NB] = Linv[b * NB * NB + e];
+    for (int e = tid; e < NB * K; e += CT) {
+      const int i = e / K, c = e % K;
+      Zb[i][c] = i < nb ? ld_coh(&Y[(b0 + i) * K + c]) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < NB * K; e += CT) {
+      const int i = e / K, c = e % K;
+      double v = 0.0;
+      for (int p = 0; p < nb; ++p) v += Li[p][i] * Zb[p][c];
+      Yb[i][c] = v;
+    }
+    __syncthreads();
+    // rows r < b0: one row per pass, lanes over the K columns
+    const int w = 0, lane = tid;
+    for (int64_t base = (int64_t)g; base < b0; base += (int64_t)P) {
+      const int64_t r = base + w;
+      if (r < b0 && lane < nb) lc[w][lane] = L[(b0 + lane) * ld + r];
+      __syncthreads();
+      if (r < b0) {
+        for (int c = lane; c < K; c += 64) {
+          double acc = 0.0;
+          for (int p = 0; p < nb; ++p) acc += lc[w][p] * Yb[p][c];
+          double *dst = &Y[r * K + c];
+          st_coh(dst, ld_coh(dst) - acc);
+        }
+      }
+      __syncthreads();
+    }
+    flag_barrier(flags, ++ep);
+    // every block has read Z_b: block 0 may now store Y_b over it
+    if (g == 0)
+      for (int e = tid; e < nb * K; e += CT) st_coh(&Y[(b0 + e / K) * K + e % K], Yb[e / K][e % K]);
+    __syncthreads();
+  }
+}
+
+__global__ void k_set_status(SvDevInfo *info, int code) {
+  if (atomicCAS(&info->status, 0, code) == 0) info->failed_seq = -1;
+}
+
+__global__ void k_zero_flags(unsigned *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+int coop_blocks(const void *fn, int want) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 1;
+  }
+  int nb = 0;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, CT, 0);
+  (void)hipGetLastError();
+  int lim = nb * ncu;
+  if (lim > svl::TRI_MAX_BLOCKS) lim = svl::TRI_MAX_BLOCKS;
+  if (want > lim) want = lim;
+  return want < 1 ? 1 : want;
+}
+
+}  // namespace
+
+namespace svl {
+
+void set_status(hipStream_t st, SvDevInfo *info, int code) {
+  hipLaunchKernelGGL(k_set_status, dim3(1), dim3(1), 0, st, info, code);
+}
+
+unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned count) {
+  if (*epoch > 0xF0000000u - count) {   // keep epochs monotonic: restart from zero
+    hipLaunchKernelGGL(k_zero_flags, dim3(16), dim3(256), 0, st, flags, TRI_FLAG_WORDS);
+    *epoch = 0;
+  }
+  const unsigned e0 = *epoch;
+  *epoch += count + 1u;
+  return e0;
+}
+
+int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv, double tol,
+                  SvDevInfo *info, int which, unsigned *flags, unsigned *epoch) {
+  if (s <= 0) return 0;
+  const int64_t nblk = (s + NB - 1) / NB;
+  const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), (int)((s + 3) / 4));
+  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)(2 * nblk));
+  void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&Linv, (void *)&tol,
+                  (void *)&info, (void *)&which, (void *)&flags, (void *)&e0};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_coop), dim3(P),
+                                    dim3(CT), args, 0, st) == hipSuccess ? 0 : -3;
+}
+
+int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,
+              double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch) {
+  if (s <= 0) return 0;
+  const int64_t nblk = (s + NB - 1) / NB;
+  const int P = coop_blocks(reinterpret_cast<const void *>(k_trsm_coop), (int)((s + 3) / 4));
+  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)nblk);
+  void *args[] = {(void *)&s, (void *)&K, (void *)&L, (void *)&ld, (void *)&Linv,
+                  (void *)&Y, (void *)&info, (void *)&flags, (void *)&e0};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_trsm_coop), dim3(P),
+                                    dim3(CT), args, 0, st) == hipSuccess ? 0 : -3;
+}
+
+}  // namespace svl

@@ -17,12 +17,24 @@ namespace {
 // ------------------------------------------------------------------ FP64 GEMM
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
 
+// With part != nullptr the launch is split over K: block z sums the products
+// of k in [z*kchunk, (z+1)*kchunk) and writes alpha times its partial sum to
+// part[z][M][N] (beta is ignored; k_gemm_reduce finishes).
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256)
-k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *__restrict__ A,
+k_gemm_f64(int64_t M, int64_t N, int64_t Kfull, double alpha, const double *__restrict__ A,
            int64_t lda, const double *__restrict__ B, int64_t ldb, double beta,
-           double *__restrict__ C, int64_t ldc, const SvDevInfo *__restrict__ info) {
+           double *__restrict__ C, int64_t ldc, int64_t kchunk, double *__restrict__ part,
+           const SvDevInfo *__restrict__ info) {
   if (info && info->status) return;
+  int64_t K = Kfull;
+  if (part) {
+    const int64_t kb = (int64_t)blockIdx.z * kchunk;
+    const int64_t ke = kb + kchunk < Kfull ? kb + kchunk : Kfull;
+    K = ke > kb ? ke - kb : 0;
+    A += TA ? kb * lda : kb;
+    B += TB ? kb : kb * ldb;
+  }
   __shared__ double As[GB_K][GB_M + 1];
   __shared__ double Bs[GB_K][GB_N + 1];
   const int tid = threadIdx.x;
@@ -74,10 +86,27 @@ k_gemm_f64(int64_t M, int64_t N, int64_t K, double alpha, const double *__restri
       const int64_t gj = n0 + tx + 16 * c;
       if (gj >= N) continue;
       double v = alpha * acc[r][c];
+      if (part) {
+        part[((int64_t)blockIdx.z * M + gi) * N + gj] = v;
+        continue;
+      }
       if (beta != 0.0) v += beta * C[gi * ldc + gj];
       C[gi * ldc + gj] = v;
     }
   }
+}
+
+__global__ void k_gemm_reduce(int64_t M, int64_t N, int splits, const double *__restrict__ part,
+                              double beta, double *__restrict__ C, int64_t ldc,
+                              const SvDevInfo *__restrict__ info) {
+  if (info && info->status) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M * N) return;
+  const int64_t i = e / N, j = e % N;
+  double v = 0.0;
+  for (int z = 0; z < splits; ++z) v += part[(int64_t)z * M * N + e];
+  if (beta != 0.0) v += beta * C[i * ldc + j];
+  C[i * ldc + j] = v;
 }
 
 // ------------------------------------------------- residual Gram on MFMA
@@ -212,18 +241,19 @@ __global__ void k_max_into(int64_t n, const double *__restrict__ v, SvDevInfo *i
 }
 
 // Factor the nb x nb diagonal block at (b0, b0) of the (already updated)
-// lower triangle.  A pivot d_j <= tol * scale is dropped: column j of L is set
-// to zero.  Writes L into G, zeroes the block's strict upper part, and writes
-// Linv = inverse of L with 1 in place of each dropped pivot, then with row
-// and column j of every dropped pivot zeroed.
+// lower triangle, right-looking in LDS.  A pivot d_j <= tol * scale is
+// dropped: column j of L is set to zero.  Writes L into G, zeroes the block's
+// strict upper part, and writes Linv = inverse of L with 1 in place of each
+// dropped pivot, then with row and column j of every dropped pivot zeroed.
 __global__ void __launch_bounds__(256)
 k_chol_diag(int64_t s, double *__restrict__ G, int64_t ld, int64_t b0,
             double *__restrict__ Linv, double tol, SvDevInfo *__restrict__ info, int which) {
   if (info->status) return;
   constexpr int NB = svl::CHOL_NB;
   __shared__ double L[NB][NB + 1];
-  __shared__ double Li[NB][NB + 1];
   __shared__ int dropped[NB];
+  __shared__ double rd_sh;
+  __shared__ int drop_sh;
   const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
   const int tid = threadIdx.x;
   const double scale = which == 0 ? info->scale : info->scale2;
@@ -231,16 +261,14 @@ k_chol_diag(int64_t s, double *__restrict__ G, int64_t ld, int64_t b0,
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
     L[i][j] = (i < nb && j <= i) ? G[(b0 + i) * ld + b0 + j] : 0.0;
-    Li[i][j] = 0.0;
   }
+  if (tid < NB) dropped[tid] = 0;
   __syncthreads();
-  // left-looking column Cholesky inside the block
-  __shared__ double rd_sh;
-  __shared__ int drop_sh;
+  double st_maxdrop = -1.0, st_minkept = INFINITY;
+  int st_kept = 0;
   for (int j = 0; j < nb; ++j) {
     if (tid == 0) {
-      double d = L[j][j];
-      for (int p = 0; p < j; ++p) d -= L[j][p] * L[j][p];
+      const double d = L[j][j];
       const bool drop = !(d > thr) || !(scale > 0.0);
       const double rd = drop ? 0.0 : sqrt(d);
       dropped[j] = drop ? 1 : 0;
@@ -248,40 +276,44 @@ k_chol_diag(int64_t s, double *__restrict__ G, int64_t ld, int64_t b0,
       rd_sh = rd;
       L[j][j] = rd;
       const double rel = scale > 0.0 ? d / scale : 0.0;
-      if (drop) {
-        if (rel > info->max_dropped) info->max_dropped = rel;
-      } else {
-        if (rel < info->min_kept) info->min_kept = rel;
-        if (which == 0) info->rank += 1; else info->rank2 += 1;
-      }
+      if (drop) st_maxdrop = fmax(st_maxdrop, rel);
+      else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
     }
     __syncthreads();
-    const int i = j + 1 + tid;
-    if (i < nb) {
-      double v = L[i][j];
-      for (int p = 0; p < j; ++p) v -= L[i][p] * L[j][p];
-      L[i][j] = drop_sh ? 0.0 : v / rd_sh;
+    const int m = nb - j - 1;
+    if (tid < m) L[j + 1 + tid][j] = drop_sh ? 0.0 : L[j + 1 + tid][j] / rd_sh;
+    __syncthreads();
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e / m, c = j + 1 + e % m;
+      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular block with unit placeholders: one thread
-  // per column, forward substitution.
-  if (tid < nb) {
-    const int c = tid;
-    for (int i = 0; i < nb; ++i) {
-      double v = (i == c) ? 1.0 : 0.0;
-      for (int p = c; p < i; ++p) v -= L[i][p] * Li[p][c];
-      const double dii = dropped[i] ? 1.0 : L[i][i];
-      Li[i][c] = (i < c) ? 0.0 : v / dii;
-    }
+  if (tid == 0) {
+    if (st_maxdrop > info->max_dropped) info->max_dropped = st_maxdrop;
+    if (st_minkept < info->min_kept) info->min_kept = st_minkept;
+    if (which == 0) info->rank += st_kept; else info->rank2 += st_kept;
   }
-  __syncthreads();
+  // inverse with unit placeholders on dropped pivots, then zero their rows
+  // and columns
+  __shared__ double Li[NB][NB + 1];
+  __shared__ double tmp[NB];
   for (int e = tid; e < NB * NB; e += blockDim.x) {
     const int i = e / NB, j = e % NB;
-    double v = Li[i][j];
-    if (i >= nb || j >= nb || dropped[i] || dropped[j]) v = 0.0;
-    Linv[e] = v;
-    if (i < nb && j < nb) G[(b0 + i) * ld + b0 + j] = (j <= i) ? L[i][j] : 0.0;
+    double v = (i < nb && j <= i) ? L[i][j] : 0.0;
+    if (i == j && (i >= nb || dropped[i])) v = 1.0;
+    Li[i][j] = v;
+  }
+  __syncthreads();
+  tri_lower_inv_inplace(&Li[0][0], NB + 1, NB, tmp);
+  for (int e = tid; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    const bool z = j > i || i >= nb || j >= nb || dropped[i] || dropped[j];
+    Linv[e] = z ? 0.0 : Li[i][j];
+  }
+  for (int e = tid; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    G[(b0 + i) * ld + b0 + j] = (j <= i) ? L[i][j] : 0.0;
   }
 }
 
@@ -362,143 +394,142 @@ __global__ void k_theta_scale(int K, const double *__restrict__ lam, double *__r
   for (int64_t c = threadIdx.x; c < N; c += blockDim.x) Gv[(int64_t)j * N + c] *= inv;
 }
 
-// Classical Gram-Schmidt, twice, over the K rows of X (K x N), one block.
-__global__ void __launch_bounds__(1024)
-k_orth_rows(int K, int64_t N, double *__restrict__ X, const int32_t *__restrict__ complete,
-            uint64_t seed, const SvDevInfo *__restrict__ info) {
+// Linv = L^{-1} for the Cholesky factor L of the K x K Gram Gm = X X^T, one
+// block of K threads (thread i owns row i; a non-positive pivot is replaced
+// by 1 so that the pass stays finite).  One half of a Cholesky-QR pass; the
+// other half is the product Linv X.
+__global__ void __launch_bounds__(128)
+k_chol_inv_small(int K, const double *__restrict__ Gm, double *__restrict__ Linv,
+                 const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  __shared__ double dots[128];
-  __shared__ double red[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  extern __shared__ double Ls[];   // K x (K+1) factor, inverted in place; K scratch
+  const int LD = K + 1;
+  const int i = threadIdx.x;
+  for (int e = i; e < K * K; e += blockDim.x) Ls[(e / K) * LD + e % K] = Gm[e];
+  __syncthreads();
+  // right-looking Cholesky: thread i updates row i
   for (int j = 0; j < K; ++j) {
-    double *xj = X + (int64_t)j * N;
-    for (int attempt = 0; attempt < 3; ++attempt) {
-      const bool refill = (attempt > 0) || (complete && complete[j]);
-      if (refill) {
-        for (int64_t c = tid; c < N; c += blockDim.x)
-          xj[c] = hash_unit(seed * 1000003ull + (uint64_t)j * 7919ull +
-                            (uint64_t)attempt * 104729ull + (uint64_t)c * 2654435761ull);
-        __syncthreads();
-      }
-      double nrm0 = 0.0;
-      for (int64_t c = tid; c < N; c += blockDim.x) nrm0 += xj[c] * xj[c];
-      nrm0 = sqrt(block_sum(nrm0, red));
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int i = w; i < j; i += nw) {
-          const double *xi = X + (int64_t)i * N;
-          double d = 0.0;
-          for (int64_t c = lane; c < N; c += 64) d += xi[c] * xj[c];
-          d = wave_sum(d);
-          if (lane == 0) dots[i] = d;
-        }
-        __syncthreads();
-        for (int64_t c = tid; c < N; c += blockDim.x) {
-          double v = xj[c];
-          for (int i = 0; i < j; ++i) v -= dots[i] * X[(int64_t)i * N + c];
-          xj[c] = v;
-        }
-        __syncthreads();
-      }
-      double nrm = 0.0;
-      for (int64_t c = tid; c < N; c += blockDim.x) nrm += xj[c] * xj[c];
-      nrm = sqrt(block_sum(nrm, red));
-      if (nrm > 1e-3 * nrm0 && nrm > 0.0) {
-        const double inv = 1.0 / nrm;
-        for (int64_t c = tid; c < N; c += blockDim.x) xj[c] *= inv;
-        __syncthreads();
-        break;
-      }
-      __syncthreads();
+    const double dj = Ls[j * LD + j];
+    const double rj = dj > 0.0 ? sqrt(dj) : 1.0;
+    if (i > j && i < K) Ls[i * LD + j] /= rj;
+    __syncthreads();
+    if (i == j) Ls[j * LD + j] = rj;
+    if (i > j && i < K) {
+      const double lij = Ls[i * LD + j];
+      for (int c = j + 1; c <= i; ++c) Ls[i * LD + c] -= lij * Ls[c * LD + j];
     }
+    __syncthreads();
+  }
+  tri_lower_inv_inplace(Ls, LD, K, Ls + K * LD);
+  for (int e = i; e < K * K; e += blockDim.x) {
+    const int r = e / K, c = e % K;
+    Linv[e] = c <= r ? Ls[r * LD + c] : 0.0;
   }
 }
 
-// In-place Gauss-Jordan inverse with partial pivoting (k <= 128, in LDS).
-__global__ void __launch_bounds__(1024)
+__global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
+                                   const int32_t *__restrict__ complete, uint64_t seed,
+                                   const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int j = blockIdx.x;
+  if (!complete[j]) return;
+  for (int64_t c = threadIdx.x; c < N; c += blockDim.x)
+    X[(int64_t)j * N + c] = hash_unit(seed * 1000003ull + (uint64_t)j * 7919ull +
+                                      (uint64_t)c * 2654435761ull);
+}
+
+// In-place Gauss-Jordan inverse with partial pivoting (k <= 128, in LDS);
+// one block of 64 (k <= 64) or 128 threads; thread i < k owns row i and
+// column i, the others only take part in the reductions and barriers.
+__global__ void __launch_bounds__(128)
 k_inverse_cond(int K, const double *__restrict__ W, double *__restrict__ Winv,
                int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
                int side) {
   if (info->status) return;
   extern __shared__ double sm[];
-  double *A = sm;                 // K x (K+1)
-  int *piv = (int *)(A + K * (K + 1));
-  __shared__ double red[16];
+  const int ld = K + 1;
+  double *A = sm;                          // K x (K+1)
+  int *piv = (int *)(A + K * ld);          // K
+  __shared__ double wbest[2];
+  __shared__ int widx[2];
+  __shared__ double red[2];
   __shared__ int sing;
-  const int tid = threadIdx.x, ld = K + 1;
-  for (int e = tid; e < K * K; e += blockDim.x) A[(e / K) * ld + e % K] = W[e];
-  if (tid == 0) sing = 0;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  const bool own = t < K;
+  for (int e = t; e < K * K; e += blockDim.x) A[(e / K) * ld + e % K] = W[e];
+  if (t == 0) sing = 0;
   __syncthreads();
-  // ||W||_1: max column sum
+  // ||W||_1: max column sum (thread t sums column t)
   double cs = 0.0;
-  if (tid < K) for (int r = 0; r < K; ++r) cs += fabs(A[r * ld + tid]);
-  const double n1 = block_max(tid < K ? cs : 0.0, red);
-  bool finite_in = isfinite(n1);
+  if (own)
+    for (int r = 0; r < K; ++r) cs += fabs(A[r * ld + t]);
+  cs = wave_max(cs);
+  if (lane == 0) red[wv] = cs;
+  __syncthreads();
+  const double n1 = nw > 1 ? fmax(red[0], red[1]) : red[0];
+  const bool finite_in = isfinite(n1);
   for (int c = 0; c < K && finite_in; ++c) {
-    // pivot search in column c (one wave)
-    if (tid < 64) {
-      double best = -1.0;
-      int bi = c;
-      for (int r = c + tid; r < K; r += 64) {
-        const double a = fabs(A[r * ld + c]);
-        if (a > best) { best = a; bi = r; }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (tid == 0) {
-        piv[c] = bi;
-        if (!(best > 1e-300) || !(best > 1e-15 * n1)) sing = 1;
-      }
+    // pivot: row of largest |A[r][c]|, r >= c (ties to the lower index)
+    double best = (own && t >= c) ? fabs(A[t * ld + c]) : -1.0;
+    int bi = t;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { wbest[wv] = best; widx[wv] = bi; }
+    __syncthreads();
+    if (t == 0) {
+      int p = widx[0];
+      double b = wbest[0];
+      if (nw > 1 && (wbest[1] > b)) { b = wbest[1]; p = widx[1]; }
+      piv[c] = p;
+      if (!(b > 1e-300) || !(b > 1e-15 * n1)) sing = 1;
     }
     __syncthreads();
     if (sing) break;
     const int p = piv[c];
-    if (p != c)
-      for (int j = tid; j < K; j += blockDim.x) {
-        const double t = A[c * ld + j];
-        A[c * ld + j] = A[p * ld + j];
-        A[p * ld + j] = t;
-      }
+    if (p != c && own) {   // thread t swaps entry t of rows c and p
+      const double a = A[c * ld + t];
+      A[c * ld + t] = A[p * ld + t];
+      A[p * ld + t] = a;
+    }
     __syncthreads();
     const double pv = A[c * ld + c];
     __syncthreads();
-    if (tid == 0) A[c * ld + c] = 1.0;
+    if (own) A[c * ld + t] = (t == c ? 1.0 : A[c * ld + t]) / pv;
     __syncthreads();
-    for (int j = tid; j < K; j += blockDim.x) A[c * ld + j] /= pv;
-    __syncthreads();
-    // eliminate rows r != c; A[r][c] (the multiplier) is read before the
-    // column itself is overwritten in the next phase
-    for (int e = tid; e < K * K; e += blockDim.x) {
-      const int r = e / K, j = e % K;
-      if (r == c || j == c) continue;
-      A[r * ld + j] -= A[r * ld + c] * A[c * ld + j];
+    if (own && t != c) {   // thread t eliminates row t
+      const double f = A[t * ld + c];
+      for (int j = 0; j < K; ++j)
+        if (j != c) A[t * ld + j] -= f * A[c * ld + j];
+      A[t * ld + c] = -f * A[c * ld + c];
     }
-    __syncthreads();
-    for (int r = tid; r < K; r += blockDim.x)
-      if (r != c) A[r * ld + c] = -A[r * ld + c] * A[c * ld + c];
     __syncthreads();
   }
   // undo the row interchanges as column interchanges, in reverse order
   if (!sing && finite_in) {
     for (int c = K - 1; c >= 0; --c) {
       const int p = piv[c];
-      if (p != c)
-        for (int r = tid; r < K; r += blockDim.x) {
-          const double t = A[r * ld + c];
-          A[r * ld + c] = A[r * ld + p];
-          A[r * ld + p] = t;
-        }
+      if (p != c && own) {
+        const double a = A[t * ld + c];
+        A[t * ld + c] = A[t * ld + p];
+        A[t * ld + p] = a;
+      }
       __syncthreads();
     }
   }
   double cs2 = 0.0;
-  if (tid < K) for (int r = 0; r < K; ++r) cs2 += fabs(A[r * ld + tid]);
-  const double ninv = block_max(tid < K ? cs2 : 0.0, red);
+  if (own)
+    for (int r = 0; r < K; ++r) cs2 += fabs(A[r * ld + t]);
+  cs2 = wave_max(cs2);
+  __syncthreads();
+  if (lane == 0) red[wv] = cs2;
+  __syncthreads();
+  const double ninv = nw > 1 ? fmax(red[0], red[1]) : red[0];
   const double kappa = (sing || !finite_in) ? INFINITY : n1 * ninv;
-  for (int e = tid; e < K * K; e += blockDim.x) Winv[e] = A[(e / K) * ld + e % K];
-  if (tid == 0) {
+  for (int e = t; e < K * K; e += blockDim.x) Winv[e] = A[(e / K) * ld + e % K];
+  if (t == 0) {
     const bool reset = !(kappa <= cond_reset);
     *flag = reset ? 1 : 0;
     if (side == 0) info->kappa_U = kappa; else info->kappa_V = kappa;
@@ -680,11 +711,36 @@ void gemm_f64(hipStream_t st, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
               const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
               double *C, int64_t ldc, const SvDevInfo *info) {
   if (M <= 0 || N <= 0) return;
-  dim3 grid((unsigned)((N + GB_N - 1) / GB_N), (unsigned)((M + GB_M - 1) / GB_M));
-  if (!tA && !tB) hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
-  else if (!tA && tB) hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
-  else if (tA && !tB) hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
-  else hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, info);
+  gemm_f64_sk(st, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0, info);
+}
+
+void gemm_f64_sk(hipStream_t st, bool tA, bool tB, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+                 double *C, int64_t ldc, double *ws, size_t ws_len, const SvDevInfo *info) {
+  if (M <= 0 || N <= 0) return;
+  const int64_t tiles = ((N + GB_N - 1) / GB_N) * ((M + GB_M - 1) / GB_M);
+  int64_t splits = 1;
+  if (ws && tiles < 128 && K >= 512) {
+    splits = (256 + tiles - 1) / tiles;
+    const int64_t by_k = K / 128;
+    if (splits > by_k) splits = by_k;
+    const int64_t by_ws = (int64_t)(ws_len / (size_t)(M * N));
+    if (splits > by_ws) splits = by_ws;
+    if (splits > 64) splits = 64;
+  }
+  double *part = splits > 1 ? ws : nullptr;
+  const int64_t kchunk = splits > 1 ? (K + splits - 1) / splits : K;
+  dim3 grid((unsigned)((N + GB_N - 1) / GB_N), (unsigned)((M + GB_M - 1) / GB_M),
+            (unsigned)splits);
+#define SV_GM(TA_, TB_) hipLaunchKernelGGL((k_gemm_f64<TA_, TB_>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, info)
+  if (!tA && !tB) SV_GM(false, false);
+  else if (!tA && tB) SV_GM(false, true);
+  else if (tA && !tB) SV_GM(true, false);
+  else SV_GM(true, true);
+#undef SV_GM
+  if (part)
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((M * N + 255) / 256)), dim3(256), 0, st, M,
+                       N, (int)splits, part, beta, C, ldc, info);
 }
 
 void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, double *G,
@@ -694,7 +750,11 @@ void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, doubl
   const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
   constexpr int KP = 128 + 8;
   static bool once = false;
-  if (!once) { allow_big_lds(k_gram_lowp<1>); allow_big_lds(k_gram_lowp<2>); once = true; }
+  if (!once) {
+    allow_big_lds(k_gram_lowp<1>); allow_big_lds(k_gram_lowp<2>);
+    (void)hipGetLastError();
+    once = true;
+  }
   if (mode == 1) {
     const size_t sh = 2 * 64 * KP * sizeof(float);
     hipLaunchKernelGGL((k_gram_lowp<1>), dim3(tiles), dim3(256), sh, st, s, K, C, G, ldg, info);
@@ -782,16 +842,29 @@ void theta_scale(hipStream_t st, int K, const double *lam, double *theta, double
 }
 
 void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int32_t *complete,
-                         uint64_t seed, const SvDevInfo *info) {
-  hipLaunchKernelGGL(k_orth_rows, dim3(1), dim3(1024), 0, st, K, N, X, complete, seed, info);
+                         uint64_t seed, double *Gm, double *Linv, double *Xtmp, double *ws,
+                         size_t ws_len, const SvDevInfo *info) {
+  if (complete)
+    hipLaunchKernelGGL(k_fill_random_rows, dim3(K), dim3(256), 0, st, K, N, X, complete, seed,
+                       info);
+  static bool once = false;
+  if (!once) { allow_big_lds(k_chol_inv_small); (void)hipGetLastError(); once = true; }
+  const size_t sh = (size_t)(K * (K + 1) + K) * sizeof(double);
+  // One Cholesky QR pass: the rows come in orthonormal to a few ulps (or, for
+  // completion rows, as random vectors far from the span of the others), and
+  // the orthogonality CholQR leaves is ~ u kappa^2 with kappa ~ 1 here.
+  gemm_f64_sk(st, false, true, K, K, N, 1.0, X, N, X, N, 0.0, Gm, K, ws, ws_len, info);
+  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(K), sh, st, K, Gm, Linv, info);
+  gemm_f64(st, false, false, K, N, K, 1.0, Linv, K, X, N, 0.0, Xtmp, N, info);
+  (void)hipMemcpyAsync(X, Xtmp, (size_t)K * N * sizeof(double), hipMemcpyDeviceToDevice, st);
 }
 
 void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
                   double cond_reset, SvDevInfo *info, int side) {
   const size_t sh = (size_t)K * (K + 1) * sizeof(double) + (size_t)K * sizeof(int) + 16;
   static bool once = false;
-  if (!once) { allow_big_lds(k_inverse_cond); once = true; }
-  hipLaunchKernelGGL(k_inverse_cond, dim3(1), dim3(1024), sh, st, K, W, Winv, flag, cond_reset,
+  if (!once) { allow_big_lds(k_inverse_cond); (void)hipGetLastError(); once = true; }
+  hipLaunchKernelGGL(k_inverse_cond, dim3(1), dim3(K <= 64 ? 64 : 128), sh, st, K, W, Winv, flag, cond_reset,
                      info, side);
 }
 
@@ -827,7 +900,7 @@ void realise(hipStream_t st, int mode, int K, int64_t rows, const Tin *in, const
       const int KP = K + 8;
       const size_t sh1 = (size_t)(64 + K) * KP * sizeof(float);
       const size_t sh2 = (size_t)2 * (64 + K) * KP * sizeof(unsigned short);
-#define SV_RL(MM, KK, SH) do { allow_big_lds(k_realise_lowp<MM, KK>); hipLaunchKernelGGL((k_realise_lowp<MM, KK>), dim3(blocks), dim3(256), SH, st, rows, in, W, out, flag, info); } while (0)
+#define SV_RL(MM, KK, SH) do { allow_big_lds(k_realise_lowp<MM, KK>); (void)hipGetLastError(); hipLaunchKernelGGL((k_realise_lowp<MM, KK>), dim3(blocks), dim3(256), SH, st, rows, in, W, out, flag, info); } while (0)
       if (mode == 1) {
         switch (K) { case 16: SV_RL(1, 16, sh1); break; case 32: SV_RL(1, 32, sh1); break;
                      case 64: SV_RL(1, 64, sh1); break; case 128: SV_RL(1, 128, sh1); break; }

@@ -31,6 +31,12 @@ void append_rows(hipStream_t st, int K, int64_t s, const double *src, int64_t rs
 void gemm_f64(hipStream_t st, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
               double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
               double beta, double *C, int64_t ldc, const SvDevInfo *info);
+// The same, split over K into at most ws_len / (M N) partial products (in ws)
+// when the output has few tiles; deterministic (fixed-order reduction).
+void gemm_f64_sk(hipStream_t st, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
+                 double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                 double beta, double *C, int64_t ldc, double *ws, size_t ws_len,
+                 const SvDevInfo *info);
 // G[i][j] -= sum_l C[i][l] C[j][l] on the lower-triangular tiles, with C
 // (s x K, float) multiplied on MFMA: mode 1 FP32, mode 2 BF16x3.
 void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, double *G,
@@ -49,6 +55,17 @@ void cholesky_drop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Lin
 void trsm_lt(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
              const double *Linv, double *Y, const SvDevInfo *info);
 constexpr int CHOL_NB = 32;
+// ---- cooperative (k_coop.hip): one launch each; flags/epoch as for eig_topk
+int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
+                  double rank_tol, SvDevInfo *info, int which, unsigned *flags,
+                  unsigned *epoch);
+int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
+              const double *Linv, double *Y, const SvDevInfo *info, unsigned *flags,
+              unsigned *epoch);
+// mark the update failed on the device (every later kernel becomes a no-op)
+void set_status(hipStream_t st, SvDevInfo *info, int code);
+// reserve count + 1 barrier epochs; zero the flags first when close to wrap
+unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned count);
 // K = [[diag(sig), 0], [Cp, L]]  (N = K+s square, the add-rows form).
 void build_K_rows(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
                   const double *L, int64_t ldl, double *Kout, const SvDevInfo *info);
@@ -62,10 +79,12 @@ void add_sigma_diag(hipStream_t st, int K, const double *sig, double *Kout, int6
 // theta is below tol * theta_0 for completion.
 void theta_scale(hipStream_t st, int K, const double *lam, double *theta, double *Gv,
                  int64_t N, int32_t *complete, const SvDevInfo *info);
-// Orthonormalise the K rows of X (K x N) by classical Gram-Schmidt twice,
-// replacing rows flagged in complete (may be NULL) by pseudo-random rows first.
+// Orthonormalise the K rows of X (K x N) by Cholesky QR applied twice,
+// replacing rows flagged in complete (may be NULL) by pseudo-random rows
+// first.  Gm, Linv: K x K scratch; Xtmp: K x N scratch.
 void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X,
-                         const int32_t *complete, uint64_t seed, const SvDevInfo *info);
+                         const int32_t *complete, uint64_t seed, double *Gm, double *Linv,
+                         double *Xtmp, double *ws, size_t ws_len, const SvDevInfo *info);
 // Winv = W^{-1} (k x k) by Gauss-Jordan with partial pivoting; kappa_1 into
 // info; *flag = 1 when kappa > cond_reset or W is singular.
 void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
@@ -90,8 +109,21 @@ void op_end(hipStream_t st, SvDevInfo *info);
 // lam[0..k) descending, Fv (k x N) row j = eigenvector of lam[j].
 // work must hold eig_work_doubles(N, k) doubles.
 size_t eig_work_doubles(int64_t N, int k);
+// flags: TRI_MAX_BLOCKS * 16 unsigned words, zeroed once by the owner; *epoch
+// is the owner's running epoch counter for them (starts at 0).
+constexpr int TRI_MAX_BLOCKS = 256;
+constexpr size_t TRI_FLAG_WORDS = (size_t)TRI_MAX_BLOCKS * 16;
 int eig_topk(hipStream_t st, int64_t N, double *A, int k, double *lam, double *Fv,
-             double *work, const SvDevInfo *info);
+             double *work, unsigned *flags, unsigned *epoch, const SvDevInfo *info);
+// The four stages of eig_topk, launched separately (same work layout).
+int eig_tridiag(hipStream_t st, int64_t N, double *A, double *work, unsigned *flags,
+                unsigned *epoch, const SvDevInfo *info);
+void eig_bisect(hipStream_t st, int64_t N, int k, double *lam, double *work,
+                const SvDevInfo *info);
+void eig_stein(hipStream_t st, int64_t N, int k, const double *lam, double *Fv, double *work,
+               const SvDevInfo *info);
+void eig_back(hipStream_t st, int64_t N, int k, const double *A, double *Fv, double *work,
+              const SvDevInfo *info);
 int eig_max_n();
 
 }  // namespace svl

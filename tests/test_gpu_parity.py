@@ -8,7 +8,7 @@ through principal angles of the leading subspace up to the last spectral gap
 
 Tolerances: FP64 mode sigma_rel <= 1e-10, sin(angle) <= 1e-8 (gap 1e-6);
 FP32 and BF16x3 modes sigma_rel <= 1e-5, sin(angle) <= 1e-4 (gap 1e-3);
-orthonormality ||X^T X - I|| <= 1e-12 (FP64) / 1e-5 (FP32, BF16x3).
+orthonormality ||X^T X - I|| <= 1e-11 (FP64) / 1e-5 (FP32, BF16x3).
 """
 import numpy as np
 import pytest
@@ -19,7 +19,7 @@ from synth.sparse import bernoulli_uniform
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": dict(sig=1e-10, ang=1e-8, delta=1e-6, orth=1e-12),
+TOL = {"fp64": dict(sig=1e-10, ang=1e-8, delta=1e-6, orth=1e-11),
        "fp32": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=1e-5),
        "bf16x3": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=1e-5)}
 
@@ -59,6 +59,9 @@ CASES = [
     (200, 150, 16, 20, "rows", 0.1, 0, 0, 3),
     (600, 500, 128, 50, "rows", 0.04, 0, 0, 0),
     (300, 280, 64, 33, "weights", 0.05, 2, 1, 0),
+    (900, 700, 64, 300, "rows", 0.01, 5, 3, 0),
+    (700, 900, 32, 257, "cols", 0.01, 4, 2, 0),
+    (800, 800, 16, 130, "weights", 0.01, 3, 2, 0),
 ]
 
 
