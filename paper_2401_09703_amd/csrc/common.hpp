@@ -73,6 +73,32 @@ __device__ __forceinline__ double hash_unit(uint64_t x) {
   return (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
 }
 
+// Synchronise the lanes of one wave through LDS (no block barrier): orders
+// this wave's LDS accesses before and after the call.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave-level variant of tri_lower_inv_inplace (only the calling wave takes
+// part; lane = threadIdx.x & 63).
+__device__ inline void tri_lower_inv_wave(double *L, int ld, int n, double *tmp) {
+  const int lane = threadIdx.x & 63;
+  for (int j = n - 1; j >= 0; --j) {
+    const double ljj = 1.0 / L[j * ld + j];
+    for (int i = j + 1 + lane; i < n; i += 64) {
+      double y = 0.0;
+      for (int p = j + 1; p <= i; ++p) y += L[i * ld + p] * L[p * ld + j];
+      tmp[i] = -ljj * y;
+    }
+    wave_sync();
+    for (int i = j + 1 + lane; i < n; i += 64) L[i * ld + j] = tmp[i];
+    if (lane == 0) L[j * ld + j] = ljj;
+    wave_sync();
+  }
+}
+
 // Coherent (L2-bypassing) accesses for data that blocks of one cooperative
 // launch exchange: agent-scope relaxed atomics are served at the device
 // coherence point, so neither side needs an L2-wide writeback or invalidate.

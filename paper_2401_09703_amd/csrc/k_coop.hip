@@ -12,7 +12,7 @@ using namespace svk;
 namespace {
 
 constexpr int NB = svl::CHOL_NB;   // 32
-constexpr int CT = 64;   // one wave per block: block barriers are nearly free
+constexpr int CT = 256;
 
 // Blocked right-looking Cholesky of the lower triangle of A (s x s, row
 // stride ld), pivot dropping as in the single-block diagonal factor: a pivot
@@ -53,40 +53,44 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double *__restrict__ 
     }
     if (tid < NB) dropped[tid] = 0;
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-      if (tid == 0) {
-        const double d = Ld[j][j];
-        const bool drop = !(d > thr) || !(scale > 0.0);
-        const double rd = drop ? 0.0 : sqrt(d);
-        dropped[j] = drop ? 1 : 0;
-        drop_sh = drop ? 1 : 0;
-        rd_sh = rd;
-        Ld[j][j] = rd;
-        const double rel = scale > 0.0 ? d / scale : 0.0;
-        if (drop) st_maxdrop = fmax(st_maxdrop, rel);
-        else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
+    // factor and invert the diagonal block with wave 0 alone (wave-level
+    // synchronisation only); the other waves wait at the block barrier
+    if (tid < 64) {
+      for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+          const double d = Ld[j][j];
+          const bool drop = !(d > thr) || !(scale > 0.0);
+          const double rd = drop ? 0.0 : sqrt(d);
+          dropped[j] = drop ? 1 : 0;
+          drop_sh = drop ? 1 : 0;
+          rd_sh = rd;
+          Ld[j][j] = rd;
+          const double rel = scale > 0.0 ? d / scale : 0.0;
+          if (drop) st_maxdrop = fmax(st_maxdrop, rel);
+          else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
+        }
+        wave_sync();
+        const int m = nb - j - 1;
+        if (tid < m) Ld[j + 1 + tid][j] = drop_sh ? 0.0 : Ld[j + 1 + tid][j] / rd_sh;
+        wave_sync();
+        for (int e = tid; e < m * m; e += 64) {
+          const int i = j + 1 + e / m, c = j + 1 + e % m;
+          if (c <= i) Ld[i][c] -= Ld[i][j] * Ld[c][j];
+        }
+        wave_sync();
       }
-      __syncthreads();
-      const int m = nb - j - 1;
-      if (tid < m) Ld[j + 1 + tid][j] = drop_sh ? 0.0 : Ld[j + 1 + tid][j] / rd_sh;
-      __syncthreads();
-      for (int e = tid; e < m * m; e += CT) {
-        const int i = j + 1 + e / m, c = j + 1 + e % m;
-        if (c <= i) Ld[i][c] -= Ld[i][j] * Ld[c][j];
+      for (int e = tid; e < NB * NB; e += 64) {
+        const int i = e / NB, j = e % NB;
+        double v = (i < nb && j <= i) ? Ld[i][j] : 0.0;
+        if (i == j && (i >= nb || dropped[i])) v = 1.0;
+        Li[i][j] = v;
       }
-      __syncthreads();
-    }
-    for (int e = tid; e < NB * NB; e += CT) {
-      const int i = e / NB, j = e % NB;
-      double v = (i < nb && j <= i) ? Ld[i][j] : 0.0;
-      if (i == j && (i >= nb || dropped[i])) v = 1.0;
-      Li[i][j] = v;
-    }
-    __syncthreads();
-    tri_lower_inv_inplace(&Li[0][0], NB + 1, NB, tmp);
-    for (int e = tid; e < NB * NB; e += CT) {
-      const int i = e / NB, j = e % NB;
-      if (j > i || i >= nb || j >= nb || dropped[i] || dropped[j]) Li[i][j] = 0.0;
+      wave_sync();
+      tri_lower_inv_wave(&Li[0][0], NB + 1, NB, tmp);
+      for (int e = tid; e < NB * NB; e += 64) {
+        const int i = e / NB, j = e % NB;
+        if (j > i || i >= nb || j >= nb || dropped[i] || dropped[j]) Li[i][j] = 0.0;
+      }
     }
     __syncthreads();
     // (2) panel: L[r][b0:b0+nb] = A[r][b0:b0+nb] Linv^T for r >= r0; 8 rows
@@ -161,7 +165,7 @@ k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
   __shared__ double Zb[NB][129];
   __shared__ double Yb[NB][129];
   __shared__ double Li[NB][NB + 1];
-  __shared__ double lc[1][NB];
+  __shared__ double lc[CT / 64][NB];
   const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int64_t nblk = (s + NB - 1) / NB;
   unsigned ep = epoch0;
@@ -181,9 +185,9 @@ k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
       Yb[i][c] = v;
     }
     __syncthreads();
-    // rows r < b0: one row per pass, lanes over the K columns
-    const int w = 0, lane = tid;
-    for (int64_t base = (int64_t)g; base < b0; base += (int64_t)P) {
+    // rows r < b0: 4 rows per pass (one wave each), lanes over the K columns
+    const int w = tid >> 6, lane = tid & 63;
+    for (int64_t base = (int64_t)g * (CT / 64); base < b0; base += (int64_t)P * (CT / 64)) {
       const int64_t r = base + w;
       if (r < b0 && lane < nb) lc[w][lane] = L[(b0 + lane) * ld + r];
       __syncthreads();
