@@ -22,6 +22,9 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -32,6 +35,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
+
+CSRC = os.path.join(ROOT, "paper_2401_09703_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+# phase -> (kernel name prefix, source files whose text defines the kernel)
+PHASE_KERNEL = {
+    "tridiag": ("k_tridiag", ["k_eig.hip", "common.hpp"]),
+    "cholesky": ("k_chol_coop", ["k_coop.hip", "common.hpp"]),
+    "spmm_w": ("k_spmm_w", ["k_sparse.hip", "common.hpp"]),
+    "kkt_gemm": ("k_gemm_f64", ["k_dense.hip", "common.hpp"]),
+}
+CALIB_KERNEL = ("neg", "elementwise")   # the copy used to scale the HBM counters
 
 
 def log(*a):
@@ -48,7 +62,111 @@ def parse():
     ap.add_argument("--step-nodes", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="bf16x3,fp32")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy (y = -x, FP32) of this many MiB first; "
+                         "its HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="print a summary of a rocprofv3 --kernel-trace --stats output and exit")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--phase", default="tridiag", help="phase whose kernel --summarize-pmc covers")
+    ap.add_argument("--calib-mib", type=int, default=0, help="size of the calibration copy")
     return ap.parse_args()
+
+
+def sources_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _csvs(d, suffix):
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def summarize_stats(d):
+    rows = []
+    for f in _csvs(d, "kernel_stats.csv"):
+        rows += list(csv.DictReader(open(f)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+    print(f"{'kernel':64s} {'calls':>6s} {'avg us':>10s} {'min us':>10s} {'max us':>10s} {'%':>6s}")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        print(f"{name[:64]:64s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.1f} "
+              f"{float(r['MinNs']) / 1e3:10.1f} {float(r['MaxNs']) / 1e3:10.1f} "
+              f"{100 * float(r['TotalDurationNs']) / tot:6.2f}")
+
+
+def _pmc(d, counter):
+    """Per-kernel lists of one counter's per-dispatch values (KiB)."""
+    out = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+            out.setdefault(name, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
+    prefix, files = PHASE_KERNEL[phase]
+    fe, wr = _pmc(fetch_dir, "FETCH_SIZE"), _pmc(write_dir, "WRITE_SIZE")
+
+    def pick(tab, key):
+        vals = [v for n, vs in tab.items() if key in n for v in vs]
+        if not vals:
+            raise SystemExit(f"no dispatch of a kernel matching {key!r}")
+        return vals
+
+    f_k, w_k = pick(fe, prefix), pick(wr, prefix)
+    calib_kib = calib_mib * 1024.0
+    def pick_calib(tab):
+        for key in CALIB_KERNEL:
+            vals = [v for n, vs in tab.items() if key in n for v in vs]
+            if vals:
+                return max(vals)
+        raise SystemExit("no calibration copy in the counter output")
+
+    f_c, w_c = pick_calib(fe), pick_calib(wr)
+    ff, wf = calib_kib / f_c, calib_kib / w_c
+    fetch = sum(f_k) / len(f_k) * 1024 * ff
+    write = sum(w_k) / len(w_k) * 1024 * wf
+    print(f"phase: {phase}")
+    print(f"kernel: {prefix}")
+    print(f"sources_sha256: {sources_sha(files)}")
+    print(f"dispatches_fetch: {len(f_k)}")
+    print(f"dispatches_write: {len(w_k)}")
+    print(f"fetch_kib_per_dispatch_raw: {sum(f_k) / len(f_k):.1f}")
+    print(f"write_kib_per_dispatch_raw: {sum(w_k) / len(w_k):.1f}")
+    print(f"calibration_copy_mib: {calib_mib}")
+    print(f"calibration_fetch_kib: {f_c:.1f}")
+    print(f"calibration_write_kib: {w_c:.1f}")
+    print(f"fetch_factor: {ff:.4f}")
+    print(f"write_factor: {wf:.4f}")
+    print(f"fetch_bytes_per_launch: {fetch:.0f}")
+    print(f"write_bytes_per_launch: {write:.0f}")
+    print(f"traffic_bytes_per_launch: {fetch + write:.0f}")
+
+
+def stored_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from the committed counter
+    summary, or None when there is none or the kernel's source has changed
+    since the counters were taken."""
+    if phase not in PHASE_KERNEL:
+        return None
+    prefix, files = PHASE_KERNEL[phase]
+    for f in sorted(glob.glob(os.path.join(PROFILES, f"pmc_{prefix}_*.txt"))):
+        kv = {}
+        for line in open(f):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if kv.get("sources_sha256") == sources_sha(files) and "traffic_bytes_per_launch" in kv:
+            return float(kv["traffic_bytes_per_launch"])
+    return None
 
 
 def phase_work(name, N, s, k, nnz, d_cols):
@@ -67,6 +185,12 @@ def phase_work(name, N, s, k, nnz, d_cols):
 
 def main():
     args = parse()
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.phase, args.calib_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the update path of one matrix is not sharded across GPUs here.",
@@ -78,6 +202,12 @@ def main():
     from synth import config2_graph
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.copy_calib_mib > 0:
+        x = torch.ones(args.copy_calib_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
+        del x, y
     W, K = args.warmup, args.steps
     t = time.time()
     cfg = config2_graph(k=args.k, n_init=args.n_init, step_nodes=args.step_nodes, steps=W + K)
@@ -187,18 +317,18 @@ def main():
         if unit == "flop":
             ach = work / avg_s / 1e12
             roof = dict(kernel=name, bound=bound, achieved=ach, peak=FP64_PEAK_TFS, unit="TFLOP/s",
-                        frac=ach / FP64_PEAK_TFS, traffic=None, avg_ms=ms / cnt)
+                        frac=ach / FP64_PEAK_TFS, traffic=stored_traffic(name), avg_ms=ms / cnt)
         else:
             ach = work / avg_s / 1e9
             roof = dict(kernel=name, bound=bound, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=ach / HBM_PEAK_GBS, traffic=None, avg_ms=ms / cnt)
+                        frac=ach / HBM_PEAK_GBS, traffic=stored_traffic(name), avg_ms=ms / cnt)
     sp_ms, sp_n = hr["phases"].get("spmm_w", (0.0, 0))
     spmm_roof = None
     if sp_n:
         b = phase_work("spmm_w", N, args.step_nodes, args.k, nnz_step, d_cols)[1]
         ach = b / (sp_ms / sp_n / 1e3) / 1e9
         spmm_roof = dict(achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                         avg_us=1e3 * sp_ms / sp_n, bytes=b)
+                         avg_us=1e3 * sp_ms / sp_n, bytes=b, traffic=stored_traffic("spmm_w"))
     gate_ok = all(g["sigma_rel"] <= 1e-5 for g in gate.values()) if gate else None
     out = {
         "metric": "update rows/s at k=64, BF16x3 vs FP32 path at sigma rel err <=1e-5; "

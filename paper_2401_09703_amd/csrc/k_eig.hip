@@ -3,178 +3,25 @@
 // K are the eigenvectors of K K^T and its eigenvalues are the squared singular
 // values.
 //
-//   1. Householder tridiagonalisation Q^T M Q = T in one cooperative kernel.
-//      Each block owns the rows r = g, g + G, ... of M (cyclic, so the
-//      shrinking trailing matrix stays balanced).  Per column one grid-wide
-//      barrier: every block recomputes the next reflector redundantly from the
-//      published row, applies the pending rank-2 update to its own rows fused
-//      with the product p = tau M v, and publishes its part of p.
-//   2. Bisection on Sturm counts for the k largest eigenvalues of T, one wave
-//      per eigenvalue with 64-way multisection.
+//   1. Householder tridiagonalisation Q^T M Q = T (its own source file).
+//   2. Bisection on Sturm counts for the k largest eigenvalues of T, one block
+//      per eigenvalue with 513-way multisection.
 //   3. Inverse iteration with the eigenvalue as shift (tridiagonal LU with
 //      partial pivoting), re-orthogonalised inside clusters of close
 //      eigenvalues.
-//   4. Back-transformation of the k vectors by the stored reflectors.
-#include <hip/hip_cooperative_groups.h>
-
+//   4. Back-transformation of the k vectors by the stored reflectors, in
+//      panels of 32 reflectors in compact WY form.
 #include <cstdlib>
 
 #include "common.hpp"
 #include "kernels.hpp"
 
 using namespace svk;
-namespace cg = cooperative_groups;
 
 namespace {
 
-constexpr int TRI_MAX_BLOCKS = svl::TRI_MAX_BLOCKS;
 constexpr double EPS = 1.1102230246251565e-16;     // 2^-53
 constexpr double SAFMIN = 2.2250738585072014e-308;
-
-// Householder tridiagonalisation, one cooperative launch (all blocks
-// co-resident).  Block g owns rows r = g, g + G, ...; with LDS_ROWS they live
-// in LDS for the whole reduction, otherwise in A.  Reflector i is left in row
-// i of A (columns i+1 .., unit leading entry), d, e, tau in work arrays.
-// NT = 64 (one wave per block: block-wide reductions and barriers are nearly
-// free) for moderate N, 256 when the owned rows need more lanes.
-template <bool LDS_ROWS, int NT>
-__global__ void __launch_bounds__(NT)
-k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
-          double *__restrict__ e, double *__restrict__ tau, double *__restrict__ pbuf,
-          double *__restrict__ rowbuf, unsigned *__restrict__ flags, unsigned epoch0,
-          const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
-  extern __shared__ double sm[];
-  __shared__ double red[NT / 64];
-  const int G = gridDim.x, g = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  constexpr int nw = NT / 64;
-  if (N < 3) {
-    if (g == 0 && tid == 0) {
-      d[0] = A[0];
-      if (N == 2) { e[0] = A[1]; d[1] = A[lda + 1]; }
-    }
-    return;
-  }
-  double *X = sm, *VP = sm + N, *WP = sm + 2 * N;
-  double *rows = sm + 3 * N;   // LDS_ROWS: owned rows, local index (r - g) / G
-  if constexpr (LDS_ROWS) {
-    const int nr = (N - g + G - 1) / G;
-    for (int lr = w; lr < nr; lr += nw) {
-      const double *src = A + (int64_t)(g + lr * G) * lda;
-      for (int j = lane; j < N; j += 64) rows[(int64_t)lr * N + j] = src[j];
-    }
-  }
-  double part = 0.0;   // sum of X[j]^2 over j >= i + 2, carried between iterations
-  for (int j = tid; j < N; j += NT) {
-    const double x = A[j];
-    X[j] = x;
-    if (j >= 2) part += x * x;
-  }
-  __syncthreads();
-  for (int i = 0; i <= N - 3; ++i) {
-    const double dii = X[i];
-    // alpha is read before the reduction: its barriers order every read of
-    // X[i+1] before thread 0 overwrites it with the unit leading entry
-    const double alpha = X[i + 1];
-    const double xn2 = NT == 64 ? wave_sum(part) : block_sum(part, red);
-    double beta, t, scl;
-    if (xn2 == 0.0) {
-      t = 0.0; beta = alpha; scl = 0.0;
-    } else {
-      const double nrm = sqrt(alpha * alpha + xn2);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      t = (beta - alpha) / beta;
-      scl = 1.0 / (alpha - beta);
-    }
-    for (int j = i + 2 + tid; j < N; j += NT) X[j] *= scl;
-    if (tid == 0) X[i + 1] = 1.0;
-    __syncthreads();
-    double *pb = pbuf + (int64_t)(i & 1) * N;
-    double *rb = rowbuf + (int64_t)(i & 1) * N;
-    // owned rows r >= i+1: pending rank-2 update, then p = tau M v
-    const int lr0 = (i + 1 - g + G - 1) / G > 0 ? (i + 1 - g + G - 1) / G : 0;
-    for (int lr = lr0 + w; g + lr * G < N; lr += nw) {
-      const int r = g + lr * G;
-      double *Ar;
-      if constexpr (LDS_ROWS) Ar = rows + (int64_t)lr * N;
-      else Ar = A + (int64_t)r * lda;
-      const double vpr = i >= 1 ? VP[r] : 0.0, wpr = i >= 1 ? WP[r] : 0.0;
-      const bool pub = (r == i + 1);
-      double acc = 0.0;
-      for (int j = i + 1 + lane; j < N; j += 64) {
-        double a = Ar[j];
-        if (i >= 1) {
-          a -= vpr * WP[j] + wpr * VP[j];
-          Ar[j] = a;
-        }
-        if (pub) st_coh(&rb[j], a);
-        acc += a * X[j];
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) st_coh(&pb[r], t * acc);
-    }
-    flag_barrier(flags, epoch0 + (unsigned)i + 1u);
-    if (g == i % G) {   // row i of M is finished: keep the reflector there
-      for (int j = i + 1 + tid; j < N; j += NT) A[(int64_t)i * lda + j] = X[j];
-      if (tid == 0) { d[i] = dii; e[i] = beta; tau[i] = t; }
-    }
-    // w = p - (tau/2)(p.v) v, and the next row: published row minus update i
-    double *Xn = VP;
-    double part2 = 0.0;
-    for (int j = i + 1 + tid; j < N; j += NT) {
-      const double pj = ld_coh(&pb[j]);
-      const double rj = ld_coh(&rb[j]);
-      WP[j] = pj;
-      Xn[j] = rj;
-      part2 += pj * X[j];
-    }
-    const double pv = NT == 64 ? wave_sum(part2) : block_sum(part2, red);
-    const double aw = -0.5 * t * pv;
-    for (int j = i + 1 + tid; j < N; j += NT) WP[j] += aw * X[j];
-    __syncthreads();
-    const double wi1 = WP[i + 1];
-    part = 0.0;
-    for (int j = i + 1 + tid; j < N; j += NT) {
-      const double xn = Xn[j] - (WP[j] + wi1 * X[j]);   // X[i+1] = 1
-      Xn[j] = xn;
-      if (j >= i + 3) part += xn * xn;
-    }
-    __syncthreads();
-    VP = X;
-    X = Xn;
-  }
-  if (g == 0 && tid == 0) {
-    d[N - 2] = X[N - 2];
-    e[N - 2] = X[N - 1];
-  }
-  if (g == (N - 1) % G && tid == 0) {
-    double a;
-    if constexpr (LDS_ROWS) a = rows[(int64_t)((N - 1 - g) / G) * N + N - 1];
-    else a = A[(int64_t)(N - 1) * lda + N - 1];
-    d[N - 1] = a - 2.0 * VP[N - 1] * WP[N - 1];
-  }
-}
-
-__device__ __forceinline__ int sturm_count(int N, const double *__restrict__ d,
-                                           const double *__restrict__ e, double x,
-                                           double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  if (q <= 0.0) ++cnt;
-  for (int i = 1; i < N; ++i) {
-    const double ei = e[i - 1];
-    // e^2 / q through the hardware reciprocal refined by one Newton step
-    // (relative error ~1e-16, the size of a rounding error in e^2)
-    double r = __builtin_amdgcn_rcp(q);
-    r = r * fma(-q, r, 2.0);
-    q = d[i] - x - (ei * ei) * r;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q <= 0.0) ++cnt;
-  }
-  return cnt;
-}
 
 // Gershgorin bounds and the 1-norm of T, by one wave.
 __device__ void tri_bounds(int N, const double *__restrict__ d, const double *__restrict__ e,
@@ -198,13 +45,46 @@ __device__ void tri_bounds(int N, const double *__restrict__ d, const double *__
   gl = lo; gu = hi; onenrm = nm; emax2 = em;
 }
 
+// Number of eigenvalues of T below x (Sturm count of the LDL^T recurrence
+// q_i = d_i - x - e_{i-1}^2 / q_{i-1}); d and e2 = e^2 are in LDS.
+__device__ __forceinline__ int sturm_count(int N, const double *__restrict__ d,
+                                           const double *__restrict__ e2, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q <= 0.0;
+#pragma unroll 8
+  for (int i = 1; i < N; ++i) {
+    // e^2 / q through the hardware reciprocal refined by one Newton step
+    // (relative error ~1e-16, the size of a rounding error in e^2)
+    double r = __builtin_amdgcn_rcp(q);
+    r = r * fma(-q, r, 2.0);
+    q = d[i] - x - e2[i - 1] * r;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q <= 0.0;
+  }
+  return cnt;
+}
+
 // lam[j] = the (N-1-j)-th smallest eigenvalue of T (so lam is descending).
-__global__ void __launch_bounds__(64)
+// One block of BIS_NT threads per eigenvalue; each round evaluates BIS_NT
+// shifts (one per thread) that split the current interval into BIS_NT + 1
+// parts, so an FP64 eigenvalue is found in about six rounds.
+constexpr int BIS_NT = 512;
+
+__global__ void __launch_bounds__(BIS_NT)
 k_bisect(int N, const double *__restrict__ d, const double *__restrict__ e, int k,
          double *__restrict__ lam, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  const int j = blockIdx.x, lane = threadIdx.x;
+  extern __shared__ double bsm[];
+  __shared__ unsigned long long masks[BIS_NT / 64];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (j >= k) return;
+  double *sd = bsm, *se2 = bsm + N;
+  for (int i = tid; i < N; i += BIS_NT) {
+    sd[i] = d[i];
+    se2[i] = i < N - 1 ? e[i] * e[i] : 0.0;
+  }
   const int idx = N - 1 - j;
   double gl, gu, onenrm, emax2;
   tri_bounds(N, d, e, gl, gu, onenrm, emax2);
@@ -212,25 +92,30 @@ k_bisect(int N, const double *__restrict__ d, const double *__restrict__ e, int 
   const double pivmin = SAFMIN * fmax(1.0, emax2);
   gl -= 2.0 * EPS * tnorm * N + 4.0 * pivmin;
   gu += 2.0 * EPS * tnorm * N + 4.0 * pivmin;
+  __syncthreads();
+  constexpr double PARTS = (double)(BIS_NT + 1);
   double lo = gl, hi = gu;
   for (int round = 0; round < 40; ++round) {
     const double tol = 2.0 * EPS * fmax(fabs(lo), fabs(hi)) + 2.0 * pivmin;
     if (hi - lo <= tol) break;
-    const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
-    const int cnt = sturm_count(N, d, e, x, pivmin);
-    const unsigned long long mask = __ballot(cnt > idx);
-    const double x63 = __shfl(x, 63, 64);
-    if (mask == 0ull) {
-      lo = x63;
-    } else {
-      const int f = __builtin_ctzll(mask);
-      const double xf = __shfl(x, f, 64);
-      const double xp = __shfl(x, f > 0 ? f - 1 : 0, 64);
-      hi = xf;
-      if (f > 0) lo = xp;
-    }
+    const double h = hi - lo;
+    const double x = lo + h * (double)(tid + 1) / PARTS;
+    const int cnt = sturm_count(N, sd, se2, x, pivmin);
+    const unsigned long long m = __ballot(cnt > idx);
+    if (lane == 0) masks[w] = m;
+    __syncthreads();
+    // the first shift f whose count exceeds idx brackets the eigenvalue
+    // between shifts f-1 and f; every thread forms the same shifts
+    int f = BIS_NT;
+    for (int q = 0; q < BIS_NT / 64; ++q)
+      if (masks[q]) { f = 64 * q + __builtin_ctzll(masks[q]); break; }
+    __syncthreads();
+    const double nlo = f > 0 ? lo + h * (double)f / PARTS : lo;
+    const double nhi = f < BIS_NT ? lo + h * (double)(f + 1) / PARTS : hi;
+    lo = nlo;
+    hi = nhi;
   }
-  if (lane == 0) lam[j] = 0.5 * (lo + hi);
+  if (tid == 0) lam[j] = 0.5 * (lo + hi);
 }
 
 // Inverse iteration for the clusters of lam (descending).  One wave per
@@ -396,200 +281,136 @@ k_stein(int N, const double *__restrict__ d, const double *__restrict__ e, int k
   }
 }
 
-// x <- H_0 H_1 ... H_{N-3} x for every row of Fv; reflector i is stored in
-// row i of A (columns i+1 .., with a unit leading entry) and tau[i].
-// One wave per vector, 8 vectors per block.  Reflectors are applied four at a
-// time: with u_0..u_3 = v_i .. v_{i-3}, x <- x - sum_m c_m u_m where
-// c_m = tau_m (u_m.x - sum_{l<m} c_l u_m.u_l), so one reduction round (4 dot
-// products with x and the 6 products among the u) serves four reflectors.
-// The block stages each group of four reflectors in LDS once for all its
-// waves, loading the next group while the current one is applied.  Lane l
-// holds x[c] for c = l + 64 m (m < R) in registers.
-constexpr int BT_WAVES = 8;
-template <int R>
-__global__ void __launch_bounds__(64 * BT_WAVES)
-k_backtransform_blk(int N, int k, const double *__restrict__ A, int64_t lda,
-                    const double *__restrict__ tau, double *__restrict__ Fv,
-                    const SvDevInfo *__restrict__ info) {
+// Blocked back-transformation (compact WY form).  The reflectors are taken
+// in panels of WB: H_i0 H_i0+1 ... H_i0+nb-1 = I - Y T Y^T with Y the panel's
+// reflector vectors as columns and T upper triangular (forward accumulation:
+// T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (Y[:, 0:j]^T y_j)).
+constexpr int WB = 32;
+
+__global__ void __launch_bounds__(256)
+k_wy_tfactor(int N, const double *__restrict__ A, int64_t lda, const double *__restrict__ tau,
+             double *__restrict__ Tws, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  extern __shared__ double ub[];   // 2 buffers x 4 reflectors x N
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int j = blockIdx.x * BT_WAVES + w;
-  const bool active = j < k;
-  double x[R];
+  __shared__ double Ych[WB][65];
+  __shared__ double Gs[WB][WB + 1];
+  __shared__ double Ts[WB][WB + 1];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const int i0 = p * WB;
+  const int nb = min(WB, N - 2 - i0);
+  // Gram of the panel, 4 entries per thread: (a0 + 8q, b)
+  const int a0 = tid >> 5, b = tid & 31;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = i0 + 1; c0 < N; c0 += 64) {
+    // loads at clamped (always valid) addresses, masked afterwards
 #pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int c = lane + 64 * m;
-    x[m] = (active && c < N) ? Fv[(int64_t)j * N + c] : 0.0;
-  }
-  const int ngroups = (N - 2 + 3) / 4;   // reflectors N-3 .. 0 in groups of 4
-  // group g holds reflectors i0 - q, q = 0..3, with i0 = N - 3 - 4 g
-  constexpr int NTH = 64 * BT_WAVES;
-  constexpr int PER = (4 * 64 * R + NTH - 1) / NTH;   // staged values per thread
-  auto fetch = [&](int grp, double *pre) {
-    const int i0 = N - 3 - 4 * grp;
-#pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = tid + p * NTH;
-      double v = 0.0;
-      if (e < 4 * N) {
-        const int q = e / N, c = e % N, i = i0 - q;
-        if (i >= 0 && c > i) v = A[(int64_t)i * lda + c];
-      }
-      pre[p] = v;
+    for (int e = tid; e < WB * 64; e += 256) {
+      const int a = e >> 6, c = c0 + (e & 63);
+      const double v = A[(int64_t)min(i0 + a, N - 1) * lda + min(c, N - 1)];
+      Ych[a][e & 63] = (a < nb && c < N && c >= i0 + a + 1) ? v : 0.0;
     }
-  };
-  auto stash = [&](const double *pre, double *dst) {
+    __syncthreads();
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int e = tid + p * NTH;
-      if (e < 4 * N) dst[e] = pre[p];
-    }
-  };
-  double pre[PER];
-  fetch(0, pre);
-  stash(pre, ub);
-  __syncthreads();
-  for (int grp = 0; grp < ngroups; ++grp) {
-    double *cur = ub + (size_t)(grp & 1) * 4 * N;
-    double *nxt = ub + (size_t)((grp + 1) & 1) * 4 * N;
-    const bool more = grp + 1 < ngroups;
-    if (more) fetch(grp + 1, pre);
-    const int i0 = N - 3 - 4 * grp;
-    double t[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) t[q] = (i0 - q >= 0) ? tau[i0 - q] : 0.0;
-    double a[4] = {0, 0, 0, 0}, g10 = 0, g20 = 0, g21 = 0, g30 = 0, g31 = 0, g32 = 0;
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int c = lane + 64 * m;
-      if (c < N) {
-        const double u0 = cur[c], u1 = cur[N + c], u2 = cur[2 * N + c], u3 = cur[3 * N + c];
-        a[0] += u0 * x[m]; a[1] += u1 * x[m]; a[2] += u2 * x[m]; a[3] += u3 * x[m];
-        g10 += u1 * u0; g20 += u2 * u0; g21 += u2 * u1;
-        g30 += u3 * u0; g31 += u3 * u1; g32 += u3 * u2;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      a[0] += __shfl_xor(a[0], o, 64); a[1] += __shfl_xor(a[1], o, 64);
-      a[2] += __shfl_xor(a[2], o, 64); a[3] += __shfl_xor(a[3], o, 64);
-      g10 += __shfl_xor(g10, o, 64); g20 += __shfl_xor(g20, o, 64);
-      g21 += __shfl_xor(g21, o, 64); g30 += __shfl_xor(g30, o, 64);
-      g31 += __shfl_xor(g31, o, 64); g32 += __shfl_xor(g32, o, 64);
-    }
-    const double c0 = t[0] * a[0];
-    const double c1 = t[1] * (a[1] - c0 * g10);
-    const double c2 = t[2] * (a[2] - c0 * g20 - c1 * g21);
-    const double c3 = t[3] * (a[3] - c0 * g30 - c1 * g31 - c2 * g32);
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int c = lane + 64 * m;
-      if (c < N)
-        x[m] -= c0 * cur[c] + c1 * cur[N + c] + c2 * cur[2 * N + c] + c3 * cur[3 * N + c];
-    }
-    if (more) stash(pre, nxt);
+    for (int q = 0; q < 4; ++q)
+      for (int cc = 0; cc < 64; ++cc) acc[q] += Ych[a0 + 8 * q][cc] * Ych[b][cc];
     __syncthreads();
   }
-  if (active) {
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int c = lane + 64 * m;
-      if (c < N) Fv[(int64_t)j * N + c] = x[m];
-    }
+  for (int q = 0; q < 4; ++q) {
+    Gs[a0 + 8 * q][b] = acc[q];
+    Ts[a0 + 8 * q][b] = 0.0;
   }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double tj = tau[i0 + j];
+    double v = 0.0;
+    if (tid < j)
+      for (int c = tid; c < j; ++c) v += Ts[tid][c] * Gs[c][j];
+    __syncthreads();
+    if (tid < j) Ts[tid][j] = -tj * v;
+    if (tid == j) Ts[j][j] = tj;
+    __syncthreads();
+  }
+  for (int e = tid; e < WB * WB; e += 256) Tws[(int64_t)p * WB * WB + e] = Ts[e / WB][e % WB];
 }
 
-// Register variant for N <= 64 R: one wave per vector (one block each),
-// reflectors applied two at a time (u_0 = v_i, u_1 = v_{i-1}:
-// c_0 = tau_0 u_0.x, c_1 = tau_1 (u_1.x - c_0 u_1.u_0), x -= c_0 u_0 + c_1 u_1),
-// the next pair loaded into registers while the current one is applied.
-template <int R>
-__global__ void __launch_bounds__(64)
-k_backtransform_pair(int N, int k, const double *__restrict__ A, int64_t lda,
-                     const double *__restrict__ tau, double *__restrict__ Fv,
-                     const SvDevInfo *__restrict__ info) {
+// x <- H_0 H_1 ... H_{N-3} x for each eigenvector x (one block per vector,
+// x in LDS), panel by panel from the last: z = Y^T x, z <- T z, x -= Y z.
+// The 32 partial dot products of a thread are reduced across the wave by a
+// halving exchange (32 shuffles instead of 32 full reductions).
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_backtransform_wy(int N, int k, const double *__restrict__ A, int64_t lda,
+                   const double *__restrict__ Tws, double *__restrict__ Fv,
+                   const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  const int lane = threadIdx.x;
-  const int j = blockIdx.x;
-  double x[R], u0[R], u1[R];
-#pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int c = lane + 64 * m;
-    x[m] = c < N ? Fv[(int64_t)j * N + c] : 0.0;
-  }
-  auto fetch = [&](int i, double *u) {
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      const int c = lane + 64 * m;
-      u[m] = (i >= 0 && c > i && c < N) ? A[(int64_t)i * lda + c] : 0.0;
-    }
-  };
-  int i = N - 3;
-  fetch(i, u0);
-  fetch(i - 1, u1);
-  for (; i >= 0; i -= 2) {
-    double v0[R], v1[R];
-#pragma unroll
-    for (int m = 0; m < R; ++m) { v0[m] = u0[m]; v1[m] = u1[m]; }
-    const double t0 = tau[i];
-    const double t1 = i >= 1 ? tau[i - 1] : 0.0;
-    if (i >= 2) {
-      fetch(i - 2, u0);
-      fetch(i - 3, u1);
-    }
-    double a0 = 0.0, a1 = 0.0, g = 0.0;
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      a0 += v0[m] * x[m];
-      a1 += v1[m] * x[m];
-      g += v1[m] * v0[m];
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      a0 += __shfl_xor(a0, o, 64);
-      a1 += __shfl_xor(a1, o, 64);
-      g += __shfl_xor(g, o, 64);
-    }
-    const double c0 = t0 * a0;
-    const double c1 = t1 * (a1 - c0 * g);
-#pragma unroll
-    for (int m = 0; m < R; ++m) x[m] -= c0 * v0[m] + c1 * v1[m];
-  }
-#pragma unroll
-  for (int m = 0; m < R; ++m) {
-    const int c = lane + 64 * m;
-    if (c < N) Fv[(int64_t)j * N + c] = x[m];
-  }
-}
-
-// General-N variant with the vector in LDS.
-__global__ void k_backtransform(int N, int k, const double *__restrict__ A, int64_t lda,
-                                const double *__restrict__ tau, double *__restrict__ Fv,
-                                const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
-  extern __shared__ double xsh[];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int j = blockIdx.x * nw + w;
+  extern __shared__ double xs[];
+  __shared__ double red[NT / 64][WB];
+  __shared__ double zs[WB], zt[WB];
+  __shared__ double Ts[WB][WB + 1];
+  const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (j >= k) return;
-  double *x = xsh + (int64_t)w * N;
-  for (int c = lane; c < N; c += 64) x[c] = Fv[(int64_t)j * N + c];
-  for (int i = N - 3; i >= 0; --i) {
-    const double t = tau[i];
-    if (t == 0.0) continue;
-    const double *v = A + (int64_t)i * lda;
-    double dot = 0.0;
-    for (int c = i + 1 + lane; c < N; c += 64) dot += v[c] * x[c];
-    dot = wave_sum(dot) * t;
-    for (int c = i + 1 + lane; c < N; c += 64) x[c] -= dot * v[c];
+  for (int c = tid; c < N; c += NT) xs[c] = Fv[(int64_t)j * N + c];
+  const int nr = N - 2;
+  const int nP = nr > 0 ? (nr + WB - 1) / WB : 0;
+  __syncthreads();
+  for (int p = nP - 1; p >= 0; --p) {
+    const int i0 = p * WB;
+    const int nb = min(WB, nr - i0);
+    for (int e = tid; e < WB * WB; e += NT) Ts[e / WB][e % WB] = Tws[(int64_t)p * WB * WB + e];
+    const double *Yp = A + (int64_t)i0 * lda;
+    const int amax = N - 1 - i0;   // rows i0 + a beyond the matrix are clamped
+    double zp[WB];
+#pragma unroll
+    for (int a = 0; a < WB; ++a) zp[a] = 0.0;
+    for (int c = i0 + 1 + tid; c < N; c += NT) {
+      const double xc = xs[c];
+      double yv[WB];
+#pragma unroll
+      for (int a = 0; a < WB; ++a) yv[a] = Yp[(int64_t)min(a, amax) * lda + c];
+#pragma unroll
+      for (int a = 0; a < WB; ++a)
+        zp[a] += ((a < nb && c >= i0 + a + 1) ? yv[a] : 0.0) * xc;
+    }
+    // halving exchange: after the step with offset o, a lane keeps the half
+    // of the values selected by its bit o; finally lane l holds index l >> 1
+#pragma unroll
+    for (int o = 32, n = WB; o >= 2; o >>= 1, n >>= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int i = 0; i < n / 2; ++i) {
+        const double send = up ? zp[i] : zp[i + n / 2];
+        const double keep = up ? zp[i + n / 2] : zp[i];
+        zp[i] = keep + __shfl_xor(send, o, 64);
+      }
+    }
+    const double tot = zp[0] + __shfl_xor(zp[0], 1, 64);
+    if ((lane & 1) == 0) red[w][lane >> 1] = tot;
+    __syncthreads();
+    if (tid < WB) {
+      double sacc = 0.0;
+      for (int q = 0; q < NT / 64; ++q) sacc += red[q][tid];
+      zs[tid] = sacc;
+    }
+    __syncthreads();
+    if (tid < WB) {
+      double sacc = 0.0;
+      for (int c = tid; c < WB; ++c) sacc += Ts[tid][c] * zs[c];
+      zt[tid] = sacc;
+    }
+    __syncthreads();
+    for (int c = i0 + 1 + tid; c < N; c += NT) {
+      double yv[WB];
+#pragma unroll
+      for (int a = 0; a < WB; ++a) yv[a] = Yp[(int64_t)min(a, amax) * lda + c];
+      double sacc = 0.0;
+#pragma unroll
+      for (int a = 0; a < WB; ++a)
+        sacc += ((a < nb && c >= i0 + a + 1) ? yv[a] : 0.0) * zt[a];
+      xs[c] -= sacc;
+    }
+    __syncthreads();
   }
-  for (int c = lane; c < N; c += 64) Fv[(int64_t)j * N + c] = x[c];
-}
-
-__global__ void k_zero_u32(unsigned *p, size_t n) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+  for (int c = tid; c < N; c += NT) Fv[(int64_t)j * N + c] = xs[c];
 }
 
 }  // namespace
@@ -600,91 +421,36 @@ int eig_max_n() { return 6144; }
 
 size_t eig_work_doubles(int64_t N, int k) {
   // d, e, tau (3N) + pbuf, rowbuf (4N) + inverse-iteration scratch (7N per
-  // eigenvalue, used when the factors do not fit in LDS)
-  return (size_t)(7 * N + 7 * N * (int64_t)k + 64);
-}
-
-// Work layout: d, e, tau (3N), pbuf, rowbuf (4N), inverse-iteration scratch.
-// flags: TRI_MAX_BLOCKS * FLAG_STRIDE unsigned, zero-initialised once; *epoch
-// is advanced past the epochs this launch uses.
-int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *flags,
-                unsigned *epoch, const SvDevInfo *info) {
-  const int N = (int)N64;
-  if (N64 > eig_max_n() || N < 1) return -1;
-  double *d = work, *e = d + N, *tau = e + N, *pbuf = tau + N, *rowbuf = pbuf + 2 * N;
-  static int ncu = 0;
-  static bool once = false;
-  if (!once) {
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu <= 0) ncu = 1;
-    if (ncu > TRI_MAX_BLOCKS) ncu = TRI_MAX_BLOCKS;
-    const int lim = 160 * 1024;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<true, 64>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<false, 64>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<true, 256>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<false, 256>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_stein<true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_backtransform),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipGetLastError();
-    once = true;
-  }
-  // launch shape: block width NT (64 or 256 threads) and block count G; the
-  // defaults come from a sweep on MI355X, SVLCOV_TRI_THREADS / _BLOCKS
-  // override them for tuning
-  bool wide = true;
-  int G = N / 4;
-  if (const char *ev = getenv("SVLCOV_TRI_THREADS")) wide = atoi(ev) != 64;
-  if (const char *ev = getenv("SVLCOV_TRI_BLOCKS")) G = atoi(ev);
-  const int NT = wide ? 256 : 64;
-  if (G < 1) G = 1;
-  if (G > ncu) G = ncu;
-  const int rmax = (N + G - 1) / G;
-  const size_t base_sh = (size_t)3 * N * sizeof(double);
-  const size_t rows_sh = (size_t)rmax * N * sizeof(double);
-  const bool lds_rows = base_sh + rows_sh <= (size_t)150 * 1024;
-  const size_t sh = lds_rows ? base_sh + rows_sh : base_sh;
-  const void *fn;
-  if (wide) fn = lds_rows ? reinterpret_cast<const void *>(k_tridiag<true, 256>)
-                          : reinterpret_cast<const void *>(k_tridiag<false, 256>);
-  else fn = lds_rows ? reinterpret_cast<const void *>(k_tridiag<true, 64>)
-                     : reinterpret_cast<const void *>(k_tridiag<false, 64>);
-  int nb = 0;
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, sh);
-  (void)hipGetLastError();
-  if (nb < 1) return -2;
-  if (G > nb * ncu) G = nb * ncu;
-  if (*epoch > 0xF0000000u) {   // keep epochs monotonic: restart from zero
-    hipLaunchKernelGGL(k_zero_u32, dim3(16), dim3(256), 0, st, flags,
-                       (size_t)TRI_MAX_BLOCKS * FLAG_STRIDE);
-    *epoch = 0;
-  }
-  unsigned e0 = *epoch;
-  *epoch += (unsigned)N + 1u;
-  int64_t lda = N64;
-  void *args[] = {(void *)&N, (void *)&A, (void *)&lda, (void *)&d, (void *)&e, (void *)&tau,
-                  (void *)&pbuf, (void *)&rowbuf, (void *)&flags, (void *)&e0, (void *)&info};
-  hipError_t err = hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, sh, st);
-  return err == hipSuccess ? 0 : -3;
+  // eigenvalue, used when the factors do not fit in LDS) + the T factors of
+  // the reflector panels (WB x WB per panel)
+  return (size_t)(7 * N + 7 * N * (int64_t)k + (N / WB + 1) * WB * WB + 64);
 }
 
 void eig_bisect(hipStream_t st, int64_t N, int k, double *lam, double *work,
                 const SvDevInfo *info) {
   const double *d = work, *e = work + N;
-  hipLaunchKernelGGL(k_bisect, dim3(k), dim3(64), 0, st, (int)N, d, e, k, lam, info);
+  static bool once = false;
+  if (!once) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_bisect),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    once = true;
+  }
+  hipLaunchKernelGGL(k_bisect, dim3(k), dim3(BIS_NT), (size_t)2 * N * sizeof(double), st,
+                     (int)N, d, e, k, lam, info);
 }
 
 void eig_stein(hipStream_t st, int64_t N, int k, const double *lam, double *Fv, double *work,
                const SvDevInfo *info) {
   const double *d = work, *e = work + N;
   double *scratch = work + 7 * N;
+  static bool once = false;
+  if (!once) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_stein<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    once = true;
+  }
   const size_t sh = (size_t)N * 6 * sizeof(double) + (size_t)N * sizeof(int) + 64;
   if (sh <= (size_t)150 * 1024)
     hipLaunchKernelGGL((k_stein<true>), dim3(k), dim3(64), sh, st, (int)N, d, e, k, lam, Fv,
@@ -696,38 +462,14 @@ void eig_stein(hipStream_t st, int64_t N, int k, const double *lam, double *Fv, 
 
 void eig_back(hipStream_t st, int64_t N, int k, const double *A, double *Fv, double *work,
               const SvDevInfo *info) {
+  if (N < 3) return;
   const double *tau = work + 2 * N;
+  double *Tws = work + 7 * N + 7 * N * (int64_t)k;
   const int n = (int)N;
-  if (N >= 3 && N <= 64 * 24) {
-#define SV_BP(RR) hipLaunchKernelGGL((k_backtransform_pair<RR>), dim3(k), dim3(64), 0, st, n, k, A, N, tau, Fv, info)
-    if (N <= 64 * 4) SV_BP(4);
-    else if (N <= 64 * 8) SV_BP(8);
-    else if (N <= 64 * 12) SV_BP(12);
-    else if (N <= 64 * 16) SV_BP(16);
-    else if (N <= 64 * 20) SV_BP(20);
-    else SV_BP(24);
-#undef SV_BP
-    return;
-  }
-  if (N >= 3 && N <= 64 * 32) {
-    static bool once = false;
-    if (!once) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_backtransform_blk<32>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-      (void)hipGetLastError();
-      once = true;
-    }
-    const unsigned blocks = (unsigned)((k + BT_WAVES - 1) / BT_WAVES);
-    const size_t sh = (size_t)8 * N * sizeof(double);
-    hipLaunchKernelGGL((k_backtransform_blk<32>), dim3(blocks), dim3(64 * BT_WAVES), sh, st, n, k,
-                       A, N, tau, Fv, info);
-    return;
-  }
-  int wpb = (int)((150 * 1024) / ((size_t)N * sizeof(double)));
-  if (wpb > 4) wpb = 4;
-  if (wpb < 1) wpb = 1;
-  hipLaunchKernelGGL(k_backtransform, dim3((k + wpb - 1) / wpb), dim3(64 * wpb),
-                     (size_t)wpb * N * sizeof(double), st, n, k, A, N, tau, Fv, info);
+  const int nP = (n - 2 + WB - 1) / WB;
+  hipLaunchKernelGGL(k_wy_tfactor, dim3(nP), dim3(256), 0, st, n, A, N, tau, Tws, info);
+  hipLaunchKernelGGL((k_backtransform_wy<256>), dim3(k), dim3(256), (size_t)N * sizeof(double),
+                     st, n, k, A, N, Tws, Fv, info);
 }
 
 int eig_topk(hipStream_t st, int64_t N, double *A, int k, double *lam, double *Fv,

@@ -1,0 +1,210 @@
+// Householder tridiagonalisation Q^T M Q = T of a symmetric FP64 matrix, the
+// first stage of the top-k eigensolver behind the (k+s) Rayleigh-Ritz SVD
+// (Section 2.1, step 2), as one cooperative kernel.  Each block owns the rows
+// r = g, g + G, ... of M (cyclic, so the shrinking trailing matrix stays
+// balanced).  Per column one grid-wide barrier: every block recomputes the
+// next reflector redundantly from the published row, applies the pending
+// rank-2 update to its own rows fused with the product p = tau M v, and
+// publishes its part of p.
+#include <cstdlib>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace svk;
+
+namespace {
+
+constexpr int TRI_MAX_BLOCKS = svl::TRI_MAX_BLOCKS;
+
+// Householder tridiagonalisation, one cooperative launch (all blocks
+// co-resident).  Block g owns rows r = g, g + G, ...; with LDS_ROWS they live
+// in LDS for the whole reduction, otherwise in A.  Reflector i is left in row
+// i of A (columns i+1 .., unit leading entry), d, e, tau in work arrays.
+// NT = 64 (one wave per block: block-wide reductions and barriers are nearly
+// free) for moderate N, 256 when the owned rows need more lanes.
+template <bool LDS_ROWS, int NT>
+__global__ void __launch_bounds__(NT)
+k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
+          double *__restrict__ e, double *__restrict__ tau, double *__restrict__ pbuf,
+          double *__restrict__ rowbuf, unsigned *__restrict__ flags, unsigned epoch0,
+          const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  extern __shared__ double sm[];
+  __shared__ double red[NT / 64];
+  const int G = gridDim.x, g = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int nw = NT / 64;
+  if (N < 3) {
+    if (g == 0 && tid == 0) {
+      d[0] = A[0];
+      if (N == 2) { e[0] = A[1]; d[1] = A[lda + 1]; }
+    }
+    return;
+  }
+  double *X = sm, *VP = sm + N, *WP = sm + 2 * N;
+  double *rows = sm + 3 * N;   // LDS_ROWS: owned rows, local index (r - g) / G
+  if constexpr (LDS_ROWS) {
+    const int nr = (N - g + G - 1) / G;
+    for (int lr = w; lr < nr; lr += nw) {
+      const double *src = A + (int64_t)(g + lr * G) * lda;
+      for (int j = lane; j < N; j += 64) rows[(int64_t)lr * N + j] = src[j];
+    }
+  }
+  double part = 0.0;   // sum of X[j]^2 over j >= i + 2, carried between iterations
+  for (int j = tid; j < N; j += NT) {
+    const double x = A[j];
+    X[j] = x;
+    if (j >= 2) part += x * x;
+  }
+  __syncthreads();
+  for (int i = 0; i <= N - 3; ++i) {
+    const double dii = X[i];
+    // alpha is read before the reduction: its barriers order every read of
+    // X[i+1] before thread 0 overwrites it with the unit leading entry
+    const double alpha = X[i + 1];
+    const double xn2 = NT == 64 ? wave_sum(part) : block_sum(part, red);
+    double beta, t, scl;
+    if (xn2 == 0.0) {
+      t = 0.0; beta = alpha; scl = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + xn2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t = (beta - alpha) / beta;
+      scl = 1.0 / (alpha - beta);
+    }
+    for (int j = i + 2 + tid; j < N; j += NT) X[j] *= scl;
+    if (tid == 0) X[i + 1] = 1.0;
+    __syncthreads();
+    double *pb = pbuf + (int64_t)(i & 1) * N;
+    double *rb = rowbuf + (int64_t)(i & 1) * N;
+    // owned rows r >= i+1: pending rank-2 update, then p = tau M v
+    const int lr0 = (i + 1 - g + G - 1) / G > 0 ? (i + 1 - g + G - 1) / G : 0;
+    for (int lr = lr0 + w; g + lr * G < N; lr += nw) {
+      const int r = g + lr * G;
+      double *Ar;
+      if constexpr (LDS_ROWS) Ar = rows + (int64_t)lr * N;
+      else Ar = A + (int64_t)r * lda;
+      const double vpr = i >= 1 ? VP[r] : 0.0, wpr = i >= 1 ? WP[r] : 0.0;
+      const bool pub = (r == i + 1);
+      double acc = 0.0;
+      for (int j = i + 1 + lane; j < N; j += 64) {
+        double a = Ar[j];
+        if (i >= 1) {
+          a -= vpr * WP[j] + wpr * VP[j];
+          Ar[j] = a;
+        }
+        if (pub) st_coh(&rb[j], a);
+        acc += a * X[j];
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) st_coh(&pb[r], t * acc);
+    }
+    flag_barrier(flags, epoch0 + (unsigned)i + 1u);
+    if (g == i % G) {   // row i of M is finished: keep the reflector there
+      for (int j = i + 1 + tid; j < N; j += NT) A[(int64_t)i * lda + j] = X[j];
+      if (tid == 0) { d[i] = dii; e[i] = beta; tau[i] = t; }
+    }
+    // w = p - (tau/2)(p.v) v, and the next row: published row minus update i
+    double *Xn = VP;
+    double part2 = 0.0;
+    for (int j = i + 1 + tid; j < N; j += NT) {
+      const double pj = ld_coh(&pb[j]);
+      const double rj = ld_coh(&rb[j]);
+      WP[j] = pj;
+      Xn[j] = rj;
+      part2 += pj * X[j];
+    }
+    const double pv = NT == 64 ? wave_sum(part2) : block_sum(part2, red);
+    const double aw = -0.5 * t * pv;
+    for (int j = i + 1 + tid; j < N; j += NT) WP[j] += aw * X[j];
+    __syncthreads();
+    const double wi1 = WP[i + 1];
+    part = 0.0;
+    for (int j = i + 1 + tid; j < N; j += NT) {
+      const double xn = Xn[j] - (WP[j] + wi1 * X[j]);   // X[i+1] = 1
+      Xn[j] = xn;
+      if (j >= i + 3) part += xn * xn;
+    }
+    __syncthreads();
+    VP = X;
+    X = Xn;
+  }
+  if (g == 0 && tid == 0) {
+    d[N - 2] = X[N - 2];
+    e[N - 2] = X[N - 1];
+  }
+  if (g == (N - 1) % G && tid == 0) {
+    double a;
+    if constexpr (LDS_ROWS) a = rows[(int64_t)((N - 1 - g) / G) * N + N - 1];
+    else a = A[(int64_t)(N - 1) * lda + N - 1];
+    d[N - 1] = a - 2.0 * VP[N - 1] * WP[N - 1];
+  }
+}
+
+}  // namespace
+
+namespace svl {
+
+// Work layout: d, e, tau (3N), pbuf, rowbuf (4N), inverse-iteration scratch.
+// flags: TRI_MAX_BLOCKS * FLAG_STRIDE unsigned, zero-initialised once; *epoch
+// is advanced past the epochs this launch uses.
+int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *flags,
+                unsigned *epoch, const SvDevInfo *info) {
+  const int N = (int)N64;
+  if (N64 > eig_max_n() || N < 1) return -1;
+  double *d = work, *e = d + N, *tau = e + N, *pbuf = tau + N, *rowbuf = pbuf + 2 * N;
+  static int ncu = 0;
+  static bool once = false;
+  if (!once) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ncu <= 0) ncu = 1;
+    if (ncu > TRI_MAX_BLOCKS) ncu = TRI_MAX_BLOCKS;
+    const int lim = 160 * 1024;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<true, 64>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<false, 64>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<true, 256>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<false, 256>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipGetLastError();
+    once = true;
+  }
+  // launch shape: block width NT (64 or 256 threads) and block count G; the
+  // defaults come from a sweep on MI355X, SVLCOV_TRI_THREADS / _BLOCKS
+  // override them for tuning
+  bool wide = true;
+  int G = N / 4;
+  if (const char *ev = getenv("SVLCOV_TRI_THREADS")) wide = atoi(ev) != 64;
+  if (const char *ev = getenv("SVLCOV_TRI_BLOCKS")) G = atoi(ev);
+  const int NT = wide ? 256 : 64;
+  if (G < 1) G = 1;
+  if (G > ncu) G = ncu;
+  const int rmax = (N + G - 1) / G;
+  const size_t base_sh = (size_t)3 * N * sizeof(double);
+  const size_t rows_sh = (size_t)rmax * N * sizeof(double);
+  const bool lds_rows = base_sh + rows_sh <= (size_t)150 * 1024;
+  const size_t sh = lds_rows ? base_sh + rows_sh : base_sh;
+  const void *fn;
+  if (wide) fn = lds_rows ? reinterpret_cast<const void *>(k_tridiag<true, 256>)
+                          : reinterpret_cast<const void *>(k_tridiag<false, 256>);
+  else fn = lds_rows ? reinterpret_cast<const void *>(k_tridiag<true, 64>)
+                     : reinterpret_cast<const void *>(k_tridiag<false, 64>);
+  int nb = 0;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, sh);
+  (void)hipGetLastError();
+  if (nb < 1) return -2;
+  if (G > nb * ncu) G = nb * ncu;
+  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)N);
+  int64_t lda = N64;
+  void *args[] = {(void *)&N, (void *)&A, (void *)&lda, (void *)&d, (void *)&e, (void *)&tau,
+                  (void *)&pbuf, (void *)&rowbuf, (void *)&flags, (void *)&e0, (void *)&info};
+  hipError_t err = hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, sh, st);
+  return err == hipSuccess ? 0 : -3;
+}
+
+}  // namespace svl
