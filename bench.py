@@ -40,7 +40,7 @@ CSRC = os.path.join(ROOT, "paper_2401_09703_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 # phase -> (kernel name prefix, source files whose text defines the kernel)
 PHASE_KERNEL = {
-    "tridiag": ("k_tridiag", ["k_eig.hip", "common.hpp"]),
+    "tridiag": ("k_tridiag", ["k_tridiag.hip", "common.hpp"]),
     "cholesky": ("k_chol_coop", ["k_coop.hip", "common.hpp"]),
     "spmm_w": ("k_spmm_w", ["k_sparse.hip", "common.hpp"]),
     "kkt_gemm": ("k_gemm_f64", ["k_dense.hip", "common.hpp"]),
