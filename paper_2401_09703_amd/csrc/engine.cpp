@@ -260,7 +260,7 @@ int mode_of(int prec) { return prec == SVLCOV_FP64 ? 0 : (prec == SVLCOV_FP32 ? 
 // Cholesky (Algorithm 2 realised as R^T R = E E^T - (E V)(E V)^T, Lemma 3).
 template <typename T>
 void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
-                   float *Cp32, double *rown, double *Gm, double *Linv, int which) {
+                   float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which) {
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
@@ -271,7 +271,7 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   }
   {
     PhaseScope ps(h, PH_SGRAM);
-    svl::sparse_gram(st, s, E.rp, E.ci, E.v, E.vdt, Gm, s, h->info);
+    svl::sparse_gram(st, s, E.rp, E.ci, E.v, E.vdt, rid, Gm, s, h->info);
   }
   {
     PhaseScope ps(h, PH_RGRAM);
@@ -413,6 +413,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   Carver c{nullptr};
   double *orthw_p = nullptr;
   double **orthw = &orthw_p;
+  int32_t *rid = nullptr;   // row id per nonzero of E (sparse Gram)
   auto layout = [&](Carver &cv, double **Cp64, float **Cp32, double **rown, double **Gm,
                     double **Linv, double **Kmat, double **Mmat, double **lam, double **theta,
                     int32_t **complete, double **Fv, double **Gv, double **eigw, double **Y,
@@ -440,6 +441,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
     *Mupd = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
     *orthw = cv.take<double>(2 * K * K + 9 * K * N);
+    rid = cv.take<int32_t>(E->nnz > 0 ? E->nnz : 1);
   };
   double *Cp64, *rown, *Gm, *Linv, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA,
       *WiA, *WnB, *WiB, *Mupd;
@@ -468,7 +470,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   }
   svl::op_begin(st, h->info, 0);
   // orthogonalise the augmented matrix of the sparse side
-  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, 0);
+  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, rid, 0);
   // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
   {
     PhaseScope ps(h, PH_BUILDK);
@@ -525,6 +527,8 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
   T *Ub = (T *)h->Ubase, *Vb = (T *)h->Vbase;
   double *orthw_p = nullptr;
   double **orthw = &orthw_p;
+  int32_t *rid = nullptr;   // row id per nonzero of D^T, then of E_m^T (sparse Gram)
+  const int64_t nnz_max = D->nnz > Em->nnz ? D->nnz : Em->nnz;
   auto layout = [&](Carver &cv, double **CpD, double **CpE, float **C32D, float **C32E,
                     double **rnD, double **rnE, double **GD, double **GE, double **LiD,
                     double **LiE, double **X, double **Yx, double **Kmat, double **Mmat,
@@ -551,6 +555,7 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
     *MD = cv.take<double>(s * K); *ME = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
     *orthw = cv.take<double>(2 * K * K + 9 * K * N);
+    rid = cv.take<int32_t>(nnz_max > 0 ? nnz_max : 1);
   };
   double *CpD, *CpE, *rnD, *rnE, *GD, *GE, *LiD, *LiE, *X, *Yx, *Kmat, *Mmat, *lam, *theta, *Fv,
       *Gv, *eigw, *YD, *YE, *T1, *WnU, *WiU, *WnV, *WiV, *MD, *ME;
@@ -587,8 +592,8 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
                         h->seq);
   }
   svl::op_begin(st, h->info, 1);
-  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, 0);
-  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, 1);
+  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, rid, 0);
+  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, rid, 1);
   // K = [[Sigma, 0], [0, 0]] + [U^T D ; R_D] [V^T E_m ; R_E]^T
   {
     PhaseScope ps(h, PH_BUILDK);

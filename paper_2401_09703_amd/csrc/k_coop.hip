@@ -15,27 +15,31 @@ constexpr int NB = svl::CHOL_NB;   // 32
 constexpr int CT = 256;
 
 // Blocked right-looking Cholesky of the lower triangle of A (s x s, row
-// stride ld), pivot dropping as in the single-block diagonal factor: a pivot
-// d_j <= tol * scale sets column j of L to zero.  Per block column: every
-// block factors the diagonal block redundantly; the panel rows and the lower
-// trailing tiles are spread over the blocks; two barriers.  Linv receives the
-// inverse of each diagonal block (unit placeholders on dropped pivots, whose
-// rows and columns are then zeroed).
+// stride ld) with pivot dropping: a pivot d_j <= tol * scale sets column j of
+// L to zero.  Per block column (NB = 32):
+//   (1) every block loads the diagonal block and factors it (wave 0,
+//       column by column; the other waves wait);
+//   (2) the panel rows are spread over the blocks, two rows per wave: a row
+//       is solved against the diagonal factor by forward substitution with
+//       one lane per column;
+//   barrier; block 0 stores the diagonal factor;
+//   (3) the lower trailing tiles are spread over the blocks; each tile's
+//       operands and destination are loaded together, then updated;
+//   barrier.
+// All data exchanged between blocks goes through coherent loads and stores.
+// The inverses of the diagonal blocks are formed afterwards by
+// k_chol_blkinv, off this kernel's sequential path.
 __global__ void __launch_bounds__(CT)
-k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double *__restrict__ Linv, double tol,
+k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
             SvDevInfo *__restrict__ info, int which, unsigned *__restrict__ flags,
             unsigned epoch0) {
   if (info->status) return;
   __shared__ double Ld[NB][NB + 1];
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double pan[CT / NB][NB + 1];
+  __shared__ double rinv[NB];     // 1 / L_jj, 0 for a dropped pivot
   __shared__ double ta[NB][NB + 1];
   __shared__ double tb[NB][NB + 1];
-  __shared__ double tmp[NB];
-  __shared__ int dropped[NB];
-  __shared__ double rd_sh;
-  __shared__ int drop_sh;
   const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
   const double scale = which == 0 ? info->scale : info->scale2;
   const double thr = tol * scale;
   const int64_t nblk = (s + NB - 1) / NB;
@@ -46,66 +50,53 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double *__restrict__ 
     const int64_t b0 = b * NB;
     const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
     const int64_t r0 = b0 + nb;
-    // (1) diagonal block, factored by every block
+    // (1) diagonal block
     for (int e = tid; e < NB * NB; e += CT) {
       const int i = e / NB, j = e % NB;
       Ld[i][j] = (i < nb && j <= i) ? ld_coh(&A[(b0 + i) * ld + b0 + j]) : 0.0;
     }
-    if (tid < NB) dropped[tid] = 0;
     __syncthreads();
-    // factor and invert the diagonal block with wave 0 alone (wave-level
-    // synchronisation only); the other waves wait at the block barrier
     if (tid < 64) {
+      // lane i (< 32) and lane i + 32 share row i's dot products (even and
+      // odd terms)
+      const int i = lane & 31, half = lane >> 5;
       for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-          const double d = Ld[j][j];
+        double sacc = 0.0;
+        if (i >= j && i < nb)
+          for (int p = half; p < j; p += 2) sacc += Ld[i][p] * Ld[j][p];
+        sacc += __shfl_xor(sacc, 32, 64);
+        if (lane == j) {
+          const double d = Ld[j][j] - sacc;
           const bool drop = !(d > thr) || !(scale > 0.0);
           const double rd = drop ? 0.0 : sqrt(d);
-          dropped[j] = drop ? 1 : 0;
-          drop_sh = drop ? 1 : 0;
-          rd_sh = rd;
           Ld[j][j] = rd;
+          rinv[j] = drop ? 0.0 : 1.0 / rd;
           const double rel = scale > 0.0 ? d / scale : 0.0;
           if (drop) st_maxdrop = fmax(st_maxdrop, rel);
           else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
         }
         wave_sync();
-        const int m = nb - j - 1;
-        if (tid < m) Ld[j + 1 + tid][j] = drop_sh ? 0.0 : Ld[j + 1 + tid][j] / rd_sh;
+        if (half == 0 && i > j && i < nb) Ld[i][j] = (Ld[i][j] - sacc) * rinv[j];
         wave_sync();
-        for (int e = tid; e < m * m; e += 64) {
-          const int i = j + 1 + e / m, c = j + 1 + e % m;
-          if (c <= i) Ld[i][c] -= Ld[i][j] * Ld[c][j];
-        }
-        wave_sync();
-      }
-      for (int e = tid; e < NB * NB; e += 64) {
-        const int i = e / NB, j = e % NB;
-        double v = (i < nb && j <= i) ? Ld[i][j] : 0.0;
-        if (i == j && (i >= nb || dropped[i])) v = 1.0;
-        Li[i][j] = v;
-      }
-      wave_sync();
-      tri_lower_inv_wave(&Li[0][0], NB + 1, NB, tmp);
-      for (int e = tid; e < NB * NB; e += 64) {
-        const int i = e / NB, j = e % NB;
-        if (j > i || i >= nb || j >= nb || dropped[i] || dropped[j]) Li[i][j] = 0.0;
       }
     }
     __syncthreads();
-    // (2) panel: L[r][b0:b0+nb] = A[r][b0:b0+nb] Linv^T for r >= r0; 8 rows
-    // per pass, 32 threads per row
-    const int grp = tid / NB, c = tid % NB;
-    for (int64_t base = (int64_t)g * (CT / NB); base < s - r0; base += (int64_t)P * (CT / NB)) {
-      const int64_t r = r0 + base + grp;
-      pan[grp][c] = (r < s && c < nb) ? ld_coh(&A[r * ld + b0 + c]) : 0.0;
-      __syncthreads();
-      if (r < s && c < nb) {
-        double v = 0.0;
-        for (int p = 0; p < nb; ++p) v += pan[grp][p] * Li[c][p];
-        st_coh(&A[r * ld + b0 + c], v);
+    // (2) panel rows r >= r0: row r = r0 + h + 8 (g + P q) for the half-wave
+    // h of this block; lane c of the half-wave owns column c
+    {
+      const int hw = tid >> 5, c = tid & 31;   // 8 half-waves per block
+      for (int64_t base = (int64_t)g * (CT / 32); base < s - r0; base += (int64_t)P * (CT / 32)) {
+        const int64_t r = r0 + base + hw;
+        const bool act = r < s;
+        double acc = (act && c < nb) ? ld_coh(&A[r * ld + b0 + c]) : 0.0;
+        double x = 0.0;
+        for (int j = 0; j < nb; ++j) {
+          const double xj = __shfl(acc * rinv[j], (lane & 32) + j, 64);
+          if (c == j) x = xj;
+          if (c > j) acc -= Ld[c][j] * xj;
+        }
+        if (act && c < nb) st_coh(&A[r * ld + b0 + c], x);
       }
-      __syncthreads();
     }
     flag_barrier(flags, ++ep);
     // every block has read the diagonal block: block 0 may now overwrite it
@@ -115,7 +106,6 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double *__restrict__ 
         const int i = e / nb, j = e % nb;
         st_coh(&A[(b0 + i) * ld + b0 + j], j <= i ? Ld[i][j] : 0.0);
       }
-      for (int e = tid; e < NB * NB; e += CT) Linv[b * NB * NB + e] = Li[e / NB][e % NB];
     }
     // (3) trailing update of the lower tiles of rows/columns >= r0
     const int64_t T = (s - r0 + NB - 1) / NB;
@@ -126,37 +116,84 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double *__restrict__ 
       while (ti * (ti + 1) / 2 > t) --ti;
       const int64_t tj = t - ti * (ti + 1) / 2;
       const int64_t ra = r0 + ti * NB, rb = r0 + tj * NB;
+      constexpr int PER = NB * NB / CT;   // destination elements per thread
+      double dv[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * CT, i = e / NB, j = e % NB;
+        dv[q] = (ra + i < s && rb + j < s && (ti != tj || j <= i))
+                    ? ld_coh(&A[(ra + i) * ld + rb + j]) : 0.0;
+      }
       for (int e = tid; e < NB * NB; e += CT) {
         const int i = e / NB, p = e % NB;
         ta[i][p] = (ra + i < s && p < nb) ? ld_coh(&A[(ra + i) * ld + b0 + p]) : 0.0;
         tb[i][p] = (rb + i < s && p < nb) ? ld_coh(&A[(rb + i) * ld + b0 + p]) : 0.0;
       }
       __syncthreads();
-      for (int e = tid; e < NB * NB; e += CT) {
-        const int i = e / NB, j = e % NB;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * CT, i = e / NB, j = e % NB;
         if (ra + i < s && rb + j < s && (ti != tj || j <= i)) {
           double acc = 0.0;
           for (int p = 0; p < nb; ++p) acc += ta[i][p] * tb[j][p];
-          double *dst = &A[(ra + i) * ld + rb + j];
-          st_coh(dst, ld_coh(dst) - acc);
+          st_coh(&A[(ra + i) * ld + rb + j], dv[q] - acc);
         }
       }
       __syncthreads();
     }
     flag_barrier(flags, ++ep);
   }
-  if (g == 0 && tid == 0) {
-    if (st_maxdrop > info->max_dropped) info->max_dropped = st_maxdrop;
-    if (st_minkept < info->min_kept) info->min_kept = st_minkept;
-    if (which == 0) info->rank += st_kept; else info->rank2 += st_kept;
+  if (g == 0 && tid < 64) {
+    // the pivot statistics were kept by the lane of each column
+    for (int o = 32; o > 0; o >>= 1) {
+      st_maxdrop = fmax(st_maxdrop, __shfl_xor(st_maxdrop, o, 64));
+      st_minkept = fmin(st_minkept, __shfl_xor(st_minkept, o, 64));
+      st_kept += __shfl_xor(st_kept, o, 64);
+    }
+    if (tid == 0) {
+      if (st_maxdrop > info->max_dropped) info->max_dropped = st_maxdrop;
+      if (st_minkept < info->min_kept) info->min_kept = st_minkept;
+      if (which == 0) info->rank += st_kept; else info->rank2 += st_kept;
+    }
+  }
+}
+
+// Inverse of every NB x NB diagonal block of the factor (one wave per block):
+// unit placeholders on dropped pivots (zero diagonal), then their rows and
+// columns zeroed.
+__global__ void __launch_bounds__(64)
+k_chol_blkinv(int64_t s, const double *__restrict__ L, int64_t ld, double *__restrict__ Linv,
+              const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ double Li[NB][NB + 1];
+  __shared__ double tmp[NB];
+  __shared__ int dropped[NB];
+  const int64_t b = blockIdx.x, b0 = b * NB;
+  const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
+  const int tid = threadIdx.x;
+  if (tid < NB) dropped[tid] = tid < nb ? (L[(b0 + tid) * ld + b0 + tid] == 0.0) : 1;
+  wave_sync();
+  for (int e = tid; e < NB * NB; e += 64) {
+    const int i = e / NB, j = e % NB;
+    double v = (i < nb && j <= i) ? L[(b0 + i) * ld + b0 + j] : 0.0;
+    if (i == j && dropped[i]) v = 1.0;
+    Li[i][j] = v;
+  }
+  wave_sync();
+  tri_lower_inv_wave(&Li[0][0], NB + 1, NB, tmp);
+  for (int e = tid; e < NB * NB; e += 64) {
+    const int i = e / NB, j = e % NB;
+    const bool z = j > i || dropped[i] || dropped[j];
+    Linv[b * NB * NB + e] = z ? 0.0 : Li[i][j];
   }
 }
 
 // Y <- L^{-T} Y (Y is s x K row-major, K <= 128) with the factor and the
-// diagonal-block inverses of k_chol_coop, by block rows from the bottom.
-// Per block row b every block forms Y_b = Linv_b^T Z_b redundantly; block 0
-// stores it; the rows above are updated, Z_r -= L[b rows, r]^T Y_b, spread
-// over the blocks; one barrier.
+// diagonal-block inverses, by block rows from the bottom.  Per block row b
+// every block forms Y_b = Linv_b^T Z_b redundantly; the rows above are
+// updated, Z_r -= L[b rows, r]^T Y_b, spread over the blocks (their current
+// values loaded before the block's barrier); one grid barrier; block 0 stores
+// Y_b.
 __global__ void __launch_bounds__(CT)
 k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
             const double *__restrict__ Linv, double *__restrict__ Y,
@@ -167,6 +204,7 @@ k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
   __shared__ double Li[NB][NB + 1];
   __shared__ double lc[CT / 64][NB];
   const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
   const int64_t nblk = (s + NB - 1) / NB;
   unsigned ep = epoch0;
   for (int64_t b = nblk - 1; b >= 0; --b) {
@@ -184,23 +222,30 @@ k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
       for (int p = 0; p < nb; ++p) v += Li[p][i] * Zb[p][c];
       Yb[i][c] = v;
     }
-    __syncthreads();
     // rows r < b0: 4 rows per pass (one wave each), lanes over the K columns
-    const int w = tid >> 6, lane = tid & 63;
     for (int64_t base = (int64_t)g * (CT / 64); base < b0; base += (int64_t)P * (CT / 64)) {
       const int64_t r = base + w;
-      if (r < b0 && lane < nb) lc[w][lane] = L[(b0 + lane) * ld + r];
+      const bool act = r < b0;
+      double z0 = 0.0, z1 = 0.0;
+      if (act) {
+        if (lane < nb) lc[w][lane] = L[(b0 + lane) * ld + r];
+        if (lane < K) z0 = ld_coh(&Y[r * K + lane]);
+        if (lane + 64 < K) z1 = ld_coh(&Y[r * K + lane + 64]);
+      }
       __syncthreads();
-      if (r < b0) {
-        for (int c = lane; c < K; c += 64) {
-          double acc = 0.0;
-          for (int p = 0; p < nb; ++p) acc += lc[w][p] * Yb[p][c];
-          double *dst = &Y[r * K + c];
-          st_coh(dst, ld_coh(dst) - acc);
+      if (act) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int p = 0; p < nb; ++p) {
+          const double l = lc[w][p];
+          if (lane < K) a0 += l * Yb[p][lane];
+          if (lane + 64 < K) a1 += l * Yb[p][lane + 64];
         }
+        if (lane < K) st_coh(&Y[r * K + lane], z0 - a0);
+        if (lane + 64 < K) st_coh(&Y[r * K + lane + 64], z1 - a1);
       }
       __syncthreads();
     }
+    __syncthreads();
     flag_barrier(flags, ++ep);
     // every block has read Z_b: block 0 may now store Y_b over it
     if (g == 0)
@@ -260,10 +305,13 @@ int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv
   const int64_t nblk = (s + NB - 1) / NB;
   const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), (int)((s + 3) / 4));
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)(2 * nblk));
-  void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&Linv, (void *)&tol,
+  void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&tol,
                   (void *)&info, (void *)&which, (void *)&flags, (void *)&e0};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_coop), dim3(P),
-                                    dim3(CT), args, 0, st) == hipSuccess ? 0 : -3;
+  if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_coop), dim3(P), dim3(CT),
+                                 args, 0, st) != hipSuccess)
+    return -3;
+  hipLaunchKernelGGL(k_chol_blkinv, dim3((unsigned)nblk), dim3(64), 0, st, s, G, ld, Linv, info);
+  return 0;
 }
 
 int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,

@@ -240,103 +240,6 @@ __global__ void k_max_into(int64_t n, const double *__restrict__ v, SvDevInfo *i
   }
 }
 
-// Factor the nb x nb diagonal block at (b0, b0) of the (already updated)
-// lower triangle, right-looking in LDS.  A pivot d_j <= tol * scale is
-// dropped: column j of L is set to zero.  Writes L into G, zeroes the block's
-// strict upper part, and writes Linv = inverse of L with 1 in place of each
-// dropped pivot, then with row and column j of every dropped pivot zeroed.
-__global__ void __launch_bounds__(256)
-k_chol_diag(int64_t s, double *__restrict__ G, int64_t ld, int64_t b0,
-            double *__restrict__ Linv, double tol, SvDevInfo *__restrict__ info, int which) {
-  if (info->status) return;
-  constexpr int NB = svl::CHOL_NB;
-  __shared__ double L[NB][NB + 1];
-  __shared__ int dropped[NB];
-  __shared__ double rd_sh;
-  __shared__ int drop_sh;
-  const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
-  const int tid = threadIdx.x;
-  const double scale = which == 0 ? info->scale : info->scale2;
-  const double thr = tol * scale;
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    L[i][j] = (i < nb && j <= i) ? G[(b0 + i) * ld + b0 + j] : 0.0;
-  }
-  if (tid < NB) dropped[tid] = 0;
-  __syncthreads();
-  double st_maxdrop = -1.0, st_minkept = INFINITY;
-  int st_kept = 0;
-  for (int j = 0; j < nb; ++j) {
-    if (tid == 0) {
-      const double d = L[j][j];
-      const bool drop = !(d > thr) || !(scale > 0.0);
-      const double rd = drop ? 0.0 : sqrt(d);
-      dropped[j] = drop ? 1 : 0;
-      drop_sh = drop ? 1 : 0;
-      rd_sh = rd;
-      L[j][j] = rd;
-      const double rel = scale > 0.0 ? d / scale : 0.0;
-      if (drop) st_maxdrop = fmax(st_maxdrop, rel);
-      else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
-    }
-    __syncthreads();
-    const int m = nb - j - 1;
-    if (tid < m) L[j + 1 + tid][j] = drop_sh ? 0.0 : L[j + 1 + tid][j] / rd_sh;
-    __syncthreads();
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e / m, c = j + 1 + e % m;
-      if (c <= i) L[i][c] -= L[i][j] * L[c][j];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    if (st_maxdrop > info->max_dropped) info->max_dropped = st_maxdrop;
-    if (st_minkept < info->min_kept) info->min_kept = st_minkept;
-    if (which == 0) info->rank += st_kept; else info->rank2 += st_kept;
-  }
-  // inverse with unit placeholders on dropped pivots, then zero their rows
-  // and columns
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double tmp[NB];
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    double v = (i < nb && j <= i) ? L[i][j] : 0.0;
-    if (i == j && (i >= nb || dropped[i])) v = 1.0;
-    Li[i][j] = v;
-  }
-  __syncthreads();
-  tri_lower_inv_inplace(&Li[0][0], NB + 1, NB, tmp);
-  for (int e = tid; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    const bool z = j > i || i >= nb || j >= nb || dropped[i] || dropped[j];
-    Linv[e] = z ? 0.0 : Li[i][j];
-  }
-  for (int e = tid; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    G[(b0 + i) * ld + b0 + j] = (j <= i) ? L[i][j] : 0.0;
-  }
-}
-
-// Y_b = Linv_b^T Y_b for one nb-row block of Y (K columns), in place.
-__global__ void k_trsm_diag(int64_t s, int K, int64_t b0, const double *__restrict__ Linv,
-                            double *__restrict__ Y, const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
-  constexpr int NB = svl::CHOL_NB;
-  __shared__ double Yb[NB][129];
-  __shared__ double Li[NB][NB + 1];
-  const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) Li[e / NB][e % NB] = Linv[e];
-  for (int e = threadIdx.x; e < nb * K; e += blockDim.x)
-    Yb[e / K][e % K] = Y[(b0 + e / K) * K + e % K];
-  __syncthreads();
-  for (int e = threadIdx.x; e < nb * K; e += blockDim.x) {
-    const int i = e / K, c = e % K;
-    double v = 0.0;
-    for (int p = 0; p < nb; ++p) v += Li[p][i] * Yb[p][c];
-    Y[(b0 + i) * K + c] = v;
-  }
-}
-
 __global__ void k_build_K_rows(int K, int64_t s, const double *__restrict__ sig,
                                const double *__restrict__ Cp, const double *__restrict__ L,
                                int64_t ldl, double *__restrict__ Ko,
@@ -776,44 +679,6 @@ void max_into(hipStream_t st, int64_t n, const double *v, SvDevInfo *info, int w
   hipLaunchKernelGGL(k_max_into, dim3(1), dim3(1024), 0, st, n, v, info, which);
 }
 
-void cholesky_drop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
-                   double tol, SvDevInfo *info, int which) {
-  const int NB = CHOL_NB;
-  for (int64_t b0 = 0; b0 < s; b0 += NB) {
-    const int64_t bi = b0 / NB;
-    double *Lb = Linv + bi * NB * NB;
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, s, G, ld, b0, Lb, tol, info,
-                       which);
-    const int64_t rest = s - b0 - NB;
-    if (rest > 0) {
-      // panel: L21 = A21 * Linv^T  (in place through a GEMM into the panel)
-      // the panel is read and written by the same GEMM tile only when the
-      // tile covers all NB columns, which holds (GB_N >= NB).
-      gemm_f64(st, false, true, rest, NB, NB, 1.0, G + (b0 + NB) * ld + b0, ld, Lb, NB, 0.0,
-               G + (b0 + NB) * ld + b0, ld, info);
-      // trailing update A22 -= L21 L21^T
-      gemm_f64(st, false, true, rest, rest, NB, -1.0, G + (b0 + NB) * ld + b0, ld,
-               G + (b0 + NB) * ld + b0, ld, 1.0, G + (b0 + NB) * ld + b0 + NB, ld, info);
-    }
-  }
-}
-
-void trsm_lt(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,
-             double *Y, const SvDevInfo *info) {
-  const int NB = CHOL_NB;
-  const int64_t nblk = (s + NB - 1) / NB;
-  for (int64_t bi = nblk - 1; bi >= 0; --bi) {
-    const int64_t b0 = bi * NB;
-    hipLaunchKernelGGL(k_trsm_diag, dim3(1), dim3(256), 0, st, s, K, b0, Linv + bi * NB * NB, Y,
-                       info);
-    if (b0 > 0) {
-      const int64_t nb = (s - b0) < NB ? (s - b0) : NB;
-      // Y[0:b0] -= L[b0:b0+nb, 0:b0]^T * Y[b0:b0+nb]
-      gemm_f64(st, true, false, b0, K, nb, -1.0, L + b0 * ld, ld, Y + b0 * K, K, 1.0, Y, K,
-               info);
-    }
-  }
-}
 
 void build_K_rows(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
                   const double *L, int64_t ldl, double *Ko, const SvDevInfo *info) {

@@ -40,97 +40,132 @@ __global__ void k_validate_csr(int64_t rows, int64_t cols, int64_t nnz,
   }
 }
 
+// Row kernels take one block of SP_NW waves per row of E: the waves take
+// interleaved chunks of 64 nonzeros, each chunk loaded coalesced (one nonzero
+// per lane) and then broadcast lane by lane with shuffles, so that a lane
+// keeps SP_U independent gathers of base rows in flight.  Long (hub) rows are
+// thus spread over SP_NW waves and never wait on one load per nonzero.
+constexpr int SP_NW = 4;
+constexpr int SP_U = 8;
+
+__device__ __forceinline__ double ldv(const void *val, int vdtype, int64_t p) {
+  return vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
+}
+
 // P = E * base (s x K, accumulated in T), C' = P * W (FP64, W is K x K FP64),
-// plus ||e_i||^2.  One wavefront per row of E.  For K <= 64 the wave splits
-// into 64/K groups of K lanes that take every (64/K)-th nonzero; for K = 128
-// each lane owns two columns.
+// plus ||e_i||^2.  For K <= 64 a wave splits into 64/K groups of K lanes that
+// take alternate nonzeros of a chunk; for K = 128 each lane owns two columns.
 template <typename T, int K>
-__global__ void k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr,
-                         const int32_t *__restrict__ col_idx,
-                         const void *__restrict__ val, int vdtype,
-                         const T *__restrict__ base,
-                         const double *__restrict__ W,
-                         double *__restrict__ Cp64, float *__restrict__ Cp32,
-                         double *__restrict__ rownorm2,
-                         const SvDevInfo *__restrict__ info) {
+__global__ void __launch_bounds__(64 * SP_NW)
+k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+         const void *__restrict__ val, int vdtype, const T *__restrict__ base,
+         const double *__restrict__ W, double *__restrict__ Cp64, float *__restrict__ Cp32,
+         double *__restrict__ rownorm2, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int G = K <= 64 ? 64 / K : 1;
+  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  __shared__ double red[SP_NW][K];
+  __shared__ double ptot[K];
+  __shared__ double nred[SP_NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = blockIdx.x;
+  const int g = lane / (64 / G), c = lane % (64 / G);
+  const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
+  T acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = (T)0;
+  double nrm = 0.0;
+  for (int64_t cb = p0 + 64 * w; cb < p1; cb += 64 * SP_NW) {
+    const int n = (int)((p1 - cb) < 64 ? (p1 - cb) : 64);
+    int32_t mc = 0;
+    double mvd = 0.0;
+    if (lane < n) {
+      mc = col_idx[cb + lane];
+      mvd = ldv(val, vdtype, cb + lane);
+    }
+    nrm += mvd * mvd;
+    const T mv = (T)mvd;
+    // lanes >= n carry column 0 and value 0: their gathers are valid and add 0
+    for (int j0 = 0; j0 < n; j0 += SP_U * G) {
+      int32_t cc[SP_U];
+      T vv[SP_U];
+#pragma unroll
+      for (int u = 0; u < SP_U; ++u) {
+        const int jj = j0 + u * G + g;
+        cc[u] = __shfl(mc, jj, 64);
+        vv[u] = __shfl(mv, jj, 64);
+      }
+      T bb[SP_U][CPL];
+#pragma unroll
+      for (int u = 0; u < SP_U; ++u)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) bb[u][q] = base[(int64_t)cc[u] * K + c + 64 * q];
+#pragma unroll
+      for (int u = 0; u < SP_U; ++u)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) acc[q] += vv[u] * bb[u][q];
+    }
+  }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int o = K; o < 64; o <<= 1) acc[0] += __shfl_xor(acc[0], o, 64);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) red[w][c + 64 * q] = (double)acc[q];
+  }
+  nrm = wave_sum(nrm);
+  if (lane == 0) nred[w] = nrm;
+  __syncthreads();
+  for (int t = threadIdx.x; t < K; t += 64 * SP_NW) {
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < SP_NW; ++q) sum += red[q][t];
+    ptot[t] = sum;
+  }
+  __syncthreads();
+  // epilogue: C'[i, col] = sum_l P[i, l] W[l, col]
+  for (int col = threadIdx.x; col < K; col += 64 * SP_NW) {
+    double out = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < K; ++l) out += ptot[l] * W[l * K + col];
+    Cp64[i * K + col] = out;
+    if (Cp32) Cp32[i * K + col] = (float)out;
+  }
+  if (threadIdx.x == 0) {
+    double tn = 0.0;
+    for (int q = 0; q < SP_NW; ++q) tn += nred[q];
+    rownorm2[i] = tn;
+  }
+}
+
+// row id of every nonzero (the CSR row pointers expanded)
+__global__ void k_row_ids(int64_t s, const int64_t *__restrict__ row_ptr,
+                          int32_t *__restrict__ rid, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
   const int lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= s) return;
-  const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-  double nrm = 0.0;
-  for (int64_t p = p0 + lane; p < p1; p += 64) {
-    const double v = vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
-    nrm += v * v;
-  }
-  nrm = wave_sum(nrm);
-  if constexpr (K <= 64) {
-    constexpr int G = 64 / K;
-    const int g = lane / K, c = lane % K;
-    T acc = 0;
-    for (int64_t p = p0 + g; p < p1; p += G) {
-      const int32_t col = col_idx[p];
-      const T v = (T)(vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p]);
-      acc += v * base[(int64_t)col * K + c];
-    }
-#pragma unroll
-    for (int o = K; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    // epilogue: lanes 0..K-1 compute column c of C' = P W
-    double out = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < K; ++l) {
-      const double pl = (double)__shfl(acc, l, 64);
-      out += pl * W[l * K + c];
-    }
-    if (lane < K) {
-      Cp64[i * K + c] = out;
-      if (Cp32) Cp32[i * K + c] = (float)out;
-    }
-  } else {
-    T a0 = 0, a1 = 0;
-    for (int64_t p = p0; p < p1; ++p) {
-      const int32_t col = col_idx[p];
-      const T v = (T)(vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p]);
-      a0 += v * base[(int64_t)col * K + lane];
-      a1 += v * base[(int64_t)col * K + 64 + lane];
-    }
-    double o0 = 0.0, o1 = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < 64; ++l) {
-      const double pl = (double)__shfl(a0, l, 64);
-      o0 += pl * W[l * K + lane];
-      o1 += pl * W[l * K + 64 + lane];
-    }
-#pragma unroll 8
-    for (int l = 0; l < 64; ++l) {
-      const double pl = (double)__shfl(a1, l, 64);
-      o0 += pl * W[(64 + l) * K + lane];
-      o1 += pl * W[(64 + l) * K + 64 + lane];
-    }
-    Cp64[i * K + lane] = o0;
-    Cp64[i * K + 64 + lane] = o1;
-    if (Cp32) {
-      Cp32[i * K + lane] = (float)o0;
-      Cp32[i * K + 64 + lane] = (float)o1;
-    }
-  }
-  if (lane == 0) rownorm2[i] = nrm;
+  for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += 64) rid[p] = (int32_t)i;
 }
 
-constexpr int GRAM_LDS_CAP = 4096;
+constexpr int GRAM_LDS_CAP = 4096;      // nonzeros of the pivot row kept in LDS
+constexpr int GRAM_ACC_CAP = 8192;      // rows j accumulated in LDS (dynamic)
 
 // S = E E^T (FP64, full s x s).  Block b handles rows i = b and s-1-b (folded
-// so that every block does about s/2 row pairs).  Row i is staged in LDS and
-// every row j <= i is intersected with it by binary search; one wave per j.
+// so that every block does about s/2 row pairs).  Row i is staged in LDS; the
+// nonzeros of rows 0..i are contiguous in the CSR, so the block streams them
+// with coalesced loads (one nonzero per thread), finds each column in row i
+// by binary search, and accumulates the products per row j in LDS.
 __global__ void __launch_bounds__(256)
 k_sparse_gram(int64_t s, const int64_t *__restrict__ row_ptr,
-              const int32_t *__restrict__ col_idx,
+              const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rid,
               const void *__restrict__ val, int vdtype, double *__restrict__ S,
               int64_t lds, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
   __shared__ int32_t sc[GRAM_LDS_CAP];
   __shared__ double sv[GRAM_LDS_CAP];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  extern __shared__ double acc[];   // s doubles
   for (int pass = 0; pass < 2; ++pass) {
     const int64_t i = pass == 0 ? (int64_t)blockIdx.x : s - 1 - (int64_t)blockIdx.x;
     if (pass == 1 && i <= (int64_t)blockIdx.x) break;
@@ -142,68 +177,72 @@ k_sparse_gram(int64_t s, const int64_t *__restrict__ row_ptr,
     if (in_lds) {
       for (int64_t t = threadIdx.x; t < ni; t += blockDim.x) {
         sc[t] = col_idx[q0 + t];
-        sv[t] = vdtype ? ((const double *)val)[q0 + t] : (double)((const float *)val)[q0 + t];
+        sv[t] = ldv(val, vdtype, q0 + t);
+      }
+    }
+    for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) acc[j] = 0.0;
+    __syncthreads();
+    const int32_t *ci = in_lds ? sc : col_idx + q0;
+    if (ni > 0) {
+      for (int64_t p = threadIdx.x; p < q1; p += blockDim.x) {
+        const int32_t c = col_idx[p];
+        int64_t lo = 0, hi = ni;   // first position with ci[pos] >= c
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (ci[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        if (lo < ni && ci[lo] == c) {
+          const double vi = in_lds ? sv[lo] : ldv(val, vdtype, q0 + lo);
+          atomicAdd(&acc[rid[p]], vi * ldv(val, vdtype, p));
+        }
       }
     }
     __syncthreads();
-    const int32_t *ci = in_lds ? sc : col_idx + q0;
-    for (int64_t j = w; j <= i; j += nw) {
-      const int64_t p0 = row_ptr[j], p1 = row_ptr[j + 1];
-      double acc = 0.0;
-      if (ni > 0) {
-        for (int64_t p = p0 + lane; p < p1; p += 64) {
-          const int32_t c = col_idx[p];
-          int64_t lo = 0, hi = ni;   // first position with ci[pos] >= c
-          while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (ci[mid] < c) lo = mid + 1; else hi = mid;
-          }
-          if (lo < ni && ci[lo] == c) {
-            const double vi = in_lds ? sv[lo]
-                                     : (vdtype ? ((const double *)val)[q0 + lo]
-                                               : (double)((const float *)val)[q0 + lo]);
-            const double vj = vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
-            acc += vi * vj;
-          }
-        }
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) {
-        S[i * lds + j] = acc;
-        S[j * lds + i] = acc;
-      }
+    for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) {
+      const double a = acc[j];
+      S[i * lds + j] = a;
+      S[j * lds + i] = a;
     }
   }
 }
 
 // base[col] += sum_i E[i, col] * M[i]  (the sparse row update of the tall
-// factor, Equation (1) second term).  One wave per row of E; FP atomics.
+// factor, Equation (1) second term), with FP atomics; nonzeros are taken in
+// coalesced chunks as in k_spmm_w.
 template <typename T, int K>
-__global__ void k_scatter(int64_t s, const int64_t *__restrict__ row_ptr,
-                          const int32_t *__restrict__ col_idx,
-                          const void *__restrict__ val, int vdtype,
-                          const double *__restrict__ M, T *__restrict__ base,
-                          const SvDevInfo *__restrict__ info) {
+__global__ void __launch_bounds__(64 * SP_NW)
+k_scatter(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+          const void *__restrict__ val, int vdtype, const double *__restrict__ M,
+          T *__restrict__ base, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= s) return;
+  constexpr int G = K <= 64 ? 64 / K : 1;
+  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = blockIdx.x;
+  const int g = lane / (64 / G), c = lane % (64 / G);
   const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-  if constexpr (K <= 64) {
-    constexpr int G = 64 / K;
-    const int g = lane / K, c = lane % K;
-    const double mc = M[i * K + c];
-    for (int64_t p = p0 + g; p < p1; p += G) {
-      const double v = vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
-      atomicAdd(&base[(int64_t)col_idx[p] * K + c], (T)(v * mc));
+  double mrow[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) mrow[q] = M[i * K + c + 64 * q];
+  for (int64_t cb = p0 + 64 * w; cb < p1; cb += 64 * SP_NW) {
+    const int n = (int)((p1 - cb) < 64 ? (p1 - cb) : 64);
+    int32_t mc = 0;
+    double mv = 0.0;
+    if (lane < n) {
+      mc = col_idx[cb + lane];
+      mv = ldv(val, vdtype, cb + lane);
     }
-  } else {
-    const double m0 = M[i * K + lane], m1 = M[i * K + 64 + lane];
-    for (int64_t p = p0; p < p1; ++p) {
-      const double v = vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
-      T *dst = base + (int64_t)col_idx[p] * K;
-      atomicAdd(dst + lane, (T)(v * m0));
-      atomicAdd(dst + 64 + lane, (T)(v * m1));
+    // the loop is uniform over the wave so that every source lane of the
+    // shuffles is active (a shuffle from an inactive lane reads zero)
+    for (int j0 = 0; j0 < n; j0 += G) {
+      const int jj = j0 + g;
+      const int32_t cc = __shfl(mc, jj, 64);
+      const double vv = __shfl(mv, jj, 64);
+      if (jj < n) {
+        T *dst = base + (int64_t)cc * K + c;
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) atomicAdd(dst + 64 * q, (T)(vv * mrow[q]));
+      }
     }
   }
 }
@@ -253,8 +292,8 @@ void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
             float *Cp32, double *rownorm2, const SvDevInfo *info) {
   if (s <= 0) return;
-  const unsigned blocks = (unsigned)((s + 3) / 4);
-#define SV_SPMM(KK) hipLaunchKernelGGL((k_spmm_w<T, KK>), dim3(blocks), dim3(256), 0, st, \
+  const unsigned blocks = (unsigned)s;
+#define SV_SPMM(KK) hipLaunchKernelGGL((k_spmm_w<T, KK>), dim3(blocks), dim3(64 * SP_NW), 0, st, \
                                        s, rp, ci, v, vdt, base, W, Cp64, Cp32, rownorm2, info)
   switch (K) {
     case 16: SV_SPMM(16); break;
@@ -271,20 +310,32 @@ template void spmm_w<double>(hipStream_t, int, int64_t, const int64_t *, const i
                              const void *, int, const double *, const double *, double *,
                              float *, double *, const SvDevInfo *);
 
+int gram_max_rows() { return GRAM_ACC_CAP; }
+
 void sparse_gram(hipStream_t st, int64_t s, const int64_t *rp, const int32_t *ci,
-                 const void *v, int vdt, double *S, int64_t lds, const SvDevInfo *info) {
+                 const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
+                 const SvDevInfo *info) {
   if (s <= 0) return;
+  hipLaunchKernelGGL(k_row_ids, dim3((unsigned)((s + 3) / 4)), dim3(256), 0, st, s, rp, rid,
+                     info);
+  static bool once = false;
+  if (!once) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sparse_gram),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 112 * 1024);
+    (void)hipGetLastError();
+    once = true;
+  }
   const unsigned blocks = (unsigned)((s + 1) / 2);
-  hipLaunchKernelGGL(k_sparse_gram, dim3(blocks), dim3(256), 0, st, s, rp, ci, v, vdt, S,
-                     lds, info);
+  hipLaunchKernelGGL(k_sparse_gram, dim3(blocks), dim3(256), (size_t)s * sizeof(double), st, s,
+                     rp, ci, rid, v, vdt, S, lds, info);
 }
 
 template <typename T>
 void scatter(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
              const void *v, int vdt, const double *M, T *base, const SvDevInfo *info) {
   if (s <= 0) return;
-  const unsigned blocks = (unsigned)((s + 3) / 4);
-#define SV_SC(KK) hipLaunchKernelGGL((k_scatter<T, KK>), dim3(blocks), dim3(256), 0, st, \
+  const unsigned blocks = (unsigned)s;
+#define SV_SC(KK) hipLaunchKernelGGL((k_scatter<T, KK>), dim3(blocks), dim3(64 * SP_NW), 0, st, \
                                      s, rp, ci, v, vdt, M, base, info)
   switch (K) {
     case 16: SV_SC(16); break;

@@ -15,8 +15,12 @@ template <typename T>
 void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
             float *Cp32, double *rownorm2, const SvDevInfo *info);
+// S = E E^T; rid receives the row id of every nonzero (nnz int32 scratch).
+// s <= gram_max_rows().
+int gram_max_rows();
 void sparse_gram(hipStream_t st, int64_t s, const int64_t *rp, const int32_t *ci,
-                 const void *v, int vdt, double *S, int64_t lds, const SvDevInfo *info);
+                 const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
+                 const SvDevInfo *info);
 template <typename T>
 void scatter(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
              const void *v, int vdt, const double *M, T *base, const SvDevInfo *info);
@@ -46,14 +50,6 @@ void copy_strided(hipStream_t st, int64_t R, int64_t C, const double *src, int64
                   int64_t cs, double *dst, int64_t ldd, const SvDevInfo *info);
 // max_i v[i] into info->scale (which = 0) or info->scale2 (which = 1).
 void max_into(hipStream_t st, int64_t n, const double *v, SvDevInfo *info, int which);
-// Blocked right-looking Cholesky of the lower triangle of G (s x s, ld) with
-// pivot dropping; L overwrites the lower triangle, the upper triangle is
-// zeroed.  Linv receives the inverses of the nb x nb diagonal blocks.
-void cholesky_drop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
-                   double rank_tol, SvDevInfo *info, int which);
-// Y = L^{-T} Y in place (Y s x K, row-major), using the diagonal-block inverses.
-void trsm_lt(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
-             const double *Linv, double *Y, const SvDevInfo *info);
 constexpr int CHOL_NB = 32;
 // ---- cooperative (k_coop.hip): one launch each; flags/epoch as for eig_topk
 int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,

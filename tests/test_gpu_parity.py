@@ -8,7 +8,7 @@ through principal angles of the leading subspace up to the last spectral gap
 
 Tolerances: FP64 mode sigma_rel <= 1e-10, sin(angle) <= 1e-8 (gap 1e-6);
 FP32 and BF16x3 modes sigma_rel <= 1e-5, sin(angle) <= 1e-4 (gap 1e-3);
-orthonormality ||X^T X - I|| <= 1e-11 (FP64) / 1e-5 (FP32, BF16x3).
+orthonormality ||X^T X - I|| <= 1e-11 (FP64), 1e-5 (FP32), 5e-5 (BF16x3).
 """
 import numpy as np
 import pytest
@@ -19,9 +19,12 @@ from synth.sparse import bernoulli_uniform
 
 pytestmark = pytest.mark.gpu
 
+# BF16x3 products carry a relative error up to about 3 * 2^-16 of sum |a||b|
+# (two-term BF16 split, lo*lo dropped), so the residual Gram and with it the
+# orthonormality of the sparse-side factor are only good to ~5e-5.
 TOL = {"fp64": dict(sig=1e-10, ang=1e-8, delta=1e-6, orth=1e-11),
        "fp32": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=1e-5),
-       "bf16x3": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=1e-5)}
+       "bf16x3": dict(sig=1e-5, ang=1e-4, delta=1e-3, orth=5e-5)}
 
 
 def _L():
