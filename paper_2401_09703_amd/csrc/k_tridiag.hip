@@ -31,7 +31,6 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
           const SvDevInfo *__restrict__ info) {
   if (info->status) return;
   extern __shared__ double sm[];
-  __shared__ double red[NT / 64];
   const int G = gridDim.x, g = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   constexpr int nw = NT / 64;
@@ -51,19 +50,28 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
       for (int j = lane; j < N; j += 64) rows[(int64_t)lr * N + j] = src[j];
     }
   }
+  // Every per-entry loop below gives entry j to thread j mod NT, so a thread
+  // only reads back what it wrote itself; the three block barriers per
+  // column cover the cross-thread reads (the scalars alpha, w_{i+1} and the
+  // reductions, and the row loop that reads whole vectors).
+  __shared__ double red0[NT / 64], red1[NT / 64];
+  __shared__ double p_lead;   // p_{i+1}, published by its owner thread
+  auto first = [&](int lo) { return lo + ((tid - lo) & (NT - 1)); };
   double part = 0.0;   // sum of X[j]^2 over j >= i + 2, carried between iterations
   for (int j = tid; j < N; j += NT) {
     const double x = A[j];
     X[j] = x;
     if (j >= 2) part += x * x;
   }
+  part = wave_sum(part);
+  if (lane == 0) red1[w] = part;
   __syncthreads();
   for (int i = 0; i <= N - 3; ++i) {
     const double dii = X[i];
-    // alpha is read before the reduction: its barriers order every read of
-    // X[i+1] before thread 0 overwrites it with the unit leading entry
     const double alpha = X[i + 1];
-    const double xn2 = NT == 64 ? wave_sum(part) : block_sum(part, red);
+    double xn2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < nw; ++q) xn2 += red1[q];
     double beta, t, scl;
     if (xn2 == 0.0) {
       t = 0.0; beta = alpha; scl = 0.0;
@@ -73,8 +81,7 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
       t = (beta - alpha) / beta;
       scl = 1.0 / (alpha - beta);
     }
-    for (int j = i + 2 + tid; j < N; j += NT) X[j] *= scl;
-    if (tid == 0) X[i + 1] = 1.0;
+    for (int j = first(i + 1); j < N; j += NT) X[j] = (j == i + 1) ? 1.0 : X[j] * scl;
     __syncthreads();
     double *pb = pbuf + (int64_t)(i & 1) * N;
     double *rb = rowbuf + (int64_t)(i & 1) * N;
@@ -101,31 +108,40 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
       if (lane == 0) st_coh(&pb[r], t * acc);
     }
     flag_barrier(flags, epoch0 + (unsigned)i + 1u);
-    if (g == i % G) {   // row i of M is finished: keep the reflector there
-      for (int j = i + 1 + tid; j < N; j += NT) A[(int64_t)i * lda + j] = X[j];
-      if (tid == 0) { d[i] = dii; e[i] = beta; tau[i] = t; }
-    }
+    const bool owner = (g == i % G);   // row i of M is finished: keep the reflector there
+    if (owner && tid == 0) { d[i] = dii; e[i] = beta; tau[i] = t; }
     // w = p - (tau/2)(p.v) v, and the next row: published row minus update i
     double *Xn = VP;
     double part2 = 0.0;
-    for (int j = i + 1 + tid; j < N; j += NT) {
+    for (int j = first(i + 1); j < N; j += NT) {
       const double pj = ld_coh(&pb[j]);
       const double rj = ld_coh(&rb[j]);
+      const double xj = X[j];
+      if (owner) A[(int64_t)i * lda + j] = xj;
+      if (j == i + 1) p_lead = pj;
       WP[j] = pj;
       Xn[j] = rj;
-      part2 += pj * X[j];
+      part2 += pj * xj;
     }
-    const double pv = NT == 64 ? wave_sum(part2) : block_sum(part2, red);
-    const double aw = -0.5 * t * pv;
-    for (int j = i + 1 + tid; j < N; j += NT) WP[j] += aw * X[j];
+    part2 = wave_sum(part2);
+    if (lane == 0) red0[w] = part2;
     __syncthreads();
-    const double wi1 = WP[i + 1];
+    double pv = 0.0;
+#pragma unroll
+    for (int q = 0; q < nw; ++q) pv += red0[q];
+    const double aw = -0.5 * t * pv;
+    const double wi1 = p_lead + aw;   // w_{i+1} (v_{i+1} = 1)
     part = 0.0;
-    for (int j = i + 1 + tid; j < N; j += NT) {
-      const double xn = Xn[j] - (WP[j] + wi1 * X[j]);   // X[i+1] = 1
+    for (int j = first(i + 1); j < N; j += NT) {
+      const double xj = X[j];
+      const double wj = WP[j] + aw * xj;
+      WP[j] = wj;
+      const double xn = Xn[j] - (wj + wi1 * xj);
       Xn[j] = xn;
       if (j >= i + 3) part += xn * xn;
     }
+    part = wave_sum(part);
+    if (lane == 0) red1[w] = part;
     __syncthreads();
     VP = X;
     X = Xn;
