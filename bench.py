@@ -17,6 +17,12 @@ latency.  The singular values of both paths after one step are checked
 against the FP64 oracle (sigma relative error <= 1e-5 gate); the oracle's own
 time on the same step is the CPU baseline.
 
+--workload selects the other single-GPU workloads: "bernoulli" (2000 x 1000,
+k = 16, FP64, appends of 100 rows), "ratings" (500k x 50k user-item ratings,
+k = 128, appends of 5000 users; gated on oracle-free properties because the
+oracle's dense QR of a 50k x 5000 residual takes minutes), "weights" (1M-node
+weighted graph, k = 64, rank-32 weight updates; rows = touched rows).
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -57,11 +63,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--k", type=int, default=64)
+    ap.add_argument("--workload", default="graph", choices=("graph", "bernoulli", "ratings",
+                                                             "weights"))
+    ap.add_argument("--k", type=int, default=0, help="rank of the graph workload (default 64)")
     ap.add_argument("--n-init", type=int, default=90000)
     ap.add_argument("--step-nodes", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="bf16x3,fp32")
+    ap.add_argument("--modes", default="", help="precision modes (default per workload)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy (y = -x, FP32) of this many MiB first; "
                          "its HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
@@ -183,6 +191,70 @@ def phase_work(name, N, s, k, nnz, d_cols):
     return None, None, None
 
 
+WORKLOADS = ("graph", "bernoulli", "ratings", "weights")
+
+
+def build_workload(args, W, K):
+    """The update stream of one workload, its per-step accounting and the
+    state capacities.  One step = the updates of one batch of new data."""
+    from synth import config1_rows, config2_graph, config3_ratings, config4_weights
+    wl = args.workload
+    if wl == "graph":
+        k = args.k or 64
+        cfg = config2_graph(k=k, n_init=args.n_init, step_nodes=args.step_nodes, steps=W + K)
+        nodes = args.n_init + (W + K) * args.step_nodes
+        return dict(cfg=cfg, per_step=2, rows_per_step=2 * args.step_nodes,
+                    cap=(nodes + 16, nodes + 16), modes="bf16x3,fp32", gate="oracle",
+                    desc=f"chung-lu graph adjacency, {nodes} nodes, mean degree 20, k={k}, "
+                         f"{args.step_nodes} nodes appended per step as add_cols + add_rows",
+                    extra=dict(k=k, s=args.step_nodes, nodes=nodes), s=args.step_nodes)
+    if wl == "bernoulli":
+        cfg = config1_rows(steps=W + K)
+        return dict(cfg=cfg, per_step=1, rows_per_step=100, cap=(2000 + 100 * (W + K) + 16, 1016),
+                    modes="fp64", gate="oracle",
+                    desc=f"bernoulli 2000x1000 density 0.5%, k=16, {W + K} appends of 100 rows",
+                    extra=dict(k=16, s=100), s=100)
+    if wl == "ratings":
+        cfg = config3_ratings(steps=W + K)
+        m0 = cfg["U"].shape[0]
+        return dict(cfg=cfg, per_step=1, rows_per_step=5000,
+                    cap=(m0 + 5000 * (W + K) + 16, cfg["V"].shape[0] + 16),
+                    modes="bf16x3,fp32", gate="properties",
+                    desc="user-item ratings 500000x50000, 10M ratings 1-5, Zipf(1.1) items, "
+                         "k=128, appends of 5000 user rows",
+                    extra=dict(k=128, s=5000), s=5000)
+    if wl == "weights":
+        cfg = config4_weights(steps=W + K)
+        return dict(cfg=cfg, per_step=1, rows_per_step=32, cap=(1_000_016, 1_000_016),
+                    modes="bf16x3,fp32", gate="oracle",
+                    desc="weight change on a 1M-node chung-lu graph (LogNormal weights), k=64, "
+                         "one rank-32 update per step (50k re-weighted + 10k new entries)",
+                    extra=dict(k=64, s=32), s=32)
+    raise SystemExit(f"unknown workload {wl}")
+
+
+def to_device(L, up):
+    if up[0] == "weights":
+        return ("weights", L.DeviceCSR.from_host(up[1]), L.DeviceCSR.from_host(up[2]))
+    return (up[0], L.DeviceCSR.from_host(up[1]))
+
+
+def property_gate(U0, s0, V0, up, U1, s1, V1):
+    """Checks that need no oracle run (used where the oracle's dense QR would
+    take minutes): orthonormality, the singular-triplet residual of the
+    updated matrix [U0 S0 V0^T; E] (add rows) and interlacing."""
+    import numpy as np
+    from oracle import metrics
+    E = up[1].to_scipy()
+    AV = np.vstack([(U0 * s0) @ (V0.T @ V1), E @ V1])
+    res_v = np.linalg.norm(AV - U1 * s1) / s1[0]
+    AtU = V0 @ (s0[:, None] * (U0.T @ U1[:U0.shape[0]])) + E.T @ U1[U0.shape[0]:]
+    res_u = np.linalg.norm(AtU - V1 * s1) / s1[0]
+    inter = float(np.max(np.maximum(s0 - s1, 0.0)) / s1[0])
+    return dict(residual_V=float(res_v), residual_U=float(res_u), interlacing=inter,
+                orth_U=metrics.orth_err(U1), orth_V=metrics.orth_err(V1))
+
+
 def main():
     args = parse()
     if args.summarize_stats:
@@ -199,7 +271,6 @@ def main():
     import numpy as np
     import torch
     import paper_2401_09703_amd as L
-    from synth import config2_graph
 
     assert torch.cuda.is_available(), "no GPU"
     if args.copy_calib_mib > 0:
@@ -210,45 +281,44 @@ def main():
         del x, y
     W, K = args.warmup, args.steps
     t = time.time()
-    cfg = config2_graph(k=args.k, n_init=args.n_init, step_nodes=args.step_nodes, steps=W + K)
+    wl = build_workload(args, W, K)
+    cfg, P = wl["cfg"], wl["per_step"]
     log(f"[bench] generated {cfg['name']} in {time.time() - t:.1f}s; "
-        f"nnz={cfg['nnz_total']}, init sigma_1={cfg['s'][0]:.3f} sigma_k={cfg['s'][-1]:.3f}")
-    ups = cfg["updates"]
-    dev_ups = [(kind, L.DeviceCSR.from_host(E)) for kind, E in ups]
+        f"init sigma_1={cfg['s'][0]:.3f} sigma_k={cfg['s'][-1]:.3f}")
+    ups = cfg["updates"][:P * (W + K)]
+    dev_ups = [to_device(L, up) for up in ups]
     torch.cuda.synchronize()
-    nfinal_rows = args.n_init + (W + K) * args.step_nodes
-    rows_per_step = 2 * args.step_nodes
+    capU, capV = wl["cap"]
+    modes = (args.modes or wl["modes"]).split(",")
 
     results = {}
-    for mode in args.modes.split(","):
+    for mode in modes:
         svd = L.TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision=mode,
-                             row_capacity=nfinal_rows + 16, col_capacity=nfinal_rows + 16,
-                             validate_device_inputs=False)
+                             row_capacity=capU, col_capacity=capV, validate_device_inputs=False)
         stream = torch.cuda.ExternalStream(svd.stream)
-        for t_ in range(W):
-            for j in (2 * t_, 2 * t_ + 1):
-                svd.apply(dev_ups[j])
+        for j in range(P * W):
+            svd.apply(dev_ups[j])
         svd.sync()
         svd.profile(True)
         svd.phase_times()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K + 1)]
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(P * K + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         evs[0].record(stream)
-        for t_ in range(W, W + K):
-            for j in (2 * t_, 2 * t_ + 1):
-                svd.apply(dev_ups[j])
-                evs[j - 2 * W + 1].record(stream)
+        for j in range(P * W, P * (W + K)):
+            svd.apply(dev_ups[j])
+            evs[j - P * W + 1].record(stream)
         svd.sync()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         svd.profile(False)
         phases = svd.phase_times()
-        lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(2 * K)])
+        lat = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(P * K)])
         st = svd.stats()
         svd.close()
         elapsed = t1 - t0
-        results[mode] = dict(rows_per_s=rows_per_step * K / elapsed, ms_per_step=1e3 * elapsed / K,
+        results[mode] = dict(rows_per_s=wl["rows_per_step"] * K / elapsed,
+                             ms_per_step=1e3 * elapsed / K,
                              p50_ms=float(np.percentile(lat, 50)),
                              p99_ms=float(np.percentile(lat, 99)), phases=phases, stats=st)
         log(f"[bench] {mode}: {results[mode]['rows_per_s']:.0f} rows/s, "
@@ -267,14 +337,18 @@ def main():
     gpu_first = {}
     for mode in results:
         svd = L.TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision=mode,
-                             row_capacity=nfinal_rows + 16, col_capacity=nfinal_rows + 16)
+                             row_capacity=capU, col_capacity=capV)
         U0, s0, V0 = svd.factors()
-        svd.apply(dev_ups[0])
-        svd.apply(dev_ups[1])
+        for j in range(P):
+            svd.apply(dev_ups[j])
         svd.sync()
         gpu_first[mode] = ((U0, s0, V0), svd.factors())
         svd.close()
-    if not args.no_cpu_baseline:
+    if wl["gate"] == "properties":
+        for mode, ((U0, s0, V0), (U1, s1, V1)) in gpu_first.items():
+            gate[mode] = property_gate(U0, s0, V0, ups[0], U1, s1, V1)
+            log(f"[bench] gate {mode} (properties): {gate[mode]}")
+    else:
         try:
             from threadpoolctl import threadpool_info
             cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
@@ -282,15 +356,18 @@ def main():
             cores = os.cpu_count()
         log("[bench] oracle (FP64 Zha-Simon, dense QR + LAPACK SVD) on step 1 ...")
         t = time.perf_counter()
-        Ua, sa, Va, _ = zha_simon.apply(cfg["U"], cfg["s"], cfg["V"], ups[0])
-        Ub, sb, Vb, info = zha_simon.apply(Ua, sa, Va, ups[1])
+        Ur, sr, Vr = cfg["U"], cfg["s"], cfg["V"]
+        for j in range(P):
+            Ur, sr, Vr, info = zha_simon.apply(Ur, sr, Vr, ups[j])
         dt = time.perf_counter() - t
-        cpu = dict(value=rows_per_step / dt, unit="update rows/s", cores=int(cores), kind="oracle",
-                   sample=f"one step (add_cols + add_rows of {args.step_nodes} nodes, "
-                          f"{rows_per_step} update rows) of the same graph from the same "
-                          f"starting factors: {dt:.1f} s wall")
+        if not args.no_cpu_baseline:
+            cpu = dict(value=wl["rows_per_step"] / dt, unit="update rows/s", cores=int(cores),
+                       kind="oracle",
+                       sample=f"one step ({P} update(s), {wl['rows_per_step']} update rows) of "
+                              f"the same workload from the same starting factors: {dt:.1f} s wall")
         for mode, (_, (U1, s1, V1)) in gpu_first.items():
-            r = metrics.compare((U1, s1, V1), (Ub, sb, Vb), info["theta_hat"], 1e-3)
+            delta = 1e-6 if mode == "fp64" else 1e-3
+            r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], delta)
             gate[mode] = dict(sigma_rel=r["sigma_rel"], angle_U=r["angle_U"],
                               angle_V=r["angle_V"], jstar=r["jstar"],
                               orth_U=r["orth_U"], orth_V=r["orth_V"])
@@ -300,12 +377,15 @@ def main():
     head = "bf16x3" if "bf16x3" in results else list(results)[0]
     hr = results[head]
     # roofline of the dominant single-kernel phase
-    N = args.k + args.step_nodes
-    nnz_step = sum(E.nnz for _, E in ups[2 * W:2 * W + 2 * K]) / (2 * K)
-    d_cols = float(np.mean([len(np.unique(E.col_idx)) for _, E in ups[2 * W:2 * W + 2 * K]]))
+    k, s = wl["extra"]["k"], wl["s"]
+    N = k + s
+    timed = ups[P * W:P * (W + K)]
+    sp = [u[1] for u in timed] + [u[2] for u in timed if u[0] == "weights"]
+    nnz_step = float(np.mean([E.nnz for E in sp]))
+    d_cols = float(np.mean([len(np.unique(E.col_idx)) for E in sp]))
     best = None
     for name, (ms, cnt) in hr["phases"].items():
-        bound, work, unit = phase_work(name, N, args.step_nodes, args.k, nnz_step, d_cols)
+        bound, work, unit = phase_work(name, N, s, k, nnz_step, d_cols)
         if bound is None or cnt == 0:
             continue
         if best is None or ms > best[1]:
@@ -325,11 +405,17 @@ def main():
     sp_ms, sp_n = hr["phases"].get("spmm_w", (0.0, 0))
     spmm_roof = None
     if sp_n:
-        b = phase_work("spmm_w", N, args.step_nodes, args.k, nnz_step, d_cols)[1]
+        b = phase_work("spmm_w", N, s, k, nnz_step, d_cols)[1]
         ach = b / (sp_ms / sp_n / 1e3) / 1e9
         spmm_roof = dict(achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                          avg_us=1e3 * sp_ms / sp_n, bytes=b, traffic=stored_traffic("spmm_w"))
-    gate_ok = all(g["sigma_rel"] <= 1e-5 for g in gate.values()) if gate else None
+    if wl["gate"] == "properties":
+        tol = {"fp64": 1e-10}
+        gate_ok = all(g["residual_U"] <= tol.get(m, 1e-5) and g["residual_V"] <= tol.get(m, 1e-5)
+                      for m, g in gate.items()) if gate else None
+    else:
+        gate_ok = all(g["sigma_rel"] <= (1e-10 if m == "fp64" else 1e-5)
+                      for m, g in gate.items()) if gate else None
     out = {
         "metric": "update rows/s at k=64, BF16x3 vs FP32 path at sigma rel err <=1e-5; "
                   "p50/p99 latency",
@@ -338,13 +424,9 @@ def main():
         "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x3" if head == "bf16x3" else head,
+        "dtype": head,
         "data": "synthetic",
-        "config": {"workload": f"chung-lu graph adjacency, {nfinal_rows} nodes, mean degree 20, "
-                               f"k={args.k}, {args.step_nodes} nodes appended per step as "
-                               "add_cols + add_rows",
-                   "k": args.k, "s": args.step_nodes, "nodes": nfinal_rows,
-                   "parallelism": "single GPU"},
+        "config": dict({"workload": wl["desc"], "parallelism": "single GPU"}, **wl["extra"]),
         "p50_ms": hr["p50_ms"], "p99_ms": hr["p99_ms"],
         "paths": {m: dict(rows_per_s=r["rows_per_s"], ms_per_step=r["ms_per_step"],
                           p50_ms=r["p50_ms"], p99_ms=r["p99_ms"]) for m, r in results.items()},

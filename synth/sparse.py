@@ -160,6 +160,24 @@ def _qr_signfixed(x: np.ndarray) -> np.ndarray:
     return q * np.sign(np.where(d == 0, 1.0, d))
 
 
+def _orth_tall(Y: np.ndarray) -> np.ndarray:
+    """Orthonormal basis of the columns of a tall matrix: two Cholesky-QR
+    passes (fast, accurate to rounding while cond(Y) < ~1e6), else a
+    Householder QR."""
+    Q = Y
+    for _ in range(2):
+        G = Q.T @ Q
+        try:
+            R = np.linalg.cholesky(G).T
+        except np.linalg.LinAlgError:
+            return np.linalg.qr(Y)[0]
+        d = np.abs(np.diag(R))
+        if d.min() <= 1e-6 * d.max():
+            return np.linalg.qr(Y)[0]
+        Q = Q @ np.linalg.inv(R)
+    return Q
+
+
 def random_orthonormal(m: int, k: int, rng) -> np.ndarray:
     """m x k with orthonormal columns: Q of a Gaussian matrix, signs fixed so
     that diag(R) > 0."""
@@ -185,15 +203,17 @@ def randomized_init(A: CSR, k: int, rng, oversample: int = 16, power: int = 4):
     m, n = S.shape
     l = min(k + oversample, m, n)
     Y = S @ rng.standard_normal((n, l))
-    Q, _ = np.linalg.qr(Y)
+    Q = _orth_tall(Y)
     for _ in range(power):
-        Z, _ = np.linalg.qr(S.T @ Q)
-        Q, _ = np.linalg.qr(S @ Z)
-    B = (S.T @ Q).T                      # l x n
-    Ub, s, Vt = np.linalg.svd(B, full_matrices=False)
+        Z = _orth_tall(S.T @ Q)
+        Q = _orth_tall(S @ Z)
+    Bt = S.T @ Q                         # n x l, B = Q^T S = Bt^T
+    Qb = _orth_tall(Bt)                  # Bt = Qb Rb with Rb = Qb^T Bt
+    Ub, s, Vst = np.linalg.svd((Qb.T @ Bt).T)   # B = Rb^T Qb^T = Ub diag(s) (Qb Vs)^T
     U = Q @ Ub[:, :k]
-    V = Vt[:k].T.copy()
-    # re-orthonormalise in FP64 so that U^T U = V^T V = I to rounding
-    U = _qr_signfixed(U)
-    V = _qr_signfixed(V)
+    V = Qb @ Vst[:k].T
+    # re-orthonormalise in FP64 so that U^T U = V^T V = I to rounding (both
+    # are orthonormal up to rounding already, so Cholesky-QR is exact enough)
+    U = _orth_tall(U)
+    V = _orth_tall(V)
     return np.ascontiguousarray(U), s[:k].copy(), np.ascontiguousarray(V)

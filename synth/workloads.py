@@ -86,12 +86,14 @@ def config3_ratings(users: int = 500000, items: int = 50000,
 
 def config4_weights(N: int = 1_000_000, avg_deg: float = 20.0, k: int = 64,
                     steps: int = 10, s: int = 32, perturbed: int = 50000,
-                    added: int = 10000, gamma: float = 2.1, power: int = 2):
+                    added: int = 10000, gamma: float = 2.1, power: int = 1):
     """Weight change: LogNormal-weighted Chung-Lu graph; each step is one
     rank-s update ``A + D Em^T`` with ``D = I[:, R]`` for s rows R drawn with
     probability proportional to degree, and ``Em^T`` holding ``perturbed``
     re-weighted existing entries of those rows (new LogNormal minus old) and
-    ``added`` new entries (columns by Chung-Lu weight, LogNormal values)."""
+    ``added`` new entries (columns by Chung-Lu weight, LogNormal values).
+    When the drawn rows hold fewer than ``perturbed`` entries, all of them
+    are re-weighted."""
     rngs = seed_children(4, steps + 2)
     G = chung_lu_graph(N, gamma, avg_deg, rngs[0], values="lognormal")
     U, sig, V = randomized_init(G, k, rngs[1], power=power)
@@ -101,10 +103,18 @@ def config4_weights(N: int = 1_000_000, avg_deg: float = 20.0, k: int = 64,
     ups = []
     for t in range(steps):
         rng = rngs[2 + t]
-        while True:
+        # s rows drawn with probability proportional to degree; up to 64 draws
+        # are tried for a set holding ``perturbed`` existing entries and the
+        # draw with the most entries is kept (a degree-biased draw of 32 rows
+        # of a 1M-node graph rarely holds 50k entries)
+        best = None
+        for _ in range(64):
             R = rng.choice(N, size=s, replace=False, p=deg / deg.sum())
+            if best is None or deg[R].sum() > deg[best].sum():
+                best = R
             if deg[R].sum() >= perturbed:
                 break
+        R = best
         rows, cols, vals = [], [], []
         sub = Gs[R]
         nnz_sub = sub.nnz
