@@ -179,6 +179,70 @@ const char *svlcov_phase_name(int32_t i);
 svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,
                                   double *vecs, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Request server (continuous batching of updates over many matrices).
+ *
+ * A server keeps the factors of many matrices resident on one GPU and runs
+ * their update requests (the three forms above) as they arrive.  A scheduler
+ * thread admits requests in arrival order whenever one of max_inflight slots
+ * is free and the device workspace of the admitted requests stays within
+ * workspace_budget bytes (a request's footprint is the exact workspace its
+ * update carves, plus staging for host inputs; a request larger than the
+ * budget is admitted alone).  Requests of one matrix run one at a time in
+ * submission order; requests of different matrices run on their own streams
+ * and overlap on the device.  Cooperative kernels of different requests are
+ * ordered one after another (each needs all of its blocks resident).  Each
+ * request's result equals the result of the same update applied alone, up
+ * to the rounding of floating-point atomics.
+ * ---------------------------------------------------------------------- */
+typedef struct svlcov_server svlcov_server;
+
+typedef struct {
+  int32_t device;             /* HIP device ordinal (= the attached states')   */
+  int32_t max_inflight;       /* concurrent requests, 1..64                    */
+  int64_t workspace_budget;   /* bytes of device workspace for in-flight       */
+                              /* requests; <= 0 selects 8 GiB                  */
+} svlcov_server_options;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t peak_inflight;          /* most requests in flight at once          */
+  int64_t peak_workspace_bytes;   /* largest admitted workspace sum           */
+} svlcov_server_stats;
+
+void svlcov_server_default_options(svlcov_server_options *opt);
+svlcov_status svlcov_server_create(svlcov_server **out, const svlcov_server_options *opt);
+
+/* Hand a state (from svlcov_init, idle) to the server; from now on only the
+ * server may update it (svlcov_get_factors / svlcov_query_row are fine once
+ * svlcov_server_drain has returned).  Its own update workspaces are freed:
+ * requests borrow a slot's.  *matrix_id receives the id used by submit. */
+svlcov_status svlcov_server_attach(svlcov_server *srv, svlcov_state *h, int32_t *matrix_id);
+
+/* Queue one update: op 0 add rows (A = E_r), 1 add columns (A = E_c^T),
+ * 2 update weights (A = D^T, B = E_m^T).  Host CSR inputs are copied before
+ * the call returns; device CSR inputs must stay valid until the request
+ * completes.  Shape and format errors are reported as the request's result. */
+svlcov_status svlcov_server_submit(svlcov_server *srv, int32_t matrix_id, int32_t op,
+                                   const svlcov_csr *A, const svlcov_csr *B, int64_t *ticket);
+
+/* Result of a request: *result is its status (as the direct call would
+ * return it, device-side failures included), *latency_ms the time from
+ * submit to completion.  wait blocks; poll sets *done = 0 while it runs.  A
+ * ticket is forgotten once its result has been returned. */
+svlcov_status svlcov_server_wait(svlcov_server *srv, int64_t ticket, svlcov_status *result,
+                                 double *latency_ms);
+svlcov_status svlcov_server_poll(svlcov_server *srv, int64_t ticket, int32_t *done,
+                                 svlcov_status *result, double *latency_ms);
+
+/* Wait until every submitted request has completed. */
+svlcov_status svlcov_server_drain(svlcov_server *srv);
+svlcov_status svlcov_server_get_stats(svlcov_server *srv, svlcov_server_stats *out);
+
+/* Drain, stop the scheduler, and give the attached states back to the caller
+ * (they are not destroyed). */
+void svlcov_server_destroy(svlcov_server *srv);
+
 /* The hipStream_t the state enqueues on. */
 void *svlcov_stream(svlcov_state *h);
 

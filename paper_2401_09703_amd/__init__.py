@@ -58,11 +58,24 @@ class _Stats(C.Structure):
                 ("last_min_kept_pivot", C.c_double), ("last_max_dropped_pivot", C.c_double)]
 
 
+class _ServerOptions(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32),
+                ("workspace_budget", C.c_int64)]
+
+
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("peak_inflight", C.c_int64), ("peak_workspace_bytes", C.c_int64)]
+
+
 EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_add_cols",
            "svlcov_update_weights", "svlcov_get_factors", "svlcov_query_row", "svlcov_sync",
            "svlcov_get_stats", "svlcov_stream", "svlcov_destroy", "svlcov_status_str",
            "svlcov_profile", "svlcov_phase_times", "svlcov_phase_name",
-           "svlcov_sym_eig_topk"]
+           "svlcov_sym_eig_topk", "svlcov_server_default_options", "svlcov_server_create",
+           "svlcov_server_attach", "svlcov_server_submit", "svlcov_server_wait",
+           "svlcov_server_poll", "svlcov_server_drain", "svlcov_server_get_stats",
+           "svlcov_server_destroy"]
 NUM_PHASES = 16
 
 
@@ -96,6 +109,23 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_sym_eig_topk.restype = I32
     lib.svlcov_status_str.argtypes = [I32]
     lib.svlcov_status_str.restype = C.c_char_p
+    lib.svlcov_server_default_options.argtypes = [C.POINTER(_ServerOptions)]
+    lib.svlcov_server_default_options.restype = None
+    lib.svlcov_server_create.argtypes = [C.POINTER(P), C.POINTER(_ServerOptions)]
+    lib.svlcov_server_attach.argtypes = [P, P, C.POINTER(I32)]
+    lib.svlcov_server_submit.argtypes = [P, I32, I32, C.POINTER(_Csr), C.POINTER(_Csr),
+                                         C.POINTER(I64)]
+    lib.svlcov_server_wait.argtypes = [P, I64, C.POINTER(I32), C.POINTER(C.c_double)]
+    lib.svlcov_server_poll.argtypes = [P, I64, C.POINTER(I32), C.POINTER(I32),
+                                       C.POINTER(C.c_double)]
+    lib.svlcov_server_drain.argtypes = [P]
+    lib.svlcov_server_get_stats.argtypes = [P, C.POINTER(_ServerStats)]
+    lib.svlcov_server_destroy.argtypes = [P]
+    lib.svlcov_server_destroy.restype = None
+    for name in ("svlcov_server_create", "svlcov_server_attach", "svlcov_server_submit",
+                 "svlcov_server_wait", "svlcov_server_poll", "svlcov_server_drain",
+                 "svlcov_server_get_stats"):
+        getattr(lib, name).restype = I32
     for name in ("svlcov_init", "svlcov_add_rows", "svlcov_add_cols", "svlcov_update_weights",
                  "svlcov_get_factors", "svlcov_query_row", "svlcov_sync", "svlcov_get_stats"):
         getattr(lib, name).restype = I32
@@ -284,5 +314,82 @@ class TruncatedSVD:
             pass
 
 
-__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "load_library", "LIB_PATH", "EXPORTS",
+_OPS = {"rows": 0, "cols": 1, "weights": 2}
+
+
+class Server:
+    """Continuous-batching request server over many matrices on one GPU (the
+    svlcov_server_* calls).  attach() hands a TruncatedSVD to the server;
+    after that only the server updates it, and its factors may be read once
+    drain() has returned.  Close the server before the attached states."""
+
+    def __init__(self, device: int = 0, max_inflight: int = 8, workspace_budget: int = 0):
+        opt = _ServerOptions()
+        _lib.svlcov_server_default_options(C.byref(opt))
+        opt.device, opt.max_inflight = device, max_inflight
+        if workspace_budget:
+            opt.workspace_budget = workspace_budget
+        h = C.c_void_p()
+        _check(_lib.svlcov_server_create(C.byref(h), C.byref(opt)), "svlcov_server_create")
+        self._h = h
+        self._keep = {}
+
+    def attach(self, svd: "TruncatedSVD") -> int:
+        mid = C.c_int32()
+        _check(_lib.svlcov_server_attach(self._h, svd._h, C.byref(mid)), "svlcov_server_attach")
+        return int(mid.value)
+
+    def submit(self, matrix_id: int, update) -> int:
+        keep = []
+        a = _csr_struct(update[1], keep)
+        b = _csr_struct(update[2], keep) if update[0] == "weights" else None
+        t = C.c_int64()
+        _check(_lib.svlcov_server_submit(self._h, matrix_id, _OPS[update[0]], C.byref(a),
+                                         C.byref(b) if b is not None else None, C.byref(t)),
+               "svlcov_server_submit")
+        # host inputs were copied; device tensors must outlive the request
+        if any(_is_torch(x) for x in keep):
+            self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(status code, latency in ms) of a request; blocks."""
+        st, lat = C.c_int32(), C.c_double()
+        _check(_lib.svlcov_server_wait(self._h, ticket, C.byref(st), C.byref(lat)),
+               "svlcov_server_wait")
+        self._keep.pop(ticket, None)
+        return int(st.value), float(lat.value)
+
+    def poll(self, ticket: int):
+        """None while the request runs, else (status code, latency in ms)."""
+        done, st, lat = C.c_int32(), C.c_int32(), C.c_double()
+        _check(_lib.svlcov_server_poll(self._h, ticket, C.byref(done), C.byref(st),
+                                       C.byref(lat)), "svlcov_server_poll")
+        if not done.value:
+            return None
+        self._keep.pop(ticket, None)
+        return int(st.value), float(lat.value)
+
+    def drain(self):
+        _check(_lib.svlcov_server_drain(self._h), "svlcov_server_drain")
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(_lib.svlcov_server_get_stats(self._h, C.byref(st)), "svlcov_server_get_stats")
+        return {f: int(getattr(st, f)) for f, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.svlcov_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "load_library", "LIB_PATH", "EXPORTS",
            "FP64", "FP32", "BF16X3"]

@@ -12,21 +12,16 @@
 
 #include "../../include/svlcov.h"
 #include "kernels.hpp"
+#include "state.hpp"
+
+using svl_state::DevBuf;
+using svl_state::EvRec;
+using svl_state::Snapshot;
 
 namespace {
 
 constexpr double DEF_TOL[3] = {1e-13, 1e-6, 1e-5};   // FP64, FP32, BF16X3
 constexpr double DEF_COND[3] = {1e8, 1e2, 1e2};
-
-struct Snapshot {
-  int seq;
-  int64_t m, n;
-};
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-};
 
 // Phases of one update, timed with HIP events on the state's stream when
 // profiling is enabled (names in svlcov_phase_name).
@@ -39,40 +34,7 @@ const char *PHASE_NAMES[PH_COUNT] = {
     "tridiag", "bisect", "stein", "backtransform", "recover_G", "orthonormalize",
     "small_factor", "trsm", "commit"};
 
-struct EvRec {
-  int ph;
-  hipEvent_t a, b;
-};
-
 }  // namespace
-
-struct svlcov_state {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  int prec = SVLCOV_FP64;
-  int k = 0;
-  int64_t m = 0, n = 0;
-  int64_t capU = 0, capV = 0;
-  void *Ubase = nullptr, *Vbase = nullptr;  // double (FP64) or float
-  double *WU = nullptr, *WV = nullptr, *sigma = nullptr;
-  SvDevInfo *info = nullptr;
-  unsigned *flags = nullptr;   // tridiagonalisation barrier flags
-  unsigned epoch = 0;
-  bool launch_failed = false;   // a cooperative launch was refused
-  DevBuf ws;        // update workspace
-  DevBuf stage;     // device copies of host CSR inputs
-  DevBuf outbuf;    // get_factors staging
-  double rank_tol = 0, cond_reset = 0;
-  int validate = 1;
-  int seq = 0;
-  std::vector<Snapshot> history;
-  std::atomic<bool> busy{false};
-  bool prof = false;
-  std::vector<EvRec> recs;
-  std::vector<hipEvent_t> evpool;
-  size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
-};
 
 namespace {
 
@@ -256,6 +218,48 @@ struct Carver {
 
 int mode_of(int prec) { return prec == SVLCOV_FP64 ? 0 : (prec == SVLCOV_FP32 ? 1 : 2); }
 
+}  // namespace
+
+// Device workspace of one update (the carving of op_append / op_weights
+// below, replayed without memory): op 0 add_rows, 1 add_cols, 2 weights.
+size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int64_t nnzB) {
+  Carver c{nullptr};
+  const int64_t N = K + s;
+  const size_t nbl = ((s + svl::CHOL_NB - 1) / svl::CHOL_NB) * svl::CHOL_NB * svl::CHOL_NB;
+  const int64_t nnz = nnzA > nnzB ? nnzA : nnzB;
+  const int sides = op == 2 ? 2 : 1;
+  for (int q = 0; q < sides; ++q) {
+    c.take<double>(s * K);   // C'
+    c.take<float>(s * K);    // C' (FP32)
+    c.take<double>(s);       // row norms
+    c.take<double>(s * s);   // Gram / Cholesky factor
+    c.take<double>(nbl);     // diagonal-block inverses
+    c.take<double>(s * K);   // Y
+    c.take<double>(s * K);   // M rows
+  }
+  if (op == 2) {
+    c.take<double>(N * s);
+    c.take<double>(N * s);
+  }
+  c.take<double>(N * N);
+  c.take<double>(N * N);
+  c.take<double>(K);
+  c.take<double>(K);
+  c.take<int32_t>(K);
+  c.take<double>(K * N);
+  c.take<double>(K * N);
+  c.take<double>(svl::eig_work_doubles(N, K));
+  c.take<double>(K * K);
+  for (int q = 0; q < 4; ++q) c.take<double>(K * K);
+  c.take<int32_t>(2);
+  c.take<double>(2 * K * K + 9 * K * N);
+  c.take<int32_t>(nnz > 0 ? nnz : 1);
+  return c.off;
+}
+
+namespace {
+
+
 // One side's orthogonalisation: projection, sparse Gram, residual Gram and its
 // Cholesky (Algorithm 2 realised as R^T R = E E^T - (E V)(E V)^T, Lemma 3).
 template <typename T>
@@ -282,7 +286,11 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   }
   PhaseScope ps(h, PH_CHOL);
   svl::max_into(st, s, rown, h->info, which);
-  if (svl::cholesky_coop(st, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags, &h->epoch)) {
+  coop_enter(h);
+  const int crc = svl::cholesky_coop(st, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags,
+                                     &h->epoch);
+  coop_exit(h);
+  if (crc) {
     h->launch_failed = true;
     svl::set_status(st, h->info, SVLCOV_E_DEVICE);
   }
@@ -303,7 +311,10 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
   }
   {
     PhaseScope ps(h, PH_TRIDIAG);
-    if (svl::eig_tridiag(st, N, Mmat, eigw, h->flags, &h->epoch, h->info) != 0) {
+    coop_enter(h);
+    const int trc = svl::eig_tridiag(st, N, Mmat, eigw, h->flags, &h->epoch, h->info);
+    coop_exit(h);
+    if (trc != 0) {
       h->launch_failed = true;
       svl::set_status(st, h->info, SVLCOV_E_DEVICE);
     }
@@ -354,7 +365,10 @@ void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, c
   {
     PhaseScope ps(h, PH_TRSM);
     svl::copy_strided(st, s, K, Xv + K, 1, N, Y, K, h->info);
-    if (svl::trsm_coop(st, s, K, L, s, Linv, Y, h->info, h->flags, &h->epoch)) {
+    coop_enter(h);
+    const int src = svl::trsm_coop(st, s, K, L, s, Linv, Y, h->info, h->flags, &h->epoch);
+    coop_exit(h);
+    if (src) {
       h->launch_failed = true;
       svl::set_status(st, h->info, SVLCOV_E_DEVICE);
     }

@@ -1,0 +1,79 @@
+// The factor state of one matrix (internal; shared by the update engine and
+// the request server).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <vector>
+
+#include "../../include/svlcov.h"
+#include "common.hpp"
+
+namespace svl_state {
+
+struct Snapshot {
+  int seq;
+  int64_t m, n;
+};
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+struct EvRec {
+  int ph;
+  hipEvent_t a, b;
+};
+
+// Device workspace bytes of one update of the given form (op 0 add_rows,
+// 1 add_cols, 2 update_weights) at rank K with s update rows.
+size_t op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int64_t nnzB);
+
+}  // namespace svl_state
+
+struct svlcov_state {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int prec = SVLCOV_FP64;
+  int k = 0;
+  int64_t m = 0, n = 0;
+  int64_t capU = 0, capV = 0;
+  void *Ubase = nullptr, *Vbase = nullptr;  // double (FP64) or float
+  double *WU = nullptr, *WV = nullptr, *sigma = nullptr;
+  SvDevInfo *info = nullptr;
+  unsigned *flags = nullptr;   // tridiagonalisation barrier flags
+  unsigned epoch = 0;
+  bool launch_failed = false;   // a cooperative launch was refused
+  svl_state::DevBuf ws;        // update workspace
+  svl_state::DevBuf stage;     // device copies of host CSR inputs
+  svl_state::DevBuf outbuf;    // get_factors staging
+  double rank_tol = 0, cond_reset = 0;
+  int validate = 1;
+  int seq = 0;
+  std::vector<svl_state::Snapshot> history;
+  std::atomic<bool> busy{false};
+  bool prof = false;
+  std::vector<svl_state::EvRec> recs;
+  std::vector<hipEvent_t> evpool;
+  // Set while a request server drives the state: every cooperative launch
+  // first waits for *coop_chain and then re-records it, so that cooperative
+  // kernels of different matrices never run at the same time (each needs all
+  // of its blocks resident at once).
+  hipEvent_t *coop_chain = nullptr;
+  bool *coop_chain_live = nullptr;
+  size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
+};
+
+
+// Cooperative-launch ordering hooks (no-ops unless a server drives the state).
+inline void coop_enter(svlcov_state *h) {
+  if (h->coop_chain && *h->coop_chain_live) (void)hipStreamWaitEvent(h->stream, *h->coop_chain, 0);
+}
+inline void coop_exit(svlcov_state *h) {
+  if (h->coop_chain) {
+    (void)hipEventRecord(*h->coop_chain, h->stream);
+    *h->coop_chain_live = true;
+  }
+}

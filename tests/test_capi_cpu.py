@@ -63,3 +63,31 @@ def test_init_rejects_bad_arguments_before_device_use():
     # NULL state handles
     assert lib.svlcov_sync(None) == 1
     assert lib.svlcov_add_rows(None, None) == 1
+
+
+def test_server_rejects_bad_arguments_before_device_use():
+    import paper_2401_09703_amd as L
+    lib = L._lib
+    opt = L._ServerOptions()
+    lib.svlcov_server_default_options(C.byref(opt))
+    assert opt.max_inflight == 8 and opt.workspace_budget == 8 << 30
+    h = C.c_void_p()
+    opt.max_inflight = 0
+    assert lib.svlcov_server_create(C.byref(h), C.byref(opt)) == 1
+    opt.max_inflight = 65
+    assert lib.svlcov_server_create(C.byref(h), C.byref(opt)) == 1
+    assert not h.value
+    t = C.c_int64()
+    assert lib.svlcov_server_submit(None, 0, 0, None, None, C.byref(t)) == 1
+    assert lib.svlcov_server_drain(None) == 1
+    assert lib.svlcov_server_attach(None, None, None) == 1
+
+
+def test_server_binding_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: the server starts normally there")
+    import paper_2401_09703_amd as L
+    with pytest.raises(L.SvlcovError) as e:
+        L.Server(max_inflight=2)
+    assert e.value.code == 5

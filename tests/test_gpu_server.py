@@ -1,0 +1,132 @@
+"""The request server (continuous batching over many matrices): every
+request's result is the same alone and in the mix, within the mode's
+tolerance; requests of one matrix keep their order; admission respects the
+slot count and the workspace budget; a malformed request fails alone.
+
+Alone = each matrix's updates applied with direct calls on its own state;
+mix = fresh states attached to one server, all requests submitted
+interleaved across matrices before any result is collected.
+"""
+import numpy as np
+import pytest
+
+from oracle import metrics, zha_simon
+from synth import CSR, synthetic_factors
+from synth.sparse import bernoulli_uniform
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": dict(sig=1e-10, ang=1e-8, delta=1e-6),
+       "bf16x3": dict(sig=1e-5, ang=1e-4, delta=1e-3),
+       "fp32": dict(sig=1e-5, ang=1e-4, delta=1e-3)}
+
+
+def _matrices(prec, count=8, seed=11):
+    rng = np.random.default_rng(seed)
+    mats = []
+    for i in range(count):
+        m, n = int(rng.integers(300, 1500)), int(rng.integers(200, 900))
+        k = [16, 32, 64][i % 3]
+        U, s, V = synthetic_factors(m, n, k, rng)
+        ups = []
+        for j in range(3):
+            kind = ["rows", "cols", "weights"][(i + j) % 3]
+            sz = int(rng.integers(10, 160))
+            dens = float(rng.uniform(0.005, 0.03))
+            cur_m = m + sum(u[1].rows for u in ups if u[0] == "rows")
+            cur_n = n + sum(u[1].rows for u in ups if u[0] == "cols")
+            if kind == "rows":
+                ups.append(("rows", bernoulli_uniform(sz, cur_n, dens, rng)))
+            elif kind == "cols":
+                ups.append(("cols", bernoulli_uniform(sz, cur_m, dens, rng)))
+            else:
+                sz = min(sz, 32)
+                ups.append(("weights", bernoulli_uniform(sz, cur_m, 2 * dens, rng),
+                            bernoulli_uniform(sz, cur_n, dens, rng)))
+        mats.append((U, s, V, ups))
+    return mats
+
+
+def _compare(a, b, prec, ref_hat):
+    t = TOL[prec]
+    r = metrics.compare(a, b, ref_hat, t["delta"])
+    assert r["sigma_rel"] <= t["sig"] and r["angle_U"] <= t["ang"] and r["angle_V"] <= t["ang"], r
+    return r
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_alone_vs_mix(prec):
+    import paper_2401_09703_amd as L
+    mats = _matrices(prec)
+    alone = []
+    for U, s, V, ups in mats:
+        svd = L.TruncatedSVD(U, s, V, precision=prec)
+        for up in ups:
+            svd.apply(up)
+        svd.sync()
+        alone.append(svd.factors())
+        svd.close()
+    states = [L.TruncatedSVD(U, s, V, precision=prec) for U, s, V, _ in mats]
+    srv = L.Server(max_inflight=4)
+    try:
+        ids = [srv.attach(st) for st in states]
+        tickets = []
+        for j in range(3):                      # interleave across matrices
+            for i, (_, _, _, ups) in enumerate(mats):
+                tickets.append(srv.submit(ids[i], ups[j]))
+        res = [srv.wait(t) for t in tickets]
+        srv.drain()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    try:
+        assert all(code == 0 for code, _ in res), res
+        assert all(lat > 0 for _, lat in res)
+        assert stats["completed"] == stats["submitted"] == len(tickets) and stats["failed"] == 0
+        assert stats["peak_inflight"] >= 2, stats      # requests of different matrices overlapped
+        for i, (U, s, V, ups) in enumerate(mats):
+            mix = states[i].factors()
+            # the oracle run of the same sequence gives the spectrum for the gap prefix
+            Ur, sr, Vr = U, s, V
+            for up in ups:
+                Ur, sr, Vr, info = zha_simon.apply(Ur, sr, Vr, up)
+            _compare(mix, alone[i], prec, info["theta_hat"])
+            if prec == "fp64":
+                _compare(mix, (Ur, sr, Vr), prec, info["theta_hat"])
+    finally:
+        for st in states:
+            st.close()
+
+
+def test_budget_order_and_errors():
+    import paper_2401_09703_amd as L
+    mats = _matrices("fp32", count=3, seed=5)
+    states = [L.TruncatedSVD(U, s, V, precision="fp32") for U, s, V, _ in mats]
+    # a 1-byte budget admits one request at a time (an oversized request runs alone)
+    srv = L.Server(max_inflight=8, workspace_budget=1)
+    try:
+        ids = [srv.attach(st) for st in states]
+        U0, s0, V0, ups0 = mats[0]
+        bad = bernoulli_uniform(5, U0.shape[0] + 7, 0.1, np.random.default_rng(1))  # wrong width
+        t_bad = srv.submit(ids[0], ("cols", bad))
+        tickets = [srv.submit(ids[i], up) for j in range(3) for i, (_, _, _, ups) in
+                   enumerate(mats) for up in [ups[j]]]
+        code_bad, _ = srv.wait(t_bad)
+        res = [srv.wait(t) for t in tickets]
+        srv.drain()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    try:
+        assert code_bad == 2                       # shape error, matrix 0 unchanged by it
+        assert all(code == 0 for code, _ in res), res
+        assert stats["peak_inflight"] == 1, stats
+        # in-order application per matrix: equal to the direct sequence
+        for i, (U, s, V, ups) in enumerate(mats):
+            Ur, sr, Vr = U, s, V
+            for up in ups:
+                Ur, sr, Vr, info = zha_simon.apply(Ur, sr, Vr, up)
+            _compare(states[i].factors(), (Ur, sr, Vr), "fp32", info["theta_hat"])
+    finally:
+        for st in states:
+            st.close()
