@@ -206,9 +206,22 @@ class TruncatedSVD:
     def __init__(self, U, s, V, precision: str = "fp64", device: int = 0, stream=None,
                  row_capacity: int = 0, col_capacity: int = 0, rank_tol: float = 0.0,
                  cond_reset: float = 0.0, validate_device_inputs: bool = True):
-        U = np.ascontiguousarray(U, dtype=np.float64)
-        V = np.ascontiguousarray(V, dtype=np.float64)
-        s = np.ascontiguousarray(s, dtype=np.float64)
+        on_dev = 0
+        if _is_torch(U):
+            # device factors (FP64 CUDA tensors), read on the state's stream
+            import torch
+            for t in (U, s, V):
+                assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+            torch.cuda.synchronize()
+            on_dev = 1
+            m_, n_, k_ = U.shape[0], V.shape[0], s.numel()
+            pU, ps, pV = U.data_ptr(), s.data_ptr(), V.data_ptr()
+        else:
+            U = np.ascontiguousarray(U, dtype=np.float64)
+            V = np.ascontiguousarray(V, dtype=np.float64)
+            s = np.ascontiguousarray(s, dtype=np.float64)
+            m_, n_, k_ = U.shape[0], V.shape[0], s.size
+            pU, ps, pV = U.ctypes.data, s.ctypes.data, V.ctypes.data
         opt = _Options()
         _lib.svlcov_default_options(C.byref(opt))
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -220,10 +233,10 @@ class TruncatedSVD:
         opt.cond_reset = cond_reset
         opt.validate_device_inputs = 1 if validate_device_inputs else 0
         h = C.c_void_p()
-        _check(_lib.svlcov_init(C.byref(h), U.shape[0], V.shape[0], s.size, U.ctypes.data,
-                                s.ctypes.data, V.ctypes.data, 0, C.byref(opt)), "svlcov_init")
+        _check(_lib.svlcov_init(C.byref(h), m_, n_, k_, pU, ps, pV, on_dev, C.byref(opt)),
+               "svlcov_init")
         self._h = h
-        self.k = int(s.size)
+        self.k = int(k_)
         self.precision = precision
         self._keep = []
 

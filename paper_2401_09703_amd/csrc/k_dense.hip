@@ -4,6 +4,7 @@
 // orthonormalisation and the tall-skinny realisation GEMM.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "lane.hpp"
 
 #include <type_traits>
 
@@ -297,36 +298,76 @@ __global__ void k_theta_scale(int K, const double *__restrict__ lam, double *__r
   for (int64_t c = threadIdx.x; c < N; c += blockDim.x) Gv[(int64_t)j * N + c] *= inv;
 }
 
-// Linv = L^{-1} for the Cholesky factor L of the K x K Gram Gm = X X^T, one
-// block of K threads (thread i owns row i; a non-positive pivot is replaced
-// by 1 so that the pass stays finite).  One half of a Cholesky-QR pass; the
-// other half is the product Linv X.
-__global__ void __launch_bounds__(128)
+// Cholesky factor of the K x K Gram Gm (K <= 128) and the inverse of the
+// factor, by one block of SMALL_NT threads.  The factorisation is
+// right-looking on the unscaled columns (A[i][c] -= A[i][j] A[c][j] / d_j),
+// one barrier per column, the trailing lower triangle spread over all
+// threads; the columns are scaled at the end.  A non-positive pivot is taken
+// as 1 (the rows are then far from orthonormal, which the caller's checks
+// catch).  The inverse X = L^{-1} is formed column by column in parallel:
+// SMALL_NT / K threads per column share each forward-substitution dot
+// product; X is kept transposed in the strict upper triangle of the same
+// array, its diagonal apart.
+constexpr int SMALL_NT = 256;
+
+__global__ void __launch_bounds__(SMALL_NT)
 k_chol_inv_small(int K, const double *__restrict__ Gm, double *__restrict__ Linv,
                  const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  extern __shared__ double Ls[];   // K x (K+1) factor, inverted in place; K scratch
+  extern __shared__ double Ls[];   // K x (K+1): L below the diagonal, X^T above
   const int LD = K + 1;
-  const int i = threadIdx.x;
-  for (int e = i; e < K * K; e += blockDim.x) Ls[(e / K) * LD + e % K] = Gm[e];
+  double *dg = Ls + K * LD;        // K: pivots, then the diagonal of X
+  const int tid = threadIdx.x;
+  for (int e = tid; e < K * K; e += SMALL_NT) {
+    const int i = e / K, j = e % K;
+    if (j <= i) Ls[i * LD + j] = Gm[e];
+  }
   __syncthreads();
-  // right-looking Cholesky: thread i updates row i
   for (int j = 0; j < K; ++j) {
-    const double dj = Ls[j * LD + j];
-    const double rj = dj > 0.0 ? sqrt(dj) : 1.0;
-    if (i > j && i < K) Ls[i * LD + j] /= rj;
-    __syncthreads();
-    if (i == j) Ls[j * LD + j] = rj;
-    if (i > j && i < K) {
-      const double lij = Ls[i * LD + j];
-      for (int c = j + 1; c <= i; ++c) Ls[i * LD + c] -= lij * Ls[c * LD + j];
+    const double d = Ls[j * LD + j];
+    const double invd = d > 0.0 ? 1.0 / d : 1.0;
+    // rows over the waves, columns over the lanes
+    for (int i = j + 1 + (tid >> 6); i < K; i += SMALL_NT / 64) {
+      const double lij = Ls[i * LD + j] * invd;
+      for (int c = j + 1 + (tid & 63); c <= i; c += 64) Ls[i * LD + c] -= lij * Ls[c * LD + j];
     }
     __syncthreads();
   }
-  tri_lower_inv_inplace(Ls, LD, K, Ls + K * LD);
-  for (int e = i; e < K * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    Linv[e] = c <= r ? Ls[r * LD + c] : 0.0;
+  // scale: L[i][j] = A[i][j] / sqrt(d_j), L[j][j] = sqrt(d_j) (d_j <= 0: 1)
+  for (int j = tid; j < K; j += SMALL_NT) {
+    const double d = Ls[j * LD + j];
+    dg[j] = d > 0.0 ? sqrt(d) : 1.0;
+  }
+  __syncthreads();
+  for (int i = tid >> 6; i < K; i += SMALL_NT / 64)
+    for (int j = tid & 63; j <= i; j += 64) Ls[i * LD + j] = (j < i) ? Ls[i * LD + j] / dg[j] : dg[i];
+  __syncthreads();
+  // X = L^{-1}: column c = tid / TPC; its TPC threads split the terms p of
+  // x_i = (delta_ic - sum_{c<=p<i} L[i][p] x_p) / L[i][i] by p mod TPC.
+  // X[p][c] lives at Ls[c][p] (p > c) or dg[c] (p = c).
+  const int TPC = SMALL_NT / K;
+  const int c = tid / TPC, q = tid % TPC;
+  for (int i = 0; i < K; ++i) {
+    double acc = 0.0;
+    if (c < K && i > c)
+      for (int p = c + q; p < i; p += TPC)
+        acc += Ls[i * LD + p] * (p == c ? dg[c] : Ls[c * LD + p]);
+    for (int o = 1; o < TPC; o <<= 1) acc += __shfl_xor(acc, o, 64);
+    if (c < K && q == 0 && i >= c) {
+      const double x = ((i == c ? 1.0 : 0.0) - acc) / Ls[i * LD + i];
+      if (i == c) dg[c] = x;
+      else Ls[c * LD + i] = x;
+    }
+    // the TPC threads of a column are lanes of one wave: the next step reads
+    // x_i through LDS after this wave's store
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  __syncthreads();
+  for (int e = tid; e < K * K; e += SMALL_NT) {
+    const int r = e / K, cc = e % K;
+    Linv[e] = cc < r ? Ls[cc * LD + r] : (cc == r ? dg[r] : 0.0);
   }
 }
 
@@ -341,97 +382,155 @@ __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
                                       (uint64_t)c * 2654435761ull);
 }
 
-// In-place Gauss-Jordan inverse with partial pivoting (k <= 128, in LDS);
-// one block of 64 (k <= 64) or 128 threads; thread i < k owns row i and
-// column i, the others only take part in the reductions and barriers.
-__global__ void __launch_bounds__(128)
-k_inverse_cond(int K, const double *__restrict__ W, double *__restrict__ Winv,
+// Gauss-Jordan inverse with partial pivoting of the K x K matrix W (K <= 128)
+// held in registers, with the 1-norm condition number
+// kappa_1 = ||W||_1 ||W^{-1}||_1 and the reset flag (kappa_1 > cond_reset or
+// W numerically singular).  One block of 4 waves; wave w holds rows
+// [w K/4, (w+1) K/4), lane l holds columns l and l + 64.  Per column: the
+// pivot candidates of the waves meet in LDS (one barrier); the pivot row and
+// the displaced row are exchanged through LDS (one barrier); the elimination
+// multipliers come from the owning lane by v_readlane.  The row interchanges
+// are undone at the end as one column permutation.
+template <int K>
+__global__ void __launch_bounds__(256)
+k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
                int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
                int side) {
   if (info->status) return;
-  extern __shared__ double sm[];
-  const int ld = K + 1;
-  double *A = sm;                          // K x (K+1)
-  int *piv = (int *)(A + K * ld);          // K
-  __shared__ double wbest[2];
-  __shared__ int widx[2];
-  __shared__ double red[2];
-  __shared__ int sing;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
-  const bool own = t < K;
-  for (int e = t; e < K * K; e += blockDim.x) A[(e / K) * ld + e % K] = W[e];
-  if (t == 0) sing = 0;
-  __syncthreads();
-  // ||W||_1: max column sum (thread t sums column t)
-  double cs = 0.0;
-  if (own)
-    for (int r = 0; r < K; ++r) cs += fabs(A[r * ld + t]);
-  cs = wave_max(cs);
-  if (lane == 0) red[wv] = cs;
-  __syncthreads();
-  const double n1 = nw > 1 ? fmax(red[0], red[1]) : red[0];
-  const bool finite_in = isfinite(n1);
-  for (int c = 0; c < K && finite_in; ++c) {
-    // pivot: row of largest |A[r][c]|, r >= c (ties to the lower index)
-    double best = (own && t >= c) ? fabs(A[t * ld + c]) : -1.0;
-    int bi = t;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  constexpr int R = K / 4;                  // rows per wave
+  constexpr int CPL = K > 64 ? 2 : 1;       // columns per lane
+  __shared__ double rowc[K], rowp[K];
+  __shared__ double cand_v[4];
+  __shared__ int cand_i[4];
+  __shared__ double red[4];
+  __shared__ int piv[K], perm[K];
+  __shared__ double As[K][K + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int r0 = w * R;
+  double a[R][CPL];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int j = lane + 64 * q;
+      a[i][q] = j < K ? W[(r0 + i) * K + j] : 0.0;
     }
-    if (lane == 0) { wbest[wv] = best; widx[wv] = bi; }
-    __syncthreads();
-    if (t == 0) {
-      int p = widx[0];
-      double b = wbest[0];
-      if (nw > 1 && (wbest[1] > b)) { b = wbest[1]; p = widx[1]; }
-      piv[c] = p;
-      if (!(b > 1e-300) || !(b > 1e-15 * n1)) sing = 1;
-    }
-    __syncthreads();
-    if (sing) break;
-    const int p = piv[c];
-    if (p != c && own) {   // thread t swaps entry t of rows c and p
-      const double a = A[c * ld + t];
-      A[c * ld + t] = A[p * ld + t];
-      A[p * ld + t] = a;
-    }
-    __syncthreads();
-    const double pv = A[c * ld + c];
-    __syncthreads();
-    if (own) A[c * ld + t] = (t == c ? 1.0 : A[c * ld + t]) / pv;
-    __syncthreads();
-    if (own && t != c) {   // thread t eliminates row t
-      const double f = A[t * ld + c];
-      for (int j = 0; j < K; ++j)
-        if (j != c) A[t * ld + j] -= f * A[c * ld + j];
-      A[t * ld + c] = -f * A[c * ld + c];
-    }
-    __syncthreads();
+  // ||W||_1: column sums
+  double cs[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    cs[q] = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) cs[q] += fabs(a[i][q]);
   }
-  // undo the row interchanges as column interchanges, in reverse order
-  if (!sing && finite_in) {
+#pragma unroll
+  for (int q = 0; q < CPL; ++q)
+    if (lane + 64 * q < K) As[w][lane + 64 * q] = cs[q];
+  __syncthreads();
+  double mx = 0.0;
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int j = lane + 64 * q;
+    if (j < K) mx = fmax(mx, As[0][j] + As[1][j] + As[2][j] + As[3][j]);
+  }
+  mx = wave_max(mx);
+  if (lane == 0) red[w] = mx;
+  __syncthreads();
+  const double n1 = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const bool finite_in = isfinite(n1);
+  bool sing = !finite_in;
+  for (int c = 0; c < K && !sing; ++c) {
+    const int cl = c & 63, cq = c >> 6;
+    // this wave's candidate: largest |A[r][c]| over its rows r >= c (lowest index on ties)
+    double best = -1.0;
+    int bi = K;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const double v = fabs(readlane_d(CPL == 2 && cq ? a[i][CPL - 1] : a[i][0], cl));
+      if (r0 + i >= c && v > best) { best = v; bi = r0 + i; }
+    }
+    if (lane == 0) { cand_v[w] = best; cand_i[w] = bi; }
+    __syncthreads();
+    double pb = cand_v[0];
+    int p = cand_i[0];
+    for (int q = 1; q < 4; ++q)
+      if (cand_v[q] > pb) { pb = cand_v[q]; p = cand_i[q]; }
+    if (!(pb > 1e-300) || !(pb > 1e-15 * n1)) { sing = true; break; }
+    // publish rows c and p
+    if (c >= r0 && c < r0 + R) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (r0 + i == c)
+#pragma unroll
+          for (int q = 0; q < CPL; ++q)
+            if (lane + 64 * q < K) rowc[lane + 64 * q] = a[i][q];
+    }
+    if (p >= r0 && p < r0 + R) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (r0 + i == p)
+#pragma unroll
+          for (int q = 0; q < CPL; ++q)
+            if (lane + 64 * q < K) rowp[lane + 64 * q] = a[i][q];
+    }
+    if (t == 0) piv[c] = p;
+    __syncthreads();
+    const double pinv = 1.0 / rowp[c];
+    double prow[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int j = lane + 64 * q;
+      prow[q] = j < K ? (j == c ? pinv : rowp[j] * pinv) : 0.0;
+    }
+    const double fp = rowc[c];   // multiplier of row p after the interchange
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int r = r0 + i;
+      const double f = r == p ? fp : readlane_d(CPL == 2 && cq ? a[i][CPL - 1] : a[i][0], cl);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int j = lane + 64 * q;
+        if (r == c) {
+          a[i][q] = prow[q];
+        } else {
+          const double cur = r == p ? rowc[j < K ? j : 0] : a[i][q];
+          a[i][q] = j == c ? -f * pinv : cur - f * prow[q];
+        }
+      }
+    }
+  }
+  // the inverse is the final matrix with its columns permuted: column j of
+  // W^{-1} is column perm[j] of a (the row interchanges undone in reverse)
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+#pragma unroll
+    for (int q = 0; q < CPL; ++q)
+      if (lane + 64 * q < K) As[r0 + i][lane + 64 * q] = a[i][q];
+  if (t == 0 && !sing) {
+    for (int j = 0; j < K; ++j) perm[j] = j;
     for (int c = K - 1; c >= 0; --c) {
       const int p = piv[c];
-      if (p != c && own) {
-        const double a = A[t * ld + c];
-        A[t * ld + c] = A[t * ld + p];
-        A[t * ld + p] = a;
-      }
-      __syncthreads();
+      const int tmp = perm[c];
+      perm[c] = perm[p];
+      perm[p] = tmp;
     }
   }
-  double cs2 = 0.0;
-  if (own)
-    for (int r = 0; r < K; ++r) cs2 += fabs(A[r * ld + t]);
-  cs2 = wave_max(cs2);
   __syncthreads();
-  if (lane == 0) red[wv] = cs2;
+  // ||W^{-1}||_1 (max column sum, invariant under the column permutation)
+  double ci = 0.0;
+  for (int j = t; j < K; j += 256) {
+    double sacc = 0.0;
+    for (int r = 0; r < K; ++r) sacc += fabs(As[r][j]);
+    ci = fmax(ci, sacc);
+  }
+  ci = wave_max(ci);
   __syncthreads();
-  const double ninv = nw > 1 ? fmax(red[0], red[1]) : red[0];
-  const double kappa = (sing || !finite_in) ? INFINITY : n1 * ninv;
-  for (int e = t; e < K * K; e += blockDim.x) Winv[e] = A[(e / K) * ld + e % K];
+  if (lane == 0) red[w] = ci;
+  __syncthreads();
+  const double ninv = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  const double kappa = sing ? INFINITY : n1 * ninv;
+  if (!sing)
+    for (int e = t; e < K * K; e += 256) Winv[e] = As[e / K][perm[e % K]];
   if (t == 0) {
     const bool reset = !(kappa <= cond_reset);
     *flag = reset ? 1 : 0;
@@ -719,18 +818,22 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
   // completion rows, as random vectors far from the span of the others), and
   // the orthogonality CholQR leaves is ~ u kappa^2 with kappa ~ 1 here.
   gemm_f64_sk(st, false, true, K, K, N, 1.0, X, N, X, N, 0.0, Gm, K, ws, ws_len, info);
-  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(K), sh, st, K, Gm, Linv, info);
+  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(SMALL_NT), sh, st, K, Gm, Linv, info);
   gemm_f64(st, false, false, K, N, K, 1.0, Linv, K, X, N, 0.0, Xtmp, N, info);
   (void)hipMemcpyAsync(X, Xtmp, (size_t)K * N * sizeof(double), hipMemcpyDeviceToDevice, st);
 }
 
 void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
                   double cond_reset, SvDevInfo *info, int side) {
-  const size_t sh = (size_t)K * (K + 1) * sizeof(double) + (size_t)K * sizeof(int) + 16;
-  static bool once = false;
-  if (!once) { allow_big_lds(k_inverse_cond); (void)hipGetLastError(); once = true; }
-  hipLaunchKernelGGL(k_inverse_cond, dim3(1), dim3(K <= 64 ? 64 : 128), sh, st, K, W, Winv, flag, cond_reset,
-                     info, side);
+#define SV_INV(KK) hipLaunchKernelGGL((k_inverse_cond<KK>), dim3(1), dim3(256), 0, st, W, Winv, \
+                                      flag, cond_reset, info, side)
+  switch (K) {
+    case 16: SV_INV(16); break;
+    case 32: SV_INV(32); break;
+    case 64: SV_INV(64); break;
+    case 128: SV_INV(128); break;
+  }
+#undef SV_INV
 }
 
 void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,

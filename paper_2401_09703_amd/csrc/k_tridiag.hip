@@ -51,12 +51,17 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
     }
   }
   // Every per-entry loop below gives entry j to thread j mod NT, so a thread
-  // only reads back what it wrote itself; the three block barriers per
-  // column cover the cross-thread reads (the scalars alpha, w_{i+1} and the
-  // reductions, and the row loop that reads whole vectors).
+  // only reads back what it wrote itself; the two block barriers per column
+  // (plus the grid barrier's) cover the cross-thread reads: the scalars
+  // alpha, w_{i+1}, the two reductions, and the row loop that reads whole
+  // vectors.  The new column X stays unscaled until after the grid barrier:
+  // the row loop applies the reflector's scale on the fly.
   __shared__ double red0[NT / 64], red1[NT / 64];
   __shared__ double p_lead;   // p_{i+1}, published by its owner thread
-  auto first = [&](int lo) { return lo + ((tid - lo) & (NT - 1)); };
+  auto first = [&](int lo) {
+    int o = (tid - lo) % NT;
+    return lo + (o < 0 ? o + NT : o);
+  };
   double part = 0.0;   // sum of X[j]^2 over j >= i + 2, carried between iterations
   for (int j = tid; j < N; j += NT) {
     const double x = A[j];
@@ -81,8 +86,6 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
       t = (beta - alpha) / beta;
       scl = 1.0 / (alpha - beta);
     }
-    for (int j = first(i + 1); j < N; j += NT) X[j] = (j == i + 1) ? 1.0 : X[j] * scl;
-    __syncthreads();
     double *pb = pbuf + (int64_t)(i & 1) * N;
     double *rb = rowbuf + (int64_t)(i & 1) * N;
     // owned rows r >= i+1: pending rank-2 update, then p = tau M v
@@ -94,7 +97,9 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
       else Ar = A + (int64_t)r * lda;
       const double vpr = i >= 1 ? VP[r] : 0.0, wpr = i >= 1 ? WP[r] : 0.0;
       const bool pub = (r == i + 1);
-      double acc = 0.0;
+      // p_r = tau (a_{r,i+1} + scl sum_{j>i+1} a_rj X_j): v_{i+1} = 1, v_j = scl X_j
+      double acc = 0.0, lead = 0.0;
+#pragma unroll 2
       for (int j = i + 1 + lane; j < N; j += 64) {
         double a = Ar[j];
         if (i >= 1) {
@@ -102,10 +107,12 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
           Ar[j] = a;
         }
         if (pub) st_coh(&rb[j], a);
-        acc += a * X[j];
+        if (j == i + 1) lead = a;
+        else acc += a * X[j];
       }
       acc = wave_sum(acc);
-      if (lane == 0) st_coh(&pb[r], t * acc);
+      lead = wave_sum(lead);
+      if (lane == 0) st_coh(&pb[r], t * (lead + scl * acc));
     }
     flag_barrier(flags, epoch0 + (unsigned)i + 1u);
     const bool owner = (g == i % G);   // row i of M is finished: keep the reflector there
@@ -116,7 +123,8 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
     for (int j = first(i + 1); j < N; j += NT) {
       const double pj = ld_coh(&pb[j]);
       const double rj = ld_coh(&rb[j]);
-      const double xj = X[j];
+      const double xj = (j == i + 1) ? 1.0 : X[j] * scl;   // v_j
+      X[j] = xj;
       if (owner) A[(int64_t)i * lda + j] = xj;
       if (j == i + 1) p_lead = pj;
       WP[j] = pj;
@@ -172,6 +180,15 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
   double *d = work, *e = d + N, *tau = e + N, *pbuf = tau + N, *rowbuf = pbuf + 2 * N;
   static int ncu = 0;
   static bool once = false;
+  // block widths: 256 threads, or one wave per owned row (5..8 waves) when
+  // the rows live in LDS, so that no wave carries two rows
+  static const void *const fns_lds[5] = {
+      reinterpret_cast<const void *>(k_tridiag<true, 256>),
+      reinterpret_cast<const void *>(k_tridiag<true, 320>),
+      reinterpret_cast<const void *>(k_tridiag<true, 384>),
+      reinterpret_cast<const void *>(k_tridiag<true, 448>),
+      reinterpret_cast<const void *>(k_tridiag<true, 512>)};
+  static const void *const fn_mem = reinterpret_cast<const void *>(k_tridiag<false, 256>);
   if (!once) {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -179,25 +196,16 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
     if (ncu <= 0) ncu = 1;
     if (ncu > TRI_MAX_BLOCKS) ncu = TRI_MAX_BLOCKS;
     const int lim = 160 * 1024;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<true, 64>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<false, 64>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<true, 256>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag<false, 256>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    for (const void *f : fns_lds)
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute(fn_mem, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipGetLastError();
     once = true;
   }
-  // launch shape: block width NT (64 or 256 threads) and block count G; the
-  // defaults come from a sweep on MI355X, SVLCOV_TRI_THREADS / _BLOCKS
-  // override them for tuning
-  bool wide = true;
+  // block count G (default N/4, at most one block per CU; SVLCOV_TRI_BLOCKS
+  // overrides it for tuning sweeps)
   int G = N / 4;
-  if (const char *ev = getenv("SVLCOV_TRI_THREADS")) wide = atoi(ev) != 64;
   if (const char *ev = getenv("SVLCOV_TRI_BLOCKS")) G = atoi(ev);
-  const int NT = wide ? 256 : 64;
   if (G < 1) G = 1;
   if (G > ncu) G = ncu;
   const int rmax = (N + G - 1) / G;
@@ -205,16 +213,15 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
   const size_t rows_sh = (size_t)rmax * N * sizeof(double);
   const bool lds_rows = base_sh + rows_sh <= (size_t)150 * 1024;
   const size_t sh = lds_rows ? base_sh + rows_sh : base_sh;
-  const void *fn;
-  if (wide) fn = lds_rows ? reinterpret_cast<const void *>(k_tridiag<true, 256>)
-                          : reinterpret_cast<const void *>(k_tridiag<false, 256>);
-  else fn = lds_rows ? reinterpret_cast<const void *>(k_tridiag<true, 64>)
-                     : reinterpret_cast<const void *>(k_tridiag<false, 64>);
+  int waves = 4;
+  if (lds_rows) waves = rmax < 4 ? 4 : (rmax > 8 ? 8 : rmax);
+  const int NT = 64 * waves;
+  const void *fn = lds_rows ? fns_lds[waves - 4] : fn_mem;
   int nb = 0;
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, sh);
   (void)hipGetLastError();
   if (nb < 1) return -2;
-  if (G > nb * ncu) G = nb * ncu;
+  if (G > nb * ncu) return -2;   // (cannot happen: G <= ncu) every block must be co-resident
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)N);
   int64_t lda = N64;
   void *args[] = {(void *)&N, (void *)&A, (void *)&lda, (void *)&d, (void *)&e, (void *)&tau,
