@@ -6,6 +6,7 @@
 // factorisation of s = 1000 costs two launches instead of ~150.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "lane.hpp"
 
 using namespace svk;
 
@@ -17,8 +18,8 @@ constexpr int CT = 256;
 // Blocked right-looking Cholesky of the lower triangle of A (s x s, row
 // stride ld) with pivot dropping: a pivot d_j <= tol * scale sets column j of
 // L to zero.  Per block column (NB = 32):
-//   (1) every block loads the diagonal block and factors it (wave 0,
-//       column by column; the other waves wait);
+//   (1) every block loads the diagonal block and factors it (wave 0, rows
+//       in registers; the other waves wait);
 //   (2) the panel rows are spread over the blocks, two rows per wave: a row
 //       is solved against the diagonal factor by forward substitution with
 //       one lane per column;
@@ -36,6 +37,7 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
   if (info->status) return;
   __shared__ double Ld[NB][NB + 1];
   __shared__ double rinv[NB];     // 1 / L_jj, 0 for a dropped pivot
+  __shared__ double colj[NB];     // scaled column of the diagonal factor
   __shared__ double ta[NB][NB + 1];
   __shared__ double tb[NB][NB + 1];
   const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
@@ -57,28 +59,39 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
     }
     __syncthreads();
     if (tid < 64) {
-      // lane i (< 32) and lane i + 32 share row i's dot products (even and
-      // odd terms)
-      const int i = lane & 31, half = lane >> 5;
-      for (int j = 0; j < nb; ++j) {
-        double sacc = 0.0;
-        if (i >= j && i < nb)
-          for (int p = half; p < j; p += 2) sacc += Ld[i][p] * Ld[j][p];
-        sacc += __shfl_xor(sacc, 32, 64);
-        if (lane == j) {
-          const double d = Ld[j][j] - sacc;
+      // wave 0 factors the block right-looking with row i in lane i's
+      // registers: per column the pivot comes from lane j (v_readlane), the
+      // scaled column is shared through LDS, and the trailing update is a
+      // fully unrolled register loop
+      const int i = lane & 31;
+      double a[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) a[c] = Ld[i][c];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        if (j < nb) {
+          const double d = readlane_d(a[j], j);
           const bool drop = !(d > thr) || !(scale > 0.0);
           const double rd = drop ? 0.0 : sqrt(d);
-          Ld[j][j] = rd;
-          rinv[j] = drop ? 0.0 : 1.0 / rd;
-          const double rel = scale > 0.0 ? d / scale : 0.0;
-          if (drop) st_maxdrop = fmax(st_maxdrop, rel);
-          else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
+          const double ri = drop ? 0.0 : 1.0 / rd;
+          if (lane == 0) {
+            rinv[j] = ri;
+            const double rel = scale > 0.0 ? d / scale : 0.0;
+            if (drop) st_maxdrop = fmax(st_maxdrop, rel);
+            else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
+          }
+          const double lij = i > j ? a[j] * ri : (i == j ? rd : 0.0);
+          a[j] = lij;
+          if (lane < NB) colj[i] = i > j ? lij : 0.0;
+          wave_sync();
+#pragma unroll
+          for (int c = j + 1; c < NB; ++c) a[c] -= lij * colj[c];
+          wave_sync();
         }
-        wave_sync();
-        if (half == 0 && i > j && i < nb) Ld[i][j] = (Ld[i][j] - sacc) * rinv[j];
-        wave_sync();
       }
+      if (lane < NB)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) Ld[i][c] = c <= i ? a[c] : 0.0;
     }
     __syncthreads();
     // (2) panel rows r >= r0: row r = r0 + h + 8 (g + P q) for the half-wave
@@ -90,10 +103,18 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
         const bool act = r < s;
         double acc = (act && c < nb) ? ld_coh(&A[r * ld + b0 + c]) : 0.0;
         double x = 0.0;
-        for (int j = 0; j < nb; ++j) {
-          const double xj = __shfl(acc * rinv[j], (lane & 32) + j, 64);
-          if (c == j) x = xj;
-          if (c > j) acc -= Ld[c][j] * xj;
+        // the pivot reciprocals and this lane's row of the factor in
+        // registers, then a fully unrolled substitution
+        double ri[NB], lr[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) { ri[j] = rinv[j]; lr[j] = Ld[c][j]; }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          if (j < nb) {
+            const double xj = __shfl(acc * ri[j], (lane & 32) + j, 64);
+            if (c == j) x = xj;
+            if (c > j) acc -= lr[j] * xj;
+          }
         }
         if (act && c < nb) st_coh(&A[r * ld + b0 + c], x);
       }
@@ -134,8 +155,9 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
       for (int q = 0; q < PER; ++q) {
         const int e = tid + q * CT, i = e / NB, j = e % NB;
         if (ra + i < s && rb + j < s && (ti != tj || j <= i)) {
-          double acc = 0.0;
-          for (int p = 0; p < nb; ++p) acc += ta[i][p] * tb[j][p];
+          double acc = 0.0;   // entries p >= nb of ta, tb are zero
+#pragma unroll
+          for (int p = 0; p < NB; ++p) acc += ta[i][p] * tb[j][p];
           st_coh(&A[(ra + i) * ld + rb + j], dv[q] - acc);
         }
       }
@@ -218,8 +240,9 @@ k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
     __syncthreads();
     for (int e = tid; e < NB * K; e += CT) {
       const int i = e / K, c = e % K;
-      double v = 0.0;
-      for (int p = 0; p < nb; ++p) v += Li[p][i] * Zb[p][c];
+      double v = 0.0;   // rows p >= nb of Li, Zb are zero
+#pragma unroll
+      for (int p = 0; p < NB; ++p) v += Li[p][i] * Zb[p][c];
       Yb[i][c] = v;
     }
     // rows r < b0: 4 rows per pass (one wave each), lanes over the K columns
@@ -228,17 +251,19 @@ k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
       const bool act = r < b0;
       double z0 = 0.0, z1 = 0.0;
       if (act) {
-        if (lane < nb) lc[w][lane] = L[(b0 + lane) * ld + r];
+        if (lane < NB) lc[w][lane] = lane < nb ? L[(b0 + lane) * ld + r] : 0.0;
         if (lane < K) z0 = ld_coh(&Y[r * K + lane]);
         if (lane + 64 < K) z1 = ld_coh(&Y[r * K + lane + 64]);
       }
       __syncthreads();
       if (act) {
         double a0 = 0.0, a1 = 0.0;
-        for (int p = 0; p < nb; ++p) {
+        const int c0 = lane < K ? lane : 0, c1 = lane + 64 < K ? lane + 64 : 0;
+#pragma unroll
+        for (int p = 0; p < NB; ++p) {   // lc[w][p] = 0 for p >= nb
           const double l = lc[w][p];
-          if (lane < K) a0 += l * Yb[p][lane];
-          if (lane + 64 < K) a1 += l * Yb[p][lane + 64];
+          a0 += l * Yb[p][c0];
+          a1 += l * Yb[p][c1];
         }
         if (lane < K) st_coh(&Y[r * K + lane], z0 - a0);
         if (lane + 64 < K) st_coh(&Y[r * K + lane + 64], z1 - a1);

