@@ -4,7 +4,6 @@
 // orthonormalisation and the tall-skinny realisation GEMM.
 #include "common.hpp"
 #include "kernels.hpp"
-#include "lane.hpp"
 
 #include <type_traits>
 
@@ -387,10 +386,10 @@ __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
 // kappa_1 = ||W||_1 ||W^{-1}||_1 and the reset flag (kappa_1 > cond_reset or
 // W numerically singular).  One block of 4 waves; wave w holds rows
 // [w K/4, (w+1) K/4), lane l holds columns l and l + 64.  Per column: the
-// pivot candidates of the waves meet in LDS (one barrier); the pivot row and
-// the displaced row are exchanged through LDS (one barrier); the elimination
-// multipliers come from the owning lane by v_readlane.  The row interchanges
-// are undone at the end as one column permutation.
+// lane holding column c publishes it and its wave's pivot candidate in LDS
+// (one barrier); the pivot row and the displaced row are exchanged through
+// LDS (one barrier).  The row interchanges are undone at the end as one
+// column permutation.
 template <int K>
 __global__ void __launch_bounds__(256)
 k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
@@ -399,7 +398,7 @@ k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
   if (info->status) return;
   constexpr int R = K / 4;                  // rows per wave
   constexpr int CPL = K > 64 ? 2 : 1;       // columns per lane
-  __shared__ double rowc[K], rowp[K];
+  __shared__ double rowc[K], rowp[K], colc[K];
   __shared__ double cand_v[4];
   __shared__ int cand_i[4];
   __shared__ double red[4];
@@ -441,15 +440,21 @@ k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
   bool sing = !finite_in;
   for (int c = 0; c < K && !sing; ++c) {
     const int cl = c & 63, cq = c >> 6;
-    // this wave's candidate: largest |A[r][c]| over its rows r >= c (lowest index on ties)
-    double best = -1.0;
-    int bi = K;
+    // lane cl holds column c of this wave's rows: it finds the wave's pivot
+    // candidate (largest |A[r][c]| over rows r >= c, lowest index on ties)
+    // and publishes the column for the multipliers
+    if (lane == cl) {
+      double best = -1.0;
+      int bi = K;
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const double v = fabs(readlane_d(CPL == 2 && cq ? a[i][CPL - 1] : a[i][0], cl));
-      if (r0 + i >= c && v > best) { best = v; bi = r0 + i; }
+      for (int i = 0; i < R; ++i) {
+        const double v = CPL == 2 && cq ? a[i][CPL - 1] : a[i][0];
+        colc[r0 + i] = v;
+        if (r0 + i >= c && fabs(v) > best) { best = fabs(v); bi = r0 + i; }
+      }
+      cand_v[w] = best;
+      cand_i[w] = bi;
     }
-    if (lane == 0) { cand_v[w] = best; cand_i[w] = bi; }
     __syncthreads();
     double pb = cand_v[0];
     int p = cand_i[0];
@@ -486,7 +491,7 @@ k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int r = r0 + i;
-      const double f = r == p ? fp : readlane_d(CPL == 2 && cq ? a[i][CPL - 1] : a[i][0], cl);
+      const double f = r == p ? fp : colc[r];
 #pragma unroll
       for (int q = 0; q < CPL; ++q) {
         const int j = lane + 64 * q;
