@@ -190,8 +190,11 @@ svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double 
  * update carves, plus staging for host inputs; a request larger than the
  * budget is admitted alone).  Requests of one matrix run one at a time in
  * submission order; requests of different matrices run on their own streams
- * and overlap on the device.  Cooperative kernels of different requests are
- * ordered one after another (each needs all of its blocks resident).  Each
+ * and overlap on the device.  The projections (C' = E base W, the first step)
+ * of all requests admitted together whose inputs are device-resident and not
+ * re-validated on the device run as one fused launch.  Cooperative kernels of
+ * different requests are ordered one after another (each needs all of its
+ * blocks resident).  Each
  * request's result equals the result of the same update applied alone, up
  * to the rounding of floating-point atomics.
  * ---------------------------------------------------------------------- */
@@ -208,6 +211,9 @@ typedef struct {
   int64_t submitted, completed, failed;
   int64_t peak_inflight;          /* most requests in flight at once          */
   int64_t peak_workspace_bytes;   /* largest admitted workspace sum           */
+  int64_t fused_launches;         /* fused projection launches                */
+  int64_t fused_requests;         /* requests whose projection was fused      */
+  double fused_ms;                /* device time of those launches            */
 } svlcov_server_stats;
 
 void svlcov_server_default_options(svlcov_server_options *opt);
@@ -242,6 +248,18 @@ svlcov_status svlcov_server_get_stats(svlcov_server *srv, svlcov_server_stats *o
 /* Drain, stop the scheduler, and give the attached states back to the caller
  * (they are not destroyed). */
 void svlcov_server_destroy(svlcov_server *srv);
+
+/* The projection C' = E base W of many updates in one launch (the first
+ * step of an update, Lemma 1; the fused form the request server uses).
+ * Item i projects E[i] (device CSR; width m of states[i] for side 0, n for
+ * side 1) on U_base W_U (side 0) or V_base W_V (side 1) of states[i], writing
+ * C' (E[i].rows x k FP64, row-major, device) to out[i] and the squared row
+ * norms of E[i] to rown[i] (device, may be NULL).  The states must be idle
+ * (synced) and on one device; the launch runs on `stream` and the call waits
+ * for it. */
+svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const int32_t *sides,
+                                   const svlcov_csr *E, double *const *out, double *const *rown,
+                                   void *stream);
 
 /* The hipStream_t the state enqueues on. */
 void *svlcov_stream(svlcov_state *h);

@@ -65,7 +65,9 @@ class _ServerOptions(C.Structure):
 
 class _ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
-                ("peak_inflight", C.c_int64), ("peak_workspace_bytes", C.c_int64)]
+                ("peak_inflight", C.c_int64), ("peak_workspace_bytes", C.c_int64),
+                ("fused_launches", C.c_int64), ("fused_requests", C.c_int64),
+                ("fused_ms", C.c_double)]
 
 
 EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_add_cols",
@@ -75,7 +77,7 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_sym_eig_topk", "svlcov_server_default_options", "svlcov_server_create",
            "svlcov_server_attach", "svlcov_server_submit", "svlcov_server_wait",
            "svlcov_server_poll", "svlcov_server_drain", "svlcov_server_get_stats",
-           "svlcov_server_destroy"]
+           "svlcov_server_destroy", "svlcov_project_batch"]
 NUM_PHASES = 16
 
 
@@ -109,6 +111,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_sym_eig_topk.restype = I32
     lib.svlcov_status_str.argtypes = [I32]
     lib.svlcov_status_str.restype = C.c_char_p
+    lib.svlcov_project_batch.argtypes = [I32, P, P, P, P, P, P]
+    lib.svlcov_project_batch.restype = I32
     lib.svlcov_server_default_options.argtypes = [C.POINTER(_ServerOptions)]
     lib.svlcov_server_default_options.restype = None
     lib.svlcov_server_create.argtypes = [C.POINTER(P), C.POINTER(_ServerOptions)]
@@ -327,6 +331,28 @@ class TruncatedSVD:
             pass
 
 
+def project_batch(states, sides, Es, stream=None):
+    """The fused projection C' = E base W of many updates in one launch
+    (svlcov_project_batch): states are idle TruncatedSVD objects, sides 0 (U)
+    or 1 (V), Es DeviceCSR.  Returns the C' tensors (rows x k FP64 CUDA) and
+    the squared row norms of each E."""
+    import torch
+    n = len(states)
+    keep, outs, norms = [], [], []
+    csrs = (_Csr * n)()
+    for q, (svd, E) in enumerate(zip(states, Es)):
+        csrs[q] = _csr_struct(E, keep)
+        outs.append(torch.empty((E.rows, svd.k), dtype=torch.float64, device="cuda"))
+        norms.append(torch.empty(E.rows, dtype=torch.float64, device="cuda"))
+    hs = (C.c_void_p * n)(*[svd._h for svd in states])
+    sd = (C.c_int32 * n)(*sides)
+    po = (C.c_void_p * n)(*[t.data_ptr() for t in outs])
+    pn = (C.c_void_p * n)(*[t.data_ptr() for t in norms])
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    _check(_lib.svlcov_project_batch(n, hs, sd, csrs, po, pn, st), "svlcov_project_batch")
+    return outs, norms
+
+
 _OPS = {"rows": 0, "cols": 1, "weights": 2}
 
 
@@ -389,7 +415,7 @@ class Server:
     def stats(self) -> dict:
         st = _ServerStats()
         _check(_lib.svlcov_server_get_stats(self._h, C.byref(st)), "svlcov_server_get_stats")
-        return {f: int(getattr(st, f)) for f, _ in st._fields_}
+        return {f: getattr(st, f) for f, _ in st._fields_}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -404,5 +430,5 @@ class Server:
             pass
 
 
-__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "load_library", "LIB_PATH", "EXPORTS",
+__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "project_batch", "load_library", "LIB_PATH", "EXPORTS",
            "FP64", "FP32", "BF16X3"]

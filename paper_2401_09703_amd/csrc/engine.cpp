@@ -257,6 +257,28 @@ size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int
   return c.off;
 }
 
+void svl_state::proj_offsets(int op, int K, int64_t s, int q, size_t *cp64, size_t *cp32,
+                             size_t *rown) {
+  Carver c{nullptr};
+  if (op != 2) {   // op_append: C', C' (FP32), row norms first
+    *cp64 = c.off; c.take<double>(s * K);
+    *cp32 = c.off; c.take<float>(s * K);
+    *rown = c.off; c.take<double>(s);
+    return;
+  }
+  // op_weights: C'_D, C'_E, FP32 copies, row norms of D and of E_m
+  size_t o[6];
+  o[0] = c.off; c.take<double>(s * K);
+  o[1] = c.off; c.take<double>(s * K);
+  o[2] = c.off; c.take<float>(s * K);
+  o[3] = c.off; c.take<float>(s * K);
+  o[4] = c.off; c.take<double>(s);
+  o[5] = c.off; c.take<double>(s);
+  *cp64 = o[q];
+  *cp32 = o[2 + q];
+  *rown = o[4 + q];
+}
+
 namespace {
 
 
@@ -268,7 +290,7 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
-  {
+  if (!h->proj_ready[which]) {
     PhaseScope ps(h, PH_SPMM);
     svl::spmm_w<T>(st, K, s, E.rp, E.ci, E.v, E.vdt, base, W, Cp64,
                    h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info);
@@ -781,7 +803,9 @@ svlcov_status svlcov_add_rows(svlcov_state *h, const svlcov_csr *E) {
   BusyGuard g(h);
   if (!g.ok) return SVLCOV_E_BUSY;
   if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
-  return h->prec == SVLCOV_FP64 ? op_append<double>(h, E, true) : op_append<float>(h, E, true);
+  const svlcov_status r = h->prec == SVLCOV_FP64 ? op_append<double>(h, E, true) : op_append<float>(h, E, true);
+  h->proj_ready[0] = h->proj_ready[1] = false;
+  return r;
 }
 
 svlcov_status svlcov_add_cols(svlcov_state *h, const svlcov_csr *E) {
@@ -789,7 +813,9 @@ svlcov_status svlcov_add_cols(svlcov_state *h, const svlcov_csr *E) {
   BusyGuard g(h);
   if (!g.ok) return SVLCOV_E_BUSY;
   if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
-  return h->prec == SVLCOV_FP64 ? op_append<double>(h, E, false) : op_append<float>(h, E, false);
+  const svlcov_status r = h->prec == SVLCOV_FP64 ? op_append<double>(h, E, false) : op_append<float>(h, E, false);
+  h->proj_ready[0] = h->proj_ready[1] = false;
+  return r;
 }
 
 svlcov_status svlcov_update_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr *Em) {
@@ -797,7 +823,9 @@ svlcov_status svlcov_update_weights(svlcov_state *h, const svlcov_csr *D, const 
   BusyGuard g(h);
   if (!g.ok) return SVLCOV_E_BUSY;
   if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
-  return h->prec == SVLCOV_FP64 ? op_weights<double>(h, D, Em) : op_weights<float>(h, D, Em);
+  const svlcov_status r = h->prec == SVLCOV_FP64 ? op_weights<double>(h, D, Em) : op_weights<float>(h, D, Em);
+  h->proj_ready[0] = h->proj_ready[1] = false;
+  return r;
 }
 
 svlcov_status svlcov_sync(svlcov_state *h) {
@@ -959,6 +987,59 @@ void svlcov_destroy(svlcov_state *h) {
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
+}
+
+svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const int32_t *sides,
+                                   const svlcov_csr *E, double *const *out, double *const *rown,
+                                   void *stream) {
+  if (n <= 0 || n > 65536 || !states || !sides || !E || !out) return SVLCOV_E_INVALID;
+  const int dev = states[0] ? states[0]->device : 0;
+  std::vector<svl::ProjDesc> d((size_t)n);
+  int64_t total = 0, rown_need = 0;
+  for (int32_t q = 0; q < n; ++q) {
+    svlcov_state *h = states[q];
+    if (!h || h->device != dev || (sides[q] != 0 && sides[q] != 1) || !out[q])
+      return SVLCOV_E_INVALID;
+    svlcov_status r = check_csr_header(&E[q]);
+    if (r != SVLCOV_OK) return r;
+    if (!E[q].on_device) return SVLCOV_E_INVALID;
+    if (E[q].cols != (sides[q] == 0 ? h->m : h->n)) return SVLCOV_E_SHAPE;
+    svl::ProjDesc &x = d[(size_t)q];
+    x.row_ptr = E[q].row_ptr;
+    x.col_idx = E[q].col_idx;
+    x.val = E[q].val;
+    x.base = sides[q] == 0 ? h->Ubase : h->Vbase;
+    x.W = sides[q] == 0 ? h->WU : h->WV;
+    x.Cp64 = out[q];
+    x.Cp32 = nullptr;
+    x.rown = rown ? rown[q] : nullptr;
+    x.info = h->info;
+    x.s = E[q].rows;
+    x.row0 = total;
+    x.vdtype = E[q].val_dtype;
+    x.K = h->k;
+    x.fp64 = h->prec == SVLCOV_FP64 ? 1 : 0;
+    x.pad = 0;
+    total += E[q].rows;
+    if (!x.rown) rown_need += E[q].rows;
+  }
+  if (hipSetDevice(dev) != hipSuccess) return SVLCOV_E_DEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  svl::ProjDesc *dd = nullptr;
+  double *scratch = nullptr;
+  SV_TRY(hipMallocAsync((void **)&dd, d.size() * sizeof(svl::ProjDesc), st));
+  if (rown_need > 0) SV_TRY(hipMallocAsync((void **)&scratch, (size_t)rown_need * 8, st));
+  int64_t off = 0;
+  for (svl::ProjDesc &x : d)
+    if (!x.rown) { x.rown = scratch + off; off += x.s; }
+  SV_TRY(hipMemcpyAsync(dd, d.data(), d.size() * sizeof(svl::ProjDesc), hipMemcpyHostToDevice,
+                        st));
+  svl::spmm_batch(st, n, dd, total);
+  const hipError_t le = hipGetLastError();
+  (void)hipFreeAsync(dd, st);
+  if (scratch) (void)hipFreeAsync(scratch, st);
+  SV_TRY(hipStreamSynchronize(st));   // the host descriptor table must outlive the copy
+  return le == hipSuccess ? SVLCOV_OK : SVLCOV_E_DEVICE;
 }
 
 svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,

@@ -52,23 +52,20 @@ __device__ __forceinline__ double ldv(const void *val, int vdtype, int64_t p) {
   return vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
 }
 
-// P = E * base (s x K, accumulated in T), C' = P * W (FP64, W is K x K FP64),
-// plus ||e_i||^2.  For K <= 64 a wave splits into 64/K groups of K lanes that
-// take alternate nonzeros of a chunk; for K = 128 each lane owns two columns.
+// Row i of P = E * base (K columns, accumulated in T), C'[i] = P[i] W (FP64,
+// W is K x K FP64) and ||e_i||^2, by one block of SP_NW waves.  For K <= 64 a
+// wave splits into 64/K groups of K lanes that take alternate nonzeros of a
+// chunk; for K = 128 each lane owns two columns.  red (SP_NW x K), ptot (K)
+// and nred (SP_NW) are LDS scratch of the caller.
 template <typename T, int K>
-__global__ void __launch_bounds__(64 * SP_NW)
-k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+__device__ __forceinline__ void
+spmm_row(int64_t i, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
          const void *__restrict__ val, int vdtype, const T *__restrict__ base,
          const double *__restrict__ W, double *__restrict__ Cp64, float *__restrict__ Cp32,
-         double *__restrict__ rownorm2, const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
+         double *__restrict__ rownorm2, double *red, double *ptot, double *nred) {
   constexpr int G = K <= 64 ? 64 / K : 1;
   constexpr int CPL = K <= 64 ? 1 : K / 64;
-  __shared__ double red[SP_NW][K];
-  __shared__ double ptot[K];
-  __shared__ double nred[SP_NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t i = blockIdx.x;
   const int g = lane / (64 / G), c = lane % (64 / G);
   const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
   T acc[CPL];
@@ -112,7 +109,7 @@ k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restri
   }
   if (g == 0) {
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) red[w][c + 64 * q] = (double)acc[q];
+    for (int q = 0; q < CPL; ++q) red[w * K + c + 64 * q] = (double)acc[q];
   }
   nrm = wave_sum(nrm);
   if (lane == 0) nred[w] = nrm;
@@ -120,7 +117,7 @@ k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restri
   for (int t = threadIdx.x; t < K; t += 64 * SP_NW) {
     double sum = 0.0;
 #pragma unroll
-    for (int q = 0; q < SP_NW; ++q) sum += red[q][t];
+    for (int q = 0; q < SP_NW; ++q) sum += red[q * K + t];
     ptot[t] = sum;
   }
   __syncthreads();
@@ -137,6 +134,60 @@ k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restri
     for (int q = 0; q < SP_NW; ++q) tn += nred[q];
     rownorm2[i] = tn;
   }
+}
+
+// The projection of one update: one block per row of E.
+template <typename T, int K>
+__global__ void __launch_bounds__(64 * SP_NW)
+k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+         const void *__restrict__ val, int vdtype, const T *__restrict__ base,
+         const double *__restrict__ W, double *__restrict__ Cp64, float *__restrict__ Cp32,
+         double *__restrict__ rownorm2, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ double red[SP_NW * K];
+  __shared__ double ptot[K];
+  __shared__ double nred[SP_NW];
+  spmm_row<T, K>((int64_t)blockIdx.x, row_ptr, col_idx, val, vdtype, base, W, Cp64, Cp32,
+                 rownorm2, red, ptot, nred);
+}
+
+// The projections of many updates (of different matrices, ranks and storage
+// types) in one launch: block b takes row b - row0[r] of request r, with
+// row0 the prefix sums of the requests' row counts.
+__global__ void __launch_bounds__(64 * SP_NW)
+k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs) {
+  __shared__ double red[SP_NW * 128];
+  __shared__ double ptot[128];
+  __shared__ double nred[SP_NW];
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = n - 1;   // last request with row0 <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].row0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const svl::ProjDesc &d = descs[lo];
+  if (d.info && d.info->status) return;
+  const int64_t i = b - d.row0;
+  if (i >= d.s) return;
+#define SV_ROW(TT, KK) spmm_row<TT, KK>(i, d.row_ptr, d.col_idx, d.val, d.vdtype, \
+                                          (const TT *)d.base, d.W, d.Cp64, d.Cp32, d.rown, red, \
+                                          ptot, nred)
+  if (d.fp64) {
+    switch (d.K) {
+      case 16: SV_ROW(double, 16); break;
+      case 32: SV_ROW(double, 32); break;
+      case 64: SV_ROW(double, 64); break;
+      default: SV_ROW(double, 128); break;
+    }
+  } else {
+    switch (d.K) {
+      case 16: SV_ROW(float, 16); break;
+      case 32: SV_ROW(float, 32); break;
+      case 64: SV_ROW(float, 64); break;
+      default: SV_ROW(float, 128); break;
+    }
+  }
+#undef SV_ROW
 }
 
 // row id of every nonzero (the CSR row pointers expanded)
@@ -309,6 +360,12 @@ template void spmm_w<float>(hipStream_t, int, int64_t, const int64_t *, const in
 template void spmm_w<double>(hipStream_t, int, int64_t, const int64_t *, const int32_t *,
                              const void *, int, const double *, const double *, double *,
                              float *, double *, const SvDevInfo *);
+
+void spmm_batch(hipStream_t st, int n, const ProjDesc *descs_dev, int64_t total_rows) {
+  if (n <= 0 || total_rows <= 0) return;
+  hipLaunchKernelGGL(k_spmm_batch, dim3((unsigned)total_rows), dim3(64 * SP_NW), 0, st, n,
+                     descs_dev);
+}
 
 int gram_max_rows() { return GRAM_ACC_CAP; }
 

@@ -15,6 +15,22 @@ template <typename T>
 void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
             float *Cp32, double *rownorm2, const SvDevInfo *info);
+// One projection of a fused batch (k_spmm_batch): C' = E base W and the row
+// norms of E for s rows; row0 is the prefix sum of the batch's row counts.
+struct ProjDesc {
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const void *val;
+  const void *base;
+  const double *W;
+  double *Cp64;
+  float *Cp32;
+  double *rown;
+  const SvDevInfo *info;
+  int64_t s, row0;
+  int32_t vdtype, K, fp64, pad;
+};
+void spmm_batch(hipStream_t st, int n, const ProjDesc *descs_dev, int64_t total_rows);
 // S = E E^T; rid receives the row id of every nonzero (nnz int32 scratch).
 // s <= gram_max_rows().
 int gram_max_rows();

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "../../include/svlcov.h"
+#include "kernels.hpp"
 #include "state.hpp"
 
 namespace {
@@ -105,6 +106,16 @@ struct svlcov_server {
   hipEvent_t coop_chain = nullptr;
   bool coop_live = false;
   svlcov_server_stats stats{};
+  // fused projections: the server's stream, the descriptor table (pinned
+  // staging and device copy) and the timing events of each fused launch
+  hipStream_t stream = nullptr;
+  svl::ProjDesc *desc_host = nullptr;
+  size_t desc_host_cap = 0;
+  svl::ProjDesc *desc_dev = nullptr;
+  size_t desc_dev_cap = 0;
+  hipEvent_t desc_copy_ev = nullptr, proj_ev = nullptr;
+  bool desc_copy_live = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> fused_ev;
 };
 
 namespace {
@@ -127,6 +138,118 @@ void complete(svlcov_server *srv, Req *r, svlcov_status st) {
   if (r->done) srv->evpool.push_back(r->done);
   delete r;
   srv->cv_done.notify_all();
+}
+
+// Fused projection: the first step of every admitted update whose inputs
+// are device-resident (and not re-validated on the device) runs as one
+// launch over all of them on the server's stream, writing C', its FP32 copy
+// and the row norms straight into each request's slot workspace at the
+// offsets the update will carve; each matrix's stream then waits for it and
+// the update skips its own projection.
+void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
+  std::vector<svl::ProjDesc> d;
+  std::vector<std::pair<Req *, int>> users;   // request, number of sides
+  int64_t total = 0;
+  for (Req *r : admit) {
+    svlcov_state *h = r->h;
+    if (h->validate || !r->A.c.on_device || (r->op == 2 && !r->B.c.on_device)) continue;
+    const int64_t s = r->A.c.rows;
+    const bool shape_ok =
+        r->op == 0 ? r->A.c.cols == h->n
+        : r->op == 1 ? r->A.c.cols == h->m
+        : (r->B.c.rows == s && r->A.c.cols == h->m && r->B.c.cols == h->n);
+    if (!shape_ok || s <= 0 || h->k + s > svl::eig_max_n() || s > svl::gram_max_rows()) continue;
+    Slot &sl = srv->slots[r->slot];
+    const size_t need = svl_state::op_workspace_bytes(r->op, h->k, s, r->A.c.nnz,
+                                                      r->op == 2 ? r->B.c.nnz : 0);
+    if (sl.ws.bytes < need) {   // the same growth rule as the update's own
+      if (sl.ws.p) (void)hipFreeAsync(sl.ws.p, srv->stream);
+      sl.ws = svl_state::DevBuf{};
+      const size_t want = need + need / 4 + 4096;
+      if (hipMallocAsync(&sl.ws.p, want, srv->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        sl.ws.p = nullptr;
+        continue;
+      }
+      sl.ws.bytes = want;
+    }
+    const int sides = r->op == 2 ? 2 : 1;
+    for (int q = 0; q < sides; ++q) {
+      // add rows projects on V, add columns on U; weights: D on U, E_m on V
+      const bool onU = r->op == 1 || (r->op == 2 && q == 0);
+      const svlcov_csr &E = q == 0 ? r->A.c : r->B.c;
+      size_t o64, o32, orn;
+      svl_state::proj_offsets(r->op, h->k, s, q, &o64, &o32, &orn);
+      char *ws = (char *)sl.ws.p;
+      svl::ProjDesc x;
+      x.row_ptr = E.row_ptr;
+      x.col_idx = E.col_idx;
+      x.val = E.val;
+      x.base = onU ? h->Ubase : h->Vbase;
+      x.W = onU ? h->WU : h->WV;
+      x.Cp64 = (double *)(ws + o64);
+      x.Cp32 = h->prec == SVLCOV_FP64 ? nullptr : (float *)(ws + o32);
+      x.rown = (double *)(ws + orn);
+      x.info = h->info;
+      x.s = s;
+      x.row0 = total;
+      x.vdtype = E.val_dtype;
+      x.K = h->k;
+      x.fp64 = h->prec == SVLCOV_FP64 ? 1 : 0;
+      x.pad = 0;
+      d.push_back(x);
+      total += s;
+    }
+    users.push_back({r, sides});
+  }
+  if (d.empty()) return;
+  // the pinned staging table is reused once the previous copy has read it
+  if (srv->desc_copy_live) (void)hipEventSynchronize(srv->desc_copy_ev);
+  if (srv->desc_host_cap < d.size()) {
+    if (srv->desc_host) (void)hipHostFree(srv->desc_host);
+    srv->desc_host = nullptr;
+    srv->desc_host_cap = 0;
+    if (hipHostMalloc((void **)&srv->desc_host, d.size() * 2 * sizeof(svl::ProjDesc)) !=
+        hipSuccess) {
+      srv->desc_host = nullptr;
+      return;
+    }
+    srv->desc_host_cap = d.size() * 2;
+  }
+  if (srv->desc_dev_cap < d.size()) {
+    if (srv->desc_dev) (void)hipFreeAsync(srv->desc_dev, srv->stream);
+    srv->desc_dev = nullptr;
+    srv->desc_dev_cap = 0;
+    if (hipMallocAsync((void **)&srv->desc_dev, d.size() * 2 * sizeof(svl::ProjDesc),
+                       srv->stream) != hipSuccess) {
+      srv->desc_dev = nullptr;
+      return;
+    }
+    srv->desc_dev_cap = d.size() * 2;
+  }
+  std::memcpy(srv->desc_host, d.data(), d.size() * sizeof(svl::ProjDesc));
+  if (hipMemcpyAsync(srv->desc_dev, srv->desc_host, d.size() * sizeof(svl::ProjDesc),
+                     hipMemcpyHostToDevice, srv->stream) != hipSuccess)
+    return;
+  (void)hipEventRecord(srv->desc_copy_ev, srv->stream);
+  srv->desc_copy_live = true;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  (void)hipEventCreate(&t0);
+  (void)hipEventCreate(&t1);
+  if (t0) (void)hipEventRecord(t0, srv->stream);
+  svl::spmm_batch(srv->stream, (int)d.size(), srv->desc_dev, total);
+  if (hipGetLastError() != hipSuccess) return;   // the updates project on their own
+  if (t1) (void)hipEventRecord(t1, srv->stream);
+  if (t0 && t1) srv->fused_ev.push_back({t0, t1});
+  (void)hipEventRecord(srv->proj_ev, srv->stream);
+  for (auto &u : users) {
+    svlcov_state *h = u.first->h;
+    (void)hipStreamWaitEvent(h->stream, srv->proj_ev, 0);
+    for (int q = 0; q < u.second; ++q) h->proj_ready[q] = true;
+  }
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->stats.fused_launches += 1;
+  srv->stats.fused_requests += (int64_t)users.size();
 }
 
 // Enqueue one admitted request on its matrix's stream with the slot's
@@ -201,6 +324,7 @@ void worker_loop(svlcov_server *srv) {
       if ((int64_t)srv->inflight_bytes > srv->stats.peak_workspace_bytes)
         srv->stats.peak_workspace_bytes = (int64_t)srv->inflight_bytes;
     }
+    if (!admit.empty()) fuse_projections(srv, admit);
     for (Req *r : admit) {
       if (!r->done && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) {
         r->done = nullptr;
@@ -256,7 +380,10 @@ svlcov_status svlcov_server_create(svlcov_server **out, const svlcov_server_opti
   srv->budget = o.workspace_budget > 0 ? (size_t)o.workspace_budget : (size_t)8 << 30;
   srv->slots.resize((size_t)o.max_inflight);
   if (hipSetDevice(srv->device) != hipSuccess ||
-      hipEventCreateWithFlags(&srv->coop_chain, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&srv->coop_chain, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&srv->desc_copy_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&srv->proj_ev, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
     delete srv;
     return SVLCOV_E_DEVICE;
   }
@@ -354,6 +481,13 @@ svlcov_status svlcov_server_get_stats(svlcov_server *srv, svlcov_server_stats *o
   if (!srv || !out) return SVLCOV_E_INVALID;
   std::lock_guard<std::mutex> lk(srv->mu);
   *out = srv->stats;
+  out->fused_ms = 0.0;
+  for (auto &e : srv->fused_ev) {   // completed fused launches only
+    float ms = 0.f;
+    if (hipEventQuery(e.second) == hipSuccess && hipEventElapsedTime(&ms, e.first, e.second) ==
+                                                     hipSuccess)
+      out->fused_ms += ms;
+  }
   return SVLCOV_OK;
 }
 
@@ -377,7 +511,17 @@ void svlcov_server_destroy(svlcov_server *srv) {
     if (s.stage.p) (void)hipFree(s.stage.p);
   }
   for (hipEvent_t e : srv->evpool) (void)hipEventDestroy(e);
+  if (srv->stream) (void)hipStreamSynchronize(srv->stream);
+  for (auto &e : srv->fused_ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  if (srv->desc_dev) (void)hipFree(srv->desc_dev);
+  if (srv->desc_host) (void)hipHostFree(srv->desc_host);
   if (srv->coop_chain) (void)hipEventDestroy(srv->coop_chain);
+  if (srv->desc_copy_ev) (void)hipEventDestroy(srv->desc_copy_ev);
+  if (srv->proj_ev) (void)hipEventDestroy(srv->proj_ev);
+  if (srv->stream) (void)hipStreamDestroy(srv->stream);
   delete srv;
 }
 

@@ -29,6 +29,9 @@ struct EvRec {
 // Device workspace bytes of one update of the given form (op 0 add_rows,
 // 1 add_cols, 2 update_weights) at rank K with s update rows.
 size_t op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int64_t nnzB);
+// Offsets in that workspace of the projection outputs of side q (0: the
+// sparse side of add rows / add cols, or D of a weight update; 1: E_m).
+void proj_offsets(int op, int K, int64_t s, int q, size_t *cp64, size_t *cp32, size_t *rown);
 
 }  // namespace svl_state
 
@@ -63,6 +66,10 @@ struct svlcov_state {
   // of its blocks resident at once).
   hipEvent_t *coop_chain = nullptr;
   bool *coop_chain_live = nullptr;
+  // Set by a request server for the next update only: the projection of
+  // side q (C', its FP32 copy and the row norms) is already in the lent
+  // workspace, written by a fused multi-request launch.
+  bool proj_ready[2] = {false, false};
   size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
 };
 

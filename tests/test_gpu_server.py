@@ -130,3 +130,80 @@ def test_budget_order_and_errors():
     finally:
         for st in states:
             st.close()
+
+
+def test_fused_projection_matches_definition():
+    """svlcov_project_batch: C' = E base W for many (state, side, E) in one
+    launch, against E @ V (or E @ U) of the realised factors, for every rank
+    and both storage types; FP64 to 1e-12, FP32 storage to 1e-5 relative."""
+    import torch
+    import paper_2401_09703_amd as L
+    rng = np.random.default_rng(21)
+    states, sides, Es, host = [], [], [], []
+    for i, (k, prec) in enumerate([(16, "fp64"), (32, "fp32"), (64, "bf16x3"), (128, "fp64"),
+                                   (64, "fp32"), (16, "bf16x3")]):
+        m, n = int(rng.integers(300, 900)), int(rng.integers(200, 700))
+        U, s, V = synthetic_factors(m, n, k, rng)
+        svd = L.TruncatedSVD(U, s, V, precision=prec)
+        side = i % 2
+        E = bernoulli_uniform(int(rng.integers(5, 120)), m if side == 0 else n,
+                              float(rng.uniform(0.01, 0.2)), rng)
+        states.append(svd); sides.append(side); Es.append(L.DeviceCSR.from_host(E)); host.append(E)
+    try:
+        outs, norms = L.project_batch(states, sides, Es)
+        torch.cuda.synchronize()
+        for svd, side, E, out, nrm in zip(states, sides, host, outs, norms):
+            U, s, V = svd.factors()
+            ref = E.to_scipy() @ (U if side == 0 else V)
+            tol = 1e-12 if svd.precision == "fp64" else 1e-5
+            err = np.abs(out.cpu().numpy() - ref).max() / max(np.abs(ref).max(), 1e-300)
+            assert err <= tol, (svd.precision, err)
+            rn = np.asarray(E.to_scipy().multiply(E.to_scipy()).sum(axis=1)).ravel()
+            np.testing.assert_allclose(nrm.cpu().numpy(), rn, rtol=1e-12, atol=1e-300)
+    finally:
+        for svd in states:
+            svd.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp64"])
+def test_alone_vs_mix_fused(prec):
+    """Device-resident inputs on states that skip device re-validation: the
+    server fuses the projections of the requests it admits together; each
+    result still equals the sequential run."""
+    import paper_2401_09703_amd as L
+    mats = _matrices(prec, seed=17)
+    alone = []
+    for U, s, V, ups in mats:
+        svd = L.TruncatedSVD(U, s, V, precision=prec)
+        for up in ups:
+            svd.apply(up)
+        svd.sync()
+        alone.append(svd.factors())
+        svd.close()
+
+    def dev(up):
+        return (up[0],) + tuple(L.DeviceCSR.from_host(x) for x in up[1:])
+
+    dev_ups = [[dev(up) for up in ups] for _, _, _, ups in mats]
+    states = [L.TruncatedSVD(U, s, V, precision=prec, validate_device_inputs=False)
+              for U, s, V, _ in mats]
+    srv = L.Server(max_inflight=8)
+    try:
+        ids = [srv.attach(st) for st in states]
+        tickets = [srv.submit(ids[i], dev_ups[i][j]) for j in range(3) for i in range(len(mats))]
+        res = [srv.wait(t) for t in tickets]
+        srv.drain()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    try:
+        assert all(code == 0 for code, _ in res), res
+        assert stats["fused_launches"] >= 1 and stats["fused_requests"] >= 2, stats
+        for i, (U, s, V, ups) in enumerate(mats):
+            Ur, sr, Vr = U, s, V
+            for up in ups:
+                Ur, sr, Vr, info = zha_simon.apply(Ur, sr, Vr, up)
+            _compare(states[i].factors(), alone[i], prec, info["theta_hat"])
+    finally:
+        for st in states:
+            st.close()
