@@ -64,7 +64,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="graph", choices=("graph", "bernoulli", "ratings",
-                                                             "weights"))
+                                                             "weights", "stream"))
+    ap.add_argument("--requests", type=int, default=512, help="stream workload: requests")
+    ap.add_argument("--matrices", type=int, default=512, help="stream workload: matrices")
+    ap.add_argument("--inflight", type=int, default=64, help="stream workload: server slots")
+    ap.add_argument("--fused", type=int, default=128,
+                    help="stream workload: requests in the fused-projection measurement")
     ap.add_argument("--k", type=int, default=0, help="rank of the graph workload (default 64)")
     ap.add_argument("--n-init", type=int, default=90000)
     ap.add_argument("--step-nodes", type=int, default=1000)
@@ -255,6 +260,145 @@ def property_gate(U0, s0, V0, up, U1, s1, V1):
                 orth_U=metrics.orth_err(U1), orth_V=metrics.orth_err(V1))
 
 
+def gen_request_gpu(s, n, dens, seed):
+    """Update rows of a stream request on the device: each of the s rows holds
+    Binomial(n, dens) columns in expectation (uniform positions, repeats
+    merged), values 1 - U[0,1)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed % (2 ** 63))
+    nnz = max(int(round(s * n * dens)), 1)
+    r = torch.randint(0, s, (nnz,), generator=g, device="cuda", dtype=torch.int64)
+    c = torch.randint(0, n, (nnz,), generator=g, device="cuda", dtype=torch.int64)
+    key = torch.unique(r * n + c)
+    r, c = key // n, key % n
+    rp = torch.zeros(s + 1, dtype=torch.int64, device="cuda")
+    rp[1:] = torch.cumsum(torch.bincount(r, minlength=s), 0)
+    v = 1.0 - torch.rand(key.numel(), generator=g, device="cuda", dtype=torch.float64)
+    return rp, c.to(torch.int32).contiguous(), v
+
+
+def measure_fused_projection(L, torch, np, states, mats, reqs, dev_reqs, count):
+    """One fused launch projecting the first ``count`` requests (C' = E V_base
+    W_V of each, k_spmm_batch) on their idle states; device time of the
+    launch (best of 3 after one warm-up) against the compulsory bytes: CSR
+    (4 B column + 8 B value per nonzero, 8 B row pointers), the distinct rows
+    of V_base it gathers (FP32 storage), W, and the FP64 output and row
+    norms."""
+    sel = list(range(min(count, len(reqs))))
+    sts = [states[reqs[j]["mat"]] for j in sel]
+    Es = [dev_reqs[j] for j in sel]
+    byts = 0
+    for j in sel:
+        md, E = mats[reqs[j]["mat"]], dev_reqs[j]
+        d = int(torch.unique(E.col_idx).numel())
+        w = 8 if sts[0].precision == "fp64" else 4
+        byts += (E.col_idx.numel() * 12 + 8 * (E.rows + 1) + d * md["k"] * w
+                 + md["k"] * md["k"] * 8 + E.rows * md["k"] * 8 + E.rows * 8)
+    times = []
+    for _ in range(4):
+        L.project_batch(sts, [1] * len(sel), Es, timing=times)
+    ms = min(times[1:])
+    ach = byts / (ms / 1e3) / 1e9
+    return dict(requests=len(sel), bytes=int(byts), ms=ms, achieved_GBs=ach,
+                frac=ach / HBM_PEAK_GBS)
+
+
+def run_stream(args):
+    """Streaming batch: independent matrices resident on the GPU, row-append
+    requests of 10..2000 rows on uniformly chosen matrices, all submitted to
+    the request server at once (saturation); throughput over the whole batch
+    and per-request latency from submit to completion.  The same requests
+    run again with one slot (no overlap) for comparison."""
+    import numpy as np
+    import torch
+    import paper_2401_09703_amd as L
+    from synth import config5_stream
+    mats, reqs = config5_stream(n_mat=args.matrices, requests=args.requests)
+    prec = (args.modes or "bf16x3").split(",")[0]
+    t = time.time()
+    dev_reqs = []
+    for rq in reqs:
+        md = mats[rq["mat"]]
+        rp, ci, v = gen_request_gpu(rq["s"], md["n"], md["density"], rq["seed"])
+        dev_reqs.append(L.DeviceCSR(rq["s"], md["n"], rp, ci, v))
+    torch.cuda.synchronize()
+    nnz = sum(int(d.col_idx.numel()) for d in dev_reqs)
+    log(f"[bench] stream: {len(mats)} matrices, {len(reqs)} requests, {nnz} update nonzeros "
+        f"generated in {time.time() - t:.1f}s")
+    growth = {}
+    for rq in reqs:
+        growth[rq["mat"]] = growth.get(rq["mat"], 0) + rq["s"]
+    out_runs = {}
+    for slots in (args.inflight, 1):
+        t = time.time()
+        states = []
+        for i, md in enumerate(mats):
+            g = torch.Generator(device="cuda")
+            g.manual_seed(md["seed"] % (2 ** 63))
+            U = torch.linalg.qr(torch.randn(md["m"], md["k"], generator=g, device="cuda",
+                                            dtype=torch.float64)).Q.contiguous()
+            V = torch.linalg.qr(torch.randn(md["n"], md["k"], generator=g, device="cuda",
+                                            dtype=torch.float64)).Q.contiguous()
+            sg = 100.0 * torch.arange(1, md["k"] + 1, device="cuda", dtype=torch.float64) ** -0.5
+            states.append(L.TruncatedSVD(U, sg, V, precision=prec,
+                                         row_capacity=md["m"] + growth.get(i, 0) + 16,
+                                         validate_device_inputs=False))
+        torch.cuda.synchronize()
+        log(f"[bench] stream: {len(states)} states initialised in {time.time() - t:.1f}s")
+        if slots == args.inflight and args.fused > 0:
+            fused = measure_fused_projection(L, torch, np, states, mats, reqs, dev_reqs,
+                                             args.fused)
+            log(f"[bench] fused projection: {fused}")
+        srv = L.Server(max_inflight=slots, workspace_budget=32 << 30)
+        ids = [srv.attach(st) for st in states]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [srv.submit(ids[rq["mat"]], ("rows", dev_reqs[j])) for j, rq in enumerate(reqs)]
+        res = [srv.wait(tk) for tk in tickets]
+        srv.drain()
+        t1 = time.perf_counter()
+        stats = srv.stats()
+        srv.close()
+        for st in states:
+            st.close()
+        bad = [c for c, _ in res if c != 0]
+        lat = np.array([l for _, l in res])
+        rows = sum(rq["s"] for rq in reqs)
+        out_runs[slots] = dict(rows_per_s=rows / (t1 - t0), requests_per_s=len(reqs) / (t1 - t0),
+                               wall_s=t1 - t0, p50_ms=float(np.percentile(lat, 50)),
+                               p99_ms=float(np.percentile(lat, 99)), failed=len(bad),
+                               peak_inflight=stats["peak_inflight"],
+                               peak_workspace_gb=stats["peak_workspace_bytes"] / 2 ** 30)
+        log(f"[bench] stream slots={slots}: {out_runs[slots]}")
+    head = out_runs[args.inflight]
+    fused_roof = None
+    if args.fused > 0:
+        fused_roof = dict(kernel="k_spmm_batch", bound="hbm", achieved=fused["achieved_GBs"],
+                          peak=HBM_PEAK_GBS, unit="GB/s", frac=fused["frac"], traffic=None,
+                          requests=fused["requests"], bytes=fused["bytes"],
+                          avg_ms=fused["ms"])
+    out = {
+        "metric": "update rows/s (streaming batch of row-append requests, continuous batching); "
+                  "p50/p99 request latency",
+        "value": head["rows_per_s"] if head["failed"] == 0 else 0.0,
+        "unit": "update rows/s",
+        "n_gpus": 1, "steps": len(reqs), "warmup": 0,
+        "ms_per_step": 1e3 * head["wall_s"] / len(reqs),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"streaming batch: {len(mats)} matrices (rows 5k-200k, cols "
+                               f"1k-50k, density 0.05-1%, k in 16/32/64), {len(reqs)} row-append "
+                               "requests of 10-2000 rows, all submitted at once",
+                   "parallelism": "single GPU", "slots": args.inflight},
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "requests_per_s": head["requests_per_s"],
+        "runs": {f"slots={k}": v for k, v in out_runs.items()},
+        "roofline": fused_roof, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.summarize_stats:
@@ -273,6 +417,9 @@ def main():
     import paper_2401_09703_amd as L
 
     assert torch.cuda.is_available(), "no GPU"
+    if args.workload == "stream":
+        run_stream(args)
+        return
     if args.copy_calib_mib > 0:
         x = torch.ones(args.copy_calib_mib * (1 << 18), dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -256,10 +256,10 @@ void svlcov_server_destroy(svlcov_server *srv);
  * C' (E[i].rows x k FP64, row-major, device) to out[i] and the squared row
  * norms of E[i] to rown[i] (device, may be NULL).  The states must be idle
  * (synced) and on one device; the launch runs on `stream` and the call waits
- * for it. */
+ * for it.  kernel_ms (may be NULL) receives the launch's device time. */
 svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const int32_t *sides,
                                    const svlcov_csr *E, double *const *out, double *const *rown,
-                                   void *stream);
+                                   void *stream, float *kernel_ms);
 
 /* The hipStream_t the state enqueues on. */
 void *svlcov_stream(svlcov_state *h);

@@ -111,7 +111,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_sym_eig_topk.restype = I32
     lib.svlcov_status_str.argtypes = [I32]
     lib.svlcov_status_str.restype = C.c_char_p
-    lib.svlcov_project_batch.argtypes = [I32, P, P, P, P, P, P]
+    lib.svlcov_project_batch.argtypes = [I32, P, P, P, P, P, P, C.POINTER(C.c_float)]
     lib.svlcov_project_batch.restype = I32
     lib.svlcov_server_default_options.argtypes = [C.POINTER(_ServerOptions)]
     lib.svlcov_server_default_options.restype = None
@@ -331,11 +331,12 @@ class TruncatedSVD:
             pass
 
 
-def project_batch(states, sides, Es, stream=None):
+def project_batch(states, sides, Es, stream=None, timing=None):
     """The fused projection C' = E base W of many updates in one launch
     (svlcov_project_batch): states are idle TruncatedSVD objects, sides 0 (U)
     or 1 (V), Es DeviceCSR.  Returns the C' tensors (rows x k FP64 CUDA) and
-    the squared row norms of each E."""
+    the squared row norms of each E; with a list as ``timing`` the launch's
+    device time in ms is appended to it."""
     import torch
     n = len(states)
     keep, outs, norms = [], [], []
@@ -349,7 +350,12 @@ def project_batch(states, sides, Es, stream=None):
     po = (C.c_void_p * n)(*[t.data_ptr() for t in outs])
     pn = (C.c_void_p * n)(*[t.data_ptr() for t in norms])
     st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
-    _check(_lib.svlcov_project_batch(n, hs, sd, csrs, po, pn, st), "svlcov_project_batch")
+    ms = C.c_float(0.0)
+    _check(_lib.svlcov_project_batch(n, hs, sd, csrs, po, pn, st,
+                                     C.byref(ms) if timing is not None else None),
+           "svlcov_project_batch")
+    if timing is not None:
+        timing.append(float(ms.value))
     return outs, norms
 
 

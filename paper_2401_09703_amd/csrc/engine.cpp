@@ -991,7 +991,7 @@ void svlcov_destroy(svlcov_state *h) {
 
 svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const int32_t *sides,
                                    const svlcov_csr *E, double *const *out, double *const *rown,
-                                   void *stream) {
+                                   void *stream, float *kernel_ms) {
   if (n <= 0 || n > 65536 || !states || !sides || !E || !out) return SVLCOV_E_INVALID;
   const int dev = states[0] ? states[0]->device : 0;
   std::vector<svl::ProjDesc> d((size_t)n);
@@ -1034,11 +1034,21 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
     if (!x.rown) { x.rown = scratch + off; off += x.s; }
   SV_TRY(hipMemcpyAsync(dd, d.data(), d.size() * sizeof(svl::ProjDesc), hipMemcpyHostToDevice,
                         st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    return SVLCOV_E_DEVICE;
+  if (e0) SV_TRY(hipEventRecord(e0, st));
   svl::spmm_batch(st, n, dd, total);
   const hipError_t le = hipGetLastError();
+  if (e1) SV_TRY(hipEventRecord(e1, st));
   (void)hipFreeAsync(dd, st);
   if (scratch) (void)hipFreeAsync(scratch, st);
   SV_TRY(hipStreamSynchronize(st));   // the host descriptor table must outlive the copy
+  if (e0 && e1) {
+    if (hipEventElapsedTime(kernel_ms, e0, e1) != hipSuccess) *kernel_ms = -1.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   return le == hipSuccess ? SVLCOV_OK : SVLCOV_E_DEVICE;
 }
 
