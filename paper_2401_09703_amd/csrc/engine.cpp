@@ -995,7 +995,7 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
   if (n <= 0 || n > 65536 || !states || !sides || !E || !out) return SVLCOV_E_INVALID;
   const int dev = states[0] ? states[0]->device : 0;
   std::vector<svl::ProjDesc> d((size_t)n);
-  int64_t total = 0, rown_need = 0;
+  int64_t rown_need = 0;
   for (int32_t q = 0; q < n; ++q) {
     svlcov_state *h = states[q];
     if (!h || h->device != dev || (sides[q] != 0 && sides[q] != 1) || !out[q])
@@ -1015,14 +1015,14 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
     x.rown = rown ? rown[q] : nullptr;
     x.info = h->info;
     x.s = E[q].rows;
-    x.row0 = total;
+    x.row0 = 0;
     x.vdtype = E[q].val_dtype;
     x.K = h->k;
     x.fp64 = h->prec == SVLCOV_FP64 ? 1 : 0;
     x.pad = 0;
-    total += E[q].rows;
     if (!x.rown) rown_need += E[q].rows;
   }
+  svl::spmm_batch_prepare(d);
   if (hipSetDevice(dev) != hipSuccess) return SVLCOV_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
   svl::ProjDesc *dd = nullptr;
@@ -1038,7 +1038,7 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
   if (kernel_ms && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     return SVLCOV_E_DEVICE;
   if (e0) SV_TRY(hipEventRecord(e0, st));
-  svl::spmm_batch(st, n, dd, total);
+  svl::spmm_batch(st, d, dd);
   const hipError_t le = hipGetLastError();
   if (e1) SV_TRY(hipEventRecord(e1, st));
   (void)hipFreeAsync(dd, st);

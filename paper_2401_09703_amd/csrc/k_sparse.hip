@@ -2,6 +2,9 @@
 // update onto the tall factor (SpMM with the k x k factor as epilogue), the
 // sparse Gram E E^T, and the two writes into the tall factors (the sparse row
 // update and the appended rows).
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -151,14 +154,82 @@ k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restri
                  rownorm2, red, ptot, nred);
 }
 
-// The projections of many updates (of different matrices, ranks and storage
-// types) in one launch: block b takes row b - row0[r] of request r, with
-// row0 the prefix sums of the requests' row counts.
+constexpr int PB_U = 16;   // gathers in flight per lane in the fused projection
+
+// Row i of P = E * base accumulated by one wave (T accumulate); lanes c < K
+// (and c + 64 for K = 128) end with P[i][c] in out[c] (LDS); *nrm receives
+// ||e_i||^2 (lane 0).  Same gather scheme as spmm_row.
+template <typename T, int K>
+__device__ __forceinline__ void
+wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
+                 const int32_t *__restrict__ col_idx, const void *__restrict__ val, int vdtype,
+                 const T *__restrict__ base, double *out, double *nrm_out) {
+  constexpr int G = K <= 64 ? 64 / K : 1;
+  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  const int lane = threadIdx.x & 63;
+  const int g = lane / (64 / G), c = lane % (64 / G);
+  const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
+  T acc[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) acc[q] = (T)0;
+  double nrm = 0.0;
+  for (int64_t cb = p0; cb < p1; cb += 64) {
+    const int n = (int)((p1 - cb) < 64 ? (p1 - cb) : 64);
+    int32_t mc = 0;
+    double mvd = 0.0;
+    if (lane < n) {
+      mc = col_idx[cb + lane];
+      mvd = ldv(val, vdtype, cb + lane);
+    }
+    nrm += mvd * mvd;
+    const T mv = (T)mvd;
+    for (int j0 = 0; j0 < n; j0 += PB_U * G) {
+      int32_t cc[PB_U];
+      T vv[PB_U];
+#pragma unroll
+      for (int u = 0; u < PB_U; ++u) {
+        const int jj = j0 + u * G + g;
+        cc[u] = __shfl(mc, jj, 64);
+        vv[u] = __shfl(mv, jj, 64);
+      }
+      T bb[PB_U][CPL];
+#pragma unroll
+      for (int u = 0; u < PB_U; ++u)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) bb[u][q] = base[(int64_t)cc[u] * K + c + 64 * q];
+#pragma unroll
+      for (int u = 0; u < PB_U; ++u)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) acc[q] += vv[u] * bb[u][q];
+    }
+  }
+  if constexpr (G > 1) {
+#pragma unroll
+    for (int o = K; o < 64; o <<= 1) acc[0] += __shfl_xor(acc[0], o, 64);
+  }
+  if (g == 0) {
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) out[c + 64 * q] = (double)acc[q];
+  }
+  nrm = wave_sum(nrm);
+  if (lane == 0) *nrm_out = nrm;
+}
+
+// The projections of many updates of one rank and storage type in one
+// launch (a batch of mixed ranks and types is one launch per group, so each
+// launch keeps the registers of its own shape and its occupancy).  Block b
+// takes a tile of PB_RB consecutive rows of request r, with row0 the prefix
+// sums of the group's tile counts: each
+// wave accumulates whole rows of P (one row at a time, 16 gathers in flight
+// per lane), the tile's rows of P meet in LDS, and C' = P W is formed for the
+// tile (W from L2; small LDS keeps many blocks resident per CU).
+constexpr int PB_RB = 8;
+
+template <typename T, int K>
 __global__ void __launch_bounds__(64 * SP_NW)
 k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs) {
-  __shared__ double red[SP_NW * 128];
-  __shared__ double ptot[128];
-  __shared__ double nred[SP_NW];
+  __shared__ double Pt[PB_RB][K];
+  __shared__ double nr[PB_RB];
   const int64_t b = blockIdx.x;
   int lo = 0, hi = n - 1;   // last request with row0 <= b
   while (lo < hi) {
@@ -167,27 +238,23 @@ k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs) {
   }
   const svl::ProjDesc &d = descs[lo];
   if (d.info && d.info->status) return;
-  const int64_t i = b - d.row0;
-  if (i >= d.s) return;
-#define SV_ROW(TT, KK) spmm_row<TT, KK>(i, d.row_ptr, d.col_idx, d.val, d.vdtype, \
-                                          (const TT *)d.base, d.W, d.Cp64, d.Cp32, d.rown, red, \
-                                          ptot, nred)
-  if (d.fp64) {
-    switch (d.K) {
-      case 16: SV_ROW(double, 16); break;
-      case 32: SV_ROW(double, 32); break;
-      case 64: SV_ROW(double, 64); break;
-      default: SV_ROW(double, 128); break;
-    }
-  } else {
-    switch (d.K) {
-      case 16: SV_ROW(float, 16); break;
-      case 32: SV_ROW(float, 32); break;
-      case 64: SV_ROW(float, 64); break;
-      default: SV_ROW(float, 128); break;
-    }
+  const int64_t i0 = (b - d.row0) * PB_RB;
+  const int rows = (int)((d.s - i0) < PB_RB ? (d.s - i0) : PB_RB);
+  if (rows <= 0) return;
+  const int tid = threadIdx.x, w = tid >> 6;
+  for (int rr = w; rr < rows; rr += SP_NW)
+    wave_row_project<T, K>(i0 + rr, d.row_ptr, d.col_idx, d.val, d.vdtype, (const T *)d.base,
+                           Pt[rr], &nr[rr]);
+  __syncthreads();
+  for (int e = tid; e < rows * K; e += 64 * SP_NW) {
+    const int rr = e / K, col = e % K;
+    double o = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < K; ++l) o += Pt[rr][l] * d.W[l * K + col];
+    d.Cp64[(i0 + rr) * K + col] = o;
+    if (d.Cp32) d.Cp32[(i0 + rr) * K + col] = (float)o;
   }
-#undef SV_ROW
+  if (tid < rows) d.rown[i0 + tid] = nr[tid];
 }
 
 // row id of every nonzero (the CSR row pointers expanded)
@@ -361,10 +428,51 @@ template void spmm_w<double>(hipStream_t, int, int64_t, const int64_t *, const i
                              const void *, int, const double *, const double *, double *,
                              float *, double *, const SvDevInfo *);
 
-void spmm_batch(hipStream_t st, int n, const ProjDesc *descs_dev, int64_t total_rows) {
-  if (n <= 0 || total_rows <= 0) return;
-  hipLaunchKernelGGL(k_spmm_batch, dim3((unsigned)total_rows), dim3(64 * SP_NW), 0, st, n,
-                     descs_dev);
+int spmm_batch_rows_per_block() { return PB_RB; }
+
+void spmm_batch_prepare(std::vector<ProjDesc> &d) {
+  std::stable_sort(d.begin(), d.end(), [](const ProjDesc &a, const ProjDesc &b) {
+    return a.fp64 != b.fp64 ? a.fp64 < b.fp64 : a.K < b.K;
+  });
+  int64_t tiles = 0;
+  for (size_t q = 0; q < d.size(); ++q) {
+    if (q > 0 && (d[q].fp64 != d[q - 1].fp64 || d[q].K != d[q - 1].K)) tiles = 0;
+    d[q].row0 = tiles;
+    tiles += (d[q].s + PB_RB - 1) / PB_RB;
+  }
+}
+
+void spmm_batch(hipStream_t st, const std::vector<ProjDesc> &d, const ProjDesc *descs_dev) {
+  size_t g0 = 0;
+  while (g0 < d.size()) {
+    size_t g1 = g0 + 1;
+    while (g1 < d.size() && d[g1].fp64 == d[g0].fp64 && d[g1].K == d[g0].K) ++g1;
+    const ProjDesc &last = d[g1 - 1];
+    const int64_t tiles = last.row0 + (last.s + PB_RB - 1) / PB_RB;
+    const int n = (int)(g1 - g0);
+    const ProjDesc *dd = descs_dev + g0;
+    if (tiles > 0) {
+#define SV_PB(TT, KK) hipLaunchKernelGGL((k_spmm_batch<TT, KK>), dim3((unsigned)tiles), \
+                                         dim3(64 * SP_NW), 0, st, n, dd)
+      if (d[g0].fp64) {
+        switch (d[g0].K) {
+          case 16: SV_PB(double, 16); break;
+          case 32: SV_PB(double, 32); break;
+          case 64: SV_PB(double, 64); break;
+          default: SV_PB(double, 128); break;
+        }
+      } else {
+        switch (d[g0].K) {
+          case 16: SV_PB(float, 16); break;
+          case 32: SV_PB(float, 32); break;
+          case 64: SV_PB(float, 64); break;
+          default: SV_PB(float, 128); break;
+        }
+      }
+#undef SV_PB
+    }
+    g0 = g1;
+  }
 }
 
 int gram_max_rows() { return GRAM_ACC_CAP; }

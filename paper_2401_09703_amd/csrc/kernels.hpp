@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace svl {
@@ -16,7 +18,8 @@ void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
             float *Cp32, double *rownorm2, const SvDevInfo *info);
 // One projection of a fused batch (k_spmm_batch): C' = E base W and the row
-// norms of E for s rows; row0 is the prefix sum of the batch's row counts.
+// norms of E for s rows; row0 is the prefix sum of the batch's tile counts
+// (tiles of spmm_batch_rows_per_block() rows).
 struct ProjDesc {
   const int64_t *row_ptr;
   const int32_t *col_idx;
@@ -30,7 +33,11 @@ struct ProjDesc {
   int64_t s, row0;
   int32_t vdtype, K, fp64, pad;
 };
-void spmm_batch(hipStream_t st, int n, const ProjDesc *descs_dev, int64_t total_rows);
+int spmm_batch_rows_per_block();
+// Order a batch by (storage type, rank) and set each row0 to the tile offset
+// within its group; then upload it and launch one kernel per group.
+void spmm_batch_prepare(std::vector<ProjDesc> &d);
+void spmm_batch(hipStream_t st, const std::vector<ProjDesc> &d, const ProjDesc *descs_dev);
 // S = E E^T; rid receives the row id of every nonzero (nnz int32 scratch).
 // s <= gram_max_rows().
 int gram_max_rows();

@@ -149,7 +149,6 @@ void complete(svlcov_server *srv, Req *r, svlcov_status st) {
 void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
   std::vector<svl::ProjDesc> d;
   std::vector<std::pair<Req *, int>> users;   // request, number of sides
-  int64_t total = 0;
   for (Req *r : admit) {
     svlcov_state *h = r->h;
     if (h->validate || !r->A.c.on_device || (r->op == 2 && !r->B.c.on_device)) continue;
@@ -192,17 +191,17 @@ void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
       x.rown = (double *)(ws + orn);
       x.info = h->info;
       x.s = s;
-      x.row0 = total;
+      x.row0 = 0;
       x.vdtype = E.val_dtype;
       x.K = h->k;
       x.fp64 = h->prec == SVLCOV_FP64 ? 1 : 0;
       x.pad = 0;
       d.push_back(x);
-      total += s;
     }
     users.push_back({r, sides});
   }
   if (d.empty()) return;
+  svl::spmm_batch_prepare(d);
   // the pinned staging table is reused once the previous copy has read it
   if (srv->desc_copy_live) (void)hipEventSynchronize(srv->desc_copy_ev);
   if (srv->desc_host_cap < d.size()) {
@@ -237,7 +236,7 @@ void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
   if (t0) (void)hipEventRecord(t0, srv->stream);
-  svl::spmm_batch(srv->stream, (int)d.size(), srv->desc_dev, total);
+  svl::spmm_batch(srv->stream, d, srv->desc_dev);
   if (hipGetLastError() != hipSuccess) return;   // the updates project on their own
   if (t1) (void)hipEventRecord(t1, srv->stream);
   if (t0 && t1) srv->fused_ev.push_back({t0, t1});
