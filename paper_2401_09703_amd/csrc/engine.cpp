@@ -1016,34 +1016,36 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
     x.info = h->info;
     x.s = E[q].rows;
     x.row0 = 0;
+    x.nnz = E[q].nnz;
     x.vdtype = E[q].val_dtype;
     x.K = h->k;
     x.fp64 = h->prec == SVLCOV_FP64 ? 1 : 0;
     x.pad = 0;
     if (!x.rown) rown_need += E[q].rows;
   }
-  svl::spmm_batch_prepare(d);
   if (hipSetDevice(dev) != hipSuccess) return SVLCOV_E_DEVICE;
   hipStream_t st = (hipStream_t)stream;
-  svl::ProjDesc *dd = nullptr;
   double *scratch = nullptr;
-  SV_TRY(hipMallocAsync((void **)&dd, d.size() * sizeof(svl::ProjDesc), st));
   if (rown_need > 0) SV_TRY(hipMallocAsync((void **)&scratch, (size_t)rown_need * 8, st));
   int64_t off = 0;
   for (svl::ProjDesc &x : d)
     if (!x.rown) { x.rown = scratch + off; off += x.s; }
-  SV_TRY(hipMemcpyAsync(dd, d.data(), d.size() * sizeof(svl::ProjDesc), hipMemcpyHostToDevice,
-                        st));
+  const svl::ProjBatch pb = svl::spmm_batch_prepare(std::move(d));
+  std::vector<char> blob(pb.bytes());
+  pb.pack(blob.data());
+  void *dd = nullptr;
+  SV_TRY(hipMallocAsync(&dd, blob.size(), st));
+  SV_TRY(hipMemcpyAsync(dd, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (kernel_ms && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
     return SVLCOV_E_DEVICE;
   if (e0) SV_TRY(hipEventRecord(e0, st));
-  svl::spmm_batch(st, d, dd);
+  svl::spmm_batch(st, pb, dd);
   const hipError_t le = hipGetLastError();
   if (e1) SV_TRY(hipEventRecord(e1, st));
   (void)hipFreeAsync(dd, st);
   if (scratch) (void)hipFreeAsync(scratch, st);
-  SV_TRY(hipStreamSynchronize(st));   // the host descriptor table must outlive the copy
+  SV_TRY(hipStreamSynchronize(st));   // the host blob must outlive the copy
   if (e0 && e1) {
     if (hipEventElapsedTime(kernel_ms, e0, e1) != hipSuccess) *kernel_ms = -1.f;
     (void)hipEventDestroy(e0);

@@ -3,6 +3,9 @@
 // sparse Gram E E^T, and the two writes into the tall factors (the sparse row
 // update and the appended rows).
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "common.hpp"
@@ -154,62 +157,80 @@ k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restri
                  rownorm2, red, ptot, nred);
 }
 
-constexpr int PB_U = 16;   // gathers in flight per lane in the fused projection
+// 16-byte vectors of the base storage type: one gather per lane moves four
+// FP32 or two FP64 columns of a base row.
+typedef float sv_f4 __attribute__((ext_vector_type(4)));
+typedef double sv_d2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Wide;
+template <> struct Wide<float> { typedef sv_f4 V; static constexpr int E = 4; };
+template <> struct Wide<double> { typedef sv_d2 V; static constexpr int E = 2; };
 
-// Row i of P = E * base accumulated by one wave (T accumulate); lanes c < K
-// (and c + 64 for K = 128) end with P[i][c] in out[c] (LDS); *nrm receives
-// ||e_i||^2 (lane 0).  Same gather scheme as spmm_row.
+constexpr int PB_U = 8;   // 16-byte gathers in flight per lane in the fused projection
+
+// Row i of P = E * base accumulated by one wave (T accumulate).  A base row of
+// K columns is read by LPR = K/E lanes with one 16-byte load each, so one
+// load instruction gathers G = 64/LPR rows (G nonzeros of E) and a lane keeps
+// PB_U such loads in flight; loads past the row's last nonzero are skipped
+// (a uniform branch).  Lanes of group 0 end with P[i][c..c+E) in out (LDS);
+// *nrm_out receives ||e_i||^2.
 template <typename T, int K>
 __device__ __forceinline__ void
 wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
                  const int32_t *__restrict__ col_idx, const void *__restrict__ val, int vdtype,
                  const T *__restrict__ base, double *out, double *nrm_out) {
-  constexpr int G = K <= 64 ? 64 / K : 1;
-  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  typedef typename Wide<T>::V V;
+  constexpr int E = Wide<T>::E;
+  constexpr int LPR = K / E;                   // lanes per base row
+  constexpr int G = 64 / LPR;                  // base rows per load
+  constexpr int NB = PB_U * G;                 // nonzeros per batch of loads
+  constexpr int CH = NB > 64 ? NB / 64 : 1;    // CSR entries held per lane
+  constexpr int CW = 64 * CH;                  // nonzeros per CSR chunk
+  static_assert(LPR >= 1 && LPR <= 64 && (NB % 64 == 0 || 64 % NB == 0), "tile shape");
   const int lane = threadIdx.x & 63;
-  const int g = lane / (64 / G), c = lane % (64 / G);
+  const int g = lane / LPR, c = (lane % LPR) * E;
   const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-  T acc[CPL];
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) acc[q] = (T)0;
+  V acc = (V)(T)0;
   double nrm = 0.0;
-  for (int64_t cb = p0; cb < p1; cb += 64) {
-    const int n = (int)((p1 - cb) < 64 ? (p1 - cb) : 64);
-    int32_t mc = 0;
-    double mvd = 0.0;
-    if (lane < n) {
-      mc = col_idx[cb + lane];
-      mvd = ldv(val, vdtype, cb + lane);
+  for (int64_t cb = p0; cb < p1; cb += CW) {
+    const int n = (int)((p1 - cb) < CW ? (p1 - cb) : CW);
+    int32_t mc[CH];
+    T mv[CH];
+#pragma unroll
+    for (int h = 0; h < CH; ++h) {
+      const int p = h * 64 + lane;
+      mc[h] = 0;
+      mv[h] = (T)0;
+      if (p < n) {
+        mc[h] = col_idx[cb + p];
+        const double x = ldv(val, vdtype, cb + p);
+        nrm += x * x;
+        mv[h] = (T)x;
+      }
     }
-    nrm += mvd * mvd;
-    const T mv = (T)mvd;
-    for (int j0 = 0; j0 < n; j0 += PB_U * G) {
-      int32_t cc[PB_U];
+    // one pass when NB >= CW, else CW / NB passes over the chunk
+    for (int j0 = 0; j0 < n; j0 += NB) {
+      V bb[PB_U];
       T vv[PB_U];
 #pragma unroll
       for (int u = 0; u < PB_U; ++u) {
-        const int jj = j0 + u * G + g;
-        cc[u] = __shfl(mc, jj, 64);
-        vv[u] = __shfl(mv, jj, 64);
+        const int h = (u * G) / 64;              // j0 == 0 whenever CH > 1
+        const int jj = (j0 + u * G + g) & 63;
+        const int32_t col = __shfl(mc[h], jj, 64);
+        vv[u] = __shfl(mv[h], jj, 64);
+        bb[u] = (V)(T)0;
+        if (j0 + u * G < n) bb[u] = *(const V *)(base + (int64_t)col * K + c);
       }
-      T bb[PB_U][CPL];
 #pragma unroll
-      for (int u = 0; u < PB_U; ++u)
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) bb[u][q] = base[(int64_t)cc[u] * K + c + 64 * q];
-#pragma unroll
-      for (int u = 0; u < PB_U; ++u)
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) acc[q] += vv[u] * bb[u][q];
+      for (int u = 0; u < PB_U; ++u) acc += vv[u] * bb[u];
     }
   }
-  if constexpr (G > 1) {
 #pragma unroll
-    for (int o = K; o < 64; o <<= 1) acc[0] += __shfl_xor(acc[0], o, 64);
-  }
+  for (int o = LPR; o < 64; o <<= 1)
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] += __shfl_xor(acc[e], o, 64);
   if (g == 0) {
 #pragma unroll
-    for (int q = 0; q < CPL; ++q) out[c + 64 * q] = (double)acc[q];
+    for (int e = 0; e < E; ++e) out[c + e] = (double)acc[e];
   }
   nrm = wave_sum(nrm);
   if (lane == 0) *nrm_out = nrm;
@@ -218,39 +239,68 @@ wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
 // The projections of many updates of one rank and storage type in one
 // launch (a batch of mixed ranks and types is one launch per group, so each
 // launch keeps the registers of its own shape and its occupancy).  Block b
-// takes a tile of PB_RB consecutive rows of request r, with row0 the prefix
-// sums of the group's tile counts: each
-// wave accumulates whole rows of P (one row at a time, 16 gathers in flight
-// per lane), the tile's rows of P meet in LDS, and C' = P W is formed for the
-// tile (W from L2; small LDS keeps many blocks resident per CU).
+// takes tile t = order[b], a tile of PB_RB consecutive rows of the request
+// whose tiles start at row0 <= t: each wave accumulates whole rows of P (one
+// row at a time, 16-byte gathers), the tile's rows of P meet in
+// LDS, and C' = P W is formed for the tile with each element of W read once
+// (from L2) by the thread that owns its column and part of the inner index.
 constexpr int PB_RB = 8;
+constexpr int SV_XCDS = 8;   // MI355X: workgroup b runs on XCD b mod 8
 
 template <typename T, int K>
 __global__ void __launch_bounds__(64 * SP_NW)
-k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs) {
+k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs, const int32_t *__restrict__ order) {
+  constexpr int Q = 64 * SP_NW / K;   // parts of the inner index in C' = P W
+  constexpr int LQ = K / Q;
   __shared__ double Pt[PB_RB][K];
+  __shared__ double Pp[Q][PB_RB][K];
   __shared__ double nr[PB_RB];
-  const int64_t b = blockIdx.x;
-  int lo = 0, hi = n - 1;   // last request with row0 <= b
+  const int64_t t = order[blockIdx.x];
+  if (t < 0) return;
+  int lo = 0, hi = n - 1;   // last request with row0 <= t
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].row0 <= b) lo = mid; else hi = mid - 1;
+    if (descs[mid].row0 <= t) lo = mid; else hi = mid - 1;
   }
   const svl::ProjDesc &d = descs[lo];
   if (d.info && d.info->status) return;
-  const int64_t i0 = (b - d.row0) * PB_RB;
+  const int64_t i0 = (t - d.row0) * PB_RB;
   const int rows = (int)((d.s - i0) < PB_RB ? (d.s - i0) : PB_RB);
   if (rows <= 0) return;
   const int tid = threadIdx.x, w = tid >> 6;
   for (int rr = w; rr < rows; rr += SP_NW)
     wave_row_project<T, K>(i0 + rr, d.row_ptr, d.col_idx, d.val, d.vdtype, (const T *)d.base,
                            Pt[rr], &nr[rr]);
+  for (int rr = rows + w; rr < PB_RB; rr += SP_NW)   // rows past the end stay finite
+    for (int c = tid & 63; c < K; c += 64) Pt[rr][c] = 0.0;
+  __syncthreads();
+  // thread (part, col): the part's LQ inner indices for all rows of the tile,
+  // so every element of W is read once per tile
+  {
+    const int col = tid % K, part = tid / K;
+    double o[PB_RB];
+#pragma unroll
+    for (int r = 0; r < PB_RB; ++r) o[r] = 0.0;
+    constexpr int UB = LQ < 16 ? LQ : 16;   // W loads in flight per thread
+#pragma unroll 1
+    for (int u0 = 0; u0 < LQ; u0 += UB) {
+      double wv[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) wv[u] = d.W[(part * LQ + u0 + u) * K + col];
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+#pragma unroll
+        for (int r = 0; r < PB_RB; ++r) o[r] += Pt[r][part * LQ + u0 + u] * wv[u];
+    }
+#pragma unroll
+    for (int r = 0; r < PB_RB; ++r) Pp[part][r][col] = o[r];
+  }
   __syncthreads();
   for (int e = tid; e < rows * K; e += 64 * SP_NW) {
     const int rr = e / K, col = e % K;
     double o = 0.0;
-#pragma unroll 8
-    for (int l = 0; l < K; ++l) o += Pt[rr][l] * d.W[l * K + col];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) o += Pp[q][rr][col];
     d.Cp64[(i0 + rr) * K + col] = o;
     if (d.Cp32) d.Cp32[(i0 + rr) * K + col] = (float)o;
   }
@@ -430,48 +480,116 @@ template void spmm_w<double>(hipStream_t, int, int64_t, const int64_t *, const i
 
 int spmm_batch_rows_per_block() { return PB_RB; }
 
-void spmm_batch_prepare(std::vector<ProjDesc> &d) {
+void ProjBatch::pack(void *host) const {
+  char *p = (char *)host;
+  std::memcpy(p, d.data(), d.size() * sizeof(ProjDesc));
+  std::memcpy(p + d.size() * sizeof(ProjDesc), order.data(), order.size() * sizeof(int32_t));
+}
+
+ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
+  // SVLCOV_PROJ_ORDER=xcd keeps each update's tiles on one XCD
+  static const bool xcd_affine = [] {
+    const char *e = std::getenv("SVLCOV_PROJ_ORDER");
+    return e && std::strcmp(e, "xcd") == 0;
+  }();
   std::stable_sort(d.begin(), d.end(), [](const ProjDesc &a, const ProjDesc &b) {
     return a.fp64 != b.fp64 ? a.fp64 < b.fp64 : a.K < b.K;
   });
-  int64_t tiles = 0;
-  for (size_t q = 0; q < d.size(); ++q) {
-    if (q > 0 && (d[q].fp64 != d[q - 1].fp64 || d[q].K != d[q - 1].K)) tiles = 0;
-    d[q].row0 = tiles;
-    tiles += (d[q].s + PB_RB - 1) / PB_RB;
-  }
-}
-
-void spmm_batch(hipStream_t st, const std::vector<ProjDesc> &d, const ProjDesc *descs_dev) {
+  ProjBatch out;
   size_t g0 = 0;
   while (g0 < d.size()) {
     size_t g1 = g0 + 1;
     while (g1 < d.size() && d[g1].fp64 == d[g0].fp64 && d[g1].K == d[g0].K) ++g1;
-    const ProjDesc &last = d[g1 - 1];
-    const int64_t tiles = last.row0 + (last.s + PB_RB - 1) / PB_RB;
-    const int n = (int)(g1 - g0);
-    const ProjDesc *dd = descs_dev + g0;
-    if (tiles > 0) {
-#define SV_PB(TT, KK) hipLaunchKernelGGL((k_spmm_batch<TT, KK>), dim3((unsigned)tiles), \
-                                         dim3(64 * SP_NW), 0, st, n, dd)
-      if (d[g0].fp64) {
-        switch (d[g0].K) {
-          case 16: SV_PB(double, 16); break;
-          case 32: SV_PB(double, 32); break;
-          case 64: SV_PB(double, 64); break;
-          default: SV_PB(double, 128); break;
-        }
-      } else {
-        switch (d[g0].K) {
-          case 16: SV_PB(float, 16); break;
-          case 32: SV_PB(float, 32); break;
-          case 64: SV_PB(float, 64); break;
-          default: SV_PB(float, 128); break;
-        }
-      }
-#undef SV_PB
+    int64_t tiles = 0;
+    for (size_t q = g0; q < g1; ++q) {
+      d[q].row0 = tiles;
+      tiles += (d[q].s + PB_RB - 1) / PB_RB;
     }
+    if (!xcd_affine) {   // tiles in request order, dealt round-robin over the XCDs
+      out.g_desc.push_back(g0);
+      out.g_order.push_back(out.order.size());
+      for (int64_t u = 0; u < tiles; ++u) out.order.push_back((int32_t)u);
+      g0 = g1;
+      continue;
+    }
+    // estimated cost of one tile of request q: its gathered elements plus the
+    // K x K of W, in units of one gathered element
+    const int K = d[g0].K;
+    std::vector<double> tc(g1 - g0);
+    double total_cost = 0.0;
+    for (size_t q = g0; q < g1; ++q) {
+      const int64_t nt = (d[q].s + PB_RB - 1) / PB_RB;
+      tc[q - g0] = nt > 0 ? (double)d[q].nnz / (double)nt * K + (double)K * K : 0.0;
+      total_cost += tc[q - g0] * (double)nt;
+    }
+    // chunks of at most a quarter of one XCD's share, costliest first, each
+    // to the least loaded XCD (longest-processing-time rule)
+    const double cap = total_cost / (4.0 * SV_XCDS);
+    struct Chunk { int64_t t0, n; double cost; };
+    std::vector<Chunk> ch;
+    for (size_t q = g0; q < g1; ++q) {
+      const int64_t nt = (d[q].s + PB_RB - 1) / PB_RB;
+      const double c1 = tc[q - g0];
+      const int64_t pieces = std::max<int64_t>(
+          1, std::min<int64_t>(nt, (int64_t)std::ceil(c1 * (double)nt / std::max(cap, 1.0))));
+      for (int64_t c = 0; c < pieces; ++c) {
+        const int64_t a = nt * c / pieces, b = nt * (c + 1) / pieces;
+        if (b > a) ch.push_back({d[q].row0 + a, b - a, c1 * (double)(b - a)});
+      }
+    }
+    std::stable_sort(ch.begin(), ch.end(),
+                     [](const Chunk &a, const Chunk &b) { return a.cost > b.cost; });
+    std::vector<std::vector<int32_t>> lists(SV_XCDS);
+    std::vector<double> load(SV_XCDS, 0.0);
+    for (const Chunk &c : ch) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      for (int64_t u = 0; u < c.n; ++u) lists[x].push_back((int32_t)(c.t0 + u));
+      load[x] += c.cost;
+    }
+    size_t len = 0;
+    for (int x = 0; x < SV_XCDS; ++x) len = std::max(len, lists[x].size());
+    out.g_desc.push_back(g0);
+    out.g_order.push_back(out.order.size());
+    const size_t base = out.order.size();
+    out.order.resize(base + len * SV_XCDS, -1);
+    for (int x = 0; x < SV_XCDS; ++x)
+      for (size_t l = 0; l < lists[x].size(); ++l) out.order[base + l * SV_XCDS + x] = lists[x][l];
     g0 = g1;
+  }
+  out.g_desc.push_back(d.size());
+  out.g_order.push_back(out.order.size());
+  out.d = std::move(d);
+  return out;
+}
+
+void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev) {
+  const ProjDesc *descs = (const ProjDesc *)blob_dev;
+  const int32_t *order = (const int32_t *)((const char *)blob_dev + b.d.size() * sizeof(ProjDesc));
+  for (size_t g = 0; g + 1 < b.g_desc.size(); ++g) {
+    const size_t q0 = b.g_desc[g], o0 = b.g_order[g];
+    const size_t blocks = b.g_order[g + 1] - o0;
+    const int n = (int)(b.g_desc[g + 1] - q0);
+    if (blocks == 0 || n == 0) continue;
+    const ProjDesc *dd = descs + q0;
+    const int32_t *oo = order + o0;
+#define SV_PB(TT, KK) hipLaunchKernelGGL((k_spmm_batch<TT, KK>), dim3((unsigned)blocks), \
+                                         dim3(64 * SP_NW), 0, st, n, dd, oo)
+    if (b.d[q0].fp64) {
+      switch (b.d[q0].K) {
+        case 16: SV_PB(double, 16); break;
+        case 32: SV_PB(double, 32); break;
+        case 64: SV_PB(double, 64); break;
+        default: SV_PB(double, 128); break;
+      }
+    } else {
+      switch (b.d[q0].K) {
+        case 16: SV_PB(float, 16); break;
+        case 32: SV_PB(float, 32); break;
+        case 64: SV_PB(float, 64); break;
+        default: SV_PB(float, 128); break;
+      }
+    }
+#undef SV_PB
   }
 }
 

@@ -18,8 +18,8 @@ void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
             float *Cp32, double *rownorm2, const SvDevInfo *info);
 // One projection of a fused batch (k_spmm_batch): C' = E base W and the row
-// norms of E for s rows; row0 is the prefix sum of the batch's tile counts
-// (tiles of spmm_batch_rows_per_block() rows).
+// norms of E for s rows; row0 is the offset of its first tile (tiles of
+// spmm_batch_rows_per_block() rows) within its group.
 struct ProjDesc {
   const int64_t *row_ptr;
   const int32_t *col_idx;
@@ -31,13 +31,25 @@ struct ProjDesc {
   double *rown;
   const SvDevInfo *info;
   int64_t s, row0;
+  int64_t nnz;   // nonzeros of E (host-side balance hint)
   int32_t vdtype, K, fp64, pad;
 };
+// A fused batch as uploaded: the descriptors ordered by (storage type, rank),
+// one group per launch, followed by each group's block-to-tile table (-1 marks
+// an idle block).  The table keeps the tiles of one update on one XCD where
+// the load balance allows it, so the rows of its base are gathered through
+// one L2 instead of all eight.
+struct ProjBatch {
+  std::vector<ProjDesc> d;
+  std::vector<int32_t> order;
+  std::vector<size_t> g_desc, g_order;   // group starts in d and order, plus the ends
+  size_t bytes() const { return d.size() * sizeof(ProjDesc) + order.size() * sizeof(int32_t); }
+  void pack(void *host) const;
+};
 int spmm_batch_rows_per_block();
-// Order a batch by (storage type, rank) and set each row0 to the tile offset
-// within its group; then upload it and launch one kernel per group.
-void spmm_batch_prepare(std::vector<ProjDesc> &d);
-void spmm_batch(hipStream_t st, const std::vector<ProjDesc> &d, const ProjDesc *descs_dev);
+ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d);
+// blob_dev holds pack()'s bytes (device memory).
+void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev);
 // S = E E^T; rid receives the row id of every nonzero (nnz int32 scratch).
 // s <= gram_max_rows().
 int gram_max_rows();

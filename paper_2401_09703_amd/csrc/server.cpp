@@ -109,9 +109,9 @@ struct svlcov_server {
   // fused projections: the server's stream, the descriptor table (pinned
   // staging and device copy) and the timing events of each fused launch
   hipStream_t stream = nullptr;
-  svl::ProjDesc *desc_host = nullptr;
+  char *desc_host = nullptr;   // packed fused batch (pinned staging), bytes
   size_t desc_host_cap = 0;
-  svl::ProjDesc *desc_dev = nullptr;
+  char *desc_dev = nullptr;
   size_t desc_dev_cap = 0;
   hipEvent_t desc_copy_ev = nullptr, proj_ev = nullptr;
   bool desc_copy_live = false;
@@ -192,6 +192,7 @@ void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
       x.info = h->info;
       x.s = s;
       x.row0 = 0;
+      x.nnz = E.nnz;
       x.vdtype = E.val_dtype;
       x.K = h->k;
       x.fp64 = h->prec == SVLCOV_FP64 ? 1 : 0;
@@ -201,34 +202,33 @@ void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
     users.push_back({r, sides});
   }
   if (d.empty()) return;
-  svl::spmm_batch_prepare(d);
-  // the pinned staging table is reused once the previous copy has read it
+  const svl::ProjBatch pb = svl::spmm_batch_prepare(std::move(d));
+  const size_t bytes = pb.bytes();
+  // the pinned staging blob is reused once the previous copy has read it
   if (srv->desc_copy_live) (void)hipEventSynchronize(srv->desc_copy_ev);
-  if (srv->desc_host_cap < d.size()) {
+  if (srv->desc_host_cap < bytes) {
     if (srv->desc_host) (void)hipHostFree(srv->desc_host);
     srv->desc_host = nullptr;
     srv->desc_host_cap = 0;
-    if (hipHostMalloc((void **)&srv->desc_host, d.size() * 2 * sizeof(svl::ProjDesc)) !=
-        hipSuccess) {
+    if (hipHostMalloc((void **)&srv->desc_host, bytes * 2) != hipSuccess) {
       srv->desc_host = nullptr;
       return;
     }
-    srv->desc_host_cap = d.size() * 2;
+    srv->desc_host_cap = bytes * 2;
   }
-  if (srv->desc_dev_cap < d.size()) {
+  if (srv->desc_dev_cap < bytes) {
     if (srv->desc_dev) (void)hipFreeAsync(srv->desc_dev, srv->stream);
     srv->desc_dev = nullptr;
     srv->desc_dev_cap = 0;
-    if (hipMallocAsync((void **)&srv->desc_dev, d.size() * 2 * sizeof(svl::ProjDesc),
-                       srv->stream) != hipSuccess) {
+    if (hipMallocAsync((void **)&srv->desc_dev, bytes * 2, srv->stream) != hipSuccess) {
       srv->desc_dev = nullptr;
       return;
     }
-    srv->desc_dev_cap = d.size() * 2;
+    srv->desc_dev_cap = bytes * 2;
   }
-  std::memcpy(srv->desc_host, d.data(), d.size() * sizeof(svl::ProjDesc));
-  if (hipMemcpyAsync(srv->desc_dev, srv->desc_host, d.size() * sizeof(svl::ProjDesc),
-                     hipMemcpyHostToDevice, srv->stream) != hipSuccess)
+  pb.pack(srv->desc_host);
+  if (hipMemcpyAsync(srv->desc_dev, srv->desc_host, bytes, hipMemcpyHostToDevice,
+                     srv->stream) != hipSuccess)
     return;
   (void)hipEventRecord(srv->desc_copy_ev, srv->stream);
   srv->desc_copy_live = true;
@@ -236,7 +236,7 @@ void fuse_projections(svlcov_server *srv, const std::vector<Req *> &admit) {
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
   if (t0) (void)hipEventRecord(t0, srv->stream);
-  svl::spmm_batch(srv->stream, d, srv->desc_dev);
+  svl::spmm_batch(srv->stream, pb, srv->desc_dev);
   if (hipGetLastError() != hipSuccess) return;   // the updates project on their own
   if (t1) (void)hipEventRecord(t1, srv->stream);
   if (t0 && t1) srv->fused_ev.push_back({t0, t1});
