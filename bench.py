@@ -50,6 +50,8 @@ PHASE_KERNEL = {
     "cholesky": ("k_chol_coop", ["k_coop.hip", "common.hpp"]),
     "spmm_w": ("k_spmm_w", ["k_sparse.hip", "common.hpp"]),
     "kkt_gemm": ("k_gemm_f64", ["k_dense.hip", "common.hpp"]),
+    # one fused projection = one k_spmm_batch dispatch per (storage type, rank)
+    "fused": ("k_spmm_batch", ["k_sparse.hip", "common.hpp", "kernels.hpp"]),
 }
 CALIB_KERNEL = ("neg", "elementwise")   # the copy used to scale the HBM counters
 
@@ -70,6 +72,8 @@ def parse():
     ap.add_argument("--inflight", type=int, default=64, help="stream workload: server slots")
     ap.add_argument("--fused", type=int, default=128,
                     help="stream workload: requests in the fused-projection measurement")
+    ap.add_argument("--fused-only", action="store_true",
+                    help="stream workload: only the fused-projection measurement (for counters)")
     ap.add_argument("--k", type=int, default=0, help="rank of the graph workload (default 64)")
     ap.add_argument("--n-init", type=int, default=90000)
     ap.add_argument("--step-nodes", type=int, default=1000)
@@ -134,7 +138,13 @@ def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
             raise SystemExit(f"no dispatch of a kernel matching {key!r}")
         return vals
 
+    def per_name(tab):
+        # mean per dispatch of every matching kernel; a launch of the phase
+        # is one dispatch of each (the fused projection has one per group)
+        return {n: sum(vs) / len(vs) for n, vs in tab.items() if prefix in n}
+
     f_k, w_k = pick(fe, prefix), pick(wr, prefix)
+    f_n, w_n = per_name(fe), per_name(wr)
     calib_kib = calib_mib * 1024.0
     def pick_calib(tab):
         for key in CALIB_KERNEL:
@@ -145,15 +155,17 @@ def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
 
     f_c, w_c = pick_calib(fe), pick_calib(wr)
     ff, wf = calib_kib / f_c, calib_kib / w_c
-    fetch = sum(f_k) / len(f_k) * 1024 * ff
-    write = sum(w_k) / len(w_k) * 1024 * wf
+    fetch = sum(f_n.values()) * 1024 * ff
+    write = sum(w_n.values()) * 1024 * wf
     print(f"phase: {phase}")
     print(f"kernel: {prefix}")
     print(f"sources_sha256: {sources_sha(files)}")
     print(f"dispatches_fetch: {len(f_k)}")
     print(f"dispatches_write: {len(w_k)}")
-    print(f"fetch_kib_per_dispatch_raw: {sum(f_k) / len(f_k):.1f}")
-    print(f"write_kib_per_dispatch_raw: {sum(w_k) / len(w_k):.1f}")
+    for n in sorted(f_n):
+        print(f"# {n[:100]}: fetch {f_n[n]:.1f} KiB, write {w_n.get(n, 0.0):.1f} KiB per dispatch (raw)")
+    print(f"fetch_kib_per_launch_raw: {sum(f_n.values()):.1f}")
+    print(f"write_kib_per_launch_raw: {sum(w_n.values()):.1f}")
     print(f"calibration_copy_mib: {calib_mib}")
     print(f"calibration_fetch_kib: {f_c:.1f}")
     print(f"calibration_write_kib: {w_c:.1f}")
@@ -350,6 +362,11 @@ def run_stream(args):
             fused = measure_fused_projection(L, torch, np, states, mats, reqs, dev_reqs,
                                              args.fused)
             log(f"[bench] fused projection: {fused}")
+            if args.fused_only:
+                for st in states:
+                    st.close()
+                print(json.dumps({"fused_projection": fused}), flush=True)
+                return
         srv = L.Server(max_inflight=slots, workspace_budget=32 << 30)
         ids = [srv.attach(st) for st in states]
         torch.cuda.synchronize()
@@ -375,7 +392,8 @@ def run_stream(args):
     fused_roof = None
     if args.fused > 0:
         fused_roof = dict(kernel="k_spmm_batch", bound="hbm", achieved=fused["achieved_GBs"],
-                          peak=HBM_PEAK_GBS, unit="GB/s", frac=fused["frac"], traffic=None,
+                          peak=HBM_PEAK_GBS, unit="GB/s", frac=fused["frac"],
+                          traffic=stored_traffic("fused"),
                           requests=fused["requests"], bytes=fused["bytes"],
                           avg_ms=fused["ms"])
     out = {
@@ -417,15 +435,15 @@ def main():
     import paper_2401_09703_amd as L
 
     assert torch.cuda.is_available(), "no GPU"
-    if args.workload == "stream":
-        run_stream(args)
-        return
     if args.copy_calib_mib > 0:
         x = torch.ones(args.copy_calib_mib * (1 << 18), dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         torch.neg(x, out=y)
         torch.cuda.synchronize()
         del x, y
+    if args.workload == "stream":
+        run_stream(args)
+        return
     W, K = args.warmup, args.steps
     t = time.time()
     wl = build_workload(args, W, K)

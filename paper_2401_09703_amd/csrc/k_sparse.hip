@@ -487,10 +487,10 @@ void ProjBatch::pack(void *host) const {
 }
 
 ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
-  // SVLCOV_PROJ_ORDER=xcd keeps each update's tiles on one XCD
+  // XCD-affine by default; SVLCOV_PROJ_ORDER=rr deals the tiles round-robin
   static const bool xcd_affine = [] {
     const char *e = std::getenv("SVLCOV_PROJ_ORDER");
-    return e && std::strcmp(e, "xcd") == 0;
+    return !(e && std::strcmp(e, "rr") == 0);
   }();
   std::stable_sort(d.begin(), d.end(), [](const ProjDesc &a, const ProjDesc &b) {
     return a.fp64 != b.fp64 ? a.fp64 < b.fp64 : a.K < b.K;
