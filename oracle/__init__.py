@@ -14,6 +14,10 @@ Contents
   svlcov      O2: the paper's own method as written, on the CPU: SV-LCOV
               modified Gram-Schmidt (Algorithm 2) and the extended
               decomposition (Section 3.2) driven by Algorithms 3, 4 and 11.
+  approx      O3: the -GKL and -RPI variants (the appendix on approximating
+              the augmented space): an l-dimensional basis of a Krylov or
+              power-iteration subspace of the augmented matrix in place of its
+              QR, then the Zha-Simon rotation with K of k + l columns.
   metrics     comparison metrics (singular values, principal angles,
               orthonormality, spectral-gap prefix).
 
