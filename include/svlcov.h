@@ -136,6 +136,43 @@ svlcov_status svlcov_add_cols(svlcov_state *h, const svlcov_csr *E_c_T);
 svlcov_status svlcov_update_weights(svlcov_state *h, const svlcov_csr *D_T,
                                     const svlcov_csr *E_m_T);
 
+/* The -GKL and -RPI variants (the appendix on approximating the augmented
+ * space; the variants paragraph of Section 4).  The augmented matrix
+ * Z = (I - V V^T) E_r^T (rows) or (I - U U^T) E_c (columns) is replaced by
+ * an l-dimensional orthonormal basis Q of a subspace of its range together
+ * with P = Z^T Q, so that the Rayleigh-Ritz problem has k + l columns on that
+ * side instead of k + s; everything else is the update of svlcov_add_rows /
+ * svlcov_add_cols.  Q never exists: it is kept as coefficients Y (q = Z y)
+ * and every product with Z or Z^T goes through the residual Gram Z^T Z.
+ *   method  SVLCOV_APPROX_GKL: Golub-Kahan-Lanczos from the start vector p_1
+ *           (start: s doubles of nonzero norm, normalised here; NULL = all
+ *           ones), every new p orthogonalised against all previous ones; a
+ *           coefficient whose square falls to rank_tol times the largest
+ *           squared row norm of the update stops the process (the rest of
+ *           the basis is zero).
+ *           SVLCOV_APPROX_RPI: t rounds of P <- orth(P), Q <- orth(Z P),
+ *           P <- Z^T Q from the start P_0 (start: l vectors of s doubles,
+ *           vector j at start[j * s]; required); directions whose pivot
+ *           falls to the same threshold are dropped.
+ *   l       1 <= l <= 64, clamped to s; RPI reads min(l, s) start vectors.
+ *   t       RPI rounds, 1 <= t <= 16 (ignored by GKL).
+ *   start_on_device  0: host memory (read before the call returns),
+ *           1: device memory of the state (valid until the next sync).
+ * Errors as for svlcov_add_rows, and SVLCOV_E_INVALID for a bad method, l,
+ * t or a missing RPI start; SVLCOV_E_NUMERIC for a non-finite host start. */
+typedef enum { SVLCOV_APPROX_GKL = 1, SVLCOV_APPROX_RPI = 2 } svlcov_approx_method;
+typedef struct {
+  int32_t method;            /* svlcov_approx_method                          */
+  int32_t l;                 /* dimension of the approximate space            */
+  int32_t t;                 /* RPI rounds                                    */
+  int32_t start_on_device;   /* 0 host, 1 device                              */
+  const double *start;       /* p_1 (GKL, may be NULL) or P_0 (RPI)           */
+} svlcov_approx;
+svlcov_status svlcov_add_rows_approx(svlcov_state *h, const svlcov_csr *E_r,
+                                     const svlcov_approx *a);
+svlcov_status svlcov_add_cols_approx(svlcov_state *h, const svlcov_csr *E_c_T,
+                                     const svlcov_approx *a);
+
 /* Realise and return the factors U = U_base W_U (m x k), sigma (k) and
  * V = V_base W_V (n x k).  Any output pointer may be NULL; m, n, k receive the
  * current shape when non-NULL.  out_dtype selects float or double outputs,

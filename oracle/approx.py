@@ -21,7 +21,9 @@ Readings where the paper is silent (listed in the design notes):
     rtol * (largest row norm of the update) or below, that coefficient is set
     to zero and every later q, p, alpha, beta is zero.
   * RPI's QR of Z P keeps a direction iff its pivot exceeds the same threshold
-    (Householder with column pivoting); dropped directions leave zero columns.
+    (Householder with column pivoting); the QR of P keeps a direction iff its
+    pivot exceeds rtol times the largest; dropped directions leave zero
+    columns.
   * The start vectors are inputs: GKL's p_1 (normalised here; all ones when
     none is given) and RPI's P_0 are drawn by the caller.
 
@@ -108,7 +110,13 @@ def rpi(Z, l, t, P0, scale=None, rtol=RANK_RTOL):
     Y = np.zeros((s, l))
     r = 0
     for _ in range(t):
-        P, _r = np.linalg.qr(P)
+        # P <- QR(P); a direction whose pivot falls to rtol times the largest
+        # one is dropped (zero column), so a rank-deficient Z^T Q stays so
+        Qp, Rp, _pv = sla.qr(P, mode="economic", pivoting=True)
+        dp = np.abs(np.diag(Rp))
+        rp = int(np.sum(dp > rtol * dp.max())) if dp.size and dp.max() > 0 else 0
+        P = np.zeros_like(P)
+        P[:, :rp] = Qp[:, :rp]
         X = Z @ P
         Qf, R, piv = sla.qr(X, mode="economic", pivoting=True)
         d = np.abs(np.diag(R))

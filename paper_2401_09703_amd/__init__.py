@@ -58,6 +58,44 @@ class _Stats(C.Structure):
                 ("last_min_kept_pivot", C.c_double), ("last_max_dropped_pivot", C.c_double)]
 
 
+class _Approx(C.Structure):
+    _fields_ = [("method", C.c_int32), ("l", C.c_int32), ("t", C.c_int32),
+                ("start_on_device", C.c_int32), ("start", C.c_void_p)]
+
+
+class Approx:
+    """The -GKL / -RPI variant of an append (svlcov_add_rows_approx /
+    svlcov_add_cols_approx): method "gkl" or "rpi", dimension l, RPI rounds t,
+    and the start (GKL: p_1 of s values or None for all ones; RPI: an s x l
+    array whose columns are P_0), a host array or a device tensor."""
+
+    METHODS = {"gkl": 1, "rpi": 2}
+
+    def __init__(self, method: str = "gkl", l: int = 10, t: int = 3, start=None):
+        if method not in self.METHODS:
+            raise ValueError(method)
+        self.method, self.l, self.t, self.start = method, int(l), int(t), start
+
+    def _struct(self, keep: list) -> "_Approx":
+        st = _Approx(self.METHODS[self.method], self.l, self.t, 0, None)
+        x = self.start
+        if x is None:
+            return st
+        if _is_torch(x):
+            import torch
+            v = x.detach().to(torch.float64)
+            v = (v.t() if v.dim() == 2 else v).contiguous()   # RPI: vector j at j*s
+            keep.append(v)
+            st.start_on_device = 1 if v.is_cuda else 0
+            st.start = v.data_ptr()
+        else:
+            v = np.asarray(x, dtype=np.float64)
+            v = np.ascontiguousarray(v.T if v.ndim == 2 else v)
+            keep.append(v)
+            st.start = v.ctypes.data
+        return st
+
+
 class _ServerOptions(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_inflight", C.c_int32),
                 ("workspace_budget", C.c_int64)]
@@ -77,7 +115,8 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_sym_eig_topk", "svlcov_server_default_options", "svlcov_server_create",
            "svlcov_server_attach", "svlcov_server_submit", "svlcov_server_wait",
            "svlcov_server_poll", "svlcov_server_drain", "svlcov_server_get_stats",
-           "svlcov_server_destroy", "svlcov_project_batch"]
+           "svlcov_server_destroy", "svlcov_project_batch", "svlcov_add_rows_approx",
+           "svlcov_add_cols_approx"]
 NUM_PHASES = 16
 
 
@@ -92,6 +131,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_add_rows.argtypes = [P, C.POINTER(_Csr)]
     lib.svlcov_add_cols.argtypes = [P, C.POINTER(_Csr)]
     lib.svlcov_update_weights.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Csr)]
+    lib.svlcov_add_rows_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Approx)]
+    lib.svlcov_add_cols_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Approx)]
     lib.svlcov_get_factors.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), I32,
                                        I32, P, P, P]
     lib.svlcov_query_row.argtypes = [P, I32, I64, P]
@@ -245,13 +286,23 @@ class TruncatedSVD:
         self._keep = []
 
     # -- updates (asynchronous; inputs must stay alive until sync)
-    def add_rows(self, E):
+    def add_rows(self, E, approx: "Approx" = None):
         st = _csr_struct(E, self._keep)
-        _check(_lib.svlcov_add_rows(self._h, C.byref(st)), "svlcov_add_rows")
+        if approx is None:
+            _check(_lib.svlcov_add_rows(self._h, C.byref(st)), "svlcov_add_rows")
+        else:
+            a = approx._struct(self._keep)
+            _check(_lib.svlcov_add_rows_approx(self._h, C.byref(st), C.byref(a)),
+                   "svlcov_add_rows_approx")
 
-    def add_cols(self, Ec_T):
+    def add_cols(self, Ec_T, approx: "Approx" = None):
         st = _csr_struct(Ec_T, self._keep)
-        _check(_lib.svlcov_add_cols(self._h, C.byref(st)), "svlcov_add_cols")
+        if approx is None:
+            _check(_lib.svlcov_add_cols(self._h, C.byref(st)), "svlcov_add_cols")
+        else:
+            a = approx._struct(self._keep)
+            _check(_lib.svlcov_add_cols_approx(self._h, C.byref(st), C.byref(a)),
+                   "svlcov_add_cols_approx")
 
     def update_weights(self, D_T, Em_T):
         a = _csr_struct(D_T, self._keep)
@@ -259,13 +310,15 @@ class TruncatedSVD:
         _check(_lib.svlcov_update_weights(self._h, C.byref(a), C.byref(b)),
                "svlcov_update_weights")
 
-    def apply(self, update):
+    def apply(self, update, approx: "Approx" = None):
         kind = update[0]
         if kind == "rows":
-            self.add_rows(update[1])
+            self.add_rows(update[1], approx)
         elif kind == "cols":
-            self.add_cols(update[1])
+            self.add_cols(update[1], approx)
         elif kind == "weights":
+            if approx is not None:
+                raise NotImplementedError("the variants are built for the append forms")
             self.update_weights(update[1], update[2])
         else:
             raise ValueError(kind)
@@ -436,5 +489,5 @@ class Server:
             pass
 
 
-__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "project_batch", "load_library", "LIB_PATH", "EXPORTS",
+__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "project_batch", "Approx", "load_library", "LIB_PATH", "EXPORTS",
            "FP64", "FP32", "BF16X3"]

@@ -286,7 +286,8 @@ namespace {
 // Cholesky (Algorithm 2 realised as R^T R = E E^T - (E V)(E V)^T, Lemma 3).
 template <typename T>
 void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
-                   float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which) {
+                   float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which,
+                   bool chol = true) {
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
@@ -306,8 +307,9 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
     else
       svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
   }
-  PhaseScope ps(h, PH_CHOL);
   svl::max_into(st, s, rown, h->info, which);
+  if (!chol) return;   // the approximate variants use the Gram itself
+  PhaseScope ps(h, PH_CHOL);
   coop_enter(h);
   const int crc = svl::cholesky_coop(st, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags,
                                      &h->epoch);
@@ -375,6 +377,21 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
   return SVLCOV_OK;
 }
 
+// Wnew = W (X[:k] - Cp^T Y), its inverse and condition (X by rows, K x N).
+void sparse_side_small(svlcov_state *h, int64_t s, int64_t N, const double *Xv,
+                       const double *Cp64, const double *W, const double *Y, double *T1,
+                       double *Wnew, double *Winv, int32_t *flag, int side, double *gws,
+                       size_t gws_len) {
+  const int K = h->k;
+  hipStream_t st = h->stream;
+  PhaseScope ps(h, PH_SMALL);
+  svl::copy_strided(st, K, K, Xv, 1, N, T1, K, h->info);
+  svl::gemm_f64_sk(st, true, false, K, K, s, -1.0, Cp64, K, Y, K, 1.0, T1, K, gws, gws_len,
+                   h->info);
+  svl::gemm_f64(st, false, false, K, K, K, 1.0, W, K, T1, K, 0.0, Wnew, K, h->info);
+  svl::inverse_cond(st, K, Wnew, Winv, flag, h->cond_reset, h->info, side);
+}
+
 // The sparse-side factor update (Equation (1)): Y = T X[k:] with T = L^{-T}
 // (the normalisation of Algorithm 2), Wnew = W (X[:k] - C_n X[k:]) with
 // C_n X[k:] = Cp^T Y.  X is given by rows (Xv, K x N).
@@ -395,12 +412,7 @@ void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, c
       svl::set_status(st, h->info, SVLCOV_E_DEVICE);
     }
   }
-  PhaseScope ps(h, PH_SMALL);
-  svl::copy_strided(st, K, K, Xv, 1, N, T1, K, h->info);
-  svl::gemm_f64_sk(st, true, false, K, K, s, -1.0, Cp64, K, Y, K, 1.0, T1, K, gws, gws_len,
-                   h->info);
-  svl::gemm_f64(st, false, false, K, K, K, 1.0, W, K, T1, K, 0.0, Wnew, K, h->info);
-  svl::inverse_cond(st, K, Wnew, Winv, flag, h->cond_reset, h->info, side);
+  sparse_side_small(h, s, N, Xv, Cp64, W, Y, T1, Wnew, Winv, flag, side, gws, gws_len);
 }
 
 template <typename T>
@@ -536,6 +548,218 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   // commit: sparse side
   sparse_side_commit<T>(h, dE, nB, B_base, Y, Mupd, WnB, WiB, flags + 1, W_B, nullptr, nullptr,
                         sideB);
+  svl::op_end(st, h->info);
+  if (rows_form) h->m += s; else h->n += s;
+  if (h->launch_failed) {
+    h->launch_failed = false;
+    return SVLCOV_E_DEVICE;
+  }
+  return SVLCOV_OK;
+}
+
+// The -GKL / -RPI variants of the row-append form (the appendix's variants
+// with an approximate augmented space): the projection and the residual Gram
+// G = Z^T Z are those of the exact path; an l-dimensional basis Q = Z Y of a
+// Krylov (GKL) or power-iteration (RPI) subspace of range(Z) and P = Z^T Q
+// replace the Cholesky factor, so K = [[Sigma, 0], [E V, P]] is (k+s) x (k+l)
+// and its Rayleigh-Ritz SVD is taken through the eigenpairs of K^T K
+// ((k+l) square): G from them, F = K G diag(theta)^{-1}.  The sparse side's
+// rotation uses Y G[k:] where the exact path uses T G[k:].
+template <typename T>
+svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_form,
+                               const svlcov_approx *ap) {
+  svlcov_status r = check_csr_header(E);
+  if (r != SVLCOV_OK) return r;
+  if (!ap || (ap->method != SVLCOV_APPROX_GKL && ap->method != SVLCOV_APPROX_RPI) ||
+      ap->l < 1 || ap->l > svl::AP_LMAX)
+    return SVLCOV_E_INVALID;
+  if (ap->method == SVLCOV_APPROX_RPI && (!ap->start || ap->t < 1 || ap->t > 16))
+    return SVLCOV_E_INVALID;
+  const int K = h->k;
+  const int64_t s = E->rows;
+  const int64_t nB = rows_form ? h->n : h->m;
+  const int64_t nA = rows_form ? h->m : h->n;
+  if (E->cols != nB) return SVLCOV_E_SHAPE;
+  if (s == 0) return SVLCOV_OK;
+  const int l = (int)(ap->l < s ? ap->l : s);
+  const int64_t N = K + s, N2 = K + l;
+  if (N2 > svl::eig_max_n() || s > svl::gram_max_rows()) return SVLCOV_E_UNSUPPORTED;
+  if (!E->on_device) {
+    r = check_host_csr(E);
+    if (r != SVLCOV_OK) return r;
+  }
+  const bool gkl = ap->method == SVLCOV_APPROX_GKL;
+  void **Abase = rows_form ? &h->Ubase : &h->Vbase;
+  int64_t *Acap = rows_form ? &h->capU : &h->capV;
+  r = grow_base(h, Abase, Acap, nA, nA + s);
+  if (r != SVLCOV_OK) return r;
+  T *A_base = (T *)*Abase;
+  T *B_base = (T *)(rows_form ? h->Vbase : h->Ubase);
+  double *W_A = rows_form ? h->WU : h->WV;
+  double *W_B = rows_form ? h->WV : h->WU;
+  const int sideA = rows_form ? 0 : 1, sideB = 1 - sideA;
+  struct Bufs {
+    double *Cp64, *rown, *Gm, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA, *WiA,
+        *WnB, *WiB, *Mupd, *orthw, *Pv, *Yc, *gv, *ab, *Xl, *Tl, *Gm2, *Om;
+    float *Cp32;
+    int32_t *complete, *flags, *rid, *brk;
+  } b;
+  auto layout = [&](Carver &cv) {
+    b.Cp64 = cv.take<double>(s * K);
+    b.Cp32 = cv.take<float>(s * K);
+    b.rown = cv.take<double>(s);
+    b.Gm = cv.take<double>(s * s);
+    b.Kmat = cv.take<double>(N * N2);
+    b.Mmat = cv.take<double>(N2 * N2);
+    b.lam = cv.take<double>(K);
+    b.theta = cv.take<double>(K);
+    b.complete = cv.take<int32_t>(K);
+    b.Fv = cv.take<double>(K * N);
+    b.Gv = cv.take<double>(K * N2);
+    b.eigw = cv.take<double>(svl::eig_work_doubles(N2, K));
+    b.Y = cv.take<double>(s * K);
+    b.T1 = cv.take<double>(K * K);
+    b.WnA = cv.take<double>(K * K);
+    b.WiA = cv.take<double>(K * K);
+    b.WnB = cv.take<double>(K * K);
+    b.WiB = cv.take<double>(K * K);
+    b.Mupd = cv.take<double>(s * K);
+    b.flags = cv.take<int32_t>(2);
+    b.orthw = cv.take<double>(2 * K * K + 9 * K * N);
+    b.rid = cv.take<int32_t>(E->nnz > 0 ? E->nnz : 1);
+    b.Pv = cv.take<double>((int64_t)(l + 1) * s);
+    b.Yc = cv.take<double>((int64_t)l * s);
+    b.gv = cv.take<double>(s);
+    b.ab = cv.take<double>(2 * svl::AP_LMAX);
+    b.brk = cv.take<int32_t>(1);
+    b.Xl = cv.take<double>((int64_t)l * s);
+    b.Tl = cv.take<double>((int64_t)l * s);
+    b.Gm2 = cv.take<double>((int64_t)l * l);
+    b.Om = cv.take<double>((int64_t)l * l);
+  };
+  Carver c{nullptr};
+  layout(c);
+  r = ensure(h, h->ws, c.off);
+  if (r != SVLCOV_OK) return r;
+  r = ensure(h, h->stage, csr_stage_bytes(E) + 256);
+  if (r != SVLCOV_OK) return r;
+  Carver c2{(char *)h->ws.p};
+  layout(c2);
+  char *cursor = (char *)h->stage.p;
+  DevCsr dE;
+  r = to_device(h, E, cursor, &dE);
+  if (r != SVLCOV_OK) return r;
+  hipStream_t st = h->stream;
+  // the start vectors: GKL's p_1 into gv (read once by the first step), RPI's
+  // P_0 into the rows of Pv that the iteration overwrites
+  if (ap->start) {
+    const hipMemcpyKind kind = ap->start_on_device ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyHostToDevice;
+    double *dst = gkl ? b.gv : b.Pv;
+    const size_t bytes = (size_t)(gkl ? s : (int64_t)l * s) * sizeof(double);
+    if (!ap->start_on_device) {
+      for (int64_t e = 0; e < (int64_t)(bytes / 8); ++e)
+        if (!std::isfinite(ap->start[e])) return SVLCOV_E_NUMERIC;
+    }
+    SV_TRY(hipMemcpyAsync(dst, ap->start, bytes, kind, st));
+  }
+
+  h->seq += 1;
+  h->history.push_back({h->seq, h->m, h->n});
+  if (E->on_device && h->validate) {
+    PhaseScope ps(h, PH_VALIDATE);
+    svl::validate_csr(st, dE.rows, dE.cols, dE.nnz, dE.rp, dE.ci, dE.v, dE.vdt, h->info, h->seq);
+  }
+  svl::op_begin(st, h->info, 0);
+  orthogonalise<T>(h, dE, B_base, W_B, b.Cp64, b.Cp32, b.rown, b.Gm, nullptr, b.rid, 0, false);
+  double *gws = b.orthw + 2 * K * K + K * N;
+  const size_t gws_len = (size_t)8 * K * N;
+  {
+    PhaseScope ps(h, PH_CHOL);   // the basis takes the Cholesky's place
+    svl::sym_lower(st, s, b.Gm, s, h->info);
+    if (gkl) {
+      svl::gkl_basis(st, s, l, b.Gm, s, ap->start ? b.gv : nullptr, b.Pv, b.Yc, b.gv, b.ab,
+                     b.brk, h->rank_tol, h->info);
+    } else {
+      svl::rpi_basis(st, s, l, ap->t, b.Gm, s, b.Pv, b.Yc, b.Xl, b.Tl, b.Gm2, b.Om, gws,
+                     gws_len, h->rank_tol, h->info);
+    }
+  }
+  {
+    PhaseScope ps(h, PH_BUILDK);
+    svl::build_K_approx(st, K, s, l, h->sigma, b.Cp64, b.Kmat, h->info);
+    if (gkl)
+      svl::gkl_pblock(st, s, l, b.Pv, b.ab, b.Kmat, N2, K, K, h->info);
+    else
+      svl::rows_to_block(st, s, l, b.Pv, b.Kmat, N2, K, K, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_KKT);
+    svl::gemm_f64_sk(st, true, false, N2, N2, N, 1.0, b.Kmat, N2, b.Kmat, N2, 0.0, b.Mmat, N2,
+                     gws, gws_len, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_TRIDIAG);
+    coop_enter(h);
+    const int trc = svl::eig_tridiag(st, N2, b.Mmat, b.eigw, h->flags, &h->epoch, h->info);
+    coop_exit(h);
+    if (trc != 0) {
+      h->launch_failed = true;
+      svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+    }
+  }
+  {
+    PhaseScope ps(h, PH_BISECT);
+    svl::eig_bisect(st, N2, K, b.lam, b.eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_STEIN);
+    svl::eig_stein(st, N2, K, b.lam, b.Gv, b.eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_BACK);
+    svl::eig_back(st, N2, K, b.Mmat, b.Gv, b.eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_RECOVER);   // F = K G diag(theta)^{-1}
+    svl::gemm_f64(st, false, true, K, N, N2, 1.0, b.Gv, N2, b.Kmat, N2, 0.0, b.Fv, N, h->info);
+    svl::theta_scale(st, K, b.lam, b.theta, b.Fv, N, b.complete, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_ORTH);
+    double *gram_kk = b.orthw, *linv_kk = b.orthw + K * K, *xtmp = b.orthw + 2 * K * K;
+    svl::orthonormalize_rows(st, K, N, b.Fv, b.complete, (uint64_t)h->seq * 2 + 1, gram_kk,
+                             linv_kk, xtmp, gws, gws_len, h->info);
+    svl::orthonormalize_rows(st, K, N2, b.Gv, nullptr, (uint64_t)h->seq * 2 + 2, gram_kk,
+                             linv_kk, xtmp, gws, gws_len, h->info);
+    svl::check_finite(st, K, b.theta, h->info, h->seq);
+  }
+  {
+    PhaseScope ps(h, PH_SMALL);
+    svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, b.Fv, N, 0.0, b.WnA, K, h->info);
+    svl::inverse_cond(st, K, b.WnA, b.WiA, b.flags, h->cond_reset, h->info, sideA);
+  }
+  {
+    PhaseScope ps(h, PH_TRSM);   // Y G[k:] in place of T G[k:]
+    svl::gemm_f64(st, true, true, s, K, l, 1.0, b.Yc, s, b.Gv + K, N2, 0.0, b.Y, K, h->info);
+  }
+  sparse_side_small(h, s, N2, b.Gv, b.Cp64, W_B, b.Y, b.T1, b.WnB, b.WiB, b.flags + 1, sideB,
+                    gws, gws_len);
+  svl::check_finite(st, K * K, b.WnB, h->info, h->seq);
+  svl::check_finite(st, K * K, b.WnA, h->info, h->seq);
+  if (hipGetLastError() != hipSuccess) {
+    h->launch_failed = true;
+    svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+  }
+  const int mode = mode_of(h->prec);
+  {
+    PhaseScope ps(h, PH_COMMIT);
+    svl::realise<T, T>(st, mode, K, nA, A_base, b.WnA, A_base, b.flags, h->info);
+    svl::append_rows<T>(st, K, s, b.Fv + K, 1, N, b.WiA, b.flags, A_base + nA * K, h->info);
+    svl::commit_small(st, K, b.WnA, b.flags, W_A, b.theta, h->sigma, h->info, sideA);
+  }
+  sparse_side_commit<T>(h, dE, nB, B_base, b.Y, b.Mupd, b.WnB, b.WiB, b.flags + 1, W_B, nullptr,
+                        nullptr, sideB);
   svl::op_end(st, h->info);
   if (rows_form) h->m += s; else h->n += s;
   if (h->launch_failed) {
@@ -814,6 +1038,28 @@ svlcov_status svlcov_add_cols(svlcov_state *h, const svlcov_csr *E) {
   if (!g.ok) return SVLCOV_E_BUSY;
   if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
   const svlcov_status r = h->prec == SVLCOV_FP64 ? op_append<double>(h, E, false) : op_append<float>(h, E, false);
+  h->proj_ready[0] = h->proj_ready[1] = false;
+  return r;
+}
+
+svlcov_status svlcov_add_rows_approx(svlcov_state *h, const svlcov_csr *E, const svlcov_approx *a) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  const svlcov_status r = h->prec == SVLCOV_FP64 ? op_append_approx<double>(h, E, true, a)
+                                                 : op_append_approx<float>(h, E, true, a);
+  h->proj_ready[0] = h->proj_ready[1] = false;
+  return r;
+}
+
+svlcov_status svlcov_add_cols_approx(svlcov_state *h, const svlcov_csr *E, const svlcov_approx *a) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  const svlcov_status r = h->prec == SVLCOV_FP64 ? op_append_approx<double>(h, E, false, a)
+                                                 : op_append_approx<float>(h, E, false, a);
   h->proj_ready[0] = h->proj_ready[1] = false;
   return r;
 }

@@ -135,6 +135,39 @@ void fill_identity(hipStream_t st, int K, double *W);
 void op_begin(hipStream_t st, SvDevInfo *info, int two_sided);
 void op_end(hipStream_t st, SvDevInfo *info);
 
+// ---- approximate augmented space (k_approx.hip): the -GKL / -RPI variants
+constexpr int AP_LMAX = 64;   // largest dimension l of the approximate space
+// Copy the lower triangle of the symmetric s x s G onto its strict upper one.
+void sym_lower(hipStream_t st, int64_t s, double *G, int64_t ld, const SvDevInfo *info);
+// Y[j] = G X[j] for the nv rows of X and Y (s each); a no-op once *brk != 0.
+void symv_rows(hipStream_t st, int64_t s, int nv, const double *G, int64_t ld, const double *X,
+               double *Y, const int32_t *brk, const SvDevInfo *info);
+// GKL in coefficient space on G = Z^T Z: Pv ((l+1) x s) the p vectors, Yc
+// (l x s) the coefficients of q_i = Z y_i, ab alpha (AP_LMAX) then beta
+// (AP_LMAX); g (s) scratch; start (s, device) or NULL for all ones.
+void gkl_basis(hipStream_t st, int64_t s, int l, const double *G, int64_t ld,
+               const double *start, double *Pv, double *Yc, double *g, double *ab,
+               int32_t *brk, double rtol, SvDevInfo *info);
+// Kout[row0 + t][col0 + i] = alpha_i Pv[i][t] + beta_i Pv[i+1][t].
+void gkl_pblock(hipStream_t st, int64_t s, int l, const double *Pv, const double *ab,
+                double *Kout, int64_t ldk, int64_t row0, int64_t col0, const SvDevInfo *info);
+// Kout[row0 + t][col0 + i] = X[i][t] (X: l rows of s).
+void rows_to_block(hipStream_t st, int64_t s, int l, const double *X, double *Kout, int64_t ldk,
+                   int64_t row0, int64_t col0, const SvDevInfo *info);
+// Kout ((K+s) x (K+l)) = [[diag(sig), 0], [Cp, 0]].
+void build_K_approx(hipStream_t st, int K, int64_t s, int l, const double *sig, const double *Cp,
+                    double *Kout, const SvDevInfo *info);
+// Pivoted Cholesky of an l x l Gram with dropping (pivot <= rtol * scale of
+// E, or rtol * the largest diagonal when rel); Out (l x l) maps the Gram's
+// vectors to orthonormal ones (zero rows for dropped directions).
+void pchol_small(hipStream_t st, int l, const double *A, double *Out, double rtol, int rel,
+                 const SvDevInfo *info);
+// RPI in coefficient space: t rounds from the rows of P (l x s, overwritten
+// with Z^T Q); Yc receives the coefficients of Q.
+void rpi_basis(hipStream_t st, int64_t s, int l, int t, const double *G, int64_t ld, double *P,
+               double *Yc, double *X, double *T, double *Gm2, double *Om, double *ws,
+               size_t ws_len, double rtol, const SvDevInfo *info);
+
 // ---- eigen (k_eig.hip)
 // Top-k eigenpairs of a symmetric N x N FP64 matrix (A is destroyed):
 // lam[0..k) descending, Fv (k x N) row j = eigenvector of lam[j].
