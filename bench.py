@@ -79,6 +79,11 @@ def parse():
     ap.add_argument("--step-nodes", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="", help="precision modes (default per workload)")
+    ap.add_argument("--approx", default="gkl,rpi",
+                    help="-GKL / -RPI variants timed beside the exact path on the append "
+                         "workloads ('none' to skip)")
+    ap.add_argument("--approx-l", type=int, default=10, help="dimension l of the variants")
+    ap.add_argument("--approx-t", type=int, default=3, help="RPI rounds t")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy (y = -x, FP32) of this many MiB first; "
                          "its HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
@@ -456,13 +461,35 @@ def main():
     capU, capV = wl["cap"]
     modes = (args.modes or wl["modes"]).split(",")
 
+    # the -GKL / -RPI variants (append workloads only) run as extra paths in
+    # the headline precision; their start vectors are drawn per update, seeded,
+    # and resident on the device before the timed region
+    methods = [] if args.approx in ("", "none") or any(u[0] == "weights" for u in ups) \
+        else args.approx.split(",")
+    head_mode = "bf16x3" if "bf16x3" in modes else modes[0]
+    la, ta = args.approx_l, args.approx_t
+    srng = np.random.default_rng(2401_09703)
+    starts = {}
+    for meth in methods:
+        hs = []
+        for up in ups:
+            sj = up[1].rows
+            hs.append(srng.standard_normal(sj) if meth == "gkl"
+                      else srng.standard_normal((sj, min(la, sj))))
+        starts[meth] = (hs, [torch.tensor(x, device="cuda") for x in hs])
+    paths = [(m, None) for m in modes] + [(head_mode, meth) for meth in methods]
+
+    def approx_of(meth, j):
+        return None if meth is None else L.Approx(meth, la, ta, starts[meth][1][j])
+
     results = {}
-    for mode in modes:
+    for mode, meth in paths:
+        name = mode if meth is None else f"{mode}+{meth}"
         svd = L.TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision=mode,
                              row_capacity=capU, col_capacity=capV, validate_device_inputs=False)
         stream = torch.cuda.ExternalStream(svd.stream)
         for j in range(P * W):
-            svd.apply(dev_ups[j])
+            svd.apply(dev_ups[j], approx_of(meth, j))
         svd.sync()
         svd.profile(True)
         svd.phase_times()
@@ -471,7 +498,7 @@ def main():
         t0 = time.perf_counter()
         evs[0].record(stream)
         for j in range(P * W, P * (W + K)):
-            svd.apply(dev_ups[j])
+            svd.apply(dev_ups[j], approx_of(meth, j))
             evs[j - P * W + 1].record(stream)
         svd.sync()
         torch.cuda.synchronize()
@@ -482,13 +509,14 @@ def main():
         st = svd.stats()
         svd.close()
         elapsed = t1 - t0
-        results[mode] = dict(rows_per_s=wl["rows_per_step"] * K / elapsed,
+        results[name] = dict(rows_per_s=wl["rows_per_step"] * K / elapsed,
                              ms_per_step=1e3 * elapsed / K,
                              p50_ms=float(np.percentile(lat, 50)),
-                             p99_ms=float(np.percentile(lat, 99)), phases=phases, stats=st)
-        log(f"[bench] {mode}: {results[mode]['rows_per_s']:.0f} rows/s, "
-            f"{results[mode]['ms_per_step']:.2f} ms/step, p50 {results[mode]['p50_ms']:.2f} ms, "
-            f"p99 {results[mode]['p99_ms']:.2f} ms, resets U/V {st['resets_U']}/{st['resets_V']}")
+                             p99_ms=float(np.percentile(lat, 99)), phases=phases, stats=st,
+                             mode=mode, method=meth)
+        log(f"[bench] {name}: {results[name]['rows_per_s']:.0f} rows/s, "
+            f"{results[name]['ms_per_step']:.2f} ms/step, p50 {results[name]['p50_ms']:.2f} ms, "
+            f"p99 {results[name]['p99_ms']:.2f} ms, resets U/V {st['resets_U']}/{st['resets_V']}")
         tot = sum(v[0] for v in phases.values())
         for name, (ms, cnt) in sorted(phases.items(), key=lambda x: -x[1][0]):
             if cnt:
@@ -496,21 +524,44 @@ def main():
                     f"{cnt} launches)")
 
     # --- parity gate after one step, and the oracle as CPU baseline
+    from oracle import approx as approx_oracle
     from oracle import metrics, zha_simon
     gate = {}
     cpu = None
     gpu_first = {}
-    for mode in results:
-        svd = L.TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision=mode,
+    for name, r in results.items():
+        svd = L.TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision=r["mode"],
                              row_capacity=capU, col_capacity=capV)
         U0, s0, V0 = svd.factors()
         for j in range(P):
-            svd.apply(dev_ups[j])
+            svd.apply(dev_ups[j], approx_of(r["method"], j))
         svd.sync()
-        gpu_first[mode] = ((U0, s0, V0), svd.factors())
+        gpu_first[name] = ((U0, s0, V0), svd.factors())
         svd.close()
+    # the variants against the oracle's variant (same start vectors), and how
+    # far the variant lies from the exact update (for information)
+    approx_ref = {}
+    for meth in methods:
+        t = time.perf_counter()
+        Ua, sa, Va = cfg["U"], cfg["s"], cfg["V"]
+        for j in range(P):
+            f = approx_oracle.add_rows if ups[j][0] == "rows" else approx_oracle.add_cols
+            Ua, sa, Va, ia = f(Ua, sa, Va, ups[j][1], method=meth, l=la, t=ta,
+                               start=starts[meth][0][j])
+        approx_ref[meth] = (Ua, sa, Va, ia, time.perf_counter() - t)
+        name = f"{head_mode}+{meth}"
+        U1, s1, V1 = gpu_first[name][1]
+        r = metrics.compare((U1, s1, V1), (Ua, sa, Va), ia["theta_hat"], 1e-3)
+        gate[name] = dict(sigma_rel=r["sigma_rel"], angle_U=r["angle_U"], angle_V=r["angle_V"],
+                          jstar=r["jstar"], orth_U=r["orth_U"], orth_V=r["orth_V"],
+                          oracle="O3 (same variant, same start vectors)")
+        log(f"[bench] gate {name}: sigma_rel {r['sigma_rel']:.2e} angle U/V "
+            f"{r['angle_U']:.2e}/{r['angle_V']:.2e} at j*={r['jstar']}; oracle "
+            f"{approx_ref[meth][4]:.1f}s")
+    modes_exact = [n for n, r in results.items() if r["method"] is None]
     if wl["gate"] == "properties":
-        for mode, ((U0, s0, V0), (U1, s1, V1)) in gpu_first.items():
+        for mode in modes_exact:
+            (U0, s0, V0), (U1, s1, V1) = gpu_first[mode]
             gate[mode] = property_gate(U0, s0, V0, ups[0], U1, s1, V1)
             log(f"[bench] gate {mode} (properties): {gate[mode]}")
     else:
@@ -530,7 +581,16 @@ def main():
                        kind="oracle",
                        sample=f"one step ({P} update(s), {wl['rows_per_step']} update rows) of "
                               f"the same workload from the same starting factors: {dt:.1f} s wall")
-        for mode, (_, (U1, s1, V1)) in gpu_first.items():
+        for meth in methods:   # distance of the variant from the exact update
+            Ua, sa, Va, ia, _ = approx_ref[meth]
+            r = metrics.compare((Ua, sa, Va), (Ur, sr, Vr), info["theta_hat"], 1e-3)
+            gate[f"{head_mode}+{meth}"]["vs_exact"] = dict(
+                sigma_rel=r["sigma_rel"], angle_U=r["angle_U"], angle_V=r["angle_V"],
+                jstar=r["jstar"])
+            log(f"[bench] {meth} vs exact (oracles): sigma_rel {r['sigma_rel']:.2e} "
+                f"angle U/V {r['angle_U']:.2e}/{r['angle_V']:.2e} at j*={r['jstar']}")
+        for mode in modes_exact:
+            U1, s1, V1 = gpu_first[mode][1]
             delta = 1e-6 if mode == "fp64" else 1e-3
             r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], delta)
             gate[mode] = dict(sigma_rel=r["sigma_rel"], angle_U=r["angle_U"],
@@ -574,13 +634,17 @@ def main():
         ach = b / (sp_ms / sp_n / 1e3) / 1e9
         spmm_roof = dict(achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                          avg_us=1e3 * sp_ms / sp_n, bytes=b, traffic=stored_traffic("spmm_w"))
+    ex = [m for m in modes_exact if m in gate]
     if wl["gate"] == "properties":
         tol = {"fp64": 1e-10}
-        gate_ok = all(g["residual_U"] <= tol.get(m, 1e-5) and g["residual_V"] <= tol.get(m, 1e-5)
-                      for m, g in gate.items()) if gate else None
+        gate_ok = all(gate[m]["residual_U"] <= tol.get(m, 1e-5) and
+                      gate[m]["residual_V"] <= tol.get(m, 1e-5) for m in ex) if ex else None
     else:
-        gate_ok = all(g["sigma_rel"] <= (1e-10 if m == "fp64" else 1e-5)
-                      for m, g in gate.items()) if gate else None
+        gate_ok = all(gate[m]["sigma_rel"] <= (1e-10 if m == "fp64" else 1e-5)
+                      for m in ex) if ex else None
+    var_names = [f"{head_mode}+{m}" for m in methods]
+    variants_ok = all(gate[n]["sigma_rel"] <= (1e-10 if head_mode == "fp64" else 1e-5)
+                      for n in var_names) if var_names else None
     out = {
         "metric": "update rows/s at k=64, BF16x3 vs FP32 path at sigma rel err <=1e-5; "
                   "p50/p99 latency",
@@ -594,8 +658,10 @@ def main():
         "config": dict({"workload": wl["desc"], "parallelism": "single GPU"}, **wl["extra"]),
         "p50_ms": hr["p50_ms"], "p99_ms": hr["p99_ms"],
         "paths": {m: dict(rows_per_s=r["rows_per_s"], ms_per_step=r["ms_per_step"],
-                          p50_ms=r["p50_ms"], p99_ms=r["p99_ms"]) for m, r in results.items()},
-        "gate": gate, "gate_ok": gate_ok,
+                          p50_ms=r["p50_ms"], p99_ms=r["p99_ms"],
+                          **({"variant": dict(method=r["method"], l=la, t=ta)}
+                             if r["method"] else {})) for m, r in results.items()},
+        "gate": gate, "gate_ok": gate_ok, "variants_gate_ok": variants_ok,
         "phases_ms_per_step": {n: v[0] / K for n, v in hr["phases"].items() if v[1]},
         "roofline": roof,
         "spmm_roofline": spmm_roof,
