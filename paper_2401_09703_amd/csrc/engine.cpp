@@ -381,7 +381,7 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
 void sparse_side_small(svlcov_state *h, int64_t s, int64_t N, const double *Xv,
                        const double *Cp64, const double *W, const double *Y, double *T1,
                        double *Wnew, double *Winv, int32_t *flag, int side, double *gws,
-                       size_t gws_len) {
+                       size_t gws_len, bool do_inverse = true) {
   const int K = h->k;
   hipStream_t st = h->stream;
   PhaseScope ps(h, PH_SMALL);
@@ -389,7 +389,7 @@ void sparse_side_small(svlcov_state *h, int64_t s, int64_t N, const double *Xv,
   svl::gemm_f64_sk(st, true, false, K, K, s, -1.0, Cp64, K, Y, K, 1.0, T1, K, gws, gws_len,
                    h->info);
   svl::gemm_f64(st, false, false, K, K, K, 1.0, W, K, T1, K, 0.0, Wnew, K, h->info);
-  svl::inverse_cond(st, K, Wnew, Winv, flag, h->cond_reset, h->info, side);
+  if (do_inverse) svl::inverse_cond(st, K, Wnew, Winv, flag, h->cond_reset, h->info, side);
 }
 
 // The sparse-side factor update (Equation (1)): Y = T X[k:] with T = L^{-T}
@@ -398,7 +398,7 @@ void sparse_side_small(svlcov_state *h, int64_t s, int64_t N, const double *Xv,
 void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, const double *Cp64,
                       const double *L, const double *Linv, const double *W, double *Y,
                       double *T1, double *Wnew, double *Winv, int32_t *flag, int side,
-                      double *gws, size_t gws_len) {
+                      double *gws, size_t gws_len, bool do_inverse = true) {
   const int K = h->k;
   hipStream_t st = h->stream;
   {
@@ -412,7 +412,8 @@ void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, c
       svl::set_status(st, h->info, SVLCOV_E_DEVICE);
     }
   }
-  sparse_side_small(h, s, N, Xv, Cp64, W, Y, T1, Wnew, Winv, flag, side, gws, gws_len);
+  sparse_side_small(h, s, N, Xv, Cp64, W, Y, T1, Wnew, Winv, flag, side, gws, gws_len,
+                    do_inverse);
 }
 
 template <typename T>
@@ -530,11 +531,15 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   {
     PhaseScope ps(h, PH_SMALL);
     svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
-    svl::inverse_cond(st, K, WnA, WiA, flags, h->cond_reset, h->info, sideA);
   }
-  // sparse side: W_B (G[:k] - C_n G[k:])
+  // sparse side: W_B (G[:k] - C_n G[k:]); then both inverses in one launch
   sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
-                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N);
+                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
+  {
+    PhaseScope ps(h, PH_SMALL);
+    svl::inverse_cond_pair(st, K, WnA, WiA, flags, sideA, WnB, WiB, flags + 1, sideB,
+                           h->cond_reset, h->info);
+  }
   svl::check_finite(st, K * K, WnB, h->info, h->seq);
   svl::check_finite(st, K * K, WnA, h->info, h->seq);
   // commit: append side (realise on reset, appended rows F[k:] W^{-1})
@@ -737,14 +742,18 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
   {
     PhaseScope ps(h, PH_SMALL);
     svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, b.Fv, N, 0.0, b.WnA, K, h->info);
-    svl::inverse_cond(st, K, b.WnA, b.WiA, b.flags, h->cond_reset, h->info, sideA);
   }
   {
     PhaseScope ps(h, PH_TRSM);   // Y G[k:] in place of T G[k:]
     svl::gemm_f64(st, true, true, s, K, l, 1.0, b.Yc, s, b.Gv + K, N2, 0.0, b.Y, K, h->info);
   }
   sparse_side_small(h, s, N2, b.Gv, b.Cp64, W_B, b.Y, b.T1, b.WnB, b.WiB, b.flags + 1, sideB,
-                    gws, gws_len);
+                    gws, gws_len, false);
+  {
+    PhaseScope ps(h, PH_SMALL);
+    svl::inverse_cond_pair(st, K, b.WnA, b.WiA, b.flags, sideA, b.WnB, b.WiB, b.flags + 1,
+                           sideB, h->cond_reset, h->info);
+  }
   svl::check_finite(st, K * K, b.WnB, h->info, h->seq);
   svl::check_finite(st, K * K, b.WnA, h->info, h->seq);
   if (hipGetLastError() != hipSuccess) {
@@ -865,9 +874,14 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
   r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p);
   if (r != SVLCOV_OK) return r;
   sparse_side_math(h, s, N, Fv, CpD, GD, LiD, h->WU, YD, T1, WnU, WiU, flags, 0,
-                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N);
+                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
   sparse_side_math(h, s, N, Gv, CpE, GE, LiE, h->WV, YE, T1, WnV, WiV, flags + 1, 1,
-                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N);
+                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
+  {
+    PhaseScope ps(h, PH_SMALL);
+    svl::inverse_cond_pair(st, K, WnU, WiU, flags, 0, WnV, WiV, flags + 1, 1, h->cond_reset,
+                           h->info);
+  }
   svl::check_finite(st, K * K, WnU, h->info, h->seq);
   svl::check_finite(st, K * K, WnV, h->info, h->seq);
   sparse_side_commit<T>(h, dD, h->m, Ub, YD, MD, WnU, WiU, flags, h->WU, theta, h->sigma, 0);

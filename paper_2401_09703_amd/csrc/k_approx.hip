@@ -144,11 +144,24 @@ k_gkl_step(int64_t s, int i, int l, double *__restrict__ Pv, double *__restrict_
     pn[e] = g[e] * ia - a * pi[e];
   }
   __syncthreads();
-  // two passes of classical Gram-Schmidt against p_1 .. p_i
+  // two passes of classical Gram-Schmidt against p_1 .. p_i; the i + 1 dot
+  // products of a pass are reduced together (per-wave sums in LDS, one
+  // barrier, then one thread per product sums the waves)
+  __shared__ double wred[AP_NT / 64][AP_LMAX + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int pass = 0; pass < 2; ++pass) {
     for (int j = 0; j <= i; ++j) {
-      const double c = blk_dot(Pv + (int64_t)j * s, pn, s, red);
-      if (threadIdx.x == 0) cj[j] = c;
+      const double *pj = Pv + (int64_t)j * s;
+      double v = 0.0;
+      for (int64_t e = threadIdx.x; e < s; e += blockDim.x) v += pj[e] * pn[e];
+      v = wave_sum(v);
+      if (lane == 0) wred[wv][j] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= i) {
+      double c = 0.0;
+      for (int q = 0; q < AP_NT / 64; ++q) c += wred[q][threadIdx.x];
+      cj[threadIdx.x] = c;
     }
     __syncthreads();
     for (int64_t e = threadIdx.x; e < s; e += blockDim.x) {

@@ -391,10 +391,10 @@ __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
 // LDS (one barrier).  The row interchanges are undone at the end as one
 // column permutation.
 template <int K>
-__global__ void __launch_bounds__(256)
-k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
-               int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
-               int side) {
+__device__ __forceinline__ void
+inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
+                   int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
+                   int side) {
   if (info->status) return;
   constexpr int R = K / 4;                  // rows per wave
   constexpr int CPL = K > 64 ? 2 : 1;       // columns per lane
@@ -544,6 +544,29 @@ k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
       if (atomicCAS(&info->status, 0, 4) == 0) info->failed_seq = -1;
     }
   }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256)
+k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
+               int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
+               int side) {
+  inverse_cond_block<K>(W, Winv, flag, cond_reset, info, side);
+}
+
+// The two sides' inverses of one update in one launch (block 0: side a,
+// block 1: side b); they are independent, so they run side by side.
+struct InvJob {
+  const double *W;
+  double *Winv;
+  int32_t *flag;
+  int side;
+};
+template <int K>
+__global__ void __launch_bounds__(256)
+k_inverse_cond2(InvJob a, InvJob b, double cond_reset, SvDevInfo *__restrict__ info) {
+  const InvJob j = blockIdx.x ? b : a;
+  inverse_cond_block<K>(j.W, j.Winv, j.flag, cond_reset, info, j.side);
 }
 
 __global__ void k_commit_small(int K, const double *__restrict__ Wnew,
@@ -839,6 +862,21 @@ void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t 
     case 128: SV_INV(128); break;
   }
 #undef SV_INV
+}
+
+void inverse_cond_pair(hipStream_t st, int K, const double *Wa, double *Wia, int32_t *fa, int sa,
+                       const double *Wb, double *Wib, int32_t *fb, int sb, double cond_reset,
+                       SvDevInfo *info) {
+  const InvJob a{Wa, Wia, fa, sa}, b{Wb, Wib, fb, sb};
+#define SV_INV2(KK) hipLaunchKernelGGL((k_inverse_cond2<KK>), dim3(2), dim3(256), 0, st, a, b, \
+                                       cond_reset, info)
+  switch (K) {
+    case 16: SV_INV2(16); break;
+    case 32: SV_INV2(32); break;
+    case 64: SV_INV2(64); break;
+    case 128: SV_INV2(128); break;
+  }
+#undef SV_INV2
 }
 
 void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,

@@ -165,6 +165,98 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
   }
 }
 
+// The same reduction for small N (N <= TRI_SMALL_N) in one block with the
+// whole matrix in LDS (row stride N + 1): no grid-wide exchange, six block
+// barriers per column.  Same conventions and outputs as k_tridiag: beta =
+// -sign(alpha) ||x||, tau = (beta - alpha) / beta, v_{i+1} = 1, v_j = x_j /
+// (alpha - beta), reflector i left in row i of A (columns i+1 ..).
+constexpr int TRI_SMALL_N = 128;
+constexpr int TRI_SMALL_NT = 256;
+
+__global__ void __launch_bounds__(TRI_SMALL_NT)
+k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
+                double *__restrict__ e, double *__restrict__ tau,
+                const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  extern __shared__ double sm[];
+  constexpr int NT = TRI_SMALL_NT, nw = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (N < 3) {
+    if (tid == 0) {
+      d[0] = A[0];
+      if (N == 2) { e[0] = A[1]; d[1] = A[lda + 1]; }
+    }
+    return;
+  }
+  const int ld = N + 1;
+  double *S = sm, *V = sm + (int64_t)N * ld, *P = V + N;
+  __shared__ double red[nw];
+  for (int q = tid; q < N * N; q += NT) S[(q / N) * ld + q % N] = A[(int64_t)(q / N) * lda + q % N];
+  __syncthreads();
+  for (int i = 0; i <= N - 3; ++i) {
+    const double *Si = S + (int64_t)i * ld;
+    // ||x_{2..}||^2 of the column below the diagonal (row i by symmetry)
+    double part = 0.0;
+    for (int j = i + 2 + tid; j < N; j += NT) part += Si[j] * Si[j];
+    part = wave_sum(part);
+    if (lane == 0) red[w] = part;
+    __syncthreads();
+    double xn2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < nw; ++q) xn2 += red[q];
+    const double alpha = Si[i + 1];
+    double beta, t, scl;
+    if (xn2 == 0.0) {
+      t = 0.0; beta = alpha; scl = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + xn2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t = (beta - alpha) / beta;
+      scl = 1.0 / (alpha - beta);
+    }
+    for (int j = i + 1 + tid; j < N; j += NT) {
+      const double vj = (j == i + 1) ? 1.0 : Si[j] * scl;
+      V[j] = vj;
+      A[(int64_t)i * lda + j] = vj;
+    }
+    if (tid == 0) { d[i] = Si[i]; e[i] = beta; tau[i] = t; }
+    __syncthreads();
+    // p = tau M22 v, one wave per row
+    for (int r = i + 1 + w; r < N; r += nw) {
+      const double *Sr = S + (int64_t)r * ld;
+      double acc = 0.0;
+      for (int j = i + 1 + lane; j < N; j += 64) acc += Sr[j] * V[j];
+      acc = wave_sum(acc);
+      if (lane == 0) P[r] = t * acc;
+    }
+    __syncthreads();
+    // w = p - (tau / 2)(p.v) v
+    double pv = 0.0;
+    for (int j = i + 1 + tid; j < N; j += NT) pv += P[j] * V[j];
+    pv = wave_sum(pv);
+    if (lane == 0) red[w] = pv;
+    __syncthreads();
+    double pvs = 0.0;
+#pragma unroll
+    for (int q = 0; q < nw; ++q) pvs += red[q];
+    const double aw = -0.5 * t * pvs;
+    for (int j = i + 1 + tid; j < N; j += NT) P[j] += aw * V[j];
+    __syncthreads();
+    // M22 -= v w^T + w v^T
+    const int n2 = N - i - 1;
+    for (int q = tid; q < n2 * n2; q += NT) {
+      const int r = i + 1 + q / n2, c = i + 1 + q % n2;
+      S[(int64_t)r * ld + c] -= V[r] * P[c] + P[r] * V[c];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    d[N - 2] = S[(int64_t)(N - 2) * ld + N - 2];
+    e[N - 2] = S[(int64_t)(N - 2) * ld + N - 1];
+    d[N - 1] = S[(int64_t)(N - 1) * ld + N - 1];
+  }
+}
+
 }  // namespace
 
 namespace svl {
@@ -177,6 +269,19 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
   const int N = (int)N64;
   if (N64 > eig_max_n() || N < 1) return -1;
   double *d = work, *e = d + N, *tau = e + N, *pbuf = tau + N, *rowbuf = pbuf + 2 * N;
+  if (N <= TRI_SMALL_N) {   // one block, the matrix in LDS
+    static bool small_once = false;
+    if (!small_once) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_small),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      (void)hipGetLastError();
+      small_once = true;
+    }
+    const size_t sh = ((size_t)N * (N + 1) + 2 * N) * sizeof(double);
+    hipLaunchKernelGGL(k_tridiag_small, dim3(1), dim3(TRI_SMALL_NT), sh, st, N, A, N64, d, e,
+                       tau, info);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
   static int ncu = 0;
   static bool once = false;
   // block widths: 256 threads, or one wave per owned row (5..8 waves) when

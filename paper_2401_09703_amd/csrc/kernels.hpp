@@ -120,6 +120,10 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X,
 // info; *flag = 1 when kappa > cond_reset or W is singular.
 void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
                   double cond_reset, SvDevInfo *info, int side);
+// Both sides' inverses of one update in one launch (two blocks).
+void inverse_cond_pair(hipStream_t st, int K, const double *Wa, double *Wia, int32_t *fa, int sa,
+                       const double *Wb, double *Wib, int32_t *fb, int sb, double cond_reset,
+                       SvDevInfo *info);
 // W = (reset ? I : Wnew); sig = theta (when sig_out != NULL); count resets.
 void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,
                   const double *theta, double *sig_out, SvDevInfo *info, int side);
