@@ -166,12 +166,21 @@ k_tridiag(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
 }
 
 // The same reduction for small N (N <= TRI_SMALL_N) in one block with the
-// whole matrix in LDS (row stride N + 1): no grid-wide exchange, six block
-// barriers per column.  Same conventions and outputs as k_tridiag: beta =
-// -sign(alpha) ||x||, tau = (beta - alpha) / beta, v_{i+1} = 1, v_j = x_j /
-// (alpha - beta), reflector i left in row i of A (columns i+1 ..).
+// whole matrix in LDS (row stride N + 1), three block barriers per column.
+// Four threads own row i+1+q of the trailing matrix, one in four columns
+// each: they form its entry of p = tau M v and of w, apply the rank-2 update
+// to the row, and the four owning the next column's row also form that row's
+// norm for the next reflector.  Every row loop issues its LDS loads in
+// batches of 8 before using them (an LDS round trip is ~120 cycles, so a
+// dependent load per iteration would dominate).  v is read from row i of S
+// (v_j = scl x_j), which no later step of the column writes.  Conventions
+// and outputs as k_tridiag: beta = -sign(alpha) ||x||, tau = (beta - alpha) /
+// beta, v_{i+1} = 1, reflector i left in row i of A (columns i+1 ..).
 constexpr int TRI_SMALL_N = 128;
-constexpr int TRI_SMALL_NT = 256;
+constexpr int TRI_SMALL_NT = 512;
+constexpr int TS_TPR = 4;                             // threads per row
+constexpr int TS_CPT = TRI_SMALL_N / TS_TPR;          // columns per thread (max)
+constexpr int TS_B = 8;                               // loads in flight
 
 __global__ void __launch_bounds__(TRI_SMALL_NT)
 k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
@@ -181,6 +190,7 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
   extern __shared__ double sm[];
   constexpr int NT = TRI_SMALL_NT, nw = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int q = tid / TS_TPR, sub = tid % TS_TPR;
   if (N < 3) {
     if (tid == 0) {
       d[0] = A[0];
@@ -189,22 +199,26 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
     return;
   }
   const int ld = N + 1;
-  double *S = sm, *V = sm + (int64_t)N * ld, *P = V + N;
+  double *S = sm, *P = sm + (int64_t)N * ld;
   __shared__ double red[nw];
-  for (int q = tid; q < N * N; q += NT) S[(q / N) * ld + q % N] = A[(int64_t)(q / N) * lda + q % N];
+  __shared__ double xn2_s, alpha_s;
+  for (int r = tid / 64; r < N; r += nw)
+    for (int c = lane; c < N; c += 64) S[r * ld + c] = A[(int64_t)r * lda + c];
+  double part = 0.0;
+  for (int j = 2 + tid; j < N; j += NT) part += A[j] * A[j];   // row 0 = column 0
+  part = wave_sum(part);
+  if (lane == 0) red[w] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double x = 0.0;
+    for (int u = 0; u < nw; ++u) x += red[u];
+    xn2_s = x;
+    alpha_s = S[1];
+  }
   __syncthreads();
   for (int i = 0; i <= N - 3; ++i) {
-    const double *Si = S + (int64_t)i * ld;
-    // ||x_{2..}||^2 of the column below the diagonal (row i by symmetry)
-    double part = 0.0;
-    for (int j = i + 2 + tid; j < N; j += NT) part += Si[j] * Si[j];
-    part = wave_sum(part);
-    if (lane == 0) red[w] = part;
-    __syncthreads();
-    double xn2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < nw; ++q) xn2 += red[q];
-    const double alpha = Si[i + 1];
+    const double *Si = S + i * ld;
+    const double xn2 = xn2_s, alpha = alpha_s;
     double beta, t, scl;
     if (xn2 == 0.0) {
       t = 0.0; beta = alpha; scl = 0.0;
@@ -214,46 +228,82 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
       t = (beta - alpha) / beta;
       scl = 1.0 / (alpha - beta);
     }
-    for (int j = i + 1 + tid; j < N; j += NT) {
-      const double vj = (j == i + 1) ? 1.0 : Si[j] * scl;
-      V[j] = vj;
-      A[(int64_t)i * lda + j] = vj;
-    }
     if (tid == 0) { d[i] = Si[i]; e[i] = beta; tau[i] = t; }
-    __syncthreads();
-    // p = tau M22 v, one wave per row
-    for (int r = i + 1 + w; r < N; r += nw) {
-      const double *Sr = S + (int64_t)r * ld;
-      double acc = 0.0;
-      for (int j = i + 1 + lane; j < N; j += 64) acc += Sr[j] * V[j];
-      acc = wave_sum(acc);
-      if (lane == 0) P[r] = t * acc;
+    for (int j = i + 1 + tid; j < N; j += NT)
+      A[(int64_t)i * lda + j] = (j == i + 1) ? 1.0 : Si[j] * scl;
+    const int r = i + 1 + q;
+    const bool act = r < N;
+    const int c0 = i + 1 + sub;                   // this thread's first column
+    const int nc = act && c0 < N ? (N - c0 + TS_TPR - 1) / TS_TPR : 0;
+    double *Sr = S + (act ? r : i) * ld;
+    // p_r = tau sum_j M_rj v_j
+    double acc = 0.0;
+    for (int u0 = 0; u0 < nc; u0 += TS_B) {
+      double a[TS_B], x[TS_B];
+#pragma unroll
+      for (int u = 0; u < TS_B; ++u) {
+        const int c = c0 + (u0 + u) * TS_TPR;
+        const int cc = c < N ? c : c0;
+        a[u] = Sr[cc];
+        x[u] = Si[cc];
+      }
+#pragma unroll
+      for (int u = 0; u < TS_B; ++u) {
+        const int c = c0 + (u0 + u) * TS_TPR;
+        if (c < N) acc += a[u] * (c == i + 1 ? 1.0 : x[u] * scl);
+      }
     }
-    __syncthreads();
-    // w = p - (tau / 2)(p.v) v
-    double pv = 0.0;
-    for (int j = i + 1 + tid; j < N; j += NT) pv += P[j] * V[j];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    const double pr = t * acc;
+    const double vr = act ? ((r == i + 1) ? 1.0 : Si[r] * scl) : 0.0;
+    double pv = (act && sub == 0) ? pr * vr : 0.0;
     pv = wave_sum(pv);
     if (lane == 0) red[w] = pv;
     __syncthreads();
     double pvs = 0.0;
 #pragma unroll
-    for (int q = 0; q < nw; ++q) pvs += red[q];
-    const double aw = -0.5 * t * pvs;
-    for (int j = i + 1 + tid; j < N; j += NT) P[j] += aw * V[j];
+    for (int u = 0; u < nw; ++u) pvs += red[u];
+    const double wr = pr - 0.5 * t * pvs * vr;   // w_r
+    if (act && sub == 0) P[r] = wr;
     __syncthreads();
-    // M22 -= v w^T + w v^T
-    const int n2 = N - i - 1;
-    for (int q = tid; q < n2 * n2; q += NT) {
-      const int r = i + 1 + q / n2, c = i + 1 + q % n2;
-      S[(int64_t)r * ld + c] -= V[r] * P[c] + P[r] * V[c];
+    // M22 -= v w^T + w v^T on the row; the next reflector's row norm
+    double nn = 0.0;
+    for (int u0 = 0; u0 < nc; u0 += TS_B) {
+      double a[TS_B], x[TS_B], pw[TS_B];
+#pragma unroll
+      for (int u = 0; u < TS_B; ++u) {
+        const int c = c0 + (u0 + u) * TS_TPR;
+        const int cc = c < N ? c : c0;
+        a[u] = Sr[cc];
+        x[u] = Si[cc];
+        pw[u] = P[cc];
+      }
+#pragma unroll
+      for (int u = 0; u < TS_B; ++u) {
+        const int c = c0 + (u0 + u) * TS_TPR;
+        if (c < N) {
+          const double vc = (c == i + 1) ? 1.0 : x[u] * scl;
+          const double v = a[u] - (vr * pw[u] + wr * vc);
+          Sr[c] = v;
+          if (r == i + 1) {
+            if (c >= i + 3) nn += v * v;
+            if (c == i + 2) alpha_s = v;
+          }
+        }
+      }
+    }
+    if (q == 0) {   // the four threads of row i + 1: lanes 0..3 of wave 0
+      nn += __shfl_xor(nn, 1, 64);
+      nn += __shfl_xor(nn, 2, 64);
+      if (sub == 0) xn2_s = nn;
     }
     __syncthreads();
   }
   if (tid == 0) {
-    d[N - 2] = S[(int64_t)(N - 2) * ld + N - 2];
-    e[N - 2] = S[(int64_t)(N - 2) * ld + N - 1];
-    d[N - 1] = S[(int64_t)(N - 1) * ld + N - 1];
+    d[N - 2] = S[(N - 2) * ld + N - 2];
+    e[N - 2] = S[(N - 2) * ld + N - 1];
+    d[N - 1] = S[(N - 1) * ld + N - 1];
   }
 }
 
@@ -277,7 +327,7 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
       (void)hipGetLastError();
       small_once = true;
     }
-    const size_t sh = ((size_t)N * (N + 1) + 2 * N) * sizeof(double);
+    const size_t sh = ((size_t)N * (N + 1) + N) * sizeof(double);
     hipLaunchKernelGGL(k_tridiag_small, dim3(1), dim3(TRI_SMALL_NT), sh, st, N, A, N64, d, e,
                        tau, info);
     return hipGetLastError() == hipSuccess ? 0 : -3;
