@@ -7,10 +7,41 @@
 
 namespace svk {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+// Cross-lane moves of a double through DPP (the two 32-bit halves moved
+// separately); CTRL is the DPP control word.  A DPP move costs a few cycles,
+// a shuffle through ds_bpermute an LDS round trip.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_dbl(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+constexpr int DPP_QUAD_XOR1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_MIRROR = 0x140;
+
+// Sum over each group of four consecutive lanes, in every lane of the group.
+__device__ __forceinline__ double quad_sum(double v) {
+  v += dpp_d<DPP_QUAD_XOR1>(v);
+  v += dpp_d<DPP_QUAD_XOR2>(v);
   return v;
+}
+
+// Wave-wide sum in every lane: DPP within each row of 16 lanes, then the four
+// row sums read from lanes 0, 16, 32, 48 (fixed order, so every lane and
+// every call with the same inputs gets the same bits).  All 64 lanes must be
+// active (every caller reduces in converged code).
+__device__ __forceinline__ double wave_sum(double v) {
+  v = quad_sum(v);
+  v += dpp_d<DPP_ROW_HALF_MIRROR>(v);
+  v += dpp_d<DPP_ROW_MIRROR>(v);
+  return (readlane_dbl(v, 0) + readlane_dbl(v, 16)) + (readlane_dbl(v, 32) + readlane_dbl(v, 48));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -19,10 +50,14 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Wave-wide maximum in every lane (DPP as for wave_sum; all lanes active).
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_d<DPP_QUAD_XOR1>(v));
+  v = fmax(v, dpp_d<DPP_QUAD_XOR2>(v));
+  v = fmax(v, dpp_d<DPP_ROW_HALF_MIRROR>(v));
+  v = fmax(v, dpp_d<DPP_ROW_MIRROR>(v));
+  return fmax(fmax(readlane_dbl(v, 0), readlane_dbl(v, 16)),
+              fmax(readlane_dbl(v, 32), readlane_dbl(v, 48)));
 }
 
 // Block-wide sum; every thread returns the same value (fixed summation order,

@@ -446,10 +446,11 @@ k_trsm_rows(int64_t N, const double *__restrict__ L, double *__restrict__ X,
   for (int i = 0; i < K; ++i) x[i] = X[(int64_t)i * N + n];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    double acc = x[i];
+    // four independent partial sums, so the FMAs do not form one chain
+    double acc[4] = {x[i], 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int p = 0; p < i; ++p) acc -= Ls[i * K + p] * x[p];
-    x[i] = acc * dinv[i];
+    for (int p = 0; p < i; ++p) acc[p & 3] -= Ls[i * K + p] * x[p];
+    x[i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * dinv[i];
   }
 #pragma unroll
   for (int i = 0; i < K; ++i) X[(int64_t)i * N + n] = x[i];

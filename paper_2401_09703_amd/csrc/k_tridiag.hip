@@ -200,6 +200,9 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
   }
   const int ld = N + 1;
   double *S = sm, *P = sm + (int64_t)N * ld;
+  // d, e, tau and the reflectors' scales stay in LDS until the end: a global
+  // store inside the loop would make every block barrier wait for it
+  double *dd = P + N, *ee = dd + N, *tt = ee + N, *sc = tt + N;
   __shared__ double red[nw];
   __shared__ double xn2_s, alpha_s;
   for (int r = tid / 64; r < N; r += nw)
@@ -228,9 +231,7 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
       t = (beta - alpha) / beta;
       scl = 1.0 / (alpha - beta);
     }
-    if (tid == 0) { d[i] = Si[i]; e[i] = beta; tau[i] = t; }
-    for (int j = i + 1 + tid; j < N; j += NT)
-      A[(int64_t)i * lda + j] = (j == i + 1) ? 1.0 : Si[j] * scl;
+    if (tid == 0) { dd[i] = Si[i]; ee[i] = beta; tt[i] = t; sc[i] = scl; }
     const int r = i + 1 + q;
     const bool act = r < N;
     const int c0 = i + 1 + sub;                   // this thread's first column
@@ -253,8 +254,7 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
         if (c < N) acc += a[u] * (c == i + 1 ? 1.0 : x[u] * scl);
       }
     }
-    acc += __shfl_xor(acc, 1, 64);
-    acc += __shfl_xor(acc, 2, 64);
+    acc = quad_sum(acc);   // the four threads of a row are one lane quad
     const double pr = t * acc;
     const double vr = act ? ((r == i + 1) ? 1.0 : Si[r] * scl) : 0.0;
     double pv = (act && sub == 0) ? pr * vr : 0.0;
@@ -293,17 +293,25 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
         }
       }
     }
-    if (q == 0) {   // the four threads of row i + 1: lanes 0..3 of wave 0
-      nn += __shfl_xor(nn, 1, 64);
-      nn += __shfl_xor(nn, 2, 64);
-      if (sub == 0) xn2_s = nn;
-    }
+    nn = quad_sum(nn);   // converged: every lane takes part
+    if (q == 0 && sub == 0) xn2_s = nn;   // the quad of row i + 1
     __syncthreads();
   }
   if (tid == 0) {
-    d[N - 2] = S[(N - 2) * ld + N - 2];
-    e[N - 2] = S[(N - 2) * ld + N - 1];
-    d[N - 1] = S[(N - 1) * ld + N - 1];
+    dd[N - 2] = S[(N - 2) * ld + N - 2];
+    ee[N - 2] = S[(N - 2) * ld + N - 1];
+    dd[N - 1] = S[(N - 1) * ld + N - 1];
+  }
+  __syncthreads();
+  // row i of S (columns > i) is no longer touched after column i: it still
+  // holds x, and v_j = scl_i x_j
+  for (int i = w; i <= N - 3; i += nw)
+    for (int j = i + 1 + lane; j < N; j += 64)
+      A[(int64_t)i * lda + j] = (j == i + 1) ? 1.0 : S[i * ld + j] * sc[i];
+  for (int i = tid; i < N; i += NT) {
+    d[i] = dd[i];
+    if (i < N - 1) e[i] = ee[i];
+    if (i < N - 2) tau[i] = tt[i];
   }
 }
 
@@ -327,7 +335,7 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
       (void)hipGetLastError();
       small_once = true;
     }
-    const size_t sh = ((size_t)N * (N + 1) + N) * sizeof(double);
+    const size_t sh = ((size_t)N * (N + 1) + 5 * N) * sizeof(double);
     hipLaunchKernelGGL(k_tridiag_small, dim3(1), dim3(TRI_SMALL_NT), sh, st, N, A, N64, d, e,
                        tau, info);
     return hipGetLastError() == hipSuccess ? 0 : -3;
