@@ -206,6 +206,21 @@ svlcov_status svlcov_profile(svlcov_state *h, int32_t enable);
 svlcov_status svlcov_phase_times(svlcov_state *h, double *ms, int64_t *count, int32_t n);
 const char *svlcov_phase_name(int32_t i);
 
+/* Tile shapes of the fused projection (svlcov_project_batch and the request
+ * server's fused launches): variant v gathers with loads_in_flight 16-byte
+ * loads per lane and takes rows_per_tile rows of an update per workgroup.
+ * The shape used for an update is looked up in a process-wide table by
+ * (fp64: 1 for FP64 storage, 0 for FP32; the rank k in 16/32/64/128; the
+ * row bin of its mean nonzeros per row: 0 below 16, 1 below 64, 2 below 256,
+ * 3 otherwise).  Every entry starts at variant 0; the tuner writes the
+ * measured best ones.  These calls touch no device.  Errors: SVLCOV_E_INVALID
+ * for a variant or key out of range or a NULL output. */
+int32_t svlcov_spmm_variant_count(void);
+svlcov_status svlcov_spmm_variant_shape(int32_t v, int32_t *loads_in_flight,
+                                        int32_t *rows_per_tile);
+svlcov_status svlcov_spmm_tune_set(int32_t fp64, int32_t k, int32_t row_bin, int32_t variant);
+svlcov_status svlcov_spmm_tune_get(int32_t fp64, int32_t k, int32_t row_bin, int32_t *variant);
+
 /* Building block of the (k+s) Rayleigh-Ritz SVD (Section 2.1, step 2): the k
  * largest eigenpairs of the symmetric N x N FP64 matrix M (row-major, device
  * memory, not modified).  lam (device, k doubles) receives the eigenvalues in

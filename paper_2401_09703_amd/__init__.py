@@ -116,7 +116,8 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_server_attach", "svlcov_server_submit", "svlcov_server_wait",
            "svlcov_server_poll", "svlcov_server_drain", "svlcov_server_get_stats",
            "svlcov_server_destroy", "svlcov_project_batch", "svlcov_add_rows_approx",
-           "svlcov_add_cols_approx"]
+           "svlcov_add_cols_approx", "svlcov_spmm_variant_count", "svlcov_spmm_variant_shape",
+           "svlcov_spmm_tune_set", "svlcov_spmm_tune_get"]
 NUM_PHASES = 16
 
 
@@ -131,6 +132,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_add_rows.argtypes = [P, C.POINTER(_Csr)]
     lib.svlcov_add_cols.argtypes = [P, C.POINTER(_Csr)]
     lib.svlcov_update_weights.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Csr)]
+    lib.svlcov_spmm_variant_count.argtypes = []
+    lib.svlcov_spmm_variant_count.restype = I32
+    lib.svlcov_spmm_variant_shape.argtypes = [I32, C.POINTER(I32), C.POINTER(I32)]
+    lib.svlcov_spmm_tune_set.argtypes = [I32, I32, I32, I32]
+    lib.svlcov_spmm_tune_get.argtypes = [I32, I32, I32, C.POINTER(I32)]
     lib.svlcov_add_rows_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Approx)]
     lib.svlcov_add_cols_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Approx)]
     lib.svlcov_get_factors.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), I32,
@@ -412,6 +418,56 @@ def project_batch(states, sides, Es, stream=None, timing=None):
     return outs, norms
 
 
+# ---- tile shapes of the fused projection and their tuning table
+SPMM_ROW_BINS = (16, 64, 256)   # bin edges in mean nonzeros per row
+TUNING_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "spmm_tuning_gfx950.json")
+
+
+def spmm_variants():
+    """[(loads in flight per lane, rows per tile)] of every variant."""
+    out = []
+    for v in range(_lib.svlcov_spmm_variant_count()):
+        u, rb = C.c_int32(), C.c_int32()
+        _check(_lib.svlcov_spmm_variant_shape(v, C.byref(u), C.byref(rb)),
+               "svlcov_spmm_variant_shape")
+        out.append((u.value, rb.value))
+    return out
+
+
+def spmm_row_bin(nnz_per_row: float) -> int:
+    return sum(nnz_per_row >= e for e in SPMM_ROW_BINS)
+
+
+def spmm_tune_set(fp64: int, k: int, row_bin: int, variant: int):
+    _check(_lib.svlcov_spmm_tune_set(int(fp64), int(k), int(row_bin), int(variant)),
+           "svlcov_spmm_tune_set")
+
+
+def spmm_tune_get(fp64: int, k: int, row_bin: int) -> int:
+    v = C.c_int32()
+    _check(_lib.svlcov_spmm_tune_get(int(fp64), int(k), int(row_bin), C.byref(v)),
+           "svlcov_spmm_tune_get")
+    return v.value
+
+
+def load_spmm_tuning(path: str = TUNING_PATH) -> int:
+    """Apply a tuning cache written by ``paper_2401_09703_amd.autotune``;
+    returns the number of entries applied (0 when there is no file)."""
+    import json
+    if not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        data = json.load(f)
+    n = 0
+    for e in data.get("entries", []):
+        spmm_tune_set(e["fp64"], e["k"], e["row_bin"], e["variant"])
+        n += 1
+    return n
+
+
+load_spmm_tuning(os.environ.get("SVLCOV_SPMM_TUNING", TUNING_PATH))
+
+
 _OPS = {"rows": 0, "cols": 1, "weights": 2}
 
 
@@ -489,5 +545,6 @@ class Server:
             pass
 
 
-__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "project_batch", "Approx", "load_library", "LIB_PATH", "EXPORTS",
+__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "project_batch", "Approx",
+           "spmm_variants", "spmm_tune_set", "spmm_tune_get", "load_spmm_tuning", "spmm_row_bin", "load_library", "LIB_PATH", "EXPORTS",
            "FP64", "FP32", "BF16X3"]

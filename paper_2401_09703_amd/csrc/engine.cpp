@@ -1314,6 +1314,30 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
   return le == hipSuccess ? SVLCOV_OK : SVLCOV_E_DEVICE;
 }
 
+int32_t svlcov_spmm_variant_count(void) { return svl::spmm_variant_count(); }
+
+svlcov_status svlcov_spmm_variant_shape(int32_t v, int32_t *loads_in_flight,
+                                        int32_t *rows_per_tile) {
+  int u = 0, rb = 0;
+  if (!loads_in_flight || !rows_per_tile || !svl::spmm_variant_shape(v, &u, &rb))
+    return SVLCOV_E_INVALID;
+  *loads_in_flight = u;
+  *rows_per_tile = rb;
+  return SVLCOV_OK;
+}
+
+svlcov_status svlcov_spmm_tune_set(int32_t fp64, int32_t k, int32_t row_bin, int32_t variant) {
+  return svl::spmm_tune_set(fp64, k, row_bin, variant) ? SVLCOV_OK : SVLCOV_E_INVALID;
+}
+
+svlcov_status svlcov_spmm_tune_get(int32_t fp64, int32_t k, int32_t row_bin, int32_t *variant) {
+  if (!variant) return SVLCOV_E_INVALID;
+  const int v = svl::spmm_tune_get(fp64, k, row_bin);
+  if (v < 0) return SVLCOV_E_INVALID;
+  *variant = v;
+  return SVLCOV_OK;
+}
+
 svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,
                                   double *vecs, void *stream) {
   if (N < 1 || k < 1 || k > N || !M || !lam || !vecs) return SVLCOV_E_INVALID;

@@ -3,6 +3,7 @@
 // sparse Gram E E^T, and the two writes into the tall factors (the sparse row
 // update and the appended rows).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -165,15 +166,13 @@ template <typename T> struct Wide;
 template <> struct Wide<float> { typedef sv_f4 V; static constexpr int E = 4; };
 template <> struct Wide<double> { typedef sv_d2 V; static constexpr int E = 2; };
 
-constexpr int PB_U = 8;   // 16-byte gathers in flight per lane in the fused projection
-
 // Row i of P = E * base accumulated by one wave (T accumulate).  A base row of
 // K columns is read by LPR = K/E lanes with one 16-byte load each, so one
 // load instruction gathers G = 64/LPR rows (G nonzeros of E) and a lane keeps
-// PB_U such loads in flight; loads past the row's last nonzero are skipped
-// (a uniform branch).  Lanes of group 0 end with P[i][c..c+E) in out (LDS);
+// U such loads in flight; loads past the row's last nonzero are skipped (a
+// uniform branch).  Lanes of group 0 end with P[i][c..c+E) in out (LDS);
 // *nrm_out receives ||e_i||^2.
-template <typename T, int K>
+template <typename T, int K, int U>
 __device__ __forceinline__ void
 wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
                  const int32_t *__restrict__ col_idx, const void *__restrict__ val, int vdtype,
@@ -182,7 +181,7 @@ wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
   constexpr int E = Wide<T>::E;
   constexpr int LPR = K / E;                   // lanes per base row
   constexpr int G = 64 / LPR;                  // base rows per load
-  constexpr int NB = PB_U * G;                 // nonzeros per batch of loads
+  constexpr int NB = U * G;                    // nonzeros per batch of loads
   constexpr int CH = NB > 64 ? NB / 64 : 1;    // CSR entries held per lane
   constexpr int CW = 64 * CH;                  // nonzeros per CSR chunk
   static_assert(LPR >= 1 && LPR <= 64 && (NB % 64 == 0 || 64 % NB == 0), "tile shape");
@@ -209,10 +208,10 @@ wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
     }
     // one pass when NB >= CW, else CW / NB passes over the chunk
     for (int j0 = 0; j0 < n; j0 += NB) {
-      V bb[PB_U];
-      T vv[PB_U];
+      V bb[U];
+      T vv[U];
 #pragma unroll
-      for (int u = 0; u < PB_U; ++u) {
+      for (int u = 0; u < U; ++u) {
         const int h = (u * G) / 64;              // j0 == 0 whenever CH > 1
         const int jj = (j0 + u * G + g) & 63;
         const int32_t col = __shfl(mc[h], jj, 64);
@@ -221,7 +220,7 @@ wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
         if (j0 + u * G < n) bb[u] = *(const V *)(base + (int64_t)col * K + c);
       }
 #pragma unroll
-      for (int u = 0; u < PB_U; ++u) acc += vv[u] * bb[u];
+      for (int u = 0; u < U; ++u) acc += vv[u] * bb[u];
     }
   }
 #pragma unroll
@@ -236,25 +235,26 @@ wave_row_project(int64_t i, const int64_t *__restrict__ row_ptr,
   if (lane == 0) *nrm_out = nrm;
 }
 
-// The projections of many updates of one rank and storage type in one
-// launch (a batch of mixed ranks and types is one launch per group, so each
+// The projections of many updates of one rank, storage type and tile shape
+// in one launch (a batch of mixed ones is one launch per group, so each
 // launch keeps the registers of its own shape and its occupancy).  Block b
-// takes tile t = order[b], a tile of PB_RB consecutive rows of the request
-// whose tiles start at row0 <= t: each wave accumulates whole rows of P (one
-// row at a time, 16-byte gathers), the tile's rows of P meet in
-// LDS, and C' = P W is formed for the tile with each element of W read once
-// (from L2) by the thread that owns its column and part of the inner index.
-constexpr int PB_RB = 8;
+// takes tile t = order[b], a tile of RB consecutive rows of the request whose
+// tiles start at row0 <= t: each wave accumulates whole rows of P (one row at
+// a time, 16-byte gathers, U in flight per lane), the tile's rows of P meet
+// in LDS, and C' = P W is formed for the tile with each element of W read
+// once (from L2) by the thread that owns its column and part of the inner
+// index.  (U, RB) is chosen per launch from the tuning table by storage
+// type, rank and the bin of the launch's mean nonzeros per row.
 constexpr int SV_XCDS = 8;   // MI355X: workgroup b runs on XCD b mod 8
 
-template <typename T, int K>
+template <typename T, int K, int U, int RB>
 __global__ void __launch_bounds__(64 * SP_NW)
 k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs, const int32_t *__restrict__ order) {
   constexpr int Q = 64 * SP_NW / K;   // parts of the inner index in C' = P W
   constexpr int LQ = K / Q;
-  __shared__ double Pt[PB_RB][K];
-  __shared__ double Pp[Q][PB_RB][K];
-  __shared__ double nr[PB_RB];
+  __shared__ double Pt[RB][K];
+  __shared__ double Pp[Q][RB][K];
+  __shared__ double nr[RB];
   const int64_t t = order[blockIdx.x];
   if (t < 0) return;
   int lo = 0, hi = n - 1;   // last request with row0 <= t
@@ -264,23 +264,23 @@ k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs, const int32_t *__re
   }
   const svl::ProjDesc &d = descs[lo];
   if (d.info && d.info->status) return;
-  const int64_t i0 = (t - d.row0) * PB_RB;
-  const int rows = (int)((d.s - i0) < PB_RB ? (d.s - i0) : PB_RB);
+  const int64_t i0 = (t - d.row0) * RB;
+  const int rows = (int)((d.s - i0) < RB ? (d.s - i0) : RB);
   if (rows <= 0) return;
   const int tid = threadIdx.x, w = tid >> 6;
   for (int rr = w; rr < rows; rr += SP_NW)
-    wave_row_project<T, K>(i0 + rr, d.row_ptr, d.col_idx, d.val, d.vdtype, (const T *)d.base,
+    wave_row_project<T, K, U>(i0 + rr, d.row_ptr, d.col_idx, d.val, d.vdtype, (const T *)d.base,
                            Pt[rr], &nr[rr]);
-  for (int rr = rows + w; rr < PB_RB; rr += SP_NW)   // rows past the end stay finite
+  for (int rr = rows + w; rr < RB; rr += SP_NW)   // rows past the end stay finite
     for (int c = tid & 63; c < K; c += 64) Pt[rr][c] = 0.0;
   __syncthreads();
   // thread (part, col): the part's LQ inner indices for all rows of the tile,
   // so every element of W is read once per tile
   {
     const int col = tid % K, part = tid / K;
-    double o[PB_RB];
+    double o[RB];
 #pragma unroll
-    for (int r = 0; r < PB_RB; ++r) o[r] = 0.0;
+    for (int r = 0; r < RB; ++r) o[r] = 0.0;
     constexpr int UB = LQ < 16 ? LQ : 16;   // W loads in flight per thread
 #pragma unroll 1
     for (int u0 = 0; u0 < LQ; u0 += UB) {
@@ -290,10 +290,10 @@ k_spmm_batch(int n, const svl::ProjDesc *__restrict__ descs, const int32_t *__re
 #pragma unroll
       for (int u = 0; u < UB; ++u)
 #pragma unroll
-        for (int r = 0; r < PB_RB; ++r) o[r] += Pt[r][part * LQ + u0 + u] * wv[u];
+        for (int r = 0; r < RB; ++r) o[r] += Pt[r][part * LQ + u0 + u] * wv[u];
     }
 #pragma unroll
-    for (int r = 0; r < PB_RB; ++r) Pp[part][r][col] = o[r];
+    for (int r = 0; r < RB; ++r) Pp[part][r][col] = o[r];
   }
   __syncthreads();
   for (int e = tid; e < rows * K; e += 64 * SP_NW) {
@@ -478,7 +478,43 @@ template void spmm_w<double>(hipStream_t, int, int64_t, const int64_t *, const i
                              const void *, int, const double *, const double *, double *,
                              float *, double *, const SvDevInfo *);
 
-int spmm_batch_rows_per_block() { return PB_RB; }
+// Tile shapes of the fused projection: (16-byte loads in flight per lane,
+// rows per tile).  Variant 0 is the default.
+struct PbShape { int u, rb; };
+constexpr PbShape PB_SHAPES[] = {{8, 8}, {4, 8}, {16, 8}, {8, 16}, {4, 16}, {8, 4}};
+constexpr int PB_NSHAPES = (int)(sizeof(PB_SHAPES) / sizeof(PB_SHAPES[0]));
+
+// Tuning table: variant per (FP64 storage, rank index log2(K/16), row bin),
+// process-wide; written by the tuner through the C ABI, read per batch.
+std::atomic<int> g_pb_tune[2][4][PB_ROW_BINS];
+
+int k_index(int K) { return K <= 16 ? 0 : K <= 32 ? 1 : K <= 64 ? 2 : 3; }
+
+int spmm_batch_rows_per_block() { return PB_SHAPES[0].rb; }
+int spmm_variant_count() { return PB_NSHAPES; }
+bool spmm_variant_shape(int v, int *u, int *rb) {
+  if (v < 0 || v >= PB_NSHAPES) return false;
+  *u = PB_SHAPES[v].u;
+  *rb = PB_SHAPES[v].rb;
+  return true;
+}
+int spmm_row_bin(int64_t nnz, int64_t s) {
+  const double m = s > 0 ? (double)nnz / (double)s : 0.0;
+  return m < 16.0 ? 0 : m < 64.0 ? 1 : m < 256.0 ? 2 : 3;
+}
+bool spmm_tune_set(int fp64, int K, int bin, int v) {
+  if ((fp64 != 0 && fp64 != 1) || (K != 16 && K != 32 && K != 64 && K != 128) || bin < 0 ||
+      bin >= PB_ROW_BINS || v < 0 || v >= PB_NSHAPES)
+    return false;
+  g_pb_tune[fp64][k_index(K)][bin].store(v, std::memory_order_relaxed);
+  return true;
+}
+int spmm_tune_get(int fp64, int K, int bin) {
+  if ((fp64 != 0 && fp64 != 1) || (K != 16 && K != 32 && K != 64 && K != 128) || bin < 0 ||
+      bin >= PB_ROW_BINS)
+    return -1;
+  return g_pb_tune[fp64][k_index(K)][bin].load(std::memory_order_relaxed);
+}
 
 void ProjBatch::pack(void *host) const {
   char *p = (char *)host;
@@ -492,6 +528,9 @@ ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
     const char *e = std::getenv("SVLCOV_PROJ_ORDER");
     return !(e && std::strcmp(e, "rr") == 0);
   }();
+  // one launch per (storage type, rank); its tile shape is the tuned one for
+  // the group's mean nonzeros per row (kept in pad), so mixed row lengths do
+  // not split a launch
   std::stable_sort(d.begin(), d.end(), [](const ProjDesc &a, const ProjDesc &b) {
     return a.fp64 != b.fp64 ? a.fp64 < b.fp64 : a.K < b.K;
   });
@@ -500,10 +539,15 @@ ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
   while (g0 < d.size()) {
     size_t g1 = g0 + 1;
     while (g1 < d.size() && d[g1].fp64 == d[g0].fp64 && d[g1].K == d[g0].K) ++g1;
+    int64_t gnnz = 0, gs = 0;
+    for (size_t q = g0; q < g1; ++q) { gnnz += d[q].nnz; gs += d[q].s; }
+    const int v = spmm_tune_get(d[g0].fp64, d[g0].K, spmm_row_bin(gnnz, gs));
+    for (size_t q = g0; q < g1; ++q) d[q].pad = v < 0 ? 0 : v;
+    const int RB = PB_SHAPES[d[g0].pad].rb;
     int64_t tiles = 0;
     for (size_t q = g0; q < g1; ++q) {
       d[q].row0 = tiles;
-      tiles += (d[q].s + PB_RB - 1) / PB_RB;
+      tiles += (d[q].s + RB - 1) / RB;
     }
     if (!xcd_affine) {   // tiles in request order, dealt round-robin over the XCDs
       out.g_desc.push_back(g0);
@@ -518,7 +562,7 @@ ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
     std::vector<double> tc(g1 - g0);
     double total_cost = 0.0;
     for (size_t q = g0; q < g1; ++q) {
-      const int64_t nt = (d[q].s + PB_RB - 1) / PB_RB;
+      const int64_t nt = (d[q].s + RB - 1) / RB;
       tc[q - g0] = nt > 0 ? (double)d[q].nnz / (double)nt * K + (double)K * K : 0.0;
       total_cost += tc[q - g0] * (double)nt;
     }
@@ -528,7 +572,7 @@ ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
     struct Chunk { int64_t t0, n; double cost; };
     std::vector<Chunk> ch;
     for (size_t q = g0; q < g1; ++q) {
-      const int64_t nt = (d[q].s + PB_RB - 1) / PB_RB;
+      const int64_t nt = (d[q].s + RB - 1) / RB;
       const double c1 = tc[q - g0];
       const int64_t pieces = std::max<int64_t>(
           1, std::min<int64_t>(nt, (int64_t)std::ceil(c1 * (double)nt / std::max(cap, 1.0))));
@@ -562,7 +606,24 @@ ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d) {
   return out;
 }
 
+template <typename T, int K>
+void launch_pb(hipStream_t st, int v, unsigned blocks, int n, const ProjDesc *dd,
+               const int32_t *oo) {
+#define SV_PBV(UU, RR) hipLaunchKernelGGL((k_spmm_batch<T, K, UU, RR>), dim3(blocks), \
+                                          dim3(64 * SP_NW), 0, st, n, dd, oo)
+  switch (v) {
+    case 1: SV_PBV(4, 8); break;
+    case 2: SV_PBV(16, 8); break;
+    case 3: SV_PBV(8, 16); break;
+    case 4: SV_PBV(4, 16); break;
+    case 5: SV_PBV(8, 4); break;
+    default: SV_PBV(8, 8); break;
+  }
+#undef SV_PBV
+}
+
 void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev) {
+  static_assert(PB_NSHAPES == 6, "launch_pb covers every tile shape");
   const ProjDesc *descs = (const ProjDesc *)blob_dev;
   const int32_t *order = (const int32_t *)((const char *)blob_dev + b.d.size() * sizeof(ProjDesc));
   for (size_t g = 0; g + 1 < b.g_desc.size(); ++g) {
@@ -572,24 +633,23 @@ void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev) {
     if (blocks == 0 || n == 0) continue;
     const ProjDesc *dd = descs + q0;
     const int32_t *oo = order + o0;
-#define SV_PB(TT, KK) hipLaunchKernelGGL((k_spmm_batch<TT, KK>), dim3((unsigned)blocks), \
-                                         dim3(64 * SP_NW), 0, st, n, dd, oo)
+    const int v = b.d[q0].pad;
+    const unsigned nb = (unsigned)blocks;
     if (b.d[q0].fp64) {
       switch (b.d[q0].K) {
-        case 16: SV_PB(double, 16); break;
-        case 32: SV_PB(double, 32); break;
-        case 64: SV_PB(double, 64); break;
-        default: SV_PB(double, 128); break;
+        case 16: launch_pb<double, 16>(st, v, nb, n, dd, oo); break;
+        case 32: launch_pb<double, 32>(st, v, nb, n, dd, oo); break;
+        case 64: launch_pb<double, 64>(st, v, nb, n, dd, oo); break;
+        default: launch_pb<double, 128>(st, v, nb, n, dd, oo); break;
       }
     } else {
       switch (b.d[q0].K) {
-        case 16: SV_PB(float, 16); break;
-        case 32: SV_PB(float, 32); break;
-        case 64: SV_PB(float, 64); break;
-        default: SV_PB(float, 128); break;
+        case 16: launch_pb<float, 16>(st, v, nb, n, dd, oo); break;
+        case 32: launch_pb<float, 32>(st, v, nb, n, dd, oo); break;
+        case 64: launch_pb<float, 64>(st, v, nb, n, dd, oo); break;
+        default: launch_pb<float, 128>(st, v, nb, n, dd, oo); break;
       }
     }
-#undef SV_PB
   }
 }
 

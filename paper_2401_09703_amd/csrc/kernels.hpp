@@ -31,8 +31,8 @@ struct ProjDesc {
   double *rown;
   const SvDevInfo *info;
   int64_t s, row0;
-  int64_t nnz;   // nonzeros of E (host-side balance hint)
-  int32_t vdtype, K, fp64, pad;
+  int64_t nnz;   // nonzeros of E (host-side balance and tile-shape choice)
+  int32_t vdtype, K, fp64, pad;   // pad: the tile-shape variant (set by prepare)
 };
 // A fused batch as uploaded: the descriptors ordered by (storage type, rank),
 // one group per launch, followed by each group's block-to-tile table (-1 marks
@@ -47,6 +47,14 @@ struct ProjBatch {
   void pack(void *host) const;
 };
 int spmm_batch_rows_per_block();
+// Tile shapes of the fused projection and the process-wide tuning table:
+// variant per (FP64 storage, rank, bin of nonzeros per row).
+constexpr int PB_ROW_BINS = 4;   // < 16, < 64, < 256, >= 256 nonzeros per row
+int spmm_variant_count();
+bool spmm_variant_shape(int v, int *loads_in_flight, int *rows_per_tile);
+int spmm_row_bin(int64_t nnz, int64_t s);
+bool spmm_tune_set(int fp64, int K, int bin, int v);
+int spmm_tune_get(int fp64, int K, int bin);   // -1 for a bad key
 ProjBatch spmm_batch_prepare(std::vector<ProjDesc> d);
 // blob_dev holds pack()'s bytes (device memory).
 void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev);

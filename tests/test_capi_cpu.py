@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "svlcov.h")
 
 def _declared():
     txt = open(HEADER).read()
-    decl = r"^\s*(?:svlcov_status|void\s*\*|void|const\s+char\s*\*)\s*(svlcov_[a-z_0-9]+)\s*\("
+    decl = r"^\s*(?:svlcov_status|void\s*\*|void|int32_t|const\s+char\s*\*)\s*(svlcov_[a-z_0-9]+)\s*\("
     return sorted(set(re.findall(decl, txt, flags=re.M)))
 
 
@@ -91,3 +91,34 @@ def test_server_binding_without_gpu():
     with pytest.raises(L.SvlcovError) as e:
         L.Server(max_inflight=2)
     assert e.value.code == 5
+
+
+def test_spmm_tuning_table_without_gpu(tmp_path):
+    """The fused projection's tile-shape table: variants, set/get round trip,
+    key and variant validation, and the JSON cache loader (no device use)."""
+    import json
+    import paper_2401_09703_amd as L
+    shapes = L.spmm_variants()
+    assert shapes[0] == (8, 8) and len(shapes) == len(set(shapes)) >= 4
+    saved = {(f, k, b): L.spmm_tune_get(f, k, b) for f in (0, 1) for k in (16, 32, 64, 128)
+             for b in range(4)}
+    try:
+        L.spmm_tune_set(1, 32, 3, len(shapes) - 1)
+        assert L.spmm_tune_get(1, 32, 3) == len(shapes) - 1
+        for bad in ((2, 64, 0, 0), (0, 48, 0, 0), (0, 64, 4, 0), (0, 64, 0, len(shapes)),
+                    (0, 64, -1, 0)):
+            with pytest.raises(L.SvlcovError):
+                L.spmm_tune_set(*bad)
+        with pytest.raises(L.SvlcovError):
+            L.spmm_tune_get(0, 64, 9)
+        assert [L.spmm_row_bin(x) for x in (0, 15.9, 16, 63, 64, 255, 256, 1e6)] == \
+            [0, 0, 1, 1, 2, 2, 3, 3]
+        p = tmp_path / "tune.json"
+        p.write_text(json.dumps({"entries": [{"fp64": 0, "k": 16, "row_bin": 1, "variant": 2},
+                                             {"fp64": 1, "k": 128, "row_bin": 0, "variant": 1}]}))
+        assert L.load_spmm_tuning(str(p)) == 2
+        assert L.spmm_tune_get(0, 16, 1) == 2 and L.spmm_tune_get(1, 128, 0) == 1
+        assert L.load_spmm_tuning(str(tmp_path / "missing.json")) == 0
+    finally:
+        for (f, k, b), v in saved.items():
+            L.spmm_tune_set(f, k, b, v)

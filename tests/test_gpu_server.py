@@ -207,3 +207,40 @@ def test_alone_vs_mix_fused(prec):
     finally:
         for st in states:
             st.close()
+
+
+@pytest.mark.parametrize("variant", range(6))
+def test_fused_projection_every_tile_shape(variant):
+    """Each tile shape of the fused projection (forced for every key of the
+    tuning table) gives C' = E base W: ranks 16..128, both storage types,
+    updates shorter and longer than a tile, sparse and dense rows."""
+    import torch
+    import paper_2401_09703_amd as L
+    keys = [(f, k, b) for f in (0, 1) for k in (16, 32, 64, 128) for b in range(4)]
+    saved = {key: L.spmm_tune_get(*key) for key in keys}
+    rng = np.random.default_rng(300 + variant)
+    states, Es, host = [], [], []
+    try:
+        for key in keys:
+            L.spmm_tune_set(*key, variant)
+        for i, (k, prec, s, dens) in enumerate([(16, "fp64", 3, 0.2), (32, "fp32", 37, 0.02),
+                                                (64, "bf16x3", 70, 0.3), (128, "fp64", 21, 0.05),
+                                                (64, "fp32", 9, 0.6), (16, "bf16x3", 130, 0.01)]):
+            m, n = int(rng.integers(200, 600)), int(rng.integers(150, 500))
+            U, sg, V = synthetic_factors(m, n, k, rng)
+            svd = L.TruncatedSVD(U, sg, V, precision=prec)
+            E = bernoulli_uniform(s, n, dens, rng)
+            states.append(svd); Es.append(L.DeviceCSR.from_host(E)); host.append(E)
+        outs, norms = L.project_batch(states, [1] * len(states), Es)
+        torch.cuda.synchronize()
+        for svd, E, out in zip(states, host, outs):
+            _, _, V = svd.factors()
+            ref = E.to_scipy() @ V
+            tol = 1e-12 if svd.precision == "fp64" else 1e-5
+            err = np.abs(out.cpu().numpy() - ref).max() / max(np.abs(ref).max(), 1e-300)
+            assert err <= tol, (variant, svd.precision, svd.k, err)
+    finally:
+        for key, v in saved.items():
+            L.spmm_tune_set(*key, v)
+        for svd in states:
+            svd.close()
