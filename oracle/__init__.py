@@ -18,6 +18,8 @@ Contents
               the augmented space): an l-dimensional basis of a Krylov or
               power-iteration subspace of the augmented matrix in place of its
               QR, then the Zha-Simon rotation with K of k + l columns.
+  query       O4: Query(i) of Theorem 1 and the pair score U[i]^T Sigma V[j]
+              of the link-prediction / collaborative-filtering workloads.
   metrics     comparison metrics (singular values, principal angles,
               orthonormality, spectral-gap prefix).
 
