@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="graph", choices=("graph", "bernoulli", "ratings",
-                                                             "weights", "stream"))
+                                                             "weights", "stream", "score"))
     ap.add_argument("--requests", type=int, default=512, help="stream workload: requests")
     ap.add_argument("--matrices", type=int, default=512, help="stream workload: matrices")
     ap.add_argument("--inflight", type=int, default=64, help="stream workload: server slots")
@@ -213,7 +213,7 @@ def phase_work(name, N, s, k, nnz, d_cols):
     return None, None, None
 
 
-WORKLOADS = ("graph", "bernoulli", "ratings", "weights")
+WORKLOADS = ("graph", "bernoulli", "ratings", "weights")   # plus "stream" and "score"
 
 
 def build_workload(args, W, K):
@@ -319,6 +319,73 @@ def measure_fused_projection(L, torch, np, states, mats, reqs, dev_reqs, count):
     ach = byts / (ms / 1e3) / 1e9
     return dict(requests=len(sel), bytes=int(byts), ms=ms, achieved_GBs=ach,
                 frac=ach / HBM_PEAK_GBS)
+
+
+def run_score(args):
+    """Link-prediction scoring (the paper's link-prediction task): the rank-64
+    factors of the graph workload's start (90,000 nodes), 2^24 node pairs
+    drawn uniformly, each scored as max(U[i]^T S V[j], U[j]^T S V[i]) by
+    svlcov_score_pairs.  Throughput in scored pairs/s over the scoring kernel
+    (factors realised beforehand), its compulsory bytes against HBM, and a
+    sample of 20,000 pairs against the oracle."""
+    import numpy as np
+    import torch
+    import paper_2401_09703_amd as L
+    from oracle import query
+    from synth import config2_graph
+    cfg = config2_graph(k=64, n_init=args.n_init, step_nodes=args.step_nodes, steps=1)
+    prec = (args.modes or "bf16x3").split(",")[0]
+    svd = L.TruncatedSVD(cfg["U"], cfg["s"], cfg["V"], precision=prec)
+    nodes, k = cfg["U"].shape[0], cfg["k"]
+    npairs = 1 << 24
+    g = torch.Generator(device="cuda")
+    g.manual_seed(240109703)
+    I = torch.randint(0, nodes, (npairs,), generator=g, device="cuda", dtype=torch.int64)
+    J = torch.randint(0, nodes, (npairs,), generator=g, device="cuda", dtype=torch.int64)
+    times = []
+    for _ in range(args.warmup + args.steps):
+        out = svd.score_pairs(I, J, both=True, timing=times)
+    ms = min(times[args.warmup:])
+    w = 8 if prec == "fp64" else 4
+    # compulsory bytes: the index pairs and the scores once, and every row of
+    # both realised factors once (2^25 uniform draws touch all of them); the
+    # four row gathers per pair are logical reads that the 256 MB Infinity
+    # Cache and the L2s serve for factors of this size
+    byts = npairs * (16 + 8) + 2 * nodes * k * w
+    gather = npairs * 4 * k * w
+    ach = byts / (ms / 1e3) / 1e9
+    U, s, V = svd.factors()
+    samp = np.arange(0, npairs, npairs // 20000)[:20000]
+    Ih, Jh, got = I.cpu().numpy()[samp], J.cpu().numpy()[samp], out.cpu().numpy()[samp]
+    t = time.perf_counter()
+    ref = query.score_pairs(U, s, V, Ih, Jh, both=True)
+    cpu_s = time.perf_counter() - t
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    svd.close()
+    log(f"[bench] score: {npairs} pairs in {ms:.3f} ms = {npairs / ms / 1e6:.2f} G pairs/s, "
+        f"{ach:.0f} GB/s compulsory, {gather / (ms / 1e3) / 1e9:.0f} GB/s of row gathers, "
+        f"max rel err {err:.2e}")
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    out_j = {
+        "metric": "link-prediction scores/s (max of both directions, k=64)",
+        "value": npairs / (ms / 1e3) if err <= (1e-12 if prec == "fp64" else 1e-6) else 0.0,
+        "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": f"chung-lu graph start factors ({nodes} nodes, k={k}), 2^24 "
+                               "uniform node pairs, both directions", "parallelism": "single GPU"},
+        "gate": {"max_rel_err_vs_oracle": err, "sample_pairs": len(samp)},
+        "roofline": dict(kernel="k_score_pairs", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
+                         unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None, avg_ms=ms,
+                         bytes=byts, gather_GBs=gather / (ms / 1e3) / 1e9),
+        "cpu_baseline": dict(value=len(samp) / cpu_s, unit="pairs/s", cores=int(cores),
+                             kind="oracle", sample=f"{len(samp)} pairs of the same batch"),
+    }
+    print(json.dumps(out_j), flush=True)
 
 
 def run_stream(args):
@@ -448,6 +515,9 @@ def main():
         del x, y
     if args.workload == "stream":
         run_stream(args)
+        return
+    if args.workload == "score":
+        run_score(args)
         return
     W, K = args.warmup, args.steps
     t = time.time()

@@ -188,7 +188,28 @@ svlcov_status svlcov_get_factors(svlcov_state *h, int64_t *m, int64_t *n,
 svlcov_status svlcov_query_row(svlcov_state *h, int32_t side, int64_t i,
                                double *out_k);
 
-/* Wait for all work queued on the state and report a deferred error. */
+/* Query(i) of Theorem 1 for many rows at once: out (device, n x k FP64,
+ * row-major) receives row idx[r] of U (side 0) or V (side 1) formed as
+ * base[idx[r]] W in O(k^2) each.  idx is device int64; rows with an index
+ * outside the factor are NaN.  Asynchronous on the state's stream. */
+svlcov_status svlcov_query_rows(svlcov_state *h, int32_t side, int64_t n, const int64_t *idx,
+                                double *out);
+
+/* The pair score of the link-prediction and collaborative-filtering
+ * workloads (Section 5): out[p] = U[i_p]^T Sigma V[j_p]; with both = 1 the
+ * larger of that and U[j_p]^T Sigma V[i_p] (undirected graphs; both indices
+ * must then lie in both factors).  i, j are device int64, out device FP64
+ * (n each); a pair outside the factors scores NaN.  The factors are realised
+ * once per factor version as U_base (W_U Sigma) and V_base W_V in the storage
+ * type (FP32 products for the FP32 and BF16x3 modes) and kept on the state
+ * until its next update; each pair is then two row gathers and a k-term dot
+ * product (four gathers with both).  Asynchronous on the state's stream;
+ * with kernel_ms non-NULL the call waits and reports the scoring kernel's
+ * device time. */
+svlcov_status svlcov_score_pairs(svlcov_state *h, int64_t n, const int64_t *i, const int64_t *j,
+                                 int32_t both, double *out, float *kernel_ms);
+
+/* Wait for all work queued on the state and report a deferred error. *//* Wait for all work queued on the state and report a deferred error. */
 svlcov_status svlcov_sync(svlcov_state *h);
 
 /* Counters and the numerical diagnostics of the last update (waits). */

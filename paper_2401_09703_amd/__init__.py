@@ -117,7 +117,8 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_server_poll", "svlcov_server_drain", "svlcov_server_get_stats",
            "svlcov_server_destroy", "svlcov_project_batch", "svlcov_add_rows_approx",
            "svlcov_add_cols_approx", "svlcov_spmm_variant_count", "svlcov_spmm_variant_shape",
-           "svlcov_spmm_tune_set", "svlcov_spmm_tune_get"]
+           "svlcov_spmm_tune_set", "svlcov_spmm_tune_get", "svlcov_query_rows",
+           "svlcov_score_pairs"]
 NUM_PHASES = 16
 
 
@@ -132,6 +133,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_add_rows.argtypes = [P, C.POINTER(_Csr)]
     lib.svlcov_add_cols.argtypes = [P, C.POINTER(_Csr)]
     lib.svlcov_update_weights.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Csr)]
+    lib.svlcov_query_rows.argtypes = [P, I32, I64, P, P]
+    lib.svlcov_score_pairs.argtypes = [P, I64, P, P, I32, P, C.POINTER(C.c_float)]
     lib.svlcov_spmm_variant_count.argtypes = []
     lib.svlcov_spmm_variant_count.restype = I32
     lib.svlcov_spmm_variant_shape.argtypes = [I32, C.POINTER(I32), C.POINTER(I32)]
@@ -359,6 +362,51 @@ class TruncatedSVD:
     def query(self, side: int, i: int):
         out = np.empty(self.k, dtype=np.float64)
         _check(_lib.svlcov_query_row(self._h, side, i, out.ctypes.data), "svlcov_query_row")
+        return out
+
+    def query_rows(self, side: int, idx):
+        """Rows idx of U (side 0) or V (side 1) as a (len(idx), k) FP64 CUDA
+        tensor (svlcov_query_rows; NaN rows for indices outside the factor)."""
+        import torch
+        ix = torch.as_tensor(idx, dtype=torch.int64, device="cuda").contiguous()
+        out = torch.empty((ix.numel(), self.k), dtype=torch.float64, device="cuda")
+        self._follow_torch()
+        _check(_lib.svlcov_query_rows(self._h, int(side), ix.numel(), ix.data_ptr(),
+                                      out.data_ptr()), "svlcov_query_rows")
+        self._keep.append(ix)
+        self._lead_torch()
+        return out
+
+    def _follow_torch(self):
+        """The state's stream waits for torch's current stream (inputs)."""
+        import torch
+        ext = torch.cuda.ExternalStream(self.stream)
+        ext.wait_stream(torch.cuda.current_stream())
+
+    def _lead_torch(self):
+        """Torch's current stream waits for the state's stream (outputs)."""
+        import torch
+        ext = torch.cuda.ExternalStream(self.stream)
+        torch.cuda.current_stream().wait_stream(ext)
+
+    def score_pairs(self, i, j, both: bool = False, timing=None):
+        """U[i]^T Sigma V[j] per pair (the larger of both directions with
+        both) as an FP64 CUDA tensor (svlcov_score_pairs); with a list as
+        timing the scoring kernel's device time in ms is appended."""
+        import torch
+        ti = torch.as_tensor(i, dtype=torch.int64, device="cuda").contiguous()
+        tj = torch.as_tensor(j, dtype=torch.int64, device="cuda").contiguous()
+        out = torch.empty(ti.numel(), dtype=torch.float64, device="cuda")
+        ms = C.c_float(0.0)
+        self._follow_torch()
+        _check(_lib.svlcov_score_pairs(self._h, ti.numel(), ti.data_ptr(), tj.data_ptr(),
+                                       1 if both else 0, out.data_ptr(),
+                                       C.byref(ms) if timing is not None else None),
+               "svlcov_score_pairs")
+        self._keep += [ti, tj]
+        self._lead_torch()
+        if timing is not None:
+            timing.append(float(ms.value))
         return out
 
     def stats(self) -> dict:

@@ -1172,6 +1172,81 @@ svlcov_status svlcov_query_row(svlcov_state *h, int32_t side, int64_t i, double 
   return SVLCOV_OK;
 }
 
+svlcov_status svlcov_query_rows(svlcov_state *h, int32_t side, int64_t n, const int64_t *idx,
+                                double *out) {
+  if (!h || (side != 0 && side != 1) || n < 0 || (n > 0 && (!idx || !out)))
+    return SVLCOV_E_INVALID;
+  if (n == 0) return SVLCOV_OK;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  const int64_t rows = side == 0 ? h->m : h->n;
+  const double *W = side == 0 ? h->WU : h->WV;
+  const void *base = side == 0 ? h->Ubase : h->Vbase;
+  if (h->prec == SVLCOV_FP64)
+    svl::query_rows<double>(h->stream, h->k, n, idx, rows, (const double *)base, W, out);
+  else
+    svl::query_rows<float>(h->stream, h->k, n, idx, rows, (const float *)base, W, out);
+  return hipGetLastError() == hipSuccess ? SVLCOV_OK : SVLCOV_E_DEVICE;
+}
+
+svlcov_status svlcov_score_pairs(svlcov_state *h, int64_t n, const int64_t *i, const int64_t *j,
+                                 int32_t both, double *out, float *kernel_ms) {
+  if (!h || n < 0 || (both != 0 && both != 1) || (n > 0 && (!i || !j || !out)))
+    return SVLCOV_E_INVALID;
+  if (n == 0) return SVLCOV_OK;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  const int K = h->k;
+  const bool f64 = h->prec == SVLCOV_FP64;
+  const size_t elem = f64 ? 8 : 4;
+  hipStream_t st = h->stream;
+  if (h->q_seq != h->seq || h->qU.bytes < (size_t)h->m * K * elem ||
+      h->qV.bytes < (size_t)h->n * K * elem) {
+    // realise U_base (W_U Sigma) and V_base W_V once per factor version
+    svlcov_status r = ensure(h, h->qU, (size_t)h->m * K * elem);
+    if (r != SVLCOV_OK) return r;
+    r = ensure(h, h->qV, (size_t)h->n * K * elem);
+    if (r != SVLCOV_OK) return r;
+    r = ensure(h, h->qW, (size_t)K * K * 8);
+    if (r != SVLCOV_OK) return r;
+    svl::scale_cols(st, K, h->WU, h->sigma, (double *)h->qW.p);
+    const int mode = f64 ? 0 : 1;   // FP32 MFMA for FP32 storage (no BF16 split here)
+    if (f64) {
+      svl::realise<double, double>(st, mode, K, h->m, (const double *)h->Ubase,
+                                   (const double *)h->qW.p, (double *)h->qU.p, nullptr, nullptr);
+      svl::realise<double, double>(st, mode, K, h->n, (const double *)h->Vbase, h->WV,
+                                   (double *)h->qV.p, nullptr, nullptr);
+    } else {
+      svl::realise<float, float>(st, mode, K, h->m, (const float *)h->Ubase,
+                                 (const double *)h->qW.p, (float *)h->qU.p, nullptr, nullptr);
+      svl::realise<float, float>(st, mode, K, h->n, (const float *)h->Vbase, h->WV,
+                                 (float *)h->qV.p, nullptr, nullptr);
+    }
+    h->q_seq = h->seq;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (kernel_ms && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    return SVLCOV_E_DEVICE;
+  if (e0) SV_TRY(hipEventRecord(e0, st));
+  if (f64)
+    svl::score_pairs<double>(st, K, n, i, j, both, h->m, h->n, (const double *)h->qU.p,
+                             (const double *)h->qV.p, out);
+  else
+    svl::score_pairs<float>(st, K, n, i, j, both, h->m, h->n, (const float *)h->qU.p,
+                            (const float *)h->qV.p, out);
+  const hipError_t le = hipGetLastError();
+  if (e1) {
+    SV_TRY(hipEventRecord(e1, st));
+    SV_TRY(hipEventSynchronize(e1));
+    if (hipEventElapsedTime(kernel_ms, e0, e1) != hipSuccess) *kernel_ms = -1.f;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  return le == hipSuccess ? SVLCOV_OK : SVLCOV_E_DEVICE;
+}
+
 svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out) {
   if (!h || !out) return SVLCOV_E_INVALID;
   BusyGuard g(h);
@@ -1233,6 +1308,9 @@ void svlcov_destroy(svlcov_state *h) {
   if (h->ws.p) (void)hipFree(h->ws.p);
   if (h->stage.p) (void)hipFree(h->stage.p);
   if (h->outbuf.p) (void)hipFree(h->outbuf.p);
+  if (h->qU.p) (void)hipFree(h->qU.p);
+  if (h->qV.p) (void)hipFree(h->qV.p);
+  if (h->qW.p) (void)hipFree(h->qW.p);
   if (h->Ubase) (void)hipFree(h->Ubase);
   if (h->Vbase) (void)hipFree(h->Vbase);
   if (h->WU) (void)hipFree(h->WU);

@@ -180,6 +180,19 @@ void rpi_basis(hipStream_t st, int64_t s, int l, int t, const double *G, int64_t
                double *Yc, double *X, double *T, double *Gm2, double *Om, double *ws,
                size_t ws_len, double rtol, const SvDevInfo *info);
 
+// ---- queries and scores (k_query.hip)
+// out[r] = base[idx[r]] W (K FP64 each); NaN rows for indices outside [0, rows).
+template <typename T>
+void query_rows(hipStream_t st, int K, int64_t n, const int64_t *idx, int64_t rows,
+                const T *base, const double *W, double *out);
+// WS = W diag(sig).
+void scale_cols(hipStream_t st, int K, const double *W, const double *sig, double *WS);
+// out[p] = Ut[I[p]] . Vt[J[p]] (max with Ut[J[p]] . Vt[I[p]] when both); NaN
+// for a pair outside the factors (m rows of Ut, nn rows of Vt).
+template <typename T>
+void score_pairs(hipStream_t st, int K, int64_t n, const int64_t *I, const int64_t *J, int both,
+                 int64_t m, int64_t nn, const T *Ut, const T *Vt, double *out);
+
 // ---- eigen (k_eig.hip)
 // Top-k eigenpairs of a symmetric N x N FP64 matrix (A is destroyed):
 // lam[0..k) descending, Fv (k x N) row j = eigenvector of lam[j].

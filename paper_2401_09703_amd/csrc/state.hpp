@@ -52,6 +52,10 @@ struct svlcov_state {
   svl_state::DevBuf ws;        // update workspace
   svl_state::DevBuf stage;     // device copies of host CSR inputs
   svl_state::DevBuf outbuf;    // get_factors staging
+  // realised factors for pair scores, U_base (W_U Sigma) and V_base W_V in
+  // the storage type, valid while q_seq equals seq
+  svl_state::DevBuf qU, qV, qW;
+  int64_t q_seq = -1;
   double rank_tol = 0, cond_reset = 0;
   int validate = 1;
   int seq = 0;
