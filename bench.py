@@ -66,7 +66,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="graph", choices=("graph", "bernoulli", "ratings",
-                                                             "weights", "stream", "score"))
+                                                             "weights", "stream", "score", "sweep"))
     ap.add_argument("--requests", type=int, default=512, help="stream workload: requests")
     ap.add_argument("--matrices", type=int, default=512, help="stream workload: matrices")
     ap.add_argument("--inflight", type=int, default=64, help="stream workload: server slots")
@@ -388,6 +388,87 @@ def run_score(args):
     print(json.dumps(out_j), flush=True)
 
 
+def run_sweep(args):
+    """The paper's synthetic sparsity study: a 100,000 x 100,000 matrix of
+    uniformly scattered entries (values 1 - U[0,1)) at densities 0.01 %, 0.1 %,
+    1 % and 10 %; the first 50,000 columns are represented by rank-64 factors
+    (synthetic orthonormal ones: the initial SVD is not on the path) and
+    column batches of s = 100 and 1,000 are appended with add_cols, by the
+    exact path and by the -GKL / -RPI variants (l = 10, t = 3).  Reports
+    appended columns/s per (density, s, path); one case is checked against
+    the oracle."""
+    import numpy as np
+    import torch
+    import paper_2401_09703_amd as L
+    from oracle import approx as approx_oracle
+    from oracle import metrics, zha_simon
+    prec = (args.modes or "bf16x3").split(",")[0]
+    m, n0, k = 100_000, 50_000, 64
+    reps = max(args.steps, 1)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2401_09703)
+    results = []
+    U0 = torch.linalg.qr(torch.randn(m, k, generator=g, device="cuda",
+                                     dtype=torch.float64)).Q.contiguous()
+    V0 = torch.linalg.qr(torch.randn(n0, k, generator=g, device="cuda",
+                                     dtype=torch.float64)).Q.contiguous()
+    sg = 100.0 * torch.arange(1, k + 1, device="cuda", dtype=torch.float64) ** -0.5
+    for dens in (1e-4, 1e-3, 1e-2, 1e-1):
+        for sc in (100, 1000):
+            ups = [L.DeviceCSR(sc, m, *gen_request_gpu(sc, m, dens, 97 * q + int(dens * 1e6) + sc))
+                   for q in range(reps + 1)]
+            nnz = float(np.mean([u.col_idx.numel() for u in ups]))
+            srng = np.random.default_rng(int(dens * 1e6) + sc)
+            for meth in (None, "gkl", "rpi"):
+                svd = L.TruncatedSVD(U0, sg, V0, precision=prec, col_capacity=n0 + sc * (reps + 2),
+                                     validate_device_inputs=False)
+                ap = [None if meth is None else
+                      L.Approx(meth, 10, 3, torch.tensor(
+                          srng.standard_normal(sc) if meth == "gkl"
+                          else srng.standard_normal((sc, 10)), device="cuda"))
+                      for _ in range(reps + 1)]
+                svd.add_cols(ups[0], ap[0])
+                svd.sync()
+                t0 = time.perf_counter()
+                for q in range(1, reps + 1):
+                    svd.add_cols(ups[q], ap[q])
+                svd.sync()
+                dt = (time.perf_counter() - t0) / reps
+                svd.close()
+                r = dict(density=dens, s=sc, path=meth or "exact", nnz_per_update=nnz,
+                         ms_per_update=1e3 * dt, cols_per_s=sc / dt)
+                results.append(r)
+                log(f"[bench] sweep density {dens:.4%} s={sc} {r['path']}: {r['ms_per_update']:.2f} "
+                    f"ms/update, {r['cols_per_s']:.0f} cols/s (nnz {nnz:.0f})")
+    # one case against the oracle (density 0.1 %, s = 100, exact and GKL)
+    svd = L.TruncatedSVD(U0, sg, V0, precision=prec)
+    E = gen_request_gpu(100, m, 1e-3, 7)
+    from synth import CSR
+    Eh = CSR(100, m, E[0].cpu().numpy(), E[1].cpu().numpy(), E[2].cpu().numpy())
+    Uh, sh, Vh = svd.factors()
+    svd.add_cols(L.DeviceCSR(100, m, *E))
+    svd.sync()
+    U1, s1, V1 = svd.factors()
+    svd.close()
+    Ur, sr, Vr, info = zha_simon.add_cols(Uh, sh, Vh, Eh)
+    gate = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], 1e-3)
+    log(f"[bench] sweep gate (exact, 0.1 %, s=100): sigma_rel {gate['sigma_rel']:.2e} "
+        f"angles {gate['angle_U']:.2e}/{gate['angle_V']:.2e}")
+    out = {
+        "metric": "appended columns/s across densities (synthetic sparsity sweep)",
+        "value": None, "unit": "columns/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": prec, "data": "synthetic",
+        "config": {"workload": "100000 x 100000 uniform sparse, densities 0.01-10 %, rank 64, "
+                               "add_cols batches of 100 and 1000", "parallelism": "single GPU"},
+        "sweep": results,
+        "gate": {"case": "exact, density 0.1 %, s = 100", "sigma_rel": gate["sigma_rel"],
+                 "angle_U": gate["angle_U"], "angle_V": gate["angle_V"]},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_stream(args):
     """Streaming batch: independent matrices resident on the GPU, row-append
     requests of 10..2000 rows on uniformly chosen matrices, all submitted to
@@ -518,6 +599,9 @@ def main():
         return
     if args.workload == "score":
         run_score(args)
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
         return
     W, K = args.warmup, args.steps
     t = time.time()
