@@ -287,7 +287,7 @@ namespace {
 template <typename T>
 void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
                    float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which,
-                   bool chol = true) {
+                   bool chol = true, double *dws = nullptr, size_t dws_len = 0) {
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
@@ -298,7 +298,8 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   }
   {
     PhaseScope ps(h, PH_SGRAM);
-    svl::sparse_gram(st, s, E.rp, E.ci, E.v, E.vdt, rid, Gm, s, h->info);
+    svl::sparse_gram(st, s, E.cols, E.nnz, E.rp, E.ci, E.v, E.vdt, rid, Gm, s, dws, dws_len,
+                     h->info);
   }
   {
     PhaseScope ps(h, PH_RGRAM);
@@ -519,7 +520,8 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   }
   svl::op_begin(st, h->info, 0);
   // orthogonalise the augmented matrix of the sparse side
-  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, rid, 0);
+  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, rid, 0, true, Kmat,
+                   (size_t)N * N);   // K is formed only after the Gram
   // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
   {
     PhaseScope ps(h, PH_BUILDK);
@@ -603,9 +605,13 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
   double *W_A = rows_form ? h->WU : h->WV;
   double *W_B = rows_form ? h->WV : h->WU;
   const int sideA = rows_form ? 0 : 1, sideB = 1 - sideA;
+  // a dense update's Gram goes through column blocks of up to 8192 columns
+  const size_t dws_want = (size_t)s * (8192 + 1);
+  const size_t dws_len =
+      svl::gram_dense_block(s, E->cols, E->nnz, dws_want) > 0 ? dws_want : 1;
   struct Bufs {
     double *Cp64, *rown, *Gm, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA, *WiA,
-        *WnB, *WiB, *Mupd, *orthw, *Pv, *Yc, *gv, *ab, *Xl, *Tl, *Gm2, *Om;
+        *WnB, *WiB, *Mupd, *orthw, *Pv, *Yc, *gv, *ab, *Xl, *Tl, *Gm2, *Om, *Dws;
     float *Cp32;
     int32_t *complete, *flags, *rid, *brk;
   } b;
@@ -641,6 +647,7 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
     b.Tl = cv.take<double>((int64_t)l * s);
     b.Gm2 = cv.take<double>((int64_t)l * l);
     b.Om = cv.take<double>((int64_t)l * l);
+    b.Dws = cv.take<double>(dws_len);
   };
   Carver c{nullptr};
   layout(c);
@@ -676,7 +683,8 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
     svl::validate_csr(st, dE.rows, dE.cols, dE.nnz, dE.rp, dE.ci, dE.v, dE.vdt, h->info, h->seq);
   }
   svl::op_begin(st, h->info, 0);
-  orthogonalise<T>(h, dE, B_base, W_B, b.Cp64, b.Cp32, b.rown, b.Gm, nullptr, b.rid, 0, false);
+  orthogonalise<T>(h, dE, B_base, W_B, b.Cp64, b.Cp32, b.rown, b.Gm, nullptr, b.rid, 0, false,
+                   dws_len > 1 ? b.Dws : nullptr, dws_len > 1 ? dws_len : 0);
   double *gws = b.orthw + 2 * K * K + K * N;
   const size_t gws_len = (size_t)8 * K * N;
   {
@@ -861,8 +869,8 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
                         h->seq);
   }
   svl::op_begin(st, h->info, 1);
-  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, rid, 0);
-  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, rid, 1);
+  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, rid, 0, true, Kmat, (size_t)N * N);
+  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, rid, 1, true, Kmat, (size_t)N * N);
   // K = [[Sigma, 0], [0, 0]] + [U^T D ; R_D] [V^T E_m ; R_E]^T
   {
     PhaseScope ps(h, PH_BUILDK);

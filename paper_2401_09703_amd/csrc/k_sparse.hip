@@ -317,6 +317,49 @@ __global__ void k_row_ids(int64_t s, const int64_t *__restrict__ row_ptr,
   for (int64_t p = row_ptr[i] + lane; p < row_ptr[i + 1]; p += 64) rid[p] = (int32_t)i;
 }
 
+// Dense updates (s >= 512, density >= GRAM_DENSE_MIN, long rows): S = E E^T as a sum
+// of D D^T over column blocks D of E made dense in workspace, since the
+// sparse kernel's cost grows with the product of the rows' lengths.
+constexpr double GRAM_DENSE_MIN = 0.02;
+
+// cur[i] = row_ptr[i]: the first nonzero of row i not yet made dense.
+__global__ void k_row_cursor(int64_t s, const int64_t *__restrict__ row_ptr,
+                             int64_t *__restrict__ cur, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < s) cur[i] = row_ptr[i];
+}
+
+__global__ void k_fill_zero(int64_t n, double *__restrict__ x, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    x[e] = 0.0;
+}
+
+// Row i's nonzeros with columns in [c0, c0 + nb) into D[i][col - c0]; they
+// follow cur[i] (columns are sorted), which moves past them.  One wave per row.
+__global__ void k_densify(int64_t s, const int64_t *__restrict__ row_ptr,
+                          const int32_t *__restrict__ col_idx, const void *__restrict__ val,
+                          int vdtype, int64_t c0, int64_t nb, int64_t *__restrict__ cur,
+                          double *__restrict__ D, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= s) return;
+  const int64_t end = row_ptr[i + 1];
+  int64_t p = cur[i];
+  while (p < end) {
+    const int64_t q = p + lane;
+    const bool in = q < end && (int64_t)col_idx[q] < c0 + nb;
+    if (in) D[i * nb + ((int64_t)col_idx[q] - c0)] = ldv(val, vdtype, q);
+    const int taken = __popcll(__ballot(in));   // an in-range prefix of the chunk
+    p += taken;
+    if (taken < 64) break;
+  }
+  if (lane == 0) cur[i] = p;
+}
+
 constexpr int GRAM_LDS_CAP = 4096;      // nonzeros of the pivot row kept in LDS
 constexpr int GRAM_ACC_CAP = 8192;      // rows j accumulated in LDS (dynamic)
 
@@ -655,10 +698,39 @@ void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev) {
 
 int gram_max_rows() { return GRAM_ACC_CAP; }
 
-void sparse_gram(hipStream_t st, int64_t s, const int64_t *rp, const int32_t *ci,
-                 const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
-                 const SvDevInfo *info) {
+int64_t gram_dense_block(int64_t s, int64_t cols, int64_t nnz, size_t dws_len) {
+  if (s <= 0 || cols <= 0 || dws_len == 0) return 0;
+  const double dens = (double)nnz / ((double)s * (double)cols);
+  // a small s gives the block products too few output tiles to fill the chip
+  if (s < 512 || dens < GRAM_DENSE_MIN || nnz / s < 1024) return 0;
+  const size_t avail = dws_len > (size_t)s ? dws_len - (size_t)s : 0;   // s cursors first
+  int64_t nb = (int64_t)(avail / (size_t)s);
+  nb = std::min<int64_t>(nb, 8192) / 64 * 64;
+  if (nb < 256) return 0;
+  return std::min<int64_t>(nb, (cols + 63) / 64 * 64);
+}
+
+void sparse_gram(hipStream_t st, int64_t s, int64_t cols, int64_t nnz, const int64_t *rp,
+                 const int32_t *ci, const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
+                 double *dws, size_t dws_len, const SvDevInfo *info) {
   if (s <= 0) return;
+  const int64_t nb = gram_dense_block(s, cols, nnz, dws_len);
+  if (nb > 0) {   // a dense update: S = sum over column blocks of D D^T
+    int64_t *cur = (int64_t *)dws;
+    double *D = dws + s;
+    const unsigned rb = (unsigned)((s + 3) / 4);
+    hipLaunchKernelGGL(k_row_cursor, dim3(rb), dim3(256), 0, st, s, rp, cur, info);
+    for (int64_t c0 = 0; c0 < cols; c0 += nb) {
+      const int64_t nbl = std::min<int64_t>(nb, cols - c0);
+      const int64_t cnt = s * nb;
+      hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>((cnt + 255) / 256, 16384)),
+                         dim3(256), 0, st, cnt, D, info);
+      hipLaunchKernelGGL(k_densify, dim3(rb), dim3(256), 0, st, s, rp, ci, v, vdt, c0, nb, cur, D,
+                         info);
+      gemm_f64(st, false, true, s, s, nbl, 1.0, D, nb, D, nb, c0 == 0 ? 0.0 : 1.0, S, lds, info);
+    }
+    return;
+  }
   hipLaunchKernelGGL(k_row_ids, dim3((unsigned)((s + 3) / 4)), dim3(256), 0, st, s, rp, rid,
                      info);
   static bool once = false;

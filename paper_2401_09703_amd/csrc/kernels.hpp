@@ -61,9 +61,13 @@ void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev);
 // S = E E^T; rid receives the row id of every nonzero (nnz int32 scratch).
 // s <= gram_max_rows().
 int gram_max_rows();
-void sparse_gram(hipStream_t st, int64_t s, const int64_t *rp, const int32_t *ci,
-                 const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
-                 const SvDevInfo *info);
+// Dense updates use dws (dws_len doubles, s of them cursors) for column
+// blocks of E made dense; gram_dense_block gives the block width, 0 for the
+// sparse kernel.
+int64_t gram_dense_block(int64_t s, int64_t cols, int64_t nnz, size_t dws_len);
+void sparse_gram(hipStream_t st, int64_t s, int64_t cols, int64_t nnz, const int64_t *rp,
+                 const int32_t *ci, const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
+                 double *dws, size_t dws_len, const SvDevInfo *info);
 template <typename T>
 void scatter(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
              const void *v, int vdt, const double *M, T *base, const SvDevInfo *info);
