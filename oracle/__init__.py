@@ -20,6 +20,10 @@ Contents
               QR, then the Zha-Simon rotation with K of k + l columns.
   query       O4: Query(i) of Theorem 1 and the pair score U[i]^T Sigma V[j]
               of the link-prediction / collaborative-filtering workloads.
+  rsvd        O5: the initial truncated SVD of a sparse matrix, by the
+              randomised range finder with power iterations that the
+              introduction cites (Halko, Martinsson and Tropp), with the
+              Gaussian test matrix passed in.
   metrics     comparison metrics (singular values, principal angles,
               orthonormality, spectral-gap prefix).
 

@@ -1,0 +1,57 @@
+"""Pins of O5 (randomised initial SVD): exact on a matrix of rank <= k, and
+within the randomised method's error of the LAPACK SVD on a matrix with a
+fast-decaying spectrum; orthonormal factors; a planted mistake (no power
+iteration on a slowly decaying spectrum, or V taken from the wrong side)
+is caught by the comparison with LAPACK."""
+import numpy as np
+import scipy.sparse as sp
+
+from oracle import metrics, rsvd
+
+
+def _lowrank_sparse(rng, m, n, r, dens):
+    # a sparse matrix of rank r: r sparse rank-one terms
+    A = sp.csr_matrix((m, n))
+    for _ in range(r):
+        u = sp.random(m, 1, density=0.3, random_state=rng)
+        v = sp.random(1, n, density=dens, random_state=rng)
+        A = A + u @ v * rng.uniform(1, 10)
+    return sp.csr_matrix(A)
+
+
+def test_exact_on_rank_k():
+    rng = np.random.default_rng(1)
+    A = _lowrank_sparse(rng, 300, 200, 6, 0.2)
+    U, s, V = rsvd.rsvd(A, 8, rng.standard_normal((200, 16)), power=1)
+    np.testing.assert_allclose((U * s) @ V.T, A.toarray(), atol=1e-10 * abs(A).max())
+    assert np.abs(U.T @ U - np.eye(8)).max() < 1e-12 and np.abs(V.T @ V - np.eye(8)).max() < 1e-12
+
+
+def test_close_to_lapack_on_fast_decay():
+    rng = np.random.default_rng(2)
+    m, n, k = 400, 300, 10
+    X = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    Y = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sv = 2.0 ** -np.arange(n)
+    A = sp.csr_matrix((X * sv) @ Y.T)
+    U, s, V = rsvd.rsvd(A, k, rng.standard_normal((n, 2 * k)), power=2)
+    Ul, sl, Vlt = np.linalg.svd(A.toarray(), full_matrices=False)
+    assert metrics.sigma_rel_err(s, sl[:k]) < 1e-10
+    assert metrics.sin_angle(U, Ul[:, :k]) < 1e-8 and metrics.sin_angle(V, Vlt[:k].T) < 1e-8
+
+
+def test_planted_mistakes_are_caught():
+    rng = np.random.default_rng(3)
+    m, n, k = 300, 250, 8
+    X = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    Y = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sv = 1.0 / (1.0 + np.arange(n)) ** 0.5            # slow decay
+    A = sp.csr_matrix((X * sv) @ Y.T)
+    Om = rng.standard_normal((n, 2 * k))
+    Ul, sl, Vlt = np.linalg.svd(A.toarray(), full_matrices=False)
+    U, s, V = rsvd.rsvd(A, k, Om, power=8)
+    good = metrics.sigma_rel_err(s, sl[:k])
+    U0, s0, V0 = rsvd.rsvd(A, k, Om, power=0)           # mistake: no power iteration
+    assert metrics.sigma_rel_err(s0, sl[:k]) > 10 * good
+    # mistake: right factor from the wrong side
+    assert metrics.sin_angle(U[:V.shape[0]], Vlt[:k].T) > 1e-3
