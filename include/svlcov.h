@@ -252,6 +252,35 @@ svlcov_status svlcov_spmm_tune_get(int32_t fp64, int32_t k, int32_t row_bin, int
 svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,
                                   double *vecs, void *stream);
 
+/* Initial rank-k truncated SVD of a sparse m x n matrix A, the starting
+ * factors U', sigma, V' that every experiment of Section 5 updates from (the
+ * paper leaves their computation to the randomised methods its introduction
+ * cites).  The randomised range finder with `power` subspace iterations
+ * (Halko, Martinsson and Tropp 2011, Algorithms 4.4 and 5.1):
+ *     Q = orth(A Omega);  repeat power times: Q = orth(A orth(A^T Q));
+ *     B = Q^T A = U_B diag(sigma_B) V_B^T;  U = Q U_B[:, :k],
+ *     sigma = sigma_B[:k],  V = V_B[:, :k].
+ * A: canonical CSR (host or device memory per on_device; FP32 or FP64
+ * values); checked on the device, SVLCOV_E_INVALID if malformed.
+ * Omega: the n x l Gaussian test matrix (device, FP64 row-major), drawn by
+ * the caller, so that the result is a deterministic function of (A, Omega).
+ * l in {16, 32, 64, 128} (SVLCOV_E_UNSUPPORTED otherwise), 1 <= k <= l,
+ * l <= min(m, n) (SVLCOV_E_SHAPE), 0 <= power <= 64, nnz < 2^31.
+ * Outputs (device, FP64 row-major, caller-owned): U m x k, sigma k
+ * (non-increasing), V n x k; U and V have orthonormal columns to rounding.
+ * Singular values below 1e-7 sigma_0 are not resolved by the l x l Gram:
+ * their vectors are an orthonormal completion.  phase_ms (host, NULL for
+ * none) receives SVLCOV_RSVD_PHASES times in ms: transpose and validation,
+ * products with A and A^T, orthonormalisations, the l x l eigenproblem, the
+ * final products.  Workspace (about 16 (m + n) l + 40 nnz bytes) is allocated
+ * and freed on `stream` (hipStream_t, NULL = default stream); the call
+ * returns after the stream has finished the work.  Non-finite values in
+ * Omega give SVLCOV_E_NUMERIC. */
+#define SVLCOV_RSVD_PHASES 5
+svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t power,
+                          const double *Omega, double *U, double *sigma, double *V,
+                          double *phase_ms, void *stream);
+
 /* ------------------------------------------------------------------------
  * Request server (continuous batching of updates over many matrices).
  *

@@ -118,8 +118,9 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_server_destroy", "svlcov_project_batch", "svlcov_add_rows_approx",
            "svlcov_add_cols_approx", "svlcov_spmm_variant_count", "svlcov_spmm_variant_shape",
            "svlcov_spmm_tune_set", "svlcov_spmm_tune_get", "svlcov_query_rows",
-           "svlcov_score_pairs"]
+           "svlcov_score_pairs", "svlcov_rsvd"]
 NUM_PHASES = 16
+RSVD_PHASES = ("transpose", "products", "orthonormalise", "small_eig", "final")
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -159,6 +160,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_phase_name.restype = C.c_char_p
     lib.svlcov_sym_eig_topk.argtypes = [I64, P, I32, P, P, P]
     lib.svlcov_sym_eig_topk.restype = I32
+    lib.svlcov_rsvd.argtypes = [C.POINTER(_Csr), I32, I32, I32, P, P, P, P, P, P]
+    lib.svlcov_rsvd.restype = I32
     lib.svlcov_status_str.argtypes = [I32]
     lib.svlcov_status_str.restype = C.c_char_p
     lib.svlcov_project_batch.argtypes = [I32, P, P, P, P, P, P, C.POINTER(C.c_float)]
@@ -251,6 +254,41 @@ def sym_eig_topk(M, k: int, stream=None):
     _check(_lib.svlcov_sym_eig_topk(N, M.data_ptr(), k, lam.data_ptr(), vecs.data_ptr(), st),
            "svlcov_sym_eig_topk")
     return lam, vecs
+
+
+def rsvd(A, k: int, l: int = None, power: int = 2, Omega=None, seed: int = 0, stream=None,
+         timing: dict = None):
+    """Initial rank-k truncated SVD of the sparse matrix A (DeviceCSR or a
+    host CSR with .rows .cols .row_ptr .col_idx .val) on the GPU by the
+    randomised range finder with ``power`` subspace iterations
+    (svlcov_rsvd).  Omega is the n x l FP64 CUDA test matrix; when None it is
+    drawn (standard normal) from a torch generator seeded with ``seed``.  l
+    defaults to the smallest of 16, 32, 64, 128 that is >= 2k (or 128).
+    Returns (U, s, V) as FP64 CUDA tensors; ``timing`` (a dict) receives the
+    per-phase milliseconds."""
+    import torch as _t
+    m, n = int(A.rows), int(A.cols)
+    if l is None:
+        l = next((c for c in (16, 32, 64, 128) if c >= 2 * k), 128)
+    if Omega is None:
+        g = _t.Generator(device="cuda")
+        g.manual_seed(int(seed))
+        Omega = _t.randn((n, l), generator=g, device="cuda", dtype=_t.float64)
+    assert Omega.is_cuda and Omega.dtype == _t.float64 and Omega.is_contiguous()
+    assert tuple(Omega.shape) == (n, l)
+    U = _t.empty((m, k), dtype=_t.float64, device=Omega.device)
+    V = _t.empty((n, k), dtype=_t.float64, device=Omega.device)
+    s = _t.empty(k, dtype=_t.float64, device=Omega.device)
+    keep = []
+    cs = _csr_struct(A, keep)
+    st = stream if stream is not None else _t.cuda.current_stream().cuda_stream
+    ms = (C.c_double * len(RSVD_PHASES))()
+    _check(_lib.svlcov_rsvd(C.byref(cs), k, l, power, Omega.data_ptr(), U.data_ptr(),
+                            s.data_ptr(), V.data_ptr(), ms if timing is not None else None, st),
+           "svlcov_rsvd")
+    if timing is not None:
+        timing.update({name: ms[i] for i, name in enumerate(RSVD_PHASES)})
+    return U, s, V
 
 
 class TruncatedSVD:
@@ -593,6 +631,6 @@ class Server:
             pass
 
 
-__all__ = ["TruncatedSVD", "DeviceCSR", "SvlcovError", "Server", "project_batch", "Approx",
+__all__ = ["TruncatedSVD", "DeviceCSR", "rsvd", "SvlcovError", "Server", "project_batch", "Approx",
            "spmm_variants", "spmm_tune_set", "spmm_tune_get", "load_spmm_tuning", "spmm_row_bin", "load_library", "LIB_PATH", "EXPORTS",
            "FP64", "FP32", "BF16X3"]

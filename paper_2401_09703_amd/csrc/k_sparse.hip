@@ -483,6 +483,22 @@ __global__ void k_append(int64_t s, const double *__restrict__ src, int64_t rs, 
   }
 }
 
+// Y = A X for a CSR A (rows x cols) and a dense FP64 X (cols x L, row-major):
+// one wave per row of A, its nonzeros gathered as in the projection (16-byte
+// loads of rows of X, U of them in flight per lane); the lanes of group 0
+// store the row of Y.
+template <int L, int U>
+__global__ void __launch_bounds__(256)
+k_csr_dense(int64_t rows, const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+            const void *__restrict__ val, int vdtype, const double *__restrict__ X,
+            double *__restrict__ Y, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ double nr[4];
+  const int w = threadIdx.x >> 6;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < rows; i += (int64_t)gridDim.x * 4)
+    wave_row_project<double, L, U>(i, rp, ci, val, vdtype, X, Y + i * L, &nr[w]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -785,5 +801,21 @@ template void append_rows<float>(hipStream_t, int, int64_t, const double *, int6
                                  const double *, const int32_t *, float *, const SvDevInfo *);
 template void append_rows<double>(hipStream_t, int, int64_t, const double *, int64_t, int64_t,
                                   const double *, const int32_t *, double *, const SvDevInfo *);
+
+void csr_dense(hipStream_t st, int L, int64_t rows, const int64_t *rp, const int32_t *ci,
+               const void *v, int vdt, const double *X, double *Y, const SvDevInfo *info) {
+  if (rows <= 0) return;
+  const int64_t nb = (rows + 3) / 4;
+  const unsigned grid = (unsigned)(nb < (1 << 30) ? nb : (1 << 30));
+#define SV_CD(LL) hipLaunchKernelGGL((k_csr_dense<LL, 8>), dim3(grid), dim3(256), 0, st, rows, rp, \
+                                     ci, v, vdt, X, Y, info)
+  switch (L) {
+    case 16: SV_CD(16); break;
+    case 32: SV_CD(32); break;
+    case 64: SV_CD(64); break;
+    case 128: SV_CD(128); break;
+  }
+#undef SV_CD
+}
 
 }  // namespace svl

@@ -197,6 +197,34 @@ template <typename T>
 void score_pairs(hipStream_t st, int K, int64_t n, const int64_t *I, const int64_t *J, int both,
                  int64_t m, int64_t nn, const T *Ut, const T *Vt, double *out);
 
+// ---- initial truncated SVD (k_rsvd.hip; the product in k_sparse.hip)
+// Y = A X, A a CSR (rows x cols), X cols x L FP64 row-major, L in {16..128}.
+void csr_dense(hipStream_t st, int L, int64_t rows, const int64_t *rp, const int32_t *ci,
+               const void *v, int vdt, const double *X, double *Y, const SvDevInfo *info);
+// CSR of A^T (cols x rows; rows ascending within each row of A^T, FP64
+// values) by a stable radix sort; scratch holds csr_transpose_bytes bytes.
+size_t csr_transpose_bytes(int64_t nnz, int64_t cols);
+void csr_transpose(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz, const int64_t *rp,
+                   const int32_t *ci, const void *v, int vdt, int64_t *rpT, int32_t *ciT,
+                   double *vT, void *scratch, const SvDevInfo *info);
+// status = E_NUMERIC when any of x[0..n) is not finite (many blocks).
+void check_finite_wide(hipStream_t st, int64_t n, const double *x, SvDevInfo *info);
+// Out = L^{-1} of the L x L Gram G (L <= 128) with dropped columns (pivot <=
+// rtol * max diag) as zero rows, flagged in complete.
+void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *complete,
+               double rtol, const SvDevInfo *info);
+void fill_cols(hipStream_t st, int64_t R, int L, double *X, const int32_t *complete,
+               uint64_t seed, const SvDevInfo *info);
+// sig = sqrt(max(lam, 0)); X (R x k) columns scaled by 1/sig, or zeroed when
+// sig <= tol * sig_0.
+void inv_sigma_cols(hipStream_t st, int64_t R, int k, const double *lam, double *sig, double *X,
+                    double tol, const SvDevInfo *info);
+// Orthonormal basis of the columns of the R x L panel X in Y (X overwritten);
+// G, Out: L x L; complete: L; ws / ws_len: split-K scratch.
+void orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, double *G, double *Out,
+               int32_t *complete, double *ws, size_t ws_len, uint64_t seed, double rtol,
+               const SvDevInfo *info);
+
 // ---- eigen (k_eig.hip)
 // Top-k eigenpairs of a symmetric N x N FP64 matrix (A is destroyed):
 // lam[0..k) descending, Fv (k x N) row j = eigenvector of lam[j].

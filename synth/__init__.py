@@ -14,7 +14,7 @@ only the result ``A~ = U S V^T`` matters for every comparison downstream.
 from .sparse import (CSR, bernoulli_uniform, chung_lu_weights, chung_lu_graph,
                      zipf_ratings, lognormal_values, random_orthonormal,
                      synthetic_factors, randomized_init)
-from .workloads import (seed_children, config1_rows, config2_graph,
+from .workloads import (seed_children, config1_rows, config2_graph, config2_initial_matrix,
                         config3_ratings, config4_weights, config5_stream,
                         materialise_matrix, materialise_request, small_case)
 
@@ -22,6 +22,6 @@ __all__ = [
     "CSR", "bernoulli_uniform", "chung_lu_weights", "chung_lu_graph",
     "zipf_ratings", "lognormal_values", "random_orthonormal",
     "synthetic_factors", "randomized_init", "seed_children", "config1_rows",
-    "config2_graph", "config3_ratings", "config4_weights", "config5_stream",
+    "config2_graph", "config2_initial_matrix", "config3_ratings", "config4_weights", "config5_stream",
     "materialise_matrix", "materialise_request", "small_case",
 ]

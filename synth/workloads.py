@@ -68,6 +68,17 @@ def config2_graph(k: int = 64, n_init: int = 90000, step_nodes: int = 1000,
                 updates=ups, nnz_total=G.nnz)
 
 
+def config2_initial_matrix(n_init: int = 90000, step_nodes: int = 1000, steps: int = 10,
+                           avg_deg: float = 20.0, gamma: float = 2.1) -> CSR:
+    """The starting matrix of ``config2_graph`` (same seeds and sizes): the
+    adjacency of the induced subgraph on the first n_init nodes, without the
+    starting factors."""
+    N = n_init + steps * step_nodes
+    rngs = seed_children(2, 2)
+    G = chung_lu_graph(N, gamma, avg_deg, rngs[0]).to_scipy().tocsr()
+    return CSR.from_scipy(G[:n_init, :n_init])
+
+
 def config3_ratings(users: int = 500000, items: int = 50000,
                     nnz: int = 10_000_000, init_users: int = 400000,
                     k: int = 128, steps: int = 20, s: int = 5000,

@@ -65,6 +65,27 @@ def test_init_rejects_bad_arguments_before_device_use():
     assert lib.svlcov_add_rows(None, None) == 1
 
 
+def test_rsvd_rejects_bad_arguments_before_device_use():
+    import paper_2401_09703_amd as L
+    lib = L._lib
+    rp = np.zeros(41, np.int64)
+    keep = []
+    A = L._csr_struct(type("M", (), dict(rows=40, cols=30, row_ptr=rp,
+                                         col_idx=np.zeros(0, np.int32),
+                                         val=np.zeros(0)))(), keep)
+    buf = np.zeros(64)
+    p = buf.ctypes.data
+    call = lambda k, l, power, csr=A: lib.svlcov_rsvd(C.byref(csr), k, l, power, p, p, p, p,
+                                                      None, None)
+    assert call(8, 48, 1) == 7          # l outside {16, 32, 64, 128}
+    assert call(20, 16, 1) == 1         # k > l
+    assert call(8, 16, -1) == 1         # negative power
+    assert call(8, 32, 1) == 2          # l > min(m, n)
+    assert lib.svlcov_rsvd(None, 8, 16, 1, p, p, p, p, None, None) == 1
+    A.val_dtype = 5
+    assert call(8, 16, 1) == 1
+
+
 def test_server_rejects_bad_arguments_before_device_use():
     import paper_2401_09703_amd as L
     lib = L._lib
