@@ -262,14 +262,18 @@ k_stein(int N, const double *__restrict__ d, const double *__restrict__ e, int k
         }
       }
       __syncthreads();
-      for (int p = j0; p < j; ++p) {
-        const double *fp = Fv + (int64_t)p * N;
-        double dot = 0.0;
-        for (int c = lane; c < N; c += 64) dot += fp[c] * xs[c];
-        dot = wave_sum(dot);
-        for (int c = lane; c < N; c += 64) xs[c] -= dot * fp[c];
-        __syncthreads();
-      }
+      // against the earlier members of the cluster, twice: one pass leaves
+      // an error of the order of u times the cancellation, which for a
+      // (near-)degenerate cluster can be all of the vector
+      for (int pass = 0; pass < (j > j0 ? 2 : 0); ++pass)
+        for (int p = j0; p < j; ++p) {
+          const double *fp = Fv + (int64_t)p * N;
+          double dot = 0.0;
+          for (int c = lane; c < N; c += 64) dot += fp[c] * xs[c];
+          dot = wave_sum(dot);
+          for (int c = lane; c < N; c += 64) xs[c] -= dot * fp[c];
+          __syncthreads();
+        }
       double amax = 0.0;
       for (int c = lane; c < N; c += 64) amax = fmax(amax, fabs(xs[c]));
       amax = wave_max(amax);

@@ -164,77 +164,256 @@ __global__ void k_gather_T(int64_t nnz, const uint32_t *__restrict__ perm,
 }
 
 // ------------------------------------------------- panel orthonormalisation
-// Cholesky factor of the L x L Gram G (L <= 128) with column dropping, and
-// Out = L^{-1} with the rows of dropped columns zero, by one block of 256
-// threads.  Column j is dropped when its pivot (the squared norm of what is
-// left of the panel's column j after the earlier kept columns are taken out)
-// is at or below rtol times the largest diagonal entry of G; a dropped column
-// leaves the trailing matrix untouched.  complete[j] = 1 marks the dropped
-// columns.  Right-looking on the unscaled columns, one barrier per column;
-// the inverse by forward substitution with TPC threads per column.
-__global__ void __launch_bounds__(256)
+// Out = L^{-1} for the Cholesky factor L of the L x L Gram G (L <= 128), with
+// column dropping, by one block of CD_NT threads.  Symmetric elimination of G
+// applied to the identity beside it: after column j is eliminated, row i > j
+// of the augmented part holds row i of (unit lower L)^{-1} as far as it is
+// known, so at the end Out[i] = Aug[i] / sqrt(d_i) with d_i the pivots.
+// Column j is dropped when its pivot (the squared norm of what is left of the
+// panel's column j after the earlier kept columns are taken out) is at or
+// below rtol times the largest diagonal entry of G: it eliminates nothing,
+// and its row of Out is zero (complete[j] = 1).  One array of L x (L+1): the
+// trailing part of G in the lower triangle with the diagonal, the strict lower
+// part of Aug transposed into the strict upper triangle (Aug[i][c] at
+// S[c][i], the unit diagonal implicit).  Per column the update of the
+// trailing lower triangle (c > j) and of the augmented rows (c <= j) read
+// only column j of G and row j of Aug, which no thread writes in that step,
+// so one barrier per column suffices.
+constexpr int CD_NT = 1024;
+constexpr int CD_RW = (128 + CD_NT / 64 - 1) / (CD_NT / 64);   // rows per wave and column
+
+__global__ void __launch_bounds__(CD_NT)
 k_chol_drop(int L, const double *__restrict__ G, double *__restrict__ Out,
             int32_t *__restrict__ complete, double rtol, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  extern __shared__ double Ls[];   // L x (L+1): L below the diagonal, X^T above
+  extern __shared__ double S[];
   const int LD = L + 1;
-  double *dg = Ls + L * LD;        // L: pivots, then the diagonal of X
-  int *dr = (int *)(dg + L);       // L: dropped flags
-  __shared__ double red[4];
-  const int tid = threadIdx.x;
+  double *dg = S + L * LD;         // pivots
+  int *dr = (int *)(dg + L);       // dropped flags
+  __shared__ double red[CD_NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int NW = CD_NT / 64;
   double mx = 0.0;
-  for (int e = tid; e < L * L; e += 256) {
-    const int i = e / L, j = e % L;
-    if (j <= i) Ls[i * LD + j] = G[e];
-    if (i == j) mx = fmax(mx, G[e]);
+  for (int e = tid; e < L * L; e += CD_NT) {
+    const int i = e / L, c = e % L;
+    S[i * LD + c] = (c <= i) ? G[e] : 0.0;   // Aug starts as the identity
+    if (i == c) mx = fmax(mx, G[e]);
   }
   mx = block_max(mx, red);
   const double thr = rtol * mx;
   __syncthreads();
   for (int j = 0; j < L; ++j) {
-    const double d = Ls[j * LD + j];
+    const double d = S[j * LD + j];
     const bool drop = !(d > thr);
     if (!drop) {
+      // column j of G below the diagonal and row j of Aug (c < j): the two
+      // entries this lane needs, then the wave's row multipliers, all loaded
+      // before the first update
       const double invd = 1.0 / d;
-      for (int i = j + 1 + (tid >> 6); i < L; i += 4) {
-        const double lij = Ls[i * LD + j] * invd;
-        for (int c = j + 1 + (tid & 63); c <= i; c += 64) Ls[i * LD + c] -= lij * Ls[c * LD + j];
+      const int c0 = lane, c1 = lane + 64;
+      const double a0 = c0 < L ? S[c0 * LD + j] : 0.0;
+      const double a1 = c1 < L ? S[c1 * LD + j] : 0.0;
+      double li[CD_RW];
+#pragma unroll
+      for (int t = 0; t < CD_RW; ++t) {
+        const int i = j + 1 + w + NW * t;
+        li[t] = i < L ? S[i * LD + j] * invd : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < CD_RW; ++t) {
+        const int i = j + 1 + w + NW * t;
+        if (i >= L) break;
+        if (c0 <= i) {
+          if (c0 > j) S[i * LD + c0] -= li[t] * a0;
+          else if (c0 < j) S[c0 * LD + i] -= li[t] * a0;
+          else S[j * LD + i] = -li[t];
+        }
+        if (c1 <= i) {
+          if (c1 > j) S[i * LD + c1] -= li[t] * a1;
+          else if (c1 < j) S[c1 * LD + i] -= li[t] * a1;
+          else S[j * LD + i] = -li[t];
+        }
       }
     }
-    if (tid == 0) dr[j] = drop ? 1 : 0;
+    if (tid == 0) {
+      dg[j] = d;
+      dr[j] = drop ? 1 : 0;
+    }
     __syncthreads();
   }
-  for (int j = tid; j < L; j += 256) dg[j] = dr[j] ? 1.0 : sqrt(Ls[j * LD + j]);
-  __syncthreads();
-  for (int i = tid >> 6; i < L; i += 4)
-    for (int j = tid & 63; j <= i; j += 64)
-      Ls[i * LD + j] = (j < i) ? (dr[j] ? 0.0 : Ls[i * LD + j] / dg[j]) : dg[i];
-  __syncthreads();
-  // X = L^{-1}: column c = tid / TPC; its TPC lanes (one aligned group of a
-  // wave) split the terms p of x_i = (delta_ic - sum_{c<=p<i} L[i][p] x_p) /
-  // L[i][i].  X[p][c] lives at Ls[c][p] (p > c) or dg[c] (p = c).
-  int TPC = 1;
-  while (TPC < 64 && TPC * 2 * L <= 256) TPC *= 2;
-  const int c = tid / TPC, q = tid % TPC;
-  for (int i = 0; i < L; ++i) {
-    double acc = 0.0;
-    if (c < L && i > c)
-      for (int p = c + q; p < i; p += TPC) acc += Ls[i * LD + p] * (p == c ? dg[c] : Ls[c * LD + p]);
-    for (int o = 1; o < TPC; o <<= 1) acc += __shfl_xor(acc, o, 64);
-    if (c < L && q == 0 && i >= c) {
-      const double x = ((i == c ? 1.0 : 0.0) - acc) / Ls[i * LD + i];
-      if (i == c) dg[c] = x;
-      else Ls[c * LD + i] = x;
+  for (int e = tid; e < L * L; e += CD_NT) {
+    const int i = e / L, c = e % L;
+    double v = 0.0;
+    if (!dr[i] && c <= i) v = (c == i ? 1.0 : S[c * LD + i]) / sqrt(dg[i]);
+    Out[e] = v;
+  }
+  for (int j = tid; j < L; j += CD_NT) complete[j] = dr[j];
+}
+
+// -------------------------------------------- tall-skinny FP64 MFMA products
+// v_mfma_f64_16x16x4: A 16 x 4 with lane l holding A[l % 16][l / 16], B 4 x 16
+// with lane l holding B[l / 16][l % 16], D 16 x 16 with lane l holding
+// D[l / 16 + 4 q][l % 16] in element q (rows interleaved, unlike the FP32
+// 16 x 16 x 4 form).
+typedef double rv_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rv_d4 mfma_f64(double a, double b, rv_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Partial Grams of an R x L panel Y (L = 16 LT): block z sums Y_r^T Y_r over
+// its rows r in [z rpb, (z+1) rpb), for the NT = LT (LT+1)/2 lower 16 x 16
+// tiles only (tile t = ti (ti+1)/2 + tj, ti >= tj), into part[z][t][16][16].
+// Rows are staged TG_KC at a time in LDS (the next chunk is loaded into
+// registers while the current one is multiplied); wave w owns the tiles t
+// with t mod 4 = w, and every lane's operands for all tiles of a step of four
+// rows are the LT values Y[r][16 t + l % 16], r = step + l / 16.
+constexpr int TG_KC = 32;
+
+template <int L>
+__global__ void __launch_bounds__(256)
+k_ts_gram(int64_t R, int64_t rpb, const double *__restrict__ Y, double *__restrict__ part,
+          const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int LT = L / 16;
+  constexpr int NT = LT * (LT + 1) / 2;
+  constexpr int TW = (NT + 3) / 4;
+  constexpr int LDY = L + 8;
+  constexpr int PER = TG_KC * L / 2 / 256;   // 16-byte loads per thread and chunk
+  __shared__ double Ys[TG_KC * LDY];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  rv_d4 acc[TW];
+#pragma unroll
+  for (int u = 0; u < TW; ++u) acc[u] = rv_d4{0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int64_t r1 = r0 + rpb < R ? r0 + rpb : R;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  d2 nx[PER > 0 ? PER : 1];
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+      const int e = (h * 256 + tid) * 2;
+      const int rr = e / L, cc = e % L;
+      const int64_t r = c0 + rr;
+      nx[h] = r < r1 ? *(const d2 *)(Y + r * L + cc) : d2{0.0, 0.0};
     }
-    wave_sync();
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t c0 = r0; c0 < r1; c0 += TG_KC) {
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+      const int e = (h * 256 + tid) * 2;
+      *(d2 *)(Ys + (e / L) * LDY + e % L) = nx[h];
+    }
+    __syncthreads();
+    if (c0 + TG_KC < r1) fetch(c0 + TG_KC);
+#pragma unroll
+    for (int kk = 0; kk < TG_KC; kk += 4) {
+      double a[LT];
+#pragma unroll
+      for (int t = 0; t < LT; ++t) a[t] = Ys[(kk + lk) * LDY + t * 16 + li];
+#pragma unroll
+      for (int ti = 0; ti < LT; ++ti)
+#pragma unroll
+        for (int tj = 0; tj <= ti; ++tj) {
+          const int t = ti * (ti + 1) / 2 + tj;
+          if ((t & 3) == w) acc[t >> 2] = mfma_f64(a[ti], a[tj], acc[t >> 2]);
+        }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  for (int e = tid; e < L * L; e += 256) {
-    const int r = e / L, cc = e % L;
-    double v = cc < r ? Ls[cc * LD + r] : (cc == r ? dg[r] : 0.0);
-    Out[e] = dr[r] ? 0.0 : v;
+#pragma unroll
+  for (int u = 0; u < TW; ++u) {
+    const int t = 4 * u + w;
+    if (t < NT)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        part[((int64_t)blockIdx.x * NT + t) * 256 + (lk + 4 * q) * 16 + li] = acc[u][q];
   }
-  for (int j = tid; j < L; j += 256) complete[j] = dr[j];
+}
+
+// part2[s][e] = sum over z = s, s + S, s + 2S, ... < Z of part[z][e]
+// (e < NE); then G from the S slabs, both triangles (fixed order: identical
+// inputs give identical bits).
+__global__ void k_gram_reduce1(int Z, int S, int64_t NE, const double *__restrict__ part,
+                               double *__restrict__ part2, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
+  if (e >= NE) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int u = 0;
+  for (int z = s; z < Z; z += S, ++u) acc[u & 3] += part[(int64_t)z * NE + e];
+  part2[(int64_t)s * NE + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+__global__ void k_gram_reduce2(int L, int S, const double *__restrict__ part2,
+                               double *__restrict__ G, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int LT = L / 16, NT = LT * (LT + 1) / 2;
+  const int64_t NE = (int64_t)NT * 256;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= NE) return;
+  double v = 0.0;
+  for (int s = 0; s < S; ++s) v += part2[(int64_t)s * NE + e];
+  const int t = (int)(e >> 8), x = (int)(e & 255);
+  int ti = 0;
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int i = ti * 16 + (x >> 4), j = tj * 16 + (x & 15);
+  G[i * L + j] = v;
+  G[j * L + i] = v;
+}
+
+// Y = X Out^T for the R x L panel X and the lower-triangular L x L Out
+// (L = 16 LT): block = 64 rows, wave w its rows 16 w .. 16 w + 15 for all LT
+// column tiles.  The inner index runs in chunks of 16 staged in LDS (the
+// chunk of X and of Out); chunk c meets only column tiles tj >= c, since
+// Out[j][k] = 0 for k > j.
+template <int L>
+__global__ void __launch_bounds__(256)
+k_ts_mul_lt(int64_t R, const double *__restrict__ X, const double *__restrict__ Out,
+            double *__restrict__ Y, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int LT = L / 16;
+  constexpr int LD = 16 + 1;
+  __shared__ double Xs[64 * LD];
+  __shared__ double Os[L * LD];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  rv_d4 acc[LT];
+#pragma unroll
+  for (int t = 0; t < LT; ++t) acc[t] = rv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < LT; ++c) {
+    const int kc = 16 * c;
+    for (int e = tid; e < 64 * 16; e += 256) {
+      const int rr = e >> 4, cc = e & 15;
+      const int64_t r = r0 + rr;
+      Xs[rr * LD + cc] = r < R ? X[r * L + kc + cc] : 0.0;
+    }
+    for (int e = tid; e < L * 16; e += 256) {
+      const int j = e >> 4, cc = e & 15;
+      Os[j * LD + cc] = Out[j * L + kc + cc];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const double a = Xs[(w * 16 + li) * LD + kk + lk];
+#pragma unroll
+      for (int tj = c; tj < LT; ++tj) acc[tj] = mfma_f64(a, Os[(tj * 16 + li) * LD + kk + lk], acc[tj]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int tj = 0; tj < LT; ++tj)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = r0 + w * 16 + lk + 4 * q;
+      if (r < R) Y[r * L + tj * 16 + li] = acc[tj][q];
+    }
 }
 
 // Columns c of the R x L panel X with complete[c] set receive pseudo-random
@@ -360,6 +539,43 @@ void check_finite_wide(hipStream_t st, int64_t n, const double *x, SvDevInfo *in
                      x, info);
 }
 
+// Gram of a tall panel on FP64 MFMA; ws must hold ts_gram_ws(R, L) doubles.
+size_t ts_gram_ws(int64_t R, int L) {
+  const int LT = L / 16, NT = LT * (LT + 1) / 2;
+  const int64_t Z = std::min<int64_t>(256, std::max<int64_t>(1, (R + 127) / 128));
+  return (size_t)(Z + 16) * NT * 256;
+}
+
+void ts_gram(hipStream_t st, int64_t R, int L, const double *Y, double *G, double *ws,
+             const SvDevInfo *info) {
+  const int LT = L / 16, NT = LT * (LT + 1) / 2;
+  int64_t Z = std::min<int64_t>(256, std::max<int64_t>(1, (R + 127) / 128));
+  int64_t rpb = (R + Z - 1) / Z;
+  rpb = (rpb + TG_KC - 1) / TG_KC * TG_KC;
+  Z = std::max<int64_t>(1, (R + rpb - 1) / rpb);
+  const int S = (int)std::min<int64_t>(16, Z);
+  const int64_t NE = (int64_t)NT * 256;
+  double *part = ws, *part2 = ws + Z * NE;
+#define SV_TG(LL) hipLaunchKernelGGL((k_ts_gram<LL>), dim3((unsigned)Z), dim3(256), 0, st, R, rpb, \
+                                     Y, part, info)
+  switch (L) { case 16: SV_TG(16); break; case 32: SV_TG(32); break;
+               case 64: SV_TG(64); break; case 128: SV_TG(128); break; }
+#undef SV_TG
+  hipLaunchKernelGGL(k_gram_reduce1, dim3((unsigned)((NE + 255) / 256), (unsigned)S), dim3(256), 0,
+                     st, (int)Z, S, NE, part, part2, info);
+  hipLaunchKernelGGL(k_gram_reduce2, dim3((unsigned)((NE + 255) / 256)), dim3(256), 0, st, L, S,
+                     part2, G, info);
+}
+
+void ts_mul_lt(hipStream_t st, int64_t R, int L, const double *X, const double *Out, double *Y,
+               const SvDevInfo *info) {
+  const unsigned nb = (unsigned)((R + 63) / 64);
+#define SV_TM(LL) hipLaunchKernelGGL((k_ts_mul_lt<LL>), dim3(nb), dim3(256), 0, st, R, X, Out, Y, info)
+  switch (L) { case 16: SV_TM(16); break; case 32: SV_TM(32); break;
+               case 64: SV_TM(64); break; case 128: SV_TM(128); break; }
+#undef SV_TM
+}
+
 void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *complete,
                double rtol, const SvDevInfo *info) {
   static bool once = false;
@@ -369,7 +585,7 @@ void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *com
     once = true;
   }
   const size_t sh = (size_t)L * (L + 2) * sizeof(double) + (size_t)L * sizeof(int);
-  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(256), sh, st, L, G, Out, complete, rtol, info);
+  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(CD_NT), sh, st, L, G, Out, complete, rtol, info);
 }
 
 void fill_cols(hipStream_t st, int64_t R, int L, double *X, const int32_t *complete,
@@ -384,25 +600,34 @@ void inv_sigma_cols(hipStream_t st, int64_t R, int k, const double *lam, double 
                      lam, sig, X, tol, info);
 }
 
-// Orthonormal basis of the columns of the R x L panel X (R >= L), written to
-// Y; X is overwritten.  Three passes of Cholesky QR with column dropping: the
-// first keeps the columns that are independent to within rtol (squared,
-// relative to the largest column) and replaces the others by random columns,
-// the second restores orthogonality to rounding for kept columns of
-// condition number up to ~1/sqrt(u), the third does so for the random ones.
-// Without dropping the columns keep their order: column j of Y spans the
-// first j + 1 columns of X.
-void orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, double *G, double *Out,
-               int32_t *complete, double *ws, size_t ws_len, uint64_t seed, double rtol,
-               const SvDevInfo *info) {
-  for (int pass = 0; pass < 3; ++pass) {
-    double *src = (pass & 1) ? Y : X;
-    double *dst = (pass & 1) ? X : Y;
-    gemm_f64_sk(st, true, false, L, L, R, 1.0, src, L, src, L, 0.0, G, L, ws, ws_len, info);
+// Orthonormal basis of the columns of the R x L panel X (R >= L) by passes
+// of Cholesky QR with column dropping, alternating between X and Y; returns
+// the buffer that holds the result (Y after an odd number of passes, X after
+// an even one).  Each pass keeps the columns that are independent to within
+// rtol (squared, relative to the largest column) and replaces the others by
+// random columns, which in R >> L dimensions are nearly orthogonal to the
+// kept ones; one pass leaves a basis of condition number 1 + O(u kappa^2)
+// for kept columns of condition number kappa up to ~1/sqrt(rtol), which is
+// what a power iteration needs, and a second pass makes it orthonormal to
+// rounding.  Without dropping the columns keep their order: column j of the
+// result spans the first j + 1 columns of X.
+double *orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, int passes, double *G,
+                  double *Out, int32_t *complete, double *ws, size_t ws_len, uint64_t seed,
+                  double rtol, const SvDevInfo *info) {
+  double *src = X, *dst = Y;
+  const bool mf = (L == 16 || L == 32 || L == 64 || L == 128) && ws_len >= ts_gram_ws(R, L);
+  for (int pass = 0; pass < passes; ++pass) {
+    if (mf) ts_gram(st, R, L, src, G, ws, info);
+    else gemm_f64_sk(st, true, false, L, L, R, 1.0, src, L, src, L, 0.0, G, L, ws, ws_len, info);
     chol_drop(st, L, G, Out, complete, rtol, info);
-    gemm_f64(st, false, true, R, L, L, 1.0, src, L, Out, L, 0.0, dst, L, info);
+    if (mf) ts_mul_lt(st, R, L, src, Out, dst, info);
+    else gemm_f64(st, false, true, R, L, L, 1.0, src, L, Out, L, 0.0, dst, L, info);
     fill_cols(st, R, L, dst, complete, seed * 3 + (uint64_t)pass, info);
+    double *t = src;
+    src = dst;
+    dst = t;
   }
+  return src;
 }
 
 }  // namespace svl

@@ -219,11 +219,20 @@ void fill_cols(hipStream_t st, int64_t R, int L, double *X, const int32_t *compl
 // sig <= tol * sig_0.
 void inv_sigma_cols(hipStream_t st, int64_t R, int k, const double *lam, double *sig, double *X,
                     double tol, const SvDevInfo *info);
-// Orthonormal basis of the columns of the R x L panel X in Y (X overwritten);
-// G, Out: L x L; complete: L; ws / ws_len: split-K scratch.
-void orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, double *G, double *Out,
-               int32_t *complete, double *ws, size_t ws_len, uint64_t seed, double rtol,
+// G = Y^T Y (both triangles) for the R x L panel Y (L in {16..128}) on FP64
+// MFMA; ws holds ts_gram_ws(R, L) doubles.
+size_t ts_gram_ws(int64_t R, int L);
+void ts_gram(hipStream_t st, int64_t R, int L, const double *Y, double *G, double *ws,
+             const SvDevInfo *info);
+// Y = X Out^T for the R x L panel X and a lower-triangular L x L Out.
+void ts_mul_lt(hipStream_t st, int64_t R, int L, const double *X, const double *Out, double *Y,
                const SvDevInfo *info);
+// Orthonormal basis of the columns of the R x L panel X by `passes` passes
+// of Cholesky QR alternating between X and Y; returns the buffer holding the
+// result.  G, Out: L x L; complete: L; ws / ws_len: split-K scratch.
+double *orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, int passes, double *G,
+                  double *Out, int32_t *complete, double *ws, size_t ws_len, uint64_t seed,
+                  double rtol, const SvDevInfo *info);
 
 // ---- eigen (k_eig.hip)
 // Top-k eigenpairs of a symmetric N x N FP64 matrix (A is destroyed):

@@ -5,15 +5,18 @@
 //
 //   Q = orth(A Omega);  q times: Z = orth(A^T Q), Q = orth(A Z)
 //   W = A^T Q (= B^T for B = Q^T A);  W^T W = F diag(lambda) F^T
-//   U = Q F_k,  sigma = sqrt(lambda_k),  V = orth(W F_k diag(1/sigma))
+//   U = orth(Q F_k),  sigma = sqrt(lambda_k),  V = orth(W F_k diag(1/sigma))
 //
 // Every product with A or A^T is the CSR-times-panel kernel on the CSR of A
 // and on the CSR of A^T that the radix-sort transpose builds once; every
-// orth() is three passes of Cholesky QR with column dropping and random
-// completion; the l x l eigenproblem is the Rayleigh-Ritz eigensolver of the
+// orth() is Cholesky QR with column dropping and random completion (one pass
+// where the basis only feeds the next product, two where it becomes a
+// factor); the l x l eigenproblem is the Rayleigh-Ritz eigensolver of the
 // update path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "../../include/svlcov.h"
@@ -91,7 +94,7 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
   const bool host = A->on_device == 0;
 
   const size_t ewd = svl::eig_work_doubles(l, k);
-  const size_t ws_len = (size_t)64 * l * l;
+  const size_t ws_len = std::max((size_t)64 * l * l, svl::ts_gram_ws(std::max(m, n), l));
   size_t total = al(sizeof(SvDevInfo)) + al(svl::TRI_FLAG_WORDS * sizeof(unsigned));
   if (host) total += al((size_t)(m + 1) * 8) + al((size_t)nnz * 4) + al((size_t)nnz * vsz);
   total += al(svl::csr_transpose_bytes(nnz, n)) + al((size_t)(n + 1) * 8) + al((size_t)nnz * 4) +
@@ -153,17 +156,22 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
     tm.mark(1);
     svl::csr_dense(st, l, n, rpT, ciT, vT, SVLCOV_F64, X, Y, info);
   };
-  auto orth = [&](int64_t R, int L, double *X, double *Y) {
+  // an orthonormalisation that only feeds the next product needs a
+  // well-conditioned basis (one pass); the bases that become factors need
+  // two passes
+  auto orth = [&](int64_t R, int L, double *&X, double *&Y, int passes) {
     tm.mark(2);
-    svl::orth_cols(st, R, L, X, Y, G, Out, complete, ws, ws_len, ++seed, ORTH_RTOL, info);
+    double *r = svl::orth_cols(st, R, L, X, Y, passes, G, Out, complete, ws, ws_len, ++seed,
+                               ORTH_RTOL, info);
+    if (r != Y) std::swap(X, Y);   // the result is always left in Y
   };
   prod_A(Omega, Pm);
-  orth(m, l, Pm, Qm);
+  orth(m, l, Pm, Qm, power > 0 ? 1 : 2);
   for (int it = 0; it < power; ++it) {
     prod_AT(Qm, Pn);
-    orth(n, l, Pn, Qn);
+    orth(n, l, Pn, Qn, 1);
     prod_A(Qn, Pm);
-    orth(m, l, Pm, Qm);
+    orth(m, l, Pm, Qm, it == power - 1 ? 2 : 1);
   }
   prod_AT(Qm, Pn);   // W = A^T Q
   tm.mark(3);
@@ -171,11 +179,26 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
   unsigned epoch = 0;
   const int er = svl::eig_topk(st, l, G, k, lam, Fv, ework, flags, &epoch, info);
   tm.mark(4);
+  // U = Q F is orthonormal when F is; the vectors of a (near-)zero cluster
+  // of eigenvalues need not be, so U too gets two passes in column order
+  // (the columns of resolved singular values come first and stay as they are)
   svl::gemm_f64(st, false, true, m, k, l, 1.0, Qm, l, Fv, l, 0.0, U, k, info);
-  svl::gemm_f64(st, false, true, n, k, l, 1.0, Pn, l, Fv, l, 0.0, Qn, k, info);
-  svl::inv_sigma_cols(st, n, k, lam, sigma, Qn, SIGMA_TOL, info);
   tm.mark(2);
-  svl::orth_cols(st, n, k, Qn, V, G, Out, complete, ws, ws_len, ++seed, ORTH_RTOL, info);
+  {
+    double *ux = U, *uy = Pm;
+    (void)svl::orth_cols(st, m, k, ux, uy, 2, G, Out, complete, ws, ws_len, ++seed, ORTH_RTOL,
+                         info);
+  }
+  tm.mark(4);
+  svl::gemm_f64(st, false, true, n, k, l, 1.0, Pn, l, Fv, l, 0.0, V, k, info);
+  svl::inv_sigma_cols(st, n, k, lam, sigma, V, SIGMA_TOL, info);
+  tm.mark(2);
+  {   // two passes V -> Qn -> V
+    double *vx = V, *vy = Qn;
+    double *r = svl::orth_cols(st, n, k, vx, vy, 2, G, Out, complete, ws, ws_len, ++seed,
+                               ORTH_RTOL, info);
+    (void)r;   // == V
+  }
   tm.mark(4);
   svl::check_finite(st, k, sigma, info, 0);
   tm.mark(-1);

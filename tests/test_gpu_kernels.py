@@ -80,3 +80,21 @@ def test_ratings_size():
     M = X @ X.T
     M += np.diag(rng.uniform(0, 1, N))
     _check(M, k, tol_val=1e-11, tol_ang=1e-8)
+
+
+@pytest.mark.parametrize("N,r", [(16, 6), (32, 3), (64, 10), (128, 6)])
+def test_rank_deficient_grams_of_tall_panels(N, r):
+    """Grams W^T W of tall rank-r panels (as in the initial SVD's l x l
+    problem): the top-k vectors include a cluster of rounding-level
+    eigenvalues, whose vectors must still come out orthonormal."""
+    for seed in range(4):
+        rng = np.random.default_rng(1000 * N + 10 * r + seed)
+        W = rng.standard_normal((3000, r)) @ rng.standard_normal((r, N))
+        M = W.T @ W
+        k = 3 * N // 4
+        lam, V = _run(M, k)
+        w = np.linalg.eigvalsh(M)[::-1]
+        assert np.max(np.abs(lam - w[:k])) <= 1e-11 * w[0]
+        assert np.linalg.norm(V @ V.T - np.eye(k), 2) <= 1e-10
+        res = np.max(np.linalg.norm(M @ V.T - V.T * lam, axis=0)) / w[0]
+        assert res <= 1e-11
