@@ -55,31 +55,84 @@ k_radix_hist(int64_t nnz, const uint32_t *__restrict__ keys, int shift, int64_t 
   hist[(int64_t)tid * tiles + t] = h[tid];
 }
 
-// Exclusive prefix sum of n counts in place, by one block of 1024 threads:
-// each thread sums a contiguous chunk, the chunk sums are scanned in LDS, and
-// every thread rewrites its chunk.
-__global__ void __launch_bounds__(1024)
-k_scan_excl(int64_t n, uint32_t *__restrict__ a, const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
-  __shared__ uint32_t s[1024];
+// Exclusive prefix sum of n counts in place, in three launches: the sums of
+// tiles of SC_TILE counts, the scan of those sums (one block), and the scan
+// of every tile in LDS plus its offset.  All loads and stores are coalesced.
+constexpr int SC_NT = 256, SC_PER = 8, SC_TILE = SC_NT * SC_PER;
+
+__device__ __forceinline__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t *sh, uint32_t *total) {
+  // Hillis-Steele over the block's SC_NT values; sh holds SC_NT entries
   const int tid = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = (int64_t)tid * chunk, e = b + chunk < n ? b + chunk : n;
-  uint32_t sum = 0;
-  for (int64_t i = b; i < e; ++i) sum += a[i];
-  s[tid] = sum;
+  sh[tid] = v;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {   // Hillis-Steele inclusive scan
-    const uint32_t v = tid >= o ? s[tid - o] : 0u;
+  for (int o = 1; o < SC_NT; o <<= 1) {
+    const uint32_t x = tid >= o ? sh[tid - o] : 0u;
     __syncthreads();
-    s[tid] += v;
+    sh[tid] += x;
     __syncthreads();
   }
-  uint32_t run = s[tid] - sum;
-  for (int64_t i = b; i < e; ++i) {
-    const uint32_t x = a[i];
-    a[i] = run;
-    run += x;
+  const uint32_t incl = sh[tid];
+  *total = sh[SC_NT - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(SC_NT)
+k_scan_sums(int64_t n, const uint32_t *__restrict__ a, uint32_t *__restrict__ bsum,
+            const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ uint32_t sh[SC_NT];
+  const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  uint32_t s = 0;
+  for (int u = 0; u < SC_PER; ++u) {
+    const int64_t i = base + (int64_t)u * SC_NT + threadIdx.x;
+    if (i < n) s += a[i];
+  }
+  uint32_t tot;
+  (void)block_excl_scan_u32(s, sh, &tot);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(SC_NT)
+k_scan_bsum(int64_t nb, uint32_t *__restrict__ bsum, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ uint32_t sh[SC_NT];
+  uint32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += SC_NT) {
+    const int64_t i = b0 + threadIdx.x;
+    const uint32_t v = i < nb ? bsum[i] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_u32(v, sh, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+}
+
+__global__ void __launch_bounds__(SC_NT)
+k_scan_apply(int64_t n, uint32_t *__restrict__ a, const uint32_t *__restrict__ bsum,
+             const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  __shared__ uint32_t tile[SC_TILE];
+  __shared__ uint32_t sh[SC_NT];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SC_TILE;
+  for (int u = 0; u < SC_PER; ++u) {
+    const int64_t i = base + (int64_t)u * SC_NT + tid;
+    tile[u * SC_NT + tid] = i < n ? a[i] : 0u;
+  }
+  __syncthreads();
+  uint32_t loc[SC_PER], s = 0;
+  for (int u = 0; u < SC_PER; ++u) {   // thread tid owns counts [tid SC_PER, (tid+1) SC_PER)
+    loc[u] = s;
+    s += tile[tid * SC_PER + u];
+  }
+  uint32_t tot;
+  const uint32_t off = block_excl_scan_u32(s, sh, &tot) + bsum[blockIdx.x];
+  for (int u = 0; u < SC_PER; ++u) tile[tid * SC_PER + u] = off + loc[u];
+  __syncthreads();
+  for (int u = 0; u < SC_PER; ++u) {
+    const int64_t i = base + (int64_t)u * SC_NT + tid;
+    if (i < n) a[i] = tile[u * SC_NT + tid];
   }
 }
 
@@ -219,20 +272,25 @@ k_chol_drop(int L, const double *__restrict__ G, double *__restrict__ Out,
         const int i = j + 1 + w + NW * t;
         li[t] = i < L ? S[i * LD + j] * invd : 0.0;
       }
+      // the targets of this lane: (row i_t, column c0 / c1) in the trailing
+      // lower triangle (c > j), Aug[i_t][c] at S[c][i_t] (c < j), or
+      // Aug[i_t][j] (c = j, overwritten); all loaded before any store
+      int o0[CD_RW], o1[CD_RW];
+      double v0[CD_RW], v1[CD_RW];
 #pragma unroll
       for (int t = 0; t < CD_RW; ++t) {
         const int i = j + 1 + w + NW * t;
-        if (i >= L) break;
-        if (c0 <= i) {
-          if (c0 > j) S[i * LD + c0] -= li[t] * a0;
-          else if (c0 < j) S[c0 * LD + i] -= li[t] * a0;
-          else S[j * LD + i] = -li[t];
-        }
-        if (c1 <= i) {
-          if (c1 > j) S[i * LD + c1] -= li[t] * a1;
-          else if (c1 < j) S[c1 * LD + i] -= li[t] * a1;
-          else S[j * LD + i] = -li[t];
-        }
+        o0[t] = -1;
+        o1[t] = -1;
+        if (i < L && c0 <= i) o0[t] = c0 > j ? i * LD + c0 : (c0 < j ? c0 * LD + i : j * LD + i);
+        if (i < L && c1 <= i) o1[t] = c1 > j ? i * LD + c1 : (c1 < j ? c1 * LD + i : j * LD + i);
+        v0[t] = (o0[t] >= 0 && c0 != j) ? S[o0[t]] : 0.0;
+        v1[t] = (o1[t] >= 0 && c1 != j) ? S[o1[t]] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < CD_RW; ++t) {
+        if (o0[t] >= 0) S[o0[t]] = c0 == j ? -li[t] : v0[t] - li[t] * a0;
+        if (o1[t] >= 0) S[o1[t]] = c1 == j ? -li[t] : v1[t] - li[t] * a1;
       }
     }
     if (tid == 0) {
@@ -416,6 +474,174 @@ k_ts_mul_lt(int64_t R, const double *__restrict__ X, const double *__restrict__ 
     }
 }
 
+// The same factor and inverse for L = 16 NB (L <= 128) in 16 x 16 blocks,
+// by one block of CB_NT threads, the block updates on FP64 MFMA.  Per block
+// column b: wave 0 factors the diagonal block (right-looking, with the same
+// dropping rule) and inverts it into X'_bb (the rows of dropped columns zero);
+// the panel below becomes L_rb = A_rb X'_bb^T (which leaves the columns of
+// dropped pivots zero); the trailing lower tiles take A_rc -= L_rb L_cb^T.
+// Then block rows of X' = L^{-1} (dropped rows zero) follow from
+// X'_ij = -X'_ii sum_{k=j}^{i-1} L_ik X'_kj.  S holds L in its lower triangle
+// and X'^T strictly above the diagonal; dg the diagonal of X'.
+constexpr int CB_NT = 512;
+constexpr int CB_NW = CB_NT / 64;
+
+__global__ void __launch_bounds__(CB_NT)
+k_chol_drop_blk(int L, const double *__restrict__ G, double *__restrict__ Out,
+                int32_t *__restrict__ complete, double rtol, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  extern __shared__ double S[];
+  const int LD = L + 1, NB = L / 16;
+  double *dg = S + L * LD;              // diagonal of X'
+  double *piv = dg + L;                 // pivots
+  double *wsc = piv + L;                // CB_NW scratch tiles of 16 x 17
+  int *dr = (int *)(wsc + CB_NW * 16 * 17);
+  __shared__ double red[CB_NW];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double mx = 0.0;
+  for (int e = tid; e < L * L; e += CB_NT) {
+    const int i = e / L, c = e % L;
+    S[i * LD + c] = (c <= i) ? G[e] : 0.0;
+    if (i == c) mx = fmax(mx, G[e]);
+  }
+  mx = block_max(mx, red);
+  const double thr = rtol * mx;
+  __syncthreads();
+  for (int b = 0; b < NB; ++b) {
+    const int o = 16 * b;
+    if (w == 0) {
+      // the diagonal block, four of its 256 entries per lane
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = o + jj;
+        const double d = S[j * LD + j];
+        const bool drop = !(d > thr);
+        if (!drop) {
+          const double invd = 1.0 / d;
+          int idx[4];
+          double upd[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u, i = e >> 4, c = e & 15;
+            const bool on = i > jj && c > jj && c <= i;
+            idx[u] = on ? (o + i) * LD + o + c : -1;
+            upd[u] = on ? S[(o + i) * LD + j] * S[(o + c) * LD + j] * invd : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (idx[u] >= 0) S[idx[u]] -= upd[u];
+        }
+        if (lane == 0) {
+          dr[j] = drop ? 1 : 0;
+          piv[j] = d;
+        }
+        wave_sync();
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u, i = e >> 4, c = e & 15;
+        double *x = &S[(o + i) * LD + o + c];
+        if (c < i) *x = dr[o + c] ? 0.0 : *x / sqrt(piv[o + c]);
+        else if (c == i) *x = dr[o + i] ? 1.0 : sqrt(piv[o + i]);
+      }
+      wave_sync();
+      if (lane < 16) {   // column c of L_bb^{-1} by forward substitution
+        const int c = lane;
+        double x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          double acc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+          for (int p = 0; p < i; ++p) acc -= S[(o + i) * LD + o + p] * x[p];
+          x[i] = i < c ? 0.0 : acc / S[(o + i) * LD + o + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          if (i < c) continue;
+          const double v = dr[o + i] ? 0.0 : x[i];
+          if (i == c) dg[o + c] = v;
+          else S[(o + c) * LD + o + i] = v;
+        }
+      }
+    }
+    __syncthreads();
+    // L_rb = A_rb X'_bb^T: B[k][n] = X'_bb[n][k]
+    for (int rb = b + 1 + w; rb < NB; rb += CB_NW) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 4 * s4 + lk, n = li;
+        av[s4] = S[(16 * rb + li) * LD + o + k];
+        bv[s4] = (k == n) ? dg[o + n] : (k < n ? S[(o + k) * LD + o + n] : 0.0);
+      }
+      rv_d4 acc = rv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) acc = mfma_f64(av[s4], bv[s4], acc);
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S[(16 * rb + lk + 4 * q) * LD + o + li] = acc[q];
+    }
+    __syncthreads();
+    // A_rc -= L_rb L_cb^T for b < c <= r
+    {
+      int t = 0;
+      for (int r = b + 1; r < NB; ++r)
+        for (int c = b + 1; c <= r; ++c, ++t) {
+          if (t % CB_NW != w) continue;
+          rv_d4 acc;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] = S[(16 * r + lk + 4 * q) * LD + 16 * c + li];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int k = 4 * s4 + lk;
+            acc = mfma_f64(-S[(16 * r + li) * LD + o + k], S[(16 * c + li) * LD + o + k], acc);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) S[(16 * r + lk + 4 * q) * LD + 16 * c + li] = acc[q];
+        }
+    }
+    __syncthreads();
+  }
+  // block rows of X' below the diagonal
+  double *wt = wsc + w * 16 * 17;
+  for (int i = 1; i < NB; ++i) {
+    for (int j = w; j < i; j += CB_NW) {
+      rv_d4 T = rv_d4{0.0, 0.0, 0.0, 0.0};
+      for (int k = j; k < i; ++k) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int q = 4 * s4 + lk, n = li;
+          const double a = S[(16 * i + li) * LD + 16 * k + q];
+          double bq;
+          if (k == j) bq = q == n ? dg[16 * j + q] : (q > n ? S[(16 * j + n) * LD + 16 * j + q] : 0.0);
+          else bq = S[(16 * j + n) * LD + 16 * k + q];
+          T = mfma_f64(a, bq, T);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) wt[(lk + 4 * q) * 17 + li] = T[q];
+      wave_sync();
+      rv_d4 X = rv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int kq = 4 * s4 + lk;
+        const double xi = li == kq ? dg[16 * i + li]
+                                   : (li > kq ? S[(16 * i + kq) * LD + 16 * i + li] : 0.0);
+        X = mfma_f64(-xi, wt[kq * 17 + li], X);
+      }
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S[(16 * j + li) * LD + 16 * i + lk + 4 * q] = X[q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < L * L; e += CB_NT) {
+    const int i = e / L, c = e % L;
+    Out[e] = c > i ? 0.0 : (c == i ? dg[i] : S[c * LD + i]);
+  }
+  for (int j = tid; j < L; j += CB_NT) complete[j] = dr[j];
+}
+
 // Columns c of the R x L panel X with complete[c] set receive pseudo-random
 // entries of variance 1 / R (uniform on [-sqrt(3/R), sqrt(3/R)]).
 __global__ void k_fill_cols(int64_t R, int L, double *__restrict__ X,
@@ -489,8 +715,9 @@ namespace svl {
 
 size_t csr_transpose_bytes(int64_t nnz, int64_t n) {
   const int64_t tiles = (nnz + RS_TILE - 1) / RS_TILE;
-  return (size_t)nnz * (4 * sizeof(uint32_t) + sizeof(int32_t)) +
-         (size_t)(tiles > 0 ? tiles : 1) * RS_DIG * sizeof(uint32_t) + 1024;
+  const int64_t nh = (tiles > 0 ? tiles : 1) * RS_DIG;
+  return (size_t)nnz * (4 * sizeof(uint32_t) + sizeof(int32_t)) + (size_t)nh * sizeof(uint32_t) +
+         (size_t)((nh + SC_TILE - 1) / SC_TILE + 1) * sizeof(uint32_t) + 1024;
 }
 
 void csr_transpose(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz, const int64_t *rp,
@@ -504,6 +731,7 @@ void csr_transpose(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz, cons
   uint32_t *pb = (uint32_t *)p; p += (size_t)nnz * sizeof(uint32_t);
   int32_t *rid = (int32_t *)p; p += (size_t)nnz * sizeof(int32_t);
   uint32_t *hist = (uint32_t *)p;
+  uint32_t *bsum = hist + (tiles > 0 ? tiles : 1) * RS_DIG;
   if (nnz > 0) {
     hipLaunchKernelGGL(k_row_ids, dim3(grid_for(rows, 4, 1 << 20)), dim3(256), 0, st, rows, nnz,
                        rp, rid, info);
@@ -517,7 +745,10 @@ void csr_transpose(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz, cons
       uint32_t *pout = (ps & 1) ? pb : pa;
       hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)tiles), dim3(RS_NT), 0, st, nnz, kin,
                          8 * ps, tiles, hist, info);
-      hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, tiles * RS_DIG, hist, info);
+      const int64_t nh = tiles * RS_DIG, nb = (nh + SC_TILE - 1) / SC_TILE;
+      hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SC_NT), 0, st, nh, hist, bsum, info);
+      hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(SC_NT), 0, st, nb, bsum, info);
+      hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SC_NT), 0, st, nh, hist, bsum, info);
       hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(RS_NT), 0, st, nnz, kin, pin,
                          8 * ps, tiles, hist, kout, pout, info);
       kin = kout;
@@ -583,6 +814,19 @@ void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *com
     allow_big_lds(k_chol_drop);
     (void)hipGetLastError();
     once = true;
+  }
+  static bool once_b = false;
+  if (!once_b) {
+    allow_big_lds(k_chol_drop_blk);
+    (void)hipGetLastError();
+    once_b = true;
+  }
+  if (L % 16 == 0 && L <= 128) {
+    const size_t shb = ((size_t)L * (L + 3) + (size_t)CB_NW * 16 * 17) * sizeof(double) +
+                       (size_t)L * sizeof(int);
+    hipLaunchKernelGGL(k_chol_drop_blk, dim3(1), dim3(CB_NT), shb, st, L, G, Out, complete, rtol,
+                       info);
+    return;
   }
   const size_t sh = (size_t)L * (L + 2) * sizeof(double) + (size_t)L * sizeof(int);
   hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(CD_NT), sh, st, L, G, Out, complete, rtol, info);

@@ -21,29 +21,36 @@ __device__ __forceinline__ void fail(SvDevInfo *info, int code, int seq) {
 }
 
 // Canonical-CSR check (0-based, monotone row_ptr, strictly increasing
-// in-range column ids per row, finite values).  Every access is bounded by
-// the declared nnz, so a malformed row_ptr cannot push reads out of range.
-__global__ void k_validate_csr(int64_t rows, int64_t cols, int64_t nnz,
-                               const int64_t *__restrict__ row_ptr,
-                               const int32_t *__restrict__ col_idx,
-                               const void *__restrict__ val, int vdtype,
-                               SvDevInfo *info, int seq) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  if (tid == 0) {
+// in-range column ids per row, finite values), one wave per row with the
+// row's entries spread over the lanes (each lane compares its entry with the
+// one before it).  Every access is bounded by the declared nnz, so a
+// malformed row_ptr cannot push reads out of range.  Within a row a
+// structural error is reported before a non-finite value.
+__global__ void __launch_bounds__(256)
+k_validate_csr(int64_t rows, int64_t cols, int64_t nnz, const int64_t *__restrict__ row_ptr,
+               const int32_t *__restrict__ col_idx, const void *__restrict__ val, int vdtype,
+               SvDevInfo *info, int seq) {
+  const int lane = threadIdx.x & 63;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (row_ptr[0] != 0 || row_ptr[rows] != nnz) fail(info, 1, seq);
   }
-  for (int64_t i = tid; i < rows; i += stride) {
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < rows;
+       i += (int64_t)gridDim.x * 4) {
     const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-    if (p0 < 0 || p1 < p0 || p1 > nnz) { fail(info, 1, seq); continue; }
-    int32_t prev = -1;
-    for (int64_t p = p0; p < p1; ++p) {
-      const int32_t c = col_idx[p];
-      if (c <= prev || c >= cols) { fail(info, 1, seq); break; }
-      prev = c;
-      const double v = vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
-      if (!isfinite(v)) { fail(info, 4, seq); break; }
+    if (p0 < 0 || p1 < p0 || p1 > nnz) {
+      if (lane == 0) fail(info, 1, seq);
+      continue;
     }
+    bool bad_s = false, bad_v = false;
+    for (int64_t p = p0 + lane; p < p1; p += 64) {
+      const int32_t c = col_idx[p];
+      const int32_t prev = p > p0 ? col_idx[p - 1] : -1;
+      bad_s |= c <= prev || c >= cols;
+      const double v = vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
+      bad_v |= !isfinite(v);
+    }
+    const bool any_s = __ballot(bad_s) != 0, any_v = __ballot(bad_v) != 0;
+    if (lane == 0 && (any_s || any_v)) fail(info, any_s ? 1 : 4, seq);
   }
 }
 
@@ -507,9 +514,9 @@ namespace svl {
 void validate_csr(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz,
                   const int64_t *rp, const int32_t *ci, const void *v, int vdt,
                   SvDevInfo *info, int seq) {
-  int64_t blocks = (rows + 255) / 256;
+  int64_t blocks = (rows + 3) / 4;
   if (blocks < 1) blocks = 1;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)blocks), dim3(256), 0, st,
                      rows, cols, nnz, rp, ci, v, vdt, info, seq);
 }

@@ -175,7 +175,7 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
   }
   prod_AT(Qm, Pn);   // W = A^T Q
   tm.mark(3);
-  svl::gemm_f64_sk(st, true, false, l, l, n, 1.0, Pn, l, Pn, l, 0.0, G, l, ws, ws_len, info);
+  svl::ts_gram(st, n, l, Pn, G, ws, info);   // W^T W, both triangles
   unsigned epoch = 0;
   const int er = svl::eig_topk(st, l, G, k, lam, Fv, ework, flags, &epoch, info);
   tm.mark(4);
