@@ -172,6 +172,15 @@ svlcov_status svlcov_add_rows_approx(svlcov_state *h, const svlcov_csr *E_r,
                                      const svlcov_approx *a);
 svlcov_status svlcov_add_cols_approx(svlcov_state *h, const svlcov_csr *E_c_T,
                                      const svlcov_approx *a);
+/* The same variants for the weight form A + D E_m^T (the appendix's weight
+ * algorithm): a_D gives the method, l, t and start of the basis of the
+ * augmented space of D against U, a_E those of E_m against V (the two may
+ * differ); K = [[Sigma, 0], [0, 0]] + [U^T D ; P_D^T] [V^T E_m ; P_E^T]^T is
+ * (k + l_D) x (k + l_E), each l clamped to s.  Arguments, errors and the
+ * asynchronous behaviour are those of svlcov_update_weights. */
+svlcov_status svlcov_update_weights_approx(svlcov_state *h, const svlcov_csr *D_T,
+                                           const svlcov_csr *E_m_T, const svlcov_approx *a_D,
+                                           const svlcov_approx *a_E);
 
 /* Realise and return the factors U = U_base W_U (m x k), sigma (k) and
  * V = V_base W_V (n x k).  Any output pointer may be NULL; m, n, k receive the

@@ -118,7 +118,7 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_server_destroy", "svlcov_project_batch", "svlcov_add_rows_approx",
            "svlcov_add_cols_approx", "svlcov_spmm_variant_count", "svlcov_spmm_variant_shape",
            "svlcov_spmm_tune_set", "svlcov_spmm_tune_get", "svlcov_query_rows",
-           "svlcov_score_pairs", "svlcov_rsvd"]
+           "svlcov_score_pairs", "svlcov_rsvd", "svlcov_update_weights_approx"]
 NUM_PHASES = 16
 RSVD_PHASES = ("transpose", "products", "orthonormalise", "small_eig", "final")
 
@@ -143,6 +143,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_spmm_tune_get.argtypes = [I32, I32, I32, C.POINTER(I32)]
     lib.svlcov_add_rows_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Approx)]
     lib.svlcov_add_cols_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Approx)]
+    lib.svlcov_update_weights_approx.argtypes = [P, C.POINTER(_Csr), C.POINTER(_Csr),
+                                                 C.POINTER(_Approx), C.POINTER(_Approx)]
+    lib.svlcov_update_weights_approx.restype = I32
     lib.svlcov_get_factors.argtypes = [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), I32,
                                        I32, P, P, P]
     lib.svlcov_query_row.argtypes = [P, I32, I64, P]
@@ -351,11 +354,26 @@ class TruncatedSVD:
             _check(_lib.svlcov_add_cols_approx(self._h, C.byref(st), C.byref(a)),
                    "svlcov_add_cols_approx")
 
-    def update_weights(self, D_T, Em_T):
+    def update_weights(self, D_T, Em_T, approx=None):
+        """A + D E_m^T; with approx (an Approx for both sides, whose start may
+        be a pair (start for D, start for E_m), or a pair of Approx) the -GKL
+        / -RPI variant."""
         a = _csr_struct(D_T, self._keep)
         b = _csr_struct(Em_T, self._keep)
-        _check(_lib.svlcov_update_weights(self._h, C.byref(a), C.byref(b)),
-               "svlcov_update_weights")
+        if approx is None:
+            _check(_lib.svlcov_update_weights(self._h, C.byref(a), C.byref(b)),
+                   "svlcov_update_weights")
+            return
+        if isinstance(approx, (tuple, list)):
+            aD, aE = approx
+        elif isinstance(approx.start, (tuple, list)):
+            aD = Approx(approx.method, approx.l, approx.t, approx.start[0])
+            aE = Approx(approx.method, approx.l, approx.t, approx.start[1])
+        else:
+            aD = aE = approx
+        sD, sE = aD._struct(self._keep), aE._struct(self._keep)
+        _check(_lib.svlcov_update_weights_approx(self._h, C.byref(a), C.byref(b), C.byref(sD),
+                                                 C.byref(sE)), "svlcov_update_weights_approx")
 
     def apply(self, update, approx: "Approx" = None):
         kind = update[0]
@@ -364,9 +382,7 @@ class TruncatedSVD:
         elif kind == "cols":
             self.add_cols(update[1], approx)
         elif kind == "weights":
-            if approx is not None:
-                raise NotImplementedError("the variants are built for the append forms")
-            self.update_weights(update[1], update[2])
+            self.update_weights(update[1], update[2], approx)
         else:
             raise ValueError(kind)
 

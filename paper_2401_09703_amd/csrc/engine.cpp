@@ -786,6 +786,242 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
   return SVLCOV_OK;
 }
 
+// The -GKL / -RPI variant of the weight form (the appendix's weight
+// algorithm): one l-dimensional basis Q_D = Z_D Y_D^T of the augmented space
+// of D against U and one Q_E of E_m against V, each in coefficient space on
+// its residual Gram as in the append variants; K_w = [C_D; P_D^T] [C_E;
+// P_E^T]^T + diag(Sigma, 0) of (k + l_D) x (k + l_E); SVD_k of K_w through
+// K_w^T K_w; then both sides are updated as sparse sides with Y = Yc^T X[k:]
+// in place of the Cholesky solve.
+bool approx_ok(const svlcov_approx *ap) {
+  if (!ap || (ap->method != SVLCOV_APPROX_GKL && ap->method != SVLCOV_APPROX_RPI) || ap->l < 1 ||
+      ap->l > svl::AP_LMAX)
+    return false;
+  if (ap->method == SVLCOV_APPROX_RPI && (!ap->start || ap->t < 1 || ap->t > 16)) return false;
+  return true;
+}
+
+template <typename T>
+svlcov_status op_weights_approx(svlcov_state *h, const svlcov_csr *D, const svlcov_csr *Em,
+                                const svlcov_approx *apD, const svlcov_approx *apE) {
+  svlcov_status r = check_csr_header(D);
+  if (r != SVLCOV_OK) return r;
+  r = check_csr_header(Em);
+  if (r != SVLCOV_OK) return r;
+  if (!approx_ok(apD) || !approx_ok(apE)) return SVLCOV_E_INVALID;
+  const int K = h->k;
+  if (D->rows != Em->rows) return SVLCOV_E_SHAPE;
+  if (D->cols != h->m || Em->cols != h->n) return SVLCOV_E_SHAPE;
+  const int64_t s = D->rows;
+  if (s == 0) return SVLCOV_OK;
+  const svlcov_approx *ap[2] = {apD, apE};
+  int lq[2];
+  for (int q = 0; q < 2; ++q) lq[q] = (int)(ap[q]->l < s ? ap[q]->l : s);
+  const int64_t ND = K + lq[0], NE = K + lq[1], N0 = K + s;
+  if (ND > svl::eig_max_n() || NE > svl::eig_max_n() || s > svl::gram_max_rows())
+    return SVLCOV_E_UNSUPPORTED;
+  if (!D->on_device) { r = check_host_csr(D); if (r != SVLCOV_OK) return r; }
+  if (!Em->on_device) { r = check_host_csr(Em); if (r != SVLCOV_OK) return r; }
+  const svlcov_csr *Eq[2] = {D, Em};
+  const size_t dws_want = (size_t)s * (8192 + 1);
+  size_t dws_len = 1;
+  for (int q = 0; q < 2; ++q)
+    if (svl::gram_dense_block(s, Eq[q]->cols, Eq[q]->nnz, dws_want) > 0) dws_len = dws_want;
+  const int64_t nnz_max = D->nnz > Em->nnz ? D->nnz : Em->nnz;
+  struct Side {
+    double *Cp64, *rown, *Gm, *Pv, *Yc, *gv, *ab, *Xl, *Tl, *Gm2, *Om, *XT, *Y, *M;
+    float *Cp32;
+    int32_t *brk;
+  } sd[2];
+  struct Shared {
+    double *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *T1, *WnU, *WiU, *WnV, *WiV, *orthw, *Dws;
+    int32_t *complete, *flags, *rid;
+  } b;
+  auto layout = [&](Carver &cv) {
+    for (int q = 0; q < 2; ++q) {
+      const int l = lq[q];
+      sd[q].Cp64 = cv.take<double>(s * K);
+      sd[q].Cp32 = cv.take<float>(s * K);
+      sd[q].rown = cv.take<double>(s);
+      sd[q].Gm = cv.take<double>(s * s);
+      sd[q].Pv = cv.take<double>((int64_t)(l + 1) * s);
+      sd[q].Yc = cv.take<double>((int64_t)l * s);
+      sd[q].gv = cv.take<double>(s);
+      sd[q].ab = cv.take<double>(2 * svl::AP_LMAX);
+      sd[q].brk = cv.take<int32_t>(1);
+      sd[q].Xl = cv.take<double>((int64_t)l * s);
+      sd[q].Tl = cv.take<double>((int64_t)l * s);
+      sd[q].Gm2 = cv.take<double>((int64_t)l * l);
+      sd[q].Om = cv.take<double>((int64_t)l * l);
+      sd[q].XT = cv.take<double>(s * (K + l));
+      sd[q].Y = cv.take<double>(s * K);
+      sd[q].M = cv.take<double>(s * K);
+    }
+    b.Kmat = cv.take<double>(ND * NE);
+    b.Mmat = cv.take<double>(NE * NE);
+    b.lam = cv.take<double>(K);
+    b.theta = cv.take<double>(K);
+    b.complete = cv.take<int32_t>(K);
+    b.Fv = cv.take<double>(K * ND);
+    b.Gv = cv.take<double>(K * NE);
+    b.eigw = cv.take<double>(svl::eig_work_doubles(NE, K));
+    b.T1 = cv.take<double>(K * K);
+    b.WnU = cv.take<double>(K * K);
+    b.WiU = cv.take<double>(K * K);
+    b.WnV = cv.take<double>(K * K);
+    b.WiV = cv.take<double>(K * K);
+    b.flags = cv.take<int32_t>(2);
+    b.orthw = cv.take<double>(2 * K * K + 9 * K * N0);
+    b.rid = cv.take<int32_t>(nnz_max > 0 ? nnz_max : 1);
+    b.Dws = cv.take<double>(dws_len);
+  };
+  Carver c{nullptr};
+  layout(c);
+  r = ensure(h, h->ws, c.off);
+  if (r != SVLCOV_OK) return r;
+  r = ensure(h, h->stage, csr_stage_bytes(D) + csr_stage_bytes(Em) + 512);
+  if (r != SVLCOV_OK) return r;
+  Carver c2{(char *)h->ws.p};
+  layout(c2);
+  char *cursor = (char *)h->stage.p;
+  DevCsr dq[2];
+  r = to_device(h, D, cursor, &dq[0]);
+  if (r != SVLCOV_OK) return r;
+  r = to_device(h, Em, cursor, &dq[1]);
+  if (r != SVLCOV_OK) return r;
+  hipStream_t st = h->stream;
+  for (int q = 0; q < 2; ++q) {   // start vectors as in the append variants
+    const svlcov_approx *a = ap[q];
+    if (!a->start) continue;
+    const bool gkl = a->method == SVLCOV_APPROX_GKL;
+    const hipMemcpyKind kind = a->start_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    double *dst = gkl ? sd[q].gv : sd[q].Pv;
+    const size_t bytes = (size_t)(gkl ? s : (int64_t)lq[q] * s) * sizeof(double);
+    if (!a->start_on_device)
+      for (int64_t e = 0; e < (int64_t)(bytes / 8); ++e)
+        if (!std::isfinite(a->start[e])) return SVLCOV_E_NUMERIC;
+    SV_TRY(hipMemcpyAsync(dst, a->start, bytes, kind, st));
+  }
+
+  h->seq += 1;
+  h->history.push_back({h->seq, h->m, h->n});
+  if (h->validate) {
+    PhaseScope ps(h, PH_VALIDATE);
+    for (int q = 0; q < 2; ++q)
+      if (Eq[q]->on_device)
+        svl::validate_csr(st, dq[q].rows, dq[q].cols, dq[q].nnz, dq[q].rp, dq[q].ci, dq[q].v,
+                          dq[q].vdt, h->info, h->seq);
+  }
+  svl::op_begin(st, h->info, 1);
+  T *Ub = (T *)h->Ubase, *Vb = (T *)h->Vbase;
+  const T *baseq[2] = {Ub, Vb};
+  const double *Wq[2] = {h->WU, h->WV};
+  double *gws = b.orthw + 2 * K * K + K * N0;
+  const size_t gws_len = (size_t)8 * K * N0;
+  for (int q = 0; q < 2; ++q) {
+    const int l = lq[q];
+    orthogonalise<T>(h, dq[q], baseq[q], Wq[q], sd[q].Cp64, sd[q].Cp32, sd[q].rown, sd[q].Gm,
+                     nullptr, b.rid, q, false, dws_len > 1 ? b.Dws : nullptr,
+                     dws_len > 1 ? dws_len : 0);
+    // the basis reads its drop scale from the first slot
+    if (q == 1) svl::max_into(st, s, sd[q].rown, h->info, 0);
+    PhaseScope ps(h, PH_CHOL);
+    svl::sym_lower(st, s, sd[q].Gm, s, h->info);
+    const bool gkl = ap[q]->method == SVLCOV_APPROX_GKL;
+    if (gkl)
+      svl::gkl_basis(st, s, l, sd[q].Gm, s, ap[q]->start ? sd[q].gv : nullptr, sd[q].Pv, sd[q].Yc,
+                     sd[q].gv, sd[q].ab, sd[q].brk, h->rank_tol, h->info);
+    else
+      svl::rpi_basis(st, s, l, ap[q]->t, sd[q].Gm, s, sd[q].Pv, sd[q].Yc, sd[q].Xl, sd[q].Tl,
+                     sd[q].Gm2, sd[q].Om, gws, gws_len, h->rank_tol, h->info);
+    // XT = [C' | P] (s x (k + l)), P = Z^T Q
+    svl::copy_strided(st, s, K, sd[q].Cp64, K, 1, sd[q].XT, K + l, h->info);
+    if (gkl)
+      svl::gkl_pblock(st, s, l, sd[q].Pv, sd[q].ab, sd[q].XT, K + l, 0, K, h->info);
+    else
+      svl::rows_to_block(st, s, l, sd[q].Pv, sd[q].XT, K + l, 0, K, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_BUILDK);   // K_w = XT_D^T XT_E + diag(Sigma, 0)
+    svl::gemm_f64_sk(st, true, false, ND, NE, s, 1.0, sd[0].XT, ND, sd[1].XT, NE, 0.0, b.Kmat, NE,
+                     gws, gws_len, h->info);
+    svl::add_sigma_diag(st, K, h->sigma, b.Kmat, NE, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_KKT);
+    svl::gemm_f64_sk(st, true, false, NE, NE, ND, 1.0, b.Kmat, NE, b.Kmat, NE, 0.0, b.Mmat, NE,
+                     gws, gws_len, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_TRIDIAG);
+    coop_enter(h);
+    const int trc = svl::eig_tridiag(st, NE, b.Mmat, b.eigw, h->flags, &h->epoch, h->info);
+    coop_exit(h);
+    if (trc != 0) {
+      h->launch_failed = true;
+      svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+    }
+  }
+  {
+    PhaseScope ps(h, PH_BISECT);
+    svl::eig_bisect(st, NE, K, b.lam, b.eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_STEIN);
+    svl::eig_stein(st, NE, K, b.lam, b.Gv, b.eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_BACK);
+    svl::eig_back(st, NE, K, b.Mmat, b.Gv, b.eigw, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_RECOVER);   // F = K_w G diag(theta)^{-1}
+    svl::gemm_f64(st, false, true, K, ND, NE, 1.0, b.Gv, NE, b.Kmat, NE, 0.0, b.Fv, ND, h->info);
+    svl::theta_scale(st, K, b.lam, b.theta, b.Fv, ND, b.complete, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_ORTH);
+    double *gram_kk = b.orthw, *linv_kk = b.orthw + K * K, *xtmp = b.orthw + 2 * K * K;
+    svl::orthonormalize_rows(st, K, ND, b.Fv, b.complete, (uint64_t)h->seq * 2 + 1, gram_kk,
+                             linv_kk, xtmp, gws, gws_len, h->info);
+    svl::orthonormalize_rows(st, K, NE, b.Gv, nullptr, (uint64_t)h->seq * 2 + 2, gram_kk, linv_kk,
+                             xtmp, gws, gws_len, h->info);
+    svl::check_finite(st, K, b.theta, h->info, h->seq);
+  }
+  {
+    PhaseScope ps(h, PH_TRSM);   // Y = Yc^T X[k:] on both sides
+    svl::gemm_f64(st, true, true, s, K, lq[0], 1.0, sd[0].Yc, s, b.Fv + K, ND, 0.0, sd[0].Y, K,
+                  h->info);
+    svl::gemm_f64(st, true, true, s, K, lq[1], 1.0, sd[1].Yc, s, b.Gv + K, NE, 0.0, sd[1].Y, K,
+                  h->info);
+  }
+  sparse_side_small(h, s, ND, b.Fv, sd[0].Cp64, h->WU, sd[0].Y, b.T1, b.WnU, b.WiU, b.flags, 0,
+                    gws, gws_len, false);
+  sparse_side_small(h, s, NE, b.Gv, sd[1].Cp64, h->WV, sd[1].Y, b.T1, b.WnV, b.WiV, b.flags + 1, 1,
+                    gws, gws_len, false);
+  {
+    PhaseScope ps(h, PH_SMALL);
+    svl::inverse_cond_pair(st, K, b.WnU, b.WiU, b.flags, 0, b.WnV, b.WiV, b.flags + 1, 1,
+                           h->cond_reset, h->info);
+  }
+  svl::check_finite(st, K * K, b.WnU, h->info, h->seq);
+  svl::check_finite(st, K * K, b.WnV, h->info, h->seq);
+  if (hipGetLastError() != hipSuccess) {
+    h->launch_failed = true;
+    svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+  }
+  sparse_side_commit<T>(h, dq[0], h->m, Ub, sd[0].Y, sd[0].M, b.WnU, b.WiU, b.flags, h->WU,
+                        b.theta, h->sigma, 0);
+  sparse_side_commit<T>(h, dq[1], h->n, Vb, sd[1].Y, sd[1].M, b.WnV, b.WiV, b.flags + 1, h->WV,
+                        nullptr, nullptr, 1);
+  svl::op_end(st, h->info);
+  if (h->launch_failed) {
+    h->launch_failed = false;
+    return SVLCOV_E_DEVICE;
+  }
+  return SVLCOV_OK;
+}
+
 template <typename T>
 svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr *Em) {
   svlcov_status r = check_csr_header(D);
@@ -1082,6 +1318,20 @@ svlcov_status svlcov_add_cols_approx(svlcov_state *h, const svlcov_csr *E, const
   if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
   const svlcov_status r = h->prec == SVLCOV_FP64 ? op_append_approx<double>(h, E, false, a)
                                                  : op_append_approx<float>(h, E, false, a);
+  h->proj_ready[0] = h->proj_ready[1] = false;
+  return r;
+}
+
+svlcov_status svlcov_update_weights_approx(svlcov_state *h, const svlcov_csr *D_T,
+                                           const svlcov_csr *E_m_T, const svlcov_approx *a_D,
+                                           const svlcov_approx *a_E) {
+  if (!h) return SVLCOV_E_INVALID;
+  BusyGuard g(h);
+  if (!g.ok) return SVLCOV_E_BUSY;
+  if (hipSetDevice(h->device) != hipSuccess) return SVLCOV_E_DEVICE;
+  const svlcov_status r =
+      h->prec == SVLCOV_FP64 ? op_weights_approx<double>(h, D_T, E_m_T, a_D, a_E)
+                             : op_weights_approx<float>(h, D_T, E_m_T, a_D, a_E);
   h->proj_ready[0] = h->proj_ready[1] = false;
   return r;
 }

@@ -4,9 +4,9 @@ Lock-step: the oracle starts from the factors the GPU holds before the update
 (realised in FP64) and uses the same start vectors, so a difference measures
 the update alone.  Tolerances as for the exact path (tests/test_gpu_parity):
 FP64 sigma_rel <= 1e-10 and sin(angle) <= 1e-8; BF16x3 / FP32 1e-5 and 1e-4.
-Cases: both append forms, both methods, several tiles of the Gram (s up to
-300), l > s (clamped), a rank-deficient update that stops GKL early, the
-default GKL start, sequences of updates, and argument errors.
+Cases: both append forms and the weight form, both methods, several tiles of
+the Gram (s up to 300), l > s (clamped), a rank-deficient update that stops
+GKL early, the default GKL start, sequences of updates, and argument errors.
 """
 import numpy as np
 import pytest
@@ -76,6 +76,73 @@ def test_variant_matches_oracle(prec, m, n, k, s, kind, dens, method, l, t):
     try:
         _lockstep(svd, kind, c["E"], method, l, t, _start(rng, method, s, min(l, s)), prec,
                   f"{kind} m={m} n={n} k={k} s={s} l={l} t={t}")
+    finally:
+        svd.close()
+
+
+WCASES = [
+    # m, n, k, s, density, method, l, t
+    (300, 200, 16, 40, 0.05, "gkl", 10, 1),
+    (300, 200, 16, 40, 0.05, "rpi", 10, 3),
+    (500, 400, 32, 120, 0.03, "gkl", 16, 1),
+    (500, 400, 64, 120, 0.03, "rpi", 12, 2),
+    (400, 300, 16, 6, 0.2, "gkl", 10, 1),     # l > s: clamped to s
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("m,n,k,s,dens,method,l,t", WCASES)
+def test_weight_variant_matches_oracle(prec, m, n, k, s, dens, method, l, t):
+    L = _L()
+    rng = np.random.default_rng(9100 + m + n + k + s + l + t)
+    c = small_case(rng, m, n, k, s, kind="weights", density=dens)
+    svd = L.TruncatedSVD(c["U"], c["s"], c["V"], precision=prec)
+    try:
+        U0, s0, V0 = svd.factors()
+        lc = min(l, s)
+        start = (_start(rng, method, s, lc), _start(rng, method, s, lc))
+        svd.apply(("weights", c["D_T"], c["Em_T"]), approx=L.Approx(method, l, t, start))
+        svd.sync()
+        U1, s1, V1 = svd.factors()
+        Ur, sr, Vr, info = approx.update_weights(U0, s0, V0, c["D_T"], c["Em_T"], method=method,
+                                                 l=l, t=t, start=start)
+        tol = TOL[prec]
+        r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], tol["delta"])
+        print("weights", prec, method, r, flush=True)
+        assert r["sigma_rel"] <= tol["sig"], r
+        assert r["angle_U"] <= tol["ang"] and r["angle_V"] <= tol["ang"], r
+        st = svd.stats()
+        kap = max(st["last_kappa_U"], st["last_kappa_V"])
+        orth = tol["orth"] if prec != "fp64" else max(tol["orth"], 1e3 * 2.2e-16 * min(kap, 1e8))
+        assert r["orth_U"] <= orth and r["orth_V"] <= orth, (r, st)
+    finally:
+        svd.close()
+
+
+def test_weight_variant_mixed_methods_and_errors():
+    """GKL on one side and RPI on the other (the C ABI takes one spec per
+    side): the result is an orthonormal rank-k triple with U1^T A_new V1 =
+    diag(sigma), since K_w is exactly the projection of the updated matrix
+    onto the two bases; bad specs are rejected before any device work."""
+    L = _L()
+    rng = np.random.default_rng(9200)
+    c = small_case(rng, 300, 250, 16, 50, kind="weights", density=0.05)
+    svd = L.TruncatedSVD(c["U"], c["s"], c["V"], precision="fp64")
+    try:
+        aD = L.Approx("gkl", 10, 1, rng.standard_normal(50))
+        aE = L.Approx("rpi", 10, 2, rng.standard_normal((50, 10)))
+        svd.update_weights(c["D_T"], c["Em_T"], approx=(aD, aE))
+        svd.sync()
+        U1, s1, V1 = svd.factors()
+        assert metrics.orth_err(U1) < 1e-10 and metrics.orth_err(V1) < 1e-10
+        assert np.all(np.diff(s1) <= 1e-12 * s1[0])
+        A_new = (c["U"] * c["s"]) @ c["V"].T + c["D_T"].to_dense().T @ c["Em_T"].to_dense()
+        M = U1.T @ A_new @ V1
+        assert np.abs(M - np.diag(s1)).max() <= 1e-10 * s1[0]
+        with pytest.raises(L.SvlcovError):
+            svd.update_weights(c["D_T"], c["Em_T"], approx=(aD, L.Approx("rpi", 10, 2, None)))
+        with pytest.raises(L.SvlcovError):
+            svd.update_weights(c["D_T"], c["Em_T"], approx=(aD, L.Approx("gkl", 0, 1, None)))
     finally:
         svd.close()
 
