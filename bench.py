@@ -703,22 +703,25 @@ def main():
     capU, capV = wl["cap"]
     modes = (args.modes or wl["modes"]).split(",")
 
-    # the -GKL / -RPI variants (append workloads only) run as extra paths in
-    # the headline precision; their start vectors are drawn per update, seeded,
-    # and resident on the device before the timed region
-    methods = [] if args.approx in ("", "none") or any(u[0] == "weights" for u in ups) \
-        else args.approx.split(",")
+    # the -GKL / -RPI variants run as extra paths in the headline precision;
+    # their start vectors are drawn per update (one per side for the weight
+    # form), seeded, and resident on the device before the timed region
+    methods = [] if args.approx in ("", "none") else args.approx.split(",")
     head_mode = "bf16x3" if "bf16x3" in modes else modes[0]
     la, ta = args.approx_l, args.approx_t
     srng = np.random.default_rng(2401_09703)
     starts = {}
     for meth in methods:
         hs = []
+        def draw(sj):
+            return (srng.standard_normal(sj) if meth == "gkl"
+                    else srng.standard_normal((sj, min(la, sj))))
         for up in ups:
             sj = up[1].rows
-            hs.append(srng.standard_normal(sj) if meth == "gkl"
-                      else srng.standard_normal((sj, min(la, sj))))
-        starts[meth] = (hs, [torch.tensor(x, device="cuda") for x in hs])
+            hs.append((draw(sj), draw(sj)) if up[0] == "weights" else draw(sj))
+        starts[meth] = (hs, [tuple(torch.tensor(y, device="cuda") for y in x)
+                             if isinstance(x, tuple) else torch.tensor(x, device="cuda")
+                             for x in hs])
     paths = [(m, None) for m in modes] + [(head_mode, meth) for meth in methods]
 
     def approx_of(meth, j):
@@ -787,6 +790,11 @@ def main():
         t = time.perf_counter()
         Ua, sa, Va = cfg["U"], cfg["s"], cfg["V"]
         for j in range(P):
+            if ups[j][0] == "weights":
+                Ua, sa, Va, ia = approx_oracle.update_weights(
+                    Ua, sa, Va, ups[j][1], ups[j][2], method=meth, l=la, t=ta,
+                    start=starts[meth][0][j])
+                continue
             f = approx_oracle.add_rows if ups[j][0] == "rows" else approx_oracle.add_cols
             Ua, sa, Va, ia = f(Ua, sa, Va, ups[j][1], method=meth, l=la, t=ta,
                                start=starts[meth][0][j])

@@ -302,8 +302,11 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
                      h->info);
   }
   {
+    // the approximate variants build their basis by a Lanczos or power
+    // process on this Gram, which amplifies its rounding: FP64 for them in
+    // every mode (the MFMA Gram otherwise)
     PhaseScope ps(h, PH_RGRAM);
-    if (h->prec == SVLCOV_FP64)
+    if (h->prec == SVLCOV_FP64 || !chol)
       svl::gemm_f64(st, false, true, s, s, K, -1.0, Cp64, K, Cp64, K, 1.0, Gm, s, h->info);
     else
       svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
@@ -572,6 +575,14 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
 // and its Rayleigh-Ritz SVD is taken through the eigenpairs of K^T K
 // ((k+l) square): G from them, F = K G diag(theta)^{-1}.  The sparse side's
 // rotation uses Y G[k:] where the exact path uses T G[k:].
+// Drop floor of the variants' bases.  Their Gram is FP64 in every mode, so
+// in the FP32 / BF16x3 modes the floor is set by the FP32 projection C' (a
+// relative rounding of ~1e-7 in the Gram, sqrt of which is ~5e-4 of the
+// largest row): 1e-6 (the FP32 mode's floor) rather than the BF16x3 Gram's.
+double approx_tol(const svlcov_state *h) {
+  return h->prec == SVLCOV_FP64 ? h->rank_tol : std::min(h->rank_tol, 1e-6);
+}
+
 template <typename T>
 svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_form,
                                const svlcov_approx *ap) {
@@ -692,10 +703,10 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
     svl::sym_lower(st, s, b.Gm, s, h->info);
     if (gkl) {
       svl::gkl_basis(st, s, l, b.Gm, s, ap->start ? b.gv : nullptr, b.Pv, b.Yc, b.gv, b.ab,
-                     b.brk, h->rank_tol, h->info);
+                     b.brk, approx_tol(h), h->info);
     } else {
       svl::rpi_basis(st, s, l, ap->t, b.Gm, s, b.Pv, b.Yc, b.Xl, b.Tl, b.Gm2, b.Om, gws,
-                     gws_len, h->rank_tol, h->info);
+                     gws_len, approx_tol(h), h->info);
     }
   }
   {
@@ -930,10 +941,10 @@ svlcov_status op_weights_approx(svlcov_state *h, const svlcov_csr *D, const svlc
     const bool gkl = ap[q]->method == SVLCOV_APPROX_GKL;
     if (gkl)
       svl::gkl_basis(st, s, l, sd[q].Gm, s, ap[q]->start ? sd[q].gv : nullptr, sd[q].Pv, sd[q].Yc,
-                     sd[q].gv, sd[q].ab, sd[q].brk, h->rank_tol, h->info);
+                     sd[q].gv, sd[q].ab, sd[q].brk, approx_tol(h), h->info);
     else
       svl::rpi_basis(st, s, l, ap[q]->t, sd[q].Gm, s, sd[q].Pv, sd[q].Yc, sd[q].Xl, sd[q].Tl,
-                     sd[q].Gm2, sd[q].Om, gws, gws_len, h->rank_tol, h->info);
+                     sd[q].Gm2, sd[q].Om, gws, gws_len, approx_tol(h), h->info);
     // XT = [C' | P] (s x (k + l)), P = Z^T Q
     svl::copy_strided(st, s, K, sd[q].Cp64, K, 1, sd[q].XT, K + l, h->info);
     if (gkl)
