@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="graph", choices=("graph", "bernoulli", "ratings", "init",
-                                                             "weights", "stream", "score", "sweep"))
+                                                             "weights", "weights_r2", "stream", "score", "sweep"))
     ap.add_argument("--requests", type=int, default=512, help="stream workload: requests")
     ap.add_argument("--matrices", type=int, default=512, help="stream workload: matrices")
     ap.add_argument("--inflight", type=int, default=64, help="stream workload: server slots")
@@ -215,13 +215,14 @@ def phase_work(name, N, s, k, nnz, d_cols):
     return None, None, None
 
 
-WORKLOADS = ("graph", "bernoulli", "ratings", "weights")   # plus "stream" and "score"
+WORKLOADS = ("graph", "bernoulli", "ratings", "weights", "weights_r2")   # plus "stream" and "score"
 
 
 def build_workload(args, W, K):
     """The update stream of one workload, its per-step accounting and the
     state capacities.  One step = the updates of one batch of new data."""
-    from synth import config1_rows, config2_graph, config3_ratings, config4_weights
+    from synth import (config1_rows, config2_graph, config3_ratings, config4_weights,
+                       config4_weights_r2)
     wl = args.workload
     if wl == "graph":
         k = args.k or 64
@@ -247,13 +248,24 @@ def build_workload(args, W, K):
                     desc="user-item ratings 500000x50000, 10M ratings 1-5, Zipf(1.1) items, "
                          "k=128, appends of 5000 user rows",
                     extra=dict(k=128, s=5000), s=5000)
+    if wl == "weights_r2":
+        cfg = config4_weights_r2(steps=W + K)
+        return dict(cfg=cfg, per_step=1, rows_per_step=32, cap=(1_000_016, 1_000_016),
+                    modes="bf16x3,fp32", gate="oracle",
+                    desc="weight change spread over a 1M-node chung-lu graph (LogNormal weights), "
+                         f"k=64, reading R2: 50k uniform re-weighted + 10k new entries over "
+                         f"{cfg['touched_rows']} rows = {cfg['total_updates']} consecutive rank-32 "
+                         f"updates, the first {len(cfg['updates'])} timed",
+                    extra=dict(k=64, s=32, reading="R2", total_updates=cfg["total_updates"]),
+                    s=32)
     if wl == "weights":
         cfg = config4_weights(steps=W + K)
         return dict(cfg=cfg, per_step=1, rows_per_step=32, cap=(1_000_016, 1_000_016),
                     modes="bf16x3,fp32", gate="oracle",
                     desc="weight change on a 1M-node chung-lu graph (LogNormal weights), k=64, "
-                         "one rank-32 update per step (50k re-weighted + 10k new entries)",
-                    extra=dict(k=64, s=32), s=32)
+                         "reading R1: one rank-32 update per step (50k re-weighted + 10k new "
+                         "entries)",
+                    extra=dict(k=64, s=32, reading="R1"), s=32)
     raise SystemExit(f"unknown workload {wl}")
 
 

@@ -293,8 +293,11 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   hipStream_t st = h->stream;
   if (!h->proj_ready[which]) {
     PhaseScope ps(h, PH_SPMM);
+    // the variants (no Cholesky) take C' accumulated in FP64: a Lanczos
+    // basis of a nearly flat spectrum turns the rounding of an FP32 sum into
+    // a different subspace
     svl::spmm_w<T>(st, K, s, E.rp, E.ci, E.v, E.vdt, base, W, Cp64,
-                   h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info);
+                   h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info, !chol);
   }
   {
     PhaseScope ps(h, PH_SGRAM);
@@ -575,12 +578,16 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
 // and its Rayleigh-Ritz SVD is taken through the eigenpairs of K^T K
 // ((k+l) square): G from them, F = K G diag(theta)^{-1}.  The sparse side's
 // rotation uses Y G[k:] where the exact path uses T G[k:].
-// Drop floor of the variants' bases.  Their Gram is FP64 in every mode, so
-// in the FP32 / BF16x3 modes the floor is set by the FP32 projection C' (a
-// relative rounding of ~1e-7 in the Gram, sqrt of which is ~5e-4 of the
-// largest row): 1e-6 (the FP32 mode's floor) rather than the BF16x3 Gram's.
+// Drop floor of the variants' bases.  Their Gram is FP64 and their C' is
+// accumulated in FP64 in every mode, so in the FP32 / BF16x3 modes the floor
+// is set by the orthonormality of FP32-stored factors (~1e-7, a direction
+// of the augmented space below ~1e-7 of the largest row is not resolved):
+// 1e-12 on the squared scale, a GKL breakdown at 1e-6 of the largest row.
+// The exact path's floor in those modes (the MFMA Gram's rounding, 1e-5)
+// would end GKL after one step on a nearly flat spectrum (a selection D
+// against a tall U), where every Krylov increment is small but genuine.
 double approx_tol(const svlcov_state *h) {
-  return h->prec == SVLCOV_FP64 ? h->rank_tol : std::min(h->rank_tol, 1e-6);
+  return h->prec == SVLCOV_FP64 ? h->rank_tol : std::min(h->rank_tol, 1e-12);
 }
 
 template <typename T>

@@ -66,12 +66,13 @@ __device__ __forceinline__ double ldv(const void *val, int vdtype, int64_t p) {
   return vdtype ? ((const double *)val)[p] : (double)((const float *)val)[p];
 }
 
-// Row i of P = E * base (K columns, accumulated in T), C'[i] = P[i] W (FP64,
+// Row i of P = E * base (K columns, accumulated in A: T, or FP64 for FP32
+// storage where the caller needs C' to FP64 rounding), C'[i] = P[i] W (FP64,
 // W is K x K FP64) and ||e_i||^2, by one block of SP_NW waves.  For K <= 64 a
 // wave splits into 64/K groups of K lanes that take alternate nonzeros of a
 // chunk; for K = 128 each lane owns two columns.  red (SP_NW x K), ptot (K)
 // and nred (SP_NW) are LDS scratch of the caller.
-template <typename T, int K>
+template <typename T, typename A, int K>
 __device__ __forceinline__ void
 spmm_row(int64_t i, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
          const void *__restrict__ val, int vdtype, const T *__restrict__ base,
@@ -82,9 +83,9 @@ spmm_row(int64_t i, const int64_t *__restrict__ row_ptr, const int32_t *__restri
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane / (64 / G), c = lane % (64 / G);
   const int64_t p0 = row_ptr[i], p1 = row_ptr[i + 1];
-  T acc[CPL];
+  A acc[CPL];
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) acc[q] = (T)0;
+  for (int q = 0; q < CPL; ++q) acc[q] = (A)0;
   double nrm = 0.0;
   for (int64_t cb = p0 + 64 * w; cb < p1; cb += 64 * SP_NW) {
     const int n = (int)((p1 - cb) < 64 ? (p1 - cb) : 64);
@@ -95,11 +96,11 @@ spmm_row(int64_t i, const int64_t *__restrict__ row_ptr, const int32_t *__restri
       mvd = ldv(val, vdtype, cb + lane);
     }
     nrm += mvd * mvd;
-    const T mv = (T)mvd;
+    const A mv = (A)mvd;
     // lanes >= n carry column 0 and value 0: their gathers are valid and add 0
     for (int j0 = 0; j0 < n; j0 += SP_U * G) {
       int32_t cc[SP_U];
-      T vv[SP_U];
+      A vv[SP_U];
 #pragma unroll
       for (int u = 0; u < SP_U; ++u) {
         const int jj = j0 + u * G + g;
@@ -114,7 +115,7 @@ spmm_row(int64_t i, const int64_t *__restrict__ row_ptr, const int32_t *__restri
 #pragma unroll
       for (int u = 0; u < SP_U; ++u)
 #pragma unroll
-        for (int q = 0; q < CPL; ++q) acc[q] += vv[u] * bb[u][q];
+        for (int q = 0; q < CPL; ++q) acc[q] += vv[u] * (A)bb[u][q];
     }
   }
   if constexpr (G > 1) {
@@ -151,7 +152,7 @@ spmm_row(int64_t i, const int64_t *__restrict__ row_ptr, const int32_t *__restri
 }
 
 // The projection of one update: one block per row of E.
-template <typename T, int K>
+template <typename T, typename A, int K>
 __global__ void __launch_bounds__(64 * SP_NW)
 k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
          const void *__restrict__ val, int vdtype, const T *__restrict__ base,
@@ -161,7 +162,7 @@ k_spmm_w(int64_t s, const int64_t *__restrict__ row_ptr, const int32_t *__restri
   __shared__ double red[SP_NW * K];
   __shared__ double ptot[K];
   __shared__ double nred[SP_NW];
-  spmm_row<T, K>((int64_t)blockIdx.x, row_ptr, col_idx, val, vdtype, base, W, Cp64, Cp32,
+  spmm_row<T, A, K>((int64_t)blockIdx.x, row_ptr, col_idx, val, vdtype, base, W, Cp64, Cp32,
                  rownorm2, red, ptot, nred);
 }
 
@@ -524,25 +525,32 @@ void validate_csr(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz,
 template <typename T>
 void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
-            float *Cp32, double *rownorm2, const SvDevInfo *info) {
+            float *Cp32, double *rownorm2, const SvDevInfo *info, bool acc64) {
   if (s <= 0) return;
   const unsigned blocks = (unsigned)s;
-#define SV_SPMM(KK) hipLaunchKernelGGL((k_spmm_w<T, KK>), dim3(blocks), dim3(64 * SP_NW), 0, st, \
-                                       s, rp, ci, v, vdt, base, W, Cp64, Cp32, rownorm2, info)
-  switch (K) {
-    case 16: SV_SPMM(16); break;
-    case 32: SV_SPMM(32); break;
-    case 64: SV_SPMM(64); break;
-    case 128: SV_SPMM(128); break;
+#define SV_SPMM(AA, KK) hipLaunchKernelGGL((k_spmm_w<T, AA, KK>), dim3(blocks), dim3(64 * SP_NW), 0, \
+                                           st, s, rp, ci, v, vdt, base, W, Cp64, Cp32, rownorm2, info)
+#define SV_SPMM_K(AA) \
+  switch (K) {        \
+    case 16: SV_SPMM(AA, 16); break; \
+    case 32: SV_SPMM(AA, 32); break; \
+    case 64: SV_SPMM(AA, 64); break; \
+    case 128: SV_SPMM(AA, 128); break; \
   }
+  if (acc64 || sizeof(T) == sizeof(double)) {
+    SV_SPMM_K(double)
+  } else {
+    SV_SPMM_K(T)
+  }
+#undef SV_SPMM_K
 #undef SV_SPMM
 }
 template void spmm_w<float>(hipStream_t, int, int64_t, const int64_t *, const int32_t *,
                             const void *, int, const float *, const double *, double *,
-                            float *, double *, const SvDevInfo *);
+                            float *, double *, const SvDevInfo *, bool);
 template void spmm_w<double>(hipStream_t, int, int64_t, const int64_t *, const int32_t *,
                              const void *, int, const double *, const double *, double *,
-                             float *, double *, const SvDevInfo *);
+                             float *, double *, const SvDevInfo *, bool);
 
 // Tile shapes of the fused projection: (16-byte loads in flight per lane,
 // rows per tile).  Variant 0 is the default.

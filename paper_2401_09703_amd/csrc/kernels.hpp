@@ -13,10 +13,12 @@ namespace svl {
 void validate_csr(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz,
                   const int64_t *rp, const int32_t *ci, const void *v, int vdt,
                   SvDevInfo *info, int seq);
+// C' = E base W (FP64 out, FP32 copy when Cp32) and the row norms of E;
+// accumulated in the storage type, or in FP64 when acc64.
 template <typename T>
 void spmm_w(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
             const void *v, int vdt, const T *base, const double *W, double *Cp64,
-            float *Cp32, double *rownorm2, const SvDevInfo *info);
+            float *Cp32, double *rownorm2, const SvDevInfo *info, bool acc64 = false);
 // One projection of a fused batch (k_spmm_batch): C' = E base W and the row
 // norms of E for s rows; row0 is the offset of its first tile (tiles of
 // spmm_batch_rows_per_block() rows) within its group.

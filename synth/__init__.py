@@ -15,13 +15,13 @@ from .sparse import (CSR, bernoulli_uniform, chung_lu_weights, chung_lu_graph,
                      zipf_ratings, lognormal_values, random_orthonormal,
                      synthetic_factors, randomized_init)
 from .workloads import (seed_children, config1_rows, config2_graph, config2_initial_matrix,
-                        config3_ratings, config4_weights, config5_stream,
+                        config3_ratings, config4_weights, config4_weights_r2, config5_stream,
                         materialise_matrix, materialise_request, small_case)
 
 __all__ = [
     "CSR", "bernoulli_uniform", "chung_lu_weights", "chung_lu_graph",
     "zipf_ratings", "lognormal_values", "random_orthonormal",
     "synthetic_factors", "randomized_init", "seed_children", "config1_rows",
-    "config2_graph", "config2_initial_matrix", "config3_ratings", "config4_weights", "config5_stream",
+    "config2_graph", "config2_initial_matrix", "config3_ratings", "config4_weights_r2", "config4_weights", "config5_stream",
     "materialise_matrix", "materialise_request", "small_case",
 ]

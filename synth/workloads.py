@@ -148,6 +148,43 @@ def config4_weights(N: int = 1_000_000, avg_deg: float = 20.0, k: int = 64,
                 updates=ups)
 
 
+def config4_weights_r2(N: int = 1_000_000, avg_deg: float = 20.0, k: int = 64,
+                       steps: int = 10, s: int = 32, perturbed: int = 50000,
+                       added: int = 10000, gamma: float = 2.1, power: int = 1):
+    """The weight change spread over the whole graph (the secondary reading
+    of the weight workload): ``perturbed`` existing entries drawn uniformly
+    (new LogNormal minus old) and ``added`` new entries (both endpoints by
+    Chung-Lu weight, LogNormal values), applied as consecutive rank-s updates
+    ``A + D Em^T`` with ``D = I[:, R_c]`` over the touched rows in ascending
+    chunks of s.  The same graph and starting factors as ``config4_weights``;
+    only the first ``steps`` chunks are returned, with the total count."""
+    rngs = seed_children(4, 2)
+    G = chung_lu_graph(N, gamma, avg_deg, rngs[0], values="lognormal")
+    U, sig, V = randomized_init(G, k, rngs[1], power=power)
+    Gs = G.to_scipy().tocsr()
+    coo = Gs.tocoo()
+    w = chung_lu_weights(N, gamma, avg_deg)
+    rng = seed_children(4, 64)[63]
+    pick = rng.choice(coo.nnz, size=min(perturbed, coo.nnz), replace=False)
+    r_add = rng.choice(N, size=added, p=w / w.sum())
+    c_add = rng.choice(N, size=added, p=w / w.sum())
+    rows = np.concatenate([coo.row[pick], r_add])
+    cols = np.concatenate([coo.col[pick], c_add])
+    vals = np.concatenate([rng.lognormal(0.0, 1.0, size=pick.size) - coo.data[pick],
+                           rng.lognormal(0.0, 1.0, size=added)])
+    Delta = sp.coo_matrix((vals, (rows, cols)), shape=(N, N)).tocsr()
+    Delta.sum_duplicates()
+    touched = np.flatnonzero(np.diff(Delta.indptr) > 0)
+    total = (touched.size + s - 1) // s
+    ups = []
+    for c in range(min(steps, total)):
+        R = touched[c * s:(c + 1) * s]
+        D_T = sp.csr_matrix((np.ones(R.size), (np.arange(R.size), R)), shape=(R.size, N))
+        ups.append(("weights", CSR.from_scipy(D_T), CSR.from_scipy(Delta[R])))
+    return dict(name=f"weights-r2-{N}-k{k}", A=G, U=U, s=sig, V=V, k=k, updates=ups,
+                total_updates=total, touched_rows=int(touched.size))
+
+
 def config5_stream(n_mat: int = 512, requests: int = 4096, seed_offset: int = 0,
                    m_range=(5000, 200000), n_range=(1000, 50000),
                    dens_range=(5e-4, 1e-2), ks=(16, 32, 64),
