@@ -1,4 +1,4 @@
-// Dense kernels of one update: FP64 GEMM, the residual Gram on MFMA (FP32 and
+// Dense kernels of one update: FP64 GEMM on MFMA, the residual Gram on MFMA (FP32 and
 // BF16x3), the FP64 Cholesky with pivot dropping and its triangular solve,
 // assembly of K, the k x k inverse with a condition estimate, row
 // orthonormalisation and the tall-skinny realisation GEMM.
@@ -16,6 +16,7 @@ namespace {
 
 // ------------------------------------------------------------------ FP64 GEMM
 constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+typedef double gm_d4 __attribute__((ext_vector_type(4)));
 
 // With part != nullptr the launch is split over K: block z sums the products
 // of k in [z*kchunk, (z+1)*kchunk) and writes alpha times its partial sum to
@@ -38,13 +39,15 @@ k_gemm_f64(int64_t M, int64_t N, int64_t Kfull, double alpha, const double *__re
   __shared__ double As[GB_K][GB_M + 1];
   __shared__ double Bs[GB_K][GB_N + 1];
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
+  const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;   // the wave's 32 x 32 quadrant
   const int64_t m0 = (int64_t)blockIdx.y * GB_M, n0 = (int64_t)blockIdx.x * GB_N;
-  double acc[4][4];
+  gm_d4 acc[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int u = 0; u < 2; ++u) acc[t][u] = gm_d4{0.0, 0.0, 0.0, 0.0};
   for (int64_t k0 = 0; k0 < K; k0 += GB_K) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -63,37 +66,41 @@ k_gemm_f64(int64_t M, int64_t N, int64_t Kfull, double alpha, const double *__re
       Bs[q][j] = u;
     }
     __syncthreads();
+    // v_mfma_f64_16x16x4: A[m][k] from lane (m, k) = (l % 16, l / 16), B[k][n]
+    // from lane (k, n) = (l / 16, l % 16)
 #pragma unroll
-    for (int p = 0; p < GB_K; ++p) {
-      double a[4], b[4];
+    for (int kk = 0; kk < GB_K; kk += 4) {
+      double a[2], b[2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[p][ty + 16 * r];
+      for (int t = 0; t < 2; ++t) a[t] = As[kk + lk][wm + 16 * t + li];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[p][tx + 16 * c];
+      for (int u = 0; u < 2; ++u) b[u] = Bs[kk + lk][wn + 16 * u + li];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        for (int u = 0; u < 2; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
     }
     __syncthreads();
   }
+  // D[m][n] of a 16 x 16 tile sits in lane n + 16 (m % 4), element m / 4
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t gi = m0 + ty + 16 * r;
-    if (gi >= M) continue;
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int64_t gj = n0 + tx + 16 * c;
-      if (gj >= N) continue;
-      double v = alpha * acc[r][c];
-      if (part) {
-        part[((int64_t)blockIdx.z * M + gi) * N + gj] = v;
-        continue;
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = m0 + wm + 16 * t + lk + 4 * q;
+        const int64_t gj = n0 + wn + 16 * u + li;
+        if (gi >= M || gj >= N) continue;
+        double v = alpha * acc[t][u][q];
+        if (part) {
+          part[((int64_t)blockIdx.z * M + gi) * N + gj] = v;
+          continue;
+        }
+        if (beta != 0.0) v += beta * C[gi * ldc + gj];
+        C[gi * ldc + gj] = v;
       }
-      if (beta != 0.0) v += beta * C[gi * ldc + gj];
-      C[gi * ldc + gj] = v;
-    }
-  }
 }
 
 __global__ void k_gemm_reduce(int64_t M, int64_t N, int splits, const double *__restrict__ part,

@@ -147,6 +147,38 @@ def test_weight_variant_mixed_methods_and_errors():
         svd.close()
 
 
+@pytest.mark.parametrize("method", ["gkl", "rpi"])
+def test_weight_variant_selection_against_tall_factor(method):
+    """D = I[:, R] (a selection of 32 rows) against a 20 000-row U: the
+    residual Gram of D is I - U_R U_R^T, a nearly flat spectrum whose Krylov
+    increments are small (~k/m) but genuine.  In BF16x3 mode the basis must
+    not stop at the exact path's rounding floor there (it did: one GKL step,
+    a subspace 1e-4 away from the oracle's)."""
+    import scipy.sparse as sp
+    from synth import bernoulli_uniform, synthetic_factors
+    L = _L()
+    rng = np.random.default_rng(9300)
+    m, n, k, s, l = 20000, 3000, 16, 32, 10
+    U, sig, V = synthetic_factors(m, n, k, rng)
+    R = np.sort(rng.choice(m, size=s, replace=False))
+    D_T = CSR.from_scipy(sp.csr_matrix((np.ones(s), (np.arange(s), R)), shape=(s, m)))
+    Em_T = bernoulli_uniform(s, n, 0.02, rng)
+    svd = L.TruncatedSVD(U, sig, V, precision="bf16x3")
+    try:
+        U0, s0, V0 = svd.factors()
+        start = (_start(rng, method, s, l), _start(rng, method, s, l))
+        svd.update_weights(D_T, Em_T, approx=L.Approx(method, l, 2, start))
+        svd.sync()
+        U1, s1, V1 = svd.factors()
+        Ur, sr, Vr, info = approx.update_weights(U0, s0, V0, D_T, Em_T, method=method, l=l, t=2,
+                                                 start=start)
+        r = metrics.compare((U1, s1, V1), (Ur, sr, Vr), info["theta_hat"], 1e-3)
+        assert r["sigma_rel"] <= 1e-7, r
+        assert r["angle_U"] <= 1e-5 and r["angle_V"] <= 1e-5, r
+    finally:
+        svd.close()
+
+
 def test_gkl_default_start_and_device_start():
     """start=None means all ones; a device start gives the same result as the
     same values on the host."""
