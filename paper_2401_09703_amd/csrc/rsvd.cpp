@@ -36,6 +36,18 @@ svlcov_status herr(hipError_t e) {
     if (_s != SVLCOV_OK) return _s;      \
   } while (0)
 
+// after the workspace exists: free it (ordered after the work already
+// enqueued) before reporting the failure
+#define RV_TRY_WS(expr)                                  \
+  do {                                                   \
+    svlcov_status _s = herr(expr);                       \
+    if (_s != SVLCOV_OK) {                               \
+      (void)hipFreeAsync(mem, st);                       \
+      (void)hipStreamSynchronize(st);                    \
+      return _s;                                         \
+    }                                                    \
+  } while (0)
+
 size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // pivots at or below this fraction of the largest squared column norm are
@@ -115,10 +127,10 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
     int64_t *rpd = (int64_t *)take((size_t)(m + 1) * 8);
     int32_t *cid = (int32_t *)take((size_t)nnz * 4);
     void *vd = take((size_t)nnz * vsz);
-    RV_TRY(hipMemcpyAsync(rpd, rp, (size_t)(m + 1) * 8, hipMemcpyHostToDevice, st));
+    RV_TRY_WS(hipMemcpyAsync(rpd, rp, (size_t)(m + 1) * 8, hipMemcpyHostToDevice, st));
     if (nnz > 0) {
-      RV_TRY(hipMemcpyAsync(cid, ci, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
-      RV_TRY(hipMemcpyAsync(vd, v, (size_t)nnz * vsz, hipMemcpyHostToDevice, st));
+      RV_TRY_WS(hipMemcpyAsync(cid, ci, (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+      RV_TRY_WS(hipMemcpyAsync(vd, v, (size_t)nnz * vsz, hipMemcpyHostToDevice, st));
     }
     rp = rpd;
     ci = cid;
@@ -141,7 +153,7 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
   double *Fv = (double *)take((size_t)k * l * 8);
 
   PhaseTimer tm(st, phase_ms != nullptr);
-  RV_TRY(hipMemsetAsync(info, 0, al(sizeof(SvDevInfo)) + svl::TRI_FLAG_WORDS * sizeof(unsigned),
+  RV_TRY_WS(hipMemsetAsync(info, 0, al(sizeof(SvDevInfo)) + svl::TRI_FLAG_WORDS * sizeof(unsigned),
                         st));
   tm.mark(0);
   svl::validate_csr(st, m, n, nnz, rp, ci, v, vdt, info, 0);
