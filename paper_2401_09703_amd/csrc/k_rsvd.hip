@@ -649,15 +649,12 @@ __global__ void k_fill_cols(int64_t R, int L, double *__restrict__ X,
                             const SvDevInfo *__restrict__ info) {
   if (info->status) return;
   __shared__ int32_t fl[128];
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
+  bool mine = false;
   for (int c = threadIdx.x; c < L; c += blockDim.x) {
     fl[c] = complete[c];
-    if (fl[c]) any = 1;
+    mine |= fl[c] != 0;
   }
-  __syncthreads();
-  if (!any) return;
+  if (!__syncthreads_or(mine)) return;
   const double sc = sqrt(3.0 / (double)R);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < R * L;
        e += (int64_t)gridDim.x * blockDim.x) {
