@@ -4,6 +4,8 @@
 // Equation (1)), each as one cooperative launch.  Blocks exchange data through
 // coherent (L2-bypassing) loads and stores and meet at flag barriers, so a
 // factorisation of s = 1000 costs two launches instead of ~150.
+#include <cstdlib>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "lane.hpp"
@@ -289,6 +291,15 @@ __global__ void k_zero_flags(unsigned *p, size_t n) {
     p[i] = 0u;
 }
 
+// blocks wanted for an s x s factor: one per ROWS_PER_BLOCK rows
+// (SVLCOV_COOP_ROWS overrides it for tuning sweeps)
+int coop_want(int64_t s) {
+  int rows = 4;
+  if (const char *ev = getenv("SVLCOV_COOP_ROWS")) rows = atoi(ev);
+  if (rows < 1) rows = 1;
+  return (int)((s + rows - 1) / rows);
+}
+
 int coop_blocks(const void *fn, int want) {
   static int ncu = 0;
   if (ncu == 0) {
@@ -328,7 +339,7 @@ int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv
                   SvDevInfo *info, int which, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
-  const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), (int)((s + 3) / 4));
+  const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), coop_want(s));
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)(2 * nblk));
   void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&tol,
                   (void *)&info, (void *)&which, (void *)&flags, (void *)&e0};
@@ -343,7 +354,7 @@ int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, con
               double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
-  const int P = coop_blocks(reinterpret_cast<const void *>(k_trsm_coop), (int)((s + 3) / 4));
+  const int P = coop_blocks(reinterpret_cast<const void *>(k_trsm_coop), coop_want(s));
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)nblk);
   void *args[] = {(void *)&s, (void *)&K, (void *)&L, (void *)&ld, (void *)&Linv,
                   (void *)&Y, (void *)&info, (void *)&flags, (void *)&e0};
