@@ -69,8 +69,10 @@ __device__ __forceinline__ int sturm_count(int N, const double *__restrict__ d,
 // lam[j] = the (N-1-j)-th smallest eigenvalue of T (so lam is descending).
 // One block of BIS_NT threads per eigenvalue; each round evaluates BIS_NT
 // shifts (one per thread) that split the current interval into BIS_NT + 1
-// parts, so an FP64 eigenvalue is found in about six rounds.
-constexpr int BIS_NT = 512;
+// parts, so an FP64 eigenvalue is found in about seven rounds.  256 shifts
+// (one wave per SIMD) measured faster on MI355X than 128 (more rounds) and
+// than 512 or 1024 (the Sturm recurrences of several waves share a SIMD).
+constexpr int BIS_NT = 256;
 
 __global__ void __launch_bounds__(BIS_NT)
 k_bisect(int N, const double *__restrict__ d, const double *__restrict__ e, int k,
