@@ -364,12 +364,15 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
     (void)hipGetLastError();
     once = true;
   }
-  // block count G: N/4 below N = 512, N/8 above (measured on MI355X: at
-  // N = 1064, 133 blocks of 8 rows beat 266 of 4 by 5 %, fewer blocks meeting
-  // at each column's grid barrier and reading the published row; small N
-  // want the rows spread); at most one block per CU; SVLCOV_TRI_BLOCKS
+  // block count G: one block per 8 rows from N = 512 while those 8 rows and
+  // the three work vectors fit in LDS, else one per 4 rows (measured on
+  // MI355X: at N = 1064, 133 blocks of 8 rows beat 266 of 4 by 5 %, fewer
+  // blocks meeting at each column's grid barrier and reading the published
+  // row; small N want the rows spread, and a block whose rows leave LDS is
+  // several times slower); at most one block per CU; SVLCOV_TRI_BLOCKS
   // overrides it for tuning sweeps
-  int G = N < 512 ? N / 4 : N / 8;
+  const bool eight = N >= 512 && (size_t)(3 + 8) * N * sizeof(double) <= (size_t)150 * 1024;
+  int G = N / (eight ? 8 : 4);
   if (const char *ev = getenv("SVLCOV_TRI_BLOCKS")) G = atoi(ev);
   if (G < 1) G = 1;
   if (G > ncu) G = ncu;
