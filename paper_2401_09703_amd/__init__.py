@@ -125,7 +125,7 @@ RSVD_PHASES = ("transpose", "products", "orthonormalise", "small_eig", "final")
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
-        raise ImportError(f"libsvlcov.so not built at {path}; run __graft_entry__.build()")
+        raise ImportError(f"libsvlcov.so not built at {path}; run python paper_2401_09703_amd/build.py")
     lib = C.CDLL(path)
     P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     lib.svlcov_default_options.argtypes = [C.POINTER(_Options)]
