@@ -371,8 +371,12 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
   // row; small N want the rows spread, and a block whose rows leave LDS is
   // several times slower); at most one block per CU; SVLCOV_TRI_BLOCKS
   // overrides it for tuning sweeps
+  // (rounded up, so that no block gets a ninth or fifth row: with a floor,
+  // N not a multiple of the row count left some waves with two rows, or a
+  // block's rows outside LDS)
   const bool eight = N >= 512 && (size_t)(3 + 8) * N * sizeof(double) <= (size_t)150 * 1024;
-  int G = N / (eight ? 8 : 4);
+  const int rows = eight ? 8 : 4;
+  int G = (N + rows - 1) / rows;
   if (const char *ev = getenv("SVLCOV_TRI_BLOCKS")) G = atoi(ev);
   if (G < 1) G = 1;
   if (G > ncu) G = ncu;
