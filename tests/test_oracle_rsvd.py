@@ -55,3 +55,32 @@ def test_planted_mistakes_are_caught():
     assert metrics.sigma_rel_err(s0, sl[:k]) > 10 * good
     # mistake: right factor from the wrong side
     assert metrics.sin_angle(U[:V.shape[0]], Vlt[:k].T) > 1e-3
+
+
+def test_planted_transposed_operand_is_caught():
+    """A copy of the oracle whose power step multiplies by A where A^T is
+    due (a transposed operand) drifts away from LAPACK's subspaces on a
+    non-symmetric matrix with a decaying spectrum."""
+    rng = np.random.default_rng(4)
+    m, n, k = 260, 260, 6
+    X = np.linalg.qr(rng.standard_normal((m, m)))[0]
+    Y = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    sv = 0.8 ** np.arange(n)
+    A = (X * sv) @ Y.T                      # non-symmetric, left and right bases differ
+    Om = rng.standard_normal((n, 2 * k))
+    Ul, sl, Vlt = np.linalg.svd(A, full_matrices=False)
+
+    def mutated(A, k, Om, power):
+        Q = np.linalg.qr(A @ Om)[0]
+        for _ in range(power):
+            Z = np.linalg.qr(A @ Q)[0]      # mistake: A instead of A^T
+            Q = np.linalg.qr(A @ Z)[0]
+        B = (A.T @ Q).T
+        Ub, s, Vbt = np.linalg.svd(B, full_matrices=False)
+        return Q @ Ub[:, :k], s[:k], Vbt[:k].T
+
+    U, s, V = rsvd.rsvd(A, k, Om, power=4)
+    Um, sm, Vm = mutated(A, k, Om, 4)
+    good = metrics.sin_angle(U, Ul[:, :k])
+    bad = metrics.sin_angle(Um, Ul[:, :k])
+    assert good < 1e-3 and bad > 10 * good
