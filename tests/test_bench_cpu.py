@@ -1,0 +1,84 @@
+"""The benchmark's host-side contract on a machine without a GPU: argument
+defaults, the refusal of more than one GPU, the rocprofv3 summaries it
+turns into the committed profiles (kernel statistics and HBM counters
+scaled by a calibration copy), and the source-hash check that drops a
+stored traffic figure once its kernel's source has changed."""
+import csv
+import io
+import os
+import subprocess
+import sys
+from contextlib import redirect_stdout
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_defaults(monkeypatch):
+    monkeypatch.setattr(sys, "argv", ["bench.py"])
+    a = bench.parse()
+    assert a.gpus == 1 and a.steps >= 1 and a.warmup >= 0 and a.workload == "graph"
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _write_csv(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_summarize_stats(tmp_path):
+    _write_csv(str(tmp_path / "x" / "prof_kernel_stats.csv"),
+               ["Name", "Calls", "TotalDurationNs", "AverageNs", "MinNs", "MaxNs"],
+               [["(anonymous namespace)::k_a(int)", 4, 4000, 1000, 900, 1100],
+                ["k_b(int)", 1, 12000, 12000, 12000, 12000]])
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        bench.summarize_stats(str(tmp_path))
+    lines = buf.getvalue().splitlines()
+    assert lines[1].startswith("k_b(int)") and lines[2].startswith("k_a(int)")
+    assert "75.00" in lines[1] and "1.0" in lines[2]
+
+
+def test_summarize_pmc_scales_by_the_calibration_copy(tmp_path):
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    # the copy of 1 MiB reads 512 KiB of FETCH_SIZE and writes 1024 KiB:
+    # factors 2 and 1
+    _write_csv(str(tmp_path / "f" / "p_counter_collection.csv"), hdr,
+               [["void at::native::neg_kernel", "FETCH_SIZE", 512.0],
+                ["k_tridiag<true, 512>(int)", "FETCH_SIZE", 100.0],
+                ["k_tridiag<true, 512>(int)", "FETCH_SIZE", 300.0]])
+    _write_csv(str(tmp_path / "w" / "p_counter_collection.csv"), hdr,
+               [["void at::native::neg_kernel", "WRITE_SIZE", 1024.0],
+                ["k_tridiag<true, 512>(int)", "WRITE_SIZE", 50.0],
+                ["k_tridiag<true, 512>(int)", "WRITE_SIZE", 50.0]])
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        bench.summarize_pmc(str(tmp_path / "f"), str(tmp_path / "w"), "tridiag", 1)
+    kv = dict(l.split(": ", 1) for l in buf.getvalue().splitlines() if not l.startswith("#"))
+    assert float(kv["fetch_factor"]) == pytest.approx(2.0)
+    assert float(kv["fetch_bytes_per_launch"]) == pytest.approx(200.0 * 1024 * 2)
+    assert float(kv["write_bytes_per_launch"]) == pytest.approx(50.0 * 1024)
+    assert kv["sources_sha256"] == bench.sources_sha(bench.PHASE_KERNEL["tridiag"][1])
+
+
+def test_stored_traffic_needs_the_current_sources(tmp_path, monkeypatch):
+    files = bench.PHASE_KERNEL["tridiag"][1]
+    good = tmp_path / "pmc_k_tridiag_case.txt"
+    good.write_text(f"sources_sha256: {bench.sources_sha(files)}\n"
+                    "traffic_bytes_per_launch: 1234\n")
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    assert bench.stored_traffic("tridiag") == 1234.0
+    good.write_text("sources_sha256: 0\ntraffic_bytes_per_launch: 1234\n")
+    assert bench.stored_traffic("tridiag") is None
+    assert bench.stored_traffic("no-such-phase") is None
