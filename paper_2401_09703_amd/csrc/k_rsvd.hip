@@ -10,10 +10,18 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "k_rsvd.hpp"
 
 using namespace svk;
 
 namespace {
+
+// A gated pass does nothing unless the flag *need (written by k_orth_gate
+// before it) is set; need == NULL runs it always.  Every thread reads the same
+// word, so the decision is uniform across the block.
+__device__ __forceinline__ bool skip_pass(const int32_t *__restrict__ need) {
+  return need && *need == 0;
+}
 
 // ------------------------------------------------------------- CSR transpose
 // A stable LSD radix sort of the nonzeros by column id, 8 bits per pass, the
@@ -237,8 +245,14 @@ constexpr int CD_RW = (128 + CD_NT / 64 - 1) / (CD_NT / 64);   // rows per wave 
 
 __global__ void __launch_bounds__(CD_NT)
 k_chol_drop(int L, const double *__restrict__ G, double *__restrict__ Out,
-            int32_t *__restrict__ complete, double rtol, const SvDevInfo *__restrict__ info) {
+            int32_t *__restrict__ complete, double rtol, const SvDevInfo *__restrict__ info,
+            const int32_t *__restrict__ need) {
   if (info->status) return;
+  if (skip_pass(need)) {   // Out = I and nothing to complete: the product copies the panel
+    for (int e = threadIdx.x; e < L * L; e += blockDim.x) Out[e] = (e / L == e % L) ? 1.0 : 0.0;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) complete[j] = 0;
+    return;
+  }
   extern __shared__ double S[];
   const int LD = L + 1;
   double *dg = S + L * LD;         // pivots
@@ -331,8 +345,8 @@ constexpr int TG_KC = 32;
 template <int L>
 __global__ void __launch_bounds__(256)
 k_ts_gram(int64_t R, int64_t rpb, const double *__restrict__ Y, double *__restrict__ part,
-          const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
+          const SvDevInfo *__restrict__ info, const int32_t *__restrict__ need) {
+  if (info->status || skip_pass(need)) return;
   constexpr int LT = L / 16;
   constexpr int NT = LT * (LT + 1) / 2;
   constexpr int TW = (NT + 3) / 4;
@@ -395,8 +409,9 @@ k_ts_gram(int64_t R, int64_t rpb, const double *__restrict__ Y, double *__restri
 // (e < NE); then G from the S slabs, both triangles (fixed order: identical
 // inputs give identical bits).
 __global__ void k_gram_reduce1(int Z, int S, int64_t NE, const double *__restrict__ part,
-                               double *__restrict__ part2, const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
+                               double *__restrict__ part2, const SvDevInfo *__restrict__ info,
+                               const int32_t *__restrict__ need) {
+  if (info->status || skip_pass(need)) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = blockIdx.y;
   if (e >= NE) return;
@@ -407,8 +422,9 @@ __global__ void k_gram_reduce1(int Z, int S, int64_t NE, const double *__restric
 }
 
 __global__ void k_gram_reduce2(int L, int S, const double *__restrict__ part2,
-                               double *__restrict__ G, const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
+                               double *__restrict__ G, const SvDevInfo *__restrict__ info,
+                               const int32_t *__restrict__ need) {
+  if (info->status || skip_pass(need)) return;
   const int LT = L / 16, NT = LT * (LT + 1) / 2;
   const int64_t NE = (int64_t)NT * 256;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -488,8 +504,14 @@ constexpr int CB_NW = CB_NT / 64;
 
 __global__ void __launch_bounds__(CB_NT)
 k_chol_drop_blk(int L, const double *__restrict__ G, double *__restrict__ Out,
-                int32_t *__restrict__ complete, double rtol, const SvDevInfo *__restrict__ info) {
+                int32_t *__restrict__ complete, double rtol, const SvDevInfo *__restrict__ info,
+                const int32_t *__restrict__ need) {
   if (info->status) return;
+  if (skip_pass(need)) {   // Out = I and nothing to complete: the product copies the panel
+    for (int e = threadIdx.x; e < L * L; e += blockDim.x) Out[e] = (e / L == e % L) ? 1.0 : 0.0;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) complete[j] = 0;
+    return;
+  }
   extern __shared__ double S[];
   const int LD = L + 1, NB = L / 16;
   double *dg = S + L * LD;              // diagonal of X'
@@ -664,6 +686,27 @@ __global__ void k_fill_cols(int64_t R, int L, double *__restrict__ X,
   }
 }
 
+// *need = 1 unless the Gram G of the panel that a Cholesky QR pass has just
+// orthonormalised was within tau of the identity after column scaling
+// (|G_ic| <= tau sqrt(G_ii G_cc) for every i != c) and that pass completed
+// no column.  Then the panel's condition number was at most
+// sqrt((1 + (L-1) tau) / (1 - (L-1) tau)), and one pass already left it
+// orthonormal to a small multiple of the unit roundoff: a second pass would
+// change nothing but rounding.
+__global__ void k_orth_gate(int L, const double *__restrict__ G, const int32_t *__restrict__ complete,
+                            double tau, int32_t *__restrict__ need,
+                            const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  bool more = false;
+  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
+    const int i = e / L, c = e % L;
+    if (c < i) more |= !(fabs(G[e]) <= tau * sqrt(G[i * L + i] * G[c * L + c]));
+  }
+  for (int j = threadIdx.x; j < L; j += blockDim.x) more |= complete[j] != 0;
+  more = __syncthreads_or(more);
+  if (threadIdx.x == 0) *need = more ? 1 : 0;
+}
+
 // sigma_c = sqrt(max(lambda_c, 0)); column c of the R x k panel X is scaled by
 // 1 / sigma_c, or zeroed when sigma_c <= tol * sigma_0 (left for completion).
 __global__ void k_inv_sigma_cols(int64_t R, int k, const double *__restrict__ lam,
@@ -774,8 +817,8 @@ size_t ts_gram_ws(int64_t R, int L) {
   return (size_t)(Z + 16) * NT * 256;
 }
 
-void ts_gram(hipStream_t st, int64_t R, int L, const double *Y, double *G, double *ws,
-             const SvDevInfo *info) {
+void ts_gram_if(hipStream_t st, int64_t R, int L, const double *Y, double *G, double *ws,
+                const SvDevInfo *info, const int32_t *need) {
   const int LT = L / 16, NT = LT * (LT + 1) / 2;
   int64_t Z = std::min<int64_t>(256, std::max<int64_t>(1, (R + 127) / 128));
   int64_t rpb = (R + Z - 1) / Z;
@@ -785,14 +828,19 @@ void ts_gram(hipStream_t st, int64_t R, int L, const double *Y, double *G, doubl
   const int64_t NE = (int64_t)NT * 256;
   double *part = ws, *part2 = ws + Z * NE;
 #define SV_TG(LL) hipLaunchKernelGGL((k_ts_gram<LL>), dim3((unsigned)Z), dim3(256), 0, st, R, rpb, \
-                                     Y, part, info)
+                                     Y, part, info, need)
   switch (L) { case 16: SV_TG(16); break; case 32: SV_TG(32); break;
                case 64: SV_TG(64); break; case 128: SV_TG(128); break; }
 #undef SV_TG
   hipLaunchKernelGGL(k_gram_reduce1, dim3((unsigned)((NE + 255) / 256), (unsigned)S), dim3(256), 0,
-                     st, (int)Z, S, NE, part, part2, info);
+                     st, (int)Z, S, NE, part, part2, info, need);
   hipLaunchKernelGGL(k_gram_reduce2, dim3((unsigned)((NE + 255) / 256)), dim3(256), 0, st, L, S,
-                     part2, G, info);
+                     part2, G, info, need);
+}
+
+void ts_gram(hipStream_t st, int64_t R, int L, const double *Y, double *G, double *ws,
+             const SvDevInfo *info) {
+  ts_gram_if(st, R, L, Y, G, ws, info, nullptr);
 }
 
 void ts_mul_lt(hipStream_t st, int64_t R, int L, const double *X, const double *Out, double *Y,
@@ -804,8 +852,8 @@ void ts_mul_lt(hipStream_t st, int64_t R, int L, const double *X, const double *
 #undef SV_TM
 }
 
-void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *complete,
-               double rtol, const SvDevInfo *info) {
+void chol_drop_if(hipStream_t st, int L, const double *G, double *Out, int32_t *complete,
+                  double rtol, const SvDevInfo *info, const int32_t *need) {
   static bool once = false;
   if (!once) {
     allow_big_lds(k_chol_drop);
@@ -822,11 +870,17 @@ void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *com
     const size_t shb = ((size_t)L * (L + 3) + (size_t)CB_NW * 16 * 17) * sizeof(double) +
                        (size_t)L * sizeof(int);
     hipLaunchKernelGGL(k_chol_drop_blk, dim3(1), dim3(CB_NT), shb, st, L, G, Out, complete, rtol,
-                       info);
+                       info, need);
     return;
   }
   const size_t sh = (size_t)L * (L + 2) * sizeof(double) + (size_t)L * sizeof(int);
-  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(CD_NT), sh, st, L, G, Out, complete, rtol, info);
+  hipLaunchKernelGGL(k_chol_drop, dim3(1), dim3(CD_NT), sh, st, L, G, Out, complete, rtol, info,
+                     need);
+}
+
+void chol_drop(hipStream_t st, int L, const double *G, double *Out, int32_t *complete,
+               double rtol, const SvDevInfo *info) {
+  chol_drop_if(st, L, G, Out, complete, rtol, info, nullptr);
 }
 
 void fill_cols(hipStream_t st, int64_t R, int L, double *X, const int32_t *complete,
@@ -861,6 +915,35 @@ double *orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, int pa
     if (mf) ts_gram(st, R, L, src, G, ws, info);
     else gemm_f64_sk(st, true, false, L, L, R, 1.0, src, L, src, L, 0.0, G, L, ws, ws_len, info);
     chol_drop(st, L, G, Out, complete, rtol, info);
+    if (mf) ts_mul_lt(st, R, L, src, Out, dst, info);
+    else gemm_f64(st, false, true, R, L, L, 1.0, src, L, Out, L, 0.0, dst, L, info);
+    fill_cols(st, R, L, dst, complete, seed * 3 + (uint64_t)pass, info);
+    double *t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
+// orth_cols with two passes, the second gated on k_orth_gate: it runs only
+// when the first pass completed a column or its input was not orthonormal to
+// within ORTH_GATE_TAU, and otherwise the product copies the panel (the gated
+// Cholesky writes Out = I), so the result is in X either way.  For the
+// factors of the initial SVD (U = Q F and V = W F diag(1/sigma)) the input is
+// orthonormal to rounding unless some column had to be completed.
+double *orth_cols_cond(hipStream_t st, int64_t R, int L, double *X, double *Y, double *G,
+                       double *Out, int32_t *complete, int32_t *need, double *ws, size_t ws_len,
+                       uint64_t seed, double rtol, const SvDevInfo *info) {
+  const bool mf = (L == 16 || L == 32 || L == 64 || L == 128) && ws_len >= ts_gram_ws(R, L);
+  double *src = X, *dst = Y;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int32_t *gate = pass == 0 ? nullptr : need;
+    if (mf) ts_gram_if(st, R, L, src, G, ws, info, gate);
+    else gemm_f64_sk(st, true, false, L, L, R, 1.0, src, L, src, L, 0.0, G, L, ws, ws_len, info);
+    chol_drop_if(st, L, G, Out, complete, rtol, info, gate);
+    if (pass == 0)
+      hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, L, G, complete, ORTH_GATE_TAU,
+                         need, info);
     if (mf) ts_mul_lt(st, R, L, src, Out, dst, info);
     else gemm_f64(st, false, true, R, L, L, 1.0, src, L, Out, L, 0.0, dst, L, info);
     fill_cols(st, R, L, dst, complete, seed * 3 + (uint64_t)pass, info);

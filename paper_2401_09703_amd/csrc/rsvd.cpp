@@ -11,7 +11,8 @@
 // and on the CSR of A^T that the radix-sort transpose builds once; every
 // orth() is Cholesky QR with column dropping and random completion (one pass
 // where the basis only feeds the next product, two where it becomes a
-// factor); the l x l eigenproblem is the Rayleigh-Ritz eigensolver of the
+// factor, the second of U's and V's only when their first had work to do);
+// the l x l eigenproblem is the Rayleigh-Ritz eigensolver of the
 // update path.
 #include <hip/hip_runtime.h>
 
@@ -20,6 +21,7 @@
 #include <vector>
 
 #include "../../include/svlcov.h"
+#include "k_rsvd.hpp"
 #include "kernels.hpp"
 
 namespace {
@@ -113,7 +115,7 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
            al((size_t)nnz * 8);
   total += 2 * al((size_t)m * l * 8) + 2 * al((size_t)n * l * 8);
   total += 2 * al((size_t)l * l * 8) + al((size_t)l * 4) + al(ws_len * 8) + al(ewd * 8) +
-           al((size_t)k * 8) + al((size_t)k * l * 8);
+           al((size_t)k * 8) + al((size_t)k * l * 8) + al(sizeof(int32_t));
   char *mem = nullptr;
   RV_TRY(hipMallocAsync((void **)&mem, total, st));
   char *p = mem;
@@ -151,6 +153,7 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
   double *ework = (double *)take(ewd * 8);
   double *lam = (double *)take((size_t)k * 8);
   double *Fv = (double *)take((size_t)k * l * 8);
+  int32_t *need = (int32_t *)take(sizeof(int32_t));
 
   PhaseTimer tm(st, phase_ms != nullptr);
   RV_TRY_WS(hipMemsetAsync(info, 0, al(sizeof(SvDevInfo)) + svl::TRI_FLAG_WORDS * sizeof(unsigned),
@@ -192,25 +195,19 @@ svlcov_status svlcov_rsvd(const svlcov_csr *A, int32_t k, int32_t l, int32_t pow
   const int er = svl::eig_topk(st, l, G, k, lam, Fv, ework, flags, &epoch, info);
   tm.mark(4);
   // U = Q F is orthonormal when F is; the vectors of a (near-)zero cluster
-  // of eigenvalues need not be, so U too gets two passes in column order
-  // (the columns of resolved singular values come first and stay as they are)
+  // of eigenvalues need not be, so U too is orthonormalised in column order
+  // (the columns of resolved singular values come first and stay as they
+  // are), with the second pass only where the first had work to do
   svl::gemm_f64(st, false, true, m, k, l, 1.0, Qm, l, Fv, l, 0.0, U, k, info);
   tm.mark(2);
-  {
-    double *ux = U, *uy = Pm;
-    (void)svl::orth_cols(st, m, k, ux, uy, 2, G, Out, complete, ws, ws_len, ++seed, ORTH_RTOL,
-                         info);
-  }
+  (void)svl::orth_cols_cond(st, m, k, U, Pm, G, Out, complete, need, ws, ws_len, ++seed,
+                            ORTH_RTOL, info);   // result in U
   tm.mark(4);
   svl::gemm_f64(st, false, true, n, k, l, 1.0, Pn, l, Fv, l, 0.0, V, k, info);
   svl::inv_sigma_cols(st, n, k, lam, sigma, V, SIGMA_TOL, info);
   tm.mark(2);
-  {   // two passes V -> Qn -> V
-    double *vx = V, *vy = Qn;
-    double *r = svl::orth_cols(st, n, k, vx, vy, 2, G, Out, complete, ws, ws_len, ++seed,
-                               ORTH_RTOL, info);
-    (void)r;   // == V
-  }
+  (void)svl::orth_cols_cond(st, n, k, V, Qn, G, Out, complete, need, ws, ws_len, ++seed,
+                            ORTH_RTOL, info);   // result in V
   tm.mark(4);
   svl::check_finite(st, k, sigma, info, 0);
   tm.mark(-1);
