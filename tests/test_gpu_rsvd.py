@@ -122,6 +122,34 @@ def test_rank_deficient_completes_orthonormally():
     np.testing.assert_allclose((Ug * sg) @ Vg.T, A.to_dense(), atol=1e-10 * so[0])
 
 
+def test_wide_spectrum_factors_stay_orthonormal():
+    """Singular values over five decades among the top k (sigma_k ~ 1e-5
+    sigma_0, squared 1e-10: far above the pivot-drop floor of 1e-13).
+    V = W F / sigma then carries the largest rounding of the test set (its
+    column-scaled Gram ~1e-7 off the identity, under the 1e-6 bound below
+    which the second Cholesky QR pass is skipped): one pass must still leave
+    both factors orthonormal, with sigma, the Ritz property and the leading
+    subspaces in agreement with the oracle on the scale of sigma_0."""
+    rng = np.random.default_rng(21)
+    m, n, k, l = 800, 600, 32, 64
+    S = bernoulli_uniform(m, n, 0.05, rng).to_scipy()
+    j = np.arange(n)
+    d = np.where(j < k, 10.0 ** (-5.0 * j / (k - 1)), 1e-8)
+    A = CSR.from_scipy(sp.csr_matrix(S @ sp.diags(d)))
+    Om = _omega(n, l, 22)
+    Ug, sg, Vg = _gpu(A, k, l, 2, Om)
+    Uo, so, Vo = orsvd.rsvd(A.to_scipy(), k, Om, 2)
+    assert so[-1] > 5e-6 * so[0]
+    assert np.abs(sg - so).max() < 1e-10 * so[0]
+    assert metrics.orth_err(Ug) < ORTH_TOL and metrics.orth_err(Vg) < ORTH_TOL
+    M = Ug.T @ (A.to_scipy() @ Vg)
+    assert np.abs(M - np.diag(sg)).max() < 1e-10 * so[0]
+    p = metrics.gap_prefix(np.append(so, 0.0), k, 1e-3)
+    assert p >= 8
+    assert metrics.sin_angle(Ug[:, :p], Uo[:, :p]) < 1e-9
+    assert metrics.sin_angle(Vg[:, :p], Vo[:, :p]) < 1e-9
+
+
 def test_zero_matrix():
     A = CSR(64, 48, np.zeros(65, np.int64), np.zeros(0, np.int32), np.zeros(0))
     Ug, sg, Vg = _gpu(A, 8, 16, 1, _omega(48, 16, 12))
