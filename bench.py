@@ -93,6 +93,9 @@ def parse():
                     help="print a summary of a rocprofv3 --kernel-trace --stats output and exit")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="print every counter of one rocprofv3 --pmc run per kernel (mean per "
+                         "dispatch) and exit")
     ap.add_argument("--phase", default="tridiag", help="phase whose kernel --summarize-pmc covers")
     ap.add_argument("--calib-mib", type=int, default=0, help="size of the calibration copy")
     return ap.parse_args()
@@ -133,6 +136,31 @@ def _pmc(d, counter):
             name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
             out.setdefault(name, []).append(float(r["Counter_Value"]))
     return out
+
+
+def summarize_counters(d, match=""):
+    """Per kernel (name containing `match`): dispatches and the mean per
+    dispatch of every counter in the run.  The SQ_INSTS_VALU_MFMA_MOPS_<type>
+    counters count matrix-core operations in units of 512 flops; each present
+    adds mfma_flops_<type> = 512 x its mean."""
+    tab = {}
+    for f in _csvs(d, "counter_collection.csv"):
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+            if match not in name:
+                continue
+            tab.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    for name in sorted(tab):
+        cs = tab[name]
+        n = max(len(v) for v in cs.values())
+        means = {c: sum(v) / len(v) for c, v in cs.items()}
+        parts = [f"{c}={means[c]:.6g}" for c in sorted(means)]
+        for c in sorted(means):
+            if c.startswith("SQ_INSTS_VALU_MFMA_MOPS_"):
+                parts.append(f"mfma_flops_{c[len('SQ_INSTS_VALU_MFMA_MOPS_'):].lower()}="
+                             f"{512 * means[c]:.6g}")
+        print(f"{name[:72]} | dispatches {n} | " + " ".join(parts))
 
 
 def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
@@ -671,6 +699,9 @@ def main():
     args = parse()
     if args.summarize_stats:
         summarize_stats(args.summarize_stats)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.summarize_pmc:
         summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.phase, args.calib_mib)

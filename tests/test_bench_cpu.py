@@ -82,3 +82,21 @@ def test_stored_traffic_needs_the_current_sources(tmp_path, monkeypatch):
     good.write_text("sources_sha256: 0\ntraffic_bytes_per_launch: 1234\n")
     assert bench.stored_traffic("tridiag") is None
     assert bench.stored_traffic("no-such-phase") is None
+
+
+def test_summarize_counters_means_and_mfma_flops(tmp_path):
+    hdr = ["Kernel_Name", "Counter_Name", "Counter_Value"]
+    _write_csv(str(tmp_path / "c" / "p_counter_collection.csv"), hdr,
+               [["(anonymous namespace)::k_gram_lowp<2>(long)", "SQ_INSTS_VALU_MFMA_MOPS_BF16", 1000.0],
+                ["(anonymous namespace)::k_gram_lowp<2>(long)", "GRBM_GUI_ACTIVE", 10.0],
+                ["(anonymous namespace)::k_gram_lowp<2>(long)", "SQ_INSTS_VALU_MFMA_MOPS_BF16", 3000.0],
+                ["(anonymous namespace)::k_gram_lowp<2>(long)", "GRBM_GUI_ACTIVE", 30.0],
+                ["k_other(int)", "GRBM_GUI_ACTIVE", 5.0]])
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        bench.summarize_counters(str(tmp_path))
+    lines = buf.getvalue().splitlines()
+    assert len(lines) == 2 and lines[0].startswith("k_gram_lowp<2>(long) | dispatches 2")
+    assert "GRBM_GUI_ACTIVE=20 " in lines[0] and "SQ_INSTS_VALU_MFMA_MOPS_BF16=2000" in lines[0]
+    assert "mfma_flops_bf16=1.024e+06" in lines[0]
+    assert "mfma_flops" not in lines[1]
