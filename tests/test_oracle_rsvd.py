@@ -84,3 +84,37 @@ def test_planted_transposed_operand_is_caught():
     good = metrics.sin_angle(U, Ul[:, :k])
     bad = metrics.sin_angle(Um, Ul[:, :k])
     assert good < 1e-3 and bad > 10 * good
+
+
+def _spectrum_matrix(rng, m, n, sv):
+    X = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    Y = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    return sp.csr_matrix((X * sv) @ Y.T)
+
+
+def test_within_the_power_scheme_error_bound():
+    """Halko, Martinsson and Tropp (2011), the power-scheme bound: with l =
+    k + p test vectors and q power iterations, except with probability at
+    most 6 p^-p, ||(I - Q Q^T) A|| <= (1 + 11 sqrt(k + p) sqrt(min(m, n)))^(1/(2q+1))
+    sigma_{k+1}; truncating Q^T A to rank k adds at most sigma_{k+1}.  Checked
+    against sigma_{k+1} of the LAPACK SVD over several test matrices, with a
+    spectrum where the bound is far below sigma_1 (so a range finder that
+    ignores A fails it)."""
+    rng = np.random.default_rng(6)
+    m, n, k, p = 500, 400, 10, 10
+    sv = 0.7 ** np.arange(n)
+    A = _spectrum_matrix(rng, m, n, sv)
+    Ad = A.toarray()
+    s_exact = np.linalg.svd(Ad, compute_uv=False)
+    for q in (0, 1, 2):
+        bound = ((1 + 11 * np.sqrt(k + p) * np.sqrt(min(m, n))) ** (1 / (2 * q + 1)) + 1) * s_exact[k]
+        assert bound < 0.5 * s_exact[0] or q == 0
+        for trial in range(3):
+            U, s, V = rsvd.rsvd(A, k, rng.standard_normal((n, k + p)), power=q)
+            err = np.linalg.norm(Ad - (U * s) @ V.T, 2)
+            assert s_exact[k] * (1 - 1e-12) <= err <= bound
+    # a basis that ignores A: same shapes, error of order sigma_1
+    Qr = np.linalg.qr(rng.standard_normal((m, k)))[0]
+    err_r = np.linalg.norm(Ad - Qr @ (Qr.T @ Ad), 2)
+    q1 = ((1 + 11 * np.sqrt(k + p) * np.sqrt(min(m, n))) ** (1 / 3) + 1) * s_exact[k]
+    assert err_r > q1
