@@ -33,7 +33,15 @@
  *     allocates (factors and workspaces).
  *   - Streams: all device work of a state is ordered on the stream given in
  *     svlcov_options (NULL = a stream the library creates).  Update calls are
- *     asynchronous; svlcov_sync() waits and reports deferred errors.
+ *     asynchronous; svlcov_sync() waits and reports deferred errors.  Device
+ *     inputs are read on that stream with no other ordering: work on another
+ *     stream that produces them must be complete, or the state's stream must
+ *     wait for it (an event recorded after the producer, hipStreamWaitEvent
+ *     on svlcov_stream()), before the update call.
+ *   - Memory: the state allocates its factors and workspaces through the
+ *     dev_alloc / dev_free hooks of svlcov_options when both are given (so a
+ *     framework's allocator can own them), else with hipMallocAsync /
+ *     hipFreeAsync on the state's stream.
  *   - Errors: return codes only, nothing is thrown or printed across the ABI.
  *     A call that fails validation on the host leaves the state unchanged.  A
  *     failure found on the device (malformed device-resident CSR, non-finite
@@ -96,8 +104,21 @@ typedef struct {
                               /* Cholesky (drop when d_j <= rank_tol * max_i   */
                               /* ||e_i||^2); <= 0 selects the mode's default   */
   double cond_reset;          /* fold W into the tall factor when its 1-norm   */
-                              /* condition number exceeds this; <= 0 default   */
+                              /* condition number exceeds this (default 1e4 in */
+                              /* FP64, 1e2 in FP32 and BF16X3); <= 0 default   */
   int32_t validate_device_inputs; /* 1: check device CSR on the device         */
+  /* Device allocator hooks (both or neither; NULL = hipMallocAsync /
+   * hipFreeAsync).  dev_alloc returns bytes of device memory of the state's
+   * device that may be used by work enqueued on `stream` (the state's stream)
+   * from the moment it returns, or NULL on failure (SVLCOV_E_NOMEM).
+   * dev_free releases a block from dev_alloc; work already enqueued on
+   * `stream` may still use it, so it may be reused only by work ordered
+   * after that (a stream-ordered caching allocator satisfies this).  Both are
+   * called from the thread of the state's call (a request server's worker
+   * thread for attached states), never concurrently for one state. */
+  void *(*dev_alloc)(size_t bytes, void *stream, void *ctx);
+  void (*dev_free)(void *ptr, size_t bytes, void *stream, void *ctx);
+  void *alloc_ctx;              /* passed to both hooks                          */
 } svlcov_options;
 
 typedef struct {
@@ -375,6 +396,10 @@ svlcov_status svlcov_project_batch(int32_t n, svlcov_state *const *states, const
 /* The hipStream_t the state enqueues on. */
 void *svlcov_stream(svlcov_state *h);
 
+/* Release the state and all device memory it holds (after waiting for its
+ * stream).  A call in flight on the state from another thread finishes
+ * first.  A state attached to a request server is not released (the call
+ * returns without effect): destroy the server first. */
 void svlcov_destroy(svlcov_state *h);
 
 const char *svlcov_status_str(svlcov_status s);

@@ -44,11 +44,41 @@ class _Csr(C.Structure):
                 ("val_dtype", C.c_int32), ("on_device", C.c_int32)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
                 ("row_capacity", C.c_int64), ("col_capacity", C.c_int64),
                 ("rank_tol", C.c_double), ("cond_reset", C.c_double),
-                ("validate_device_inputs", C.c_int32)]
+                ("validate_device_inputs", C.c_int32),
+                ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    """dev_alloc hook backed by torch's caching allocator (ctx = device ordinal):
+    the block is tied to the state's stream, so torch reuses it only for work
+    ordered after the state's earlier work."""
+    try:
+        import torch
+        dev = int(ctx or 0)
+        s = torch.cuda.ExternalStream(stream, device=dev) if stream else None
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes), device=dev, stream=s))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# one pair of C callbacks for the whole process (they must outlive every state)
+_TORCH_HOOKS = (_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free))
 
 
 class _Stats(C.Structure):
@@ -194,6 +224,25 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
 
 _lib = load_library()
 
+# Every live state and server, closed explicitly at interpreter exit (servers
+# first): their HIP frees and stream/event destroys then run while the HIP
+# runtime and any profiler attached to it are still up, not from __del__ during
+# module teardown.
+import atexit as _atexit
+import weakref as _weakref
+
+_LIVE_STATES = _weakref.WeakSet()
+_LIVE_SERVERS = _weakref.WeakSet()
+
+
+@_atexit.register
+def close_all():
+    """Close every live Server, then every live TruncatedSVD."""
+    for srv in list(_LIVE_SERVERS):
+        srv.close()
+    for svd in list(_LIVE_STATES):
+        svd.close()
+
 
 def _check(code: int, where: str):
     if code != 0:
@@ -296,11 +345,15 @@ def rsvd(A, k: int, l: int = None, power: int = 2, Omega=None, seed: int = 0, st
 
 class TruncatedSVD:
     """A rank-k truncated SVD kept on the GPU in the extended form
-    U = U_base W_U, V = V_base W_V (Section 3.2), updated by the library."""
+    U = U_base W_U, V = V_base W_V (Section 3.2), updated by the library.
+    allocator="torch" makes torch's caching allocator own the state's device
+    memory (the svlcov_options allocator hooks); the default is the library's
+    own stream-ordered HIP allocations."""
 
     def __init__(self, U, s, V, precision: str = "fp64", device: int = 0, stream=None,
                  row_capacity: int = 0, col_capacity: int = 0, rank_tol: float = 0.0,
-                 cond_reset: float = 0.0, validate_device_inputs: bool = True):
+                 cond_reset: float = 0.0, validate_device_inputs: bool = True,
+                 allocator: str = None):
         on_dev = 0
         if _is_torch(U):
             # device factors (FP64 CUDA tensors), read on the state's stream
@@ -327,6 +380,12 @@ class TruncatedSVD:
         opt.rank_tol = rank_tol
         opt.cond_reset = cond_reset
         opt.validate_device_inputs = 1 if validate_device_inputs else 0
+        if allocator == "torch":
+            # the state's factors and workspaces come from torch's caching allocator
+            opt.dev_alloc, opt.dev_free = _TORCH_HOOKS
+            opt.alloc_ctx = device
+        elif allocator is not None:
+            raise ValueError(f"allocator must be None or 'torch', not {allocator!r}")
         h = C.c_void_p()
         _check(_lib.svlcov_init(C.byref(h), m_, n_, k_, pU, ps, pV, on_dev, C.byref(opt)),
                "svlcov_init")
@@ -334,10 +393,19 @@ class TruncatedSVD:
         self.k = int(k_)
         self.precision = precision
         self._keep = []
+        self._server = None   # the Server this state is attached to, if any
+        _LIVE_STATES.add(self)
 
-    # -- updates (asynchronous; inputs must stay alive until sync)
+    # -- updates (asynchronous; inputs must stay alive until sync).  Device
+    # inputs are read on the state's stream, which first waits for torch's
+    # current stream, so whatever torch enqueued to produce them comes first.
+    def _order_inputs(self, *objs):
+        if any(_is_torch(getattr(o, "row_ptr", o)) for o in objs if o is not None):
+            self._follow_torch()
+
     def add_rows(self, E, approx: "Approx" = None):
         st = _csr_struct(E, self._keep)
+        self._order_inputs(E, approx.start if approx is not None else None)
         if approx is None:
             _check(_lib.svlcov_add_rows(self._h, C.byref(st)), "svlcov_add_rows")
         else:
@@ -347,6 +415,7 @@ class TruncatedSVD:
 
     def add_cols(self, Ec_T, approx: "Approx" = None):
         st = _csr_struct(Ec_T, self._keep)
+        self._order_inputs(Ec_T, approx.start if approx is not None else None)
         if approx is None:
             _check(_lib.svlcov_add_cols(self._h, C.byref(st)), "svlcov_add_cols")
         else:
@@ -360,6 +429,11 @@ class TruncatedSVD:
         / -RPI variant."""
         a = _csr_struct(D_T, self._keep)
         b = _csr_struct(Em_T, self._keep)
+        starts = []
+        for ap in (approx if isinstance(approx, (tuple, list)) else [approx]):
+            if ap is not None:
+                starts += list(ap.start) if isinstance(ap.start, (tuple, list)) else [ap.start]
+        self._order_inputs(D_T, Em_T, *starts)
         if approx is None:
             _check(_lib.svlcov_update_weights(self._h, C.byref(a), C.byref(b)),
                    "svlcov_update_weights")
@@ -481,9 +555,15 @@ class TruncatedSVD:
                 for i in range(NUM_PHASES)}
 
     def close(self):
+        """Destroy the state.  A state attached to a live Server belongs to it
+        until the server is closed (the library would refuse the destroy)."""
         if getattr(self, "_h", None):
+            srv = getattr(self, "_server", None)
+            if srv is not None and getattr(srv, "_h", None):
+                raise RuntimeError("TruncatedSVD is attached to a live Server; close the server first")
             _lib.svlcov_destroy(self._h)
             self._h = None
+            _LIVE_STATES.discard(self)
 
     def __del__(self):
         try:
@@ -589,13 +669,18 @@ class Server:
         _check(_lib.svlcov_server_create(C.byref(h), C.byref(opt)), "svlcov_server_create")
         self._h = h
         self._keep = {}
+        self._attached = []   # states stay alive while the server drives them
+        _LIVE_SERVERS.add(self)
 
     def attach(self, svd: "TruncatedSVD") -> int:
         mid = C.c_int32()
         _check(_lib.svlcov_server_attach(self._h, svd._h, C.byref(mid)), "svlcov_server_attach")
+        self._attached.append(svd)
+        svd._server = self
         return int(mid.value)
 
     def submit(self, matrix_id: int, update) -> int:
+        self._order_device_inputs(update)
         keep = []
         a = _csr_struct(update[1], keep)
         b = _csr_struct(update[2], keep) if update[0] == "weights" else None
@@ -607,6 +692,14 @@ class Server:
         if any(_is_torch(x) for x in keep):
             self._keep[int(t.value)] = keep
         return int(t.value)
+
+    @staticmethod
+    def _order_device_inputs(update):
+        """The server reads device inputs on its own streams: whatever torch
+        enqueued to produce them must have finished first."""
+        if any(_is_torch(getattr(x, "row_ptr", None)) for x in update[1:]):
+            import torch
+            torch.cuda.current_stream().synchronize()
 
     def wait(self, ticket: int):
         """(status code, latency in ms) of a request; blocks."""
@@ -639,6 +732,10 @@ class Server:
             _lib.svlcov_server_destroy(self._h)
             self._h = None
             self._keep.clear()
+            for svd in self._attached:
+                svd._server = None
+            self._attached = []
+            _LIVE_SERVERS.discard(self)
 
     def __del__(self):
         try:
@@ -648,5 +745,5 @@ class Server:
 
 
 __all__ = ["TruncatedSVD", "DeviceCSR", "rsvd", "SvlcovError", "Server", "project_batch", "Approx",
-           "spmm_variants", "spmm_tune_set", "spmm_tune_get", "load_spmm_tuning", "spmm_row_bin", "load_library", "LIB_PATH", "EXPORTS",
+           "close_all", "spmm_variants", "spmm_tune_set", "spmm_tune_get", "load_spmm_tuning", "spmm_row_bin", "load_library", "LIB_PATH", "EXPORTS",
            "FP64", "FP32", "BF16X3"]

@@ -258,10 +258,12 @@ void dispatch(svlcov_server *srv, Req *r) {
   Slot &sl = srv->slots[r->slot];
   std::swap(h->ws, sl.ws);
   std::swap(h->stage, sl.stage);
+  h->lent = true;
   svlcov_status st;
   if (r->op == 0) st = svlcov_add_rows(h, &r->A.c);
   else if (r->op == 1) st = svlcov_add_cols(h, &r->A.c);
   else st = svlcov_update_weights(h, &r->A.c, &r->B.c);
+  h->lent = false;
   std::swap(h->ws, sl.ws);
   std::swap(h->stage, sl.stage);
   if (st == SVLCOV_OK && hipEventRecord(r->done, h->stream) != hipSuccess) st = SVLCOV_E_DEVICE;
@@ -398,8 +400,9 @@ svlcov_status svlcov_server_attach(svlcov_server *srv, svlcov_state *h, int32_t 
   if (st != SVLCOV_OK) return st;
   std::lock_guard<std::mutex> lk(srv->mu);
   // the state's own workspaces are not needed any more: requests borrow a slot's
-  if (h->ws.p) { (void)hipFree(h->ws.p); h->ws = svl_state::DevBuf{}; }
-  if (h->stage.p) { (void)hipFree(h->stage.p); h->stage = svl_state::DevBuf{}; }
+  svl_state::release(h, h->ws);
+  svl_state::release(h, h->stage);
+  (void)hipStreamSynchronize(h->stream);
   h->coop_chain = &srv->coop_chain;
   h->coop_chain_live = &srv->coop_live;
   *matrix_id = (int32_t)srv->mats.size();

@@ -36,6 +36,14 @@ void proj_offsets(int op, int K, int64_t s, int q, size_t *cp64, size_t *cp32, s
 }  // namespace svl_state
 
 struct svlcov_state {
+  // device allocator hooks (both set or both NULL; see svlcov_options)
+  void *(*dev_alloc)(size_t, void *, void *) = nullptr;
+  void (*dev_free)(void *, size_t, void *, void *) = nullptr;
+  void *alloc_ctx = nullptr;
+  // set by a request server while it lends its slot workspaces to the state:
+  // a lent buffer that has to grow is replaced with the server's allocator
+  // (plain stream-ordered HIP), never with the hooks
+  bool lent = false;
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -77,6 +85,27 @@ struct svlcov_state {
   size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
 };
 
+
+namespace svl_state {
+// Device memory owned by the state: through its hooks when set (and `hooks`),
+// else stream-ordered HIP on the state's stream.
+inline hipError_t state_alloc(svlcov_state *h, void **p, size_t bytes, bool hooks = true) {
+  if (hooks && h->dev_alloc) {
+    *p = h->dev_alloc(bytes, (void *)h->stream, h->alloc_ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipMallocAsync(p, bytes, h->stream);
+}
+inline void state_free(svlcov_state *h, void *p, size_t bytes, bool hooks = true) {
+  if (!p) return;
+  if (hooks && h->dev_free) h->dev_free(p, bytes, (void *)h->stream, h->alloc_ctx);
+  else (void)hipFreeAsync(p, h->stream);
+}
+inline void release(svlcov_state *h, DevBuf &b) {
+  state_free(h, b.p, b.bytes);
+  b = DevBuf{};
+}
+}  // namespace svl_state
 
 // Cooperative-launch ordering hooks (no-ops unless a server drives the state).
 inline void coop_enter(svlcov_state *h) {

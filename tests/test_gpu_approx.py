@@ -47,7 +47,7 @@ def _lockstep(svd, kind, E, method, l, t, start, prec, label):
     assert r["angle_U"] <= tol["ang"] and r["angle_V"] <= tol["ang"], (label, r)
     st = svd.stats()
     kap = max(st["last_kappa_U"], st["last_kappa_V"])
-    orth = tol["orth"] if prec != "fp64" else max(tol["orth"], 1e3 * 2.2e-16 * min(kap, 1e8))
+    orth = tol["orth"] if prec != "fp64" else max(tol["orth"], 1e3 * 2.2e-16 * min(kap, 1e4))
     assert r["orth_U"] <= orth and r["orth_V"] <= orth, (label, r, st)
     return r
 
@@ -113,7 +113,7 @@ def test_weight_variant_matches_oracle(prec, m, n, k, s, dens, method, l, t):
         assert r["angle_U"] <= tol["ang"] and r["angle_V"] <= tol["ang"], r
         st = svd.stats()
         kap = max(st["last_kappa_U"], st["last_kappa_V"])
-        orth = tol["orth"] if prec != "fp64" else max(tol["orth"], 1e3 * 2.2e-16 * min(kap, 1e8))
+        orth = tol["orth"] if prec != "fp64" else max(tol["orth"], 1e3 * 2.2e-16 * min(kap, 1e4))
         assert r["orth_U"] <= orth and r["orth_V"] <= orth, (r, st)
     finally:
         svd.close()
@@ -248,5 +248,25 @@ def test_variant_argument_errors():
         svd.sync()
         # the state is unchanged and still usable
         _lockstep(svd, "rows", c["E"], "gkl", 5, 1, rng.standard_normal(20), "fp64", "after errors")
+    finally:
+        svd.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("kind", ["rows", "cols"])
+def test_rpi_rank_deficient_update(prec, kind):
+    """rank(Z) = 4 < l = 10 (30 update rows that are scaled copies of four):
+    the power iteration keeps four directions and drops the others by the
+    pivot rule, as the oracle's RPI does, and the two updates agree."""
+    L = _L()
+    rng = np.random.default_rng(7700 + len(kind))
+    m, n, k, s, l, t = 400, 300, 16, 30, 10, 2
+    c = small_case(rng, m, n, k, 4, kind=kind, density=0.08)
+    base = c["E"].to_dense()
+    E = CSR.from_dense(np.vstack([base[i % 4] * (1.0 + 0.5 * (i // 4)) for i in range(s)]))
+    svd = L.TruncatedSVD(c["U"], c["s"], c["V"], precision=prec)
+    try:
+        _lockstep(svd, kind, E, "rpi", l, t, rng.standard_normal((s, l)), prec,
+                  f"rank-deficient {kind} s={s} l={l} t={t}")
     finally:
         svd.close()

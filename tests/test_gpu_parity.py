@@ -11,6 +11,8 @@ FP32 and BF16x3 modes sigma_rel <= 1e-5, sin(angle) <= 1e-4 (gap 1e-3);
 orthonormality ||X^T X - I|| <= 1e-11 (FP64; or 1e3 eps cond(W) when the
 k x k factor is worse conditioned), 1e-5 (FP32), 5e-5 (BF16x3).
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -40,12 +42,13 @@ def _upd(c):
 def _orth_tol(prec, kappa):
     """Orthonormality bound of a factor kept as base * W: the extended
     decomposition (Section 3.2) represents U = U_base W, so rounding in W and
-    its inverse reaches U amplified by up to cond(W) (<= the reset threshold,
-    1e8 in FP64).  FP64: the fixed floor or 1e3 eps cond(W), whichever is
-    larger; FP32/BF16x3 fold W in at cond 1e2, so the fixed bound covers it."""
+    its inverse reaches U amplified by up to cond(W), which the FP64 reset
+    threshold holds at 1e4.  FP64: the fixed floor or 1e3 eps cond(W),
+    whichever is larger, so at most 2.2e-9; FP32/BF16x3 fold W in at cond
+    1e2, so the fixed bound covers it."""
     t = TOL[prec]["orth"]
     if prec == "fp64" and np.isfinite(kappa):
-        return max(t, 1e3 * 2.2e-16 * min(kappa, 1e8))
+        return max(t, 1e3 * 2.2e-16 * min(kappa, 1e4))
     return t
 
 
@@ -87,7 +90,8 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[4]}-m{c[0]}n{c[1]}k{c[2]}s{c[3]}")
 def test_single_update_parity(case, prec):
     m, n, k, s, kind, dens, dup, empty, inspan = case
-    rng = np.random.default_rng(hash((m, n, k, s, kind)) % 2**32)
+    # a fixed seed per case (crc32 of the case id), so a failure can be replayed
+    rng = np.random.default_rng(zlib.crc32(f"{kind}-m{m}n{n}k{k}s{s}".encode()))
     c = small_case(rng, m, n, k, s, kind=kind, density=dens, dup_rows=dup, empty_rows=empty,
                    in_span_rows=inspan)
     svd = _L().TruncatedSVD(c["U"], c["s"], c["V"], precision=prec)

@@ -66,3 +66,15 @@ def test_weights_workload(prec):
     from synth import config4_weights
     cfg = config4_weights(N=20000, k=64, steps=2, s=32, perturbed=2000, added=400)
     _run(cfg, prec, 2, 20000 + 16, 20000 + 16)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_ratings_workload_large_n(prec):
+    """k + s = 1928: past the size at which the residual Gram's Cholesky and
+    the tridiagonalisation keep their rows on chip, so the large-N branches
+    of both run, lock-step against the oracle."""
+    from synth import config3_ratings
+    cfg = config3_ratings(users=12000, items=4000, nnz=240_000, init_users=10000, k=128,
+                          steps=1, s=1800)
+    assert cfg["k"] + cfg["updates"][0][1].rows > 1745
+    _run(cfg, prec, 1, 12000 + 16, 4000 + 16)
