@@ -282,6 +282,25 @@ svlcov_status svlcov_spmm_tune_get(int32_t fp64, int32_t k, int32_t row_bin, int
 svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double *lam,
                                   double *vecs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, arguments and results as svlcov_sym_eig_topk, with no
+ * allocation at all.  The workspace (a copy of M, the eigensolver's work
+ * arrays, its status word and barrier flags) lives in one library-owned
+ * device array of SVLCOV_EIG_SCRATCH_BYTES per GPU, set up on the first call
+ * on that device and held until the process ends.  The call only enqueues
+ * work on `stream` (hipStream_t, NULL = default stream) and does not wait.
+ * SVLCOV_E_UNSUPPORTED when the workspace of (N, k), 8 (N^2 + 7N + 7Nk) bytes
+ * plus about 8 KiB per 32 rows and 17 KiB of flags, exceeds the array
+ * (N up to about 1500 at k = 64), as well as for N > 6144 or k > 128;
+ * SVLCOV_E_INVALID for bad arguments.  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind (the status word and flags are
+ * cleared at the start of each call): calls that overlap on one GPU, from two
+ * streams or two threads, race and must be serialised by the caller. */
+#define SVLCOV_EIG_SCRATCH_BYTES (24u << 20)
+svlcov_status svlcov_sym_eig_topk_noalloc(int64_t N, const double *M, int32_t k, double *lam,
+                                          double *vecs, void *stream);
+
 /* Initial rank-k truncated SVD of a sparse m x n matrix A, the starting
  * factors U', sigma, V' that every experiment of Section 5 updates from (the
  * paper leaves their computation to the randomised methods its introduction

@@ -148,7 +148,8 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_server_destroy", "svlcov_project_batch", "svlcov_add_rows_approx",
            "svlcov_add_cols_approx", "svlcov_spmm_variant_count", "svlcov_spmm_variant_shape",
            "svlcov_spmm_tune_set", "svlcov_spmm_tune_get", "svlcov_query_rows",
-           "svlcov_score_pairs", "svlcov_rsvd", "svlcov_update_weights_approx"]
+           "svlcov_score_pairs", "svlcov_rsvd", "svlcov_update_weights_approx",
+           "svlcov_sym_eig_topk_noalloc"]
 NUM_PHASES = 16
 RSVD_PHASES = ("transpose", "products", "orthonormalise", "small_eig", "final")
 
@@ -193,6 +194,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_phase_name.restype = C.c_char_p
     lib.svlcov_sym_eig_topk.argtypes = [I64, P, I32, P, P, P]
     lib.svlcov_sym_eig_topk.restype = I32
+    lib.svlcov_sym_eig_topk_noalloc.argtypes = [I64, P, I32, P, P, P]
+    lib.svlcov_sym_eig_topk_noalloc.restype = I32
     lib.svlcov_rsvd.argtypes = [C.POINTER(_Csr), I32, I32, I32, P, P, P, P, P, P]
     lib.svlcov_rsvd.restype = I32
     lib.svlcov_status_str.argtypes = [I32]
@@ -305,6 +308,27 @@ def sym_eig_topk(M, k: int, stream=None):
     st = stream if stream is not None else _t.cuda.current_stream().cuda_stream
     _check(_lib.svlcov_sym_eig_topk(N, M.data_ptr(), k, lam.data_ptr(), vecs.data_ptr(), st),
            "svlcov_sym_eig_topk")
+    return lam, vecs
+
+
+def sym_eig_topk_noalloc(M, k: int, lam=None, vecs=None, stream=None):
+    """sym_eig_topk through svlcov_sym_eig_topk_noalloc: the library allocates
+    nothing (its workspace is a fixed per-GPU array).  lam (k) and vecs (k x N)
+    may be passed in as preallocated FP64 CUDA tensors."""
+    import torch as _t
+    assert M.is_cuda and M.dtype == _t.float64 and M.is_contiguous()
+    N = M.shape[0]
+    if lam is None:
+        lam = _t.empty(k, dtype=_t.float64, device=M.device)
+    if vecs is None:
+        vecs = _t.empty((k, N), dtype=_t.float64, device=M.device)
+    assert lam.is_cuda and lam.dtype == _t.float64 and lam.numel() >= k
+    assert vecs.is_cuda and vecs.dtype == _t.float64 and vecs.is_contiguous()
+    assert vecs.numel() >= k * N
+    st = stream if stream is not None else _t.cuda.current_stream().cuda_stream
+    _check(_lib.svlcov_sym_eig_topk_noalloc(N, M.data_ptr(), k, lam.data_ptr(),
+                                            vecs.data_ptr(), st),
+           "svlcov_sym_eig_topk_noalloc")
     return lam, vecs
 
 

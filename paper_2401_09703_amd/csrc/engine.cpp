@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -1732,6 +1733,65 @@ svlcov_status svlcov_sym_eig_topk(int64_t N, const double *M, int32_t k, double 
   const int r = svl::eig_topk(st, N, A, k, lam, vecs, work, flags, &epoch, info);
   SV_TRY(hipFreeAsync(mem, st));
   return r == 0 ? SVLCOV_OK : SVLCOV_E_DEVICE;
+}
+
+}  // extern "C"
+
+// Workspace of svlcov_sym_eig_topk_noalloc: one fixed array per GPU, held
+// until the process ends.  In host code `scratch` names a host-side stand-in;
+// the device address of each GPU's copy is looked up once per device
+// (hipGetSymbolAddress, with that device current) and only that address is
+// handed to kernels.
+namespace {
+constexpr size_t EIG_SCRATCH_BYTES = (size_t)SVLCOV_EIG_SCRATCH_BYTES;
+static __device__ __align__(256) double scratch[EIG_SCRATCH_BYTES / sizeof(double)];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[SCRATCH_MAX_DEVICES];   // per device, null until looked up
+
+size_t eig_scratch_need(int64_t N, int32_t k) {
+  const size_t wd = svl::eig_work_doubles(N, k);
+  return ((size_t)N * N + wd) * sizeof(double) + 256 + sizeof(SvDevInfo) +
+         svl::TRI_FLAG_WORDS * sizeof(unsigned);
+}
+}  // namespace
+
+extern "C" {
+
+svlcov_status svlcov_sym_eig_topk_noalloc(int64_t N, const double *M, int32_t k, double *lam,
+                                          double *vecs, void *stream) {
+  if (N < 1 || k < 1 || k > N || !M || !lam || !vecs) return SVLCOV_E_INVALID;
+  if (N > svl::eig_max_n() || k > 128) return SVLCOV_E_UNSUPPORTED;
+  if (eig_scratch_need(N, k) > EIG_SCRATCH_BYTES) return SVLCOV_E_UNSUPPORTED;
+  int dev = 0;
+  SV_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return SVLCOV_E_UNSUPPORTED;
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_dev[dev]) {
+      void *p = nullptr;
+      SV_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      if (!p) return SVLCOV_E_DEVICE;
+      scratch_dev[dev] = p;
+    }
+    base = scratch_dev[dev];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  double *A = (double *)base;
+  double *work = A + (size_t)N * N;
+  const size_t wd = svl::eig_work_doubles(N, k);
+  SvDevInfo *info = (SvDevInfo *)(((uintptr_t)(work + wd) + 255) & ~(uintptr_t)255);
+  unsigned *flags = (unsigned *)(info + 1);
+  // status word and barrier flags start at zero on every call (a fill kernel,
+  // not a memset node, so that a captured graph replays it faithfully)
+  svl::zero_words(st, (unsigned *)info,
+                  sizeof(SvDevInfo) / sizeof(unsigned) + svl::TRI_FLAG_WORDS);
+  svl::copy_strided(st, N, N, M, N, 1, A, N, info);
+  unsigned epoch = 0;
+  const int r = svl::eig_topk(st, N, A, k, lam, vecs, work, flags, &epoch, info);
+  if (r != 0) return SVLCOV_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? SVLCOV_OK : SVLCOV_E_DEVICE;
 }
 
 const char *svlcov_status_str(svlcov_status s) {

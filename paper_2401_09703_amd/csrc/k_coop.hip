@@ -325,6 +325,11 @@ void set_status(hipStream_t st, SvDevInfo *info, int code) {
   hipLaunchKernelGGL(k_set_status, dim3(1), dim3(1), 0, st, info, code);
 }
 
+void zero_words(hipStream_t st, unsigned *p, size_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_zero_flags, dim3(16), dim3(256), 0, st, p, n);
+}
+
 unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned count) {
   if (*epoch > 0xF0000000u - count) {   // keep epochs monotonic: restart from zero
     hipLaunchKernelGGL(k_zero_flags, dim3(16), dim3(256), 0, st, flags, TRI_FLAG_WORDS);

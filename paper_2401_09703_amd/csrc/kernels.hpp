@@ -245,6 +245,8 @@ size_t eig_work_doubles(int64_t N, int k);
 // is the owner's running epoch counter for them (starts at 0).
 constexpr int TRI_MAX_BLOCKS = 256;
 constexpr size_t TRI_FLAG_WORDS = (size_t)TRI_MAX_BLOCKS * 16;
+// p[0..n) = 0 by a fill kernel on st (capturable: no memset node).
+void zero_words(hipStream_t st, unsigned *p, size_t n);
 int eig_topk(hipStream_t st, int64_t N, double *A, int k, double *lam, double *Fv,
              double *work, unsigned *flags, unsigned *epoch, const SvDevInfo *info);
 // The four stages of eig_topk, launched separately (same work layout).

@@ -143,3 +143,14 @@ def test_spmm_tuning_table_without_gpu(tmp_path):
     finally:
         for (f, k, b), v in saved.items():
             L.spmm_tune_set(f, k, b, v)
+
+
+def test_noalloc_eig_rejects_bad_sizes_before_device_use():
+    import paper_2401_09703_amd as L
+    lib = L._lib
+    buf = np.zeros(64)
+    p = buf.ctypes.data
+    assert lib.svlcov_sym_eig_topk_noalloc(2048, p, 64, p, p, None) == 7   # beyond the workspace
+    assert lib.svlcov_sym_eig_topk_noalloc(7000, p, 64, p, p, None) == 7   # N > 6144
+    assert lib.svlcov_sym_eig_topk_noalloc(8, p, 9, p, p, None) == 1       # k > N
+    assert lib.svlcov_sym_eig_topk_noalloc(8, None, 4, p, p, None) == 1
