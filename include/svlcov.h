@@ -130,6 +130,9 @@ typedef struct {
   double last_kappa_V;        /*   update (before any reset)                   */
   double last_min_kept_pivot; /* smallest kept / largest dropped pivot ratio   */
   double last_max_dropped_pivot; /* relative to max ||e_i||^2 (-1 if none)     */
+  int64_t iter_runs;          /* eigenproblems solved by the iterative solver  */
+  int64_t iter_steps;         /*   its filter steps in total                   */
+  int64_t iter_fallbacks;     /*   runs handed to the direct solver            */
 } svlcov_stats;
 
 /* Fill *opt with defaults: FP64, device 0, library stream, automatic
@@ -251,8 +254,10 @@ svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out);
  * the previous call into ms[0..n) and count[0..n) (either may be NULL).  The
  * phases are, in order: validate, spmm_w, sparse_gram, resid_gram, cholesky,
  * build_K, kkt_gemm, tridiag, bisect, stein, backtransform, recover_G,
- * orthonormalize, small_factor, trsm, commit. */
-#define SVLCOV_NUM_PHASES 16
+ * orthonormalize, small_factor, trsm, commit, subspace_iter (the iterative
+ * eigensolver of the FP32 / BF16x3 modes, which replaces tridiag .. 
+ * backtransform unless it falls back to them). */
+#define SVLCOV_NUM_PHASES 17
 svlcov_status svlcov_profile(svlcov_state *h, int32_t enable);
 svlcov_status svlcov_phase_times(svlcov_state *h, double *ms, int64_t *count, int32_t n);
 const char *svlcov_phase_name(int32_t i);

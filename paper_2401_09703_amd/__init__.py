@@ -85,7 +85,8 @@ class _Stats(C.Structure):
     _fields_ = [("updates", C.c_int64), ("resets_U", C.c_int64), ("resets_V", C.c_int64),
                 ("last_rank", C.c_int32), ("last_rank2", C.c_int32),
                 ("last_kappa_U", C.c_double), ("last_kappa_V", C.c_double),
-                ("last_min_kept_pivot", C.c_double), ("last_max_dropped_pivot", C.c_double)]
+                ("last_min_kept_pivot", C.c_double), ("last_max_dropped_pivot", C.c_double),
+                ("iter_runs", C.c_int64), ("iter_steps", C.c_int64), ("iter_fallbacks", C.c_int64)]
 
 
 class _Approx(C.Structure):
@@ -150,7 +151,7 @@ EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_a
            "svlcov_spmm_tune_set", "svlcov_spmm_tune_get", "svlcov_query_rows",
            "svlcov_score_pairs", "svlcov_rsvd", "svlcov_update_weights_approx",
            "svlcov_sym_eig_topk_noalloc"]
-NUM_PHASES = 16
+NUM_PHASES = 17
 RSVD_PHASES = ("transpose", "products", "orthonormalise", "small_eig", "final")
 
 

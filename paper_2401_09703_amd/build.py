@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsvlcov.so")
 SOURCES = ["k_sparse.hip", "k_dense.hip", "k_tridiag.hip", "k_eig.hip", "k_coop.hip", "k_approx.hip",
-           "k_query.hip", "k_rsvd.hip", "engine.cpp", "server.cpp", "rsvd.cpp"]
+           "k_query.hip", "k_rsvd.hip", "k_chefsi.hip", "engine.cpp", "server.cpp", "rsvd.cpp"]
 ARCH = os.environ.get("SVLCOV_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

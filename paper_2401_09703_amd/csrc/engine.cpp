@@ -29,12 +29,12 @@ constexpr double DEF_COND[3] = {1e4, 1e2, 1e2};   // FP64, FP32, BF16X3
 // profiling is enabled (names in svlcov_phase_name).
 enum Phase {
   PH_VALIDATE, PH_SPMM, PH_SGRAM, PH_RGRAM, PH_CHOL, PH_BUILDK, PH_KKT, PH_TRIDIAG, PH_BISECT,
-  PH_STEIN, PH_BACK, PH_RECOVER, PH_ORTH, PH_SMALL, PH_TRSM, PH_COMMIT, PH_COUNT
+  PH_STEIN, PH_BACK, PH_RECOVER, PH_ORTH, PH_SMALL, PH_TRSM, PH_COMMIT, PH_ITER, PH_COUNT
 };
 const char *PHASE_NAMES[PH_COUNT] = {
     "validate", "spmm_w", "sparse_gram", "resid_gram", "cholesky", "build_K", "kkt_gemm",
     "tridiag", "bisect", "stein", "backtransform", "recover_G", "orthonormalize",
-    "small_factor", "trsm", "commit"};
+    "small_factor", "trsm", "commit", "subspace_iter"};
 
 }  // namespace
 
@@ -251,7 +251,7 @@ size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int
   c.take<int32_t>(K);
   c.take<double>(K * N);
   c.take<double>(K * N);
-  c.take<double>(svl::eig_work_doubles(N, K));
+  c.take<double>(svl::eig_update_work_doubles(N, K));
   c.take<double>(K * K);
   for (int q = 0; q < 4; ++q) c.take<double>(K * K);
   c.take<int32_t>(2);
@@ -343,27 +343,55 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
     PhaseScope ps(h, PH_KKT);
     svl::gemm_f64(st, false, true, N, N, N, 1.0, Kmat, N, Kmat, N, 0.0, Mmat, N, h->info);
   }
-  {
-    PhaseScope ps(h, PH_TRIDIAG);
-    coop_enter(h);
-    const int trc = svl::eig_tridiag(st, N, Mmat, eigw, h->flags, &h->epoch, h->info);
-    coop_exit(h);
-    if (trc != 0) {
-      h->launch_failed = true;
-      svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+  // FP32 / BF16x3: the k leading eigenpairs by Chebyshev-filtered subspace
+  // iteration (dense products on MFMA, residuals below 1e-12 of the largest
+  // eigenvalue, far under the precision of the stored factors); FP64 keeps
+  // the direct solver, whose backward error is at rounding level.  A run that
+  // does not converge falls back to the direct solver.
+  bool solved = false;
+  if (h->prec != SVLCOV_FP64 && svl::chefsi_applies(N, K)) {
+    PhaseScope ps(h, PH_ITER);
+    if (!h->ctl_host && hipHostMalloc((void **)&h->ctl_host, 64 * sizeof(double), 0) != hipSuccess)
+      h->ctl_host = nullptr;
+    if (h->ctl_host) {
+      int iters = 0;
+      const int rc = svl::eig_topk_chefsi(st, N, Mmat, K, lam, Fv, eigw,
+                                          svl::eig_update_work_doubles(N, K), h->ctl_host,
+                                          1e-12, 8, (uint64_t)h->seq * 7919 + 17, h->info,
+                                          &iters);
+      ++h->iter_runs;
+      h->iter_steps += iters;
+      if (rc == 0) solved = true;
+      else if (rc == 1) ++h->iter_fallbacks;
+      else {
+        h->launch_failed = true;
+        svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+      }
     }
   }
-  {
-    PhaseScope ps(h, PH_BISECT);
-    svl::eig_bisect(st, N, K, lam, eigw, h->info);
-  }
-  {
-    PhaseScope ps(h, PH_STEIN);
-    svl::eig_stein(st, N, K, lam, Fv, eigw, h->info);
-  }
-  {
-    PhaseScope ps(h, PH_BACK);
-    svl::eig_back(st, N, K, Mmat, Fv, eigw, h->info);
+  if (!solved) {
+    {
+      PhaseScope ps(h, PH_TRIDIAG);
+      coop_enter(h);
+      const int trc = svl::eig_tridiag(st, N, Mmat, eigw, h->flags, &h->epoch, h->info);
+      coop_exit(h);
+      if (trc != 0) {
+        h->launch_failed = true;
+        svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+      }
+    }
+    {
+      PhaseScope ps(h, PH_BISECT);
+      svl::eig_bisect(st, N, K, lam, eigw, h->info);
+    }
+    {
+      PhaseScope ps(h, PH_STEIN);
+      svl::eig_stein(st, N, K, lam, Fv, eigw, h->info);
+    }
+    {
+      PhaseScope ps(h, PH_BACK);
+      svl::eig_back(st, N, K, Mmat, Fv, eigw, h->info);
+    }
   }
   {
     PhaseScope ps(h, PH_RECOVER);
@@ -490,7 +518,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
     *complete = cv.take<int32_t>(K);
     *Fv = cv.take<double>(K * N);
     *Gv = cv.take<double>(K * N);
-    *eigw = cv.take<double>(svl::eig_work_doubles(N, K));
+    *eigw = cv.take<double>(svl::eig_update_work_doubles(N, K));
     *Y = cv.take<double>(s * K);
     *T1 = cv.take<double>(K * K);
     *WnA = cv.take<double>(K * K);
@@ -1081,7 +1109,7 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
     *lam = cv.take<double>(K); *theta = cv.take<double>(K);
     *complete = cv.take<int32_t>(K);
     *Fv = cv.take<double>(K * N); *Gv = cv.take<double>(K * N);
-    *eigw = cv.take<double>(svl::eig_work_doubles(N, K));
+    *eigw = cv.take<double>(svl::eig_update_work_doubles(N, K));
     *YD = cv.take<double>(s * K); *YE = cv.take<double>(s * K);
     *T1 = cv.take<double>(K * K);
     *WnU = cv.take<double>(K * K); *WiU = cv.take<double>(K * K);
@@ -1551,6 +1579,9 @@ svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out) {
   out->last_kappa_V = inf.kappa_V;
   out->last_min_kept_pivot = inf.min_kept;
   out->last_max_dropped_pivot = inf.max_dropped;
+  out->iter_runs = h->iter_runs;
+  out->iter_steps = h->iter_steps;
+  out->iter_fallbacks = h->iter_fallbacks;
   return SVLCOV_OK;
 }
 
@@ -1621,6 +1652,7 @@ void svlcov_destroy(svlcov_state *h) {
   }
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  if (h->ctl_host) (void)hipHostFree(h->ctl_host);
   delete h;
 }
 

@@ -260,4 +260,25 @@ void eig_back(hipStream_t st, int64_t N, int k, const double *A, double *Fv, dou
               const SvDevInfo *info);
 int eig_max_n();
 
+// ---- Chebyshev-filtered subspace iteration (k_chefsi.hip)
+// Top-k eigenpairs of the positive semidefinite N x N matrix M (not
+// modified) with a basis of chefsi_block(k) columns, for the (N, k) that
+// chefsi_applies() accepts; ws holds chefsi_work_doubles(N, k) doubles,
+// ctl_host 4 doubles of pinned host memory.  Outputs as eig_topk.  The call
+// waits for the stream after every Rayleigh-Ritz step (the host picks the
+// filter degree and stops when max_j ||M x_j - theta_j x_j|| <= tol theta_0).
+// Returns 0 when converged, 1 when not within max_it filter steps (the
+// outputs are then not written), < 0 on a launch or argument error; *iters
+// receives the number of filter steps.
+int chefsi_block(int k);
+bool chefsi_applies(int64_t N, int k);
+size_t chefsi_work_doubles(int64_t N, int k);
+// Work of the update's eigenproblem: the direct solver's, or the iterative
+// one's where it applies (the direct solver is its fallback on the same
+// memory).
+size_t eig_update_work_doubles(int64_t N, int k);
+int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *lam, double *Fv,
+                    double *ws, size_t ws_len, double *ctl_host, double tol, int max_it,
+                    uint64_t seed, const SvDevInfo *info, int *iters);
+
 }  // namespace svl

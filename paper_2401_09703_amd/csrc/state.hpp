@@ -82,6 +82,11 @@ struct svlcov_state {
   // side q (C', its FP32 copy and the row norms) is already in the lent
   // workspace, written by a fused multi-request launch.
   bool proj_ready[2] = {false, false};
+  // pinned control words of the iterative eigensolver (allocated on first
+  // use) and its counters: filter steps taken, runs handed to the direct
+  // solver
+  double *ctl_host = nullptr;
+  int64_t iter_steps = 0, iter_fallbacks = 0, iter_runs = 0;
   size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
 };
 
