@@ -804,7 +804,9 @@ def main():
                              mode=mode, method=meth)
         log(f"[bench] {name}: {results[name]['rows_per_s']:.0f} rows/s, "
             f"{results[name]['ms_per_step']:.2f} ms/step, p50 {results[name]['p50_ms']:.2f} ms, "
-            f"p99 {results[name]['p99_ms']:.2f} ms, resets U/V {st['resets_U']}/{st['resets_V']}")
+            f"p99 {results[name]['p99_ms']:.2f} ms, resets U/V {st['resets_U']}/{st['resets_V']}, "
+            f"iterative eigensolver: {st['iter_runs']} runs, {st['iter_steps']} filter steps, "
+            f"{st['iter_fallbacks']} fallbacks")
         tot = sum(v[0] for v in phases.values())
         for name, (ms, cnt) in sorted(phases.items(), key=lambda x: -x[1][0]):
             if cnt:
@@ -952,6 +954,9 @@ def main():
         "p50_ms": hr["p50_ms"], "p99_ms": hr["p99_ms"],
         "paths": {m: dict(rows_per_s=r["rows_per_s"], ms_per_step=r["ms_per_step"],
                           p50_ms=r["p50_ms"], p99_ms=r["p99_ms"],
+                          eig_iterative=dict(runs=r["stats"]["iter_runs"],
+                                             filter_steps=r["stats"]["iter_steps"],
+                                             fallbacks=r["stats"]["iter_fallbacks"]),
                           **({"variant": dict(method=r["method"], l=la, t=ta)}
                              if r["method"] else {})) for m, r in results.items()},
         "gate": gate, "gate_ok": gate_ok, "variants_gate_ok": variants_ok,

@@ -290,7 +290,8 @@ namespace {
 template <typename T>
 void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
                    float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which,
-                   bool chol = true, double *dws = nullptr, size_t dws_len = 0) {
+                   bool chol = true, double *dws = nullptr, size_t dws_len = 0,
+                   double *Scopy = nullptr, int64_t lds_copy = 0) {
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
@@ -306,6 +307,8 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
     PhaseScope ps(h, PH_SGRAM);
     svl::sparse_gram(st, s, E.cols, E.nnz, E.rp, E.ci, E.v, E.vdt, rid, Gm, s, dws, dws_len,
                      h->info);
+    // S = E E^T is also the trailing block of M = K K^T (R^T R = S - C' C'^T)
+    if (Scopy) svl::copy_strided(st, s, s, Gm, s, 1, Scopy, lds_copy, h->info);
   }
   {
     // the approximate variants build their basis by a Lanczos or power
@@ -336,28 +339,36 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
 // re-orthonormalised, with an orthonormal completion where theta vanishes.
 svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mmat, double *lam,
                             double *theta, int32_t *complete, double *Fv, double *Gv,
-                            double *eigw, double *gram_kk) {
+                            double *eigw, double *gram_kk, const double *Cp_border = nullptr) {
   const int K = h->k;
   hipStream_t st = h->stream;
   {
     PhaseScope ps(h, PH_KKT);
-    svl::gemm_f64(st, false, true, N, N, N, 1.0, Kmat, N, Kmat, N, 0.0, Mmat, N, h->info);
+    if (Cp_border)   // append form: M from sigma, C' and the sparse Gram, no product
+      svl::build_M_border(st, K, N - K, h->sigma, Cp_border, Mmat, h->info);
+    else
+      svl::gemm_f64(st, false, true, N, N, N, 1.0, Kmat, N, Kmat, N, 0.0, Mmat, N, h->info);
   }
   // FP32 / BF16x3: the k leading eigenpairs by Chebyshev-filtered subspace
-  // iteration (dense products on MFMA, residuals below 1e-12 of the largest
-  // eigenvalue, far under the precision of the stored factors); FP64 keeps
-  // the direct solver, whose backward error is at rounding level.  A run that
-  // does not converge falls back to the direct solver.
+  // iteration (dense products on MFMA) to residuals below 1e-9 of the
+  // largest eigenvalue, two orders under the rounding of the FP32-stored
+  // factors that M is computed from; FP64 keeps the direct solver, whose
+  // backward error is at rounding level.  A run that does not converge falls
+  // back to the direct solver.
   bool solved = false;
   if (h->prec != SVLCOV_FP64 && svl::chefsi_applies(N, K)) {
     PhaseScope ps(h, PH_ITER);
-    if (!h->ctl_host && hipHostMalloc((void **)&h->ctl_host, 64 * sizeof(double), 0) != hipSuccess)
-      h->ctl_host = nullptr;
+    if (!h->ctl_host) {
+      if (hipHostMalloc((void **)&h->ctl_host, 64 * sizeof(double), 0) != hipSuccess)
+        h->ctl_host = nullptr;
+      else
+        for (int q = 0; q < 64; ++q) h->ctl_host[q] = 0.0;   // no bounds hint yet
+    }
     if (h->ctl_host) {
       int iters = 0;
       const int rc = svl::eig_topk_chefsi(st, N, Mmat, K, lam, Fv, eigw,
                                           svl::eig_update_work_doubles(N, K), h->ctl_host,
-                                          1e-12, 8, (uint64_t)h->seq * 7919 + 17, h->info,
+                                          1e-9, 8, (uint64_t)h->seq * 7919 + 17, h->info,
                                           &iters);
       ++h->iter_runs;
       h->iter_steps += iters;
@@ -558,13 +569,14 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   svl::op_begin(st, h->info, 0);
   // orthogonalise the augmented matrix of the sparse side
   orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, rid, 0, true, Kmat,
-                   (size_t)N * N);   // K is formed only after the Gram
+                   (size_t)N * N,    // K is formed only after the Gram
+                   Mmat + (size_t)K * N + K, N);
   // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
   {
     PhaseScope ps(h, PH_BUILDK);
     svl::build_K_rows(st, K, s, h->sigma, Cp64, Gm, s, Kmat, h->info);
   }
-  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p);
+  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p, Cp64);
   if (r != SVLCOV_OK) return r;
   // append side: W_A F[:k]; its inverse and condition
   {

@@ -26,23 +26,35 @@
 #include <initializer_list>
 
 #include "common.hpp"
+#include "k_rsvd.hpp"
 #include "kernels.hpp"
 
 using namespace svk;
 
 namespace {
 
-// X[i][j] = e_j (j < k, the leading coordinates: for M = K K^T of an update
-// they are the previous singular directions) or a pseudo-random entry.
+// Orthonormal start, no factorisation needed: X[:, j] = e_j for j < k (the
+// leading coordinates: for M = K K^T of an update they are the previous
+// singular directions), and for k <= j < p a vector of pseudo-random signs
+// on the coordinates c >= k with (c - k) mod (p - k) = j - k, scaled to unit
+// length; the supports are disjoint, so the columns are orthonormal.
 __global__ void k_cf_init(int64_t N, int k, int p, double *__restrict__ X, uint64_t seed,
                           const SvDevInfo *__restrict__ info) {
   if (info->status) return;
+  const int64_t q = p - k, span = N - k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < N * p;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / p;
     const int j = (int)(e % p);
-    X[e] = j < k ? (i == j ? 1.0 : 0.0)
-                 : hash_unit(seed * 0x9E3779B97F4A7C15ull + (uint64_t)e * 0xD1B54A32D192ED03ull);
+    double v = 0.0;
+    if (j < k) {
+      v = i == j ? 1.0 : 0.0;
+    } else if (i >= k && (i - k) % q == j - k) {
+      const int64_t cnt = (span - (j - k) + q - 1) / q;   // coordinates of column j
+      const double h = hash_unit(seed * 0x9E3779B97F4A7C15ull + (uint64_t)e * 0xD1B54A32D192ED03ull);
+      v = (h < 0.0 ? -1.0 : 1.0) / sqrt((double)cnt);
+    }
+    X[e] = v;
   }
 }
 
@@ -216,10 +228,15 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
 
   // basis X (in B[0]), Y = M X (B[1]); B[2..4] are scratch
   double *X = B[0], *Y = B[1];
+  // columns scaled to unit length, one pass of Cholesky QR, and a second one
+  // only when the first's input was not orthonormal to within 1e-2 per
+  // entry of its Gram (condition number at most 1 + 1.27; one pass then
+  // leaves an orthogonality error of a few u) or a column was completed
+  int32_t *need = (int32_t *)(ctl + 16);
   auto orth = [&](double *src, double *scratch) -> double * {
     hipLaunchKernelGGL(k_cf_colnorm, dim3(p), dim3(256), 0, st, N, p, src, info);
-    return orth_cols(st, N, p, src, scratch, 2, G, Out, complete, gws, gws_len, ++seed, rtol,
-                     info);
+    return orth_cols_cond(st, N, p, src, scratch, G, Out, complete, need, gws, gws_len, ++seed,
+                          rtol, info, 1e-2);
   };
   auto other = [&](std::initializer_list<const double *> used) -> double * {
     for (int q = 0; q < 5; ++q) {
@@ -253,11 +270,11 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
 
   hipLaunchKernelGGL(k_cf_init, dim3(grid_of((int64_t)panel)), dim3(256), 0, st, N, k, p, X,
                      seed, info);
-  X = orth(X, other({X, Y}));
   if (!rayleigh_ritz()) return -3;
+  bool have_y = true;
+  double res = ctl_host[0], th0 = ctl_host[1], thk = ctl_host[2], thp = ctl_host[3];
   int it = 0;
   for (;; ++it) {
-    const double res = ctl_host[0], th0 = ctl_host[1], thk = ctl_host[2], thp = ctl_host[3];
     const double scale = std::max(std::fabs(th0), 1e-300);
     if (!(res == res)) break;   // a NaN: let the direct solver take over
     if (res <= tol * scale || th0 == thp) {
@@ -291,6 +308,10 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
     // scaled Chebyshev recurrence, scale point th0 (its component stays ~1)
     const double sigma1 = th0 > c ? e / (th0 - c) : 1.0;
     double sigma = sigma1;
+    if (!have_y) {
+      Y = other({X});
+      gemm_f64_sk(st, false, false, N, p, N, 1.0, M, N, X, p, 0.0, Y, p, gws, gws_len, info);
+    }
     double *Yp = X;
     double *Yc = other({X, Y});
     hipLaunchKernelGGL(k_cf_combine, dim3(grid_of((int64_t)panel)), dim3(256), 0, st,
@@ -309,6 +330,8 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
     X = orth(Yc, other({Yc}));
     Y = other({X});
     if (!rayleigh_ritz()) return -3;
+    have_y = true;
+    res = ctl_host[0]; th0 = ctl_host[1]; thk = ctl_host[2]; thp = ctl_host[3];
   }
   if (iters) *iters = it;
   return 1;

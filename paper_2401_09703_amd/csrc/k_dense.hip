@@ -267,6 +267,25 @@ __global__ void k_build_K_rows(int K, int64_t s, const double *__restrict__ sig,
   Ko[e] = v;
 }
 
+// The leading k rows and columns of M = K K^T for K = [[Sigma, 0], [C', R^T]]:
+// M = [[Sigma^2, Sigma C'^T], [C' Sigma, S]], whose block S = E E^T (the
+// sparse Gram, since R^T R = S - C' C'^T) is copied in beforehand.  One thread
+// per entry of the border (2 k N - k^2 entries).
+__global__ void k_build_M_border(int K, int64_t s, const double *__restrict__ sig,
+                                 const double *__restrict__ Cp, double *__restrict__ M,
+                                 const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int64_t N = K + s;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)K * N) return;
+  const int64_t r = e / N, c = e % N;   // border row r < K, column c
+  double v;
+  if (c < K) v = (c == r) ? sig[r] * sig[r] : 0.0;
+  else v = sig[r] * Cp[(c - K) * K + r];
+  M[r * N + c] = v;
+  if (c >= K) M[c * N + r] = v;
+}
+
 __global__ void k_build_X(int K, int64_t s, const double *__restrict__ Cp,
                           const double *__restrict__ L, int64_t ldl, double *__restrict__ X,
                           const SvDevInfo *__restrict__ info) {
@@ -905,6 +924,13 @@ void build_K_rows(hipStream_t st, int K, int64_t s, const double *sig, const dou
   const int64_t N = K + s, n = N * N;
   hipLaunchKernelGGL(k_build_K_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, s,
                      sig, Cp, L, ldl, Ko, info);
+}
+
+void build_M_border(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
+                    double *M, const SvDevInfo *info) {
+  const int64_t n = (int64_t)K * (K + s);
+  hipLaunchKernelGGL(k_build_M_border, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, s,
+                     sig, Cp, M, info);
 }
 
 void build_X(hipStream_t st, int K, int64_t s, const double *Cp, const double *L, int64_t ldl,

@@ -933,7 +933,7 @@ double *orth_cols(hipStream_t st, int64_t R, int L, double *X, double *Y, int pa
 // orthonormal to rounding unless some column had to be completed.
 double *orth_cols_cond(hipStream_t st, int64_t R, int L, double *X, double *Y, double *G,
                        double *Out, int32_t *complete, int32_t *need, double *ws, size_t ws_len,
-                       uint64_t seed, double rtol, const SvDevInfo *info) {
+                       uint64_t seed, double rtol, const SvDevInfo *info, double gate_tau) {
   const bool mf = (L == 16 || L == 32 || L == 64 || L == 128) && ws_len >= ts_gram_ws(R, L);
   double *src = X, *dst = Y;
   for (int pass = 0; pass < 2; ++pass) {
@@ -942,7 +942,7 @@ double *orth_cols_cond(hipStream_t st, int64_t R, int L, double *X, double *Y, d
     else gemm_f64_sk(st, true, false, L, L, R, 1.0, src, L, src, L, 0.0, G, L, ws, ws_len, info);
     chol_drop_if(st, L, G, Out, complete, rtol, info, gate);
     if (pass == 0)
-      hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, L, G, complete, ORTH_GATE_TAU,
+      hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, L, G, complete, gate_tau,
                          need, info);
     if (mf) ts_mul_lt(st, R, L, src, Out, dst, info);
     else gemm_f64(st, false, true, R, L, L, 1.0, src, L, Out, L, 0.0, dst, L, info);

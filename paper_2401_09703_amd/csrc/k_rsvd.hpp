@@ -23,8 +23,12 @@ void chol_drop_if(hipStream_t st, int L, const double *G, double *Out, int32_t *
 // of Cholesky QR with dropping and completion, and a second pass only when
 // the first completed a column or its input was not orthonormal to within
 // ORTH_GATE_TAU; need is one device word of scratch.  The result is in X.
+// gate_tau replaces ORTH_GATE_TAU where the caller can accept more: one pass
+// of Cholesky QR leaves an orthogonality error of about u cond^2, and the
+// gate bounds cond by 1 + (L - 1) gate_tau.
 double *orth_cols_cond(hipStream_t st, int64_t R, int L, double *X, double *Y, double *G,
                        double *Out, int32_t *complete, int32_t *need, double *ws, size_t ws_len,
-                       uint64_t seed, double rtol, const SvDevInfo *info);
+                       uint64_t seed, double rtol, const SvDevInfo *info,
+                       double gate_tau = ORTH_GATE_TAU);
 
 }  // namespace svl

@@ -315,6 +315,157 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
   }
 }
 
+// The same reduction for N <= 128 with the matrix in registers: one block of
+// 1024 threads, thread t holds row r = t / 8 at the columns c = t % 8 + 8 j
+// (j < 16), so the eight threads of a row are one 8-lane group of a wave
+// (row sums by two DPP steps).  Per column: the threads of row i form the
+// reflector from their registers and publish v, every thread forms its row's
+// share of p = tau M v, a block reduction gives p.v, and each thread applies
+// the rank-2 update to its 16 entries with w rebuilt from p and v in LDS.
+// Two block barriers per column; v, p and the partial sums alternate between
+// two LDS buffers so that the next column's writes never meet this column's
+// reads.  A wave whose rows are all <= i only takes part in the reduction.
+// The reflectors stay in the registers of their rows (which no later update
+// changes) and d, e, tau in LDS until the end: a global store inside the
+// loop would hold up every block barrier until it completed.  Conventions as
+// k_tridiag.
+constexpr int TR_N = 128, TR_NT = 1024, TR_CPT = 16;
+
+__device__ __forceinline__ double sum8(double v) {
+  v = quad_sum(v);
+  return v + dpp_d<DPP_ROW_HALF_MIRROR>(v);
+}
+
+__global__ void __launch_bounds__(TR_NT)
+k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
+              double *__restrict__ e, double *__restrict__ tau, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int r = tid >> 3, s = tid & 7;
+  if (N < 3) {
+    if (tid == 0) {
+      d[0] = A[0];
+      if (N == 2) { e[0] = A[1]; d[1] = A[lda + 1]; }
+    }
+    return;
+  }
+  __shared__ double vb[2][TR_N];
+  __shared__ double pb[2][TR_N];
+  __shared__ double part[2][TR_NT / 64];
+  __shared__ double tb[2];
+  __shared__ double dd[TR_N], ee[TR_N], tt[TR_N];
+  double a[TR_CPT];
+#pragma unroll
+  for (int j = 0; j < TR_CPT; ++j) {
+    const int c = s + 8 * j;
+    a[j] = (r < N && c < N) ? A[(int64_t)r * lda + c] : 0.0;
+  }
+  for (int i = 0; i <= N - 3; ++i) {
+    const int b = i & 1;
+    // row i: alpha = x_{i+1}, ||x_{i+2..}||^2 and d_i (every lane computes,
+    // only the group of row i has nonzero terms)
+    {
+      double ss = 0.0, al = 0.0, di = 0.0;
+      if (r == i) {
+#pragma unroll
+        for (int j = 0; j < TR_CPT; ++j) {
+          const int c = s + 8 * j;
+          if (c >= i + 2 && c < N) ss += a[j] * a[j];
+          if (c == i + 1) al = a[j];
+          if (c == i) di = a[j];
+        }
+      }
+      ss = sum8(ss);
+      al = sum8(al);
+      di = sum8(di);
+      if (r == i) {
+        double beta, t, scl;
+        if (ss == 0.0) {
+          t = 0.0; beta = al; scl = 0.0;
+        } else {
+          const double nrm = sqrt(al * al + ss);
+          beta = al >= 0.0 ? -nrm : nrm;
+          t = (beta - al) / beta;
+          scl = 1.0 / (al - beta);
+        }
+        // row i is final: its registers keep the reflector from here on
+#pragma unroll
+        for (int j = 0; j < TR_CPT; ++j) {
+          const int c = s + 8 * j;
+          double v = 0.0;
+          if (c == i + 1) v = 1.0;
+          else if (c >= i + 2 && c < N) v = a[j] * scl;
+          vb[b][c] = v;
+          if (c >= i + 1) a[j] = v;
+        }
+        if (s == 0) {
+          tb[b] = t;
+          dd[i] = di;
+          ee[i] = beta;
+          tt[i] = t;
+        }
+      }
+    }
+    __syncthreads();
+    const double t = tb[b];
+    const bool wact = 8 * w + 7 > i && 8 * w < N;
+    double pr = 0.0, vr = 0.0, pv = 0.0;
+    if (wact) {
+      // the sixteen loads issued together (v is zero at columns <= i and p
+      // at rows <= i, so no per-column condition is needed)
+      double vv[TR_CPT];
+#pragma unroll
+      for (int j = 0; j < TR_CPT; ++j) vv[j] = vb[b][s + 8 * j];
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < TR_CPT; ++j) acc += a[j] * vv[j];
+      acc = sum8(acc);
+      const bool act = r > i && r < N;
+      pr = act ? t * acc : 0.0;
+      vr = act ? vb[b][r] : 0.0;
+      if (s == 0) pb[b][r] = pr;
+      pv = (s == 0) ? pr * vr : 0.0;
+      pv = wave_sum(pv);
+    } else if (s == 0) {
+      pb[b][r] = 0.0;
+    }
+    if (lane == 0) part[b][w] = pv;
+    __syncthreads();
+    if (wact) {
+      double pvs = 0.0;
+#pragma unroll
+      for (int q = 0; q < TR_NT / 64; ++q) pvs += part[b][q];
+      const double K = 0.5 * t * pvs;
+      const double wr = pr - K * vr;
+      double pp[TR_CPT];
+#pragma unroll
+      for (int j = 0; j < TR_CPT; ++j) pp[j] = pb[b][s + 8 * j];
+      // M_rc -= v_r w_c + w_r v_c, w_c = p_c - K v_c
+#pragma unroll
+      for (int j = 0; j < TR_CPT; ++j) {
+        const double vc = vb[b][s + 8 * j];
+        a[j] -= vr * (pp[j] - K * vc) + wr * vc;
+      }
+    }
+  }
+  // the last 2 x 2 block, the reflectors (rows 0 .. N-3 of A, columns > r)
+  // and d, e, tau
+#pragma unroll
+  for (int j = 0; j < TR_CPT; ++j) {
+    const int c = s + 8 * j;
+    if (r == N - 2 && c == N - 2) d[N - 2] = a[j];
+    if (r == N - 2 && c == N - 1) e[N - 2] = a[j];
+    if (r == N - 1 && c == N - 1) d[N - 1] = a[j];
+    if (r <= N - 3 && c > r && c < N) A[(int64_t)r * lda + c] = a[j];
+  }
+  __syncthreads();
+  for (int q = tid; q <= N - 3; q += TR_NT) {
+    d[q] = dd[q];
+    e[q] = ee[q];
+    tau[q] = tt[q];
+  }
+}
+
 }  // namespace
 
 namespace svl {
@@ -327,6 +478,10 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
   const int N = (int)N64;
   if (N64 > eig_max_n() || N < 1) return -1;
   double *d = work, *e = d + N, *tau = e + N, *pbuf = tau + N, *rowbuf = pbuf + 2 * N;
+  if (N <= TR_N && !getenv("SVLCOV_TRI_LDS")) {   // one block, the matrix in registers
+    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(TR_NT), 0, st, N, A, N64, d, e, tau, info);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
   if (N <= TRI_SMALL_N) {   // one block, the matrix in LDS
     static bool small_once = false;
     if (!small_once) {

@@ -112,6 +112,11 @@ void set_status(hipStream_t st, SvDevInfo *info, int code);
 // reserve count + 1 barrier epochs; zero the flags first when close to wrap
 unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned count);
 // K = [[diag(sig), 0], [Cp, L]]  (N = K+s square, the add-rows form).
+// M = K K^T of the append form without a product: the border (rows and
+// columns < K) from sigma and C' (s x K); the block M[K:, K:] = E E^T must be
+// in place already (copied from the sparse Gram).
+void build_M_border(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
+                    double *M, const SvDevInfo *info);
 void build_K_rows(hipStream_t st, int K, int64_t s, const double *sig, const double *Cp,
                   const double *L, int64_t ldl, double *Kout, const SvDevInfo *info);
 // X = [Cp^T ; L^T]  ((K+s) x s) for the weight form.

@@ -42,8 +42,9 @@ def _check(M, k, tol_val=1e-12, tol_ang=1e-9, delta=1e-6):
     return err
 
 
-@pytest.mark.parametrize("N,k", [(1, 1), (2, 1), (2, 2), (3, 2), (16, 16), (63, 16), (65, 32),
-                                 (130, 64), (257, 64), (1064, 64)])
+@pytest.mark.parametrize("N,k", [(1, 1), (2, 1), (2, 2), (3, 2), (4, 4), (16, 16), (63, 16),
+                                 (65, 32), (100, 100), (127, 64), (128, 128), (130, 64),
+                                 (257, 64), (1064, 64)])
 def test_random_psd(N, k):
     rng = np.random.default_rng(N * 31 + k)
     X = rng.standard_normal((N, N + 3))
