@@ -270,6 +270,17 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
 
   hipLaunchKernelGGL(k_cf_init, dim3(grid_of((int64_t)panel)), dim3(256), 0, st, N, k, p, X,
                      seed, info);
+  // two plain power steps before the first Rayleigh-Ritz step: they take
+  // the start's residual from ~1e-1 to ~1e-5 of the largest eigenvalue, so
+  // that one Chebyshev step (whose degree the spread of amplification over
+  // the wanted eigenvalues limits) usually suffices after it
+  for (int q = 0; q < 2; ++q) {
+    double *Z = other({X});
+    gemm_f64_sk(st, false, false, N, p, N, 1.0, M, N, X, p, 0.0, Z, p, gws, gws_len, info);
+    X = Z;
+  }
+  X = orth(X, other({X}));
+  Y = other({X});
   if (!rayleigh_ritz()) return -3;
   bool have_y = true;
   double res = ctl_host[0], th0 = ctl_host[1], thk = ctl_host[2], thp = ctl_host[3];
