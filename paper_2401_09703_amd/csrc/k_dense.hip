@@ -658,6 +658,114 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
   }
 }
 
+struct InvJob {
+  const double *W;
+  double *Winv;
+  int32_t *flag;
+  int side;
+};
+
+// The same inverse and condition estimate for K <= 64 by one wave: lane r
+// holds row r of W in registers and the Gauss-Jordan elimination runs in
+// place with implicit partial pivoting (the pivot of column c is the largest
+// |a[r][c]| over the rows not pivoted yet, lowest row on ties, and no row
+// moves): the pivot row goes through LDS (alternating buffers, one wave
+// barrier per column), every other row subtracts its multiple of it.  With
+// p_c the pivot row of column c, the final array S holds W^{-1}[i][m] =
+// S[p_i][q_m] with q the inverse of p.  The loop over columns is unrolled,
+// so every register index is static.  1-norms through an LDS copy, one
+// column per lane.  Flags, status and kappa as inverse_cond_block.
+template <int K>
+__device__ __forceinline__ void
+inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
+                  int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
+                  int side) {
+  if (info->status) return;
+  __shared__ double S[K][K + 1];
+  __shared__ double prow[2][K];
+  __shared__ int pv[K], qv[K];
+  const int lane = threadIdx.x;
+  const bool mine = lane < K;
+  double a[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) a[j] = mine ? W[lane * K + j] : 0.0;
+  // ||W||_1 = max column sum
+  if (mine)
+#pragma unroll
+    for (int j = 0; j < K; ++j) S[lane][j] = a[j];
+  wave_sync();
+  double csum = 0.0;
+  if (mine)
+    for (int r = 0; r < K; ++r) csum += fabs(S[r][lane]);
+  const double n1 = wave_max(csum);
+  const bool finite_in = isfinite(n1);
+  bool sing = !finite_in;
+  bool used = !mine;
+#pragma clang loop unroll(full)
+  for (int c = 0; c < K; ++c) {
+    if (!sing) {
+      const double cand = used ? -1.0 : fabs(a[c]);
+      const double best = wave_max(cand);
+      const unsigned long long hit = __ballot(cand == best && !used);
+      const int p = hit ? __builtin_ctzll(hit) : 0;
+      if (!(best > 1e-300) || !(best > 1e-15 * n1)) {
+        sing = true;
+      } else {
+        double *pr = prow[c & 1];
+        if (lane == p) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) pr[j] = a[j];
+          pv[c] = p;
+        }
+        wave_sync();
+        const double pinv = 1.0 / pr[c];
+        if (lane == p) {
+          used = true;
+#pragma unroll
+          for (int j = 0; j < K; ++j) a[j] = (j == c ? 1.0 : a[j]) * pinv;
+        } else {
+          const double f = a[c];
+#pragma unroll
+          for (int j = 0; j < K; ++j) a[j] = j == c ? -f * pinv : fma(-f, pr[j] * pinv, a[j]);
+        }
+      }
+    }
+  }
+  wave_sync();
+  double kappa = INFINITY;
+  if (!sing) {
+    if (mine) qv[pv[lane]] = lane;
+    wave_sync();
+    // W^{-1}[i][m] = a_{p_i}[q_m]: lane r (= p_i for i = q_r) holds row i
+    if (mine) {
+      const int i = qv[lane];
+#pragma unroll
+      for (int j = 0; j < K; ++j) S[i][pv[j]] = a[j];
+    }
+    wave_sync();
+    double ci = 0.0;
+    if (mine)
+      for (int r = 0; r < K; ++r) ci += fabs(S[r][lane]);
+    kappa = n1 * wave_max(ci);
+    for (int e = lane; e < K * K; e += 64) Winv[e] = S[e / K][e % K];
+  }
+  if (lane == 0) {
+    const bool reset = !(kappa <= cond_reset);
+    *flag = reset ? 1 : 0;
+    if (side == 0) info->kappa_U = kappa; else info->kappa_V = kappa;
+    if (!finite_in) {
+      if (atomicCAS(&info->status, 0, 4) == 0) info->failed_seq = -1;
+    }
+  }
+}
+
+template <int K>
+__global__ void __launch_bounds__(64)
+k_inverse_cond2_wave(InvJob a, InvJob b, double cond_reset, SvDevInfo *__restrict__ info) {
+  const InvJob j = blockIdx.x ? b : a;
+  inverse_cond_wave<K>(j.W, j.Winv, j.flag, cond_reset, info, j.side);
+}
+
 template <int K>
 __global__ void __launch_bounds__(256)
 k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
@@ -668,12 +776,7 @@ k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
 
 // The two sides' inverses of one update in one launch (block 0: side a,
 // block 1: side b); they are independent, so they run side by side.
-struct InvJob {
-  const double *W;
-  double *Winv;
-  int32_t *flag;
-  int side;
-};
+
 template <int K>
 __global__ void __launch_bounds__(256)
 k_inverse_cond2(InvJob a, InvJob b, double cond_reset, SvDevInfo *__restrict__ info) {
@@ -1005,13 +1108,16 @@ void inverse_cond_pair(hipStream_t st, int K, const double *Wa, double *Wia, int
   const InvJob a{Wa, Wia, fa, sa}, b{Wb, Wib, fb, sb};
 #define SV_INV2(KK) hipLaunchKernelGGL((k_inverse_cond2<KK>), dim3(2), dim3(256), 0, st, a, b, \
                                        cond_reset, info)
+#define SV_INV2W(KK) hipLaunchKernelGGL((k_inverse_cond2_wave<KK>), dim3(2), dim3(64), 0, st, a, \
+                                        b, cond_reset, info)
   switch (K) {
-    case 16: SV_INV2(16); break;
-    case 32: SV_INV2(32); break;
-    case 64: SV_INV2(64); break;
+    case 16: SV_INV2W(16); break;
+    case 32: SV_INV2W(32); break;
+    case 64: SV_INV2W(64); break;
     case 128: SV_INV2(128); break;
   }
 #undef SV_INV2
+#undef SV_INV2W
 }
 
 void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,
