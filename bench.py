@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--n-init", type=int, default=90000)
     ap.add_argument("--step-nodes", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=600,
+                    help="rows of the first update that the paper's method (O2) and the "
+                         "one-thread O1 are timed on (0: skip)")
     ap.add_argument("--modes", default="", help="precision modes (default per workload)")
     ap.add_argument("--approx", default="gkl,rpi",
                     help="-GKL / -RPI variants timed beside the exact path on the append "
@@ -97,6 +100,8 @@ def parse():
                     help="print every counter of one rocprofv3 --pmc run per kernel (mean per "
                          "dispatch) and exit")
     ap.add_argument("--phase", default="tridiag", help="phase whose kernel --summarize-pmc covers")
+    ap.add_argument("--pmc-size", default="",
+                    help="problem size the counters were taken at (as phase_size prints it)")
     ap.add_argument("--calib-mib", type=int, default=0, help="size of the calibration copy")
     return ap.parse_args()
 
@@ -163,7 +168,7 @@ def summarize_counters(d, match=""):
         print(f"{name[:72]} | dispatches {n} | " + " ".join(parts))
 
 
-def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
+def summarize_pmc(fetch_dir, write_dir, phase, calib_mib, size=""):
     prefix, files = PHASE_KERNEL[phase]
     fe, wr = _pmc(fetch_dir, "FETCH_SIZE"), _pmc(write_dir, "WRITE_SIZE")
 
@@ -195,6 +200,8 @@ def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
     print(f"phase: {phase}")
     print(f"kernel: {prefix}")
     print(f"sources_sha256: {sources_sha(files)}")
+    if size:
+        print(f"size: {size}")
     print(f"dispatches_fetch: {len(f_k)}")
     print(f"dispatches_write: {len(w_k)}")
     for n in sorted(f_n):
@@ -211,10 +218,10 @@ def summarize_pmc(fetch_dir, write_dir, phase, calib_mib):
     print(f"traffic_bytes_per_launch: {fetch + write:.0f}")
 
 
-def stored_traffic(phase):
+def stored_traffic(phase, size):
     """HBM bytes per launch of the phase's kernel from the committed counter
-    summary, or None when there is none or the kernel's source has changed
-    since the counters were taken."""
+    summary taken at the same problem size, or None when there is none or the
+    kernel's source has changed since the counters were taken."""
     if phase not in PHASE_KERNEL:
         return None
     prefix, files = PHASE_KERNEL[phase]
@@ -224,23 +231,102 @@ def stored_traffic(phase):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-        if kv.get("sources_sha256") == sources_sha(files) and "traffic_bytes_per_launch" in kv:
+        if (kv.get("sources_sha256") == sources_sha(files) and kv.get("size") == size
+                and "traffic_bytes_per_launch" in kv):
             return float(kv["traffic_bytes_per_launch"])
     return None
 
 
-def phase_work(name, N, s, k, nnz, d_cols):
-    """Algorithmic work of one launch of a phase: (bound, amount, unit)."""
+def phase_size(name, N, s, k):
+    """The sizes one launch of a phase's kernel depends on (keys the stored
+    counter summaries)."""
+    if name in ("tridiag", "kkt_gemm"):
+        return f"N={N}"
+    if name == "cholesky":
+        return f"s={s}"
+    return f"s={s},k={k}"
+
+
+# phases timed around a single kernel launch (the roofline's candidates);
+# the others chain several kernels and are reported as phase rates only
+SINGLE_KERNEL_PHASES = ("tridiag", "cholesky", "spmm_w", "kkt_gemm")
+
+
+def phase_work(name, N, s, k, nnz, d_cols, form="append", iter_flops=None):
+    """Algorithmic work of one launch of a phase: (bound, amount, unit).
+
+    iter_flops: the iterative eigensolver's flops per run (from the state's
+    counters), for the subspace_iter phase."""
     if name == "tridiag":
         return "alu", 4.0 / 3.0 * N ** 3, "flop"
     if name == "kkt_gemm":
-        return "alu", 2.0 * N ** 3, "flop"
+        # the weight form multiplies K K^T; the append form assembles M from
+        # sigma, C' and the sparse Gram (no product, a few MB)
+        return ("alu", 2.0 * N ** 3, "flop") if form == "weights" else (None, None, None)
+    if name == "cholesky":
+        # Cholesky factorisation of the s x s residual Gram
+        return "alu", s ** 3 / 3.0, "flop"
+    if name == "trsm":
+        # triangular solve with k right-hand sides, plus the inverses of the
+        # 32 x 32 diagonal blocks
+        return "alu", float(s) * s * k + s * 32 * 32 / 3.0, "flop"
+    if name == "resid_gram":
+        return "mfma", 2.0 * s * s * k, "flop"
+    if name == "recover_G":
+        return "mfma", 2.0 * k * N * N, "flop"
+    if name == "subspace_iter" and iter_flops:
+        return "mfma", iter_flops, "flop"
     if name == "spmm_w":
         # compulsory bytes: CSR (4 B index + 8 B value per nonzero, 8 B row
         # pointers), the distinct rows of the FP32 base it touches, the s x k
         # FP64 output
         return "hbm", nnz * 12 + 8 * (s + 1) + d_cols * k * 4 + s * k * 8, "byte"
     return None, None, None
+
+
+def head_rows(up, r):
+    """The update restricted to the first r rows of its sparse matrices."""
+    from synth.sparse import CSR
+
+    def cut(E):
+        r_ = min(r, E.rows)
+        e = int(E.row_ptr[r_])
+        return CSR(r_, E.cols, E.row_ptr[:r_ + 1].copy(), E.col_idx[:e].copy(), E.val[:e].copy())
+    return (up[0],) + tuple(cut(E) for E in up[1:])
+
+
+def bounded_oracle_samples(cfg, up, rows, cores):
+    """The paper's own method on the CPU (O2: Algorithms 2, 3, 4 and 11 in the
+    extended decomposition, FP64) and the Zha-Simon oracle on one thread (O1),
+    each timed on the first `rows` rows of the step's first update from the
+    workload's starting factors.  Both costs grow with the square of the rows
+    (Algorithm 2's s^2 column operations; the dense QR of the m x s
+    residual), so a full update takes several times longer per row than the
+    sample shows."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import svlcov, zha_simon
+    sub = head_rows(up, rows)
+    r = sub[1].rows
+    out = []
+    t = time.perf_counter()
+    ex = svlcov.ExtendedSVD(cfg["U"], cfg["s"], cfg["V"])
+    ex.apply(sub)
+    dt = time.perf_counter() - t
+    out.append(dict(value=r / dt, unit="update rows/s", cores=cores, kind="oracle",
+                    method="O2, the paper's method (Algorithm 2 column by column, extended "
+                           "decomposition)",
+                    sample=f"the first {r} rows of the first update ({up[0]}): {dt:.1f} s wall"))
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        zha_simon.apply(cfg["U"], cfg["s"], cfg["V"], sub)
+        dt = time.perf_counter() - t
+    out.append(dict(value=r / dt, unit="update rows/s", cores=1, kind="oracle",
+                    method="O1 (Zha-Simon, dense QR + LAPACK SVD) on one thread",
+                    sample=f"the first {r} rows of the first update ({up[0]}): {dt:.1f} s wall"))
+    log("[bench] bounded oracle samples: " + "; ".join(
+        f"{o['method'][:2]} {o['value']:.1f} rows/s ({o['sample']})" for o in out))
+    return out
 
 
 WORKLOADS = ("graph", "bernoulli", "ratings", "weights", "weights_r2")   # plus "stream" and "score"
@@ -505,7 +591,8 @@ def run_init(args):
         "phases_ms": ph,
         "roofline": dict(kernel="k_csr_dense", bound="hbm", achieved=ach, peak=HBM_PEAK_GBS,
                          unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                         traffic=stored_traffic("rsvd_spmm"), avg_ms=spmm_ms, bytes=byts,
+                         traffic=stored_traffic("rsvd_spmm", f"nodes={A.rows},l={l}"),
+                         avg_ms=spmm_ms, bytes=byts,
                          gather_GBs=gather),
         "cpu_baseline": dict(value=1.0 / cpu_s, unit="SVDs/s", cores=int(cores), kind="oracle",
                              sample="the whole workload once"),
@@ -671,7 +758,7 @@ def run_stream(args):
     if args.fused > 0:
         fused_roof = dict(kernel="k_spmm_batch", bound="hbm", achieved=fused["achieved_GBs"],
                           peak=HBM_PEAK_GBS, unit="GB/s", frac=fused["frac"],
-                          traffic=stored_traffic("fused"),
+                          traffic=stored_traffic("fused", f"requests={fused['requests']}"),
                           requests=fused["requests"], bytes=fused["bytes"],
                           avg_ms=fused["ms"])
     out = {
@@ -704,7 +791,8 @@ def main():
         summarize_counters(args.summarize_counters)
         return
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.phase, args.calib_mib)
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.phase, args.calib_mib,
+                      args.pmc_size)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -876,6 +964,9 @@ def main():
                        kind="oracle",
                        sample=f"one step ({P} update(s), {wl['rows_per_step']} update rows) of "
                               f"the same workload from the same starting factors: {dt:.1f} s wall")
+            if args.cpu_sample_rows > 0:
+                cpu["others"] = bounded_oracle_samples(cfg, ups[0], args.cpu_sample_rows,
+                                                       int(cores))
         for meth in methods:   # distance of the variant from the exact update
             Ua, sa, Va, ia, _ = approx_ref[meth]
             r = metrics.compare((Ua, sa, Va), (Ur, sr, Vr), info["theta_hat"], 1e-3)
@@ -896,39 +987,53 @@ def main():
 
     head = "bf16x3" if "bf16x3" in results else list(results)[0]
     hr = results[head]
-    # roofline of the dominant single-kernel phase
+    # roofline of the dominant single-kernel phase; every phase with a
+    # defined amount of work also gets its achieved rate
     k, s = wl["extra"]["k"], wl["s"]
     N = k + s
     timed = ups[P * W:P * (W + K)]
+    form = "weights" if any(u[0] == "weights" for u in timed) else "append"
     sp = [u[1] for u in timed] + [u[2] for u in timed if u[0] == "weights"]
     nnz_step = float(np.mean([E.nnz for E in sp]))
     d_cols = float(np.mean([len(np.unique(E.col_idx)) for E in sp]))
-    best = None
+    hst = hr["stats"]
+    iter_fl = hst["iter_flops"] / hst["iter_runs"] if hst["iter_runs"] else None
+    best, rates = None, {}
     for name, (ms, cnt) in hr["phases"].items():
-        bound, work, unit = phase_work(name, N, s, k, nnz_step, d_cols)
+        bound, work, unit = phase_work(name, N, s, k, nnz_step, d_cols, form, iter_fl)
         if bound is None or cnt == 0:
             continue
-        if best is None or ms > best[1]:
+        avg_s = ms / cnt / 1e3
+        rates[name] = dict(avg_ms=ms / cnt, bound=bound,
+                           **({"TFLOP/s": work / avg_s / 1e12} if unit == "flop"
+                              else {"GB/s": work / avg_s / 1e9}))
+        if name in SINGLE_KERNEL_PHASES and (best is None or ms > best[1]):
             best = (name, ms, cnt, bound, work, unit)
     roof = None
     if best:
         name, ms, cnt, bound, work, unit = best
         avg_s = ms / cnt / 1e3
+        size = phase_size(name, N, s, k)
         if unit == "flop":
             ach = work / avg_s / 1e12
-            roof = dict(kernel=name, bound=bound, achieved=ach, peak=FP64_PEAK_TFS, unit="TFLOP/s",
-                        frac=ach / FP64_PEAK_TFS, traffic=stored_traffic(name), avg_ms=ms / cnt)
+            roof = dict(kernel=PHASE_KERNEL[name][0], phase=name, bound=bound, achieved=ach,
+                        peak=FP64_PEAK_TFS, unit="TFLOP/s", frac=ach / FP64_PEAK_TFS,
+                        traffic=stored_traffic(name, size), avg_ms=ms / cnt, work=work,
+                        size=size)
         else:
             ach = work / avg_s / 1e9
-            roof = dict(kernel=name, bound=bound, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=ach / HBM_PEAK_GBS, traffic=stored_traffic(name), avg_ms=ms / cnt)
+            roof = dict(kernel=PHASE_KERNEL[name][0], phase=name, bound=bound, achieved=ach,
+                        peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                        traffic=stored_traffic(name, size), avg_ms=ms / cnt, work=work,
+                        size=size)
     sp_ms, sp_n = hr["phases"].get("spmm_w", (0.0, 0))
     spmm_roof = None
     if sp_n:
         b = phase_work("spmm_w", N, s, k, nnz_step, d_cols)[1]
         ach = b / (sp_ms / sp_n / 1e3) / 1e9
         spmm_roof = dict(achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                         avg_us=1e3 * sp_ms / sp_n, bytes=b, traffic=stored_traffic("spmm_w"))
+                         avg_us=1e3 * sp_ms / sp_n, bytes=b,
+                         traffic=stored_traffic("spmm_w", phase_size("spmm_w", N, s, k)))
     ex = [m for m in modes_exact if m in gate]
     if wl["gate"] == "properties":
         tol = {"fp64": 1e-10}
@@ -956,12 +1061,15 @@ def main():
                           p50_ms=r["p50_ms"], p99_ms=r["p99_ms"],
                           eig_iterative=dict(runs=r["stats"]["iter_runs"],
                                              filter_steps=r["stats"]["iter_steps"],
-                                             fallbacks=r["stats"]["iter_fallbacks"]),
+                                             fallbacks=r["stats"]["iter_fallbacks"],
+                                             gflop_per_run=r["stats"]["iter_flops"] / 1e9
+                                             / max(r["stats"]["iter_runs"], 1)),
                           **({"variant": dict(method=r["method"], l=la, t=ta)}
                              if r["method"] else {})) for m, r in results.items()},
         "gate": gate, "gate_ok": gate_ok, "variants_gate_ok": variants_ok,
         "phases_ms_per_step": {n: v[0] / K for n, v in hr["phases"].items() if v[1]},
         "roofline": roof,
+        "phase_rates": rates,
         "spmm_roofline": spmm_roof,
         "cpu_baseline": cpu,
     }

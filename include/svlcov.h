@@ -133,6 +133,7 @@ typedef struct {
   int64_t iter_runs;          /* eigenproblems solved by the iterative solver  */
   int64_t iter_steps;         /*   its filter steps in total                   */
   int64_t iter_fallbacks;     /*   runs handed to the direct solver            */
+  double iter_flops;          /*   its algorithmic flops (products with M)     */
 } svlcov_stats;
 
 /* Fill *opt with defaults: FP64, device 0, library stream, automatic

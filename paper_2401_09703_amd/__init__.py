@@ -86,7 +86,8 @@ class _Stats(C.Structure):
                 ("last_rank", C.c_int32), ("last_rank2", C.c_int32),
                 ("last_kappa_U", C.c_double), ("last_kappa_V", C.c_double),
                 ("last_min_kept_pivot", C.c_double), ("last_max_dropped_pivot", C.c_double),
-                ("iter_runs", C.c_int64), ("iter_steps", C.c_int64), ("iter_fallbacks", C.c_int64)]
+                ("iter_runs", C.c_int64), ("iter_steps", C.c_int64), ("iter_fallbacks", C.c_int64),
+                ("iter_flops", C.c_double)]
 
 
 class _Approx(C.Structure):

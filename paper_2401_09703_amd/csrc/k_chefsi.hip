@@ -208,8 +208,17 @@ size_t eig_update_work_doubles(int64_t N, int k) {
 
 int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *lam, double *Fv,
                     double *ws, size_t ws_len, double *ctl_host, double tol, int max_it,
-                    uint64_t seed, const SvDevInfo *info, int *iters) {
+                    uint64_t seed, const SvDevInfo *info, int *iters, double *flops) {
   const int p = chefsi_block(k);
+  // algorithmic flops: 2 N^2 p per product with M, 2 N p^2 per Rayleigh
+  // quotient and 4 N p^2 per rotation of X and M X
+  double fl = 0.0;
+  const double f_prod = 2.0 * (double)N * (double)N * p, f_rr = 6.0 * (double)N * p * p;
+  struct FlopOut {
+    double *dst;
+    double *val;
+    ~FlopOut() { if (dst) *dst = *val; }
+  } flop_out{flops, &fl};
   if (!chefsi_applies(N, k) || ws_len < chefsi_work_doubles(N, k)) return -1;
   const size_t panel = (size_t)N * p;
   double *B[5];
@@ -250,6 +259,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
   // Q^T, X <- X Q^T... (Qv holds the eigenvectors of H as rows), Y <- Y Q;
   // then the residuals and the control scalars, read by the host.
   auto rayleigh_ritz = [&]() -> bool {
+    fl += f_prod + f_rr;
     gemm_f64_sk(st, false, false, N, p, N, 1.0, M, N, X, p, 0.0, Y, p, gws, gws_len, info);
     gemm_f64_sk(st, true, false, p, p, N, 1.0, X, p, Y, p, 0.0, H, p, gws, gws_len, info);
     hipLaunchKernelGGL(k_cf_symmetrize, dim3(grid_of((int64_t)p * p)), dim3(256), 0, st, p, H,
@@ -276,6 +286,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
   // the wanted eigenvalues limits) usually suffices after it
   for (int q = 0; q < 2; ++q) {
     double *Z = other({X});
+    fl += f_prod;
     gemm_f64_sk(st, false, false, N, p, N, 1.0, M, N, X, p, 0.0, Z, p, gws, gws_len, info);
     X = Z;
   }
@@ -321,6 +332,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
     double sigma = sigma1;
     if (!have_y) {
       Y = other({X});
+      fl += f_prod;
       gemm_f64_sk(st, false, false, N, p, N, 1.0, M, N, X, p, 0.0, Y, p, gws, gws_len, info);
     }
     double *Yp = X;
@@ -332,6 +344,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
       double *T = other({Yp, Yc});
       hipLaunchKernelGGL(k_cf_combine, dim3(grid_of((int64_t)panel)), dim3(256), 0, st,
                          (int64_t)panel, -2.0 * sn * c / e, Yc, -sigma * sn, Yp, T, info);
+      fl += f_prod;
       gemm_f64_sk(st, false, false, N, p, N, 2.0 * sn / e, M, N, Yc, p, 1.0, T, p, gws, gws_len,
                   info);
       Yp = Yc;

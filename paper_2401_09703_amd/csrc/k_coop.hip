@@ -30,8 +30,8 @@ constexpr int CT = 256;
 //       operands and destination are loaded together, then updated;
 //   barrier.
 // All data exchanged between blocks goes through coherent loads and stores.
-// The inverses of the diagonal blocks are formed afterwards by
-// k_chol_blkinv, off this kernel's sequential path.
+// The inverses of the diagonal blocks are formed by k_chol_blkinv at the
+// start of the triangular solve, off this kernel's sequential path.
 __global__ void __launch_bounds__(CT)
 k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
             SvDevInfo *__restrict__ info, int which, unsigned *__restrict__ flags,
@@ -340,7 +340,7 @@ unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned 
   return e0;
 }
 
-int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv, double tol,
+int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double tol,
                   SvDevInfo *info, int which, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
@@ -351,14 +351,14 @@ int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_coop), dim3(P), dim3(CT),
                                  args, 0, st) != hipSuccess)
     return -3;
-  hipLaunchKernelGGL(k_chol_blkinv, dim3((unsigned)nblk), dim3(64), 0, st, s, G, ld, Linv, info);
   return 0;
 }
 
-int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,
+int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, double *Linv,
               double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
+  hipLaunchKernelGGL(k_chol_blkinv, dim3((unsigned)nblk), dim3(64), 0, st, s, L, ld, Linv, info);
   const int P = coop_blocks(reinterpret_cast<const void *>(k_trsm_coop), coop_want(s));
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)nblk);
   void *args[] = {(void *)&s, (void *)&K, (void *)&L, (void *)&ld, (void *)&Linv,

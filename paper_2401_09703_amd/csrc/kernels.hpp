@@ -101,12 +101,12 @@ void copy_strided(hipStream_t st, int64_t R, int64_t C, const double *src, int64
 void max_into(hipStream_t st, int64_t n, const double *v, SvDevInfo *info, int which);
 constexpr int CHOL_NB = 32;
 // ---- cooperative (k_coop.hip): one launch each; flags/epoch as for eig_topk
-int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
-                  double rank_tol, SvDevInfo *info, int which, unsigned *flags,
-                  unsigned *epoch);
-int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
-              const double *Linv, double *Y, const SvDevInfo *info, unsigned *flags,
-              unsigned *epoch);
+int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double rank_tol,
+                  SvDevInfo *info, int which, unsigned *flags, unsigned *epoch);
+// Y <- L^{-T}-solve of Y (s x K); Linv receives the inverses of L's diagonal
+// blocks first (ceil(s / CHOL_NB) blocks of CHOL_NB^2 doubles)
+int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, double *Linv,
+              double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch);
 // mark the update failed on the device (every later kernel becomes a no-op)
 void set_status(hipStream_t st, SvDevInfo *info, int code);
 // reserve count + 1 barrier epochs; zero the flags first when close to wrap
@@ -282,8 +282,9 @@ size_t chefsi_work_doubles(int64_t N, int k);
 // one's where it applies (the direct solver is its fallback on the same
 // memory).
 size_t eig_update_work_doubles(int64_t N, int k);
+// *flops (may be NULL) receives the run's algorithmic flops.
 int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *lam, double *Fv,
                     double *ws, size_t ws_len, double *ctl_host, double tol, int max_it,
-                    uint64_t seed, const SvDevInfo *info, int *iters);
+                    uint64_t seed, const SvDevInfo *info, int *iters, double *flops);
 
 }  // namespace svl

@@ -87,6 +87,7 @@ struct svlcov_state {
   // solver
   double *ctl_host = nullptr;
   int64_t iter_steps = 0, iter_fallbacks = 0, iter_runs = 0;
+  double iter_flops = 0.0;
   size_t elem() const { return prec == SVLCOV_FP64 ? sizeof(double) : sizeof(float); }
 };
 
