@@ -289,7 +289,7 @@ namespace {
 // Cholesky (Algorithm 2 realised as R^T R = E E^T - (E V)(E V)^T, Lemma 3).
 template <typename T>
 void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
-                   float *Cp32, double *rown, double *Gm, int32_t *rid, int which,
+                   float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which,
                    bool chol = true, double *dws = nullptr, size_t dws_len = 0,
                    double *Scopy = nullptr, int64_t lds_copy = 0) {
   const int K = h->k;
@@ -324,7 +324,7 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
   if (!chol) return;   // the approximate variants use the Gram itself
   PhaseScope ps(h, PH_CHOL);
   coop_enter(h);
-  const int crc = svl::cholesky_coop(st, s, Gm, s, h->rank_tol, h->info, which, h->flags,
+  const int crc = svl::cholesky_coop(st, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags,
                                      &h->epoch);
   coop_exit(h);
   if (crc) {
@@ -447,7 +447,7 @@ void sparse_side_small(svlcov_state *h, int64_t s, int64_t N, const double *Xv,
 // (the normalisation of Algorithm 2), Wnew = W (X[:k] - C_n X[k:]) with
 // C_n X[k:] = Cp^T Y.  X is given by rows (Xv, K x N).
 void sparse_side_math(svlcov_state *h, int64_t s, int64_t N, const double *Xv, const double *Cp64,
-                      const double *L, double *Linv, const double *W, double *Y,
+                      const double *L, const double *Linv, const double *W, double *Y,
                       double *T1, double *Wnew, double *Winv, int32_t *flag, int side,
                       double *gws, size_t gws_len, bool do_inverse = true) {
   const int K = h->k;
@@ -570,7 +570,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   }
   svl::op_begin(st, h->info, 0);
   // orthogonalise the augmented matrix of the sparse side
-  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, rid, 0, true, Kmat,
+  orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, rid, 0, true, Kmat,
                    (size_t)N * N,    // K is formed only after the Gram
                    Mmat + (size_t)K * N + K, N);
   // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
@@ -746,7 +746,7 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
     svl::validate_csr(st, dE.rows, dE.cols, dE.nnz, dE.rp, dE.ci, dE.v, dE.vdt, h->info, h->seq);
   }
   svl::op_begin(st, h->info, 0);
-  orthogonalise<T>(h, dE, B_base, W_B, b.Cp64, b.Cp32, b.rown, b.Gm, b.rid, 0, false,
+  orthogonalise<T>(h, dE, B_base, W_B, b.Cp64, b.Cp32, b.rown, b.Gm, nullptr, b.rid, 0, false,
                    dws_len > 1 ? b.Dws : nullptr, dws_len > 1 ? dws_len : 0);
   double *gws = b.orthw + 2 * K * K + K * N;
   const size_t gws_len = (size_t)8 * K * N;
@@ -984,7 +984,7 @@ svlcov_status op_weights_approx(svlcov_state *h, const svlcov_csr *D, const svlc
   for (int q = 0; q < 2; ++q) {
     const int l = lq[q];
     orthogonalise<T>(h, dq[q], baseq[q], Wq[q], sd[q].Cp64, sd[q].Cp32, sd[q].rown, sd[q].Gm,
-                     b.rid, q, false, dws_len > 1 ? b.Dws : nullptr,
+                     nullptr, b.rid, q, false, dws_len > 1 ? b.Dws : nullptr,
                      dws_len > 1 ? dws_len : 0);
     // the basis reads its drop scale from the first slot
     if (q == 1) svl::max_into(st, s, sd[q].rown, h->info, 0);
@@ -1168,8 +1168,8 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
                         h->seq);
   }
   svl::op_begin(st, h->info, 1);
-  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, rid, 0, true, Kmat, (size_t)N * N);
-  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, rid, 1, true, Kmat, (size_t)N * N);
+  orthogonalise<T>(h, dD, Ub, h->WU, CpD, C32D, rnD, GD, LiD, rid, 0, true, Kmat, (size_t)N * N);
+  orthogonalise<T>(h, dEm, Vb, h->WV, CpE, C32E, rnE, GE, LiE, rid, 1, true, Kmat, (size_t)N * N);
   // K = [[Sigma, 0], [0, 0]] + [U^T D ; R_D] [V^T E_m ; R_E]^T
   {
     PhaseScope ps(h, PH_BUILDK);

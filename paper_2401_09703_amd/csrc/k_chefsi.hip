@@ -3,7 +3,8 @@
 // update (Section 2.1, step 2; Theorem 1's (k+s)^3 term) needs only the k
 // leading eigenpairs of M = K K^T, so instead of reducing all of M to
 // tridiagonal form (one grid-wide exchange per column) the solver works on an
-// N x p block (p = 2k columns) with dense products M X on FP64 MFMA:
+// N x p block (p = k + 32 columns, see chefsi_block) with dense products M X on
+// FP64 MFMA:
 //
 //   X <- orth(start);  repeat:  Y = M X,  H = X^T Y,  H = Q diag(theta) Q^T,
 //   X <- X Q, Y <- Y Q;  stop when ||Y_j - theta_j X_j|| <= tol ||M|| (j < k);
@@ -22,6 +23,7 @@
 // (lam descending, Fv k x N, row j an eigenvector, its entry of largest
 // magnitude positive).
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <initializer_list>
 
@@ -184,7 +186,24 @@ unsigned grid_of(int64_t n) {
 
 namespace svl {
 
-int chefsi_block(int k) { return 2 * k; }
+// basis width p = k + 32 rounded up to a multiple of 16 (at most 128): 32
+// guard vectors keep the gap between the k-th wanted and the first damped
+// Ritz value wide enough for one Chebyshev step on the graph spectra, and
+// every p x p stage (Gram, Cholesky QR, the Rayleigh quotient's eigensolver)
+// scales with p (a sweep on the 100k-node graph workload at k = 64:
+// p = 128 3.99 ms, 96 3.63 ms, 80 3.45 ms median but with a second filter
+// step on some updates).  SVLCOV_CHEFSI_P overrides it for tuning sweeps (a
+// multiple of 16 in (k, 128]).
+int chefsi_block(int k) {
+  static int forced = -1;
+  if (forced < 0) {
+    forced = 0;
+    if (const char *ev = getenv("SVLCOV_CHEFSI_P")) forced = atoi(ev);
+  }
+  if (forced > k && forced <= 128 && forced % 16 == 0) return forced;
+  const int p = (k + 32 + 15) / 16 * 16;
+  return p < 128 ? p : 128;
+}
 
 bool chefsi_applies(int64_t N, int k) {
   const int p = chefsi_block(k);
@@ -238,14 +257,15 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
   // basis X (in B[0]), Y = M X (B[1]); B[2..4] are scratch
   double *X = B[0], *Y = B[1];
   // columns scaled to unit length, one pass of Cholesky QR, and a second one
-  // only when the first's input was not orthonormal to within 1e-2 per
-  // entry of its Gram (condition number at most 1 + 1.27; one pass then
-  // leaves an orthogonality error of a few u) or a column was completed
+  // when a column was completed or (gate_tau < 1) when the first's input was
+  // not orthonormal to within gate_tau per entry of its Gram (at 1e-2 the
+  // condition number is at most 1 + 1.27, and one pass then leaves an
+  // orthogonality error of a few u)
   int32_t *need = (int32_t *)(ctl + 16);
-  auto orth = [&](double *src, double *scratch) -> double * {
+  auto orth = [&](double *src, double *scratch, double gate_tau) -> double * {
     hipLaunchKernelGGL(k_cf_colnorm, dim3(p), dim3(256), 0, st, N, p, src, info);
     return orth_cols_cond(st, N, p, src, scratch, G, Out, complete, need, gws, gws_len, ++seed,
-                          rtol, info, 1e-2);
+                          rtol, info, gate_tau);
   };
   auto other = [&](std::initializer_list<const double *> used) -> double * {
     for (int q = 0; q < 5; ++q) {
@@ -290,7 +310,13 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
     gemm_f64_sk(st, false, false, N, p, N, 1.0, M, N, X, p, 0.0, Z, p, gws, gws_len, info);
     X = Z;
   }
-  X = orth(X, other({X}));
+  // the basis after the power steps only feeds the first Rayleigh-Ritz step
+  // (bounds and a rotation) and the filter, which needs its span alone: one
+  // pass leaves it orthonormal to about u cond(X)^2, which for the two power
+  // steps' condition number moves the Ritz values by far less than the
+  // residuals they are judged by; a completed column still takes the second
+  // pass (it is random, not orthogonal to the kept ones)
+  X = orth(X, other({X}), 2.0);
   Y = other({X});
   if (!rayleigh_ritz()) return -3;
   bool have_y = true;
@@ -351,7 +377,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
       Yc = T;
       sigma = sn;
     }
-    X = orth(Yc, other({Yc}));
+    X = orth(Yc, other({Yc}), 1e-2);
     Y = other({X});
     if (!rayleigh_ritz()) return -3;
     have_y = true;

@@ -19,156 +19,385 @@ constexpr int CT = 256;
 
 // Blocked right-looking Cholesky of the lower triangle of A (s x s, row
 // stride ld) with pivot dropping: a pivot d_j <= tol * scale sets column j of
-// L to zero.  Per block column (NB = 32):
-//   (1) every block loads the diagonal block and factors it (wave 0, rows
-//       in registers; the other waves wait);
-//   (2) the panel rows are spread over the blocks, two rows per wave: a row
-//       is solved against the diagonal factor by forward substitution with
-//       one lane per column;
-//   barrier; block 0 stores the diagonal factor;
-//   (3) the lower trailing tiles are spread over the blocks; each tile's
-//       operands and destination are loaded together, then updated;
+// L to zero.  The diagonal blocks are factored one step ahead by block 0 alone,
+// which also forms their inverses (written to Linv, NB x NB per block), so the
+// other blocks never wait on a factorisation.  Per block column b:
+//   every block loads Linv_b; the panel rows r >= r0 are x = a Linv_b^T (a
+//   product, no substitution chain): block 0 takes the NB rows of the next
+//   block row, the other blocks the rest;
+//   block 0 announces its panel rows, updates the next diagonal block with
+//   them (A_{b+1} -= X X^T), factors it (wave 0, two lanes per row, pivots
+//   by v_readlane and 1/sqrt by a Newton-refined v_rsq), inverts it (one lane
+//   per column of the inverse) and stores both;
+//   the other blocks wait for all panel rows and update the remaining lower
+//   tiles of the trailing matrix on FP64 MFMA (16 x 16 quadrant per wave; the
+//   next tile's operands are loaded while the current one is multiplied);
 //   barrier.
-// All data exchanged between blocks goes through coherent loads and stores.
-// The inverses of the diagonal blocks are formed by k_chol_blkinv at the
-// start of the triangular solve, off this kernel's sequential path.
+// A dropped pivot leaves a zero column in L; its block inverse is formed with
+// a unit placeholder on the diagonal and then has that row and column
+// zeroed, so the solve drops the same directions.  All data exchanged between
+// blocks goes through coherent loads and stores.
+typedef double cv_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ cv_d4 mfma64(double a, double b, cv_d4 c) {
+  // A[m][k] from lane (m, k) = (l % 16, l / 16), B[k][n] from lane (k, n) =
+  // (l / 16, l % 16), D[m][n] in lane (l % 16 = n, l / 16 + 4 q = m), slot q
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// 1 / sqrt(d) for d > 0: v_rsq_f64 refined by two Newton steps
+// y <- y (3 - d y^2) / 2, each doubling the correct bits.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * (1.5 - 0.5 * d * y * y);
+  y = y * (1.5 - 0.5 * d * y * y);
+  return y;
+}
+
+// Arrive at / wait for a flag barrier separately (flag_barrier does both).
+__device__ __forceinline__ void flag_arrive(unsigned *flags, unsigned epoch) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&flags[blockIdx.x * FLAG_STRIDE], epoch, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct CholSh {
+  double Li[NB][NB + 1];   // inverse of the current diagonal block
+  double Xp[NB][NB + 1];   // block 0: its panel rows (the next block row)
+  double Dg[NB][NB + 1];   // block 0: the next diagonal block
+  double ta[NB][NB + 1];   // trailing update operands / block 0: next inverse
+  double tb[NB][NB + 1];
+  double row[CT / 32][NB];   // one panel row per half-wave
+  double colA[NB], colB[NB];   // the two columns of a factorisation step
+  double rowA[NB], rowB[NB];   // the two pivot rows of the inverse
+  double piv[NB];              // the pivots d_j before the square root
+  int dropped[NB];             // also set for the padding beyond nb
+};
+
+// C = D - X_a X_b^T for one NB x NB tile (X_a = ta, X_b = tb, D = dv in the
+// output layout), wave w computing quadrant (w >> 1, w & 1); returns the
+// lane's four results of its quadrant.
+__device__ __forceinline__ cv_d4 tile_update(const double (*ta)[NB + 1],
+                                             const double (*tb)[NB + 1], cv_d4 dv, int w,
+                                             int lane) {
+  const int li = lane & 15, lk = lane >> 4;
+  const int qi = w >> 1, qj = w & 1;
+  cv_d4 acc = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < NB; kk += 4)
+    acc = mfma64(ta[16 * qi + li][kk + lk], tb[16 * qj + li][kk + lk], acc);
+  return dv - acc;
+}
+
+// Block 0: factor the nb x nb block in Dg in place and form the inverse of
+// the factor in Ld (all NB x NB entries; zero outside the nb x nb lower part
+// and on the rows and columns of dropped pivots), by wave 0 alone, two columns
+// per step.  Lane (i, h) = (lane % 32, lane / 32) holds row i of the block,
+// columns 16 h .. 16 h + 15, and rows 16 h .. 16 h + 15 of column i of the
+// inverse, which starts as the identity and takes the same row operations as
+// the block (elimination applied to [A | I] yields L^{-1}).  Per step the
+// three entries of the 2 x 2 pivot block come by v_readlane and both inverse
+// square roots are taken at once: with q = a11 d0 - a10^2 the second pivot
+// is d1 = q / d0 and 1 / sqrt(d1) = sqrt(d0) / sqrt(q).  The two columns of
+// L and the two pivot rows of the inverse then go through LDS for one rank-2
+// update of both.  A dropped pivot zeroes its column of L and its row of the
+// inverse.
+__device__ void factor_and_invert(CholSh &sh, double (*Ld)[NB + 1], int nb, double thr,
+                                  double scale, double &st_maxdrop, double &st_minkept,
+                                  int &st_kept) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 64) {
+    const int i = lane & 31, h = lane >> 5;
+    double a[16], x[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      a[c] = sh.Dg[i][16 * h + c];
+      x[c] = (16 * h + c == i) ? 1.0 : 0.0;
+    }
+    const bool scale_ok = scale > 0.0;
+#pragma unroll
+    for (int jp = 0; jp < NB; jp += 2) {
+      if (jp < nb) {
+        const int hj = jp >> 4, c0 = jp & 15, c1 = c0 + 1, lj = jp + 32 * hj;
+        const bool two = jp + 1 < nb;
+        const double d0 = readlane_d(a[c0], lj);
+        const double a10 = readlane_d(a[c0], lj + 1);
+        const double a11 = readlane_d(a[c1], lj + 1);
+        const double q = a11 * d0 - a10 * a10;
+        // three independent inverse square roots
+        const double r0v = rsqrt_nr(fmax(d0, 1e-300));
+        const double rqv = rsqrt_nr(fmax(q, 1e-300));
+        const double rav = rsqrt_nr(fmax(a11, 1e-300));
+        const bool drop0 = !(d0 > thr) || !scale_ok;
+        const double r0 = drop0 ? 0.0 : r0v;
+        const double d1 = drop0 ? a11 : q * r0 * r0;
+        const bool drop1 = !(d1 > thr) || !scale_ok || !two;
+        const double r1 = drop1 ? 0.0 : (drop0 ? rav : rqv * d0 * r0);
+        const double l0n = a10 * r0;                 // L[jp + 1][jp]
+        const double l0 = a[c0] * r0;                // L[i][jp]
+        const double l1 = (a[c1] - l0 * l0n) * r1;   // L[i][jp + 1]
+        if (lane == 0) {
+          sh.piv[jp] = d0;
+          if (two) sh.piv[jp + 1] = d1;
+        }
+        if (h == hj) {
+          a[c0] = i > jp ? l0 : (i == jp ? d0 * r0 : 0.0);
+          a[c1] = i > jp + 1 ? l1 : (i == jp + 1 ? d1 * r1 : 0.0);
+          // the two columns below the pair (zero elsewhere, so finished rows
+          // and columns are left unchanged by the update)
+          sh.colA[i] = i > jp + 1 ? l0 : 0.0;
+          sh.colB[i] = i > jp + 1 ? l1 : 0.0;
+          // the pair's rows of the inverse, scaled (column i of the inverse)
+          const double xa = x[c0] * r0;
+          const double xb = (x[c1] - l0n * xa) * r1;
+          x[c0] = xa;
+          x[c1] = xb;
+          sh.rowA[i] = xa;
+          sh.rowB[i] = xb;
+        }
+        wave_sync();
+        const double la = sh.colA[i], lb = sh.colB[i];
+        const double xa = sh.rowA[i], xb = sh.rowB[i];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const double ca = sh.colA[16 * h + c], cb = sh.colB[16 * h + c];
+          a[c] -= la * ca;
+          a[c] -= lb * cb;
+          x[c] -= ca * xa;
+          x[c] -= cb * xb;
+        }
+        wave_sync();
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int cc = 16 * h + c;
+      sh.Dg[i][cc] = (i < nb && cc <= i) ? a[c] : 0.0;
+    }
+    // pivot decisions and statistics (lane j: pivot j)
+    if (lane < NB) {
+      const int j = lane;
+      const double d = j < nb ? sh.piv[j] : 0.0;
+      const bool drop = j < nb && (!(d > thr) || !scale_ok);
+      sh.dropped[j] = (j >= nb || drop) ? 1 : 0;
+      if (j < nb) {
+        const double rel = scale_ok ? d / scale : 0.0;
+        if (drop) st_maxdrop = fmax(st_maxdrop, rel);
+        else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int r = 16 * h + c;   // row r, column i of the inverse
+      Ld[r][i] = (r < i || sh.dropped[r] || sh.dropped[i]) ? 0.0 : x[c];
+    }
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(CT)
 k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
             SvDevInfo *__restrict__ info, int which, unsigned *__restrict__ flags,
-            unsigned epoch0) {
+            unsigned epoch0, double *__restrict__ Linv) {
   if (info->status) return;
-  __shared__ double Ld[NB][NB + 1];
-  __shared__ double rinv[NB];     // 1 / L_jj, 0 for a dropped pivot
-  __shared__ double colj[NB];     // scaled column of the diagonal factor
-  __shared__ double ta[NB][NB + 1];
-  __shared__ double tb[NB][NB + 1];
+  __shared__ CholSh sh;
   const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const double scale = which == 0 ? info->scale : info->scale2;
   const double thr = tol * scale;
   const int64_t nblk = (s + NB - 1) / NB;
   unsigned ep = epoch0;
   double st_maxdrop = -1.0, st_minkept = INFINITY;
   int st_kept = 0;
+  // the blocks other than 0 share the panel rows and trailing tiles (block 0
+  // joins them only when it is alone)
+  const bool other = P == 1 || g >= 1;
+  const int Po = P > 1 ? P - 1 : 1, go = P > 1 ? g - 1 : 0;
+
+  // prologue: block 0 factors and inverts the first diagonal block
+  if (g == 0) {
+    const int nb = (int)(s < NB ? s : NB);
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int i = e / NB, j = e % NB;
+      sh.Dg[i][j] = (i < nb && j <= i) ? ld_coh(&A[i * ld + j]) : 0.0;
+    }
+    __syncthreads();
+    factor_and_invert(sh, sh.ta, nb, thr, scale, st_maxdrop, st_minkept, st_kept);
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int i = e / NB, j = e % NB;
+      if (i < nb && j < nb) st_coh(&A[i * ld + j], sh.Dg[i][j]);
+      st_coh(&Linv[e], sh.ta[i][j]);
+    }
+  }
+  flag_barrier(flags, ++ep);
+
   for (int64_t b = 0; b < nblk; ++b) {
     const int64_t b0 = b * NB;
     const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
-    const int64_t r0 = b0 + nb;
-    // (1) diagonal block
-    for (int e = tid; e < NB * NB; e += CT) {
-      const int i = e / NB, j = e % NB;
-      Ld[i][j] = (i < nb && j <= i) ? ld_coh(&A[(b0 + i) * ld + b0 + j]) : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      // wave 0 factors the block right-looking with row i in lane i's
-      // registers: per column the pivot comes from lane j (v_readlane), the
-      // scaled column is shared through LDS, and the trailing update is a
-      // fully unrolled register loop
-      const int i = lane & 31;
-      double a[NB];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) a[c] = Ld[i][c];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        if (j < nb) {
-          const double d = readlane_d(a[j], j);
-          const bool drop = !(d > thr) || !(scale > 0.0);
-          const double rd = drop ? 0.0 : sqrt(d);
-          const double ri = drop ? 0.0 : 1.0 / rd;
-          if (lane == 0) {
-            rinv[j] = ri;
-            const double rel = scale > 0.0 ? d / scale : 0.0;
-            if (drop) st_maxdrop = fmax(st_maxdrop, rel);
-            else { st_minkept = fmin(st_minkept, rel); ++st_kept; }
-          }
-          const double lij = i > j ? a[j] * ri : (i == j ? rd : 0.0);
-          a[j] = lij;
-          if (lane < NB) colj[i] = i > j ? lij : 0.0;
-          wave_sync();
-#pragma unroll
-          for (int c = j + 1; c < NB; ++c) a[c] -= lij * colj[c];
-          wave_sync();
-        }
-      }
-      if (lane < NB)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) Ld[i][c] = c <= i ? a[c] : 0.0;
-    }
-    __syncthreads();
-    // (2) panel rows r >= r0: row r = r0 + h + 8 (g + P q) for the half-wave
-    // h of this block; lane c of the half-wave owns column c
-    {
-      const int hw = tid >> 5, c = tid & 31;   // 8 half-waves per block
-      for (int64_t base = (int64_t)g * (CT / 32); base < s - r0; base += (int64_t)P * (CT / 32)) {
-        const int64_t r = r0 + base + hw;
-        const bool act = r < s;
-        double acc = (act && c < nb) ? ld_coh(&A[r * ld + b0 + c]) : 0.0;
-        double x = 0.0;
-        // the pivot reciprocals and this lane's row of the factor in
-        // registers, then a fully unrolled substitution
-        double ri[NB], lr[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) { ri[j] = rinv[j]; lr[j] = Ld[c][j]; }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          if (j < nb) {
-            const double xj = __shfl(acc * ri[j], (lane & 32) + j, 64);
-            if (c == j) x = xj;
-            if (c > j) acc -= lr[j] * xj;
-          }
-        }
-        if (act && c < nb) st_coh(&A[r * ld + b0 + c], x);
-      }
-    }
-    flag_barrier(flags, ++ep);
-    // every block has read the diagonal block: block 0 may now overwrite it
-    // with its factor (nothing reads it again in this launch)
+    const int64_t r0 = b0 + nb, rem = s - r0;
+    const int nb1 = (int)(rem < NB ? rem : NB);   // rows of the next block row
+    // block 0 fetches the next diagonal block with Linv_b
+    double dgv[NB * NB / CT];
     if (g == 0) {
-      for (int e = tid; e < nb * nb; e += CT) {
-        const int i = e / nb, j = e % nb;
-        st_coh(&A[(b0 + i) * ld + b0 + j], j <= i ? Ld[i][j] : 0.0);
+#pragma unroll
+      for (int q = 0; q < NB * NB / CT; ++q) {
+        const int e = tid + q * CT, i = e / NB, j = e % NB;
+        dgv[q] = (i < nb1 && j <= i) ? ld_coh(&A[(r0 + i) * ld + r0 + j]) : 0.0;
       }
     }
-    // (3) trailing update of the lower tiles of rows/columns >= r0
-    const int64_t T = (s - r0 + NB - 1) / NB;
-    const int64_t ntiles = T * (T + 1) / 2;
-    for (int64_t t = g; t < ntiles; t += P) {
-      int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-      while (ti * (ti + 1) / 2 > t) --ti;
-      const int64_t tj = t - ti * (ti + 1) / 2;
-      const int64_t ra = r0 + ti * NB, rb = r0 + tj * NB;
-      constexpr int PER = NB * NB / CT;   // destination elements per thread
-      double dv[PER];
+    for (int e = tid; e < NB * NB; e += CT) sh.Li[e / NB][e % NB] = ld_coh(&Linv[b * NB * NB + e]);
+    // panel rows: x_c = sum_{j <= c} a_j Linv[c][j] (half-wave hw, lane c)
+    const int hw = tid >> 5, c = tid & 31;
+    auto panel_row = [&](int64_t r, double a, bool act) -> double {
+      sh.row[hw][c] = a;
+      wave_sync();
+      double x = 0.0;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
+      for (int j = 0; j < NB; ++j) x += sh.row[hw][j] * sh.Li[c][j];
+      wave_sync();
+      if (act && c < nb) st_coh(&A[r * ld + b0 + c], x);
+      return x;
+    };
+    if (g == 0) {
+      // the next block row, X = A_{b+1,b} Linv_b^T, as one MFMA tile product
+      // (quadrant per wave) into tb and A
+      double av[NB * NB / CT];
+#pragma unroll
+      for (int q = 0; q < NB * NB / CT; ++q) {
         const int e = tid + q * CT, i = e / NB, j = e % NB;
-        dv[q] = (ra + i < s && rb + j < s && (ti != tj || j <= i))
-                    ? ld_coh(&A[(ra + i) * ld + rb + j]) : 0.0;
+        av[q] = (i < nb1 && j < nb) ? ld_coh(&A[(r0 + i) * ld + b0 + j]) : 0.0;
       }
-      for (int e = tid; e < NB * NB; e += CT) {
-        const int i = e / NB, p = e % NB;
-        ta[i][p] = (ra + i < s && p < nb) ? ld_coh(&A[(ra + i) * ld + b0 + p]) : 0.0;
-        tb[i][p] = (rb + i < s && p < nb) ? ld_coh(&A[(rb + i) * ld + b0 + p]) : 0.0;
+#pragma unroll
+      for (int q = 0; q < NB * NB / CT; ++q) {
+        const int e = tid + q * CT;
+        sh.Xp[e / NB][e % NB] = av[q];
       }
+      __syncthreads();   // Li and the rows complete
+      const int qi = w >> 1, qj = w & 1;
+      const cv_d4 x = tile_update(sh.Xp, sh.Li, cv_d4{0.0, 0.0, 0.0, 0.0}, w, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = 16 * qi + lk + 4 * q, col = 16 * qj + li;
+        sh.tb[row][col] = -x[q];
+        if (row < nb1 && col < nb) st_coh(&A[(r0 + row) * ld + b0 + col], -x[q]);
+      }
+    } else {
       __syncthreads();
+    }
+    if (other) {
+      // the remaining rows r0 + nb1 + idx, idx = 8 go + hw + 8 Po q
+      for (int64_t base = (int64_t)go * (CT / 32); base < rem - nb1;
+           base += (int64_t)Po * (CT / 32) * 4) {
+        double av[4];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int e = tid + q * CT, i = e / NB, j = e % NB;
-        if (ra + i < s && rb + j < s && (ti != tj || j <= i)) {
-          double acc = 0.0;   // entries p >= nb of ta, tb are zero
+        for (int q = 0; q < 4; ++q) {
+          const int64_t idx = base + hw + (int64_t)q * Po * (CT / 32);
+          av[q] = (idx < rem - nb1 && c < nb) ? ld_coh(&A[(r0 + nb1 + idx) * ld + b0 + c]) : 0.0;
+        }
 #pragma unroll
-          for (int p = 0; p < NB; ++p) acc += ta[i][p] * tb[j][p];
-          st_coh(&A[(ra + i) * ld + rb + j], dv[q] - acc);
+        for (int q = 0; q < 4; ++q) {
+          const int64_t idx = base + hw + (int64_t)q * Po * (CT / 32);
+          panel_row(r0 + nb1 + idx, av[q], idx < rem - nb1);
         }
       }
-      __syncthreads();
+    }
+    if (g == 0) {
+      flag_arrive(flags, ++ep);   // the next block row is stored
+      if (nb1 > 0) {
+        // A_{b+1} -= X X^T, factor, invert, store
+#pragma unroll
+        for (int q = 0; q < NB * NB / CT; ++q) {
+          const int e = tid + q * CT;
+          sh.Dg[e / NB][e % NB] = dgv[q];
+        }
+        __syncthreads();
+        {
+          const int qi = w >> 1, qj = w & 1;
+          cv_d4 dv;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dv[q] = sh.Dg[16 * qi + lk + 4 * q][16 * qj + li];
+          const cv_d4 r = tile_update(sh.tb, sh.tb, dv, w, lane);
+          __syncthreads();
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sh.Dg[16 * qi + lk + 4 * q][16 * qj + li] = r[q];
+        }
+        __syncthreads();
+        factor_and_invert(sh, sh.ta, nb1, thr, scale, st_maxdrop, st_minkept, st_kept);
+        for (int e = tid; e < NB * NB; e += CT) {
+          const int i = e / NB, j = e % NB;
+          if (i < nb1 && j < nb1) st_coh(&A[(r0 + i) * ld + r0 + j], sh.Dg[i][j]);
+          st_coh(&Linv[(b + 1) * NB * NB + e], sh.ta[i][j]);
+        }
+      }
+    } else {
+      flag_barrier(flags, ++ep);   // every panel row is stored
+    }
+    if (other) {
+      if (P == 1) flag_barrier(flags, ep);   // block 0 alone: its own stores are complete
+      // trailing tiles t >= 1 of the lower triangle of rows / columns >= r0
+      // (tile 0 is the next diagonal block, block 0's)
+      const int64_t T = (rem + NB - 1) / NB;
+      const int64_t ntiles = T * (T + 1) / 2;
+      const int qi = w >> 1, qj = w & 1;
+      auto coords = [&](int64_t t, int64_t &ra, int64_t &rb, bool &diag) {
+        int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        while (ti * (ti + 1) / 2 > t) --ti;
+        const int64_t tj = t - ti * (ti + 1) / 2;
+        ra = r0 + ti * NB;
+        rb = r0 + tj * NB;
+        diag = ti == tj;
+      };
+      // operands of a tile in registers: 4 entries each of X_a, X_b, D
+      double pa[4], pb[4], pd[4];
+      auto fetch = [&](int64_t t) {
+        int64_t ra, rb;
+        bool diag;
+        coords(t, ra, rb, diag);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * CT, i = e / NB, p = e % NB;
+          pa[q] = (ra + i < s && p < nb) ? ld_coh(&A[(ra + i) * ld + b0 + p]) : 0.0;
+          pb[q] = (rb + i < s && p < nb) ? ld_coh(&A[(rb + i) * ld + b0 + p]) : 0.0;
+          const int64_t oi = ra + 16 * qi + lk + 4 * q, oj = rb + 16 * qj + li;
+          pd[q] = (oi < s && oj < s && (!diag || oj - rb <= oi - ra)) ? ld_coh(&A[oi * ld + oj])
+                                                                    : 0.0;
+        }
+      };
+      int64_t t = 1 + go;
+      if (t < ntiles) fetch(t);
+      for (; t < ntiles; t += Po) {
+        int64_t ra, rb;
+        bool diag;
+        coords(t, ra, rb, diag);
+        __syncthreads();   // the previous tile's operands are consumed
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + q * CT, i = e / NB, p = e % NB;
+          sh.ta[i][p] = pa[q];
+          sh.tb[i][p] = pb[q];
+        }
+        const cv_d4 dv = cv_d4{pd[0], pd[1], pd[2], pd[3]};
+        __syncthreads();
+        if (t + Po < ntiles) fetch(t + Po);   // in flight during the products
+        if (!(diag && qi < qj)) {
+          const cv_d4 r = tile_update(sh.ta, sh.tb, dv, w, lane);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t oi = ra + 16 * qi + lk + 4 * q, oj = rb + 16 * qj + li;
+            if (oi < s && oj < s && (!diag || oj - rb <= oi - ra)) st_coh(&A[oi * ld + oj], r[q]);
+          }
+        }
+      }
     }
     flag_barrier(flags, ++ep);
   }
   if (g == 0 && tid < 64) {
-    // the pivot statistics were kept by the lane of each column
+    // the pivot statistics were kept by lane 0 of block 0
     for (int o = 32; o > 0; o >>= 1) {
       st_maxdrop = fmax(st_maxdrop, __shfl_xor(st_maxdrop, o, 64));
       st_minkept = fmin(st_minkept, __shfl_xor(st_minkept, o, 64));
@@ -179,36 +408,6 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
       if (st_minkept < info->min_kept) info->min_kept = st_minkept;
       if (which == 0) info->rank += st_kept; else info->rank2 += st_kept;
     }
-  }
-}
-
-// Inverse of every NB x NB diagonal block of the factor (one wave per block):
-// unit placeholders on dropped pivots (zero diagonal), then their rows and
-// columns zeroed.
-__global__ void __launch_bounds__(64)
-k_chol_blkinv(int64_t s, const double *__restrict__ L, int64_t ld, double *__restrict__ Linv,
-              const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double tmp[NB];
-  __shared__ int dropped[NB];
-  const int64_t b = blockIdx.x, b0 = b * NB;
-  const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
-  const int tid = threadIdx.x;
-  if (tid < NB) dropped[tid] = tid < nb ? (L[(b0 + tid) * ld + b0 + tid] == 0.0) : 1;
-  wave_sync();
-  for (int e = tid; e < NB * NB; e += 64) {
-    const int i = e / NB, j = e % NB;
-    double v = (i < nb && j <= i) ? L[(b0 + i) * ld + b0 + j] : 0.0;
-    if (i == j && dropped[i]) v = 1.0;
-    Li[i][j] = v;
-  }
-  wave_sync();
-  tri_lower_inv_wave(&Li[0][0], NB + 1, NB, tmp);
-  for (int e = tid; e < NB * NB; e += 64) {
-    const int i = e / NB, j = e % NB;
-    const bool z = j > i || dropped[i] || dropped[j];
-    Linv[b * NB * NB + e] = z ? 0.0 : Li[i][j];
   }
 }
 
@@ -340,25 +539,24 @@ unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned 
   return e0;
 }
 
-int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double tol,
+int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv, double tol,
                   SvDevInfo *info, int which, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
   const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), coop_want(s));
-  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)(2 * nblk));
-  void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&tol,
-                  (void *)&info, (void *)&which, (void *)&flags, (void *)&e0};
+  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)(2 * nblk + 1));
+  void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&tol, (void *)&info,
+                  (void *)&which, (void *)&flags, (void *)&e0, (void *)&Linv};
   if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_chol_coop), dim3(P), dim3(CT),
                                  args, 0, st) != hipSuccess)
     return -3;
   return 0;
 }
 
-int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, double *Linv,
+int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,
               double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
-  hipLaunchKernelGGL(k_chol_blkinv, dim3((unsigned)nblk), dim3(64), 0, st, s, L, ld, Linv, info);
   const int P = coop_blocks(reinterpret_cast<const void *>(k_trsm_coop), coop_want(s));
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)nblk);
   void *args[] = {(void *)&s, (void *)&K, (void *)&L, (void *)&ld, (void *)&Linv,

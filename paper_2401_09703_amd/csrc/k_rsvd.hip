@@ -693,16 +693,33 @@ __global__ void k_fill_cols(int64_t R, int L, double *__restrict__ X,
 // sqrt((1 + (L-1) tau) / (1 - (L-1) tau)), and one pass already left it
 // orthonormal to a small multiple of the unit roundoff: a second pass would
 // change nothing but rounding.
-__global__ void k_orth_gate(int L, const double *__restrict__ G, const int32_t *__restrict__ complete,
-                            double tau, int32_t *__restrict__ need,
-                            const SvDevInfo *__restrict__ info) {
+__global__ void __launch_bounds__(1024)
+k_orth_gate(int L, const double *__restrict__ G, const int32_t *__restrict__ complete,
+            double tau, int32_t *__restrict__ need, const SvDevInfo *__restrict__ info) {
   if (info->status) return;
+  extern __shared__ double dg[];   // sqrt(G_ii), L entries
   bool more = false;
-  for (int e = threadIdx.x; e < L * L; e += blockDim.x) {
-    const int i = e / L, c = e % L;
-    if (c < i) more |= !(fabs(G[e]) <= tau * sqrt(G[i * L + i] * G[c * L + c]));
+  for (int j = threadIdx.x; j < L; j += blockDim.x) {
+    dg[j] = sqrt(G[j * L + j]);
+    more |= complete[j] != 0;
   }
-  for (int j = threadIdx.x; j < L; j += blockDim.x) more |= complete[j] != 0;
+  __syncthreads();
+  // eight independent entries in flight per thread
+  const int n = L * L;
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * (int)blockDim.x) {
+    double g[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      g[u] = e < n ? G[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * (int)blockDim.x;
+      const int i = e / L, c = e - (e / L) * L;
+      if (e < n && c < i) more |= !(fabs(g[u]) <= tau * (dg[i] * dg[c]));
+    }
+  }
   more = __syncthreads_or(more);
   if (threadIdx.x == 0) *need = more ? 1 : 0;
 }
@@ -942,8 +959,8 @@ double *orth_cols_cond(hipStream_t st, int64_t R, int L, double *X, double *Y, d
     else gemm_f64_sk(st, true, false, L, L, R, 1.0, src, L, src, L, 0.0, G, L, ws, ws_len, info);
     chol_drop_if(st, L, G, Out, complete, rtol, info, gate);
     if (pass == 0)
-      hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, L, G, complete, gate_tau,
-                         need, info);
+      hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(1024), (size_t)L * sizeof(double), st, L, G,
+                         complete, gate_tau, need, info);
     if (mf) ts_mul_lt(st, R, L, src, Out, dst, info);
     else gemm_f64(st, false, true, R, L, L, 1.0, src, L, Out, L, 0.0, dst, L, info);
     fill_cols(st, R, L, dst, complete, seed * 3 + (uint64_t)pass, info);

@@ -101,12 +101,16 @@ void copy_strided(hipStream_t st, int64_t R, int64_t C, const double *src, int64
 void max_into(hipStream_t st, int64_t n, const double *v, SvDevInfo *info, int which);
 constexpr int CHOL_NB = 32;
 // ---- cooperative (k_coop.hip): one launch each; flags/epoch as for eig_topk
-int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double rank_tol,
-                  SvDevInfo *info, int which, unsigned *flags, unsigned *epoch);
-// Y <- L^{-T}-solve of Y (s x K); Linv receives the inverses of L's diagonal
-// blocks first (ceil(s / CHOL_NB) blocks of CHOL_NB^2 doubles)
-int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, double *Linv,
-              double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch);
+// G = L L^T in place (lower triangle); Linv receives the inverses of L's
+// diagonal blocks (ceil(s / CHOL_NB) blocks of CHOL_NB^2 doubles, rows and
+// columns of dropped pivots zero), which trsm_coop reads.
+int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
+                  double rank_tol, SvDevInfo *info, int which, unsigned *flags,
+                  unsigned *epoch);
+// Y <- L^{-T} Y (s x K) with the factor and its block inverses.
+int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
+              const double *Linv, double *Y, const SvDevInfo *info, unsigned *flags,
+              unsigned *epoch);
 // mark the update failed on the device (every later kernel becomes a no-op)
 void set_status(hipStream_t st, SvDevInfo *info, int code);
 // reserve count + 1 barrier epochs; zero the flags first when close to wrap
