@@ -4,9 +4,11 @@
 // Equation (1)), each as one cooperative launch.  Blocks exchange data through
 // coherent (L2-bypassing) loads and stores and meet at flag barriers, so a
 // factorisation of s = 1000 costs two launches instead of ~150.
+#include <algorithm>
 #include <cstdlib>
 
 #include "common.hpp"
+#include "svlcov.h"
 #include "kernels.hpp"
 #include "lane.hpp"
 
@@ -412,72 +414,192 @@ k_chol_coop(int64_t s, double *__restrict__ A, int64_t ld, double tol,
 }
 
 // Y <- L^{-T} Y (Y is s x K row-major, K <= 128) with the factor and the
-// diagonal-block inverses, by block rows from the bottom.  Per block row b
-// every block forms Y_b = Linv_b^T Z_b redundantly; the rows above are
-// updated, Z_r -= L[b rows, r]^T Y_b, spread over the blocks (their current
-// values loaded before the block's barrier); one grid barrier; block 0 stores
-// Y_b.
+// diagonal-block inverses, by block rows from the bottom:
+//   Y_b = Linv_b^T (Z_b - sum_{r > b} L_rb^T Y_r).
+// Block 0 carries the sequential part one step ahead: having formed Y_b it
+// applies Y_b to the next block row itself (Z_{b-1} -= L_{b,b-1}^T Y_b), forms
+// Y_{b-1} and stores it, while the other blocks apply Y_b (published the step
+// before) to the rows further up, one 32-row tile at a time; one grid
+// barrier per block row.  Every product is on FP64 MFMA: an output tile of
+// 16 x 16 per wave and step (the block row's 32 x K output is 2 K / 16 of
+// them).  Dynamic LDS: Yb and Zb (32 x (K16 + 1) each, K16 = K rounded up to
+// 16), the L tile and the inverse (32 x 33 each).
+constexpr int TS_PAD = 1;
+
+__device__ __forceinline__ void trsm_tile_mul(const double *__restrict__ At, int lda,
+                                              const double *__restrict__ Bm, int ldb,
+                                              double *__restrict__ Out, int ldo, int K16,
+                                              bool subtract, int w, int lane) {
+  // Out[m][n] (+)= sum_p At[p][m] * Bm[p][n], m < 32, n < K16, p < 32
+  const int li = lane & 15, lk = lane >> 4;
+  const int ntile = 2 * (K16 / 16);
+  for (int t = w; t < ntile; t += CT / 64) {
+    const int m0 = 16 * (t & 1), n0 = 16 * (t >> 1);
+    cv_d4 acc = cv_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < NB; kk += 4)
+      acc = mfma64(At[(kk + lk) * lda + m0 + li], Bm[(kk + lk) * ldb + n0 + li], acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double *o = &Out[(m0 + lk + 4 * q) * ldo + n0 + li];
+      *o = subtract ? *o - acc[q] : acc[q];
+    }
+  }
+}
+
 __global__ void __launch_bounds__(CT)
 k_trsm_coop(int64_t s, int K, const double *__restrict__ L, int64_t ld,
             const double *__restrict__ Linv, double *__restrict__ Y,
             const SvDevInfo *__restrict__ info, unsigned *__restrict__ flags, unsigned epoch0) {
   if (info->status) return;
-  __shared__ double Zb[NB][129];
-  __shared__ double Yb[NB][129];
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double lc[CT / 64][NB];
+  extern __shared__ double tsm[];
+  const int K16 = (K + 15) / 16 * 16, ldy = K16 + TS_PAD;
+  double *Yb = tsm, *Zb = Yb + NB * ldy, *Lt = Zb + NB * ldy, *Li = Lt + NB * (NB + 1);
   const int P = gridDim.x, g = blockIdx.x, tid = threadIdx.x;
   const int w = tid >> 6, lane = tid & 63;
   const int64_t nblk = (s + NB - 1) / NB;
   unsigned ep = epoch0;
-  for (int64_t b = nblk - 1; b >= 0; --b) {
-    const int64_t b0 = b * NB;
-    const int nb = (int)((s - b0) < NB ? (s - b0) : NB);
-    for (int e = tid; e < NB * NB; e += CT) Li[e / NB][e % NB] = Linv[b * NB * NB + e];
-    for (int e = tid; e < NB * K; e += CT) {
-      const int i = e / K, c = e % K;
-      Zb[i][c] = i < nb ? ld_coh(&Y[(b0 + i) * K + c]) : 0.0;
-    }
+  const bool other = P == 1 || g >= 1;
+  const int Po = P > 1 ? P - 1 : 1, go = P > 1 ? g - 1 : 0;
+  auto rows_of = [&](int64_t blk) { return (int)((s - blk * NB) < NB ? (s - blk * NB) : NB); };
+  auto load_Li = [&](int64_t blk) {
+    for (int e = tid; e < NB * NB; e += CT) Li[(e / NB) * (NB + 1) + e % NB] = Linv[blk * NB * NB + e];
+  };
+  // Y_b = Linv_b^T Zb into Yb (Li loaded, all threads past a barrier since),
+  // stored to Y (block 0)
+  auto solve_block = [&](int64_t blk) {
+    const int nbk = rows_of(blk);
+    trsm_tile_mul(Li, NB + 1, Zb, ldy, Yb, ldy, K16, false, w, lane);
     __syncthreads();
-    for (int e = tid; e < NB * K; e += CT) {
-      const int i = e / K, c = e % K;
-      double v = 0.0;   // rows p >= nb of Li, Zb are zero
-#pragma unroll
-      for (int p = 0; p < NB; ++p) v += Li[p][i] * Zb[p][c];
-      Yb[i][c] = v;
+    for (int e = tid; e < nbk * K; e += CT)
+      st_coh(&Y[(blk * NB + e / K) * K + e % K], Yb[(e / K) * ldy + e % K]);
+  };
+  auto load_rows = [&](double *dst, int64_t blk) {
+    const int nbk = rows_of(blk);
+    for (int e = tid; e < NB * K16; e += CT) {
+      const int i = e / K16, c = e % K16;
+      dst[i * ldy + c] = (i < nbk && c < K) ? ld_coh(&Y[(blk * NB + i) * K + c]) : 0.0;
     }
-    // rows r < b0: 4 rows per pass (one wave each), lanes over the K columns
-    for (int64_t base = (int64_t)g * (CT / 64); base < b0; base += (int64_t)P * (CT / 64)) {
-      const int64_t r = base + w;
-      const bool act = r < b0;
-      double z0 = 0.0, z1 = 0.0;
-      if (act) {
-        if (lane < NB) lc[w][lane] = lane < nb ? L[(b0 + lane) * ld + r] : 0.0;
-        if (lane < K) z0 = ld_coh(&Y[r * K + lane]);
-        if (lane + 64 < K) z1 = ld_coh(&Y[r * K + lane + 64]);
-      }
-      __syncthreads();
-      if (act) {
-        double a0 = 0.0, a1 = 0.0;
-        const int c0 = lane < K ? lane : 0, c1 = lane + 64 < K ? lane + 64 : 0;
-#pragma unroll
-        for (int p = 0; p < NB; ++p) {   // lc[w][p] = 0 for p >= nb
-          const double l = lc[w][p];
-          a0 += l * Yb[p][c0];
-          a1 += l * Yb[p][c1];
-        }
-        if (lane < K) st_coh(&Y[r * K + lane], z0 - a0);
-        if (lane + 64 < K) st_coh(&Y[r * K + lane + 64], z1 - a1);
-      }
-      __syncthreads();
+  };
+  // the L tile of block rows (rb) and block columns (cb): Lt[p][m] = L[rb*NB+p][cb*NB+m]
+  auto load_L = [&](int64_t rb, int64_t cb) {
+    const int nr = rows_of(rb), nc = rows_of(cb);
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int p_ = e / NB, m = e % NB;
+      Lt[p_ * (NB + 1) + m] = (p_ < nr && m < nc) ? L[(rb * NB + p_) * ld + cb * NB + m] : 0.0;
     }
+  };
+
+  // prologue: block 0 solves the last block row
+  if (g == 0) {
+    load_rows(Zb, nblk - 1);
+    load_Li(nblk - 1);
     __syncthreads();
-    flag_barrier(flags, ++ep);
-    // every block has read Z_b: block 0 may now store Y_b over it
-    if (g == 0)
-      for (int e = tid; e < nb * K; e += CT) st_coh(&Y[(b0 + e / K) * K + e % K], Yb[e / K][e % K]);
-    __syncthreads();
+    solve_block(nblk - 1);
   }
+  flag_barrier(flags, ++ep);
+  for (int64_t b = nblk - 1; b >= 1; --b) {
+    if (other && b >= 2) {
+      // the rows of block rows 0 .. b-2 take Y_b (stored the step before;
+      // block 0, alone, still holds it in Yb, so this part comes first)
+      bool have = false;
+      for (int64_t x = go; x <= b - 2; x += Po) {
+        if (!have) {
+          if (g != 0) load_rows(Yb, b);
+          have = true;
+        }
+        load_rows(Zb, x);
+        load_L(b, x);
+        __syncthreads();
+        trsm_tile_mul(Lt, NB + 1, Yb, ldy, Zb, ldy, K16, true, w, lane);
+        __syncthreads();
+        const int nx = rows_of(x);
+        for (int e = tid; e < nx * K; e += CT)
+          st_coh(&Y[(x * NB + e / K) * K + e % K], Zb[(e / K) * ldy + e % K]);
+        __syncthreads();
+      }
+    }
+    if (g == 0) {
+      // Z_{b-1} -= L_{b,b-1}^T Y_b (Yb holds Y_b), then Y_{b-1}
+      load_rows(Zb, b - 1);
+      load_L(b, b - 1);
+      load_Li(b - 1);
+      __syncthreads();
+      trsm_tile_mul(Lt, NB + 1, Yb, ldy, Zb, ldy, K16, true, w, lane);
+      __syncthreads();
+      solve_block(b - 1);
+    }
+    flag_barrier(flags, ++ep);
+  }
+}
+
+// The same solve with one block per block row (up to 256 block rows) and
+// point-to-point readiness flags instead of grid barriers: block x keeps its
+// rows' Z_x in LDS, applies each Y_b (b > x, newest last) as soon as block b
+// has flagged it (L_{b,x} is loaded ahead, Y_b by coherent loads), then forms
+// Y_x = Linv_x^T Z_x, stores it and raises its own flag.  Block nblk - 1
+// waits for nobody and block x only for blocks above it, so every wait ends;
+// a wait that exceeds its spin limit marks the update failed and the block
+// stops, and its own flag is still raised so that nothing waits for it.
+__global__ void __launch_bounds__(CT)
+k_trsm_p2p(int64_t s, int K, const double *__restrict__ L, int64_t ld,
+           const double *__restrict__ Linv, double *__restrict__ Y, SvDevInfo *__restrict__ info,
+           unsigned *__restrict__ flags, unsigned epoch) {
+  if (info->status) return;
+  extern __shared__ double tsm[];
+  const int K16 = (K + 15) / 16 * 16, ldy = K16 + TS_PAD;
+  double *Yb = tsm, *Zb = Yb + NB * ldy, *Lt = Zb + NB * ldy, *Li = Lt + NB * (NB + 1);
+  __shared__ int bad;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int64_t nblk = (s + NB - 1) / NB, x = blockIdx.x;
+  auto rows_of = [&](int64_t blk) { return (int)((s - blk * NB) < NB ? (s - blk * NB) : NB); };
+  const int nx = rows_of(x);
+  if (tid == 0) bad = 0;
+  for (int e = tid; e < NB * K16; e += CT) {
+    const int i = e / K16, c = e % K16;
+    Zb[i * ldy + c] = (i < nx && c < K) ? Y[(x * NB + i) * K + c] : 0.0;
+  }
+  for (int e = tid; e < NB * NB; e += CT) Li[(e / NB) * (NB + 1) + e % NB] = Linv[x * NB * NB + e];
+  for (int64_t b = nblk - 1; b > x; --b) {
+    const int nr = rows_of(b);
+    __syncthreads();   // the previous product has consumed Lt and Yb
+    for (int e = tid; e < NB * NB; e += CT) {
+      const int p_ = e / NB, m = e % NB;
+      Lt[p_ * (NB + 1) + m] = (p_ < nr && m < nx) ? L[(b * NB + p_) * ld + x * NB + m] : 0.0;
+    }
+    if (tid == 0) {
+      unsigned spins = 0;
+      while (__hip_atomic_load(&flags[b * FLAG_STRIDE], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1u << 26)) { bad = 1; break; }
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    for (int e = tid; e < NB * K16; e += CT) {
+      const int i = e / K16, c = e % K16;
+      Yb[i * ldy + c] = (i < nr && c < K) ? ld_coh(&Y[(b * NB + i) * K + c]) : 0.0;
+    }
+    __syncthreads();
+    trsm_tile_mul(Lt, NB + 1, Yb, ldy, Zb, ldy, K16, true, w, lane);
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) {
+      atomicCAS(&info->status, 0, (int)SVLCOV_E_DEVICE);
+      __hip_atomic_store(&flags[x * FLAG_STRIDE], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  trsm_tile_mul(Li, NB + 1, Zb, ldy, Yb, ldy, K16, false, w, lane);
+  __syncthreads();
+  for (int e = tid; e < nx * K; e += CT)
+    st_coh(&Y[(x * NB + e / K) * K + e % K], Yb[(e / K) * ldy + e % K]);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0)
+    __hip_atomic_store(&flags[x * FLAG_STRIDE], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void k_set_status(SvDevInfo *info, int code) {
@@ -556,13 +678,58 @@ int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv
 int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, const double *Linv,
               double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
+  if (K <= 0 || K > 128) return -3;
+  static bool once = false;
+  if (!once) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_coop),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    once = true;
+  }
   const int64_t nblk = (s + NB - 1) / NB;
-  const int P = coop_blocks(reinterpret_cast<const void *>(k_trsm_coop), coop_want(s));
-  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)nblk);
+  const int K16 = (K + 15) / 16 * 16;
+  const size_t sh = (size_t)(2 * NB * (K16 + TS_PAD) + 2 * NB * (NB + 1)) * sizeof(double);
+  static bool once_p = false;
+  if (!once_p) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_p2p),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipGetLastError();
+    once_p = true;
+  }
+  {
+    // one block per block row, all resident at once (cooperative launch)
+    int nbp = 0, ncu = 0, dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nbp, reinterpret_cast<const void *>(k_trsm_p2p), CT, sh);
+    (void)hipGetLastError();
+    if (nblk <= svl::TRI_MAX_BLOCKS && nblk <= (int64_t)nbp * ncu) {
+      unsigned e0 = take_epochs(st, flags, epoch, 1u);
+      unsigned ready = e0 + 1u;
+      SvDevInfo *inf = const_cast<SvDevInfo *>(info);
+      void *args[] = {(void *)&s, (void *)&K, (void *)&L, (void *)&ld, (void *)&Linv,
+                      (void *)&Y, (void *)&inf, (void *)&flags, (void *)&ready};
+      return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_trsm_p2p),
+                                        dim3((unsigned)nblk), dim3(CT), args, sh, st) == hipSuccess
+                 ? 0 : -3;
+    }
+  }
+  // block 0 and one block per remaining block row at most
+  int want = (int)std::min<int64_t>(nblk, 256);
+  int nb = 0, ncu = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(k_trsm_coop),
+                                                     CT, sh);
+  (void)hipGetLastError();
+  const int lim = std::max(1, std::min(nb * std::max(ncu, 1), svl::TRI_MAX_BLOCKS));
+  const int P = std::max(1, std::min(want, lim));
+  unsigned e0 = take_epochs(st, flags, epoch, (unsigned)nblk + 1u);
   void *args[] = {(void *)&s, (void *)&K, (void *)&L, (void *)&ld, (void *)&Linv,
                   (void *)&Y, (void *)&info, (void *)&flags, (void *)&e0};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_trsm_coop), dim3(P),
-                                    dim3(CT), args, 0, st) == hipSuccess ? 0 : -3;
+                                    dim3(CT), args, sh, st) == hipSuccess ? 0 : -3;
 }
 
 }  // namespace svl
