@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--inflight", type=int, default=64, help="stream workload: server slots")
     ap.add_argument("--fused", type=int, default=128,
                     help="stream workload: requests in the fused-projection measurement")
+    ap.add_argument("--gate-matrices", type=int, default=3,
+                    help="stream workload: matrices checked against the oracle and alone")
     ap.add_argument("--fused-only", action="store_true",
                     help="stream workload: only the fused-projection measurement (for counters)")
     ap.add_argument("--k", type=int, default=0, help="rank of the graph workload (default 64)")
@@ -682,15 +684,23 @@ def run_sweep(args):
 
 
 def run_stream(args):
-    """Streaming batch: independent matrices resident on the GPU, row-append
-    requests of 10..2000 rows on uniformly chosen matrices, all submitted to
-    the request server at once (saturation); throughput over the whole batch
-    and per-request latency from submit to completion.  The same requests
-    run again with one slot (no overlap) for comparison."""
+    """Streaming batch: independent matrices resident on the GPU and
+    row-append requests of 10..2000 rows on uniformly chosen matrices, served
+    by the request server.  Capacity: all requests submitted at once
+    (saturation), throughput over the whole batch; the same requests with one
+    slot (no overlap) for comparison.  Then Poisson arrivals at 50 / 80 / 100 %
+    of the measured capacity (requests per second), each request submitted at
+    its arrival time, latency from arrival to completion (p50 / p99).  Gate:
+    for the matrices whose updates the oracle replays fastest, the factors
+    after the saturated run are compared with the same requests applied to the
+    same start alone (no server, no other matrices) and with O1 run from that
+    start; the oracle's time on them is the CPU baseline."""
     import numpy as np
     import torch
     import paper_2401_09703_amd as L
+    from oracle import metrics, zha_simon
     from synth import config5_stream
+    from synth.sparse import CSR
     mats, reqs = config5_stream(n_mat=args.matrices, requests=args.requests)
     prec = (args.modes or "bf16x3").split(",")[0]
     t = time.time()
@@ -701,13 +711,22 @@ def run_stream(args):
         dev_reqs.append(L.DeviceCSR(rq["s"], md["n"], rp, ci, v))
     torch.cuda.synchronize()
     nnz = sum(int(d.col_idx.numel()) for d in dev_reqs)
+    rows = sum(rq["s"] for rq in reqs)
     log(f"[bench] stream: {len(mats)} matrices, {len(reqs)} requests, {nnz} update nonzeros "
         f"generated in {time.time() - t:.1f}s")
     growth = {}
     for rq in reqs:
         growth[rq["mat"]] = growth.get(rq["mat"], 0) + rq["s"]
-    out_runs = {}
-    for slots in (args.inflight, 1):
+    by_mat = {}
+    for j, rq in enumerate(reqs):
+        by_mat.setdefault(rq["mat"], []).append(j)
+    # gate sample: the matrices cheapest for O1 (dense QR of the n x s residual)
+    cost = {i: sum(mats[i]["n"] * reqs[j]["s"] ** 2 + mats[i]["m"] * mats[i]["k"] * reqs[j]["s"]
+                   for j in js) for i, js in by_mat.items()}
+    # matrices with several requests first (they check the order of a sequence)
+    gate_mats = sorted(cost, key=lambda i: (len(by_mat[i]) < 2, cost[i]))[:args.gate_matrices]
+
+    def make_states():
         t = time.time()
         states = []
         for i, md in enumerate(mats):
@@ -723,39 +742,127 @@ def run_stream(args):
                                          validate_device_inputs=False))
         torch.cuda.synchronize()
         log(f"[bench] stream: {len(states)} states initialised in {time.time() - t:.1f}s")
-        if slots == args.inflight and args.fused > 0:
-            fused = measure_fused_projection(L, torch, np, states, mats, reqs, dev_reqs,
-                                             args.fused)
-            log(f"[bench] fused projection: {fused}")
-            if args.fused_only:
-                for st in states:
-                    st.close()
-                print(json.dumps({"fused_projection": fused}), flush=True)
-                return
+        return states
+
+    def serve(states, slots, arrivals=None):
+        """Run every request through a server with `slots` in flight; with
+        arrivals (seconds from the start) each request is submitted at its
+        arrival time and its latency counts from there."""
         srv = L.Server(max_inflight=slots, workspace_budget=32 << 30)
         ids = [srv.attach(st) for st in states]
         torch.cuda.synchronize()
+        late = np.zeros(len(reqs))
         t0 = time.perf_counter()
-        tickets = [srv.submit(ids[rq["mat"]], ("rows", dev_reqs[j])) for j, rq in enumerate(reqs)]
+        tickets = []
+        for j, rq in enumerate(reqs):
+            if arrivals is not None:
+                while True:
+                    now = time.perf_counter() - t0
+                    if now >= arrivals[j]:
+                        break
+                    if arrivals[j] - now > 2e-3:
+                        time.sleep(min(arrivals[j] - now - 1e-3, 0.05))
+                late[j] = (time.perf_counter() - t0) - arrivals[j]
+            tickets.append(srv.submit(ids[rq["mat"]], ("rows", dev_reqs[j])))
         res = [srv.wait(tk) for tk in tickets]
         srv.drain()
         t1 = time.perf_counter()
         stats = srv.stats()
         srv.close()
+        bad = [c for c, _ in res if c != 0]
+        lat = np.array([l for _, l in res]) + 1e3 * late
+        return dict(rows_per_s=rows / (t1 - t0), requests_per_s=len(reqs) / (t1 - t0),
+                    wall_s=t1 - t0, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), failed=len(bad),
+                    peak_inflight=stats["peak_inflight"],
+                    peak_workspace_gb=stats["peak_workspace_bytes"] / 2 ** 30,
+                    max_submit_lateness_ms=float(1e3 * late.max()))
+
+    out_runs = {}
+    fused = None
+    gate = {}
+    cpu = None
+    # saturated, with the gate matrices' start and end factors kept
+    states = make_states()
+    if args.fused > 0:
+        fused = measure_fused_projection(L, torch, np, states, mats, reqs, dev_reqs, args.fused)
+        log(f"[bench] fused projection: {fused}")
+        if args.fused_only:
+            for st in states:
+                st.close()
+            print(json.dumps({"fused_projection": fused}), flush=True)
+            return
+    start = {i: states[i].factors() for i in gate_mats}
+    out_runs[f"saturated, slots={args.inflight}"] = serve(states, args.inflight)
+    mix = {i: states[i].factors() for i in gate_mats}
+    for st in states:
+        st.close()
+    head = out_runs[f"saturated, slots={args.inflight}"]
+    log(f"[bench] stream saturated: {head}")
+    # the gate: alone (same requests, no server) and the oracle
+    host_req = {}
+    for i in gate_mats:
+        for j in by_mat[i]:
+            d = dev_reqs[j]
+            host_req[j] = CSR(d.rows, d.cols, d.row_ptr.cpu().numpy().astype(np.int64),
+                              d.col_idx.cpu().numpy().astype(np.int32),
+                              d.val.cpu().numpy().astype(np.float64))
+    cpu_s, cpu_rows = 0.0, 0
+    for i in gate_mats:
+        U0, s0, V0 = start[i]
+        alone = L.TruncatedSVD(U0, s0, V0, precision=prec,
+                               row_capacity=U0.shape[0] + growth.get(i, 0) + 16)
+        for j in by_mat[i]:
+            alone.add_rows(host_req[j])
+        alone.sync()
+        Ua, sa, Va = alone.factors()
+        alone.close()
+        Um, sm, Vm = mix[i]
+        t = time.perf_counter()
+        Ur, sr, Vr = U0, s0, V0
+        for j in by_mat[i]:
+            Ur, sr, Vr, info = zha_simon.add_rows(Ur, sr, Vr, host_req[j])
+        cpu_s += time.perf_counter() - t
+        cpu_rows += sum(reqs[j]["s"] for j in by_mat[i])
+        r = metrics.compare((Um, sm, Vm), (Ur, sr, Vr), info["theta_hat"], 1e-3)
+        ra = metrics.compare((Um, sm, Vm), (Ua, sa, Va), info["theta_hat"], 1e-3)
+        gate[f"matrix {i}"] = dict(
+            requests=len(by_mat[i]), rows=sum(reqs[j]["s"] for j in by_mat[i]),
+            sigma_rel=r["sigma_rel"], angle_U=r["angle_U"], angle_V=r["angle_V"],
+            jstar=r["jstar"],
+            vs_alone=dict(sigma_rel=ra["sigma_rel"], angle_U=ra["angle_U"],
+                          angle_V=ra["angle_V"]))
+        log(f"[bench] stream gate matrix {i}: {gate[f'matrix {i}']}")
+    gate_ok = all(g["sigma_rel"] <= 1e-5 and g["vs_alone"]["sigma_rel"] <= 1e-5
+                  for g in gate.values()) if gate else None
+    if cpu_s > 0:
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count()
+        cpu = dict(value=cpu_rows / cpu_s, unit="update rows/s", cores=int(cores), kind="oracle",
+                   sample=f"O1 on the gate sample: {len(gate_mats)} matrices, {cpu_rows} update "
+                          f"rows, {cpu_s:.1f} s wall")
+    # one slot (no overlap) and Poisson arrivals at fractions of the capacity
+    states = make_states()
+    out_runs["saturated, slots=1"] = serve(states, 1)
+    for st in states:
+        st.close()
+    log(f"[bench] stream one slot: {out_runs['saturated, slots=1']}")
+    cap = head["requests_per_s"]
+    for frac in (0.5, 0.8, 1.0):
+        rng = np.random.default_rng(int(frac * 1000) + 5)
+        arrivals = np.cumsum(rng.exponential(1.0 / (frac * cap), size=len(reqs)))
+        states = make_states()
+        rr = serve(states, args.inflight, arrivals)
         for st in states:
             st.close()
-        bad = [c for c, _ in res if c != 0]
-        lat = np.array([l for _, l in res])
-        rows = sum(rq["s"] for rq in reqs)
-        out_runs[slots] = dict(rows_per_s=rows / (t1 - t0), requests_per_s=len(reqs) / (t1 - t0),
-                               wall_s=t1 - t0, p50_ms=float(np.percentile(lat, 50)),
-                               p99_ms=float(np.percentile(lat, 99)), failed=len(bad),
-                               peak_inflight=stats["peak_inflight"],
-                               peak_workspace_gb=stats["peak_workspace_bytes"] / 2 ** 30)
-        log(f"[bench] stream slots={slots}: {out_runs[slots]}")
-    head = out_runs[args.inflight]
+        rr["offered_requests_per_s"] = frac * cap
+        out_runs[f"poisson {int(100 * frac)}%"] = rr
+        log(f"[bench] stream Poisson {int(100 * frac)}% of capacity: {rr}")
     fused_roof = None
-    if args.fused > 0:
+    if fused is not None:
         fused_roof = dict(kernel="k_spmm_batch", bound="hbm", achieved=fused["achieved_GBs"],
                           peak=HBM_PEAK_GBS, unit="GB/s", frac=fused["frac"],
                           traffic=stored_traffic("fused", f"requests={fused['requests']}"),
@@ -764,7 +871,7 @@ def run_stream(args):
     out = {
         "metric": "update rows/s (streaming batch of row-append requests, continuous batching); "
                   "p50/p99 request latency",
-        "value": head["rows_per_s"] if head["failed"] == 0 else 0.0,
+        "value": head["rows_per_s"] if head["failed"] == 0 and gate_ok is not False else 0.0,
         "unit": "update rows/s",
         "n_gpus": 1, "steps": len(reqs), "warmup": 0,
         "ms_per_step": 1e3 * head["wall_s"] / len(reqs),
@@ -772,12 +879,14 @@ def run_stream(args):
         "dtype": prec, "data": "synthetic",
         "config": {"workload": f"streaming batch: {len(mats)} matrices (rows 5k-200k, cols "
                                f"1k-50k, density 0.05-1%, k in 16/32/64), {len(reqs)} row-append "
-                               "requests of 10-2000 rows, all submitted at once",
+                               "requests of 10-2000 rows; capacity with all submitted at once, "
+                               "then Poisson arrivals at 50/80/100% of it",
                    "parallelism": "single GPU", "slots": args.inflight},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "requests_per_s": head["requests_per_s"],
-        "runs": {f"slots={k}": v for k, v in out_runs.items()},
-        "roofline": fused_roof, "cpu_baseline": None,
+        "runs": out_runs,
+        "gate": gate, "gate_ok": gate_ok,
+        "roofline": fused_roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 

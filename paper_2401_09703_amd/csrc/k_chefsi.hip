@@ -195,11 +195,10 @@ namespace svl {
 // step on some updates).  SVLCOV_CHEFSI_P overrides it for tuning sweeps (a
 // multiple of 16 in (k, 128]).
 int chefsi_block(int k) {
-  static int forced = -1;
-  if (forced < 0) {
-    forced = 0;
-    if (const char *ev = getenv("SVLCOV_CHEFSI_P")) forced = atoi(ev);
-  }
+  static const int forced = [] {
+    const char *ev = getenv("SVLCOV_CHEFSI_P");
+    return ev ? atoi(ev) : 0;
+  }();
   if (forced > k && forced <= 128 && forced % 16 == 0) return forced;
   const int p = (k + 32 + 15) / 16 * 16;
   return p < 128 ? p : 128;

@@ -622,13 +622,12 @@ int coop_want(int64_t s) {
 }
 
 int coop_blocks(const void *fn, int want) {
-  static int ncu = 0;
-  if (ncu == 0) {
-    int dev = 0;
+  static const int ncu = [] {
+    int dev = 0, n = 0;
     (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu <= 0) ncu = 1;
-  }
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    return n > 0 ? n : 1;
+  }();
   int nb = 0;
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, CT, 0);
   (void)hipGetLastError();
@@ -679,23 +678,25 @@ int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, con
               double *Y, const SvDevInfo *info, unsigned *flags, unsigned *epoch) {
   if (s <= 0) return 0;
   if (K <= 0 || K > 128) return -3;
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_coop),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
-    once = true;
-  }
+    return true;
+  }();
+  (void)once;
   const int64_t nblk = (s + NB - 1) / NB;
   const int K16 = (K + 15) / 16 * 16;
   const size_t sh = (size_t)(2 * NB * (K16 + TS_PAD) + 2 * NB * (NB + 1)) * sizeof(double);
-  static bool once_p = false;
-  if (!once_p) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once_p = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_trsm_p2p),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
-    once_p = true;
-  }
+    return true;
+  }();
+  (void)once_p;
   {
     // one block per block row, all resident at once (cooperative launch)
     int nbp = 0, ncu = 0, dev = 0;

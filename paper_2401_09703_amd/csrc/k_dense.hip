@@ -994,12 +994,13 @@ void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, doubl
   const int64_t nt = (s + 63) / 64;
   const unsigned tiles = (unsigned)(nt * (nt + 1) / 2);
   constexpr int KP = 128 + 8;
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     allow_big_lds(k_gram_lowp<1>); allow_big_lds(k_gram_lowp<2>);
     (void)hipGetLastError();
-    once = true;
-  }
+    return true;
+  }();
+  (void)once;
   if (mode == 1) {
     const size_t sh = 2 * 64 * KP * sizeof(float);
     hipLaunchKernelGGL((k_gram_lowp<1>), dim3(tiles), dim3(256), sh, st, s, K, C, G, ldg, info);
@@ -1061,13 +1062,14 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
   if (complete)
     hipLaunchKernelGGL(k_fill_random_rows, dim3(K), dim3(256), 0, st, K, N, X, complete, seed,
                        info);
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     allow_big_lds(k_chol_inv_small);
     allow_big_lds(k_chol_small);
     (void)hipGetLastError();
-    once = true;
-  }
+    return true;
+  }();
+  (void)once;
   // One Cholesky QR pass: the rows come in orthonormal to a few ulps (or, for
   // completion rows, as random vectors far from the span of the others), and
   // the orthogonality CholQR leaves is ~ u kappa^2 with kappa ~ 1 here.

@@ -453,13 +453,14 @@ size_t eig_work_doubles(int64_t N, int k) {
 void eig_bisect(hipStream_t st, int64_t N, int k, double *lam, double *work,
                 const SvDevInfo *info) {
   const double *d = work, *e = work + N;
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_bisect),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
-    once = true;
-  }
+    return true;
+  }();
+  (void)once;
   hipLaunchKernelGGL(k_bisect, dim3(k), dim3(BIS_NT), (size_t)2 * N * sizeof(double), st,
                      (int)N, d, e, k, lam, info);
 }
@@ -468,13 +469,14 @@ void eig_stein(hipStream_t st, int64_t N, int k, const double *lam, double *Fv, 
                const SvDevInfo *info) {
   const double *d = work, *e = work + N;
   double *scratch = work + 7 * N;
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_stein<true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipGetLastError();
-    once = true;
-  }
+    return true;
+  }();
+  (void)once;
   const size_t sh = (size_t)N * 6 * sizeof(double) + (size_t)N * sizeof(int) + 64;
   if (sh <= (size_t)150 * 1024)
     hipLaunchKernelGGL((k_stein<true>), dim3(k), dim3(64), sh, st, (int)N, d, e, k, lam, Fv,

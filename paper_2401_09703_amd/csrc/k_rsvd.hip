@@ -871,18 +871,20 @@ void ts_mul_lt(hipStream_t st, int64_t R, int L, const double *X, const double *
 
 void chol_drop_if(hipStream_t st, int L, const double *G, double *Out, int32_t *complete,
                   double rtol, const SvDevInfo *info, const int32_t *need) {
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     allow_big_lds(k_chol_drop);
     (void)hipGetLastError();
-    once = true;
-  }
-  static bool once_b = false;
-  if (!once_b) {
+    return true;
+  }();
+  (void)once;
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once_b = [] {
     allow_big_lds(k_chol_drop_blk);
     (void)hipGetLastError();
-    once_b = true;
-  }
+    return true;
+  }();
+  (void)once_b;
   if (L % 16 == 0 && L <= 128) {
     const size_t shb = ((size_t)L * (L + 3) + (size_t)CB_NW * 16 * 17) * sizeof(double) +
                        (size_t)L * sizeof(int);

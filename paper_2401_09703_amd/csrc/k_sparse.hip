@@ -764,13 +764,14 @@ void sparse_gram(hipStream_t st, int64_t s, int64_t cols, int64_t nnz, const int
   }
   hipLaunchKernelGGL(k_row_ids, dim3((unsigned)((s + 3) / 4)), dim3(256), 0, st, s, rp, rid,
                      info);
-  static bool once = false;
-  if (!once) {
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const bool once = [] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_sparse_gram),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 112 * 1024);
     (void)hipGetLastError();
-    once = true;
-  }
+    return true;
+  }();
+  (void)once;
   const unsigned blocks = (unsigned)((s + 1) / 2);
   hipLaunchKernelGGL(k_sparse_gram, dim3(blocks), dim3(256), (size_t)s * sizeof(double), st, s,
                      rp, ci, rid, v, vdt, S, lds, info);

@@ -483,20 +483,19 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
     return hipGetLastError() == hipSuccess ? 0 : -3;
   }
   if (N <= TRI_SMALL_N) {   // one block, the matrix in LDS
-    static bool small_once = false;
-    if (!small_once) {
+    // thread-safe one-time set-up (dispatch may run on several host threads)
+    static const bool small_once = [] {
       (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_tridiag_small),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       (void)hipGetLastError();
-      small_once = true;
-    }
+      return true;
+    }();
+    (void)small_once;
     const size_t sh = ((size_t)N * (N + 1) + 5 * N) * sizeof(double);
     hipLaunchKernelGGL(k_tridiag_small, dim3(1), dim3(TRI_SMALL_NT), sh, st, N, A, N64, d, e,
                        tau, info);
     return hipGetLastError() == hipSuccess ? 0 : -3;
   }
-  static int ncu = 0;
-  static bool once = false;
   // block widths: 256 threads, or one wave per owned row (5..8 waves) when
   // the rows live in LDS, so that no wave carries two rows
   static const void *const fns_lds[5] = {
@@ -506,19 +505,20 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
       reinterpret_cast<const void *>(k_tridiag<true, 448>),
       reinterpret_cast<const void *>(k_tridiag<true, 512>)};
   static const void *const fn_mem = reinterpret_cast<const void *>(k_tridiag<false, 256>);
-  if (!once) {
-    int dev = 0;
+  // thread-safe one-time set-up (dispatch may run on several host threads)
+  static const int ncu = [] {
+    int dev = 0, n = 0;
     (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (ncu <= 0) ncu = 1;
-    if (ncu > TRI_MAX_BLOCKS) ncu = TRI_MAX_BLOCKS;
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n <= 0) n = 1;
+    if (n > TRI_MAX_BLOCKS) n = TRI_MAX_BLOCKS;
     const int lim = 160 * 1024;
     for (const void *f : fns_lds)
       (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipFuncSetAttribute(fn_mem, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     (void)hipGetLastError();
-    once = true;
-  }
+    return n;
+  }();
   // block count G: one block per 8 rows from N = 512 while those 8 rows and
   // the three work vectors fit in LDS, else one per 4 rows (measured on
   // MI355X: at N = 1064, 133 blocks of 8 rows beat 266 of 4 by 5 %, fewer

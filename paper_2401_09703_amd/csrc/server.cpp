@@ -103,8 +103,15 @@ struct svlcov_server {
   size_t inflight_bytes = 0;
   bool stop = false;
   std::thread worker;
+  // admitted requests are enqueued by a pool of dispatch threads: an update
+  // waits on the host where it reads the subspace iteration's control
+  // scalars, and one thread would serialise the requests there
+  std::vector<std::thread> dispatchers;
+  std::deque<Req *> to_dispatch;
+  std::condition_variable cv_disp;
   hipEvent_t coop_chain = nullptr;
   bool coop_live = false;
+  std::mutex coop_mu;
   svlcov_server_stats stats{};
   // fused projections: the server's stream, the descriptor table (pinned
   // staging and device copy) and the timing events of each fused launch
@@ -271,8 +278,26 @@ void dispatch(svlcov_server *srv, Req *r) {
     complete(srv, r, st);
     return;
   }
-  std::lock_guard<std::mutex> lk(srv->mu);
-  srv->inflight.push_back(r);
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->inflight.push_back(r);
+  }
+  srv->cv_work.notify_one();
+}
+
+void dispatch_loop(svlcov_server *srv) {
+  (void)hipSetDevice(srv->device);
+  for (;;) {
+    Req *r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(srv->mu);
+      srv->cv_disp.wait(lk, [&] { return srv->stop || !srv->to_dispatch.empty(); });
+      if (srv->to_dispatch.empty()) break;   // stop, and nothing left
+      r = srv->to_dispatch.front();
+      srv->to_dispatch.pop_front();
+    }
+    dispatch(srv, r);
+  }
 }
 
 void worker_loop(svlcov_server *srv) {
@@ -283,14 +308,21 @@ void worker_loop(svlcov_server *srv) {
     {
       std::unique_lock<std::mutex> lk(srv->mu);
       if (srv->pending.empty() && srv->inflight.empty()) {
-        if (srv->stop) break;
-        srv->cv_work.wait(lk, [&] { return srv->stop || !srv->pending.empty(); });
-        if (srv->stop && srv->pending.empty()) break;
+        if (srv->stop && srv->stats.completed == srv->stats.submitted) break;
+        // new requests, or a dispatched one that now awaits completion
+        srv->cv_work.wait_for(lk, std::chrono::milliseconds(5), [&] {
+          return srv->stop || !srv->pending.empty() || !srv->inflight.empty();
+        });
+        if (srv->stop && srv->pending.empty() && srv->inflight.empty() &&
+            srv->stats.completed == srv->stats.submitted)
+          break;
       }
       // admission in arrival order; a matrix whose earlier request waits
       // blocks its later ones
       blocked.assign(srv->mats.size(), 0);
-      size_t nin = srv->inflight.size();
+      // admitted and not completed: in flight, or still being dispatched
+      size_t nin = 0;
+      for (const Slot &sl : srv->slots) nin += sl.busy ? 1 : 0;
       for (auto it = srv->pending.begin(); it != srv->pending.end();) {
         Req *r = *it;
         Mat &m = srv->mats[r->mid];
@@ -326,13 +358,23 @@ void worker_loop(svlcov_server *srv) {
         srv->stats.peak_workspace_bytes = (int64_t)srv->inflight_bytes;
     }
     if (!admit.empty()) fuse_projections(srv, admit);
-    for (Req *r : admit) {
-      if (!r->done && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) {
-        r->done = nullptr;
-        complete(srv, r, SVLCOV_E_DEVICE);
-        continue;
+    {
+      std::vector<Req *> ready;
+      for (Req *r : admit) {
+        if (!r->done && hipEventCreateWithFlags(&r->done, hipEventDisableTiming) != hipSuccess) {
+          r->done = nullptr;
+          complete(srv, r, SVLCOV_E_DEVICE);
+          continue;
+        }
+        ready.push_back(r);
       }
-      dispatch(srv, r);
+      if (!ready.empty()) {
+        {
+          std::lock_guard<std::mutex> lk(srv->mu);
+          for (Req *r : ready) srv->to_dispatch.push_back(r);
+        }
+        srv->cv_disp.notify_all();
+      }
     }
     // completions
     std::vector<Req *> finished;
@@ -389,6 +431,8 @@ svlcov_status svlcov_server_create(svlcov_server **out, const svlcov_server_opti
     return SVLCOV_E_DEVICE;
   }
   srv->worker = std::thread(worker_loop, srv);
+  const int nd = o.max_inflight < 16 ? o.max_inflight : 16;
+  for (int q = 0; q < nd; ++q) srv->dispatchers.emplace_back(dispatch_loop, srv);
   *out = srv;
   return SVLCOV_OK;
 }
@@ -405,6 +449,7 @@ svlcov_status svlcov_server_attach(svlcov_server *srv, svlcov_state *h, int32_t 
   (void)hipStreamSynchronize(h->stream);
   h->coop_chain = &srv->coop_chain;
   h->coop_chain_live = &srv->coop_live;
+  h->coop_mu = &srv->coop_mu;
   *matrix_id = (int32_t)srv->mats.size();
   srv->mats.push_back(Mat{h, false});
   return SVLCOV_OK;
@@ -501,12 +546,16 @@ void svlcov_server_destroy(svlcov_server *srv) {
     srv->stop = true;
   }
   srv->cv_work.notify_all();
+  srv->cv_disp.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
+  for (std::thread &t : srv->dispatchers)
+    if (t.joinable()) t.join();
   (void)hipSetDevice(srv->device);
   for (Mat &m : srv->mats) {
     if (m.h->stream) (void)hipStreamSynchronize(m.h->stream);
     m.h->coop_chain = nullptr;
     m.h->coop_chain_live = nullptr;
+    m.h->coop_mu = nullptr;
   }
   for (Slot &s : srv->slots) {
     if (s.ws.p) (void)hipFree(s.ws.p);

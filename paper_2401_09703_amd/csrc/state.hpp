@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "../../include/svlcov.h"
@@ -75,9 +76,11 @@ struct svlcov_state {
   // Set while a request server drives the state: every cooperative launch
   // first waits for *coop_chain and then re-records it, so that cooperative
   // kernels of different matrices never run at the same time (each needs all
-  // of its blocks resident at once).
+  // of its blocks resident at once).  The server dispatches from several host
+  // threads, so the wait, the launch and the re-record hold *coop_mu.
   hipEvent_t *coop_chain = nullptr;
   bool *coop_chain_live = nullptr;
+  std::mutex *coop_mu = nullptr;
   // Set by a request server for the next update only: the projection of
   // side q (C', its FP32 copy and the row norms) is already in the lent
   // workspace, written by a fused multi-request launch.
@@ -115,6 +118,7 @@ inline void release(svlcov_state *h, DevBuf &b) {
 
 // Cooperative-launch ordering hooks (no-ops unless a server drives the state).
 inline void coop_enter(svlcov_state *h) {
+  if (h->coop_mu) h->coop_mu->lock();
   if (h->coop_chain && *h->coop_chain_live) (void)hipStreamWaitEvent(h->stream, *h->coop_chain, 0);
 }
 inline void coop_exit(svlcov_state *h) {
@@ -122,4 +126,5 @@ inline void coop_exit(svlcov_state *h) {
     (void)hipEventRecord(*h->coop_chain, h->stream);
     *h->coop_chain_live = true;
   }
+  if (h->coop_mu) h->coop_mu->unlock();
 }
