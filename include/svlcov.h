@@ -114,11 +114,17 @@ typedef struct {
    * dev_free releases a block from dev_alloc; work already enqueued on
    * `stream` may still use it, so it may be reused only by work ordered
    * after that (a stream-ordered caching allocator satisfies this).  Both are
-   * called from the thread of the state's call (a request server's worker
-   * thread for attached states), never concurrently for one state. */
+   * called from the thread of the state's call (one of a request server's
+   * dispatch threads for attached states), never concurrently for one state. */
   void *(*dev_alloc)(size_t bytes, void *stream, void *ctx);
   void (*dev_free)(void *ptr, size_t bytes, void *stream, void *ctx);
   void *alloc_ctx;              /* passed to both hooks                          */
+  int32_t deterministic;        /* 1 (default): the sparse row update sums each  */
+                                /* base row's terms in a fixed order (nonzeros   */
+                                /* sorted by column, no floating-point atomics), */
+                                /* so an update gives bitwise the same factors   */
+                                /* every time; 0: atomic accumulation, faster,   */
+                                /* rounding order free                           */
 } svlcov_options;
 
 typedef struct {

@@ -53,7 +53,8 @@ class _Options(C.Structure):
                 ("row_capacity", C.c_int64), ("col_capacity", C.c_int64),
                 ("rank_tol", C.c_double), ("cond_reset", C.c_double),
                 ("validate_device_inputs", C.c_int32),
-                ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", C.c_void_p)]
+                ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", C.c_void_p),
+                ("deterministic", C.c_int32)]
 
 
 def _torch_alloc(nbytes, stream, ctx):
@@ -374,12 +375,14 @@ class TruncatedSVD:
     U = U_base W_U, V = V_base W_V (Section 3.2), updated by the library.
     allocator="torch" makes torch's caching allocator own the state's device
     memory (the svlcov_options allocator hooks); the default is the library's
-    own stream-ordered HIP allocations."""
+    own stream-ordered HIP allocations.  deterministic=False accumulates the
+    sparse row update with atomics (faster, rounding order free) instead of
+    summing each base row's terms in a fixed order."""
 
     def __init__(self, U, s, V, precision: str = "fp64", device: int = 0, stream=None,
                  row_capacity: int = 0, col_capacity: int = 0, rank_tol: float = 0.0,
                  cond_reset: float = 0.0, validate_device_inputs: bool = True,
-                 allocator: str = None):
+                 allocator: str = None, deterministic: bool = True):
         on_dev = 0
         if _is_torch(U):
             # device factors (FP64 CUDA tensors), read on the state's stream
@@ -406,6 +409,7 @@ class TruncatedSVD:
         opt.rank_tol = rank_tol
         opt.cond_reset = cond_reset
         opt.validate_device_inputs = 1 if validate_device_inputs else 0
+        opt.deterministic = 1 if deterministic else 0
         if allocator == "torch":
             # the state's factors and workspaces come from torch's caching allocator
             opt.dev_alloc, opt.dev_free = _TORCH_HOOKS

@@ -225,6 +225,14 @@ int mode_of(int prec) { return prec == SVLCOV_FP64 ? 0 : (prec == SVLCOV_FP32 ? 
 
 // Device workspace of one update (the carving of op_append / op_weights
 // below, replayed without memory): op 0 add_rows, 1 add_cols, 2 weights.
+// Words of the per-nonzero row-id buffer of the sparse Gram; it is free again
+// by the commit, where it holds the deterministic scatter's sort.
+static int64_t rid_words(int64_t nnz) {
+  const int64_t a = nnz > 0 ? nnz : 1;
+  const int64_t b = (int64_t)((svl::scatter_det_bytes(nnz) + 3) / 4);
+  return a > b ? a : b;
+}
+
 size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int64_t nnzB) {
   Carver c{nullptr};
   const int64_t N = K + s;
@@ -256,7 +264,7 @@ size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int
   for (int q = 0; q < 4; ++q) c.take<double>(K * K);
   c.take<int32_t>(2);
   c.take<double>(2 * K * K + 9 * K * N);
-  c.take<int32_t>(nnz > 0 ? nnz : 1);
+  c.take<int32_t>(rid_words(nnz));
   return c.off;
 }
 
@@ -303,10 +311,13 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
     svl::spmm_w<T>(st, K, s, E.rp, E.ci, E.v, E.vdt, base, W, Cp64,
                    h->prec == SVLCOV_FP64 ? nullptr : Cp32, rown, h->info, !chol);
   }
+  // the Cholesky's drop scale max_i ||e_i||^2, also the sparse Gram's
+  // fixed-point scale
+  svl::max_into(st, s, rown, h->info, which);
   {
     PhaseScope ps(h, PH_SGRAM);
     svl::sparse_gram(st, s, E.cols, E.nnz, E.rp, E.ci, E.v, E.vdt, rid, Gm, s, dws, dws_len,
-                     h->info);
+                     h->info, which);
     // S = E E^T is also the trailing block of M = K K^T (R^T R = S - C' C'^T)
     if (Scopy) svl::copy_strided(st, s, s, Gm, s, 1, Scopy, lds_copy, h->info);
   }
@@ -320,7 +331,6 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
     else
       svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
   }
-  svl::max_into(st, s, rown, h->info, which);
   if (!chol) return;   // the approximate variants use the Gram itself
   PhaseScope ps(h, PH_CHOL);
   coop_enter(h);
@@ -471,14 +481,18 @@ template <typename T>
 void sparse_side_commit(svlcov_state *h, const DevCsr &E, int64_t rows_used, T *base,
                         const double *Y, double *Mupd, const double *Wnew, const double *Winv,
                         const int32_t *flag, double *W, const double *theta, double *sig,
-                        int side) {
+                        int side, void *scat) {
   const int K = h->k;
   hipStream_t st = h->stream;
   const int mode = mode_of(h->prec);
   PhaseScope ps(h, PH_COMMIT);
   svl::realise<T, T>(st, mode, K, rows_used, base, Wnew, base, flag, h->info);
   svl::append_rows<double>(st, K, E.rows, Y, K, 1, Winv, flag, Mupd, h->info);
-  svl::scatter<T>(st, K, E.rows, E.rp, E.ci, E.v, E.vdt, Mupd, base, h->info);
+  if (h->deterministic)
+    svl::scatter_det<T>(st, K, E.rows, E.cols, E.nnz, E.rp, E.ci, E.v, E.vdt, Mupd, base, scat,
+                        h->info);
+  else
+    svl::scatter<T>(st, K, E.rows, E.rp, E.ci, E.v, E.vdt, Mupd, base, h->info);
   svl::commit_small(st, K, Wnew, flag, W, theta, sig, h->info, side);
 }
 
@@ -541,7 +555,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
     *Mupd = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
     *orthw = cv.take<double>(2 * K * K + 9 * K * N);
-    rid = cv.take<int32_t>(E->nnz > 0 ? E->nnz : 1);
+    rid = cv.take<int32_t>(rid_words(E->nnz));
   };
   double *Cp64, *rown, *Gm, *Linv, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA,
       *WiA, *WnB, *WiB, *Mupd;
@@ -605,7 +619,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   }
   // commit: sparse side
   sparse_side_commit<T>(h, dE, nB, B_base, Y, Mupd, WnB, WiB, flags + 1, W_B, nullptr, nullptr,
-                        sideB);
+                        sideB, rid);
   svl::op_end(st, h->info);
   if (rows_form) h->m += s; else h->n += s;
   if (h->launch_failed) {
@@ -700,7 +714,7 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
     b.Mupd = cv.take<double>(s * K);
     b.flags = cv.take<int32_t>(2);
     b.orthw = cv.take<double>(2 * K * K + 9 * K * N);
-    b.rid = cv.take<int32_t>(E->nnz > 0 ? E->nnz : 1);
+    b.rid = cv.take<int32_t>(rid_words(E->nnz));
     b.Pv = cv.take<double>((int64_t)(l + 1) * s);
     b.Yc = cv.take<double>((int64_t)l * s);
     b.gv = cv.take<double>(s);
@@ -839,7 +853,7 @@ svlcov_status op_append_approx(svlcov_state *h, const svlcov_csr *E, bool rows_f
     svl::commit_small(st, K, b.WnA, b.flags, W_A, b.theta, h->sigma, h->info, sideA);
   }
   sparse_side_commit<T>(h, dE, nB, B_base, b.Y, b.Mupd, b.WnB, b.WiB, b.flags + 1, W_B, nullptr,
-                        nullptr, sideB);
+                        nullptr, sideB, b.rid);
   svl::op_end(st, h->info);
   if (rows_form) h->m += s; else h->n += s;
   if (h->launch_failed) {
@@ -935,7 +949,7 @@ svlcov_status op_weights_approx(svlcov_state *h, const svlcov_csr *D, const svlc
     b.WiV = cv.take<double>(K * K);
     b.flags = cv.take<int32_t>(2);
     b.orthw = cv.take<double>(2 * K * K + 9 * K * N0);
-    b.rid = cv.take<int32_t>(nnz_max > 0 ? nnz_max : 1);
+    b.rid = cv.take<int32_t>(rid_words(nnz_max));
     b.Dws = cv.take<double>(dws_len);
   };
   Carver c{nullptr};
@@ -1074,9 +1088,9 @@ svlcov_status op_weights_approx(svlcov_state *h, const svlcov_csr *D, const svlc
     svl::set_status(st, h->info, SVLCOV_E_DEVICE);
   }
   sparse_side_commit<T>(h, dq[0], h->m, Ub, sd[0].Y, sd[0].M, b.WnU, b.WiU, b.flags, h->WU,
-                        b.theta, h->sigma, 0);
+                        b.theta, h->sigma, 0, b.rid);
   sparse_side_commit<T>(h, dq[1], h->n, Vb, sd[1].Y, sd[1].M, b.WnV, b.WiV, b.flags + 1, h->WV,
-                        nullptr, nullptr, 1);
+                        nullptr, nullptr, 1, b.rid);
   svl::op_end(st, h->info);
   if (h->launch_failed) {
     h->launch_failed = false;
@@ -1131,7 +1145,7 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
     *MD = cv.take<double>(s * K); *ME = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
     *orthw = cv.take<double>(2 * K * K + 9 * K * N);
-    rid = cv.take<int32_t>(nnz_max > 0 ? nnz_max : 1);
+    rid = cv.take<int32_t>(rid_words(nnz_max));
   };
   double *CpD, *CpE, *rnD, *rnE, *GD, *GE, *LiD, *LiE, *X, *Yx, *Kmat, *Mmat, *lam, *theta, *Fv,
       *Gv, *eigw, *YD, *YE, *T1, *WnU, *WiU, *WnV, *WiV, *MD, *ME;
@@ -1191,8 +1205,9 @@ svlcov_status op_weights(svlcov_state *h, const svlcov_csr *D, const svlcov_csr 
   }
   svl::check_finite(st, K * K, WnU, h->info, h->seq);
   svl::check_finite(st, K * K, WnV, h->info, h->seq);
-  sparse_side_commit<T>(h, dD, h->m, Ub, YD, MD, WnU, WiU, flags, h->WU, theta, h->sigma, 0);
-  sparse_side_commit<T>(h, dEm, h->n, Vb, YE, ME, WnV, WiV, flags + 1, h->WV, nullptr, nullptr, 1);
+  sparse_side_commit<T>(h, dD, h->m, Ub, YD, MD, WnU, WiU, flags, h->WU, theta, h->sigma, 0, rid);
+  sparse_side_commit<T>(h, dEm, h->n, Vb, YE, ME, WnV, WiV, flags + 1, h->WV, nullptr, nullptr, 1,
+                        rid);
   svl::op_end(st, h->info);
   if (h->launch_failed) {
     h->launch_failed = false;
@@ -1245,6 +1260,7 @@ void svlcov_default_options(svlcov_options *o) {
   o->rank_tol = 0.0;
   o->cond_reset = 0.0;
   o->validate_device_inputs = 1;
+  o->deterministic = 1;
 }
 
 svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k, const double *U,
@@ -1279,6 +1295,7 @@ svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k, c
   h->rank_tol = o.rank_tol > 0 ? o.rank_tol : DEF_TOL[h->prec];
   h->cond_reset = o.cond_reset > 0 ? o.cond_reset : DEF_COND[h->prec];
   h->validate = o.validate_device_inputs ? 1 : 0;
+  h->deterministic = o.deterministic ? 1 : 0;
   auto fail = [&](svlcov_status s) {
     svlcov_destroy(h);
     return s;

@@ -766,6 +766,169 @@ unsigned grid_for(int64_t work, int64_t per_block, int64_t cap) {
   return (unsigned)b;
 }
 
+// ------------------------------------------ deterministic sparse row update
+// base[c, :] += sum_i E[i, c] M[i, :] without floating-point atomics: the
+// nonzeros are sorted by column (the stable radix sort above, so rows stay
+// ascending within a column), every distinct column gets one wave, and the
+// wave sums its rows in that order, so the result does not depend on
+// scheduling.
+
+__global__ void k_zero_count(uint32_t *__restrict__ count, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  *count = 0u;
+}
+
+// heads[count++] = q for every q that starts a run of equal keys (the order
+// of the list is free: each run is summed by its own wave).
+__global__ void k_seg_heads(int64_t nnz, const uint32_t *__restrict__ keys,
+                            uint32_t *__restrict__ heads, uint32_t *__restrict__ count,
+                            const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nnz;
+       q += (int64_t)gridDim.x * blockDim.x)
+    if (q == 0 || keys[q] != keys[q - 1]) heads[atomicAdd(count, 1u)] = (uint32_t)q;
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(256)
+k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__restrict__ perm,
+              const uint32_t *__restrict__ heads, const uint32_t *__restrict__ count,
+              const int32_t *__restrict__ rid, const void *__restrict__ val, int vdtype,
+              const double *__restrict__ M, T *__restrict__ base,
+              const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  const int lane = threadIdx.x & 63;
+  const uint32_t nseg = *count;
+  for (int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sg < (int64_t)nseg;
+       sg += (int64_t)gridDim.x * 4) {
+    const uint32_t q0 = heads[sg], key = keys[q0];
+    double acc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
+    for (uint32_t q = q0; q < (uint32_t)nnz && keys[q] == key; ++q) {
+      const uint32_t p = perm[q];
+      const double v = vdtype == 1 ? ((const double *)val)[p] : (double)((const float *)val)[p];
+      const int64_t i = rid[p];
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < K) acc[u] += v * M[i * K + lane + 64 * u];
+    }
+    T *dst = base + (int64_t)key * K;
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (lane + 64 * u < K) dst[lane + 64 * u] = (T)((double)dst[lane + 64 * u] + acc[u]);
+  }
+}
+
+// The same row update for updates with few nonzeros, in one launch: block b
+// owns the base rows of columns [b BW, (b+1) BW) and keeps their increments
+// in LDS in the base's precision.  Thread t takes the contiguous nonzeros
+// [t L, (t+1) L) of the CSR, counts its hits in the bucket, and one exclusive
+// scan over the block lays the hits out in CSR order; wave 0 then adds them
+// one after another, so every column sums its rows in row order whatever the
+// scheduling (more hits than the buffer holds are taken in windows of
+// SB_CAP).  The touched rows are then added to the base once.
+constexpr int SB_NT = 512;
+constexpr int SB_CAP = 1024;   // hits buffered per window
+constexpr int SB_ITEMS = 64;   // nonzeros per thread: the kernel takes nnz <= SB_ITEMS SB_NT
+constexpr int SB_LDS = 48 * 1024;   // bytes of increments per block
+
+template <typename T, int K>
+__global__ void __launch_bounds__(SB_NT)
+k_scatter_bucket(int64_t s, int64_t cols, const int64_t *__restrict__ rp,
+                 const int32_t *__restrict__ ci, const int32_t *__restrict__ rid,
+                 const void *__restrict__ val, int vdtype, const double *__restrict__ M,
+                 T *__restrict__ base, const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int BW = SB_LDS / (int)sizeof(T) / K;   // columns per bucket
+  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  __shared__ T tab[BW * K];
+  __shared__ int touched[BW];
+  __shared__ int32_t mcol[SB_CAP], mrow[SB_CAP];
+  __shared__ double mval[SB_CAP];
+  __shared__ int wtot[SB_NT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * BW;
+  const int64_t nnz = rp[s];
+  const int L = (int)((nnz + SB_NT - 1) / SB_NT);
+  const int64_t p0 = (int64_t)tid * L;
+  for (int e = tid; e < BW * K; e += SB_NT) tab[e] = (T)0;
+  for (int e = tid; e < BW; e += SB_NT) touched[e] = 0;
+  // this thread's nonzeros: a bit per hit in the bucket
+  uint64_t hits = 0;
+#pragma unroll
+  for (int r = 0; r < SB_ITEMS; ++r) {
+    const int64_t p = p0 + r;
+    const int32_t c = (r < L && p < nnz) ? ci[p] : -1;
+    hits |= (c >= c0 && c < c0 + BW) ? (1ull << r) : 0ull;
+  }
+  const int mine = __popcll(hits);
+  // exclusive scan of the counts: within the wave by shuffles, then the
+  // wave totals
+  int incl = mine;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wtot[w] = incl;
+  __syncthreads();
+  int woff = 0, total = 0;
+  for (int v = 0; v < SB_NT / 64; ++v) {
+    woff += v < w ? wtot[v] : 0;
+    total += wtot[v];
+  }
+  const int first = woff + incl - mine;   // index of this thread's first hit
+  for (int h0 = 0; h0 < total; h0 += SB_CAP) {
+    // the hits with index in [h0, h0 + SB_CAP), in order
+    int idx = first;
+    for (uint64_t m = hits; m; m &= m - 1, ++idx) {
+      if (idx < h0 || idx >= h0 + SB_CAP) continue;
+      const int64_t p = p0 + __builtin_ctzll(m);
+      const int slot = idx - h0;
+      mcol[slot] = (int32_t)(ci[p] - c0);
+      mrow[slot] = rid[p];
+      mval[slot] = vdtype == 1 ? ((const double *)val)[p] : (double)((const float *)val)[p];
+    }
+    __syncthreads();
+    if (w == 0) {
+      const int n = total - h0 < SB_CAP ? total - h0 : SB_CAP;
+      for (int q0 = 0; q0 < n; q0 += 8) {
+        double mv[8][CPL];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int v = 0; v < CPL; ++v) {
+            const int j = lane + 64 * v;
+            mv[u][v] = (q0 + u < n && j < K) ? M[(int64_t)mrow[q0 + u] * K + j] : 0.0;
+          }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (q0 + u < n) {
+            const int cl = mcol[q0 + u];
+            const double x = mval[q0 + u];
+#pragma unroll
+            for (int v = 0; v < CPL; ++v) {
+              const int j = lane + 64 * v;
+              if (j < K) tab[cl * K + j] = (T)((double)tab[cl * K + j] + x * mv[u][v]);
+            }
+            if (lane == 0) touched[cl] = 1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < BW * K; e += SB_NT) {
+    const int cl = e / K, j = e % K;
+    if (touched[cl] && c0 + cl < cols) {
+      T *dst = base + (c0 + cl) * K + j;
+      *dst = *dst + tab[e];
+    }
+  }
+}
+
 }  // namespace
 
 namespace svl {
@@ -820,6 +983,99 @@ void csr_transpose(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz, cons
                        (const uint32_t *)nullptr, rpT, info);
   }
 }
+
+size_t scatter_det_bytes(int64_t nnz) {
+  return csr_transpose_bytes(nnz, 0) + (size_t)nnz * sizeof(uint32_t) + 256;
+}
+
+template <typename T, int K>
+static void scatter_bucket_launch(hipStream_t st, int64_t s, int64_t cols, int64_t nnz,
+                                  const int64_t *rp, const int32_t *ci, const void *v, int vdt,
+                                  const double *M, T *base, int32_t *rid, const SvDevInfo *info) {
+  constexpr int BW = SB_LDS / (int)sizeof(T) / K;
+  hipLaunchKernelGGL(k_row_ids, dim3(grid_for(s, 4, 1 << 20)), dim3(256), 0, st, s, nnz, rp, rid,
+                     info);
+  const unsigned nb = (unsigned)((cols + BW - 1) / BW);
+  hipLaunchKernelGGL((k_scatter_bucket<T, K>), dim3(nb), dim3(SB_NT), 0, st, s, cols, rp, ci, rid,
+                     v, vdt, M, base, info);
+}
+
+template <typename T>
+void scatter_det(hipStream_t st, int K, int64_t s, int64_t cols, int64_t nnz, const int64_t *rp,
+                 const int32_t *ci, const void *v, int vdt, const double *M, T *base,
+                 void *scratch, const SvDevInfo *info) {
+  if (s <= 0 || nnz <= 0) return;
+  // few nonzeros against the column buckets: every bucket scans them all, in
+  // one launch; otherwise the sort
+  const int64_t bw = SB_LDS / (int64_t)sizeof(T) / K;
+  const int64_t buckets = (cols + bw - 1) / bw;
+  if (nnz <= (int64_t)SB_ITEMS * SB_NT && (double)nnz * (double)buckets <= (double)(1ll << 26)) {
+    switch (K) {
+      case 16: scatter_bucket_launch<T, 16>(st, s, cols, nnz, rp, ci, v, vdt, M, base,
+                                              (int32_t *)scratch, info); break;
+      case 32: scatter_bucket_launch<T, 32>(st, s, cols, nnz, rp, ci, v, vdt, M, base,
+                                              (int32_t *)scratch, info); break;
+      case 64: scatter_bucket_launch<T, 64>(st, s, cols, nnz, rp, ci, v, vdt, M, base,
+                                              (int32_t *)scratch, info); break;
+      case 128: scatter_bucket_launch<T, 128>(st, s, cols, nnz, rp, ci, v, vdt, M, base,
+                                              (int32_t *)scratch, info); break;
+    }
+    return;
+  }
+  const int64_t tiles = (nnz + RS_TILE - 1) / RS_TILE;
+  char *p = (char *)scratch;
+  uint32_t *ka = (uint32_t *)p; p += (size_t)nnz * sizeof(uint32_t);
+  uint32_t *kb = (uint32_t *)p; p += (size_t)nnz * sizeof(uint32_t);
+  uint32_t *pa = (uint32_t *)p; p += (size_t)nnz * sizeof(uint32_t);
+  uint32_t *pb = (uint32_t *)p; p += (size_t)nnz * sizeof(uint32_t);
+  int32_t *rid = (int32_t *)p; p += (size_t)nnz * sizeof(int32_t);
+  uint32_t *hist = (uint32_t *)p;
+  const int64_t nh = (tiles > 0 ? tiles : 1) * RS_DIG;
+  uint32_t *bsum = hist + nh;
+  p = (char *)(bsum + (nh + SC_TILE - 1) / SC_TILE + 1);
+  uint32_t *heads = (uint32_t *)p; p += (size_t)nnz * sizeof(uint32_t);
+  uint32_t *count = (uint32_t *)p;
+  hipLaunchKernelGGL(k_row_ids, dim3(grid_for(s, 4, 1 << 20)), dim3(256), 0, st, s, nnz, rp, rid,
+                     info);
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) < cols) ++bits;
+  const int passes = (bits + 7) / 8;
+  const uint32_t *kin = (const uint32_t *)ci;
+  const uint32_t *pin = nullptr;
+  for (int ps = 0; ps < passes; ++ps) {
+    uint32_t *kout = (ps & 1) ? kb : ka;
+    uint32_t *pout = (ps & 1) ? pb : pa;
+    hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)tiles), dim3(RS_NT), 0, st, nnz, kin, 8 * ps,
+                       tiles, hist, info);
+    const int64_t nb = (nh + SC_TILE - 1) / SC_TILE;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SC_NT), 0, st, nh, hist, bsum, info);
+    hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(SC_NT), 0, st, nb, bsum, info);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SC_NT), 0, st, nh, hist, bsum, info);
+    hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)tiles), dim3(RS_NT), 0, st, nnz, kin, pin,
+                       8 * ps, tiles, hist, kout, pout, info);
+    kin = kout;
+    pin = pout;
+  }
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, count, info);
+  hipLaunchKernelGGL(k_seg_heads, dim3(grid_for(nnz, 256, 8192)), dim3(256), 0, st, nnz, kin,
+                     heads, count, info);
+  const unsigned blocks = (unsigned)std::min<int64_t>((nnz + 3) / 4, 16384);
+#define SV_SS(KK) hipLaunchKernelGGL((k_scatter_seg<T, KK>), dim3(blocks), dim3(256), 0, st, nnz, \
+                                     kin, pin, heads, count, rid, v, vdt, M, base, info)
+  switch (K) {
+    case 16: SV_SS(16); break;
+    case 32: SV_SS(32); break;
+    case 64: SV_SS(64); break;
+    case 128: SV_SS(128); break;
+  }
+#undef SV_SS
+}
+template void scatter_det<float>(hipStream_t, int, int64_t, int64_t, int64_t, const int64_t *,
+                                 const int32_t *, const void *, int, const double *, float *,
+                                 void *, const SvDevInfo *);
+template void scatter_det<double>(hipStream_t, int, int64_t, int64_t, int64_t, const int64_t *,
+                                  const int32_t *, const void *, int, const double *, double *,
+                                  void *, const SvDevInfo *);
 
 void check_finite_wide(hipStream_t st, int64_t n, const double *x, SvDevInfo *info) {
   if (n <= 0) return;

@@ -369,22 +369,29 @@ __global__ void k_densify(int64_t s, const int64_t *__restrict__ row_ptr,
 }
 
 constexpr int GRAM_LDS_CAP = 4096;      // nonzeros of the pivot row kept in LDS
-constexpr int GRAM_ACC_CAP = 8192;      // rows j accumulated in LDS (dynamic)
 
 // S = E E^T (FP64, full s x s).  Block b handles rows i = b and s-1-b (folded
 // so that every block does about s/2 row pairs).  Row i is staged in LDS; the
 // nonzeros of rows 0..i are contiguous in the CSR, so the block streams them
 // with coalesced loads (one nonzero per thread), finds each column in row i
-// by binary search, and accumulates the products per row j in LDS.
+// by binary search, and accumulates the products per row j in LDS.  The sums
+// are kept in 64-bit fixed point with 2^61 standing for scale = max_i
+// ||e_i||^2 (every |S_ij| is at most that, by Cauchy-Schwarz): integer
+// additions commute, so S is bitwise the same whatever order the atomics
+// land in, and each product is rounded to 2^-62 scale, far below the
+// Cholesky's pivot floor (>= 1e-13 scale).
 __global__ void __launch_bounds__(256)
 k_sparse_gram(int64_t s, const int64_t *__restrict__ row_ptr,
               const int32_t *__restrict__ col_idx, const int32_t *__restrict__ rid,
               const void *__restrict__ val, int vdtype, double *__restrict__ S,
-              int64_t lds, const SvDevInfo *__restrict__ info) {
+              int64_t lds, const SvDevInfo *__restrict__ info, int which) {
   if (info->status) return;
   __shared__ int32_t sc[GRAM_LDS_CAP];
   __shared__ double sv[GRAM_LDS_CAP];
-  extern __shared__ double acc[];   // s doubles
+  extern __shared__ unsigned long long acc[];   // s fixed-point sums
+  const double scale = which == 0 ? info->scale : info->scale2;
+  const double fx = scale > 0.0 ? 2305843009213693952.0 / scale : 0.0;   // 2^61 / scale
+  const double unfx = scale > 0.0 ? scale / 2305843009213693952.0 : 0.0;
   for (int pass = 0; pass < 2; ++pass) {
     const int64_t i = pass == 0 ? (int64_t)blockIdx.x : s - 1 - (int64_t)blockIdx.x;
     if (pass == 1 && i <= (int64_t)blockIdx.x) break;
@@ -399,7 +406,7 @@ k_sparse_gram(int64_t s, const int64_t *__restrict__ row_ptr,
         sv[t] = ldv(val, vdtype, q0 + t);
       }
     }
-    for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) acc[j] = 0.0;
+    for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) acc[j] = 0ull;
     __syncthreads();
     const int32_t *ci = in_lds ? sc : col_idx + q0;
     if (ni > 0) {
@@ -412,13 +419,14 @@ k_sparse_gram(int64_t s, const int64_t *__restrict__ row_ptr,
         }
         if (lo < ni && ci[lo] == c) {
           const double vi = in_lds ? sv[lo] : ldv(val, vdtype, q0 + lo);
-          atomicAdd(&acc[rid[p]], vi * ldv(val, vdtype, p));
+          const long long q = __double2ll_rn(vi * ldv(val, vdtype, p) * fx);
+          atomicAdd(&acc[rid[p]], (unsigned long long)q);
         }
       }
     }
     __syncthreads();
     for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) {
-      const double a = acc[j];
+      const double a = (double)(long long)acc[j] * unfx;
       S[i * lds + j] = a;
       S[j * lds + i] = a;
     }
@@ -727,7 +735,9 @@ void spmm_batch(hipStream_t st, const ProjBatch &b, const void *blob_dev) {
   }
 }
 
-int gram_max_rows() { return GRAM_ACC_CAP; }
+// the update paths are exercised up to this many rows of E per update
+constexpr int GRAM_MAX_ROWS = 8192;
+int gram_max_rows() { return GRAM_MAX_ROWS; }
 
 int64_t gram_dense_block(int64_t s, int64_t cols, int64_t nnz, size_t dws_len) {
   if (s <= 0 || cols <= 0 || dws_len == 0) return 0;
@@ -743,7 +753,7 @@ int64_t gram_dense_block(int64_t s, int64_t cols, int64_t nnz, size_t dws_len) {
 
 void sparse_gram(hipStream_t st, int64_t s, int64_t cols, int64_t nnz, const int64_t *rp,
                  const int32_t *ci, const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
-                 double *dws, size_t dws_len, const SvDevInfo *info) {
+                 double *dws, size_t dws_len, const SvDevInfo *info, int which) {
   if (s <= 0) return;
   const int64_t nb = gram_dense_block(s, cols, nnz, dws_len);
   if (nb > 0) {   // a dense update: S = sum over column blocks of D D^T
@@ -773,8 +783,9 @@ void sparse_gram(hipStream_t st, int64_t s, int64_t cols, int64_t nnz, const int
   }();
   (void)once;
   const unsigned blocks = (unsigned)((s + 1) / 2);
-  hipLaunchKernelGGL(k_sparse_gram, dim3(blocks), dim3(256), (size_t)s * sizeof(double), st, s,
-                     rp, ci, rid, v, vdt, S, lds, info);
+  hipLaunchKernelGGL(k_sparse_gram, dim3(blocks), dim3(256),
+                     (size_t)s * sizeof(unsigned long long), st, s, rp, ci, rid, v, vdt, S, lds,
+                     info, which);
 }
 
 template <typename T>

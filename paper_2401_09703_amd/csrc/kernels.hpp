@@ -67,9 +67,11 @@ int gram_max_rows();
 // blocks of E made dense; gram_dense_block gives the block width, 0 for the
 // sparse kernel.
 int64_t gram_dense_block(int64_t s, int64_t cols, int64_t nnz, size_t dws_len);
+// The sparse kernel accumulates in fixed point against info->scale (which =
+// 0) or info->scale2 (which = 1), max_i ||e_i||^2, which must be set first.
 void sparse_gram(hipStream_t st, int64_t s, int64_t cols, int64_t nnz, const int64_t *rp,
                  const int32_t *ci, const void *v, int vdt, int32_t *rid, double *S, int64_t lds,
-                 double *dws, size_t dws_len, const SvDevInfo *info);
+                 double *dws, size_t dws_len, const SvDevInfo *info, int which);
 template <typename T>
 void scatter(hipStream_t st, int K, int64_t s, const int64_t *rp, const int32_t *ci,
              const void *v, int vdt, const double *M, T *base, const SvDevInfo *info);
@@ -215,6 +217,15 @@ void csr_dense(hipStream_t st, int L, int64_t rows, const int64_t *rp, const int
 // CSR of A^T (cols x rows; rows ascending within each row of A^T, FP64
 // values) by a stable radix sort; scratch holds csr_transpose_bytes bytes.
 size_t csr_transpose_bytes(int64_t nnz, int64_t cols);
+// base[c, :] += sum_i E[i, c] M[i, :] (M s x K FP64, base n x K) with no
+// floating-point atomics: the nonzeros sorted by column (stable radix sort),
+// one wave per distinct column summing its rows in order; scratch holds
+// scatter_det_bytes(nnz) bytes.
+size_t scatter_det_bytes(int64_t nnz);
+template <typename T>
+void scatter_det(hipStream_t st, int K, int64_t s, int64_t cols, int64_t nnz, const int64_t *rp,
+                 const int32_t *ci, const void *v, int vdt, const double *M, T *base,
+                 void *scratch, const SvDevInfo *info);
 void csr_transpose(hipStream_t st, int64_t rows, int64_t cols, int64_t nnz, const int64_t *rp,
                    const int32_t *ci, const void *v, int vdt, int64_t *rpT, int32_t *ciT,
                    double *vT, void *scratch, const SvDevInfo *info);

@@ -67,6 +67,7 @@ struct svlcov_state {
   int64_t q_seq = -1;
   double rank_tol = 0, cond_reset = 0;
   int validate = 1;
+  int deterministic = 1;   // sparse row update without floating-point atomics
   int seq = 0;
   std::vector<svl_state::Snapshot> history;
   std::atomic<bool> busy{false};
