@@ -77,3 +77,19 @@ def test_atomic_row_update_matches_the_ordered_one():
     for A, B in ((Ua, Ub), (Va, Vb)):
         sg = np.sign(np.sum(A * B, axis=0))
         assert np.max(np.abs(A - B * sg)) <= 1e-8
+
+
+def test_large_update_takes_the_sorted_row_update_bitwise():
+    """An update with more than 32k nonzeros: the row update goes through the
+    stable radix sort by column; still bitwise reproducible."""
+    L = _L()
+    rng = np.random.default_rng(406)
+    m, n, k = 900, 800, 32
+    U, s, V = synthetic_factors(m, n, k, rng)
+    E = _hub_update(rng, 1200, n, hubs=16, density=0.04)
+    assert E.nnz > 32768
+    ups = [("rows", E)]
+    a = _run(L, U, s, V, ups, "fp32")
+    b = _run(L, U, s, V, ups, "fp32")
+    for x, y, name in zip(a, b, "UsV"):
+        assert np.array_equal(x, y), (name, float(np.max(np.abs(x - y))))
