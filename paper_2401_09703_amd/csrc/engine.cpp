@@ -377,10 +377,14 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
     if (h->ctl_host) {
       int iters = 0;
       double fl = 0.0;
+      // a basis wider than 128 uses the cooperative eigensolver inside
+      const bool coop = svl::chefsi_block(K) > 128;
+      if (coop) coop_enter(h);
       const int rc = svl::eig_topk_chefsi(st, N, Mmat, K, lam, Fv, eigw,
                                           svl::eig_update_work_doubles(N, K), h->ctl_host,
                                           1e-9, 8, (uint64_t)h->seq * 7919 + 17, h->info,
-                                          &iters, &fl);
+                                          &iters, &fl, h->flags, &h->epoch);
+      if (coop) coop_exit(h);
       ++h->iter_runs;
       h->iter_steps += iters;
       h->iter_flops += fl;

@@ -186,27 +186,29 @@ unsigned grid_of(int64_t n) {
 
 namespace svl {
 
-// basis width p = k + 32 rounded up to a multiple of 16 (at most 128): 32
+// basis width p = k + 32 rounded up to a multiple of 16 (at most 256): 32
 // guard vectors keep the gap between the k-th wanted and the first damped
 // Ritz value wide enough for one Chebyshev step on the graph spectra, and
 // every p x p stage (Gram, Cholesky QR, the Rayleigh quotient's eigensolver)
 // scales with p (a sweep on the 100k-node graph workload at k = 64:
 // p = 128 3.99 ms, 96 3.63 ms, 80 3.45 ms median but with a second filter
-// step on some updates).  SVLCOV_CHEFSI_P overrides it for tuning sweeps (a
-// multiple of 16 in (k, 128]).
+// step on some updates).  Beyond 128 columns (k = 128) the p x p eigensolver
+// is the cooperative one (flags and epoch needed) and the orthonormalisation
+// works in two column blocks.  SVLCOV_CHEFSI_P overrides p for tuning sweeps
+// (a multiple of 16 in (k, 256]).
 int chefsi_block(int k) {
   static const int forced = [] {
     const char *ev = getenv("SVLCOV_CHEFSI_P");
     return ev ? atoi(ev) : 0;
   }();
-  if (forced > k && forced <= 128 && forced % 16 == 0) return forced;
+  if (forced > k && forced <= 256 && forced % 16 == 0) return forced;
   const int p = (k + 32 + 15) / 16 * 16;
-  return p < 128 ? p : 128;
+  return p < 256 ? p : 256;
 }
 
 bool chefsi_applies(int64_t N, int k) {
   const int p = chefsi_block(k);
-  return (k == 8 || k == 16 || k == 32 || k == 64) && N > 128 && N >= p + 32;
+  return (k == 8 || k == 16 || k == 32 || k == 64 || k == 128) && N > 128 && N >= p + 32;
 }
 
 // Layout of the workspace (doubles): five N x p panels, the split-K / Gram
@@ -226,7 +228,8 @@ size_t eig_update_work_doubles(int64_t N, int k) {
 
 int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *lam, double *Fv,
                     double *ws, size_t ws_len, double *ctl_host, double tol, int max_it,
-                    uint64_t seed, const SvDevInfo *info, int *iters, double *flops) {
+                    uint64_t seed, const SvDevInfo *info, int *iters, double *flops,
+                    unsigned *flags, unsigned *epoch) {
   const int p = chefsi_block(k);
   // algorithmic flops: 2 N^2 p per product with M, 2 N p^2 per Rayleigh
   // quotient and 4 N p^2 per rotation of X and M X
@@ -261,10 +264,30 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
   // condition number is at most 1 + 1.27, and one pass then leaves an
   // orthogonality error of a few u)
   int32_t *need = (int32_t *)(ctl + 16);
-  auto orth = [&](double *src, double *scratch, double gate_tau) -> double * {
+  // p > 128 (k = 128): block Gram-Schmidt with reorthogonalisation over the
+  // first 128 columns and the rest, each block by the same Cholesky QR
+  // (its kernels take at most 128 columns); panel and scratch are two free
+  // N x p panels, the 128 x r coupling goes through H
+  auto orth = [&](double *src, double *scratch, double *spare, double gate_tau) -> double * {
     hipLaunchKernelGGL(k_cf_colnorm, dim3(p), dim3(256), 0, st, N, p, src, info);
-    return orth_cols_cond(st, N, p, src, scratch, G, Out, complete, need, gws, gws_len, ++seed,
-                          rtol, info, gate_tau);
+    if (p <= 128)
+      return orth_cols_cond(st, N, p, src, scratch, G, Out, complete, need, gws, gws_len, ++seed,
+                            rtol, info, gate_tau);
+    const int r = p - 128;
+    double *Xa = spare, *Xb = spare + (size_t)N * 128;
+    copy_strided(st, N, 128, src, p, 1, Xa, 128, info);
+    copy_strided(st, N, r, src + 128, p, 1, Xb, r, info);
+    orth_cols_cond(st, N, 128, Xa, scratch, G, Out, complete, need, gws, gws_len, ++seed, rtol,
+                   info, gate_tau);
+    for (int pass = 0; pass < 2; ++pass) {
+      gemm_f64_sk(st, true, false, 128, r, N, 1.0, Xa, 128, Xb, r, 0.0, H, r, gws, gws_len, info);
+      gemm_f64(st, false, false, N, r, 128, -1.0, Xa, 128, H, r, 1.0, Xb, r, info);
+    }
+    orth_cols_cond(st, N, r, Xb, scratch, G, Out, complete, need, gws, gws_len, ++seed, rtol,
+                   info, gate_tau);
+    copy_strided(st, N, 128, Xa, 128, 1, src, p, info);
+    copy_strided(st, N, r, Xb, r, 1, src + 128, p, info);
+    return src;
   };
   auto other = [&](std::initializer_list<const double *> used) -> double * {
     for (int q = 0; q < 5; ++q) {
@@ -283,7 +306,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
     gemm_f64_sk(st, true, false, p, p, N, 1.0, X, p, Y, p, 0.0, H, p, gws, gws_len, info);
     hipLaunchKernelGGL(k_cf_symmetrize, dim3(grid_of((int64_t)p * p)), dim3(256), 0, st, p, H,
                        info);
-    if (eig_topk(st, p, H, p, theta, Qv, ews, nullptr, nullptr, info) != 0) return false;
+    if (eig_topk(st, p, H, p, theta, Qv, ews, flags, epoch, info) != 0) return false;
     double *Xn = other({X, Y});
     gemm_f64(st, false, true, N, p, p, 1.0, X, p, Qv, p, 0.0, Xn, p, info);
     double *Yn = other({X, Y, Xn});
@@ -315,7 +338,10 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
   // steps' condition number moves the Ritz values by far less than the
   // residuals they are judged by; a completed column still takes the second
   // pass (it is random, not orthogonal to the kept ones)
-  X = orth(X, other({X}), 2.0);
+  {
+    double *sc = other({X});
+    X = orth(X, sc, other({X, sc}), 2.0);
+  }
   Y = other({X});
   if (!rayleigh_ritz()) return -3;
   bool have_y = true;
@@ -376,7 +402,10 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
       Yc = T;
       sigma = sn;
     }
-    X = orth(Yc, other({Yc}), 1e-2);
+    {
+      double *sc = other({Yc});
+      X = orth(Yc, sc, other({Yc, sc}), 1e-2);
+    }
     Y = other({X});
     if (!rayleigh_ritz()) return -3;
     have_y = true;

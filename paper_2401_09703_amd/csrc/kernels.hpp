@@ -298,8 +298,10 @@ size_t chefsi_work_doubles(int64_t N, int k);
 // memory).
 size_t eig_update_work_doubles(int64_t N, int k);
 // *flops (may be NULL) receives the run's algorithmic flops.
+// flags / epoch as for eig_topk (used when the basis is wider than 128).
 int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *lam, double *Fv,
                     double *ws, size_t ws_len, double *ctl_host, double tol, int max_it,
-                    uint64_t seed, const SvDevInfo *info, int *iters, double *flops);
+                    uint64_t seed, const SvDevInfo *info, int *iters, double *flops,
+                    unsigned *flags, unsigned *epoch);
 
 }  // namespace svl

@@ -83,6 +83,10 @@ CASES = [
     (900, 700, 64, 300, "rows", 0.01, 5, 3, 0),
     (700, 900, 32, 257, "cols", 0.01, 4, 2, 0),
     (800, 800, 16, 130, "weights", 0.01, 3, 2, 0),
+    # k = 128 with N = k + s >= 192: the FP32 / BF16x3 subspace iteration on a
+    # 160-column basis (two-block orthonormalisation, cooperative p x p solver)
+    (900, 700, 128, 100, "rows", 0.03, 2, 1, 0),
+    (700, 900, 128, 120, "cols", 0.03, 0, 0, 0),
 ]
 
 
