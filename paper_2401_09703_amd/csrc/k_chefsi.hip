@@ -211,13 +211,24 @@ bool chefsi_applies(int64_t N, int k) {
   return (k == 8 || k == 16 || k == 32 || k == 64 || k == 128) && N > 128 && N >= p + 32;
 }
 
+// Split-K / Gram scratch (doubles): room for every partial product the
+// GEMM launcher asks for (M X, X^T Y, and for p > 128 the 128 x (p - 128)
+// coupling of the two column blocks), and the Cholesky-QR Gram.
+static size_t chefsi_gws(int64_t N, int p) {
+  const size_t panel = (size_t)N * p;
+  size_t g = std::max(ts_gram_ws(N, p), (size_t)gemm_f64_splits(N, p, N) * panel);
+  g = std::max(g, (size_t)gemm_f64_splits(p, p, N) * p * p);
+  if (p > 128) g = std::max(g, (size_t)gemm_f64_splits(128, p - 128, N) * 128 * (p - 128));
+  return g + 64;
+}
+
 // Layout of the workspace (doubles): five N x p panels, the split-K / Gram
 // scratch, then the p x p blocks, theta, residuals, control words and the
 // direct solver's work for the p x p Rayleigh quotient.
 size_t chefsi_work_doubles(int64_t N, int k) {
   const int p = chefsi_block(k);
   const size_t panel = (size_t)N * p;
-  const size_t gws = std::max((size_t)8 * panel, ts_gram_ws(N, p)) + 64;
+  const size_t gws = chefsi_gws(N, p);
   return 5 * panel + gws + 4 * (size_t)p * p + 3 * (size_t)p + 64 + eig_work_doubles(p, p);
 }
 
@@ -245,7 +256,7 @@ int eig_topk_chefsi(hipStream_t st, int64_t N, const double *M, int k, double *l
   double *B[5];
   for (int q = 0; q < 5; ++q) B[q] = ws + q * panel;
   double *gws = ws + 5 * panel;
-  const size_t gws_len = std::max((size_t)8 * panel, ts_gram_ws(N, p)) + 64;
+  const size_t gws_len = chefsi_gws(N, p);
   const size_t pp = (size_t)p * p;
   double *G = gws + gws_len, *Out = G + pp, *H = Out + pp, *Qv = H + pp;
   double *theta = Qv + pp, *rj = theta + p;

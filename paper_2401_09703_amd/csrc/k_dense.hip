@@ -15,18 +15,38 @@ typedef short s16x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 // ------------------------------------------------------------------ FP64 GEMM
-constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+// Tile 64 x BN (BN 64, or 32 for widths 64 q + 32 such as the 96- and
+// 160-column panels, where 64-wide tiles would spend a quarter or a sixth of
+// the products on zero columns), stages of 64 along K.  A stage of both
+// operands is loaded into registers in one go (every load of the stage in
+// flight at once), stored to LDS k-major, and the next stage's loads are
+// issued before this stage's products, so that a block waits for memory
+// about once per stage rather than once per MFMA step.  On gfx950 an FP64
+// MFMA 16x16x4 occupies its SIMD for 64 cycles (128 flops per clock per CU),
+// so a product is spread over enough blocks to keep every CU's four SIMDs
+// busy: the operands here are small (N x p panels, N ~ 10^3) and each
+// product is only a few stages deep.
+constexpr int GB_M = 64, GB_K = 64, GB_LDA = GB_K + 1;
 typedef double gm_d4 __attribute__((ext_vector_type(4)));
+
+template <int BN>
+constexpr size_t gemm_lds_bytes() {
+  return ((size_t)GB_K * GB_LDA + (size_t)GB_K * (BN + 1)) * sizeof(double);
+}
 
 // With part != nullptr the launch is split over K: block z sums the products
 // of k in [z*kchunk, (z+1)*kchunk) and writes alpha times its partial sum to
 // part[z][M][N] (beta is ignored; k_gemm_reduce finishes).
-template <bool TA, bool TB>
+template <bool TA, bool TB, int BN>
 __global__ void __launch_bounds__(256)
 k_gemm_f64(int64_t M, int64_t N, int64_t Kfull, double alpha, const double *__restrict__ A,
            int64_t lda, const double *__restrict__ B, int64_t ldb, double beta,
            double *__restrict__ C, int64_t ldc, int64_t kchunk, double *__restrict__ part,
            const SvDevInfo *__restrict__ info) {
+  static_assert(BN == 32 || BN == 64, "tile width");
+  constexpr int LDB = BN + 1;
+  constexpr int TM = BN == 64 ? 2 : 1;   // 16-row MFMA tiles per wave
+  constexpr int NA = GB_M * GB_K / 256, NB = BN * GB_K / 256;   // loads per thread
   if (info && info->status) return;
   int64_t K = Kfull;
   if (part) {
@@ -36,47 +56,76 @@ k_gemm_f64(int64_t M, int64_t N, int64_t Kfull, double alpha, const double *__re
     A += TA ? kb * lda : kb;
     B += TB ? kb : kb * ldb;
   }
-  __shared__ double As[GB_K][GB_M + 1];
-  __shared__ double Bs[GB_K][GB_N + 1];
+  extern __shared__ double gsm[];
+  double *As = gsm, *Bs = gsm + GB_K * GB_LDA;   // [k][row], [k][col]
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;   // the wave's 32 x 32 quadrant
-  const int64_t m0 = (int64_t)blockIdx.y * GB_M, n0 = (int64_t)blockIdx.x * GB_N;
-  gm_d4 acc[2][2];
+  // the wave's block of the tile: a 32 x 32 quadrant (BN 64) or a 16 x 32
+  // strip (BN 32)
+  const int wm = BN == 64 ? (w >> 1) * 32 : 16 * w, wn = BN == 64 ? (w & 1) * 32 : 0;
+  const int64_t m0 = (int64_t)blockIdx.y * GB_M, n0 = (int64_t)blockIdx.x * BN;
+  // element e = tid + 256 t of a stage: consecutive threads take consecutive
+  // addresses of the operand in memory (a row of A, a column of A^T, ...)
+  auto a_ip = [&](int t, int &i, int &p) {
+    const int e = tid + 256 * t;
+    if (TA) { i = e & 63; p = e >> 6; } else { p = e & 63; i = e >> 6; }
+  };
+  auto b_jq = [&](int t, int &j, int &q) {
+    const int e = tid + 256 * t;
+    if (TB) { q = e & 63; j = e >> 6; } else { j = e % BN; q = e / BN; }
+  };
+  double ra[NA], rb[NB];
+  auto load = [&](int64_t k0) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < NA; ++t) {
+      int i, p;
+      a_ip(t, i, p);
+      const int64_t gi = m0 + i, gp = k0 + p;
+      ra[t] = (gi < M && gp < K) ? (TA ? A[gp * lda + gi] : A[gi * lda + gp]) : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      int j, q;
+      b_jq(t, j, q);
+      const int64_t gj = n0 + j, gq = k0 + q;
+      rb[t] = (gj < N && gq < K) ? (TB ? B[gj * ldb + gq] : B[gq * ldb + gj]) : 0.0;
+    }
+  };
+  gm_d4 acc[TM][2];
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u) acc[t][u] = gm_d4{0.0, 0.0, 0.0, 0.0};
+  if (K > 0) load(0);
   for (int64_t k0 = 0; k0 < K; k0 += GB_K) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = tid + t * 256;  // 0..1023
+    for (int t = 0; t < NA; ++t) {
       int i, p;
-      if (!TA) { p = e & 15; i = e >> 4; } else { i = e & 63; p = e >> 6; }
-      const int64_t gi = m0 + i, gp = k0 + p;
-      double v = 0.0;
-      if (gi < M && gp < K) v = TA ? A[gp * lda + gi] : A[gi * lda + gp];
-      As[p][i] = v;
+      a_ip(t, i, p);
+      As[p * GB_LDA + i] = ra[t];
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
       int j, q;
-      if (TB) { q = e & 15; j = e >> 4; } else { j = e & 63; q = e >> 6; }
-      const int64_t gj = n0 + j, gq = k0 + q;
-      double u = 0.0;
-      if (gj < N && gq < K) u = TB ? B[gj * ldb + gq] : B[gq * ldb + gj];
-      Bs[q][j] = u;
+      b_jq(t, j, q);
+      Bs[q * LDB + j] = rb[t];
     }
     __syncthreads();
+    if (k0 + GB_K < K) load(k0 + GB_K);
     // v_mfma_f64_16x16x4: A[m][k] from lane (m, k) = (l % 16, l / 16), B[k][n]
-    // from lane (k, n) = (l / 16, l % 16)
+    // from lane (k, n) = (l / 16, l % 16).  A short last stage is zero
+    // beyond K and runs whole: a branch per step would keep the compiler
+    // from reading the next step's operands during this step's products.
 #pragma unroll
     for (int kk = 0; kk < GB_K; kk += 4) {
-      double a[2], b[2];
+      double a[TM], b[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) a[t] = As[kk + lk][wm + 16 * t + li];
+      for (int t = 0; t < TM; ++t) a[t] = As[(kk + lk) * GB_LDA + wm + 16 * t + li];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) b[u] = Bs[kk + lk][wn + 16 * u + li];
+      for (int u = 0; u < 2; ++u) b[u] = Bs[(kk + lk) * LDB + wn + 16 * u + li];
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
+      for (int t = 0; t < TM; ++t)
 #pragma unroll
         for (int u = 0; u < 2; ++u)
           acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
@@ -85,7 +134,7 @@ k_gemm_f64(int64_t M, int64_t N, int64_t Kfull, double alpha, const double *__re
   }
   // D[m][n] of a 16 x 16 tile sits in lane n + 16 (m % 4), element m / 4
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < TM; ++t)
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -959,25 +1008,49 @@ void gemm_f64(hipStream_t st, bool tA, bool tB, int64_t M, int64_t N, int64_t K,
   gemm_f64_sk(st, tA, tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, nullptr, 0, info);
 }
 
+// 64-wide column tiles, or 32-wide for widths 64 q + r with 0 < r <= 32
+static int gemm_tile_n(int64_t N) { return (N % 64 != 0 && N % 64 <= 32) ? 32 : 64; }
+
+// split K when the tiles alone leave CUs idle: about two blocks per CU,
+// chunks whole stages, at most 64 (and at most max_parts) partial sums
+static int64_t gemm_split_count(int64_t M, int64_t N, int64_t K, int64_t max_parts) {
+  const int BN = gemm_tile_n(N);
+  const int64_t tiles = ((N + BN - 1) / BN) * ((M + GB_M - 1) / GB_M);
+  if (tiles >= 256 || K < 4 * GB_K) return 1;
+  const int64_t stages = (K + GB_K - 1) / GB_K;
+  int64_t splits = std::min<int64_t>(stages, (512 + tiles - 1) / tiles);
+  splits = std::max<int64_t>(1, std::min<int64_t>({splits, max_parts, 64}));
+  const int64_t per = (stages + splits - 1) / splits;   // stages per split
+  return (stages + per - 1) / per;
+}
+
+int64_t gemm_f64_splits(int64_t M, int64_t N, int64_t K) {
+  return gemm_split_count(M, N, K, 64);
+}
+
 void gemm_f64_sk(hipStream_t st, bool tA, bool tB, int64_t M, int64_t N, int64_t K, double alpha,
                  const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
                  double *C, int64_t ldc, double *ws, size_t ws_len, const SvDevInfo *info) {
   if (M <= 0 || N <= 0) return;
-  const int64_t tiles = ((N + GB_N - 1) / GB_N) * ((M + GB_M - 1) / GB_M);
-  int64_t splits = 1;
-  if (ws && tiles < 128 && K >= 512) {
-    splits = (256 + tiles - 1) / tiles;
-    const int64_t by_k = K / 128;
-    if (splits > by_k) splits = by_k;
-    const int64_t by_ws = (int64_t)(ws_len / (size_t)(M * N));
-    if (splits > by_ws) splits = by_ws;
-    if (splits > 64) splits = 64;
-  }
+  const int BN = gemm_tile_n(N);
+  const int64_t by_ws = ws ? (int64_t)(ws_len / (size_t)(M * N)) : 1;
+  const int64_t splits = gemm_split_count(M, N, K, by_ws);
   double *part = splits > 1 ? ws : nullptr;
-  const int64_t kchunk = splits > 1 ? (K + splits - 1) / splits : K;
-  dim3 grid((unsigned)((N + GB_N - 1) / GB_N), (unsigned)((M + GB_M - 1) / GB_M),
+  const int64_t kchunk =
+      splits > 1 ? ((K + GB_K - 1) / GB_K + splits - 1) / splits * GB_K : K;
+  dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + GB_M - 1) / GB_M),
             (unsigned)splits);
-#define SV_GM(TA_, TB_) hipLaunchKernelGGL((k_gemm_f64<TA_, TB_>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, info)
+  static const bool once = [] {
+    allow_big_lds(k_gemm_f64<false, false, 64>); allow_big_lds(k_gemm_f64<false, true, 64>);
+    allow_big_lds(k_gemm_f64<true, false, 64>); allow_big_lds(k_gemm_f64<true, true, 64>);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)once;
+#define SV_GM(TA_, TB_) do { \
+    if (BN == 64) hipLaunchKernelGGL((k_gemm_f64<TA_, TB_, 64>), grid, dim3(256), gemm_lds_bytes<64>(), st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, info); \
+    else hipLaunchKernelGGL((k_gemm_f64<TA_, TB_, 32>), grid, dim3(256), gemm_lds_bytes<32>(), st, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, kchunk, part, info); \
+  } while (0)
   if (!tA && !tB) SV_GM(false, false);
   else if (!tA && tB) SV_GM(false, true);
   else if (tA && !tB) SV_GM(true, false);

@@ -365,15 +365,18 @@ k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d
     // row i: alpha = x_{i+1}, ||x_{i+2..}||^2 and d_i (every lane computes,
     // only the group of row i has nonzero terms)
     {
+      // (sums in four interleaved chains: a dependent FP64 add costs ~13 ns)
       double ss = 0.0, al = 0.0, di = 0.0;
       if (r == i) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int j = 0; j < TR_CPT; ++j) {
           const int c = s + 8 * j;
-          if (c >= i + 2 && c < N) ss += a[j] * a[j];
+          if (c >= i + 2 && c < N) s4[j & 3] += a[j] * a[j];
           if (c == i + 1) al = a[j];
           if (c == i) di = a[j];
         }
+        ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
       }
       ss = sum8(ss);
       al = sum8(al);
@@ -416,10 +419,10 @@ k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d
       double vv[TR_CPT];
 #pragma unroll
       for (int j = 0; j < TR_CPT; ++j) vv[j] = vb[b][s + 8 * j];
-      double acc = 0.0;
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < TR_CPT; ++j) acc += a[j] * vv[j];
-      acc = sum8(acc);
+      for (int j = 0; j < TR_CPT; ++j) a4[j & 3] += a[j] * vv[j];
+      const double acc = sum8((a4[0] + a4[1]) + (a4[2] + a4[3]));
       const bool act = r > i && r < N;
       pr = act ? t * acc : 0.0;
       vr = act ? vb[b][r] : 0.0;
@@ -432,9 +435,10 @@ k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d
     if (lane == 0) part[b][w] = pv;
     __syncthreads();
     if (wact) {
-      double pvs = 0.0;
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < TR_NT / 64; ++q) pvs += part[b][q];
+      for (int q = 0; q < TR_NT / 64; ++q) p4[q & 3] += part[b][q];
+      const double pvs = (p4[0] + p4[1]) + (p4[2] + p4[3]);
       const double K = 0.5 * t * pvs;
       const double wr = pr - K * vr;
       double pp[TR_CPT];

@@ -92,6 +92,9 @@ void gemm_f64_sk(hipStream_t st, bool transA, bool transB, int64_t M, int64_t N,
                  double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
                  double beta, double *C, int64_t ldc, double *ws, size_t ws_len,
                  const SvDevInfo *info);
+// The number of partial products gemm_f64_sk splits an M x N x K product
+// into when ws_len does not limit it (1: not split).
+int64_t gemm_f64_splits(int64_t M, int64_t N, int64_t K);
 // G[i][j] -= sum_l C[i][l] C[j][l] on the lower-triangular tiles, with C
 // (s x K, float) multiplied on MFMA: mode 1 FP32, mode 2 BF16x3.
 void gram_lowp(hipStream_t st, int mode, int64_t s, int K, const float *C, double *G,
