@@ -266,6 +266,14 @@ svlcov_status svlcov_get_stats(svlcov_state *h, svlcov_stats *out);
  * backtransform unless it falls back to them). */
 #define SVLCOV_NUM_PHASES 17
 svlcov_status svlcov_profile(svlcov_state *h, int32_t enable);
+/* Profiling of some phases only: bit i of mask (phases numbered as
+ * svlcov_phase_name numbers them) times phase i; mask 0 turns profiling
+ * off, and svlcov_profile(h, 1) is the mask of every phase.  Each timed
+ * occurrence of a phase records two events on the state's stream, host
+ * work that can hold up the launches of a short update, so a timed run
+ * that needs one phase's duration times that phase alone.  Bits at or
+ * above SVLCOV_NUM_PHASES: SVLCOV_E_INVALID. */
+svlcov_status svlcov_profile_phases(svlcov_state *h, uint32_t mask);
 svlcov_status svlcov_phase_times(svlcov_state *h, double *ms, int64_t *count, int32_t n);
 const char *svlcov_phase_name(int32_t i);
 

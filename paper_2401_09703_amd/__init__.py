@@ -144,7 +144,7 @@ class _ServerStats(C.Structure):
 EXPORTS = ["svlcov_default_options", "svlcov_init", "svlcov_add_rows", "svlcov_add_cols",
            "svlcov_update_weights", "svlcov_get_factors", "svlcov_query_row", "svlcov_sync",
            "svlcov_get_stats", "svlcov_stream", "svlcov_destroy", "svlcov_status_str",
-           "svlcov_profile", "svlcov_phase_times", "svlcov_phase_name",
+           "svlcov_profile", "svlcov_profile_phases", "svlcov_phase_times", "svlcov_phase_name",
            "svlcov_sym_eig_topk", "svlcov_server_default_options", "svlcov_server_create",
            "svlcov_server_attach", "svlcov_server_submit", "svlcov_server_wait",
            "svlcov_server_poll", "svlcov_server_drain", "svlcov_server_get_stats",
@@ -191,6 +191,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.svlcov_destroy.restype = None
     lib.svlcov_profile.argtypes = [P, I32]
     lib.svlcov_profile.restype = I32
+    lib.svlcov_profile_phases.argtypes = [P, C.c_uint32]
+    lib.svlcov_profile_phases.restype = I32
     lib.svlcov_phase_times.argtypes = [P, P, P, I32]
     lib.svlcov_phase_times.restype = I32
     lib.svlcov_phase_name.argtypes = [I32]
@@ -572,8 +574,19 @@ class TruncatedSVD:
         _check(_lib.svlcov_get_stats(self._h, C.byref(st)), "svlcov_get_stats")
         return {f: getattr(st, f) for f, _ in _Stats._fields_}
 
-    def profile(self, enable: bool = True):
-        _check(_lib.svlcov_profile(self._h, 1 if enable else 0), "svlcov_profile")
+    def profile(self, enable: bool = True, phases=None):
+        """Time every phase of the following updates, or only the named ones
+        (svlcov_profile_phases)."""
+        if phases is None or not enable:
+            _check(_lib.svlcov_profile(self._h, 1 if enable else 0), "svlcov_profile")
+            return
+        names = [_lib.svlcov_phase_name(i).decode() for i in range(NUM_PHASES)]
+        mask = 0
+        for name in phases:
+            if name not in names:
+                raise ValueError(f"unknown phase {name!r}")
+            mask |= 1 << names.index(name)
+        _check(_lib.svlcov_profile_phases(self._h, mask), "svlcov_profile_phases")
 
     def phase_times(self) -> dict:
         """{phase name: (total ms, occurrences)} since the previous call."""

@@ -74,7 +74,7 @@ struct PhaseScope {
   int ph;
   hipEvent_t a = nullptr;
   PhaseScope(svlcov_state *hh, int p) : h(hh), ph(p) {
-    if (h->prof) {
+    if (h->prof && ((h->prof_mask >> p) & 1u)) {
       a = get_event(h);
       if (a) (void)hipEventRecord(a, h->stream);
     }
@@ -1626,6 +1626,15 @@ void *svlcov_stream(svlcov_state *h) { return h ? (void *)h->stream : nullptr; }
 svlcov_status svlcov_profile(svlcov_state *h, int32_t enable) {
   if (!h) return SVLCOV_E_INVALID;
   h->prof = enable != 0;
+  h->prof_mask = ~0u;
+  return SVLCOV_OK;
+}
+
+svlcov_status svlcov_profile_phases(svlcov_state *h, uint32_t mask) {
+  if (!h) return SVLCOV_E_INVALID;
+  if (mask >> SVLCOV_NUM_PHASES) return SVLCOV_E_INVALID;
+  h->prof = mask != 0;
+  h->prof_mask = mask;
   return SVLCOV_OK;
 }
 

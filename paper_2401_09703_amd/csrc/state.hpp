@@ -72,6 +72,7 @@ struct svlcov_state {
   std::vector<svl_state::Snapshot> history;
   std::atomic<bool> busy{false};
   bool prof = false;
+  uint32_t prof_mask = ~0u;   // phases timed while prof is set
   std::vector<svl_state::EvRec> recs;
   std::vector<hipEvent_t> evpool;
   // Set while a request server drives the state: every cooperative launch
