@@ -445,90 +445,62 @@ k_chol_inv_small(int K, const double *__restrict__ Gm, double *__restrict__ Linv
   }
 }
 
-// Cholesky factor L of the K x K Gram Gm (K <= 128), left-looking, by one
-// block of 256 threads: per column j, a pair of threads owns each row i >= j
-// (alternate terms of the dot products, loads issued 8 at a time); every
-// thread also forms the pivot d_j = G_jj - sum_p L_jp^2 itself (broadcast
-// reads of row j), so the column needs only the barrier that publishes it.
-// A non-positive pivot is taken as 1 (the rows are then far from
-// orthonormal, which the caller's checks catch).  L (K x K, zeros above the
-// diagonal) is written to global memory.
-constexpr int CS_NT = 256;
-
-__global__ void __launch_bounds__(CS_NT)
-k_chol_small(int K, const double *__restrict__ Gm, double *__restrict__ L,
-             const SvDevInfo *__restrict__ info) {
-  if (info->status) return;
-  extern __shared__ double Ls[];   // K x (K + 1), lower triangle
-  const int LD = K + 1;
-  const int tid = threadIdx.x, h = tid & 1, q = tid >> 1;
-  for (int e = tid; e < K * K; e += CS_NT) {
-    const int i = e / K, j = e % K;
-    if (j <= i) Ls[i * LD + j] = Gm[e];
-  }
-  __syncthreads();
-  for (int j = 0; j < K; ++j) {
-    const int i = j + q;
-    const bool act = i < K;
-    const double *Lj = Ls + j * LD;
-    const double *Li = Ls + (act ? i : j) * LD;
-    double di = 0.0, dj = 0.0;
-    for (int p0 = h; p0 < j; p0 += 16) {
-      double a[8], b[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int p = p0 + 2 * u;
-        const int pp = p < j ? p : 0;
-        a[u] = Li[pp];
-        b[u] = Lj[pp];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (p0 + 2 * u < j) { di += a[u] * b[u]; dj += b[u] * b[u]; }
-    }
-    di += __shfl_xor(di, 1, 64);
-    dj += __shfl_xor(dj, 1, 64);
-    const double d = Lj[j] - dj;
-    const double sd = d > 0.0 ? sqrt(d) : 1.0;
-    __syncthreads();   // every read of column j's inputs is done
-    if (act && h == 0) Ls[i * LD + j] = (i == j) ? sd : (Li[j] - di) / sd;
-    __syncthreads();
-  }
-  for (int e = tid; e < K * K; e += CS_NT) {
-    const int i = e / K, j = e % K;
-    L[e] = j <= i ? Ls[i * LD + j] : 0.0;
-  }
-}
-
-// X <- L^{-1} X for the K rows of X (K x N, row stride N): one thread per
-// column of X, the column in registers, L broadcast from LDS; forward
-// substitution fully unrolled.
-template <int K>
+// L^{-1} of the Cholesky factor of the K x K Gram Gm (K <= KM = 64) by one
+// wave, right-looking: lane i holds row i of the reduced matrix and row i of
+// the inverse in registers.  Per column j the pivot comes from lane j by
+// readlane, every lane forms its multiplier l_ij from its own entry, and the
+// column of multipliers and the finished row j of the inverse pass through
+// LDS (one store per lane, broadcast reads) for the rank-1 updates
+// a_ic -= l_ij l_cj and z_i -= l_ij z_j.  Rows at or above j take a zero
+// multiplier.  A non-positive pivot is taken as 1 (the rows are then far
+// from orthonormal, which the caller's checks catch).  Linv (K x K, zeros
+// above the diagonal) is written to global memory.
+template <int KM>
 __global__ void __launch_bounds__(64)
-k_trsm_rows(int64_t N, const double *__restrict__ L, double *__restrict__ X,
-            const SvDevInfo *__restrict__ info) {
+k_chol_inv_wave(int K, const double *__restrict__ Gm, double *__restrict__ Linv,
+                const SvDevInfo *__restrict__ info) {
   if (info->status) return;
-  __shared__ double Ls[K * K];
-  __shared__ double dinv[K];
-  for (int e = threadIdx.x; e < K * K; e += 64) Ls[e] = L[e];
-  __syncthreads();
-  for (int i = threadIdx.x; i < K; i += 64) dinv[i] = 1.0 / Ls[i * K + i];
-  __syncthreads();
-  const int64_t n = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (n >= N) return;
-  double x[K];
+  __shared__ double col[KM];
+  __shared__ double zr[KM];
+  const int i = threadIdx.x;
+  double a[KM], z[KM];
 #pragma unroll
-  for (int i = 0; i < K; ++i) x[i] = X[(int64_t)i * N + n];
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    // four independent partial sums, so the FMAs do not form one chain
-    double acc[4] = {x[i], 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int p = 0; p < i; ++p) acc[p & 3] -= Ls[i * K + p] * x[p];
-    x[i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * dinv[i];
+  for (int c = 0; c < KM; ++c) {
+    a[c] = (i < K && c <= i) ? Gm[(int64_t)i * K + c] : 0.0;
+    z[c] = c == i ? 1.0 : 0.0;
   }
 #pragma unroll
-  for (int i = 0; i < K; ++i) X[(int64_t)i * N + n] = x[i];
+  for (int j = 0; j < KM; ++j) {
+    if (j < K) {
+      const double d = readlane_dbl(a[j], j);
+      const double sd = d > 0.0 ? sqrt(d) : 1.0;
+      const double r = 1.0 / sd;
+      const double l = a[j] * r;
+      const double f = i == j ? r : 1.0;
+#pragma unroll
+      for (int c = 0; c <= j; ++c) z[c] *= f;   // row j of the inverse is final
+      col[i] = l;
+      if (i == j) {
+#pragma unroll
+        for (int c = 0; c <= j; ++c) zr[c] = z[c];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double li = i > j ? l : 0.0;
+#pragma unroll
+      for (int c = j + 1; c < KM; ++c) a[c] -= li * col[c];
+#pragma unroll
+      for (int c = 0; c <= j; ++c) z[c] -= li * zr[c];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  if (i < K)
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < K) Linv[(int64_t)i * K + c] = c <= i ? z[c] : 0.0;
 }
 
 __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
@@ -1138,7 +1110,6 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
   // thread-safe one-time set-up (dispatch may run on several host threads)
   static const bool once = [] {
     allow_big_lds(k_chol_inv_small);
-    allow_big_lds(k_chol_small);
     (void)hipGetLastError();
     return true;
   }();
@@ -1146,20 +1117,19 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
   // One Cholesky QR pass: the rows come in orthonormal to a few ulps (or, for
   // completion rows, as random vectors far from the span of the others), and
   // the orthogonality CholQR leaves is ~ u kappa^2 with kappa ~ 1 here.
+  // L^{-1} by one wave (K <= 64) or one block, then X <- L^{-1} X as a GEMM
+  // (each output row its own dot products, no chain through earlier rows).
   gemm_f64_sk(st, false, true, K, K, N, 1.0, X, N, X, N, 0.0, Gm, K, ws, ws_len, info);
-  if (K <= 64) {   // L by the left-looking kernel, then X <- L^{-1} X in place
-    const size_t sh = (size_t)K * (K + 1) * sizeof(double);
-    hipLaunchKernelGGL(k_chol_small, dim3(1), dim3(CS_NT), sh, st, K, Gm, Linv, info);
-    const unsigned nb = (unsigned)((N + 63) / 64);
-    switch (K) {
-      case 16: hipLaunchKernelGGL((k_trsm_rows<16>), dim3(nb), dim3(64), 0, st, N, Linv, X, info); break;
-      case 32: hipLaunchKernelGGL((k_trsm_rows<32>), dim3(nb), dim3(64), 0, st, N, Linv, X, info); break;
-      default: hipLaunchKernelGGL((k_trsm_rows<64>), dim3(nb), dim3(64), 0, st, N, Linv, X, info); break;
-    }
-    return;
+  if (K == 16) {
+    hipLaunchKernelGGL((k_chol_inv_wave<16>), dim3(1), dim3(64), 0, st, K, Gm, Linv, info);
+  } else if (K == 32) {
+    hipLaunchKernelGGL((k_chol_inv_wave<32>), dim3(1), dim3(64), 0, st, K, Gm, Linv, info);
+  } else if (K == 64) {
+    hipLaunchKernelGGL((k_chol_inv_wave<64>), dim3(1), dim3(64), 0, st, K, Gm, Linv, info);
+  } else {
+    const size_t sh = (size_t)(K * (K + 1) + K) * sizeof(double);
+    hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(SMALL_NT), sh, st, K, Gm, Linv, info);
   }
-  const size_t sh = (size_t)(K * (K + 1) + K) * sizeof(double);
-  hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(SMALL_NT), sh, st, K, Gm, Linv, info);
   gemm_f64(st, false, false, K, N, K, 1.0, Linv, K, X, N, 0.0, Xtmp, N, info);
   (void)hipMemcpyAsync(X, Xtmp, (size_t)K * N * sizeof(double), hipMemcpyDeviceToDevice, st);
 }
