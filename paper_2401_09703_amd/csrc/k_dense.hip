@@ -445,62 +445,47 @@ k_chol_inv_small(int K, const double *__restrict__ Gm, double *__restrict__ Linv
   }
 }
 
-// L^{-1} of the Cholesky factor of the K x K Gram Gm (K <= KM = 64) by one
-// wave, right-looking: lane i holds row i of the reduced matrix and row i of
-// the inverse in registers.  Per column j the pivot comes from lane j by
-// readlane, every lane forms its multiplier l_ij from its own entry, and the
-// column of multipliers and the finished row j of the inverse pass through
-// LDS (one store per lane, broadcast reads) for the rank-1 updates
-// a_ic -= l_ij l_cj and z_i -= l_ij z_j.  Rows at or above j take a zero
-// multiplier.  A non-positive pivot is taken as 1 (the rows are then far
-// from orthonormal, which the caller's checks catch).  Linv (K x K, zeros
-// above the diagonal) is written to global memory.
-template <int KM>
+// L^{-1} of the Cholesky factor of the K x K Gram Gm (K <= 64) by one wave,
+// right-looking: lane i holds row i of the reduced matrix and row i of the
+// inverse in registers.  Per column j the pivot, the column of multipliers
+// l_cj and the finished row j of the inverse reach the other lanes by
+// readlane (no LDS and no barriers, so the whole factorisation is one block
+// of straight-line code the compiler can schedule across columns), for the
+// rank-1 updates a_ic -= l_ij l_cj and z_i -= l_ij z_j.  Rows at or above j
+// take a zero multiplier.  A non-positive pivot is taken as 1 (the rows are
+// then far from orthonormal, which the caller's checks catch).  Linv (K x K,
+// zeros above the diagonal) is written to global memory.
+template <int K>
 __global__ void __launch_bounds__(64)
-k_chol_inv_wave(int K, const double *__restrict__ Gm, double *__restrict__ Linv,
+k_chol_inv_wave(const double *__restrict__ Gm, double *__restrict__ Linv,
                 const SvDevInfo *__restrict__ info) {
+  static_assert(K <= 64, "one row per lane");
   if (info->status) return;
-  __shared__ double col[KM];
-  __shared__ double zr[KM];
   const int i = threadIdx.x;
-  double a[KM], z[KM];
+  double a[K], z[K];
 #pragma unroll
-  for (int c = 0; c < KM; ++c) {
-    a[c] = (i < K && c <= i) ? Gm[(int64_t)i * K + c] : 0.0;
+  for (int c = 0; c < K; ++c) {
+    a[c] = (i < K && c <= i) ? Gm[i * K + c] : 0.0;
     z[c] = c == i ? 1.0 : 0.0;
   }
 #pragma unroll
-  for (int j = 0; j < KM; ++j) {
-    if (j < K) {
-      const double d = readlane_dbl(a[j], j);
-      const double sd = d > 0.0 ? sqrt(d) : 1.0;
-      const double r = 1.0 / sd;
-      const double l = a[j] * r;
-      const double f = i == j ? r : 1.0;
+  for (int j = 0; j < K; ++j) {
+    const double d = readlane_dbl(a[j], j);
+    const double sd = d > 0.0 ? sqrt(d) : 1.0;
+    const double r = 1.0 / sd;
+    const double l = a[j] * r;   // l_ij in lane i > j
+    const double li = i > j ? l : 0.0;
 #pragma unroll
-      for (int c = 0; c <= j; ++c) z[c] *= f;   // row j of the inverse is final
-      col[i] = l;
-      if (i == j) {
-#pragma unroll
-        for (int c = 0; c <= j; ++c) zr[c] = z[c];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const double li = i > j ? l : 0.0;
-#pragma unroll
-      for (int c = j + 1; c < KM; ++c) a[c] -= li * col[c];
-#pragma unroll
-      for (int c = 0; c <= j; ++c) z[c] -= li * zr[c];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int c = 0; c <= j; ++c) {   // row j of the inverse is final once scaled
+      const double zj = readlane_dbl(z[c], j) * r;
+      z[c] = i == j ? zj : z[c] - li * zj;
     }
+#pragma unroll
+    for (int c = j + 1; c < K; ++c) a[c] -= li * readlane_dbl(l, c);
   }
   if (i < K)
 #pragma unroll
-    for (int c = 0; c < KM; ++c)
-      if (c < K) Linv[(int64_t)i * K + c] = c <= i ? z[c] : 0.0;
+    for (int c = 0; c < K; ++c) Linv[i * K + c] = c <= i ? z[c] : 0.0;
 }
 
 __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
@@ -1121,11 +1106,11 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
   // (each output row its own dot products, no chain through earlier rows).
   gemm_f64_sk(st, false, true, K, K, N, 1.0, X, N, X, N, 0.0, Gm, K, ws, ws_len, info);
   if (K == 16) {
-    hipLaunchKernelGGL((k_chol_inv_wave<16>), dim3(1), dim3(64), 0, st, K, Gm, Linv, info);
+    hipLaunchKernelGGL((k_chol_inv_wave<16>), dim3(1), dim3(64), 0, st, Gm, Linv, info);
   } else if (K == 32) {
-    hipLaunchKernelGGL((k_chol_inv_wave<32>), dim3(1), dim3(64), 0, st, K, Gm, Linv, info);
+    hipLaunchKernelGGL((k_chol_inv_wave<32>), dim3(1), dim3(64), 0, st, Gm, Linv, info);
   } else if (K == 64) {
-    hipLaunchKernelGGL((k_chol_inv_wave<64>), dim3(1), dim3(64), 0, st, K, Gm, Linv, info);
+    hipLaunchKernelGGL((k_chol_inv_wave<64>), dim3(1), dim3(64), 0, st, Gm, Linv, info);
   } else {
     const size_t sh = (size_t)(K * (K + 1) + K) * sizeof(double);
     hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(SMALL_NT), sh, st, K, Gm, Linv, info);
