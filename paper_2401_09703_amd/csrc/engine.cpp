@@ -72,21 +72,57 @@ hipEvent_t get_event(svlcov_state *h) {
 struct PhaseScope {
   svlcov_state *h;
   int ph;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  PhaseScope(svlcov_state *hh, int p) : h(hh), ph(p) {
+  PhaseScope(svlcov_state *hh, int p, hipStream_t s = nullptr)
+      : h(hh), ph(p), st(s ? s : hh->stream) {
     if (h->prof && ((h->prof_mask >> p) & 1u)) {
       a = get_event(h);
-      if (a) (void)hipEventRecord(a, h->stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~PhaseScope() {
     if (!a) return;
     hipEvent_t b = get_event(h);
     if (!b) return;
-    (void)hipEventRecord(b, h->stream);
+    (void)hipEventRecord(b, st);
     h->recs.push_back({ph, a, b});
   }
 };
+
+// The append form's M = K K^T is assembled from sigma, C' and the sparse Gram
+// alone, so the eigensolver does not wait for the residual Gram's Cholesky:
+// when the eigensolver is the subspace iteration without cooperative kernels
+// (basis of at most 128 columns), the Cholesky and K go to a second stream
+// and the two meet before G = K^T F.  SVLCOV_NO_OVERLAP=1 keeps one stream.
+bool side_stream(svlcov_state *h, int64_t N, int K) {
+  static const bool off = [] {
+    const char *ev = getenv("SVLCOV_NO_OVERLAP");
+    return ev && atoi(ev) != 0;
+  }();
+  if (off || h->prec == SVLCOV_FP64 || !svl::chefsi_applies(N, K) || svl::chefsi_block(K) > 128)
+    return false;
+  if (!h->side) {
+    hipStream_t sd = nullptr;
+    if (hipStreamCreateWithFlags(&sd, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+      h->ev_fork = nullptr;
+      (void)hipStreamDestroy(sd);
+      return false;
+    }
+    h->side = sd;
+    int n = 0;
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, h->device);
+    h->ncu = n > 0 ? n : 1;
+  }
+  return true;
+}
 
 #define SV_TRY(expr)                                   \
   do {                                                 \
@@ -295,14 +331,18 @@ namespace {
 
 // One side's orthogonalisation: projection, sparse Gram, residual Gram and its
 // Cholesky (Algorithm 2 realised as R^T R = E E^T - (E V)(E V)^T, Lemma 3).
+// cst: the stream of the residual Gram and the Cholesky (the state's unless
+// the caller runs them beside the eigensolver; it then orders cst after the
+// sparse Gram here and joins cst itself).
 template <typename T>
 void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double *W, double *Cp64,
                    float *Cp32, double *rown, double *Gm, double *Linv, int32_t *rid, int which,
                    bool chol = true, double *dws = nullptr, size_t dws_len = 0,
-                   double *Scopy = nullptr, int64_t lds_copy = 0) {
+                   double *Scopy = nullptr, int64_t lds_copy = 0, hipStream_t cst = nullptr) {
   const int K = h->k;
   const int64_t s = E.rows;
   hipStream_t st = h->stream;
+  if (!cst) cst = st;
   if (!h->proj_ready[which]) {
     PhaseScope ps(h, PH_SPMM);
     // the variants (no Cholesky) take C' accumulated in FP64: a Lanczos
@@ -321,25 +361,33 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
     // S = E E^T is also the trailing block of M = K K^T (R^T R = S - C' C'^T)
     if (Scopy) svl::copy_strided(st, s, s, Gm, s, 1, Scopy, lds_copy, h->info);
   }
+  if (cst != st) {
+    (void)hipEventRecord(h->ev_fork, st);
+    (void)hipStreamWaitEvent(cst, h->ev_fork, 0);
+  }
   {
     // the approximate variants build their basis by a Lanczos or power
     // process on this Gram, which amplifies its rounding: FP64 for them in
     // every mode (the MFMA Gram otherwise)
-    PhaseScope ps(h, PH_RGRAM);
+    PhaseScope ps(h, PH_RGRAM, cst);
     if (h->prec == SVLCOV_FP64 || !chol)
-      svl::gemm_f64(st, false, true, s, s, K, -1.0, Cp64, K, Cp64, K, 1.0, Gm, s, h->info);
+      svl::gemm_f64(cst, false, true, s, s, K, -1.0, Cp64, K, Cp64, K, 1.0, Gm, s, h->info);
     else
-      svl::gram_lowp(st, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
+      svl::gram_lowp(cst, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
   }
   if (!chol) return;   // the approximate variants use the Gram itself
-  PhaseScope ps(h, PH_CHOL);
-  coop_enter(h);
-  const int crc = svl::cholesky_coop(st, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags,
-                                     &h->epoch);
-  coop_exit(h);
+  // beside the eigensolver the Cholesky takes at most half the CUs: with a
+  // block per CU it kept the eigensolver's products from starting (its
+  // chain of diagonal blocks, not its trailing products, sets its time;
+  // at s = 1000 it runs as fast with 125 blocks as with 250)
+  PhaseScope ps(h, PH_CHOL, cst);
+  coop_enter(h, cst);
+  const int crc = svl::cholesky_coop(cst, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags,
+                                     &h->epoch, cst != st ? std::max(1, h->ncu / 2) : 0);
+  coop_exit(h, cst);
   if (crc) {
     h->launch_failed = true;
-    svl::set_status(st, h->info, SVLCOV_E_DEVICE);
+    svl::set_status(cst, h->info, SVLCOV_E_DEVICE);
   }
 }
 
@@ -347,9 +395,13 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
 // F (rows of Fv) are the left singular vectors, theta the singular values,
 // G = K^T F diag(theta)^{-1} the right ones (rows of Gv); both sets are
 // re-orthonormalised, with an orthonormal completion where theta vanishes.
+// join: an event on the stream that forms K (NULL: K is formed on the
+// state's stream); the state's stream waits for it before anything needs K
+// and before a cooperative kernel could run beside the Cholesky.
 svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mmat, double *lam,
                             double *theta, int32_t *complete, double *Fv, double *Gv,
-                            double *eigw, double *gram_kk, const double *Cp_border = nullptr) {
+                            double *eigw, double *gram_kk, const double *Cp_border = nullptr,
+                            hipEvent_t join = nullptr) {
   const int K = h->k;
   hipStream_t st = h->stream;
   {
@@ -396,6 +448,7 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
       }
     }
   }
+  if (join) (void)hipStreamWaitEvent(st, join, 0);
   if (!solved) {
     {
       PhaseScope ps(h, PH_TRIDIAG);
@@ -587,16 +640,21 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
     svl::validate_csr(st, dE.rows, dE.cols, dE.nnz, dE.rp, dE.ci, dE.v, dE.vdt, h->info, h->seq);
   }
   svl::op_begin(st, h->info, 0);
+  // the residual Gram's Cholesky and K beside the eigensolver where they can
+  const bool overlap = side_stream(h, N, K);
+  hipStream_t cst = overlap ? h->side : st;
   // orthogonalise the augmented matrix of the sparse side
   orthogonalise<T>(h, dE, B_base, W_B, Cp64, Cp32, rown, Gm, Linv, rid, 0, true, Kmat,
                    (size_t)N * N,    // K is formed only after the Gram
-                   Mmat + (size_t)K * N + K, N);
+                   Mmat + (size_t)K * N + K, N, cst);
   // K = [[Sigma, 0], [E V, R^T]] and its Rayleigh-Ritz SVD
   {
-    PhaseScope ps(h, PH_BUILDK);
-    svl::build_K_rows(st, K, s, h->sigma, Cp64, Gm, s, Kmat, h->info);
+    PhaseScope ps(h, PH_BUILDK, cst);
+    svl::build_K_rows(cst, K, s, h->sigma, Cp64, Gm, s, Kmat, h->info);
   }
-  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p, Cp64);
+  if (overlap) (void)hipEventRecord(h->ev_join, cst);
+  r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p, Cp64,
+                    overlap ? h->ev_join : nullptr);
   if (r != SVLCOV_OK) return r;
   // append side: W_A F[:k]; its inverse and condition
   {
@@ -1690,7 +1748,11 @@ void svlcov_destroy(svlcov_state *h) {
   state_free(h, h->sigma, (size_t)h->k * 8);
   state_free(h, h->info, sizeof(SvDevInfo));
   state_free(h, h->flags, svl::TRI_FLAG_WORDS * sizeof(unsigned));
+  if (h->side) (void)hipStreamSynchronize(h->side);
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   for (const EvRec &r : h->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

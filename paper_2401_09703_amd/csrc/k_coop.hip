@@ -661,10 +661,12 @@ unsigned take_epochs(hipStream_t st, unsigned *flags, unsigned *epoch, unsigned 
 }
 
 int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv, double tol,
-                  SvDevInfo *info, int which, unsigned *flags, unsigned *epoch) {
+                  SvDevInfo *info, int which, unsigned *flags, unsigned *epoch, int max_blocks) {
   if (s <= 0) return 0;
   const int64_t nblk = (s + NB - 1) / NB;
-  const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), coop_want(s));
+  int want = coop_want(s);
+  if (max_blocks > 0 && want > max_blocks) want = max_blocks;
+  const int P = coop_blocks(reinterpret_cast<const void *>(k_chol_coop), want);
   unsigned e0 = take_epochs(st, flags, epoch, (unsigned)(2 * nblk + 1));
   void *args[] = {(void *)&s, (void *)&G, (void *)&ld, (void *)&tol, (void *)&info,
                   (void *)&which, (void *)&flags, (void *)&e0, (void *)&Linv};

@@ -108,10 +108,11 @@ constexpr int CHOL_NB = 32;
 // ---- cooperative (k_coop.hip): one launch each; flags/epoch as for eig_topk
 // G = L L^T in place (lower triangle); Linv receives the inverses of L's
 // diagonal blocks (ceil(s / CHOL_NB) blocks of CHOL_NB^2 doubles, rows and
-// columns of dropped pivots zero), which trsm_coop reads.
+// columns of dropped pivots zero), which trsm_coop reads.  max_blocks > 0
+// caps the launch (it then leaves CUs to work on other streams).
 int cholesky_coop(hipStream_t st, int64_t s, double *G, int64_t ld, double *Linv,
                   double rank_tol, SvDevInfo *info, int which, unsigned *flags,
-                  unsigned *epoch);
+                  unsigned *epoch, int max_blocks = 0);
 // Y <- L^{-T} Y (s x K) with the factor and its block inverses.
 int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld,
               const double *Linv, double *Y, const SvDevInfo *info, unsigned *flags,

@@ -48,6 +48,12 @@ struct svlcov_state {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // second stream of an append update (created on first use): the residual
+  // Gram, its Cholesky and K run there while the eigensolver, which needs
+  // only M, runs on `stream`; ev_fork / ev_join order the two
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int ncu = 0;   // compute units of the device (set with the side stream)
   int prec = SVLCOV_FP64;
   int k = 0;
   int64_t m = 0, n = 0;
@@ -118,14 +124,17 @@ inline void release(svlcov_state *h, DevBuf &b) {
 }
 }  // namespace svl_state
 
-// Cooperative-launch ordering hooks (no-ops unless a server drives the state).
-inline void coop_enter(svlcov_state *h) {
+// Cooperative-launch ordering hooks (no-ops unless a server drives the state);
+// st: the stream the cooperative kernel goes to (default the state's).
+inline void coop_enter(svlcov_state *h, hipStream_t st = nullptr) {
+  if (!st) st = h->stream;
   if (h->coop_mu) h->coop_mu->lock();
-  if (h->coop_chain && *h->coop_chain_live) (void)hipStreamWaitEvent(h->stream, *h->coop_chain, 0);
+  if (h->coop_chain && *h->coop_chain_live) (void)hipStreamWaitEvent(st, *h->coop_chain, 0);
 }
-inline void coop_exit(svlcov_state *h) {
+inline void coop_exit(svlcov_state *h, hipStream_t st = nullptr) {
+  if (!st) st = h->stream;
   if (h->coop_chain) {
-    (void)hipEventRecord(*h->coop_chain, h->stream);
+    (void)hipEventRecord(*h->coop_chain, st);
     *h->coop_chain_live = true;
   }
   if (h->coop_mu) h->coop_mu->unlock();
