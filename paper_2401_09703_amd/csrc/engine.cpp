@@ -269,6 +269,12 @@ static int64_t rid_words(int64_t nnz) {
   return a > b ? a : b;
 }
 
+// Scratch of F's row orthonormalisation on the side stream: Gram, inverse,
+// product and split-K partials of the k x k Gram (at most 64).
+static size_t orth_side_doubles(int K, int64_t N) {
+  return (size_t)66 * K * K + (size_t)K * N;
+}
+
 size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int64_t nnzB) {
   Carver c{nullptr};
   const int64_t N = K + s;
@@ -300,6 +306,7 @@ size_t svl_state::op_workspace_bytes(int op, int K, int64_t s, int64_t nnzA, int
   for (int q = 0; q < 4; ++q) c.take<double>(K * K);
   c.take<int32_t>(2);
   c.take<double>(2 * K * K + 9 * K * N);
+  c.take<double>(orth_side_doubles(K, N));
   c.take<int32_t>(rid_words(nnz));
   return c.off;
 }
@@ -398,10 +405,13 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
 // join: an event on the stream that forms K (NULL: K is formed on the
 // state's stream); the state's stream waits for it before anything needs K
 // and before a cooperative kernel could run beside the Cholesky.
+// orth2 (with join): scratch of orth_side_doubles(K, N) for F's
+// orthonormalisation, which then runs on the side stream (from after G is
+// formed; the caller joins it) while the state's stream takes G's.
 svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mmat, double *lam,
                             double *theta, int32_t *complete, double *Fv, double *Gv,
                             double *eigw, double *gram_kk, const double *Cp_border = nullptr,
-                            hipEvent_t join = nullptr) {
+                            hipEvent_t join = nullptr, double *orth2 = nullptr) {
   const int K = h->k;
   hipStream_t st = h->stream;
   {
@@ -479,12 +489,22 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
                      gram_kk + 2 * K * K + K * N, (size_t)8 * K * N, h->info);
     svl::theta_scale(st, K, lam, theta, Gv, N, complete, h->info);
   }
-  PhaseScope ps(h, PH_ORTH);
   double *linv_kk = gram_kk + K * K, *xtmp = gram_kk + 2 * K * K;
   double *gws = xtmp + K * N;
   const size_t gws_len = (size_t)8 * K * N;
-  svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, gram_kk, linv_kk,
-                           xtmp, gws, gws_len, h->info);
+  if (join && orth2) {   // F's rows on the side stream, G's here
+    (void)hipEventRecord(h->ev_fork, st);
+    (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
+    PhaseScope ps(h, PH_ORTH, h->side);
+    svl::orthonormalize_rows(h->side, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, orth2,
+                             orth2 + K * K, orth2 + 2 * K * K, orth2 + 2 * K * K + K * N,
+                             (size_t)64 * K * K, h->info);
+  } else {
+    PhaseScope ps(h, PH_ORTH);
+    svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, gram_kk, linv_kk,
+                             xtmp, gws, gws_len, h->info);
+  }
+  PhaseScope ps(h, PH_ORTH);
   svl::orthonormalize_rows(st, K, N, Gv, complete, (uint64_t)h->seq * 2 + 2, gram_kk, linv_kk,
                            xtmp, gws, gws_len, h->info);
   svl::check_finite(st, K, theta, h->info, h->seq);
@@ -584,6 +604,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   Carver c{nullptr};
   double *orthw_p = nullptr;
   double **orthw = &orthw_p;
+  double *orth2 = nullptr;  // F's orthonormalisation on the side stream
   int32_t *rid = nullptr;   // row id per nonzero of E (sparse Gram)
   auto layout = [&](Carver &cv, double **Cp64, float **Cp32, double **rown, double **Gm,
                     double **Linv, double **Kmat, double **Mmat, double **lam, double **theta,
@@ -612,6 +633,7 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
     *Mupd = cv.take<double>(s * K);
     *flags = cv.take<int32_t>(2);
     *orthw = cv.take<double>(2 * K * K + 9 * K * N);
+    orth2 = cv.take<double>(orth_side_doubles(K, N));
     rid = cv.take<int32_t>(rid_words(E->nnz));
   };
   double *Cp64, *rown, *Gm, *Linv, *Kmat, *Mmat, *lam, *theta, *Fv, *Gv, *eigw, *Y, *T1, *WnA,
@@ -654,26 +676,54 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   }
   if (overlap) (void)hipEventRecord(h->ev_join, cst);
   r = rayleigh_ritz(h, N, Kmat, Mmat, lam, theta, complete, Fv, Gv, eigw, orthw_p, Cp64,
-                    overlap ? h->ev_join : nullptr);
+                    overlap ? h->ev_join : nullptr, overlap ? orth2 : nullptr);
   if (r != SVLCOV_OK) return r;
-  // append side: W_A F[:k]; its inverse and condition
-  {
-    PhaseScope ps(h, PH_SMALL);
-    svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
-  }
-  // sparse side: W_B (G[:k] - C_n G[k:]); then both inverses in one launch
-  sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
-                   orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
-  {
-    PhaseScope ps(h, PH_SMALL);
-    svl::inverse_cond_pair(st, K, WnA, WiA, flags, sideA, WnB, WiB, flags + 1, sideB,
-                           h->cond_reset, h->info);
-  }
-  svl::check_finite(st, K * K, WnB, h->info, h->seq);
-  svl::check_finite(st, K * K, WnA, h->info, h->seq);
-  // commit: append side (realise on reset, appended rows F[k:] W^{-1})
   const int mode = mode_of(h->prec);
-  {
+  if (overlap) {
+    // the append side (F's rows orthonormalised on the side stream already:
+    // W_A F[:k], its inverse, the realisation on reset and the appended rows
+    // F[k:] W^{-1}) stays there, beside the sparse side's triangular solve
+    hipStream_t sd = h->side;
+    {
+      PhaseScope ps(h, PH_SMALL, sd);
+      svl::gemm_f64(sd, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
+      svl::inverse_cond_one(sd, K, WnA, WiA, flags, sideA, h->cond_reset, h->info);
+    }
+    svl::check_finite(sd, K * K, WnA, h->info, h->seq);
+    {
+      PhaseScope ps(h, PH_COMMIT, sd);
+      svl::realise<T, T>(sd, mode, K, nA, A_base, WnA, A_base, flags, h->info);
+      svl::append_rows<T>(sd, K, s, Fv + K, 1, N, WiA, flags, A_base + nA * K, h->info);
+    }
+    (void)hipEventRecord(h->ev_join, sd);
+    // sparse side: W_B (G[:k] - C_n G[k:]) and its inverse
+    sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
+                     orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
+    {
+      PhaseScope ps(h, PH_SMALL);
+      svl::inverse_cond_one(st, K, WnB, WiB, flags + 1, sideB, h->cond_reset, h->info);
+    }
+    svl::check_finite(st, K * K, WnB, h->info, h->seq);
+    (void)hipStreamWaitEvent(st, h->ev_join, 0);
+    PhaseScope ps(h, PH_COMMIT);
+    svl::commit_small(st, K, WnA, flags, W_A, theta, h->sigma, h->info, sideA);
+  } else {
+    // append side: W_A F[:k]; its inverse and condition
+    {
+      PhaseScope ps(h, PH_SMALL);
+      svl::gemm_f64(st, false, true, K, K, K, 1.0, W_A, K, Fv, N, 0.0, WnA, K, h->info);
+    }
+    // sparse side: W_B (G[:k] - C_n G[k:]); then both inverses in one launch
+    sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
+                     orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
+    {
+      PhaseScope ps(h, PH_SMALL);
+      svl::inverse_cond_pair(st, K, WnA, WiA, flags, sideA, WnB, WiB, flags + 1, sideB,
+                             h->cond_reset, h->info);
+    }
+    svl::check_finite(st, K * K, WnB, h->info, h->seq);
+    svl::check_finite(st, K * K, WnA, h->info, h->seq);
+    // commit: append side (realise on reset, appended rows F[k:] W^{-1})
     PhaseScope ps(h, PH_COMMIT);
     svl::realise<T, T>(st, mode, K, nA, A_base, WnA, A_base, flags, h->info);
     svl::append_rows<T>(st, K, s, Fv + K, 1, N, WiA, flags, A_base + nA * K, h->info);

@@ -1150,6 +1150,22 @@ void inverse_cond_pair(hipStream_t st, int K, const double *Wa, double *Wia, int
 #undef SV_INV2W
 }
 
+void inverse_cond_one(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
+                      int side, double cond_reset, SvDevInfo *info) {
+  const InvJob a{W, Winv, flag, side};
+#define SV_INV1W(KK) hipLaunchKernelGGL((k_inverse_cond2_wave<KK>), dim3(1), dim3(64), 0, st, a, a, \
+                                        cond_reset, info)
+  switch (K) {
+    case 16: SV_INV1W(16); break;
+    case 32: SV_INV1W(32); break;
+    case 64: SV_INV1W(64); break;
+    case 128:
+      hipLaunchKernelGGL((k_inverse_cond2<128>), dim3(1), dim3(256), 0, st, a, a, cond_reset, info);
+      break;
+  }
+#undef SV_INV1W
+}
+
 void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,
                   const double *theta, double *sig, SvDevInfo *info, int side) {
   hipLaunchKernelGGL(k_commit_small, dim3(1), dim3(256), 0, st, K, Wnew, flag, W, theta, sig,

@@ -153,6 +153,9 @@ void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t 
 void inverse_cond_pair(hipStream_t st, int K, const double *Wa, double *Wia, int32_t *fa, int sa,
                        const double *Wb, double *Wib, int32_t *fb, int sb, double cond_reset,
                        SvDevInfo *info);
+// One side's inverse (the same kernels, one block).
+void inverse_cond_one(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
+                      int side, double cond_reset, SvDevInfo *info);
 // W = (reset ? I : Wnew); sig = theta (when sig_out != NULL); count resets.
 void commit_small(hipStream_t st, int K, const double *Wnew, const int32_t *flag, double *W,
                   const double *theta, double *sig_out, SvDevInfo *info, int side);
