@@ -492,21 +492,28 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
   double *linv_kk = gram_kk + K * K, *xtmp = gram_kk + 2 * K * K;
   double *gws = xtmp + K * N;
   const size_t gws_len = (size_t)8 * K * N;
-  if (join && orth2) {   // F's rows on the side stream, G's here
+  const bool split = join && orth2;
+  if (!split) {
+    PhaseScope ps(h, PH_ORTH);
+    svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, gram_kk, linv_kk,
+                             xtmp, gws, gws_len, h->info);
+  }
+  {
+    PhaseScope ps(h, PH_ORTH);
+    svl::orthonormalize_rows(st, K, N, Gv, complete, (uint64_t)h->seq * 2 + 2, gram_kk, linv_kk,
+                             xtmp, gws, gws_len, h->info);
+  }
+  if (split) {
+    // F's rows on the side stream (the host enqueues G's first: they lead to
+    // the triangular solve, the longer chain, and the host's launches are
+    // what the device waits for here)
     (void)hipEventRecord(h->ev_fork, st);
     (void)hipStreamWaitEvent(h->side, h->ev_fork, 0);
     PhaseScope ps(h, PH_ORTH, h->side);
     svl::orthonormalize_rows(h->side, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, orth2,
                              orth2 + K * K, orth2 + 2 * K * K, orth2 + 2 * K * K + K * N,
                              (size_t)64 * K * K, h->info);
-  } else {
-    PhaseScope ps(h, PH_ORTH);
-    svl::orthonormalize_rows(st, K, N, Fv, nullptr, (uint64_t)h->seq * 2 + 1, gram_kk, linv_kk,
-                             xtmp, gws, gws_len, h->info);
   }
-  PhaseScope ps(h, PH_ORTH);
-  svl::orthonormalize_rows(st, K, N, Gv, complete, (uint64_t)h->seq * 2 + 2, gram_kk, linv_kk,
-                           xtmp, gws, gws_len, h->info);
   svl::check_finite(st, K, theta, h->info, h->seq);
   if (hipGetLastError() != hipSuccess) {   // a launch was refused: stop here
     h->launch_failed = true;
@@ -680,6 +687,14 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
   if (r != SVLCOV_OK) return r;
   const int mode = mode_of(h->prec);
   if (overlap) {
+    // sparse side: W_B (G[:k] - C_n G[k:]) and its inverse (enqueued first:
+    // the longer chain)
+    sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
+                     orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
+    {
+      PhaseScope ps(h, PH_SMALL);
+      svl::inverse_cond_one(st, K, WnB, WiB, flags + 1, sideB, h->cond_reset, h->info);
+    }
     // the append side (F's rows orthonormalised on the side stream already:
     // W_A F[:k], its inverse, the realisation on reset and the appended rows
     // F[k:] W^{-1}) stays there, beside the sparse side's triangular solve
@@ -696,13 +711,6 @@ svlcov_status op_append(svlcov_state *h, const svlcov_csr *E, bool rows_form) {
       svl::append_rows<T>(sd, K, s, Fv + K, 1, N, WiA, flags, A_base + nA * K, h->info);
     }
     (void)hipEventRecord(h->ev_join, sd);
-    // sparse side: W_B (G[:k] - C_n G[k:]) and its inverse
-    sparse_side_math(h, s, N, Gv, Cp64, Gm, Linv, W_B, Y, T1, WnB, WiB, flags + 1, sideB,
-                     orthw_p + 2 * K * K + K * N, (size_t)8 * K * N, false);
-    {
-      PhaseScope ps(h, PH_SMALL);
-      svl::inverse_cond_one(st, K, WnB, WiB, flags + 1, sideB, h->cond_reset, h->info);
-    }
     svl::check_finite(st, K * K, WnB, h->info, h->seq);
     (void)hipStreamWaitEvent(st, h->ev_join, 0);
     PhaseScope ps(h, PH_COMMIT);

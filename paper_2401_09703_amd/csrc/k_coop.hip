@@ -5,7 +5,11 @@
 // coherent (L2-bypassing) loads and stores and meet at flag barriers, so a
 // factorisation of s = 1000 costs two launches instead of ~150.
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "common.hpp"
 #include "svlcov.h"
@@ -628,9 +632,23 @@ int coop_blocks(const void *fn, int want) {
     (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
     return n > 0 ? n : 1;
   }();
-  int nb = 0;
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, CT, 0);
-  (void)hipGetLastError();
+  // resident blocks per CU of each kernel, queried once (the query costs
+  // host time on every update otherwise)
+  static std::mutex mu;
+  static std::vector<std::pair<const void *, int>> seen;
+  int nb = -1;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto &e : seen)
+      if (e.first == fn) nb = e.second;
+  }
+  if (nb < 0) {
+    nb = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, CT, 0);
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(mu);
+    seen.emplace_back(fn, nb);
+  }
   int lim = nb * ncu;
   if (lim > svl::TRI_MAX_BLOCKS) lim = svl::TRI_MAX_BLOCKS;
   if (want > lim) want = lim;
@@ -700,13 +718,23 @@ int trsm_coop(hipStream_t st, int64_t s, int K, const double *L, int64_t ld, con
   }();
   (void)once_p;
   {
-    // one block per block row, all resident at once (cooperative launch)
-    int nbp = 0, ncu = 0, dev = 0;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nbp, reinterpret_cast<const void *>(k_trsm_p2p), CT, sh);
-    (void)hipGetLastError();
+    // one block per block row, all resident at once (cooperative launch);
+    // resident blocks per CU queried once per LDS size (K16 / 16 in 1..8)
+    static std::atomic<int> nbp_of[9] = {};
+    static const int ncu = [] {
+      int dev = 0, n = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+      return n > 0 ? n : 1;
+    }();
+    int nbp = nbp_of[K16 / 16].load() - 1;
+    if (nbp < 0) {
+      nbp = 0;
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nbp, reinterpret_cast<const void *>(k_trsm_p2p), CT, sh);
+      (void)hipGetLastError();
+      nbp_of[K16 / 16].store(nbp + 1);
+    }
     if (nblk <= svl::TRI_MAX_BLOCKS && nblk <= (int64_t)nbp * ncu) {
       unsigned e0 = take_epochs(st, flags, epoch, 1u);
       unsigned ready = e0 + 1u;
