@@ -93,14 +93,16 @@ struct PhaseScope {
 // The append form's M = K K^T is assembled from sigma, C' and the sparse Gram
 // alone, so the eigensolver does not wait for the residual Gram's Cholesky:
 // when the eigensolver is the subspace iteration without cooperative kernels
-// (basis of at most 128 columns), the Cholesky and K go to a second stream
-// and the two meet before G = K^T F.  SVLCOV_NO_OVERLAP=1 keeps one stream.
+// (basis of at most EIG_ONE_BLOCK_N columns), the Cholesky and K go to a
+// second stream and the two meet before G = K^T F.  SVLCOV_NO_OVERLAP=1
+// keeps one stream.
 bool side_stream(svlcov_state *h, int64_t N, int K) {
   static const bool off = [] {
     const char *ev = getenv("SVLCOV_NO_OVERLAP");
     return ev && atoi(ev) != 0;
   }();
-  if (off || h->prec == SVLCOV_FP64 || !svl::chefsi_applies(N, K) || svl::chefsi_block(K) > 128)
+  if (off || h->prec == SVLCOV_FP64 || !svl::chefsi_applies(N, K) ||
+      svl::chefsi_block(K) > svl::EIG_ONE_BLOCK_N)
     return false;
   if (!h->side) {
     hipStream_t sd = nullptr;
@@ -383,14 +385,22 @@ void orthogonalise(svlcov_state *h, const DevCsr &E, const T *base, const double
       svl::gram_lowp(cst, mode_of(h->prec), s, K, Cp32, Gm, s, h->info);
   }
   if (!chol) return;   // the approximate variants use the Gram itself
-  // beside the eigensolver the Cholesky takes at most half the CUs: with a
-  // block per CU it kept the eigensolver's products from starting (its
-  // chain of diagonal blocks, not its trailing products, sets its time;
-  // at s = 1000 it runs as fast with 125 blocks as with 250)
+  // beside the eigensolver the Cholesky leaves CUs to it: with a block per
+  // CU it kept the eigensolver's products from starting.  Up to s ~ 2000 its
+  // chain of diagonal blocks, not its trailing products, sets its time (at
+  // s = 1000 it runs as fast with 125 blocks as with 250): half the CUs;
+  // beyond, the trailing products count (s = 5000: 7.2 ms with 256 blocks
+  // alone, 8.9 ms with 224 beside the iteration, 13.4 ms with 128): 7/8
   PhaseScope ps(h, PH_CHOL, cst);
   coop_enter(h, cst);
+  static const int side_blocks = [] {   // SVLCOV_SIDE_BLOCKS overrides it for sweeps
+    const char *ev = getenv("SVLCOV_SIDE_BLOCKS");
+    return ev ? atoi(ev) : 0;
+  }();
+  const int cap = side_blocks > 0 ? side_blocks
+                                  : std::max(1, s <= 2048 ? h->ncu / 2 : h->ncu * 7 / 8);
   const int crc = svl::cholesky_coop(cst, s, Gm, s, Linv, h->rank_tol, h->info, which, h->flags,
-                                     &h->epoch, cst != st ? std::max(1, h->ncu / 2) : 0);
+                                     &h->epoch, cst != st ? cap : 0);
   coop_exit(h, cst);
   if (crc) {
     h->launch_failed = true;
@@ -439,8 +449,9 @@ svlcov_status rayleigh_ritz(svlcov_state *h, int64_t N, double *Kmat, double *Mm
     if (h->ctl_host) {
       int iters = 0;
       double fl = 0.0;
-      // a basis wider than 128 uses the cooperative eigensolver inside
-      const bool coop = svl::chefsi_block(K) > 128;
+      // a basis wider than the one-block tridiagonalisation takes uses the
+      // cooperative eigensolver inside
+      const bool coop = svl::chefsi_block(K) > svl::EIG_ONE_BLOCK_N;
       if (coop) coop_enter(h);
       const int rc = svl::eig_topk_chefsi(st, N, Mmat, K, lam, Fv, eigw,
                                           svl::eig_update_work_doubles(N, K), h->ctl_host,

@@ -315,33 +315,46 @@ k_tridiag_small(int N, double *__restrict__ A, int64_t lda, double *__restrict__
   }
 }
 
-// The same reduction for N <= 128 with the matrix in registers: one block of
-// 1024 threads, thread t holds row r = t / 8 at the columns c = t % 8 + 8 j
-// (j < 16), so the eight threads of a row are one 8-lane group of a wave
-// (row sums by two DPP steps).  Per column: the threads of row i form the
-// reflector from their registers and publish v, every thread forms its row's
-// share of p = tau M v, a block reduction gives p.v, and each thread applies
-// the rank-2 update to its 16 entries with w rebuilt from p and v in LDS.
-// Two block barriers per column; v, p and the partial sums alternate between
-// two LDS buffers so that the next column's writes never meet this column's
-// reads.  A wave whose rows are all <= i only takes part in the reduction.
-// The reflectors stay in the registers of their rows (which no later update
-// changes) and d, e, tau in LDS until the end: a global store inside the
-// loop would hold up every block barrier until it completed.  Conventions as
-// k_tridiag.
-constexpr int TR_N = 128, TR_NT = 1024, TR_CPT = 16;
+// The same reduction with the matrix in registers, one block of
+// NT = NMAX * TPR threads: thread t holds row r = t / TPR at the columns
+// c = t % TPR + TPR j (j < NMAX / TPR), so the TPR threads of a row are one
+// TPR-lane group of a wave (row sums by DPP steps).  N <= 128 takes eight
+// threads per row (1024 threads, 16 entries each); 128 < N <= 160 four
+// (640 threads, 40 entries each: the registers of 1024 threads cannot hold
+// more).  Per column: the threads of row i form the reflector from their
+// registers and publish v, every thread forms its row's share of p = tau M v,
+// a block reduction gives p.v, and each thread applies the rank-2 update to
+// its entries with w rebuilt from p and v in LDS.  Two block barriers per
+// column; v, p and the partial sums alternate between two LDS buffers so
+// that the next column's writes never meet this column's reads.  A wave
+// whose rows are all <= i only takes part in the reduction.  The reflectors
+// stay in the registers of their rows (which no later update changes) and
+// d, e, tau in LDS until the end: a global store inside the loop would hold
+// up every block barrier until it completed.  Conventions as k_tridiag.
+constexpr int TR_N = 128, TR_NT = 1024;
+constexpr int TR2_N = svl::EIG_ONE_BLOCK_N, TR2_TPR = 4, TR2_NT = TR2_N * TR2_TPR;
 
 __device__ __forceinline__ double sum8(double v) {
   v = quad_sum(v);
   return v + dpp_d<DPP_ROW_HALF_MIRROR>(v);
 }
 
-__global__ void __launch_bounds__(TR_NT)
+template <int TPR>
+__device__ __forceinline__ double group_sum(double v) {
+  static_assert(TPR == 2 || TPR == 4 || TPR == 8, "row group");
+  if (TPR == 8) return sum8(v);
+  if (TPR == 4) return quad_sum(v);
+  return v + dpp_d<DPP_QUAD_XOR1>(v);
+}
+
+template <int TPR, int NMAX>
+__global__ void __launch_bounds__(NMAX * TPR)
 k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d,
               double *__restrict__ e, double *__restrict__ tau, const SvDevInfo *__restrict__ info) {
+  constexpr int NT = NMAX * TPR, CPT = NMAX / TPR, RPW = 64 / TPR;
   if (info->status) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int r = tid >> 3, s = tid & 7;
+  const int r = tid / TPR, s = tid % TPR;
   if (N < 3) {
     if (tid == 0) {
       d[0] = A[0];
@@ -349,80 +362,79 @@ k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d
     }
     return;
   }
-  __shared__ double vb[2][TR_N];
-  __shared__ double pb[2][TR_N];
-  __shared__ double part[2][TR_NT / 64];
+  __shared__ double vb[2][NMAX];
+  __shared__ double pb[2][NMAX];
+  __shared__ double part[2][NT / 64];
   __shared__ double tb[2];
-  __shared__ double dd[TR_N], ee[TR_N], tt[TR_N];
-  double a[TR_CPT];
+  __shared__ double dd[NMAX], ee[NMAX], tt[NMAX], sc[NMAX], xr[NMAX];
+  double a[CPT];
 #pragma unroll
-  for (int j = 0; j < TR_CPT; ++j) {
-    const int c = s + 8 * j;
+  for (int j = 0; j < CPT; ++j) {
+    const int c = s + TPR * j;
     a[j] = (r < N && c < N) ? A[(int64_t)r * lda + c] : 0.0;
   }
+  for (int c = tid; c < 2 * NMAX; c += NT) vb[c / NMAX][c % NMAX] = 0.0;
+  __syncthreads();
   for (int i = 0; i <= N - 3; ++i) {
     const int b = i & 1;
-    // row i: alpha = x_{i+1}, ||x_{i+2..}||^2 and d_i (every lane computes,
-    // only the group of row i has nonzero terms)
-    {
-      // (sums in four interleaved chains: a dependent FP64 add costs ~13 ns)
-      double ss = 0.0, al = 0.0, di = 0.0;
-      if (r == i) {
-        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    // row i: its group copies the row to xr, reads d_i = x_i, alpha =
+    // x_{i+1} and ||x_{i+2..}||^2 back and writes the reflector v to vb (1
+    // at i + 1, scl x_c beyond; vb[b] already holds 0 up to column i - 2 and
+    // beyond N - 1 from its last use two columns ago, and columns i - 1, i
+    // are cleared here).  The registers keep x (no later update changes row
+    // i); the reflector is written out from x and scl at the end.  No
+    // per-column conditions on the register array: those compile to one
+    // lane mask per column.
+    if (r == i) {
+      double *xw = &xr[s];
 #pragma unroll
-        for (int j = 0; j < TR_CPT; ++j) {
-          const int c = s + 8 * j;
-          if (c >= i + 2 && c < N) s4[j & 3] += a[j] * a[j];
-          if (c == i + 1) al = a[j];
-          if (c == i) di = a[j];
-        }
-        ss = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+      for (int j = 0; j < CPT; ++j) xw[TPR * j] = a[j];
+      // the group is TPR lanes of one wave, whose LDS accesses are in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int q = 0;
+      for (int c = i + 2 + s; c < N; c += TPR, ++q) {
+        const double x = xr[c];
+        s4[q & 3] += x * x;
       }
-      ss = sum8(ss);
-      al = sum8(al);
-      di = sum8(di);
-      if (r == i) {
-        double beta, t, scl;
-        if (ss == 0.0) {
-          t = 0.0; beta = al; scl = 0.0;
-        } else {
-          const double nrm = sqrt(al * al + ss);
-          beta = al >= 0.0 ? -nrm : nrm;
-          t = (beta - al) / beta;
-          scl = 1.0 / (al - beta);
-        }
-        // row i is final: its registers keep the reflector from here on
-#pragma unroll
-        for (int j = 0; j < TR_CPT; ++j) {
-          const int c = s + 8 * j;
-          double v = 0.0;
-          if (c == i + 1) v = 1.0;
-          else if (c >= i + 2 && c < N) v = a[j] * scl;
-          vb[b][c] = v;
-          if (c >= i + 1) a[j] = v;
-        }
-        if (s == 0) {
-          tb[b] = t;
-          dd[i] = di;
-          ee[i] = beta;
-          tt[i] = t;
-        }
+      const double ss = group_sum<TPR>((s4[0] + s4[1]) + (s4[2] + s4[3]));
+      const double di = xr[i], al = xr[i + 1];
+      double beta, t, scl;
+      if (ss == 0.0) {
+        t = 0.0; beta = al; scl = 0.0;
+      } else {
+        const double nrm = sqrt(al * al + ss);
+        beta = al >= 0.0 ? -nrm : nrm;
+        t = (beta - al) / beta;
+        scl = 1.0 / (al - beta);
+      }
+      for (int c = i + 2 + s; c < N; c += TPR) vb[b][c] = xr[c] * scl;
+      if (s == 0) {
+        if (i >= 1) vb[b][i - 1] = 0.0;
+        vb[b][i] = 0.0;
+        vb[b][i + 1] = 1.0;
+        tb[b] = t;
+        dd[i] = di;
+        ee[i] = beta;
+        tt[i] = t;
+        sc[i] = scl;
       }
     }
     __syncthreads();
     const double t = tb[b];
-    const bool wact = 8 * w + 7 > i && 8 * w < N;
+    const bool wact = RPW * w + RPW - 1 > i && RPW * w < N;
     double pr = 0.0, vr = 0.0, pv = 0.0;
     if (wact) {
-      // the sixteen loads issued together (v is zero at columns <= i and p
-      // at rows <= i, so no per-column condition is needed)
-      double vv[TR_CPT];
-#pragma unroll
-      for (int j = 0; j < TR_CPT; ++j) vv[j] = vb[b][s + 8 * j];
+      // v is zero at columns <= i and p at rows <= i, so no per-column
+      // condition is needed
+      // (one base address per buffer, the columns at immediate offsets)
+      const double *vs = &vb[b][s];
       double a4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < TR_CPT; ++j) a4[j & 3] += a[j] * vv[j];
-      const double acc = sum8((a4[0] + a4[1]) + (a4[2] + a4[3]));
+      for (int j = 0; j < CPT; ++j) a4[j & 3] += a[j] * vs[TPR * j];
+      const double acc = group_sum<TPR>((a4[0] + a4[1]) + (a4[2] + a4[3]));
       const bool act = r > i && r < N;
       pr = act ? t * acc : 0.0;
       vr = act ? vb[b][r] : 0.0;
@@ -437,33 +449,33 @@ k_tridiag_reg(int N, double *__restrict__ A, int64_t lda, double *__restrict__ d
     if (wact) {
       double p4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int q = 0; q < TR_NT / 64; ++q) p4[q & 3] += part[b][q];
+      for (int q = 0; q < NT / 64; ++q) p4[q & 3] += part[b][q];
       const double pvs = (p4[0] + p4[1]) + (p4[2] + p4[3]);
       const double K = 0.5 * t * pvs;
       const double wr = pr - K * vr;
-      double pp[TR_CPT];
-#pragma unroll
-      for (int j = 0; j < TR_CPT; ++j) pp[j] = pb[b][s + 8 * j];
       // M_rc -= v_r w_c + w_r v_c, w_c = p_c - K v_c
+      const double *vs = &vb[b][s], *ps = &pb[b][s];
 #pragma unroll
-      for (int j = 0; j < TR_CPT; ++j) {
-        const double vc = vb[b][s + 8 * j];
-        a[j] -= vr * (pp[j] - K * vc) + wr * vc;
+      for (int j = 0; j < CPT; ++j) {
+        const double vc = vs[TPR * j];
+        a[j] -= vr * (ps[TPR * j] - K * vc) + wr * vc;
       }
     }
   }
-  // the last 2 x 2 block, the reflectors (rows 0 .. N-3 of A, columns > r)
-  // and d, e, tau
+  // the last 2 x 2 block, the reflectors (rows 0 .. N-3 of A, columns > r:
+  // 1 at r + 1, scl_r x_c beyond) and d, e, tau
+  __syncthreads();
+  const double scr = r <= N - 3 ? sc[r] : 0.0;
 #pragma unroll
-  for (int j = 0; j < TR_CPT; ++j) {
-    const int c = s + 8 * j;
+  for (int j = 0; j < CPT; ++j) {
+    const int c = s + TPR * j;
     if (r == N - 2 && c == N - 2) d[N - 2] = a[j];
     if (r == N - 2 && c == N - 1) e[N - 2] = a[j];
     if (r == N - 1 && c == N - 1) d[N - 1] = a[j];
-    if (r <= N - 3 && c > r && c < N) A[(int64_t)r * lda + c] = a[j];
+    if (r <= N - 3 && c > r && c < N) A[(int64_t)r * lda + c] = c == r + 1 ? 1.0 : a[j] * scr;
   }
   __syncthreads();
-  for (int q = tid; q <= N - 3; q += TR_NT) {
+  for (int q = tid; q <= N - 3; q += NT) {
     d[q] = dd[q];
     e[q] = ee[q];
     tau[q] = tt[q];
@@ -483,7 +495,13 @@ int eig_tridiag(hipStream_t st, int64_t N64, double *A, double *work, unsigned *
   if (N64 > eig_max_n() || N < 1) return -1;
   double *d = work, *e = d + N, *tau = e + N, *pbuf = tau + N, *rowbuf = pbuf + 2 * N;
   if (N <= TR_N && !getenv("SVLCOV_TRI_LDS")) {   // one block, the matrix in registers
-    hipLaunchKernelGGL(k_tridiag_reg, dim3(1), dim3(TR_NT), 0, st, N, A, N64, d, e, tau, info);
+    hipLaunchKernelGGL((k_tridiag_reg<8, TR_N>), dim3(1), dim3(TR_NT), 0, st, N, A, N64, d, e,
+                       tau, info);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+  }
+  if (N <= TR2_N) {   // the same with four threads per row
+    hipLaunchKernelGGL((k_tridiag_reg<TR2_TPR, TR2_N>), dim3(1), dim3(TR2_NT), 0, st, N, A, N64,
+                       d, e, tau, info);
     return hipGetLastError() == hipSuccess ? 0 : -3;
   }
   if (N <= TRI_SMALL_N) {   // one block, the matrix in LDS

@@ -286,6 +286,10 @@ void eig_stein(hipStream_t st, int64_t N, int k, const double *lam, double *Fv, 
 void eig_back(hipStream_t st, int64_t N, int k, const double *A, double *Fv, double *work,
               const SvDevInfo *info);
 int eig_max_n();
+// Largest N whose tridiagonalisation is one block (no cooperative launch,
+// flags and epoch unused): eig_topk on such an N can run beside a
+// cooperative kernel of another stream.
+constexpr int EIG_ONE_BLOCK_N = 160;
 
 // ---- Chebyshev-filtered subspace iteration (k_chefsi.hip)
 // Top-k eigenpairs of the positive semidefinite N x N matrix M (not
