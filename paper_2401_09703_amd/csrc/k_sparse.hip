@@ -410,17 +410,31 @@ k_sparse_gram(int64_t s, const int64_t *__restrict__ row_ptr,
     __syncthreads();
     const int32_t *ci = in_lds ? sc : col_idx + q0;
     if (ni > 0) {
-      for (int64_t p = threadIdx.x; p < q1; p += blockDim.x) {
-        const int32_t c = col_idx[p];
-        int64_t lo = 0, hi = ni;   // first position with ci[pos] >= c
-        while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
-          if (ci[mid] < c) lo = mid + 1; else hi = mid;
+      // GU column indices per thread are loaded together before any search,
+      // so that a block has GU loads in flight per thread, not one
+      constexpr int GU = 8;
+      for (int64_t p0 = threadIdx.x; p0 < q1; p0 += (int64_t)GU * blockDim.x) {
+        int32_t cs[GU];
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+          const int64_t p = p0 + (int64_t)u * blockDim.x;
+          cs[u] = p < q1 ? col_idx[p] : -1;
         }
-        if (lo < ni && ci[lo] == c) {
-          const double vi = in_lds ? sv[lo] : ldv(val, vdtype, q0 + lo);
-          const long long q = __double2ll_rn(vi * ldv(val, vdtype, p) * fx);
-          atomicAdd(&acc[rid[p]], (unsigned long long)q);
+#pragma unroll
+        for (int u = 0; u < GU; ++u) {
+          const int64_t p = p0 + (int64_t)u * blockDim.x;
+          const int32_t c = cs[u];
+          if (c < 0) continue;
+          int64_t lo = 0, hi = ni;   // first position with ci[pos] >= c
+          while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (ci[mid] < c) lo = mid + 1; else hi = mid;
+          }
+          if (lo < ni && ci[lo] == c) {
+            const double vi = in_lds ? sv[lo] : ldv(val, vdtype, q0 + lo);
+            const long long q = __double2ll_rn(vi * ldv(val, vdtype, p) * fx);
+            atomicAdd(&acc[rid[p]], (unsigned long long)q);
+          }
         }
       }
     }
