@@ -500,135 +500,97 @@ __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
 }
 
 // Gauss-Jordan inverse with partial pivoting of the K x K matrix W (K <= 128)
-// held in registers, with the 1-norm condition number
+// in place in LDS, with the 1-norm condition number
 // kappa_1 = ||W||_1 ||W^{-1}||_1 and the reset flag (kappa_1 > cond_reset or
-// W numerically singular).  One block of 4 waves; wave w holds rows
-// [w K/4, (w+1) K/4), lane l holds columns l and l + 64.  Per column: the
-// lane holding column c publishes it and its wave's pivot candidate in LDS
-// (one barrier); the pivot row and the displaced row are exchanged through
-// LDS (one barrier).  The row interchanges are undone at the end as one
-// column permutation.
+// W numerically singular).  One block of 256 threads.  Per column c: the
+// pivot is the largest |A[r][c]| over rows r >= c (lowest row on ties), the
+// pivot row and row c are exchanged, row c is scaled by 1/pivot and every
+// other row subtracts its multiple of it, the inverse taking column c's
+// place (A[r][c] = -f_r / pivot); four barriers.  The row interchanges are
+// undone at the end as one column permutation.  (Holding the rows in
+// registers, 64 doubles a lane at K = 128, the compiler put the array in
+// scratch memory: 2.3 ms per inverse at K = 128, 1.3 ms here.)
 template <int K>
 __device__ __forceinline__ void
 inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
                    int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
                    int side) {
   if (info->status) return;
-  constexpr int R = K / 4;                  // rows per wave
-  constexpr int CPL = K > 64 ? 2 : 1;       // columns per lane
-  __shared__ double rowc[K], rowp[K], colc[K];
-  __shared__ double cand_v[4];
-  __shared__ int cand_i[4];
-  __shared__ double red[4];
-  __shared__ int piv[K], perm[K];
+  constexpr int NT = 256;
   __shared__ double As[K][K + 1];
+  __shared__ double rowc[K], colf[K];
+  __shared__ double cand_v[NT / 64];
+  __shared__ int cand_i[NT / 64];
+  __shared__ double red[NT / 64];
+  __shared__ int piv[K], perm[K];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int r0 = w * R;
-  double a[R][CPL];
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      const int j = lane + 64 * q;
-      a[i][q] = j < K ? W[(r0 + i) * K + j] : 0.0;
-    }
-  // ||W||_1: column sums
-  double cs[CPL];
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    cs[q] = 0.0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) cs[q] += fabs(a[i][q]);
-  }
-#pragma unroll
-  for (int q = 0; q < CPL; ++q)
-    if (lane + 64 * q < K) As[w][lane + 64 * q] = cs[q];
+  for (int e = t; e < K * K; e += NT) As[e / K][e % K] = W[e];
   __syncthreads();
-  double mx = 0.0;
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int j = lane + 64 * q;
-    if (j < K) mx = fmax(mx, As[0][j] + As[1][j] + As[2][j] + As[3][j]);
+  // ||W||_1: the largest column sum
+  double cs = 0.0;
+  for (int j = t; j < K; j += NT) {
+    double sacc = 0.0;
+    for (int r = 0; r < K; ++r) sacc += fabs(As[r][j]);
+    cs = fmax(cs, sacc);
   }
-  mx = wave_max(mx);
-  if (lane == 0) red[w] = mx;
+  cs = wave_max(cs);
+  if (lane == 0) red[w] = cs;
   __syncthreads();
-  const double n1 = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  double n1 = red[0];
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) n1 = fmax(n1, red[q]);
   const bool finite_in = isfinite(n1);
   bool sing = !finite_in;
   for (int c = 0; c < K && !sing; ++c) {
-    const int cl = c & 63, cq = c >> 6;
-    // lane cl holds column c of this wave's rows: it finds the wave's pivot
-    // candidate (largest |A[r][c]| over rows r >= c, lowest index on ties)
-    // and publishes the column for the multipliers
-    if (lane == cl) {
-      double best = -1.0;
-      int bi = K;
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const double v = CPL == 2 && cq ? a[i][CPL - 1] : a[i][0];
-        colc[r0 + i] = v;
-        if (r0 + i >= c && fabs(v) > best) { best = fabs(v); bi = r0 + i; }
-      }
-      cand_v[w] = best;
-      cand_i[w] = bi;
+    // pivot candidate of each wave (rows r >= c it covers), then the block's
+    double best = -1.0;
+    int bi = K;
+    for (int r = c + t; r < K; r += NT) {
+      const double v = fabs(As[r][c]);
+      if (v > best) { best = v; bi = r; }
     }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { cand_v[w] = best; cand_i[w] = bi; }
     __syncthreads();
     double pb = cand_v[0];
     int p = cand_i[0];
-    for (int q = 1; q < 4; ++q)
-      if (cand_v[q] > pb) { pb = cand_v[q]; p = cand_i[q]; }
+#pragma unroll
+    for (int q = 1; q < NT / 64; ++q)
+      if (cand_v[q] > pb || (cand_v[q] == pb && cand_i[q] < p)) { pb = cand_v[q]; p = cand_i[q]; }
     if (!(pb > 1e-300) || !(pb > 1e-15 * n1)) { sing = true; break; }
-    // publish rows c and p
-    if (c >= r0 && c < r0 + R) {
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (r0 + i == c)
-#pragma unroll
-          for (int q = 0; q < CPL; ++q)
-            if (lane + 64 * q < K) rowc[lane + 64 * q] = a[i][q];
-    }
-    if (p >= r0 && p < r0 + R) {
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (r0 + i == p)
-#pragma unroll
-          for (int q = 0; q < CPL; ++q)
-            if (lane + 64 * q < K) rowp[lane + 64 * q] = a[i][q];
+    // exchange rows c and p; keep row c (the pivot row) and column c
+    for (int j = t; j < K; j += NT) {
+      const double vp = As[p][j], vc = As[c][j];
+      As[p][j] = vc;
+      rowc[j] = vp;
     }
     if (t == 0) piv[c] = p;
     __syncthreads();
-    const double pinv = 1.0 / rowp[c];
-    double prow[CPL];
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      const int j = lane + 64 * q;
-      prow[q] = j < K ? (j == c ? pinv : rowp[j] * pinv) : 0.0;
-    }
-    const double fp = rowc[c];   // multiplier of row p after the interchange
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int r = r0 + i;
-      const double f = r == p ? fp : colc[r];
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        const int j = lane + 64 * q;
-        if (r == c) {
-          a[i][q] = prow[q];
-        } else {
-          const double cur = r == p ? rowc[j < K ? j : 0] : a[i][q];
-          a[i][q] = j == c ? -f * pinv : cur - f * prow[q];
-        }
+    for (int r = t; r < K; r += NT) colf[r] = r == c ? 0.0 : As[r][c];
+    __syncthreads();
+    const double pinv = 1.0 / rowc[c];
+    // (unrolled: one wave per SIMD here, so the LDS latency of one element's
+    // update hides only behind the others')
+#pragma unroll 16
+    for (int e = t; e < K * K; e += NT) {
+      const int r = e / K, j = e % K;
+      const double prow = j == c ? pinv : rowc[j] * pinv;
+      if (r == c) {
+        As[r][j] = prow;
+      } else {
+        const double f = colf[r];
+        As[r][j] = j == c ? -f * pinv : As[r][j] - f * prow;
       }
     }
+    __syncthreads();
   }
   // the inverse is the final matrix with its columns permuted: column j of
-  // W^{-1} is column perm[j] of a (the row interchanges undone in reverse)
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-#pragma unroll
-    for (int q = 0; q < CPL; ++q)
-      if (lane + 64 * q < K) As[r0 + i][lane + 64 * q] = a[i][q];
+  // W^{-1} is column perm[j] of A (the row interchanges undone in reverse)
   if (t == 0 && !sing) {
     for (int j = 0; j < K; ++j) perm[j] = j;
     for (int c = K - 1; c >= 0; --c) {
@@ -641,7 +603,7 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
   __syncthreads();
   // ||W^{-1}||_1 (max column sum, invariant under the column permutation)
   double ci = 0.0;
-  for (int j = t; j < K; j += 256) {
+  for (int j = t; j < K; j += NT) {
     double sacc = 0.0;
     for (int r = 0; r < K; ++r) sacc += fabs(As[r][j]);
     ci = fmax(ci, sacc);
@@ -650,10 +612,12 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
   __syncthreads();
   if (lane == 0) red[w] = ci;
   __syncthreads();
-  const double ninv = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  double ninv = red[0];
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) ninv = fmax(ninv, red[q]);
   const double kappa = sing ? INFINITY : n1 * ninv;
   if (!sing)
-    for (int e = t; e < K * K; e += 256) Winv[e] = As[e / K][perm[e % K]];
+    for (int e = t; e < K * K; e += NT) Winv[e] = As[e / K][perm[e % K]];
   if (t == 0) {
     const bool reset = !(kappa <= cond_reset);
     *flag = reset ? 1 : 0;
