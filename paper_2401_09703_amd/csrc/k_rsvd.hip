@@ -806,13 +806,38 @@ k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__
     double acc[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
-    for (uint32_t q = q0; q < (uint32_t)nnz && keys[q] == key; ++q) {
-      const uint32_t p = perm[q];
-      const double v = vdtype == 1 ? ((const double *)val)[p] : (double)((const float *)val)[p];
-      const int64_t i = rid[p];
+    // SU nonzeros of the segment at a time: their indices, values and rows
+    // of M are loaded together (a hot column's segment is thousands long,
+    // and one load chain per nonzero made it the kernel's whole time), then
+    // added in segment order as before
+    constexpr int SU = 32;
+    for (uint32_t q = q0;; q += SU) {
+      bool in[SU];
+      uint32_t pp[SU];
 #pragma unroll
-      for (int u = 0; u < CPL; ++u)
-        if (lane + 64 * u < K) acc[u] += v * M[i * K + lane + 64 * u];
+      for (int b = 0; b < SU; ++b) {
+        const uint32_t qq = q + b;
+        in[b] = qq < (uint32_t)nnz && keys[qq] == key;
+        pp[b] = in[b] ? perm[qq] : 0u;
+      }
+      double vb[SU], mb[SU][CPL];
+#pragma unroll
+      for (int b = 0; b < SU; ++b) {
+        vb[b] = !in[b] ? 0.0
+                       : vdtype == 1 ? ((const double *)val)[pp[b]]
+                                     : (double)((const float *)val)[pp[b]];
+        const int64_t i = in[b] ? rid[pp[b]] : 0;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          mb[b][u] = in[b] && lane + 64 * u < K ? M[i * K + lane + 64 * u] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < SU; ++b)
+        if (in[b])
+#pragma unroll
+          for (int u = 0; u < CPL; ++u)
+            if (lane + 64 * u < K) acc[u] += vb[b] * mb[b][u];
+      if (!in[SU - 1]) break;
     }
     T *dst = base + (int64_t)key * K;
 #pragma unroll
