@@ -125,6 +125,16 @@ typedef struct {
                                 /* so an update gives bitwise the same factors   */
                                 /* every time; 0: atomic accumulation, faster,   */
                                 /* rounding order free                           */
+  int32_t side_stream;          /* 1 (default): an append update (FP32/BF16X3,   */
+                                /* k+32 rounded to 16 at most 160) runs the      */
+                                /* residual Gram's Cholesky and K, later one     */
+                                /* side's k x k update, on a second stream of    */
+                                /* the state beside the eigensolver; that work   */
+                                /* is ordered after the call's earlier work on   */
+                                /* `stream` and before its later work there, so  */
+                                /* the state's stream still orders everything;   */
+                                /* the factors are bitwise those of 0 (one       */
+                                /* stream)                                       */
 } svlcov_options;
 
 typedef struct {

@@ -54,7 +54,7 @@ class _Options(C.Structure):
                 ("rank_tol", C.c_double), ("cond_reset", C.c_double),
                 ("validate_device_inputs", C.c_int32),
                 ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("deterministic", C.c_int32)]
+                ("deterministic", C.c_int32), ("side_stream", C.c_int32)]
 
 
 def _torch_alloc(nbytes, stream, ctx):
@@ -379,12 +379,16 @@ class TruncatedSVD:
     memory (the svlcov_options allocator hooks); the default is the library's
     own stream-ordered HIP allocations.  deterministic=False accumulates the
     sparse row update with atomics (faster, rounding order free) instead of
-    summing each base row's terms in a fixed order."""
+    summing each base row's terms in a fixed order.  side_stream=False keeps
+    an append update on the state's stream alone (the factors are the same
+    bit for bit; the second stream only lets the Cholesky run beside the
+    eigensolver)."""
 
     def __init__(self, U, s, V, precision: str = "fp64", device: int = 0, stream=None,
                  row_capacity: int = 0, col_capacity: int = 0, rank_tol: float = 0.0,
                  cond_reset: float = 0.0, validate_device_inputs: bool = True,
-                 allocator: str = None, deterministic: bool = True):
+                 allocator: str = None, deterministic: bool = True,
+                 side_stream: bool = True):
         on_dev = 0
         if _is_torch(U):
             # device factors (FP64 CUDA tensors), read on the state's stream
@@ -412,6 +416,7 @@ class TruncatedSVD:
         opt.cond_reset = cond_reset
         opt.validate_device_inputs = 1 if validate_device_inputs else 0
         opt.deterministic = 1 if deterministic else 0
+        opt.side_stream = 1 if side_stream else 0
         if allocator == "torch":
             # the state's factors and workspaces come from torch's caching allocator
             opt.dev_alloc, opt.dev_free = _TORCH_HOOKS

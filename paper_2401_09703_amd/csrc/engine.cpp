@@ -101,7 +101,7 @@ bool side_stream(svlcov_state *h, int64_t N, int K) {
     const char *ev = getenv("SVLCOV_NO_OVERLAP");
     return ev && atoi(ev) != 0;
   }();
-  if (off || h->prec == SVLCOV_FP64 || !svl::chefsi_applies(N, K) ||
+  if (off || !h->side_ok || h->prec == SVLCOV_FP64 || !svl::chefsi_applies(N, K) ||
       svl::chefsi_block(K) > svl::EIG_ONE_BLOCK_N)
     return false;
   if (!h->side) {
@@ -1392,6 +1392,7 @@ void svlcov_default_options(svlcov_options *o) {
   o->cond_reset = 0.0;
   o->validate_device_inputs = 1;
   o->deterministic = 1;
+  o->side_stream = 1;
 }
 
 svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k, const double *U,
@@ -1427,6 +1428,7 @@ svlcov_status svlcov_init(svlcov_state **out, int64_t m, int64_t n, int32_t k, c
   h->cond_reset = o.cond_reset > 0 ? o.cond_reset : DEF_COND[h->prec];
   h->validate = o.validate_device_inputs ? 1 : 0;
   h->deterministic = o.deterministic ? 1 : 0;
+  h->side_ok = o.side_stream ? 1 : 0;
   auto fail = [&](svlcov_status s) {
     svlcov_destroy(h);
     return s;

@@ -54,6 +54,7 @@ struct svlcov_state {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int ncu = 0;   // compute units of the device (set with the side stream)
+  int side_ok = 1;   // svlcov_options.side_stream
   int prec = SVLCOV_FP64;
   int k = 0;
   int64_t m = 0, n = 0;

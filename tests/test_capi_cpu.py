@@ -41,6 +41,7 @@ def test_status_strings_and_defaults():
     opt = L._Options()
     lib.svlcov_default_options(C.byref(opt))
     assert opt.precision == 0 and opt.validate_device_inputs == 1 and opt.stream is None
+    assert opt.deterministic == 1 and opt.side_stream == 1
 
 
 def test_init_rejects_bad_arguments_before_device_use():

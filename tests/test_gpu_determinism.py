@@ -34,8 +34,9 @@ def _hub_update(rng, s, width, hubs=12, density=0.05):
     return CSR.from_dense(E)
 
 
-def _run(L, U, s, V, ups, prec, deterministic=True):
-    svd = L.TruncatedSVD(U, s, V, precision=prec, deterministic=deterministic)
+def _run(L, U, s, V, ups, prec, deterministic=True, side_stream=True):
+    svd = L.TruncatedSVD(U, s, V, precision=prec, deterministic=deterministic,
+                         side_stream=side_stream)
     try:
         for up in ups:
             svd.apply(up)
@@ -93,3 +94,23 @@ def test_large_update_takes_the_sorted_row_update_bitwise():
     b = _run(L, U, s, V, ups, "fp32")
     for x, y, name in zip(a, b, "UsV"):
         assert np.array_equal(x, y), (name, float(np.max(np.abs(x - y))))
+
+
+@pytest.mark.parametrize("prec,k", [("fp32", 32), ("bf16x3", 64), ("bf16x3", 128)])
+def test_second_stream_gives_the_one_stream_factors(prec, k):
+    """An append update with the residual Gram's Cholesky on the state's
+    second stream (side_stream=True) gives bitwise the factors of the same
+    updates on one stream: the two streams split independent work and every
+    product keeps its order."""
+    L = _L()
+    rng = np.random.default_rng(407 + k)
+    m, n = 900, 700
+    U, s, V = synthetic_factors(m, n, k, rng)
+    ups = [("rows", _hub_update(rng, 220, n)),
+           ("cols", _hub_update(rng, 180, m + 220)),
+           ("weights", _hub_update(rng, 200, m + 220), _hub_update(rng, 200, n + 180))]
+    a = _run(L, U, s, V, ups, prec, side_stream=True)
+    b = _run(L, U, s, V, ups, prec, side_stream=False)
+    for x, y, name in zip(a, b, "UsV"):
+        assert x.shape == y.shape
+        assert np.array_equal(x, y), (prec, k, name, float(np.max(np.abs(x - y))))
