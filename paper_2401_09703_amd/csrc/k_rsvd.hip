@@ -499,6 +499,54 @@ k_ts_mul_lt(int64_t R, const double *__restrict__ X, const double *__restrict__ 
 // Then block rows of X' = L^{-1} (dropped rows zero) follow from
 // X'_ij = -X'_ii sum_{k=j}^{i-1} L_ik X'_kj.  S holds L in its lower triangle
 // and X'^T strictly above the diagonal; dg the diagonal of X'.
+// Lane J of each row of 16 lanes, to every lane of that row (DPP
+// row_newbcast; J a constant).
+template <int J>
+__device__ __forceinline__ double row_bcast16(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + J, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + J, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Steps J .. 15 of the right-looking Cholesky of a 16 x 16 block held one row
+// per lane in each row of 16 lanes (lane 16 g + i: row i of the reduced
+// block, both triangles, in a; the same in all four rows), with the inverse
+// of the factor spread over the four rows (lane 16 g + i: entries
+// 4 g .. 4 g + 3 of row i in z) and the factor's columns below the diagonal
+// (lr).  Column J's pivot d is dropped unless d > thr, which leaves a zero
+// column of multipliers (no update), a unit diagonal and a row of the inverse
+// that the caller zeroes.  Row J of the inverse is zero beyond column J, so
+// the update z_ic -= l_iJ z_Jc / sqrt(d) runs over all four entries; lane J
+// scales its row instead (l_JJ is 0 there).  Lane 0 records the pivot and the
+// drop flag.
+template <int J>
+__device__ __forceinline__ void diag16_steps(double (&a)[16], double (&z)[4], double (&lr)[16],
+                                             int i, double thr, double &ldiag, bool &mydrop,
+                                             double *piv, int *dr, bool rec) {
+  if constexpr (J < 16) {
+    const double d = row_bcast16<J>(a[J]);
+    const bool drop = !(d > thr);
+    const double sd = drop ? 1.0 : sqrt(d);
+    const double r = 1.0 / sd;
+    const double li = (i > J && !drop) ? a[J] * r : 0.0;
+    const double sc = i == J ? r : 1.0;
+    lr[J] = li;
+    if (i == J) {
+      ldiag = sd;
+      mydrop = drop;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) z[q] = fma(-li, row_bcast16<J>(z[q]) * r, z[q] * sc);
+#pragma unroll
+    for (int c = J + 1; c < 16; ++c) a[c] -= li * (row_bcast16<J>(a[c]) * r);
+    if (rec) {
+      dr[J] = drop ? 1 : 0;
+      piv[J] = d;
+    }
+    diag16_steps<J + 1>(a, z, lr, i, thr, ldiag, mydrop, piv, dr, rec);
+  }
+}
+
 constexpr int CB_NT = 512;
 constexpr int CB_NW = CB_NT / 64;
 
@@ -522,10 +570,22 @@ k_chol_drop_blk(int L, const double *__restrict__ G, double *__restrict__ Out,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   double mx = 0.0;
-  for (int e = tid; e < L * L; e += CB_NT) {
-    const int i = e / L, c = e % L;
-    S[i * LD + c] = (c <= i) ? G[e] : 0.0;
-    if (i == c) mx = fmax(mx, G[e]);
+  for (int e0 = 0; e0 < L * L; e0 += 4 * CB_NT) {   // four loads in flight per thread
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * CB_NT + tid;
+      v[u] = e < L * L ? G[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * CB_NT + tid;
+      if (e < L * L) {
+        const int i = e / L, c = e % L;
+        S[i * LD + c] = (c <= i) ? v[u] : 0.0;
+        if (i == c) mx = fmax(mx, v[u]);
+      }
+    }
   }
   mx = block_max(mx, red);
   const double thr = rtol * mx;
@@ -533,56 +593,35 @@ k_chol_drop_blk(int L, const double *__restrict__ G, double *__restrict__ Out,
   for (int b = 0; b < NB; ++b) {
     const int o = 16 * b;
     if (w == 0) {
-      // the diagonal block, four of its 256 entries per lane
-      for (int jj = 0; jj < 16; ++jj) {
-        const int j = o + jj;
-        const double d = S[j * LD + j];
-        const bool drop = !(d > thr);
-        if (!drop) {
-          const double invd = 1.0 / d;
-          int idx[4];
-          double upd[4];
+      // the diagonal block by wave 0: lane 16 g + i holds row i of the
+      // reduced block (both triangles, so that l_cj = A[j][c] / sqrt(A[j][j])
+      // is lane j's own entry c) and entries 4 g .. 4 g + 3 of row i of its
+      // inverse in registers; per column j lane j's entries reach the other
+      // lanes of its row of 16 by a row broadcast (no LDS round trip, no wave
+      // barrier).
+      const int i = lane & 15, g = lane >> 4;
+      double a[16], z[4], lr[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e = lane + 64 * u, i = e >> 4, c = e & 15;
-            const bool on = i > jj && c > jj && c <= i;
-            idx[u] = on ? (o + i) * LD + o + c : -1;
-            upd[u] = on ? S[(o + i) * LD + j] * S[(o + c) * LD + j] * invd : 0.0;
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (idx[u] >= 0) S[idx[u]] -= upd[u];
-        }
-        if (lane == 0) {
-          dr[j] = drop ? 1 : 0;
-          piv[j] = d;
-        }
-        wave_sync();
+      for (int c = 0; c < 16; ++c) {
+        a[c] = c <= i ? S[(o + i) * LD + o + c] : S[(o + c) * LD + o + i];
+        lr[c] = 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int e = lane + 64 * u, i = e >> 4, c = e & 15;
-        double *x = &S[(o + i) * LD + o + c];
-        if (c < i) *x = dr[o + c] ? 0.0 : *x / sqrt(piv[o + c]);
-        else if (c == i) *x = dr[o + i] ? 1.0 : sqrt(piv[o + i]);
+      for (int q = 0; q < 4; ++q) z[q] = 4 * g + q == i ? 1.0 : 0.0;
+      double ldiag = 1.0;
+      bool mydrop = false;
+      diag16_steps<0>(a, z, lr, i, thr, ldiag, mydrop, piv + o, dr + o, lane == 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {   // X'^T above the diagonal, the diagonal of X'
+        const int c = 4 * g + q;
+        if (c < i) S[(o + c) * LD + o + i] = mydrop ? 0.0 : z[q];
+        else if (c == i) dg[o + i] = mydrop ? 0.0 : z[q];
       }
-      wave_sync();
-      if (lane < 16) {   // column c of L_bb^{-1} by forward substitution
-        const int c = lane;
-        double x[16];
+      if (g == 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          double acc = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-          for (int p = 0; p < i; ++p) acc -= S[(o + i) * LD + o + p] * x[p];
-          x[i] = i < c ? 0.0 : acc / S[(o + i) * LD + o + i];
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          if (i < c) continue;
-          const double v = dr[o + i] ? 0.0 : x[i];
-          if (i == c) dg[o + c] = v;
-          else S[(o + c) * LD + o + i] = v;
+        for (int c = 0; c < 16; ++c) {
+          if (c < i) S[(o + i) * LD + o + c] = lr[c];   // L below the diagonal
+          else if (c == i) S[(o + i) * LD + o + i] = ldiag;
         }
       }
     }
