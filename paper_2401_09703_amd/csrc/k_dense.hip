@@ -4,6 +4,7 @@
 // orthonormalisation and the tall-skinny realisation GEMM.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "k_rsvd.hpp"
 
 #include <type_traits>
 
@@ -1066,15 +1067,19 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
   // One Cholesky QR pass: the rows come in orthonormal to a few ulps (or, for
   // completion rows, as random vectors far from the span of the others), and
   // the orthogonality CholQR leaves is ~ u kappa^2 with kappa ~ 1 here.
-  // L^{-1} by one wave (K <= 64) or one block, then X <- L^{-1} X as a GEMM
-  // (each output row its own dot products, no chain through earlier rows).
+  // L^{-1} by one wave (K <= 32) or by the blocked factor-and-invert of
+  // 16 x 16 diagonal blocks (K = 64, 128; its dropping threshold 0, so only a
+  // pivot that is not positive is dropped, leaving a zero row: the rows were
+  // then far from orthonormal), then X <- L^{-1} X as a GEMM (each output row
+  // its own dot products, no chain through earlier rows).  The drop flags go
+  // to ws, which the Gram's reduction has finished reading by then.
   gemm_f64_sk(st, false, true, K, K, N, 1.0, X, N, X, N, 0.0, Gm, K, ws, ws_len, info);
   if (K == 16) {
     hipLaunchKernelGGL((k_chol_inv_wave<16>), dim3(1), dim3(64), 0, st, Gm, Linv, info);
   } else if (K == 32) {
     hipLaunchKernelGGL((k_chol_inv_wave<32>), dim3(1), dim3(64), 0, st, Gm, Linv, info);
-  } else if (K == 64) {
-    hipLaunchKernelGGL((k_chol_inv_wave<64>), dim3(1), dim3(64), 0, st, Gm, Linv, info);
+  } else if (K == 64 || K == 128) {
+    chol_drop_if(st, K, Gm, Linv, reinterpret_cast<int32_t *>(ws), 0.0, info, nullptr);
   } else {
     const size_t sh = (size_t)(K * (K + 1) + K) * sizeof(double);
     hipLaunchKernelGGL(k_chol_inv_small, dim3(1), dim3(SMALL_NT), sh, st, K, Gm, Linv, info);
