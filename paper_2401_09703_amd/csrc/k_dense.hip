@@ -518,6 +518,10 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
                    int side) {
   if (info->status) return;
   constexpr int NT = 256;
+  static_assert(NT % K == 0, "a thread's elements share one column");
+  constexpr int GJ_PER = (K * K + NT - 1) / NT, GJ_RS = NT / K;
+  constexpr int GJ_UB = GJ_PER < 16 ? GJ_PER : 16;
+  static_assert(GJ_PER % GJ_UB == 0, "whole batches");
   __shared__ double As[K][K + 1];
   __shared__ double rowc[K], colf[K];
   __shared__ double cand_v[NT / 64];
@@ -575,17 +579,26 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
     for (int r = t; r < K; r += NT) colf[r] = r == c ? 0.0 : As[r][c];
     __syncthreads();
     const double pinv = 1.0 / rowc[c];
-    // (unrolled: one wave per SIMD here, so the LDS latency of one element's
-    // update hides only behind the others')
-#pragma unroll 16
-    for (int e = t; e < K * K; e += NT) {
-      const int r = e / K, j = e % K;
-      const double prow = j == c ? pinv : rowc[j] * pinv;
-      if (r == c) {
-        As[r][j] = prow;
-      } else {
-        const double f = colf[r];
-        As[r][j] = j == c ? -f * pinv : As[r][j] - f * prow;
+    // NT is a multiple of K, so all of a thread's elements lie in column
+    // j = t mod K, rows t / K + u NT / K.  Loads of UB elements are issued
+    // before their stores (one wave per SIMD here: each element's LDS latency
+    // hides only behind the others', and a store between two loads of As
+    // would keep the compiler from hoisting the second).
+    const int j = t % K;
+    const double pj = j == c ? pinv : rowc[j] * pinv;
+#pragma unroll
+    for (int u0 = 0; u0 < GJ_PER; u0 += GJ_UB) {
+      double v[GJ_UB], f[GJ_UB];
+#pragma unroll
+      for (int u = 0; u < GJ_UB; ++u) {
+        const int r = t / K + (u0 + u) * GJ_RS;
+        v[u] = r < K ? As[r][j] : 0.0;
+        f[u] = r < K ? colf[r] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < GJ_UB; ++u) {
+        const int r = t / K + (u0 + u) * GJ_RS;
+        if (r < K) As[r][j] = r == c ? pj : (j == c ? -f[u] * pinv : v[u] - f[u] * pj);
       }
     }
     __syncthreads();
@@ -652,8 +665,9 @@ inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
                   int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
                   int side) {
   if (info->status) return;
+  typedef double d2 __attribute__((ext_vector_type(2)));
   __shared__ double S[K][K + 1];
-  __shared__ double prow[2][K];
+  __shared__ __align__(16) double prow[2][K];
   __shared__ int pv[K], qv[K];
   const int lane = threadIdx.x;
   const bool mine = lane < K;
@@ -683,9 +697,9 @@ inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
         sing = true;
       } else {
         double *pr = prow[c & 1];
-        if (lane == p) {
+        if (lane == p) {   // 16-byte stores: half the instructions of the one lane
 #pragma unroll
-          for (int j = 0; j < K; ++j) pr[j] = a[j];
+          for (int j = 0; j < K; j += 2) *(d2 *)(pr + j) = d2{a[j], a[j + 1]};
           pv[c] = p;
         }
         wave_sync();
@@ -695,9 +709,13 @@ inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
 #pragma unroll
           for (int j = 0; j < K; ++j) a[j] = (j == c ? 1.0 : a[j]) * pinv;
         } else {
-          const double f = a[c];
+          const double g = a[c] * pinv;   // the row's multiplier
 #pragma unroll
-          for (int j = 0; j < K; ++j) a[j] = j == c ? -f * pinv : fma(-f, pr[j] * pinv, a[j]);
+          for (int j = 0; j < K; j += 2) {
+            const d2 q = *(const d2 *)(pr + j);
+            a[j] = j == c ? -g : fma(-g, q.x, a[j]);
+            a[j + 1] = j + 1 == c ? -g : fma(-g, q.y, a[j + 1]);
+          }
         }
       }
     }
