@@ -519,6 +519,7 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
   if (info->status) return;
   constexpr int NT = 256;
   static_assert(NT % K == 0, "a thread's elements share one column");
+  static_assert(K <= NT, "one pivot candidate per thread");
   constexpr int GJ_PER = (K * K + NT - 1) / NT, GJ_RS = NT / K;
   constexpr int GJ_UB = GJ_PER < 16 ? GJ_PER : 16;
   static_assert(GJ_PER % GJ_UB == 0, "whole batches");
@@ -548,19 +549,14 @@ inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
   bool sing = !finite_in;
   for (int c = 0; c < K && !sing; ++c) {
     // pivot candidate of each wave (rows r >= c it covers), then the block's
-    double best = -1.0;
-    int bi = K;
-    for (int r = c + t; r < K; r += NT) {
-      const double v = fabs(As[r][c]);
-      if (v > best) { best = v; bi = r; }
-    }
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    if (lane == 0) { cand_v[w] = best; cand_i[w] = bi; }
+    // (K <= NT: thread t covers row c + t only, so rows rise with the lane
+    // and the lowest lane holding the wave's maximum has the lowest row)
+    const int rt = c + t;
+    const double v = rt < K ? fabs(As[rt][c]) : -1.0;
+    const double wb = wave_max(v);
+    const unsigned long long hit = __ballot(v == wb && rt < K);
+    const int bi = hit ? c + (t & ~63) + __builtin_ctzll(hit) : K;
+    if (lane == 0) { cand_v[w] = hit ? wb : -1.0; cand_i[w] = bi; }
     __syncthreads();
     double pb = cand_v[0];
     int p = cand_i[0];
