@@ -503,21 +503,25 @@ __global__ void k_fill_random_rows(int K, int64_t N, double *__restrict__ X,
 // Gauss-Jordan inverse with partial pivoting of the K x K matrix W (K <= 128)
 // in place in LDS, with the 1-norm condition number
 // kappa_1 = ||W||_1 ||W^{-1}||_1 and the reset flag (kappa_1 > cond_reset or
-// W numerically singular).  One block of 256 threads.  Per column c: the
-// pivot is the largest |A[r][c]| over rows r >= c (lowest row on ties), the
-// pivot row and row c are exchanged, row c is scaled by 1/pivot and every
-// other row subtracts its multiple of it, the inverse taking column c's
-// place (A[r][c] = -f_r / pivot); four barriers.  The row interchanges are
+// W numerically singular).  One block (256 threads, 512 at K = 128).  Per
+// column c: the pivot is the largest |A[r][c]| over rows r >= c (lowest row
+// on ties), the pivot row and row c are exchanged, row c is scaled by
+// 1/pivot and every other row subtracts its multiple of it, the inverse
+// taking column c's place (A[r][c] = -f_r / pivot); four barriers.  The row interchanges are
 // undone at the end as one column permutation.  (Holding the rows in
 // registers, 64 doubles a lane at K = 128, the compiler put the array in
 // scratch memory: 2.3 ms per inverse at K = 128, 1.3 ms here.)
+// threads of the block inverse: two waves per SIMD at K = 128, so that one
+// wave's LDS latency hides behind the other's
+constexpr int inv_block_nt(int K) { return K == 128 ? 512 : 256; }
+
 template <int K>
 __device__ __forceinline__ void
 inverse_cond_block(const double *__restrict__ W, double *__restrict__ Winv,
                    int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
                    int side) {
   if (info->status) return;
-  constexpr int NT = 256;
+  constexpr int NT = inv_block_nt(K);
   static_assert(NT % K == 0, "a thread's elements share one column");
   static_assert(K <= NT, "one pivot candidate per thread");
   constexpr int GJ_PER = (K * K + NT - 1) / NT, GJ_RS = NT / K;
@@ -752,7 +756,7 @@ k_inverse_cond2_wave(InvJob a, InvJob b, double cond_reset, SvDevInfo *__restric
 }
 
 template <int K>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
                int32_t *__restrict__ flag, double cond_reset, SvDevInfo *__restrict__ info,
                int side) {
@@ -763,7 +767,7 @@ k_inverse_cond(const double *__restrict__ W, double *__restrict__ Winv,
 // block 1: side b); they are independent, so they run side by side.
 
 template <int K>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_inverse_cond2(InvJob a, InvJob b, double cond_reset, SvDevInfo *__restrict__ info) {
   const InvJob j = blockIdx.x ? b : a;
   inverse_cond_block<K>(j.W, j.Winv, j.flag, cond_reset, info, j.side);
@@ -1104,8 +1108,8 @@ void orthonormalize_rows(hipStream_t st, int K, int64_t N, double *X, const int3
 
 void inverse_cond(hipStream_t st, int K, const double *W, double *Winv, int32_t *flag,
                   double cond_reset, SvDevInfo *info, int side) {
-#define SV_INV(KK) hipLaunchKernelGGL((k_inverse_cond<KK>), dim3(1), dim3(256), 0, st, W, Winv, \
-                                      flag, cond_reset, info, side)
+#define SV_INV(KK) hipLaunchKernelGGL((k_inverse_cond<KK>), dim3(1), dim3(inv_block_nt(KK)), 0, \
+                                      st, W, Winv, flag, cond_reset, info, side)
   switch (K) {
     case 16: SV_INV(16); break;
     case 32: SV_INV(32); break;
@@ -1119,8 +1123,8 @@ void inverse_cond_pair(hipStream_t st, int K, const double *Wa, double *Wia, int
                        const double *Wb, double *Wib, int32_t *fb, int sb, double cond_reset,
                        SvDevInfo *info) {
   const InvJob a{Wa, Wia, fa, sa}, b{Wb, Wib, fb, sb};
-#define SV_INV2(KK) hipLaunchKernelGGL((k_inverse_cond2<KK>), dim3(2), dim3(256), 0, st, a, b, \
-                                       cond_reset, info)
+#define SV_INV2(KK) hipLaunchKernelGGL((k_inverse_cond2<KK>), dim3(2), dim3(inv_block_nt(KK)), 0, \
+                                       st, a, b, cond_reset, info)
 #define SV_INV2W(KK) hipLaunchKernelGGL((k_inverse_cond2_wave<KK>), dim3(2), dim3(64), 0, st, a, \
                                         b, cond_reset, info)
   switch (K) {
@@ -1143,7 +1147,8 @@ void inverse_cond_one(hipStream_t st, int K, const double *W, double *Winv, int3
     case 32: SV_INV1W(32); break;
     case 64: SV_INV1W(64); break;
     case 128:
-      hipLaunchKernelGGL((k_inverse_cond2<128>), dim3(1), dim3(256), 0, st, a, a, cond_reset, info);
+      hipLaunchKernelGGL((k_inverse_cond2<128>), dim3(1), dim3(inv_block_nt(128)), 0, st, a, a,
+                         cond_reset, info);
       break;
   }
 #undef SV_INV1W
