@@ -654,7 +654,10 @@ struct InvJob {
 // place with implicit partial pivoting (the pivot of column c is the largest
 // |a[r][c]| over the rows not pivoted yet, lowest row on ties, and no row
 // moves): the pivot row goes through LDS (alternating buffers, one wave
-// barrier per column), every other row subtracts its multiple of it.  With
+// barrier per column), every other row subtracts its multiple of it.  A pivot
+// row is scaled by 1/pivot only at the end (later columns update it linearly,
+// so the scaling commutes with them), which keeps K multiplications per
+// column out of the branch of the pivot lane.  With
 // p_c the pivot row of column c, the final array S holds W^{-1}[i][m] =
 // S[p_i][q_m] with q the inverse of p.  The loop over columns is unrolled,
 // so every register index is static.  1-norms through an LDS copy, one
@@ -686,6 +689,7 @@ inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
   const bool finite_in = isfinite(n1);
   bool sing = !finite_in;
   bool used = !mine;
+  double rs = 1.0;
 #pragma clang loop unroll(full)
   for (int c = 0; c < K; ++c) {
     if (!sing) {
@@ -704,10 +708,10 @@ inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
         }
         wave_sync();
         const double pinv = 1.0 / pr[c];
-        if (lane == p) {
+        if (lane == p) {   // the pivot row's scaling by 1/pivot waits for the end
           used = true;
-#pragma unroll
-          for (int j = 0; j < K; ++j) a[j] = (j == c ? 1.0 : a[j]) * pinv;
+          rs = pinv;
+          a[c] = 1.0;
         } else {
           const double g = a[c] * pinv;   // the row's multiplier
 #pragma unroll
@@ -723,6 +727,8 @@ inverse_cond_wave(const double *__restrict__ W, double *__restrict__ Winv,
   wave_sync();
   double kappa = INFINITY;
   if (!sing) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] *= rs;
     if (mine) qv[pv[lane]] = lane;
     wave_sync();
     // W^{-1}[i][m] = a_{p_i}[q_m]: lane r (= p_i for i = q_r) holds row i
