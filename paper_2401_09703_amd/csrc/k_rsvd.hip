@@ -828,6 +828,10 @@ __global__ void k_seg_heads(int64_t nnz, const uint32_t *__restrict__ keys,
     if (q == 0 || keys[q] != keys[q - 1]) heads[atomicAdd(count, 1u)] = (uint32_t)q;
 }
 
+// Runs longer than SEG_LONG nonzeros (the hot columns of a power-law
+// update: thousands of rows in one column) go to k_scatter_long.
+constexpr int64_t SEG_LONG = 1024;
+
 template <typename T, int K>
 __global__ void __launch_bounds__(256)
 k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__restrict__ perm,
@@ -842,6 +846,7 @@ k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__
   for (int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sg < (int64_t)nseg;
        sg += (int64_t)gridDim.x * 4) {
     const uint32_t q0 = heads[sg], key = keys[q0];
+    if ((int64_t)q0 + SEG_LONG < nnz && keys[q0 + SEG_LONG] == key) continue;   // k_scatter_long's
     double acc[CPL];
 #pragma unroll
     for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
@@ -882,6 +887,88 @@ k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__
 #pragma unroll
     for (int u = 0; u < CPL; ++u)
       if (lane + 64 * u < K) dst[lane + 64 * u] = (T)((double)dst[lane + 64 * u] + acc[u]);
+  }
+}
+
+// The runs longer than SEG_LONG, one block of LW waves each: the run's end by
+// binary search over the sorted keys, wave w sums the w-th of LW contiguous
+// pieces in row order (SU nonzeros' loads at a time, as k_scatter_seg), and
+// the LW partial sums are added in wave order, so the result is again fixed
+// by the input alone.  Blocks stride over the list of runs and skip the
+// short ones (the test is uniform across the block).
+constexpr int LW = 16;
+
+template <typename T, int K>
+__global__ void __launch_bounds__(LW * 64)
+k_scatter_long(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__restrict__ perm,
+               const uint32_t *__restrict__ heads, const uint32_t *__restrict__ count,
+               const int32_t *__restrict__ rid, const void *__restrict__ val, int vdtype,
+               const double *__restrict__ M, T *__restrict__ base,
+               const SvDevInfo *__restrict__ info) {
+  if (info->status) return;
+  constexpr int CPL = K <= 64 ? 1 : K / 64;
+  __shared__ double part[LW][K];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t nseg = *count;
+  for (int64_t sg = blockIdx.x; sg < (int64_t)nseg; sg += gridDim.x) {
+    const uint32_t q0 = heads[sg], key = keys[q0];
+    if (!((int64_t)q0 + SEG_LONG < nnz && keys[q0 + SEG_LONG] == key)) continue;
+    // keys[lo] == key, keys[hi] != key (or hi == nnz): the run ends at hi
+    int64_t lo = (int64_t)q0 + SEG_LONG, hi = nnz;
+    while (hi - lo > 1) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (keys[mid] == key) lo = mid; else hi = mid;
+    }
+    const int64_t len = hi - (int64_t)q0, per = (len + LW - 1) / LW;
+    const int64_t a = (int64_t)q0 + w * per;
+    const int64_t b = a + per < hi ? a + per : hi;
+    double acc[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
+    constexpr int SU = 32;
+    for (int64_t q = a; q < b; q += SU) {
+      bool in[SU];
+      uint32_t pp[SU];
+#pragma unroll
+      for (int e = 0; e < SU; ++e) {
+        in[e] = q + e < b;
+        pp[e] = in[e] ? perm[q + e] : 0u;
+      }
+      double vb[SU], mb[SU][CPL];
+#pragma unroll
+      for (int e = 0; e < SU; ++e) {
+        vb[e] = !in[e] ? 0.0
+                       : vdtype == 1 ? ((const double *)val)[pp[e]]
+                                     : (double)((const float *)val)[pp[e]];
+        const int64_t i = in[e] ? rid[pp[e]] : 0;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u)
+          mb[e][u] = in[e] && lane + 64 * u < K ? M[i * K + lane + 64 * u] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < SU; ++e)
+        if (in[e])
+#pragma unroll
+          for (int u = 0; u < CPL; ++u)
+            if (lane + 64 * u < K) acc[u] += vb[e] * mb[e][u];
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u)
+      if (lane + 64 * u < K) part[w][lane + 64 * u] = acc[u];
+    __syncthreads();
+    if (w == 0) {
+      T *dst = base + (int64_t)key * K;
+#pragma unroll
+      for (int u = 0; u < CPL; ++u) {
+        const int c = lane + 64 * u;
+        if (c < K) {
+          double t = 0.0;
+          for (int ww = 0; ww < LW; ++ww) t += part[ww][c];
+          dst[c] = (T)((double)dst[c] + t);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1133,6 +1220,18 @@ void scatter_det(hipStream_t st, int K, int64_t s, int64_t cols, int64_t nnz, co
     case 128: SV_SS(128); break;
   }
 #undef SV_SS
+  if (nnz > SEG_LONG) {   // runs longer than SEG_LONG exist only then
+    const unsigned lb = (unsigned)std::min<int64_t>(nnz / SEG_LONG, 1024);
+#define SV_SL(KK) hipLaunchKernelGGL((k_scatter_long<T, KK>), dim3(lb), dim3(LW * 64), 0, st, nnz, \
+                                     kin, pin, heads, count, rid, v, vdt, M, base, info)
+    switch (K) {
+      case 16: SV_SL(16); break;
+      case 32: SV_SL(32); break;
+      case 64: SV_SL(64); break;
+      case 128: SV_SL(128); break;
+    }
+#undef SV_SL
+  }
 }
 template void scatter_det<float>(hipStream_t, int, int64_t, int64_t, int64_t, const int64_t *,
                                  const int32_t *, const void *, int, const double *, float *,

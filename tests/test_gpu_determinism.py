@@ -114,3 +114,28 @@ def test_second_stream_gives_the_one_stream_factors(prec, k):
     for x, y, name in zip(a, b, "UsV"):
         assert x.shape == y.shape
         assert np.array_equal(x, y), (prec, k, name, float(np.max(np.abs(x - y))))
+
+
+@pytest.mark.parametrize("k", [32, 128])
+def test_hot_column_runs_split_over_a_block(k):
+    """Columns with more than 1024 nonzeros in one update (a power-law hot
+    column) are summed by a whole block in fixed pieces: bitwise
+    reproducible, and equal to the atomic accumulation to rounding."""
+    L = _L()
+    rng = np.random.default_rng(408 + k)
+    m, n = 900, 800
+    U, s, V = synthetic_factors(m, n, k, rng)
+    E = _hub_update(rng, 3000, n, hubs=4, density=0.02)
+    col_counts = np.bincount(E.col_idx, minlength=n)
+    assert E.nnz > 32768 and col_counts.max() > 2048
+    ups = [("rows", E)]
+    a = _run(L, U, s, V, ups, "fp32")
+    b = _run(L, U, s, V, ups, "fp32")
+    for x, y, name in zip(a, b, "UsV"):
+        assert np.array_equal(x, y), (name, float(np.max(np.abs(x - y))))
+    Ua, sa, Va = _run(L, U, s, V, ups, "fp64", deterministic=True)
+    Ub, sb, Vb = _run(L, U, s, V, ups, "fp64", deterministic=False)
+    assert np.max(np.abs(sa - sb)) <= 1e-10 * sa[0]
+    for A, B in ((Ua, Ub), (Va, Vb)):
+        sg = np.sign(np.sum(A * B, axis=0))
+        assert np.max(np.abs(A - B * sg)) <= 1e-8
