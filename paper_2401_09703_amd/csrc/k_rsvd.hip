@@ -830,7 +830,7 @@ __global__ void k_seg_heads(int64_t nnz, const uint32_t *__restrict__ keys,
 
 // Runs longer than SEG_LONG nonzeros (the hot columns of a power-law
 // update: thousands of rows in one column) go to k_scatter_long.
-constexpr int64_t SEG_LONG = 1024;
+constexpr int64_t SEG_LONG = 256;
 
 template <typename T, int K>
 __global__ void __launch_bounds__(256)
@@ -894,8 +894,10 @@ k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__
 // binary search over the sorted keys, wave w sums the w-th of LW contiguous
 // pieces in row order (SU nonzeros' loads at a time, as k_scatter_seg), and
 // the LW partial sums are added in wave order, so the result is again fixed
-// by the input alone.  Blocks stride over the list of runs and skip the
-// short ones (the test is uniform across the block).
+// by the input alone.  Blocks stride over the list of runs LW at a time, each
+// wave testing one run (three dependent loads) and listing the long ones in
+// LDS; the block then takes the listed runs one after another (their order
+// does not matter: every run writes its own base row).
 constexpr int LW = 16;
 
 template <typename T, int K>
@@ -908,67 +910,79 @@ k_scatter_long(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *_
   if (info->status) return;
   constexpr int CPL = K <= 64 ? 1 : K / 64;
   __shared__ double part[LW][K];
+  __shared__ uint32_t lq[LW];
+  __shared__ int nl;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t nseg = *count;
-  for (int64_t sg = blockIdx.x; sg < (int64_t)nseg; sg += gridDim.x) {
-    const uint32_t q0 = heads[sg], key = keys[q0];
-    if (!((int64_t)q0 + SEG_LONG < nnz && keys[q0 + SEG_LONG] == key)) continue;
-    // keys[lo] == key, keys[hi] != key (or hi == nnz): the run ends at hi
-    int64_t lo = (int64_t)q0 + SEG_LONG, hi = nnz;
-    while (hi - lo > 1) {
-      const int64_t mid = lo + (hi - lo) / 2;
-      if (keys[mid] == key) lo = mid; else hi = mid;
+  for (int64_t sg0 = (int64_t)blockIdx.x * LW; sg0 < (int64_t)nseg;
+       sg0 += (int64_t)gridDim.x * LW) {
+    if (threadIdx.x == 0) nl = 0;
+    __syncthreads();
+    if (lane == 0 && sg0 + w < (int64_t)nseg) {
+      const uint32_t q = heads[sg0 + w];
+      if ((int64_t)q + SEG_LONG < nnz && keys[q + SEG_LONG] == keys[q]) lq[atomicAdd(&nl, 1)] = q;
     }
-    const int64_t len = hi - (int64_t)q0, per = (len + LW - 1) / LW;
-    const int64_t a = (int64_t)q0 + w * per;
-    const int64_t b = a + per < hi ? a + per : hi;
-    double acc[CPL];
-#pragma unroll
-    for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
-    constexpr int SU = 32;
-    for (int64_t q = a; q < b; q += SU) {
-      bool in[SU];
-      uint32_t pp[SU];
-#pragma unroll
-      for (int e = 0; e < SU; ++e) {
-        in[e] = q + e < b;
-        pp[e] = in[e] ? perm[q + e] : 0u;
+    __syncthreads();
+    const int nlong = nl;
+    for (int t = 0; t < nlong; ++t) {
+      const uint32_t q0 = lq[t], key = keys[q0];
+      // keys[lo] == key, keys[hi] != key (or hi == nnz): the run ends at hi
+      int64_t lo = (int64_t)q0 + SEG_LONG, hi = nnz;
+      while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (keys[mid] == key) lo = mid; else hi = mid;
       }
-      double vb[SU], mb[SU][CPL];
+      const int64_t len = hi - (int64_t)q0, per = (len + LW - 1) / LW;
+      const int64_t a = (int64_t)q0 + w * per;
+      const int64_t b = a + per < hi ? a + per : hi;
+      double acc[CPL];
 #pragma unroll
-      for (int e = 0; e < SU; ++e) {
-        vb[e] = !in[e] ? 0.0
-                       : vdtype == 1 ? ((const double *)val)[pp[e]]
-                                     : (double)((const float *)val)[pp[e]];
-        const int64_t i = in[e] ? rid[pp[e]] : 0;
+      for (int u = 0; u < CPL; ++u) acc[u] = 0.0;
+      constexpr int SU = 32;
+      for (int64_t q = a; q < b; q += SU) {
+        bool in[SU];
+        uint32_t pp[SU];
 #pragma unroll
-        for (int u = 0; u < CPL; ++u)
-          mb[e][u] = in[e] && lane + 64 * u < K ? M[i * K + lane + 64 * u] : 0.0;
-      }
+        for (int e = 0; e < SU; ++e) {
+          in[e] = q + e < b;
+          pp[e] = in[e] ? perm[q + e] : 0u;
+        }
+        double vb[SU], mb[SU][CPL];
 #pragma unroll
-      for (int e = 0; e < SU; ++e)
-        if (in[e])
+        for (int e = 0; e < SU; ++e) {
+          vb[e] = !in[e] ? 0.0
+                         : vdtype == 1 ? ((const double *)val)[pp[e]]
+                                       : (double)((const float *)val)[pp[e]];
+          const int64_t i = in[e] ? rid[pp[e]] : 0;
 #pragma unroll
           for (int u = 0; u < CPL; ++u)
-            if (lane + 64 * u < K) acc[u] += vb[e] * mb[e][u];
-    }
+            mb[e][u] = in[e] && lane + 64 * u < K ? M[i * K + lane + 64 * u] : 0.0;
+        }
 #pragma unroll
-    for (int u = 0; u < CPL; ++u)
-      if (lane + 64 * u < K) part[w][lane + 64 * u] = acc[u];
-    __syncthreads();
-    if (w == 0) {
-      T *dst = base + (int64_t)key * K;
+        for (int e = 0; e < SU; ++e)
+          if (in[e])
 #pragma unroll
-      for (int u = 0; u < CPL; ++u) {
-        const int c = lane + 64 * u;
-        if (c < K) {
-          double t = 0.0;
-          for (int ww = 0; ww < LW; ++ww) t += part[ww][c];
-          dst[c] = (T)((double)dst[c] + t);
+            for (int u = 0; u < CPL; ++u)
+              if (lane + 64 * u < K) acc[u] += vb[e] * mb[e][u];
+      }
+#pragma unroll
+      for (int u = 0; u < CPL; ++u)
+        if (lane + 64 * u < K) part[w][lane + 64 * u] = acc[u];
+      __syncthreads();
+      if (w == 0) {
+        T *dst = base + (int64_t)key * K;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+          const int c = lane + 64 * u;
+          if (c < K) {
+            double tot = 0.0;
+            for (int ww = 0; ww < LW; ++ww) tot += part[ww][c];
+            dst[c] = (T)((double)dst[c] + tot);
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 

@@ -118,7 +118,7 @@ def test_second_stream_gives_the_one_stream_factors(prec, k):
 
 @pytest.mark.parametrize("k", [32, 128])
 def test_hot_column_runs_split_over_a_block(k):
-    """Columns with more than 1024 nonzeros in one update (a power-law hot
+    """Columns with more than 256 nonzeros in one update (a power-law hot
     column) are summed by a whole block in fixed pieces: bitwise
     reproducible, and equal to the atomic accumulation to rounding."""
     L = _L()
