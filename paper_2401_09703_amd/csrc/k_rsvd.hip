@@ -898,7 +898,7 @@ k_scatter_seg(int64_t nnz, const uint32_t *__restrict__ keys, const uint32_t *__
 // wave testing one run (three dependent loads) and listing the long ones in
 // LDS; the block then takes the listed runs one after another (their order
 // does not matter: every run writes its own base row).
-constexpr int LW = 16;
+constexpr int LW = 8;   // two waves per SIMD: 256 registers a lane for the batch of loads
 
 template <typename T, int K>
 __global__ void __launch_bounds__(LW * 64)
